@@ -1,0 +1,569 @@
+/*
+ * oracle.c — plain CPU oracle (test infrastructure; see oracle.h).
+ *
+ * Paper: Akhremtsev, Sanders, Schulz, "High-Quality Shared-Memory Graph
+ * Partitioning" (arXiv 1710.08231). Sections cited: §II-A (problem statement,
+ * L_max, cut, size-constrained clustering, quotient graph), §III-A
+ * (coarsening, contraction, size-constrained label propagation), §III-B
+ * (initial partitioning by recursive bisection, best of I tries), §III-C
+ * (projection, LP as local search with U = L_max), §IV-A (parallel LP: a move
+ * is made only if the target is still feasible; parallel contraction by
+ * prefix-sum relabelling), §VI (10 / 25 LP iterations, 4 initial tries).
+ *
+ * The LP here is the round-synchronous reading of §III-A/§IV-A: every vertex
+ * proposes from the labels and label weights of the round start, ties go to
+ * the lowest label, and the moves to one target are admitted in ascending
+ * vertex order while the running weight stays within U. Even rounds only
+ * allow moves to smaller labels and odd rounds only to larger ones
+ * ("direction alternation"), which rules out the two-cycles a synchronous
+ * round would otherwise fall into.
+ *
+ * Everything is written as the plain definition: dense scratch arrays,
+ * explicit loops, no blocking or fusion.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define VW(g, v) ((g)->vwgt ? (int64_t)(g)->vwgt[v] : (int64_t)1)
+#define EW(g, e) ((g)->adjwgt ? (int64_t)(g)->adjwgt[e] : (int64_t)1)
+
+static void *xcalloc(size_t count, size_t size) {
+    void *p = calloc(count ? count : 1, size);
+    if (!p) abort();
+    return p;
+}
+
+/* §II-A: L_max = (1+eps) * ceil(c(V)/k), read as the floor of the binary64 product. */
+int64_t orc_lmax(int64_t total_vwgt, int32_t k, double eps) {
+    int64_t q = total_vwgt / k + (total_vwgt % k != 0);
+    return (int64_t)floor((1.0 + eps) * (double)q);
+}
+
+int64_t orc_total_vwgt(const orc_graph *g) {
+    int64_t s = 0;
+    for (int32_t v = 0; v < g->n; v++) s += VW(g, v);
+    return s;
+}
+
+/*
+ * One synchronous LP round (§III-A clustering rule, §IV-A admission).
+ *   1. conn[L] = total weight of v's edges to vertices labelled L.
+ *   2. candidates: L != C[v], allowed by the direction of round r, and
+ *      eligible, i.e. W[L] + c(v) <= U (a cluster is overloaded only when it
+ *      exceeds its bound).
+ *   3. best = max conn, ties -> smallest L; propose iff conn[best] > conn[C[v]].
+ *   4. admission per target in ascending v: admitted iff W[t] + (sum of c over
+ *      the proposers to t up to and including v) <= U.
+ *   5. apply all admitted moves; W follows.
+ */
+int64_t orc_lp_round(const orc_graph *g, int32_t *C, int64_t *W, int32_t nlabels, int64_t U,
+                     int32_t r, int32_t dir_alternate, int32_t *prop_out) {
+    int32_t n = g->n;
+    int64_t *conn = (int64_t *)xcalloc((size_t)nlabels, sizeof(int64_t));
+    int32_t *seen = (int32_t *)xcalloc((size_t)nlabels, sizeof(int32_t));
+    int32_t *touched = (int32_t *)xcalloc((size_t)nlabels, sizeof(int32_t));
+    int32_t *prop = prop_out ? prop_out : (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
+
+    for (int32_t v = 0; v < n; v++) {
+        int32_t ntouched = 0;
+        for (int32_t e = g->xadj[v]; e < g->xadj[v + 1]; e++) {
+            int32_t L = C[g->adjncy[e]];
+            if (!seen[L]) { seen[L] = 1; touched[ntouched++] = L; }
+            conn[L] += EW(g, e);
+        }
+        int32_t own = C[v];
+        int64_t conn_own = seen[own] ? conn[own] : 0;
+        int32_t best = -1;
+        int64_t best_conn = 0;
+        for (int32_t i = 0; i < ntouched; i++) {
+            int32_t L = touched[i];
+            if (L == own) continue;
+            if (dir_alternate) {
+                if ((r % 2) == 0 && !(L < own)) continue;
+                if ((r % 2) == 1 && !(L > own)) continue;
+            }
+            if (W[L] + VW(g, v) > U) continue;
+            if (best < 0 || conn[L] > best_conn || (conn[L] == best_conn && L < best)) {
+                best = L;
+                best_conn = conn[L];
+            }
+        }
+        prop[v] = (best >= 0 && best_conn > conn_own) ? best : -1;
+        for (int32_t i = 0; i < ntouched; i++) { conn[touched[i]] = 0; seen[touched[i]] = 0; }
+    }
+
+    /* admission: running proposal weight per target, vertices in ascending order */
+    int64_t *acc = conn; /* all zero again */
+    uint8_t *admitted = (uint8_t *)xcalloc((size_t)n, 1);
+    for (int32_t v = 0; v < n; v++) {
+        if (prop[v] < 0) continue;
+        int32_t t = prop[v];
+        acc[t] += VW(g, v);
+        admitted[v] = (W[t] + acc[t] <= U);
+    }
+    int64_t moves = 0;
+    for (int32_t v = 0; v < n; v++) {
+        if (!admitted[v]) continue;
+        int32_t t = prop[v];
+        W[t] += VW(g, v);
+        W[C[v]] -= VW(g, v);
+        C[v] = t;
+        moves++;
+    }
+    free(admitted);
+    free(conn);
+    free(seen);
+    free(touched);
+    if (!prop_out) free(prop);
+    return moves;
+}
+
+/* Round loop shared by clustering and refinement; stop after two idle rounds in a row. */
+static void lp_rounds(const orc_graph *g, int32_t *C, int64_t *W, int32_t nlabels, int64_t U,
+                      int32_t rounds, int32_t dir_alternate, orc_lp_stats *st) {
+    int64_t prev = -1, total = 0;
+    int32_t run = 0;
+    for (int32_t r = 0; r < rounds; r++) {
+        int64_t m = orc_lp_round(g, C, W, nlabels, U, r, dir_alternate, NULL);
+        total += m;
+        run = r + 1;
+        if (r >= 1 && m == 0 && prev == 0) break;
+        prev = m;
+    }
+    if (st) {
+        st->rounds_run = run;
+        st->moves = total;
+        st->edge_visits = (int64_t)run * (int64_t)g->xadj[g->n];
+    }
+}
+
+/* §III-A: size-constrained LP clustering from singletons, C[v] = v, bound U. */
+int orc_lp_cluster(const orc_graph *g, int64_t U, int32_t rounds, int32_t dir_alternate,
+                   int32_t *labels_out, orc_lp_stats *st) {
+    int32_t n = g->n;
+    int64_t *W = (int64_t *)xcalloc((size_t)n, sizeof(int64_t));
+    for (int32_t v = 0; v < n; v++) { labels_out[v] = v; W[v] = VW(g, v); }
+    lp_rounds(g, labels_out, W, n, U, rounds, dir_alternate, st);
+    free(W);
+    return 0;
+}
+
+/* §III-C: LP as local search from a k-way partition with U = L_max. */
+int orc_lp_refine(const orc_graph *g, int32_t k, int64_t lmax, int32_t rounds,
+                  int32_t dir_alternate, int32_t *part, orc_lp_stats *st) {
+    int64_t *W = (int64_t *)xcalloc((size_t)k, sizeof(int64_t));
+    for (int32_t v = 0; v < g->n; v++) W[part[v]] += VW(g, v);
+    lp_rounds(g, part, W, k, lmax, rounds, dir_alternate, st);
+    free(W);
+    return 0;
+}
+
+/*
+ * §III-A / §IV-A contraction. Coarse ids: prefix sum over "label is used"
+ * indicators, so coarse id = rank of the label among the used labels.
+ * c'(i) = sum of c over cluster i; w'(i,j) = sum of w over fine edges between
+ * clusters i != j. Rows ascending by i, columns ascending by j.
+ */
+int orc_contract(const orc_graph *g, const int32_t *labels, int32_t *xadj_c, int32_t *adjncy_c,
+                 int32_t *adjwgt_c, int32_t *vwgt_c, int32_t *f2c, int32_t *n_c_out,
+                 int32_t *nnz_c_out) {
+    int32_t n = g->n;
+    int32_t *used = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
+    int32_t *id = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
+    for (int32_t v = 0; v < n; v++) used[labels[v]] = 1;
+    int32_t nc = 0;
+    for (int32_t L = 0; L < n; L++) { id[L] = nc; nc += used[L]; }
+    for (int32_t v = 0; v < n; v++) f2c[v] = id[labels[v]];
+
+    /* members of each coarse vertex, ascending fine id */
+    int32_t *mstart = (int32_t *)xcalloc((size_t)nc + 1, sizeof(int32_t));
+    int32_t *members = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
+    for (int32_t v = 0; v < n; v++) mstart[f2c[v] + 1]++;
+    for (int32_t i = 0; i < nc; i++) mstart[i + 1] += mstart[i];
+    int32_t *fill = (int32_t *)xcalloc((size_t)nc + 1, sizeof(int32_t));
+    memcpy(fill, mstart, sizeof(int32_t) * (size_t)nc);
+    for (int32_t v = 0; v < n; v++) members[fill[f2c[v]]++] = v;
+    free(fill);
+
+    int64_t *acc = (int64_t *)xcalloc((size_t)nc, sizeof(int64_t));
+    int32_t *seen = (int32_t *)xcalloc((size_t)nc, sizeof(int32_t));
+    int32_t *cols = (int32_t *)xcalloc((size_t)nc, sizeof(int32_t));
+    int64_t nnz = 0;
+    xadj_c[0] = 0;
+    for (int32_t i = 0; i < nc; i++) {
+        int64_t cw = 0;
+        int32_t ncols = 0;
+        for (int32_t m = mstart[i]; m < mstart[i + 1]; m++) {
+            int32_t v = members[m];
+            cw += VW(g, v);
+            for (int32_t e = g->xadj[v]; e < g->xadj[v + 1]; e++) {
+                int32_t j = f2c[g->adjncy[e]];
+                if (j == i) continue;
+                if (!seen[j]) { seen[j] = 1; cols[ncols++] = j; }
+                acc[j] += EW(g, e);
+            }
+        }
+        /* ascending columns: plain insertion sort */
+        for (int32_t a = 1; a < ncols; a++) {
+            int32_t x = cols[a], b = a - 1;
+            while (b >= 0 && cols[b] > x) { cols[b + 1] = cols[b]; b--; }
+            cols[b + 1] = x;
+        }
+        for (int32_t a = 0; a < ncols; a++) {
+            int32_t j = cols[a];
+            adjncy_c[nnz] = j;
+            adjwgt_c[nnz] = (int32_t)acc[j];
+            nnz++;
+            acc[j] = 0;
+            seen[j] = 0;
+        }
+        xadj_c[i + 1] = (int32_t)nnz;
+        vwgt_c[i] = (int32_t)cw;
+    }
+    *n_c_out = nc;
+    *nnz_c_out = (int32_t)nnz;
+    free(used); free(id); free(mstart); free(members); free(acc); free(seen); free(cols);
+    return 0;
+}
+
+/* §III-C: a fine vertex takes the block of its coarse representative. */
+void orc_project(int32_t n, const int32_t *f2c, const int32_t *part_coarse, int32_t *part_fine) {
+    for (int32_t v = 0; v < n; v++) part_fine[v] = part_coarse[f2c[v]];
+}
+
+/* §II-A: cut = weight of edges between different blocks, each undirected edge once. */
+int64_t orc_cut(const orc_graph *g, const int32_t *part) {
+    int64_t s = 0;
+    for (int32_t v = 0; v < g->n; v++)
+        for (int32_t e = g->xadj[v]; e < g->xadj[v + 1]; e++)
+            if (part[v] != part[g->adjncy[e]]) s += EW(g, e);
+    return s / 2;
+}
+
+void orc_block_weights(const orc_graph *g, const int32_t *part, int32_t k, int64_t *B) {
+    for (int32_t b = 0; b < k; b++) B[b] = 0;
+    for (int32_t v = 0; v < g->n; v++) B[part[v]] += VW(g, v);
+}
+
+/* splitmix64 finaliser applied to x + gamma (Steele, Lea & Flood 2014). */
+static uint64_t sm64(uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+/* Start-vertex hash of the initial bisection: chained splitmix64 over four words. */
+uint64_t orc_mix4(uint64_t seed, uint64_t a, uint64_t base, uint64_t ks) {
+    return sm64(sm64(sm64(sm64(seed) ^ a) ^ base) ^ ks);
+}
+
+/*
+ * Recursive bisection (§III-B: split into ceil(k/2) and floor(k/2) blocks and
+ * recurse). One bisection of the set S (ascending ids) with k_S blocks:
+ * target = ceil(c(S) * k_L / k_S) with k_L = ceil(k_S/2). Grow the left side
+ * by FIFO breadth-first search inside S from a hashed start vertex; vertices
+ * are marked when enqueued, appended to the left side when dequeued, and the
+ * search stops once the left side weighs at least `target`. When the queue
+ * runs dry, the smallest unmarked vertex of S is enqueued.
+ */
+typedef struct {
+    const orc_graph *g;
+    uint64_t seed;
+    int32_t attempt;
+    int32_t *part;
+    int32_t *inset;  /* inset[v] == set tag while v belongs to the current S */
+    int32_t *marked;
+    int32_t *queue;
+    int32_t tag;
+} rb_ctx;
+
+static int cmp_i32(const void *a, const void *b) {
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+static void rb(rb_ctx *cx, int32_t *S, int32_t size, int32_t ks, int32_t base) {
+    const orc_graph *g = cx->g;
+    if (size == 0) return;
+    if (ks == 1) {
+        for (int32_t i = 0; i < size; i++) cx->part[S[i]] = base;
+        return;
+    }
+    int32_t kl = (ks + 1) / 2;
+    int64_t cs = 0;
+    for (int32_t i = 0; i < size; i++) cs += VW(g, S[i]);
+    __int128 num = (__int128)cs * kl;
+    int64_t target = (int64_t)((num + ks - 1) / ks);
+
+    int32_t tag = ++cx->tag;
+    for (int32_t i = 0; i < size; i++) { cx->inset[S[i]] = tag; cx->marked[S[i]] = 0; }
+    uint64_t h = orc_mix4(cx->seed, (uint64_t)cx->attempt, (uint64_t)base, (uint64_t)ks);
+    int32_t s = S[h % (uint64_t)size];
+
+    int32_t *left = (int32_t *)xcalloc((size_t)size, sizeof(int32_t));
+    int32_t nleft = 0, head = 0, tail = 0, scan = 0;
+    int64_t cleft = 0;
+    cx->marked[s] = 1;
+    cx->queue[tail++] = s;
+    for (;;) {
+        if (head == tail) {
+            while (scan < size && cx->marked[S[scan]]) scan++;
+            if (scan == size) break; /* cannot happen: target <= c(S) */
+            cx->marked[S[scan]] = 1;
+            cx->queue[tail++] = S[scan];
+        }
+        int32_t v = cx->queue[head++];
+        left[nleft++] = v;
+        cleft += VW(g, v);
+        if (cleft >= target) break;
+        for (int32_t e = g->xadj[v]; e < g->xadj[v + 1]; e++) {
+            int32_t u = g->adjncy[e];
+            if (cx->inset[u] == tag && !cx->marked[u]) {
+                cx->marked[u] = 1;
+                cx->queue[tail++] = u;
+            }
+        }
+    }
+    /* right side: S minus left, ascending */
+    for (int32_t i = 0; i < nleft; i++) cx->marked[left[i]] = 2;
+    int32_t *right = (int32_t *)xcalloc((size_t)size, sizeof(int32_t));
+    int32_t nright = 0;
+    for (int32_t i = 0; i < size; i++)
+        if (cx->marked[S[i]] != 2) right[nright++] = S[i];
+    qsort(left, (size_t)nleft, sizeof(int32_t), cmp_i32);
+    rb(cx, left, nleft, kl, base);
+    rb(cx, right, nright, ks - kl, base + kl);
+    free(left);
+    free(right);
+}
+
+void orc_recursive_bisection(const orc_graph *g, int32_t k, uint64_t seed, int32_t attempt,
+                             int32_t *part_out) {
+    int32_t n = g->n;
+    rb_ctx cx;
+    cx.g = g;
+    cx.seed = seed;
+    cx.attempt = attempt;
+    cx.part = part_out;
+    cx.inset = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
+    cx.marked = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
+    cx.queue = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
+    cx.tag = 0;
+    int32_t *S = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
+    for (int32_t v = 0; v < n; v++) S[v] = v;
+    rb(&cx, S, n, k, 0);
+    free(S);
+    free(cx.inset);
+    free(cx.marked);
+    free(cx.queue);
+}
+
+/*
+ * Greedy rebalance (project-defined; the paper delegates this to KaHIP's
+ * local search). While a block exceeds L_max, apply the single move (v, t)
+ * with v in an overloaded block, t != P(v), B[t] + c(v) <= L_max, of maximum
+ * gain conn(v,t) - conn(v,P(v)) (§II-A gain); ties -> lowest v, then lowest t.
+ */
+int orc_rebalance(const orc_graph *g, int32_t k, int64_t lmax, int32_t *part) {
+    int64_t *B = (int64_t *)xcalloc((size_t)k, sizeof(int64_t));
+    int64_t *conn = (int64_t *)xcalloc((size_t)k, sizeof(int64_t));
+    orc_block_weights(g, part, k, B);
+    int balanced = 0;
+    for (;;) {
+        int over = 0;
+        for (int32_t b = 0; b < k; b++) over |= (B[b] > lmax);
+        if (!over) { balanced = 1; break; }
+        int32_t bv = -1, bt = -1;
+        int64_t bgain = 0;
+        for (int32_t v = 0; v < g->n; v++) {
+            int32_t pv = part[v];
+            if (B[pv] <= lmax) continue;
+            for (int32_t b = 0; b < k; b++) conn[b] = 0;
+            for (int32_t e = g->xadj[v]; e < g->xadj[v + 1]; e++) conn[part[g->adjncy[e]]] += EW(g, e);
+            for (int32_t t = 0; t < k; t++) {
+                if (t == pv || B[t] + VW(g, v) > lmax) continue;
+                int64_t gain = conn[t] - conn[pv];
+                if (bv < 0 || gain > bgain) { bv = v; bt = t; bgain = gain; }
+            }
+        }
+        if (bv < 0) break;
+        B[part[bv]] -= VW(g, bv);
+        B[bt] += VW(g, bv);
+        part[bv] = bt;
+    }
+    free(B);
+    free(conn);
+    return balanced;
+}
+
+/* §III-B / §IV-B: best of `attempts` tries by (imbalanced, cut, attempt index). */
+int orc_initial_partition(const orc_graph *g, int32_t k, int64_t lmax, uint64_t seed,
+                          int32_t attempts, int32_t rounds_refine, int32_t dir_alternate,
+                          int32_t *part_out) {
+    int32_t n = g->n;
+    int32_t *P = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
+    int best = -1, best_bal = 0;
+    int64_t best_cut = 0;
+    for (int32_t a = 0; a < attempts; a++) {
+        orc_recursive_bisection(g, k, seed, a, P);
+        orc_lp_refine(g, k, lmax, rounds_refine, dir_alternate, P, NULL);
+        int bal = orc_rebalance(g, k, lmax, P);
+        int64_t cut = orc_cut(g, P);
+        int better = best < 0 || (bal && !best_bal) || (bal == best_bal && cut < best_cut);
+        if (better) {
+            best = a;
+            best_bal = bal;
+            best_cut = cut;
+            memcpy(part_out, P, sizeof(int32_t) * (size_t)n);
+        }
+    }
+    free(P);
+    return best;
+}
+
+/* Isolated vertices (no neighbours), ascending id, each into the lightest block (ties -> lowest). */
+void orc_fill_isolated(const orc_graph *g, int32_t k, int32_t *part, int64_t *B) {
+    for (int32_t v = 0; v < g->n; v++) {
+        if (g->xadj[v + 1] != g->xadj[v]) continue;
+        int32_t b = 0;
+        for (int32_t t = 1; t < k; t++)
+            if (B[t] < B[b]) b = t;
+        part[v] = b;
+        B[b] += VW(g, v);
+    }
+}
+
+typedef struct {
+    orc_graph g;
+    int32_t *xadj, *adjncy, *adjwgt, *vwgt, *f2c; /* f2c maps this level to the next */
+} level_t;
+
+/*
+ * §III multilevel scheme with the project's stop rules:
+ *  - U_c = max(c_max, L_max - ceil(W/k)) during coarsening (the paper only
+ *    names "a given upper bound U"); U = L_max during refinement (§III-C).
+ *  - vertices without neighbours are set aside before coarsening and filled
+ *    in at the end;
+ *  - coarsen while n > coarsest_per_k * k; discard a level that did not
+ *    shrink; stop after a level with stall_den * n' > stall_num * n.
+ */
+int orc_partition(const orc_graph *g, int32_t k, double eps, const orc_params *p,
+                  int32_t *part_out, orc_result *res) {
+    int32_t n = g->n;
+    int64_t W = orc_total_vwgt(g);
+    int64_t lmax = orc_lmax(W, k, eps);
+    int64_t cmax = 0;
+    for (int32_t v = 0; v < n; v++) if (VW(g, v) > cmax) cmax = VW(g, v);
+    int64_t ceil_wk = W / k + (W % k != 0);
+    int64_t ucl = lmax - ceil_wk;
+    if (ucl < cmax) ucl = cmax;
+
+    /* level 0: vertices with at least one neighbour, renumbered ascending */
+    int32_t *newid = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
+    int32_t n0 = 0;
+    for (int32_t v = 0; v < n; v++) newid[v] = (g->xadj[v + 1] > g->xadj[v]) ? n0++ : -1;
+    int32_t nnz = g->xadj[n];
+
+    int32_t maxlev = 64;
+    level_t *lev = (level_t *)xcalloc((size_t)maxlev, sizeof(level_t));
+    lev[0].xadj = (int32_t *)xcalloc((size_t)n0 + 1, sizeof(int32_t));
+    lev[0].adjncy = (int32_t *)xcalloc((size_t)nnz, sizeof(int32_t));
+    lev[0].adjwgt = (int32_t *)xcalloc((size_t)nnz, sizeof(int32_t));
+    lev[0].vwgt = (int32_t *)xcalloc((size_t)n0, sizeof(int32_t));
+    {
+        int32_t pos = 0;
+        for (int32_t v = 0; v < n; v++) {
+            if (newid[v] < 0) continue;
+            int32_t i = newid[v];
+            lev[0].vwgt[i] = (int32_t)VW(g, v);
+            for (int32_t e = g->xadj[v]; e < g->xadj[v + 1]; e++) {
+                lev[0].adjncy[pos] = newid[g->adjncy[e]];
+                lev[0].adjwgt[pos] = (int32_t)EW(g, e);
+                pos++;
+            }
+            lev[0].xadj[i + 1] = pos;
+        }
+    }
+    lev[0].g = (orc_graph){n0, lev[0].xadj, lev[0].adjncy, lev[0].adjwgt, lev[0].vwgt};
+
+    int64_t ev_cluster = 0, ev_refine = 0;
+    int32_t L = 0;
+    while (lev[L].g.n > (int64_t)p->coarsest_per_k * k && L + 1 < maxlev) {
+        level_t *f = &lev[L], *c = &lev[L + 1];
+        int32_t fn = f->g.n, fnnz = f->g.xadj[fn];
+        int32_t *labels = (int32_t *)xcalloc((size_t)fn, sizeof(int32_t));
+        orc_lp_stats st;
+        orc_lp_cluster(&f->g, ucl, p->rounds_coarsen, p->dir_alternate, labels, &st);
+        ev_cluster += st.edge_visits;
+        c->xadj = (int32_t *)xcalloc((size_t)fn + 1, sizeof(int32_t));
+        c->adjncy = (int32_t *)xcalloc((size_t)fnnz, sizeof(int32_t));
+        c->adjwgt = (int32_t *)xcalloc((size_t)fnnz, sizeof(int32_t));
+        c->vwgt = (int32_t *)xcalloc((size_t)fn, sizeof(int32_t));
+        f->f2c = (int32_t *)xcalloc((size_t)fn, sizeof(int32_t));
+        int32_t nc, nnzc;
+        orc_contract(&f->g, labels, c->xadj, c->adjncy, c->adjwgt, c->vwgt, f->f2c, &nc, &nnzc);
+        free(labels);
+        c->g = (orc_graph){nc, c->xadj, c->adjncy, c->adjwgt, c->vwgt};
+        if (nc == fn) {
+            free(c->xadj); free(c->adjncy); free(c->adjwgt); free(c->vwgt); free(f->f2c);
+            f->f2c = NULL;
+            break;
+        }
+        L++;
+        if ((int64_t)p->stall_den * nc > (int64_t)p->stall_num * fn) break;
+    }
+
+    /* initial partition on the coarsest level, then refine every level */
+    int32_t *P = (int32_t *)xcalloc((size_t)lev[L].g.n, sizeof(int32_t));
+    if (lev[L].g.n > 0)
+        orc_initial_partition(&lev[L].g, k, lmax, p->seed, p->attempts, p->rounds_refine,
+                              p->dir_alternate, P);
+    for (int32_t l = L; l >= 0; l--) {
+        if (l < L) {
+            int32_t *Pf = (int32_t *)xcalloc((size_t)lev[l].g.n, sizeof(int32_t));
+            orc_project(lev[l].g.n, lev[l].f2c, P, Pf);
+            free(P);
+            P = Pf;
+        }
+        orc_lp_stats st;
+        orc_lp_refine(&lev[l].g, k, lmax, p->rounds_refine, p->dir_alternate, P, &st);
+        ev_refine += st.edge_visits;
+    }
+
+    /* back to original ids, then place the isolated vertices */
+    int64_t *B = (int64_t *)xcalloc((size_t)k, sizeof(int64_t));
+    int32_t niso = 0;
+    for (int32_t v = 0; v < n; v++) {
+        if (newid[v] >= 0) { part_out[v] = P[newid[v]]; B[P[newid[v]]] += VW(g, v); }
+        else { part_out[v] = -1; niso++; }
+    }
+    orc_fill_isolated(g, k, part_out, B);
+
+    int64_t maxb = 0;
+    for (int32_t b = 0; b < k; b++) if (B[b] > maxb) maxb = B[b];
+    if (res) {
+        res->cut = orc_cut(g, part_out);
+        res->max_block_w = maxb;
+        res->lmax = lmax;
+        res->ucl = ucl;
+        res->balanced = maxb <= lmax;
+        res->levels = L + 1;
+        res->edge_visits_cluster = ev_cluster;
+        res->edge_visits_refine = ev_refine;
+        res->coarsest_n = lev[L].g.n;
+        res->n_isolated = niso;
+    }
+    for (int32_t l = 0; l <= L; l++) {
+        free(lev[l].xadj); free(lev[l].adjncy); free(lev[l].adjwgt); free(lev[l].vwgt);
+        free(lev[l].f2c);
+    }
+    free(lev);
+    free(P);
+    free(B);
+    free(newid);
+    return (maxb <= lmax) ? 0 : 1;
+}

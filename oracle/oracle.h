@@ -1,0 +1,100 @@
+/*
+ * oracle.h — plain, slow, single-threaded CPU oracle for size-constrained
+ * label propagation (LP) clustering / refinement, contraction, projection,
+ * initial partitioning and the multilevel driver.
+ *
+ * TEST INFRASTRUCTURE ONLY. Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark use it. It shares no code, header, table or
+ * helper with the GPU library; the two only consume the same generated inputs.
+ *
+ * All arithmetic is integer: int32 weights, int64 sums. Every result is
+ * therefore independent of summation order and must be matched bit-exactly.
+ *
+ * Readings of the paper used here (round-synchronous LP, direction
+ * alternation, ascending-ID admission, stop rules, isolated-vertex handling,
+ * the project-defined initial partitioner) are documented per function in
+ * oracle.c.
+ */
+#ifndef ORC_ORACLE_H
+#define ORC_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int32_t n;
+    const int32_t *xadj;   /* [n+1] */
+    const int32_t *adjncy; /* [xadj[n]] */
+    const int32_t *adjwgt; /* [xadj[n]] or NULL = unit */
+    const int32_t *vwgt;   /* [n] or NULL = unit */
+} orc_graph;
+
+typedef struct {
+    int32_t rounds_run;
+    int64_t moves;
+    int64_t edge_visits;
+} orc_lp_stats;
+
+typedef struct {
+    int32_t rounds_coarsen;   /* 10 */
+    int32_t rounds_refine;    /* 25 */
+    int32_t coarsest_per_k;   /* 60 */
+    int32_t attempts;         /* 4 */
+    int32_t stall_num;        /* 19 */
+    int32_t stall_den;        /* 20 */
+    int32_t dir_alternate;    /* 1 */
+    uint64_t seed;
+} orc_params;
+
+typedef struct {
+    int64_t cut, max_block_w, lmax, ucl;
+    int32_t balanced, levels;
+    int64_t edge_visits_cluster, edge_visits_refine;
+    int32_t coarsest_n, n_isolated;
+} orc_result;
+
+int64_t orc_lmax(int64_t total_vwgt, int32_t k, double eps);
+int64_t orc_total_vwgt(const orc_graph *g);
+
+/* One LP round over all vertices; returns the number of admitted moves. */
+int64_t orc_lp_round(const orc_graph *g, int32_t *C, int64_t *W, int32_t nlabels, int64_t U,
+                     int32_t r, int32_t dir_alternate, int32_t *prop_out);
+
+int orc_lp_cluster(const orc_graph *g, int64_t U, int32_t rounds, int32_t dir_alternate,
+                   int32_t *labels_out, orc_lp_stats *st);
+int orc_lp_refine(const orc_graph *g, int32_t k, int64_t lmax, int32_t rounds,
+                  int32_t dir_alternate, int32_t *part_inout, orc_lp_stats *st);
+
+/* Coarse graph into caller buffers sized for the fine graph (n+1, nnz, nnz, n, n). */
+int orc_contract(const orc_graph *g, const int32_t *labels, int32_t *xadj_c, int32_t *adjncy_c,
+                 int32_t *adjwgt_c, int32_t *vwgt_c, int32_t *f2c, int32_t *n_c, int32_t *nnz_c);
+
+void orc_project(int32_t n, const int32_t *f2c, const int32_t *part_coarse, int32_t *part_fine);
+
+int64_t orc_cut(const orc_graph *g, const int32_t *part);
+void orc_block_weights(const orc_graph *g, const int32_t *part, int32_t k, int64_t *B);
+
+uint64_t orc_mix4(uint64_t seed, uint64_t a, uint64_t base, uint64_t ks);
+
+/* Recursive BFS-grow bisection of the whole graph (one attempt). */
+void orc_recursive_bisection(const orc_graph *g, int32_t k, uint64_t seed, int32_t attempt,
+                             int32_t *part_out);
+/* Greedy rebalance; returns 1 if balanced afterwards, 0 if no move remained. */
+int orc_rebalance(const orc_graph *g, int32_t k, int64_t lmax, int32_t *part);
+/* Best of `attempts` (bisection -> lp_refine -> rebalance). Returns chosen attempt. */
+int orc_initial_partition(const orc_graph *g, int32_t k, int64_t lmax, uint64_t seed,
+                          int32_t attempts, int32_t rounds_refine, int32_t dir_alternate,
+                          int32_t *part_out);
+
+/* Isolated-vertex fill; returns nothing, updates part and B. */
+void orc_fill_isolated(const orc_graph *g, int32_t k, int32_t *part, int64_t *B);
+
+int orc_partition(const orc_graph *g, int32_t k, double eps, const orc_params *p,
+                  int32_t *part_out, orc_result *res);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
