@@ -1,0 +1,171 @@
+/*
+ * gp.h — C ABI of the MI355X (gfx950) size-constrained label-propagation
+ * graph partitioner.
+ *
+ * Method: Akhremtsev, Sanders, Schulz, "High-Quality Shared-Memory Graph
+ * Partitioning" (arXiv 1710.08231). The library implements the data-parallel
+ * hot path of its multilevel scheme (§III, §IV): size-constrained label
+ * propagation used to cluster (§III-A, §IV-A) and to refine a k-way partition
+ * (§III-C, §IV-C with U = L_max), the contraction that builds each coarse
+ * graph (§III-A, §IV-A), projection (§III-C), and a multilevel driver around
+ * them with a project-defined initial partitioner (§III-B: recursive
+ * bisection, best of several tries).
+ *
+ * Label propagation is round-synchronous: in round r every vertex proposes a
+ * move from the labels and label weights of the round start; a move to label
+ * L requires L != own label, (r even: L < own; r odd: L > own) when direction
+ * alternation is on, W[L] + c(v) <= U (§II-A: a cluster is overloaded only
+ * when it exceeds its bound), and a strictly larger connection than the own
+ * label; ties go to the smallest label. The moves to one target t are
+ * admitted in ascending vertex id while W[t] + (weight of all proposers to t
+ * up to and including v) <= U (§IV-A: a move happens only if the cluster size
+ * is still feasible). The call stops early after two idle rounds in a row.
+ * Results are deterministic and bit-identical to the plain CPU definition.
+ *
+ * Conventions for every entry point
+ *  - Graph: symmetric CSR, no self-loops, no duplicate edges, rows need not be
+ *    sorted. All arrays inside gp_graph are DEVICE pointers on the current HIP
+ *    device. adjwgt == NULL means unit edge weights, vwgt == NULL unit vertex
+ *    weights. Weights are int32 >= 1; sums are int64.
+ *  - Outputs named *_host are host pointers; every other array is a device
+ *    pointer supplied and owned by the caller.
+ *  - Work is ordered on `stream`. Calls that return host values synchronise
+ *    the stream before returning. The library allocates its own temporary
+ *    device memory stream-ordered (hipMallocAsync on `stream`) and frees it
+ *    before returning; it never frees caller memory.
+ *  - Return value: GP_OK (0), GP_WARN_IMBALANCED (1, valid result whose
+ *    largest block exceeds L_max), or a negative error code; gp_strerror()
+ *    and gp_last_error() describe it. On error the outputs are unspecified.
+ *  - Reentrant for distinct output buffers; the only global state is a
+ *    thread-local last-error message.
+ */
+#ifndef GP_H
+#define GP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GP_OK 0
+#define GP_WARN_IMBALANCED 1
+#define GP_ERR_ARG (-1)       /* NULL pointer, n < 0, k < 1, eps < 0, rounds < 0, U < 1 */
+#define GP_ERR_GRAPH (-2)     /* bad offsets, neighbour id out of range, label out of range */
+#define GP_ERR_WORKSPACE (-3) /* reserved */
+#define GP_ERR_OVERFLOW (-4)  /* nnz >= 2^31 or a weight sum that does not fit its type */
+#define GP_ERR_HIP (-5)       /* a HIP runtime call failed */
+
+/* G = (V, E, c, w) of §II-A. n vertices, nnz = 2|E| directed CSR entries. */
+typedef struct {
+    int32_t n;
+    int32_t nnz;
+    const int32_t *xadj;   /* [n+1], xadj[0] = 0, xadj[n] = nnz */
+    const int32_t *adjncy; /* [nnz], neighbour ids in [0, n) */
+    const int32_t *adjwgt; /* [nnz] edge weights w >= 1, or NULL for unit weights */
+    const int32_t *vwgt;   /* [n] vertex weights c >= 1, or NULL for unit weights */
+} gp_graph;
+
+typedef struct {
+    int32_t rounds_run;  /* rounds executed before the two-idle-rounds stop (<= rounds) */
+    int64_t moves;       /* admitted moves summed over the rounds */
+    int64_t edge_visits; /* rounds_run * nnz */
+    float ms;            /* device time of the call (HIP events on `stream`) */
+} gp_lp_stats;
+
+/* Multilevel parameters; gp_default_params() fills the defaults shown. */
+typedef struct {
+    int32_t rounds_coarsen; /* 10: LP rounds per clustering (paper §VI configuration) */
+    int32_t rounds_refine;  /* 25: LP rounds per refinement (paper §VI configuration) */
+    int32_t coarsest_per_k; /* 60: coarsen while n > coarsest_per_k * k */
+    int32_t attempts;       /* 4: initial partitioning tries (paper: max(p, 4)) */
+    int32_t stall_num;      /* 19: stop after a level with stall_den*n' > stall_num*n */
+    int32_t stall_den;      /* 20 */
+    int32_t dir_alternate;  /* 1: direction alternation of synchronous rounds */
+    uint64_t seed;          /* start-vertex hash of the initial bisections */
+} gp_params;
+
+typedef struct {
+    int64_t cut;          /* sum of w over edges between blocks, each edge once */
+    int64_t max_block_w;  /* max_b c(V_b) */
+    int64_t lmax;         /* (1+eps)*ceil(c(V)/k), floor of the binary64 product */
+    int64_t ucl;          /* clustering bound max(c_max, lmax - ceil(c(V)/k)) */
+    int32_t balanced;     /* max_block_w <= lmax */
+    int32_t levels;       /* graphs in the hierarchy, level 0 included */
+    int32_t coarsest_n;   /* vertices of the coarsest graph */
+    int32_t n_isolated;   /* vertices without neighbours (placed at the end) */
+    int64_t edge_visits_cluster; /* sum over levels of rounds_run * nnz in clustering */
+    int64_t edge_visits_refine;  /* same for refinement */
+    float ms_coarsen, ms_init, ms_refine, ms_total; /* device-timed phases */
+} gp_result;
+
+void gp_default_params(gp_params *p);
+
+/* §II-A balance bound: floor((1+eps) * ceil(total_vwgt / k)) in binary64. Pure host function. */
+int64_t gp_lmax(int64_t total_vwgt, int32_t k, double eps);
+
+/*
+ * Size-constrained LP clustering (§III-A, §IV-A). Starts from singletons
+ * (C[v] = v, W[v] = c(v)) and runs up to `rounds` rounds with bound U >= 1.
+ * labels_out: [n] device int32, receives cluster labels in [0, n) (leader ids,
+ * not compacted). st_host (may be NULL) receives the statistics.
+ */
+int gp_lp_cluster(const gp_graph *g, int64_t U, int32_t rounds, int32_t dir_alternate,
+                  int32_t *labels_out, gp_lp_stats *st_host, hipStream_t stream);
+
+/*
+ * LP refinement (§III-C: LP started from a partition with U = L_max).
+ * part_inout: [n] device int32 with 0 <= part[v] < k; overwritten with the
+ * refined partition. lmax >= 1 bounds every block.
+ */
+int gp_lp_refine(const gp_graph *g, int32_t k, int64_t lmax, int32_t rounds, int32_t dir_alternate,
+                 int32_t *part_inout, gp_lp_stats *st_host, hipStream_t stream);
+
+/*
+ * Contraction (§III-A; coarse ids by a prefix sum over used labels, §IV-A).
+ * labels: [n] device int32 in [0, n). Coarse vertex i = the rank of its label
+ * among the used labels; c'(i) = sum of c over the cluster; the coarse edge
+ * (i, j), i != j, carries the summed weight of fine edges between the two
+ * clusters. Coarse rows ascending, columns ascending within a row.
+ * Outputs (device, caller-sized for the fine graph): xadj_c [n+1],
+ * adjncy_c [nnz], adjwgt_c [nnz], vwgt_c [n], f2c [n] (fine -> coarse id).
+ * n_c_host / nnz_c_host receive the coarse sizes.
+ */
+int gp_contract(const gp_graph *g, const int32_t *labels, int32_t *xadj_c, int32_t *adjncy_c,
+                int32_t *adjwgt_c, int32_t *vwgt_c, int32_t *f2c, int32_t *n_c_host,
+                int32_t *nnz_c_host, hipStream_t stream);
+
+/* Projection (§III-C): part_fine[v] = part_coarse[f2c[v]] for v < n (device arrays). */
+int gp_project(int32_t n, const int32_t *f2c, const int32_t *part_coarse, int32_t *part_fine,
+               hipStream_t stream);
+
+/* §II-A cut (each undirected edge once) and block weights B[k] (device int64) of a partition. */
+int gp_cut_and_blocks(const gp_graph *g, int32_t k, const int32_t *part, int64_t *cut_host,
+                      int64_t *block_w_dev, hipStream_t stream);
+
+/*
+ * Multilevel k-way partition (§III scheme): coarsen with gp_lp_cluster /
+ * gp_contract under U = max(c_max, L_max - ceil(c(V)/k)) while
+ * n > coarsest_per_k * k (vertices without neighbours are set aside first;
+ * a level that does not shrink is discarded; a level with
+ * stall_den * n' > stall_num * n is the last), partition the coarsest graph
+ * (best of `attempts` recursive BFS bisections, each followed by LP
+ * refinement and a greedy rebalance), then project and refine every level
+ * with U = L_max, and place vertices without neighbours, in ascending id,
+ * into the currently lightest block.
+ * part_out: [n] device int32 in [0, k). res_host may be NULL.
+ * Returns GP_OK, GP_WARN_IMBALANCED, or an error.
+ */
+int gp_partition(const gp_graph *g, int32_t k, double eps, const gp_params *p, int32_t *part_out,
+                 gp_result *res_host, hipStream_t stream);
+
+const char *gp_strerror(int code);
+const char *gp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,223 @@
+"""MI355X (gfx950) size-constrained label-propagation graph partitioner.
+
+Python binding of ``libgp.so`` (C ABI in ``include/gp.h``). This module only
+marshals arguments: graphs are dicts of int32 torch tensors on the GPU
+(``xadj``, ``adjncy``, optional ``adjwgt`` / ``vwgt``), outputs are torch
+tensors the binding allocates, and the current torch stream is passed to the
+library. Every step of the method runs in the library's HIP kernels; there is
+no CPU fallback: if ``libgp.so`` is missing or no GPU is present the calls
+raise.
+
+Method: Akhremtsev, Sanders, Schulz, "High-Quality Shared-Memory Graph
+Partitioning" (arXiv 1710.08231): size-constrained label propagation for
+clustering (§III-A, §IV-A) and refinement (§III-C), contraction (§III-A,
+§IV-A), projection (§III-C), inside the multilevel scheme of §III.
+"""
+import ctypes
+import os
+import subprocess
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_ROOT = os.path.dirname(_HERE)
+LIB_PATH = os.path.join(_HERE, "libgp.so")
+SOURCES = ["lp.hip", "contract.hip", "initpart.hip", "partition.hip"]
+HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+GP_OK, GP_WARN_IMBALANCED = 0, 1
+
+_lib = None
+
+
+class GPError(RuntimeError):
+    pass
+
+
+def build():
+    """Compile libgp.so for gfx950 with hipcc (always rebuilds)."""
+    src = [os.path.join(_HERE, "csrc", f) for f in SOURCES]
+    tmp = LIB_PATH + ".tmp"
+    cmd = ["hipcc", *HIPCC_FLAGS, "-I" + os.path.join(_ROOT, "include"), "-o", tmp, *src]
+    subprocess.check_call(cmd)
+    os.replace(tmp, LIB_PATH)
+
+
+class Graph(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int32), ("xadj", ctypes.c_void_p),
+                ("adjncy", ctypes.c_void_p), ("adjwgt", ctypes.c_void_p), ("vwgt", ctypes.c_void_p)]
+
+
+class LPStats(ctypes.Structure):
+    _fields_ = [("rounds_run", ctypes.c_int32), ("moves", ctypes.c_int64),
+                ("edge_visits", ctypes.c_int64), ("ms", ctypes.c_float)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("rounds_coarsen", ctypes.c_int32), ("rounds_refine", ctypes.c_int32),
+                ("coarsest_per_k", ctypes.c_int32), ("attempts", ctypes.c_int32),
+                ("stall_num", ctypes.c_int32), ("stall_den", ctypes.c_int32),
+                ("dir_alternate", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("cut", ctypes.c_int64), ("max_block_w", ctypes.c_int64), ("lmax", ctypes.c_int64),
+                ("ucl", ctypes.c_int64), ("balanced", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("coarsest_n", ctypes.c_int32), ("n_isolated", ctypes.c_int32),
+                ("edge_visits_cluster", ctypes.c_int64), ("edge_visits_refine", ctypes.c_int64),
+                ("ms_coarsen", ctypes.c_float), ("ms_init", ctypes.c_float),
+                ("ms_refine", ctypes.c_float), ("ms_total", ctypes.c_float)]
+
+
+EXPORTS = ["gp_default_params", "gp_lmax", "gp_lp_cluster", "gp_lp_refine", "gp_contract",
+           "gp_project", "gp_cut_and_blocks", "gp_partition", "gp_strerror", "gp_last_error"]
+
+
+def load():
+    """Load libgp.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise GPError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+    lib = ctypes.CDLL(LIB_PATH)
+    G = ctypes.POINTER(Graph)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.gp_default_params.argtypes = [ctypes.POINTER(Params)]
+    lib.gp_lmax.restype = i64
+    lib.gp_lmax.argtypes = [i64, i32, ctypes.c_double]
+    lib.gp_lp_cluster.argtypes = [G, i64, i32, i32, vp, ctypes.POINTER(LPStats), vp]
+    lib.gp_lp_refine.argtypes = [G, i32, i64, i32, i32, vp, ctypes.POINTER(LPStats), vp]
+    lib.gp_contract.argtypes = [G, vp, vp, vp, vp, vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i32), vp]
+    lib.gp_project.argtypes = [i32, vp, vp, vp, vp]
+    lib.gp_cut_and_blocks.argtypes = [G, i32, vp, ctypes.POINTER(i64), vp, vp]
+    lib.gp_partition.argtypes = [G, i32, ctypes.c_double, ctypes.POINTER(Params), vp,
+                                 ctypes.POINTER(Result), vp]
+    lib.gp_strerror.restype = ctypes.c_char_p
+    lib.gp_strerror.argtypes = [ctypes.c_int]
+    lib.gp_last_error.restype = ctypes.c_char_p
+    lib.gp_last_error.argtypes = []
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc < 0:
+        lib = load()
+        raise GPError(f"{lib.gp_strerror(rc).decode()} ({rc}): {lib.gp_last_error().decode()}")
+    return rc
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise GPError("no GPU: the partitioner runs only on the MI355X")
+    return torch
+
+
+def _stream():
+    return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _gstruct(g):
+    torch = _torch()
+    for key in ("xadj", "adjncy", "adjwgt", "vwgt"):
+        t = g.get(key)
+        if t is not None and (t.dtype != torch.int32 or not t.is_cuda or not t.is_contiguous()):
+            raise GPError(f"graph['{key}'] must be a contiguous int32 CUDA tensor")
+    n = g["xadj"].numel() - 1
+    nnz = g["adjncy"].numel()
+    return Graph(n, nnz, _ptr(g["xadj"]), _ptr(g["adjncy"]), _ptr(g.get("adjwgt")), _ptr(g.get("vwgt")))
+
+
+def to_device(g, device="cuda"):
+    """numpy CSR dict -> dict of int32 CUDA tensors (inputs resident in HBM)."""
+    torch = _torch()
+    out = {}
+    for key in ("xadj", "adjncy", "adjwgt", "vwgt"):
+        if g.get(key) is not None:
+            out[key] = torch.from_numpy(g[key]).to(device=device, dtype=torch.int32).contiguous()
+    return out
+
+
+def lmax(total_vwgt, k, eps):
+    return int(load().gp_lmax(total_vwgt, k, eps))
+
+
+def default_params():
+    p = Params()
+    load().gp_default_params(ctypes.byref(p))
+    return p
+
+
+def lp_cluster(g, U, rounds=10, dir_alternate=1):
+    torch = _torch()
+    gs = _gstruct(g)
+    labels = torch.empty(gs.n, dtype=torch.int32, device=g["xadj"].device)
+    st = LPStats()
+    _check(load().gp_lp_cluster(ctypes.byref(gs), U, rounds, dir_alternate, _ptr(labels), ctypes.byref(st),
+                                _stream()))
+    return labels, {"rounds_run": st.rounds_run, "moves": st.moves, "edge_visits": st.edge_visits, "ms": st.ms}
+
+
+def lp_refine(g, part, k, lmax_, rounds=25, dir_alternate=1):
+    torch = _torch()
+    gs = _gstruct(g)
+    P = part.to(dtype=torch.int32).clone().contiguous()
+    st = LPStats()
+    _check(load().gp_lp_refine(ctypes.byref(gs), k, lmax_, rounds, dir_alternate, _ptr(P), ctypes.byref(st),
+                               _stream()))
+    return P, {"rounds_run": st.rounds_run, "moves": st.moves, "edge_visits": st.edge_visits, "ms": st.ms}
+
+
+def contract(g, labels):
+    torch = _torch()
+    gs = _gstruct(g)
+    dev = g["xadj"].device
+    xc = torch.empty(gs.n + 1, dtype=torch.int32, device=dev)
+    ac = torch.empty(max(gs.nnz, 1), dtype=torch.int32, device=dev)
+    wc = torch.empty(max(gs.nnz, 1), dtype=torch.int32, device=dev)
+    vc = torch.empty(max(gs.n, 1), dtype=torch.int32, device=dev)
+    f2c = torch.empty(max(gs.n, 1), dtype=torch.int32, device=dev)
+    nc, nnzc = ctypes.c_int32(), ctypes.c_int32()
+    lab = labels.to(dtype=torch.int32).contiguous()
+    _check(load().gp_contract(ctypes.byref(gs), _ptr(lab), _ptr(xc), _ptr(ac), _ptr(wc), _ptr(vc), _ptr(f2c),
+                              ctypes.byref(nc), ctypes.byref(nnzc), _stream()))
+    nc, nnzc = nc.value, nnzc.value
+    cg = {"xadj": xc[:nc + 1], "adjncy": ac[:nnzc], "adjwgt": wc[:nnzc], "vwgt": vc[:nc]}
+    return cg, f2c[:gs.n]
+
+
+def project(f2c, part_coarse):
+    torch = _torch()
+    out = torch.empty_like(f2c)
+    _check(load().gp_project(f2c.numel(), _ptr(f2c), _ptr(part_coarse.contiguous()), _ptr(out), _stream()))
+    return out
+
+
+def cut_and_blocks(g, part, k):
+    torch = _torch()
+    gs = _gstruct(g)
+    B = torch.empty(k, dtype=torch.int64, device=g["xadj"].device)
+    cut = ctypes.c_int64()
+    _check(load().gp_cut_and_blocks(ctypes.byref(gs), k, _ptr(part.contiguous()), ctypes.byref(cut), _ptr(B),
+                                    _stream()))
+    return cut.value, B
+
+
+def partition(g, k, eps=0.03, **params):
+    torch = _torch()
+    gs = _gstruct(g)
+    p = default_params()
+    for key, val in params.items():
+        setattr(p, key, val)
+    part = torch.empty(max(gs.n, 1), dtype=torch.int32, device=g["xadj"].device)
+    r = Result()
+    code = _check(load().gp_partition(ctypes.byref(gs), k, eps, ctypes.byref(p), _ptr(part), ctypes.byref(r),
+                                      _stream()))
+    res = {f: getattr(r, f) for f, _ in Result._fields_}
+    res["code"] = code
+    return part[:gs.n], res

@@ -1,0 +1,207 @@
+// gp_common.hpp — internal definitions shared by the gfx950 kernels of the
+// label-propagation partitioner: error plumbing, the per-call scratch
+// allocator (stream-ordered), and wave64 / workgroup primitives.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "gp.h"
+
+namespace gp {
+
+constexpr int kWave = 64;
+
+void set_error(const char *msg);
+const char *last_error();
+
+// Returns GP_ERR_HIP (with a message) when a HIP call fails.
+#define GP_HIP(expr)                                                              \
+    do {                                                                          \
+        hipError_t _e = (expr);                                                   \
+        if (_e != hipSuccess) {                                                   \
+            ::gp::set_error((std::string(#expr) + ": " + hipGetErrorString(_e)).c_str()); \
+            return GP_ERR_HIP;                                                    \
+        }                                                                         \
+    } while (0)
+
+#define GP_TRY(expr)                  \
+    do {                              \
+        int _rc = (expr);             \
+        if (_rc < 0) return _rc;      \
+    } while (0)
+
+#define GP_LAUNCH_CHECK() GP_HIP(hipGetLastError())
+
+// Stream-ordered scratch memory for one library call. Every buffer is
+// released (hipFreeAsync on the same stream) when the object goes out of scope.
+class Scratch {
+  public:
+    explicit Scratch(hipStream_t s) : s_(s) {}
+    ~Scratch() { release(); }
+    Scratch(const Scratch &) = delete;
+    Scratch &operator=(const Scratch &) = delete;
+
+    template <typename T>
+    int alloc(T **out, size_t count) {
+        void *p = nullptr;
+        size_t bytes = (count ? count : 1) * sizeof(T);
+        hipError_t e = hipMallocAsync(&p, bytes, s_);
+        if (e != hipSuccess) {
+            set_error((std::string("hipMallocAsync(") + std::to_string(bytes) + "): " +
+                       hipGetErrorString(e)).c_str());
+            *out = nullptr;
+            return GP_ERR_HIP;
+        }
+        ptrs_.push_back(p);
+        *out = static_cast<T *>(p);
+        return GP_OK;
+    }
+    void release() {
+        for (void *p : ptrs_) (void)hipFreeAsync(p, s_);
+        ptrs_.clear();
+    }
+    hipStream_t stream() const { return s_; }
+
+  private:
+    hipStream_t s_;
+    std::vector<void *> ptrs_;
+};
+
+inline unsigned grid_for(int64_t items, int per_block, unsigned cap = 1u << 20) {
+    int64_t g = (items + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+inline int bits_for(int64_t maxval) {  // bits needed to represent values in [0, maxval]
+    int b = 0;
+    while (b < 63 && (int64_t(1) << b) <= maxval) b++;
+    return b;
+}
+
+// ------------------------------------------------------------------ device helpers
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T x) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        T y = __shfl_up(x, d, kWave);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T x) {
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, kWave);
+    return x;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T x) {
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+        T y = __shfl_xor(x, d, kWave);
+        x = y > x ? y : x;
+    }
+    return x;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_min(T x) {
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+        T y = __shfl_xor(x, d, kWave);
+        x = y < x ? y : x;
+    }
+    return x;
+}
+
+// Workgroup-wide exclusive scan; `tmp` must hold BLOCK/64 + 1 elements.
+// Returns the thread's exclusive prefix; *total receives the block sum.
+template <int BLOCK, typename T>
+__device__ __forceinline__ T block_excl_scan(T x, T *tmp, T *total) {
+    constexpr int NW = BLOCK / kWave;
+    const int lane = lane_id(), w = threadIdx.x / kWave;
+    T inc = wave_incl_scan(x);
+    if (lane == kWave - 1) tmp[w] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T acc = 0;
+        for (int i = 0; i < NW; i++) {
+            T t = tmp[i];
+            tmp[i] = acc;
+            acc += t;
+        }
+        tmp[NW] = acc;
+    }
+    __syncthreads();
+    T r = tmp[w] + inc - x;
+    if (total) *total = tmp[NW];
+    __syncthreads();
+    return r;
+}
+
+template <int BLOCK, typename T>
+__device__ __forceinline__ T block_sum(T x, T *tmp) {
+    constexpr int NW = BLOCK / kWave;
+    T s = wave_sum(x);
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == 0) tmp[w] = s;
+    __syncthreads();
+    T r = 0;
+    for (int i = 0; i < NW; i++) r += tmp[i];
+    __syncthreads();
+    return r;
+}
+
+template <int BLOCK, typename T>
+__device__ __forceinline__ T block_min(T x, T *tmp) {
+    constexpr int NW = BLOCK / kWave;
+    T s = wave_min(x);
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == 0) tmp[w] = s;
+    __syncthreads();
+    T r = tmp[0];
+    for (int i = 1; i < NW; i++) r = tmp[i] < r ? tmp[i] : r;
+    __syncthreads();
+    return r;
+}
+
+template <int BLOCK, typename T>
+__device__ __forceinline__ T block_max(T x, T *tmp) {
+    constexpr int NW = BLOCK / kWave;
+    T s = wave_max(x);
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == 0) tmp[w] = s;
+    __syncthreads();
+    T r = tmp[0];
+    for (int i = 1; i < NW; i++) r = tmp[i] > r ? tmp[i] : r;
+    __syncthreads();
+    return r;
+}
+
+// 8 XCDs: consecutive block ids are dealt round-robin to XCDs. Remap so each
+// XCD works on one contiguous range of tiles (shared L2 lines between
+// neighbouring CSR rows stay in one L2).
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nblocks) {
+    constexpr unsigned X = 8;
+    if (nblocks < X || (nblocks % X) != 0) return b;
+    return (b % X) * (nblocks / X) + b / X;
+}
+
+}  // namespace gp

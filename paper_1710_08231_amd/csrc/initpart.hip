@@ -1,0 +1,620 @@
+// initpart.hip — initial partitioning of the coarsest graph on the GPU
+// (§III-B: recursive bisection into ceil(k/2) / floor(k/2) blocks, best of
+// several independent tries, §IV-B), plus placement of vertices without
+// neighbours.
+//
+// Bisection of a vertex set S with k_S blocks grows the left side by a FIFO
+// breadth-first search inside S from a hashed start vertex until it weighs at
+// least ceil(c(S) * ceil(k_S/2) / k_S). The search runs in one workgroup, one
+// BFS level at a time, but reproduces the FIFO queue order exactly: a vertex
+// discovered by several frontier vertices belongs to the earliest (frontier
+// position, adjacency position) pair, found with an atomicMin over edge ranks.
+// All subproblems of one recursion depth, for all tries, run as one launch.
+//
+// Every try is then refined by LP at once, on the disjoint union of the tries
+// (try a owns vertices a*n.. and labels a*k..): LP never mixes components and
+// a component that went idle twice stays idle, so each try gets exactly the
+// result it would get alone. Then each try is greedily rebalanced by one
+// workgroup, and the best try by (imbalanced, cut, index) is kept.
+#include <climits>
+
+#include "contract.hpp"
+#include "initpart.hpp"
+#include "prims.hpp"
+
+namespace gp {
+
+namespace {
+
+constexpr int kBB = 1024;  // bisection workgroup
+
+// splitmix64 finaliser of x + gamma (Steele, Lea & Flood 2014)
+__device__ __forceinline__ uint64_t splitmix(uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ int64_t vw(const int32_t *vwgt, int32_t v) { return vwgt ? vwgt[v] : 1; }
+
+struct BisectArgs {
+    int32_t n;
+    const int32_t *xadj, *adjncy, *vwgt;
+    int32_t *blk;    // [attempts * n], -1 = not taking part
+    int32_t *mark;   // [attempts * n]
+    int32_t *claim;  // [attempts * n]
+    int32_t *slist;  // [nblocks * n]
+    int32_t *order;  // [nblocks * n]
+    int32_t *pre;    // [nblocks * (n + 1)] frontier degree prefix
+    const int32_t *sub_base, *sub_ks;
+    int32_t nsub;
+    uint64_t seed;
+};
+
+// finds the frontier position of edge rank r: largest i with pre[i] <= r
+__device__ __forceinline__ int32_t frontier_pos(const int32_t *pre, int32_t f, int32_t r) {
+    int32_t lo = 0, hi = f - 1;
+    while (lo < hi) {
+        int32_t mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= r) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kBB) void k_bisect(BisectArgs a) {
+    __shared__ int64_t t64[kBB / kWave + 1];
+    __shared__ int32_t t32[kBB / kWave + 1];
+    __shared__ int32_t sh_tail, sh_stop, sh_found;
+    const int attempt = blockIdx.x / a.nsub, sp = blockIdx.x % a.nsub;
+    const int32_t base = a.sub_base[sp], ks = a.sub_ks[sp], kl = (ks + 1) / 2;
+    const int32_t n = a.n;
+    int32_t *blk = a.blk + (int64_t)attempt * n;
+    int32_t *mark = a.mark + (int64_t)attempt * n;
+    int32_t *claim = a.claim + (int64_t)attempt * n;
+    int32_t *slist = a.slist + (int64_t)blockIdx.x * n;
+    int32_t *order = a.order + (int64_t)blockIdx.x * n;
+    int32_t *pre = a.pre + (int64_t)blockIdx.x * (n + 1);
+
+    // ---- S in ascending order, its weight; reset marks and claims
+    int32_t size = 0;
+    int64_t cs = 0;
+    for (int32_t v0 = 0; v0 < n; v0 += kBB) {
+        const int32_t v = v0 + threadIdx.x;
+        const bool in = v < n && blk[v] == base;
+        int32_t tot;
+        const int32_t ex = block_excl_scan<kBB>((int32_t)in, t32, &tot);
+        if (in) {
+            slist[size + ex] = v;
+            mark[v] = 0;
+            claim[v] = INT_MAX;
+            cs += vw(a.vwgt, v);
+        }
+        size += tot;
+    }
+    cs = block_sum<kBB>(cs, t64);
+    if (size == 0) return;
+    const int64_t q = cs / ks, rm = cs % ks;
+    const int64_t target = q * kl + (rm * kl + ks - 1) / ks;
+    const uint64_t h = splitmix(splitmix(splitmix(splitmix(a.seed) ^ (uint64_t)attempt) ^ (uint64_t)base) ^
+                                (uint64_t)ks);
+    const int32_t start = slist[h % (uint64_t)size];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        order[0] = start;
+        mark[start] = 1;
+    }
+    __syncthreads();
+
+    int32_t head = 0, tail = 1, scanp = 0, stop = -1;
+    int64_t cum = 0;
+    for (;;) {
+        // ---- pops of this frontier: first position where the left side reaches the target
+        const int32_t f = tail - head;
+        for (int32_t c0 = 0; c0 < f && stop < 0; c0 += kBB) {
+            const int32_t i = c0 + threadIdx.x;
+            const int64_t w = i < f ? vw(a.vwgt, order[head + i]) : 0;
+            int64_t tot;
+            const int64_t ex = block_excl_scan<kBB>(w, t64, &tot);
+            const int32_t hit = (i < f && cum + ex + w >= target) ? i : INT_MAX;
+            const int32_t first = block_min<kBB>(hit, t32);
+            if (first != INT_MAX) stop = head + first;
+            cum += tot;
+        }
+        if (stop >= 0) break;
+        // ---- expand: degree prefix over the frontier (edges inside S only are claimed)
+        int32_t ef = 0;
+        for (int32_t c0 = 0; c0 < f; c0 += kBB) {
+            const int32_t i = c0 + threadIdx.x;
+            int32_t d = 0;
+            if (i < f) {
+                const int32_t v = order[head + i];
+                d = a.xadj[v + 1] - a.xadj[v];
+            }
+            int32_t tot;
+            const int32_t ex = block_excl_scan<kBB>(d, t32, &tot);
+            if (i < f) pre[i] = ef + ex;
+            ef += tot;
+        }
+        __syncthreads();
+        for (int32_t r = threadIdx.x; r < ef; r += kBB) {
+            const int32_t i = frontier_pos(pre, f, r);
+            const int32_t v = order[head + i];
+            const int32_t u = a.adjncy[a.xadj[v] + (r - pre[i])];
+            if (blk[u] == base && !mark[u]) atomicMin(&claim[u], r);
+        }
+        __syncthreads();
+        int32_t nt = tail;
+        for (int32_t r0 = 0; r0 < ef; r0 += kBB) {
+            const int32_t r = r0 + threadIdx.x;
+            int32_t u = -1;
+            if (r < ef) {
+                const int32_t i = frontier_pos(pre, f, r);
+                const int32_t v = order[head + i];
+                const int32_t cand = a.adjncy[a.xadj[v] + (r - pre[i])];
+                if (blk[cand] == base && !mark[cand] &&
+                    __hip_atomic_load(&claim[cand], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == r)
+                    u = cand;
+            }
+            int32_t tot;
+            const int32_t ex = block_excl_scan<kBB>((int32_t)(u >= 0), t32, &tot);
+            if (u >= 0) order[nt + ex] = u;
+            nt += tot;
+        }
+        __syncthreads();
+        for (int32_t p = tail + threadIdx.x; p < nt; p += kBB) mark[order[p]] = 1;
+        __syncthreads();
+        head = tail;
+        tail = nt;
+        if (head == tail) {
+            // queue ran dry: smallest unmarked vertex of S
+            int32_t found = INT_MAX;
+            while (found == INT_MAX && scanp < size) {
+                const int32_t i = scanp + threadIdx.x;
+                const int32_t hit = (i < size && !mark[slist[i]]) ? i : INT_MAX;
+                found = block_min<kBB>(hit, t32);
+                if (found == INT_MAX) scanp += kBB;
+            }
+            if (found == INT_MAX) {  // cannot happen: target <= c(S)
+                stop = tail - 1;
+                break;
+            }
+            scanp = found;
+            if (threadIdx.x == 0) {
+                order[tail] = slist[found];
+                mark[slist[found]] = 1;
+            }
+            __syncthreads();
+            tail++;
+        }
+    }
+    // ---- left side = order[0..stop]; the rest of S gets base + kl
+    for (int32_t i = threadIdx.x; i < size; i += kBB) blk[slist[i]] = base + kl;
+    __syncthreads();
+    for (int32_t p = threadIdx.x; p <= stop; p += kBB) blk[order[p]] = base;
+}
+
+__global__ void k_init_blk(int32_t n, int32_t attempts, const int32_t *xadj, bool skip_isolated, int32_t *blk) {
+    const int64_t N = (int64_t)n * attempts;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = (int32_t)(i % n);
+        blk[i] = (skip_isolated && xadj[v + 1] == xadj[v]) ? -1 : 0;
+    }
+}
+
+__global__ void k_union(int32_t n, int32_t nnz, int32_t attempts, int32_t k, const int32_t *xadj,
+                        const int32_t *adjncy, const int32_t *adjwgt, const int32_t *vwgt, const int32_t *blk,
+                        int32_t *uxadj, int32_t *uadj, int32_t *uw, int32_t *uvw, int32_t *ulab) {
+    const int64_t NV = (int64_t)n * attempts, NE = (int64_t)nnz * attempts;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= NV; i += stride) {
+        if (i == NV) {
+            uxadj[NV] = (int32_t)NE;
+            continue;
+        }
+        const int64_t c = i / n, v = i % n;
+        uxadj[i] = (int32_t)(c * nnz + xadj[v]);
+        if (uvw) uvw[i] = vwgt[v];
+        const int32_t b = blk[i];
+        ulab[i] = b >= 0 ? (int32_t)(c * k + b) : -1;
+    }
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < NE; e += stride) {
+        const int64_t c = e / nnz, ee = e % nnz;
+        uadj[e] = (int32_t)(c * n + adjncy[ee]);
+        if (uw) uw[e] = adjwgt[ee];
+    }
+}
+
+// One workgroup per try: while a block exceeds lmax apply the move (v, t) of
+// maximum gain conn(v,t) - conn(v,P(v)) with v in an overloaded block and
+// B[t] + c(v) <= lmax; ties -> lowest v, then lowest t.
+constexpr int kRB = 512;
+__global__ __launch_bounds__(kRB) void k_rebalance(int32_t n, int32_t k, int64_t lmax, const int32_t *xadj,
+                                                   const int32_t *adjncy, const int32_t *adjwgt,
+                                                   const int32_t *vwgt, int32_t *ulab, int32_t *balanced) {
+    extern __shared__ int64_t dyn[];
+    constexpr int NW = kRB / kWave;
+    int64_t *B = dyn;              // [k]
+    int64_t *conn = dyn + k;       // [NW][k]
+    __shared__ int64_t bg[NW];
+    __shared__ int32_t bv[NW], bt[NW];
+    __shared__ int32_t s_over;
+    const int a = blockIdx.x;
+    const int32_t *ux = xadj;  // union graph: copy a is vertices [a*n, (a+1)*n)
+    int32_t *lab = ulab;
+    const int32_t v0 = a * n, l0 = a * k;
+    const int lane = lane_id(), w = threadIdx.x / kWave;
+    int64_t *cw = conn + (int64_t)w * k;
+    for (int b = threadIdx.x; b < k; b += kRB) B[b] = 0;
+    __syncthreads();
+    for (int32_t v = threadIdx.x; v < n; v += kRB) {
+        const int32_t L = lab[v0 + v];
+        if (L >= 0) atomicAdd((unsigned long long *)&B[L - l0], (unsigned long long)vw(vwgt, v0 + v));
+    }
+    __syncthreads();
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int over = 0;
+            for (int b = 0; b < k; b++) over |= B[b] > lmax;
+            s_over = over;
+        }
+        __syncthreads();
+        if (!s_over) {
+            if (threadIdx.x == 0) balanced[a] = 1;
+            return;
+        }
+        int64_t best_g = LLONG_MIN;
+        int32_t best_v = INT_MAX, best_t = INT_MAX;
+        for (int32_t v = w; v < n; v += NW) {
+            const int32_t L = lab[v0 + v];
+            if (L < 0 || B[L - l0] <= lmax) continue;  // wave-uniform
+            const int32_t pv = L - l0;
+            for (int b = lane; b < k; b += kWave) cw[b] = 0;
+            wave_sync();
+            for (int32_t e = ux[v0 + v] + lane; e < ux[v0 + v + 1]; e += kWave) {
+                const int32_t u = adjncy[e];
+                const int32_t Lu = lab[u];
+                atomicAdd((unsigned long long *)&cw[Lu - l0], (unsigned long long)(adjwgt ? adjwgt[e] : 1));
+            }
+            wave_sync();
+            const int64_t cv = vw(vwgt, v0 + v);
+            const int64_t own = cw[pv];
+            for (int t = lane; t < k; t += kWave) {
+                if (t == pv || B[t] + cv > lmax) continue;
+                const int64_t g = cw[t] - own;
+                if (g > best_g || (g == best_g && (v < best_v || (v == best_v && t < best_t)))) {
+                    best_g = g;
+                    best_v = v;
+                    best_t = t;
+                }
+            }
+            wave_sync();
+        }
+        // reduce (gain desc, v asc, t asc) over the wave, then the block
+        for (int d = kWave / 2; d > 0; d >>= 1) {
+            const int64_t og = __shfl_xor(best_g, d, kWave);
+            const int32_t ov = __shfl_xor(best_v, d, kWave), ot = __shfl_xor(best_t, d, kWave);
+            if (og > best_g || (og == best_g && (ov < best_v || (ov == best_v && ot < best_t)))) {
+                best_g = og;
+                best_v = ov;
+                best_t = ot;
+            }
+        }
+        if (lane == 0) {
+            bg[w] = best_g;
+            bv[w] = best_v;
+            bt[w] = best_t;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int64_t g = bg[0];
+            int32_t v = bv[0], t = bt[0];
+            for (int i = 1; i < NW; i++)
+                if (bg[i] > g || (bg[i] == g && (bv[i] < v || (bv[i] == v && bt[i] < t)))) {
+                    g = bg[i];
+                    v = bv[i];
+                    t = bt[i];
+                }
+            if (v == INT_MAX) {
+                s_over = -1;
+            } else {
+                const int64_t cv = vw(vwgt, v0 + v);
+                const int32_t pv = lab[v0 + v] - l0;
+                B[pv] -= cv;
+                B[t] += cv;
+                lab[v0 + v] = l0 + t;
+                s_over = 1;
+            }
+        }
+        __syncthreads();
+        if (s_over < 0) {
+            if (threadIdx.x == 0) balanced[a] = 0;
+            return;
+        }
+    }
+}
+
+__global__ void k_copy_cut(int32_t n, int32_t attempts, const int32_t *uxadj, const int32_t *uadj,
+                           const int32_t *uw, const int32_t *ulab, unsigned long long *cuts) {
+    const int64_t NV = (int64_t)n * attempts;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < NV; i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t s = 0;
+        const int32_t L = ulab[i];
+        for (int32_t e = uxadj[i]; e < uxadj[i + 1]; e++)
+            if (ulab[uadj[e]] != L) s += uw ? uw[e] : 1;
+        if (s) atomicAdd(&cuts[i / n], (unsigned long long)s);
+    }
+}
+
+__global__ void k_pick(int32_t n, int32_t k, int32_t attempts, const unsigned long long *cuts,
+                       const int32_t *balanced, const int32_t *ulab, int32_t *part, int32_t *chosen) {
+    __shared__ int32_t best;
+    if (threadIdx.x == 0) {
+        int32_t b = 0;
+        for (int a = 1; a < attempts; a++) {
+            const bool better = (balanced[a] && !balanced[b]) || (balanced[a] == balanced[b] && cuts[a] < cuts[b]);
+            if (better) b = a;
+        }
+        best = b;
+        if (chosen) *chosen = b;
+    }
+    __syncthreads();
+    const int32_t b = best;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t L = ulab[(int64_t)b * n + v];
+        part[v] = L >= 0 ? L - b * k : -1;
+    }
+}
+
+// ---------------------------------------------------------------- isolated fill
+
+struct IsoFlag {
+    const int32_t *xadj;
+    __device__ bool operator()(int64_t v) const { return xadj[v + 1] == xadj[v]; }
+};
+struct IsoEmit {
+    int32_t *iso;
+    __device__ void operator()(int64_t v, int32_t pos) const { iso[pos] = (int32_t)v; }
+};
+
+__global__ void k_iso_minmax(const int32_t *iso, const int32_t *niso, const int32_t *vwgt, int32_t *mm) {
+    const int32_t m = *niso;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t c = vwgt[iso[i]];
+        atomicMin(&mm[0], c);
+        atomicMax(&mm[1], c);
+    }
+}
+
+// Equal weights c: the greedy "lightest block, ties lowest id" sequence equals
+// the sorted merge of the sequences (B_b + j c, b), j >= 0. The i-th isolated
+// vertex takes the i-th smallest element: binary search its value x, then the
+// rank among blocks that reach exactly x.
+__global__ void k_iso_uniform(const int32_t *iso, const int32_t *niso, const int64_t *B, int32_t k, int64_t c,
+                              int32_t *part) {
+    const int32_t m = *niso;
+    int64_t bmin = LLONG_MAX;
+    for (int b = 0; b < k; b++) bmin = B[b] < bmin ? B[b] : bmin;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        // f(x) = #elements <= x
+        int64_t lo = bmin, hi = bmin + i * c;
+        while (lo < hi) {
+            const int64_t mid = lo + (hi - lo) / 2;
+            int64_t f = 0;
+            for (int b = 0; b < k; b++)
+                if (B[b] <= mid) f += (mid - B[b]) / c + 1;
+            if (f >= i + 1) hi = mid;
+            else lo = mid + 1;
+        }
+        const int64_t x = lo;
+        int64_t below = 0;  // elements < x
+        for (int b = 0; b < k; b++)
+            if (B[b] <= x - 1) below += (x - 1 - B[b]) / c + 1;
+        int64_t rank = i - below;
+        int32_t pick = -1;
+        for (int b = 0; b < k; b++) {
+            if (B[b] <= x && (x - B[b]) % c == 0) {
+                if (rank == 0) {
+                    pick = b;
+                    break;
+                }
+                rank--;
+            }
+        }
+        part[iso[i]] = pick;
+    }
+}
+
+// General weights: one thread, binary heap of (B_b, b).
+__global__ void k_iso_serial(const int32_t *iso, const int32_t *niso, const int64_t *B0, int32_t k,
+                             const int32_t *vwgt, int64_t *hv, int32_t *hb, int32_t *part) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    auto less = [&](int i, int j) { return hv[i] < hv[j] || (hv[i] == hv[j] && hb[i] < hb[j]); };
+    for (int b = 0; b < k; b++) {
+        hv[b] = B0[b];
+        hb[b] = b;
+        int i = b;
+        while (i > 0) {
+            int p = (i - 1) / 2;
+            if (!less(i, p)) break;
+            int64_t tv = hv[i];
+            hv[i] = hv[p];
+            hv[p] = tv;
+            int32_t tb = hb[i];
+            hb[i] = hb[p];
+            hb[p] = tb;
+            i = p;
+        }
+    }
+    const int32_t m = *niso;
+    for (int32_t q = 0; q < m; q++) {
+        const int32_t v = iso[q];
+        part[v] = hb[0];
+        hv[0] += vwgt ? vwgt[v] : 1;
+        int i = 0;
+        for (;;) {
+            int l = 2 * i + 1, r = l + 1, s = i;
+            if (l < k && less(l, s)) s = l;
+            if (r < k && less(r, s)) s = r;
+            if (s == i) break;
+            int64_t tv = hv[i];
+            hv[i] = hv[s];
+            hv[s] = tv;
+            int32_t tb = hb[i];
+            hb[i] = hb[s];
+            hb[s] = tb;
+            i = s;
+        }
+    }
+}
+
+}  // namespace
+
+int initial_partition(const DevGraph &g, bool skip_isolated, int32_t k, int64_t lmax, uint64_t seed,
+                      int32_t attempts, int32_t rounds_refine, int32_t dir_alternate, bool wide, int32_t *part,
+                      int32_t *chosen_host, Scratch &sc) {
+    hipStream_t s = sc.stream();
+    const int32_t n = g.n, nnz = g.nnz;
+    if (n == 0) return GP_OK;
+    if ((int64_t)n * attempts >= INT_MAX || (int64_t)nnz * attempts >= INT_MAX || (int64_t)k * attempts >= INT_MAX) {
+        set_error("initial partition: coarsest graph times attempts exceeds int32 indexing");
+        return GP_ERR_OVERFLOW;
+    }
+    if (k > 2048) {
+        set_error("initial partition: k > 2048 is not supported by the rebalance kernel");
+        return GP_ERR_ARG;
+    }
+    // ---- recursion tree of (base, k_S) per depth (depends only on k)
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> depth;
+    {
+        std::vector<std::pair<int32_t, int32_t>> cur{{0, k}};
+        while (!cur.empty()) {
+            std::vector<std::pair<int32_t, int32_t>> work, next;
+            for (auto &p : cur)
+                if (p.second > 1) {
+                    work.push_back(p);
+                    const int32_t kl = (p.second + 1) / 2;
+                    next.push_back({p.first, kl});
+                    next.push_back({p.first + kl, p.second - kl});
+                }
+            if (!work.empty()) depth.push_back(work);
+            cur = next;
+        }
+    }
+    size_t maxsub = 1;
+    for (auto &d : depth) maxsub = d.size() > maxsub ? d.size() : maxsub;
+    int32_t *blk = nullptr, *mark = nullptr, *claim = nullptr, *slist = nullptr, *order = nullptr, *pre = nullptr,
+            *sb = nullptr, *sk = nullptr;
+    const int64_t nb = (int64_t)maxsub * attempts;
+    GP_TRY(sc.alloc(&blk, (size_t)n * attempts));
+    GP_TRY(sc.alloc(&mark, (size_t)n * attempts));
+    GP_TRY(sc.alloc(&claim, (size_t)n * attempts));
+    GP_TRY(sc.alloc(&slist, (size_t)n * nb));
+    GP_TRY(sc.alloc(&order, (size_t)n * nb));
+    GP_TRY(sc.alloc(&pre, (size_t)(n + 1) * nb));
+    GP_TRY(sc.alloc(&sb, maxsub));
+    GP_TRY(sc.alloc(&sk, maxsub));
+    hipLaunchKernelGGL(k_init_blk, dim3(grid_for((int64_t)n * attempts, 256, 65536)), dim3(256), 0, s, n, attempts,
+                       g.xadj, skip_isolated, blk);
+    GP_LAUNCH_CHECK();
+    std::vector<int32_t> hb, hk;
+    for (auto &d : depth) {
+        hb.clear();
+        hk.clear();
+        for (auto &p : d) {
+            hb.push_back(p.first);
+            hk.push_back(p.second);
+        }
+        GP_HIP(hipMemcpyAsync(sb, hb.data(), sizeof(int32_t) * hb.size(), hipMemcpyHostToDevice, s));
+        GP_HIP(hipMemcpyAsync(sk, hk.data(), sizeof(int32_t) * hk.size(), hipMemcpyHostToDevice, s));
+        BisectArgs a{n, g.xadj, g.adjncy, g.vwgt, blk, mark, claim, slist, order, pre, sb, sk, (int32_t)d.size(), seed};
+        hipLaunchKernelGGL(k_bisect, dim3((unsigned)(d.size() * attempts)), dim3(kBB), 0, s, a);
+        GP_LAUNCH_CHECK();
+        // host vectors are reused next depth: make sure the copies have been consumed
+        GP_HIP(hipStreamSynchronize(s));
+    }
+
+    // ---- refine all tries at once on the disjoint union
+    const int32_t NV = n * attempts, NE = nnz * attempts;
+    int32_t *ux = nullptr, *ua = nullptr, *uw = nullptr, *uv = nullptr, *ul = nullptr;
+    GP_TRY(sc.alloc(&ux, (size_t)NV + 1));
+    GP_TRY(sc.alloc(&ua, NE));
+    if (g.adjwgt) GP_TRY(sc.alloc(&uw, NE));
+    if (g.vwgt) GP_TRY(sc.alloc(&uv, NV));
+    GP_TRY(sc.alloc(&ul, NV));
+    hipLaunchKernelGGL(k_union, dim3(grid_for((int64_t)NE + NV, 256, 65536)), dim3(256), 0, s, n, nnz, attempts, k,
+                       g.xadj, g.adjncy, g.adjwgt, g.vwgt, blk, ux, ua, uw, uv, ul);
+    GP_LAUNCH_CHECK();
+    DevGraph ug;
+    ug.n = NV;
+    ug.nnz = NE;
+    ug.xadj = ux;
+    ug.adjncy = ua;
+    ug.adjwgt = uw;
+    ug.vwgt = uv;
+    int64_t *W = nullptr;
+    GP_TRY(sc.alloc(&W, (size_t)k * attempts));
+    GP_TRY(label_weights(ug, ul, W, k * attempts, sc));
+    GP_TRY(lp_run(ug, ul, W, k * attempts, lmax, rounds_refine, dir_alternate, wide, nullptr, sc));
+
+    // ---- rebalance each try, pick the best
+    int32_t *bal = nullptr, *ch = nullptr;
+    unsigned long long *cuts = nullptr;
+    GP_TRY(sc.alloc(&bal, attempts));
+    GP_TRY(sc.alloc(&cuts, attempts));
+    GP_TRY(sc.alloc(&ch, 1));
+    GP_HIP(hipMemsetAsync(cuts, 0, sizeof(unsigned long long) * attempts, s));
+    const size_t dyn = sizeof(int64_t) * (size_t)k * (1 + kRB / kWave);
+    GP_HIP(hipFuncSetAttribute((const void *)k_rebalance, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
+    hipLaunchKernelGGL(k_rebalance, dim3(attempts), dim3(kRB), dyn, s, n, k, lmax, ux, ua, uw, uv, ul, bal);
+    GP_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_copy_cut, dim3(grid_for(NV, 256, 65536)), dim3(256), 0, s, n, attempts, ux, ua, uw, ul,
+                       cuts);
+    GP_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_pick, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, n, k, attempts, cuts, bal, ul, part,
+                       ch);
+    GP_LAUNCH_CHECK();
+    if (chosen_host) {
+        GP_HIP(hipMemcpyAsync(chosen_host, ch, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        GP_HIP(hipStreamSynchronize(s));
+    }
+    return GP_OK;
+}
+
+int fill_isolated(const DevGraph &g, int32_t k, int32_t *part, const int64_t *B, int32_t *niso_host, Scratch &sc) {
+    hipStream_t s = sc.stream();
+    const int32_t n = g.n;
+    int32_t *iso = nullptr, *d_niso = nullptr, *mm = nullptr;
+    GP_TRY(sc.alloc(&iso, n));
+    GP_TRY(sc.alloc(&d_niso, 1));
+    GP_TRY(sc.alloc(&mm, 2));
+    GP_TRY(compact(IsoFlag{g.xadj}, IsoEmit{iso}, n, nullptr, d_niso, sc));
+    int32_t h[2] = {1, 1}, niso = 0;
+    GP_HIP(hipMemcpyAsync(&niso, d_niso, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    if (g.vwgt) {
+        const int32_t init[2] = {INT_MAX, INT_MIN};
+        GP_HIP(hipMemcpyAsync(mm, init, sizeof(init), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_iso_minmax, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, iso, d_niso, g.vwgt, mm);
+        GP_LAUNCH_CHECK();
+        GP_HIP(hipMemcpyAsync(h, mm, sizeof(h), hipMemcpyDeviceToHost, s));
+    }
+    GP_HIP(hipStreamSynchronize(s));
+    if (niso_host) *niso_host = niso;
+    if (niso == 0) return GP_OK;
+    if (h[0] == h[1]) {
+        hipLaunchKernelGGL(k_iso_uniform, dim3(grid_for(niso, 256, 8192)), dim3(256), 0, s, iso, d_niso, B, k,
+                           (int64_t)h[0], part);
+        GP_LAUNCH_CHECK();
+    } else {
+        int64_t *hv = nullptr;
+        int32_t *hbk = nullptr;
+        GP_TRY(sc.alloc(&hv, k));
+        GP_TRY(sc.alloc(&hbk, k));
+        hipLaunchKernelGGL(k_iso_serial, dim3(1), dim3(64), 0, s, iso, d_niso, B, k, g.vwgt, hv, hbk, part);
+        GP_LAUNCH_CHECK();
+    }
+    return GP_OK;
+}
+
+}  // namespace gp

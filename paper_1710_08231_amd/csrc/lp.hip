@@ -1,0 +1,722 @@
+// lp.hip — round-synchronous size-constrained label propagation on gfx950.
+//
+// One round (clustering §III-A / §IV-A, refinement §III-C use the same
+// kernels; only the label domain and the capacity differ):
+//   1. propose: per vertex, neighbour-label connection weights are gathered
+//      into an LDS hash table (vertices binned by degree: a few lanes, a whole
+//      wave, or a whole workgroup per vertex; vertices above the LDS tiers use
+//      a table in global memory). Best = max connection, ties -> smallest
+//      label; the capacity check W[L] + c(v) <= U is evaluated on the best
+//      label first and only rescans the table when that label is full.
+//   2. compact the movers in ascending vertex id (stable scan),
+//   3. stable LSD radix sort of (target, vertex) by target, so each target's
+//      proposers stay in ascending id,
+//   4. inclusive prefix sum of c over the sorted movers; a mover is admitted
+//      iff W[t] + (its prefix within the target's segment) <= U,
+//   5. apply: write labels, then update W with integer atomics (exact,
+//      order independent), count moves, update the device stop flag.
+// No host synchronisation happens between rounds; after the stop flag is set
+// every later kernel of the call returns immediately.
+#include <climits>
+
+#include "lp.hpp"
+#include "prims.hpp"
+
+namespace gp {
+
+namespace {
+
+struct LPArgs {
+    const int32_t *xadj, *adjncy, *adjwgt, *vwgt;
+    const int32_t *labels;
+    const int64_t *W;
+    int64_t U;
+    int32_t dirmode;  // 0: any direction, 1: only smaller labels, 2: only larger labels
+    int32_t *prop;
+    const int32_t *done;
+};
+
+__device__ __forceinline__ bool dir_ok(int32_t L, int32_t own, int32_t dirmode) {
+    return dirmode == 0 || (dirmode == 1 ? (L < own) : (L > own));
+}
+
+__device__ __forceinline__ int64_t vweight(const int32_t *vwgt, int32_t v) {
+    return vwgt ? (int64_t)vwgt[v] : (int64_t)1;
+}
+
+template <typename AccT>
+__device__ __forceinline__ void lds_add(AccT *p, AccT w);
+template <>
+__device__ __forceinline__ void lds_add<int32_t>(int32_t *p, int32_t w) {
+    atomicAdd(p, w);
+}
+template <>
+__device__ __forceinline__ void lds_add<int64_t>(int64_t *p, int64_t w) {
+    atomicAdd((unsigned long long *)p, (unsigned long long)w);
+}
+
+__device__ __forceinline__ uint32_t hash_label(int32_t L) { return (uint32_t)L * 0x9E3779B1u; }
+
+// Open addressing with linear probing; capacity (a power of two) > distinct keys.
+template <typename T>
+__device__ __forceinline__ T ld_agent(const T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename AccT>
+__device__ __forceinline__ void tbl_insert(int32_t *key, AccT *val, uint32_t cap_mask, int log2cap,
+                                           int32_t L, AccT w) {
+    uint32_t h = hash_label(L) >> (32 - log2cap);
+    for (;;) {
+        int32_t k = key[h];
+        if (k == L) break;
+        if (k == -1) {
+            int32_t prev = atomicCAS(&key[h], -1, L);
+            if (prev == -1 || prev == L) break;
+        }
+        h = (h + 1) & cap_mask;
+    }
+    lds_add<AccT>(&val[h], w);
+}
+
+template <typename AccT>
+__device__ __forceinline__ void tbl_insert_global(int32_t *key, AccT *val, uint32_t cap_mask, int log2cap,
+                                                  int32_t L, AccT w) {
+    uint32_t h = hash_label(L) >> (32 - log2cap);
+    for (;;) {
+        const int32_t k = ld_agent(&key[h]);
+        if (k == L) break;
+        if (k == -1) {
+            const int32_t prev = atomicCAS(&key[h], -1, L);
+            if (prev == -1 || prev == L) break;
+        }
+        h = (h + 1) & cap_mask;
+    }
+    lds_add<AccT>(&val[h], w);
+}
+
+// (conn, label) order: larger conn first, then smaller label.
+template <typename AccT>
+__device__ __forceinline__ bool better(AccT c, int32_t L, AccT bc, int32_t bl) {
+    return c > bc || (c == bc && L < bl);
+}
+
+template <int GL, typename AccT>
+__device__ __forceinline__ void group_best(AccT &bc, int32_t &bl) {
+#pragma unroll
+    for (int d = GL / 2; d > 0; d >>= 1) {
+        AccT oc = __shfl_xor(bc, d, GL);
+        int32_t ol = __shfl_xor(bl, d, GL);
+        if (better(oc, ol, bc, bl)) {
+            bc = oc;
+            bl = ol;
+        }
+    }
+}
+
+template <int GL, typename T>
+__device__ __forceinline__ T group_sum(T x) {
+#pragma unroll
+    for (int d = GL / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, GL);
+    return x;
+}
+
+template <int BLOCK, typename AccT>
+__device__ __forceinline__ void block_best(AccT &bc, int32_t &bl, AccT *tc, int32_t *tl) {
+    constexpr int NW = BLOCK / kWave;
+    group_best<kWave, AccT>(bc, bl);
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == 0) {
+        tc[w] = bc;
+        tl[w] = bl;
+    }
+    __syncthreads();
+    bc = tc[0];
+    bl = tl[0];
+    for (int i = 1; i < NW; i++)
+        if (better(tc[i], tl[i], bc, bl)) {
+            bc = tc[i];
+            bl = tl[i];
+        }
+    __syncthreads();
+}
+
+constexpr int kPropBlock = 256;
+
+// GL lanes per vertex (GL <= 64), TBL table slots per vertex.
+template <int GL, int TBL, typename AccT>
+__global__ __launch_bounds__(kPropBlock) void k_propose_group(LPArgs a, const int32_t *__restrict__ verts,
+                                                              int32_t count) {
+    if (*a.done) return;
+    constexpr int GPW = kWave / GL;
+    constexpr int NW = kPropBlock / kWave;
+    constexpr int LOG2 = __builtin_ctz(TBL);
+    __shared__ int32_t skey[NW * GPW * TBL];
+    __shared__ AccT sval[NW * GPW * TBL];
+    const int lane = lane_id(), w = threadIdx.x / kWave;
+    const int gl = lane % GL, grp = lane / GL;
+    int32_t *key = skey + (w * GPW + grp) * TBL;
+    AccT *val = sval + (w * GPW + grp) * TBL;
+    for (int i = gl; i < TBL; i += GL) {
+        key[i] = -1;
+        val[i] = 0;
+    }
+    wave_sync();
+    const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t stride = (int64_t)gridDim.x * NW * GPW;
+    for (int64_t wb = ((int64_t)b * NW + w) * GPW; wb < count; wb += stride) {
+        const int64_t idx = wb + grp;
+        const bool valid = idx < count;
+        const int32_t v = valid ? verts[idx] : 0;
+        const int32_t beg = valid ? a.xadj[v] : 0, end = valid ? a.xadj[v + 1] : 0;
+        const int32_t own = valid ? a.labels[v] : -1;
+        AccT oc = 0;
+        const int nch = (end - beg + GL - 1) / GL;
+        const int maxch = wave_max(nch);
+        for (int ch = 0; ch < maxch; ch++) {
+            const int32_t e = beg + ch * GL + gl;
+            if (e < end) {
+                const int32_t u = a.adjncy[e];
+                const AccT wgt = a.adjwgt ? (AccT)a.adjwgt[e] : (AccT)1;
+                const int32_t L = a.labels[u];
+                if (L == own) oc += wgt;
+                else if (dir_ok(L, own, a.dirmode)) tbl_insert<AccT>(key, val, TBL - 1, LOG2, L, wgt);
+            }
+        }
+        wave_sync();
+        oc = group_sum<GL>(oc);
+        AccT bc = 0;
+        int32_t bl = INT_MAX;
+        for (int i = gl; i < TBL; i += GL) {
+            const int32_t L = key[i];
+            if (L >= 0 && better(val[i], L, bc, bl)) {
+                bc = val[i];
+                bl = L;
+            }
+        }
+        group_best<GL, AccT>(bc, bl);
+        const int64_t cv = valid ? vweight(a.vwgt, v) : 0;
+        int32_t target = -1;
+        bool need2 = false;
+        if (valid && bl != INT_MAX && bc > oc) {
+            if (a.W[bl] + cv <= a.U) target = bl;
+            else need2 = true;
+        }
+        if (__ballot(need2)) {
+            AccT bc2 = 0;
+            int32_t bl2 = INT_MAX;
+            if (need2) {
+                for (int i = gl; i < TBL; i += GL) {
+                    const int32_t L = key[i];
+                    if (L >= 0 && better(val[i], L, bc2, bl2) && a.W[L] + cv <= a.U) {
+                        bc2 = val[i];
+                        bl2 = L;
+                    }
+                }
+            }
+            group_best<GL, AccT>(bc2, bl2);
+            if (need2 && bl2 != INT_MAX && bc2 > oc) target = bl2;
+        }
+        if (valid && gl == 0) a.prop[v] = target;
+        wave_sync();
+        for (int i = gl; i < TBL; i += GL) {
+            key[i] = -1;
+            val[i] = 0;
+        }
+        wave_sync();
+    }
+}
+
+// One workgroup per vertex, table in LDS.
+template <int BLOCK, int TBL, typename AccT>
+__global__ __launch_bounds__(BLOCK) void k_propose_block(LPArgs a, const int32_t *__restrict__ verts,
+                                                         int32_t count) {
+    if (*a.done) return;
+    constexpr int LOG2 = __builtin_ctz(TBL);
+    constexpr int NW = BLOCK / kWave;
+    __shared__ int32_t key[TBL];
+    __shared__ AccT val[TBL];
+    __shared__ AccT tc[NW + 1];
+    __shared__ int32_t tl[NW + 1];
+    for (int i = threadIdx.x; i < TBL; i += BLOCK) {
+        key[i] = -1;
+        val[i] = 0;
+    }
+    __syncthreads();
+    for (int64_t idx = xcd_block(blockIdx.x, gridDim.x); idx < count; idx += gridDim.x) {
+        const int32_t v = verts[idx];
+        const int32_t beg = a.xadj[v], end = a.xadj[v + 1];
+        const int32_t own = a.labels[v];
+        AccT oc = 0;
+        for (int32_t e = beg + threadIdx.x; e < end; e += BLOCK) {
+            const int32_t u = a.adjncy[e];
+            const AccT wgt = a.adjwgt ? (AccT)a.adjwgt[e] : (AccT)1;
+            const int32_t L = a.labels[u];
+            if (L == own) oc += wgt;
+            else if (dir_ok(L, own, a.dirmode)) tbl_insert<AccT>(key, val, TBL - 1, LOG2, L, wgt);
+        }
+        __syncthreads();
+        oc = block_sum<BLOCK>(oc, tc);
+        AccT bc = 0;
+        int32_t bl = INT_MAX;
+        for (int i = threadIdx.x; i < TBL; i += BLOCK) {
+            const int32_t L = key[i];
+            if (L >= 0 && better(val[i], L, bc, bl)) {
+                bc = val[i];
+                bl = L;
+            }
+        }
+        block_best<BLOCK, AccT>(bc, bl, tc, tl);
+        const int64_t cv = vweight(a.vwgt, v);
+        int32_t target = -1;
+        if (bl != INT_MAX && bc > oc) {
+            if (a.W[bl] + cv <= a.U) {
+                target = bl;
+            } else {
+                AccT bc2 = 0;
+                int32_t bl2 = INT_MAX;
+                for (int i = threadIdx.x; i < TBL; i += BLOCK) {
+                    const int32_t L = key[i];
+                    if (L >= 0 && better(val[i], L, bc2, bl2) && a.W[L] + cv <= a.U) {
+                        bc2 = val[i];
+                        bl2 = L;
+                    }
+                }
+                block_best<BLOCK, AccT>(bc2, bl2, tc, tl);
+                if (bl2 != INT_MAX && bc2 > oc) target = bl2;
+            }
+        }
+        if (threadIdx.x == 0) a.prop[v] = target;
+        for (int i = threadIdx.x; i < TBL; i += BLOCK) {
+            key[i] = -1;
+            val[i] = 0;
+        }
+        __syncthreads();
+    }
+}
+
+// Hubs: one workgroup per vertex, table of hcap[i] (power of two) slots in
+// global memory at hoff[i]; tables start empty and are emptied again.
+template <int BLOCK, typename AccT>
+__global__ __launch_bounds__(BLOCK) void k_propose_hub(LPArgs a, const int32_t *__restrict__ verts,
+                                                       int32_t count, const int64_t *hoff,
+                                                       const int32_t *hlog, int32_t *gkey, AccT *gval) {
+    if (*a.done) return;
+    constexpr int NW = BLOCK / kWave;
+    __shared__ AccT tc[NW + 1];
+    __shared__ int32_t tl[NW + 1];
+    for (int64_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
+        const int32_t v = verts[idx];
+        const int32_t beg = a.xadj[v], end = a.xadj[v + 1];
+        const int32_t own = a.labels[v];
+        const int lg = hlog[idx];
+        const uint32_t cap = 1u << lg;
+        int32_t *key = gkey + hoff[idx];
+        AccT *val = gval + hoff[idx];
+        AccT oc = 0;
+        for (int32_t e = beg + threadIdx.x; e < end; e += BLOCK) {
+            const int32_t u = a.adjncy[e];
+            const AccT wgt = a.adjwgt ? (AccT)a.adjwgt[e] : (AccT)1;
+            const int32_t L = a.labels[u];
+            if (L == own) oc += wgt;
+            else if (dir_ok(L, own, a.dirmode)) tbl_insert_global<AccT>(key, val, cap - 1, lg, L, wgt);
+        }
+        __threadfence_block();
+        __syncthreads();
+        oc = block_sum<BLOCK>(oc, tc);
+        AccT bc = 0;
+        int32_t bl = INT_MAX;
+        for (uint32_t i = threadIdx.x; i < cap; i += BLOCK) {
+            const int32_t L = ld_agent(&key[i]);
+            const AccT c = L >= 0 ? ld_agent(&val[i]) : AccT(0);
+            if (L >= 0 && better(c, L, bc, bl)) {
+                bc = c;
+                bl = L;
+            }
+        }
+        block_best<BLOCK, AccT>(bc, bl, tc, tl);
+        const int64_t cv = vweight(a.vwgt, v);
+        int32_t target = -1;
+        if (bl != INT_MAX && bc > oc) {
+            if (a.W[bl] + cv <= a.U) {
+                target = bl;
+            } else {
+                AccT bc2 = 0;
+                int32_t bl2 = INT_MAX;
+                for (uint32_t i = threadIdx.x; i < cap; i += BLOCK) {
+                    const int32_t L = ld_agent(&key[i]);
+                    const AccT c = L >= 0 ? ld_agent(&val[i]) : AccT(0);
+                    if (L >= 0 && better(c, L, bc2, bl2) && a.W[L] + cv <= a.U) {
+                        bc2 = c;
+                        bl2 = L;
+                    }
+                }
+                block_best<BLOCK, AccT>(bc2, bl2, tc, tl);
+                if (bl2 != INT_MAX && bc2 > oc) target = bl2;
+            }
+        }
+        if (threadIdx.x == 0) a.prop[v] = target;
+        for (uint32_t i = threadIdx.x; i < cap; i += BLOCK) {
+            key[i] = -1;
+            val[i] = 0;
+        }
+        __threadfence_block();
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- tiers
+
+// Degree tiers. Tier 0: no neighbours (never proposes). Tiers 1..5: GL lanes
+// per vertex. Tier 6, 7: one workgroup per vertex. Tier 8: hub (global table).
+constexpr int kTiers = 9;
+struct TierSpec {
+    int32_t maxdeg;
+};
+// Upper degree bound per tier for narrow (int32) / wide (int64) sums.
+__host__ __device__ inline int32_t tier_max(int t, bool wide) {
+    switch (t) {
+        case 0: return 0;
+        case 1: return 4;
+        case 2: return 8;
+        case 3: return 16;
+        case 4: return 64;
+        case 5: return 256;
+        case 6: return 2048;
+        case 7: return wide ? 4096 : 8192;
+        default: return INT_MAX;
+    }
+}
+
+struct TierKey {
+    const int32_t *xadj;
+    const int32_t *active;  // optional: labels array, vertices with label < 0 go to tier 0
+    bool wide;
+};
+
+__global__ void k_tier_keys(TierKey tk, int32_t n, uint32_t *key, int32_t *val, int32_t *counts) {
+    __shared__ int32_t h[kTiers];
+    if (threadIdx.x < kTiers) h[threadIdx.x] = 0;
+    __syncthreads();
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t d = tk.xadj[v + 1] - tk.xadj[v];
+        int t = 0;
+        if (d > 0 && !(tk.active && tk.active[v] < 0)) {
+            t = 1;
+            while (t < kTiers - 1 && d > tier_max(t, tk.wide)) t++;
+        }
+        key[v] = (uint32_t)t;
+        val[v] = (int32_t)v;
+        atomicAdd(&h[t], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < kTiers && h[threadIdx.x]) atomicAdd(&counts[threadIdx.x], h[threadIdx.x]);
+}
+
+__global__ void k_hub_caps(const int32_t *xadj, const int32_t *hubs, int32_t nh, int32_t *hlog,
+                           int64_t *hcap) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nh;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = hubs[i];
+        const int64_t d = xadj[v + 1] - xadj[v];
+        int lg = 1;
+        while ((int64_t(1) << lg) < 2 * d) lg++;
+        hlog[i] = lg;
+        hcap[i] = int64_t(1) << lg;
+    }
+}
+
+// ---------------------------------------------------------------- admission / apply
+
+struct MoverFlag {
+    const int32_t *prop;
+    const int32_t *done;
+    __device__ bool operator()(int64_t i) const { return !*done && prop[i] >= 0; }
+};
+struct MoverEmit {
+    const int32_t *prop;
+    uint32_t *mk;
+    int32_t *mv;
+    __device__ void operator()(int64_t i, int32_t pos) const {
+        mk[pos] = (uint32_t)prop[i];
+        mv[pos] = (int32_t)i;
+    }
+};
+
+struct MoverWeight {
+    const int32_t *mv;
+    const int32_t *vwgt;
+    __device__ int64_t operator()(int64_t p) const { return vweight(vwgt, mv[p]); }
+};
+struct StoreIncl {
+    int64_t *S;
+    __device__ void operator()(int64_t p, int64_t ex, int64_t v) const { S[p] = ex + v; }
+};
+
+__global__ void k_heads(const uint32_t *mk, const int32_t *nmov, int32_t *headpos) {
+    const int32_t n = *nmov;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x)
+        if (p == 0 || mk[p] != mk[p - 1]) headpos[mk[p]] = (int32_t)p;
+}
+
+__global__ void k_admit(const uint32_t *mk, const int32_t *mv, const int32_t *nmov, const int32_t *headpos,
+                        const int64_t *S, const int64_t *W, int64_t U, int32_t *labels, int32_t *oldlab,
+                        LPDev *dev) {
+    const int32_t n = *nmov;
+    int32_t cnt = 0;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t t = (int32_t)mk[p];
+        const int32_t h = headpos[t];
+        const int64_t pre = S[p] - (h > 0 ? S[h - 1] : 0);
+        if (W[t] + pre <= U) {
+            const int32_t v = mv[p];
+            oldlab[p] = labels[v];
+            labels[v] = t;
+            cnt++;
+        } else {
+            oldlab[p] = -1;
+        }
+    }
+    cnt = wave_sum(cnt);
+    if (lane_id() == 0 && cnt) atomicAdd(&dev->round_moves, cnt);
+}
+
+__global__ void k_apply_w(const uint32_t *mk, const int32_t *mv, const int32_t *nmov, const int32_t *oldlab,
+                          const int32_t *vwgt, int64_t *W) {
+    const int32_t n = *nmov;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t old = oldlab[p];
+        if (old < 0) continue;
+        const unsigned long long c = (unsigned long long)vweight(vwgt, mv[p]);
+        atomicAdd((unsigned long long *)&W[mk[p]], c);
+        atomicAdd((unsigned long long *)&W[old], (unsigned long long)(-(long long)c));
+    }
+}
+
+__global__ void k_round_end(LPDev *dev, int32_t r) {
+    if (dev->done) return;
+    const int32_t m = dev->round_moves;
+    dev->rounds_run = r + 1;
+    dev->total_moves += m;
+    if (r >= 1 && m == 0 && dev->prev_moves == 0) dev->done = 1;
+    dev->prev_moves = m;
+    dev->round_moves = 0;
+}
+
+__global__ void k_label_weights(const int32_t *labels, const int32_t *vwgt, int32_t n, int64_t *W) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t L = labels[v];
+        if (L >= 0) atomicAdd((unsigned long long *)&W[L], (unsigned long long)vweight(vwgt, (int32_t)v));
+    }
+}
+
+struct EdgeWeightIn {
+    const int32_t *w;
+    __device__ int64_t operator()(int64_t i) const { return (int64_t)w[i]; }
+};
+struct NoOut64 {
+    __device__ void operator()(int64_t, int64_t, int64_t) const {}
+};
+
+template <typename AccT>
+int launch_proposals(const LPArgs &a, const int32_t *verts, const int64_t *tstart, const int32_t *hub_log,
+                     const int64_t *hub_off, int32_t *gkey, AccT *gval, hipStream_t s) {
+    auto cnt = [&](int t) { return (int32_t)(tstart[t + 1] - tstart[t]); };
+    auto lst = [&](int t) { return verts + tstart[t]; };
+    constexpr int NW = kPropBlock / kWave;
+    // blocks: enough waves to cover the tier, capped so each block loops a few times
+    auto blocks_for = [&](int32_t c, int per_block) { return grid_for(c, per_block, 16384); };
+    int32_t c;
+    if ((c = cnt(1)) > 0) {
+        hipLaunchKernelGGL((k_propose_group<4, 8, AccT>), dim3(blocks_for(c, NW * 16)), dim3(kPropBlock), 0, s,
+                           a, lst(1), c);
+    }
+    if ((c = cnt(2)) > 0) {
+        hipLaunchKernelGGL((k_propose_group<8, 16, AccT>), dim3(blocks_for(c, NW * 8)), dim3(kPropBlock), 0, s,
+                           a, lst(2), c);
+    }
+    if ((c = cnt(3)) > 0) {
+        hipLaunchKernelGGL((k_propose_group<16, 32, AccT>), dim3(blocks_for(c, NW * 4)), dim3(kPropBlock), 0,
+                           s, a, lst(3), c);
+    }
+    if ((c = cnt(4)) > 0) {
+        hipLaunchKernelGGL((k_propose_group<32, 128, AccT>), dim3(blocks_for(c, NW * 2)), dim3(kPropBlock), 0,
+                           s, a, lst(4), c);
+    }
+    if ((c = cnt(5)) > 0) {
+        hipLaunchKernelGGL((k_propose_group<64, 512, AccT>), dim3(blocks_for(c, NW)), dim3(kPropBlock), 0, s,
+                           a, lst(5), c);
+    }
+    if ((c = cnt(6)) > 0) {
+        hipLaunchKernelGGL((k_propose_block<256, 4096, AccT>), dim3(grid_for(c, 1, 8192)), dim3(256), 0, s, a,
+                           lst(6), c);
+    }
+    if ((c = cnt(7)) > 0) {
+        constexpr int T7 = sizeof(AccT) == 4 ? 16384 : 8192;
+        hipLaunchKernelGGL((k_propose_block<1024, T7, AccT>), dim3(grid_for(c, 1, 2048)), dim3(1024), 0, s, a,
+                           lst(7), c);
+    }
+    if ((c = cnt(8)) > 0) {
+        hipLaunchKernelGGL((k_propose_hub<1024, AccT>), dim3(c), dim3(1024), 0, s, a, lst(8), c, hub_off,
+                           hub_log, gkey, gval);
+    }
+    GP_LAUNCH_CHECK();
+    return GP_OK;
+}
+
+}  // namespace
+
+int total_edge_weight(const DevGraph &g, int64_t *out, Scratch &sc) {
+    if (!g.adjwgt) {
+        *out = g.nnz;
+        return GP_OK;
+    }
+    int64_t *d = nullptr;
+    GP_TRY(sc.alloc(&d, 1));
+    GP_TRY((scan<int64_t>(EdgeWeightIn{g.adjwgt}, NoOut64{}, g.nnz, nullptr, d, sc)));
+    GP_HIP(hipMemcpyAsync(out, d, sizeof(int64_t), hipMemcpyDeviceToHost, sc.stream()));
+    GP_HIP(hipStreamSynchronize(sc.stream()));
+    return GP_OK;
+}
+
+int label_weights(const DevGraph &g, const int32_t *labels, int64_t *W, int32_t nlabels, Scratch &sc) {
+    GP_HIP(hipMemsetAsync(W, 0, sizeof(int64_t) * (size_t)(nlabels > 0 ? nlabels : 1), sc.stream()));
+    if (g.n > 0) {
+        hipLaunchKernelGGL(k_label_weights, dim3(grid_for(g.n, 256, 65536)), dim3(256), 0, sc.stream(), labels,
+                           g.vwgt, g.n, W);
+        GP_LAUNCH_CHECK();
+    }
+    return GP_OK;
+}
+
+int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int64_t U, int32_t rounds,
+           int32_t dir_alternate, bool wide, LPOut *out, Scratch &sc) {
+    hipStream_t s = sc.stream();
+    const int32_t n = g.n;
+    if (n == 0 || rounds == 0) {
+        if (out) *out = LPOut{};
+        return GP_OK;
+    }
+    // ---- degree tiers (once per call)
+    uint32_t *tkey = nullptr, *tkey2 = nullptr;
+    int32_t *tval = nullptr, *tval2 = nullptr, *tcnt = nullptr;
+    GP_TRY(sc.alloc(&tkey, n));
+    GP_TRY(sc.alloc(&tkey2, n));
+    GP_TRY(sc.alloc(&tval, n));
+    GP_TRY(sc.alloc(&tval2, n));
+    GP_TRY(sc.alloc(&tcnt, kTiers));
+    GP_HIP(hipMemsetAsync(tcnt, 0, sizeof(int32_t) * kTiers, s));
+    TierKey tk{g.xadj, labels, wide};
+    hipLaunchKernelGGL(k_tier_keys, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, tk, n, tkey, tval, tcnt);
+    GP_LAUNCH_CHECK();
+    GP_TRY((radix_sort<uint32_t, int32_t>(&tkey, &tval, &tkey2, &tval2, n, nullptr, 4, sc)));
+    int32_t hcnt[kTiers];
+    GP_HIP(hipMemcpyAsync(hcnt, tcnt, sizeof(hcnt), hipMemcpyDeviceToHost, s));
+    GP_HIP(hipStreamSynchronize(s));
+    int64_t tstart[kTiers + 1];
+    tstart[0] = 0;
+    for (int t = 0; t < kTiers; t++) tstart[t + 1] = tstart[t] + hcnt[t];
+    const int32_t *verts = tval;
+
+    // ---- hub tables
+    const int32_t nh = hcnt[kTiers - 1];
+    int32_t *hub_log = nullptr, *gkey = nullptr;
+    int64_t *hub_off = nullptr;
+    void *gval = nullptr;
+    if (nh > 0) {
+        int64_t *hcap = nullptr, *htot = nullptr;
+        GP_TRY(sc.alloc(&hub_log, nh));
+        GP_TRY(sc.alloc(&hcap, nh));
+        GP_TRY(sc.alloc(&hub_off, nh));
+        GP_TRY(sc.alloc(&htot, 1));
+        hipLaunchKernelGGL(k_hub_caps, dim3(grid_for(nh, 256, 1024)), dim3(256), 0, s, g.xadj,
+                           verts + tstart[kTiers - 1], nh, hub_log, hcap);
+        GP_LAUNCH_CHECK();
+        GP_TRY((scan<int64_t>(LoadIn<int64_t>{hcap}, StoreExcl<int64_t>{hub_off}, nh, nullptr, htot, sc)));
+        int64_t total = 0;
+        GP_HIP(hipMemcpyAsync(&total, htot, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        GP_HIP(hipStreamSynchronize(s));
+        GP_TRY(sc.alloc(&gkey, total));
+        GP_HIP(hipMemsetAsync(gkey, 0xFF, sizeof(int32_t) * (size_t)total, s));
+        if (wide) {
+            int64_t *p = nullptr;
+            GP_TRY(sc.alloc(&p, total));
+            GP_HIP(hipMemsetAsync(p, 0, sizeof(int64_t) * (size_t)total, s));
+            gval = p;
+        } else {
+            int32_t *p = nullptr;
+            GP_TRY(sc.alloc(&p, total));
+            GP_HIP(hipMemsetAsync(p, 0, sizeof(int32_t) * (size_t)total, s));
+            gval = p;
+        }
+    }
+
+    // ---- per-round buffers
+    int32_t *prop = nullptr, *mv = nullptr, *mv2 = nullptr, *nmov = nullptr, *headpos = nullptr,
+            *oldlab = nullptr;
+    uint32_t *mk = nullptr, *mk2 = nullptr;
+    int64_t *S = nullptr;
+    LPDev *dev = nullptr;
+    GP_TRY(sc.alloc(&prop, n));
+    GP_TRY(sc.alloc(&mk, n));
+    GP_TRY(sc.alloc(&mk2, n));
+    GP_TRY(sc.alloc(&mv, n));
+    GP_TRY(sc.alloc(&mv2, n));
+    GP_TRY(sc.alloc(&nmov, 1));
+    GP_TRY(sc.alloc(&headpos, nlabels));
+    GP_TRY(sc.alloc(&oldlab, n));
+    GP_TRY(sc.alloc(&S, n));
+    GP_TRY(sc.alloc(&dev, 1));
+    GP_HIP(hipMemsetAsync(prop, 0xFF, sizeof(int32_t) * (size_t)n, s));
+    GP_HIP(hipMemsetAsync(dev, 0, sizeof(LPDev), s));
+    const int key_bits = bits_for(nlabels > 0 ? nlabels - 1 : 0);
+
+    for (int32_t r = 0; r < rounds; r++) {
+        LPArgs a;
+        a.xadj = g.xadj;
+        a.adjncy = g.adjncy;
+        a.adjwgt = g.adjwgt;
+        a.vwgt = g.vwgt;
+        a.labels = labels;
+        a.W = W;
+        a.U = U;
+        a.dirmode = dir_alternate ? ((r % 2 == 0) ? 1 : 2) : 0;
+        a.prop = prop;
+        a.done = &dev->done;
+        if (wide)
+            GP_TRY(launch_proposals<int64_t>(a, verts, tstart, hub_log, hub_off, gkey, (int64_t *)gval, s));
+        else
+            GP_TRY(launch_proposals<int32_t>(a, verts, tstart, hub_log, hub_off, gkey, (int32_t *)gval, s));
+        // compaction of movers (ascending vertex id)
+        GP_TRY(compact(MoverFlag{prop, &dev->done}, MoverEmit{prop, mk, mv}, n, nullptr, nmov, sc));
+        uint32_t *k1 = mk, *k2 = mk2;
+        int32_t *v1 = mv, *v2 = mv2;
+        GP_TRY((radix_sort<uint32_t, int32_t>(&k1, &v1, &k2, &v2, n, nmov, key_bits, sc)));
+        const unsigned gb = grid_for(n, 256, 8192);
+        hipLaunchKernelGGL(k_heads, dim3(gb), dim3(256), 0, s, k1, nmov, headpos);
+        GP_LAUNCH_CHECK();
+        GP_TRY((scan<int64_t>(MoverWeight{v1, g.vwgt}, StoreIncl{S}, n, nmov, (int64_t *)nullptr, sc)));
+        hipLaunchKernelGGL(k_admit, dim3(gb), dim3(256), 0, s, k1, v1, nmov, headpos, S, W, U, labels, oldlab,
+                           dev);
+        GP_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_apply_w, dim3(gb), dim3(256), 0, s, k1, v1, nmov, oldlab, g.vwgt, W);
+        GP_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_round_end, dim3(1), dim3(1), 0, s, dev, r);
+        GP_LAUNCH_CHECK();
+    }
+    if (out) {
+        LPDev h;
+        GP_HIP(hipMemcpyAsync(&h, dev, sizeof(LPDev), hipMemcpyDeviceToHost, s));
+        GP_HIP(hipStreamSynchronize(s));
+        out->rounds_run = h.rounds_run;
+        out->moves = h.total_moves;
+    }
+    return GP_OK;
+}
+
+}  // namespace gp

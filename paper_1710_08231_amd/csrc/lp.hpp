@@ -1,0 +1,43 @@
+// lp.hpp — host-side interface of the label-propagation rounds (internal).
+#pragma once
+#include "gp_common.hpp"
+
+namespace gp {
+
+// Device view of a CSR graph (all pointers on the device).
+struct DevGraph {
+    int32_t n = 0, nnz = 0;
+    const int32_t *xadj = nullptr, *adjncy = nullptr, *adjwgt = nullptr, *vwgt = nullptr;
+};
+
+// Per-call LP bookkeeping kept on the device so rounds need no host sync.
+struct LPDev {
+    int32_t done;
+    int32_t rounds_run;
+    int32_t prev_moves;
+    int32_t round_moves;
+    int64_t total_moves;
+};
+
+struct LPOut {
+    int32_t rounds_run = 0;
+    int64_t moves = 0;
+};
+
+// Runs up to `rounds` synchronous LP rounds on (labels, W) in place.
+//  labels [n]: current labels (-1 marks a vertex that takes no part: it
+//              neither proposes nor counts toward W; such vertices must have
+//              no neighbours).
+//  W [nlabels]: label weights consistent with labels.
+//  U: capacity of every label. wide: use 64-bit connection sums.
+// When `out` is non-null the stream is synchronised and statistics copied.
+int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int64_t U, int32_t rounds,
+           int32_t dir_alternate, bool wide, LPOut *out, Scratch &sc);
+
+// Sum of edge weights (nnz if adjwgt is null); synchronises the stream.
+int total_edge_weight(const DevGraph &g, int64_t *out, Scratch &sc);
+
+// W[b] = sum of c(v) over v with labels[v] == b (labels < 0 skipped).
+int label_weights(const DevGraph &g, const int32_t *labels, int64_t *W, int32_t nlabels, Scratch &sc);
+
+}  // namespace gp

@@ -1,0 +1,510 @@
+// partition.hip — the multilevel driver (§III: coarsen, partition the
+// coarsest graph, uncoarsen with refinement) and the C ABI of the library.
+//
+// Host code only orchestrates: every step of the method runs in the kernels
+// of lp.hip, contract.hip and initpart.hip. The host reads back two integers
+// per level (coarse n and nnz) and small tier counts; rounds of LP never
+// synchronise with the host.
+#include <climits>
+#include <cmath>
+#include <string>
+
+#include "contract.hpp"
+#include "initpart.hpp"
+#include "prims.hpp"
+
+namespace gp {
+
+static thread_local std::string g_err;
+void set_error(const char *msg) { g_err = msg; }
+const char *last_error() { return g_err.c_str(); }
+
+namespace {
+
+__global__ void k_identity_labels(const int32_t *xadj, int32_t n, bool skip_isolated, const int32_t *vwgt,
+                                  int32_t *labels, int64_t *W) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const bool off = skip_isolated && xadj[v + 1] == xadj[v];
+        labels[v] = off ? -1 : (int32_t)v;
+        W[v] = off ? 0 : (vwgt ? vwgt[v] : 1);
+    }
+}
+
+__global__ void k_graph_stats(const int32_t *xadj, const int32_t *adjncy, const int32_t *vwgt, int32_t n, int32_t nnz,
+                              unsigned long long *acc /* [0] sum c, [1] max c, [2] isolated, [3] bad */) {
+    unsigned long long s = 0, mx = 0, iso = 0, bad = 0;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t c = vwgt ? vwgt[v] : 1;
+        if (c < 1) bad = 1;
+        s += (unsigned long long)(c > 0 ? c : 0);
+        mx = (unsigned long long)c > mx ? (unsigned long long)c : mx;
+        const int32_t b = xadj[v], e = xadj[v + 1];
+        if (e < b || b < 0 || e > nnz) bad = 1;
+        iso += (b == e);
+    }
+    s = wave_sum(s);
+    iso = wave_sum(iso);
+    mx = wave_max(mx);
+    bad = wave_max(bad);
+    if (lane_id() == 0) {
+        atomicAdd(&acc[0], s);
+        atomicMax(&acc[1], mx);
+        atomicAdd(&acc[2], iso);
+        atomicMax(&acc[3], bad);
+    }
+}
+
+__global__ void k_check_adj(const int32_t *adjncy, const int32_t *adjwgt, int32_t n, int32_t nnz,
+                            unsigned long long *bad) {
+    unsigned long long b = 0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t u = adjncy[e];
+        if (u < 0 || u >= n) b = 1;
+        if (adjwgt && adjwgt[e] < 1) b = 1;
+    }
+    b = wave_max(b);
+    if (lane_id() == 0 && b) atomicMax(bad, b);
+}
+
+__global__ void k_check_labels(const int32_t *lab, int32_t n, int32_t lim, unsigned long long *bad) {
+    unsigned long long b = 0;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        if (lab[v] < 0 || lab[v] >= lim) b = 1;
+    b = wave_max(b);
+    if (lane_id() == 0 && b) atomicMax(bad, b);
+}
+
+struct Level {
+    DevGraph g;
+    int32_t *f2c = nullptr;  // this level -> next level
+};
+
+}  // namespace
+
+// Host-side summary of a graph: total vertex weight, max vertex weight,
+// isolated count. Also validates offsets, neighbour ids and weights.
+struct GraphInfo {
+    int64_t W = 0, cmax = 0, niso = 0;
+};
+
+static int graph_info(const DevGraph &g, GraphInfo &gi, Scratch &sc) {
+    hipStream_t s = sc.stream();
+    unsigned long long *acc = nullptr;
+    GP_TRY(sc.alloc(&acc, 5));
+    GP_HIP(hipMemsetAsync(acc, 0, sizeof(unsigned long long) * 5, s));
+    if (g.n > 0) {
+        hipLaunchKernelGGL(k_graph_stats, dim3(grid_for(g.n, 256, 4096)), dim3(256), 0, s, g.xadj, g.adjncy, g.vwgt,
+                           g.n, g.nnz, acc);
+        GP_LAUNCH_CHECK();
+    }
+    if (g.nnz > 0) {
+        hipLaunchKernelGGL(k_check_adj, dim3(grid_for(g.nnz, 256, 8192)), dim3(256), 0, s, g.adjncy, g.adjwgt, g.n,
+                           g.nnz, acc + 4);
+        GP_LAUNCH_CHECK();
+    }
+    unsigned long long h[5];
+    int32_t x0[2] = {0, 0};
+    GP_HIP(hipMemcpyAsync(h, acc, sizeof(h), hipMemcpyDeviceToHost, s));
+    GP_HIP(hipMemcpyAsync(&x0[0], g.xadj, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    GP_HIP(hipMemcpyAsync(&x0[1], g.xadj + g.n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    GP_HIP(hipStreamSynchronize(s));
+    if (h[3] || h[4] || x0[0] != 0 || x0[1] != g.nnz) {
+        set_error("graph: bad offsets, neighbour id out of range, or weight < 1");
+        return GP_ERR_GRAPH;
+    }
+    if (h[0] >= (1ull << 62)) {
+        set_error("graph: total vertex weight >= 2^62");
+        return GP_ERR_OVERFLOW;
+    }
+    gi.W = (int64_t)h[0];
+    gi.cmax = (int64_t)h[1];
+    gi.niso = (int64_t)h[2];
+    return GP_OK;
+}
+
+static int check_graph_args(const gp_graph *g) {
+    if (!g) {
+        set_error("graph is NULL");
+        return GP_ERR_ARG;
+    }
+    if (g->n < 0 || g->nnz < 0 || !g->xadj || (g->nnz > 0 && !g->adjncy)) {
+        set_error("graph: n < 0, nnz < 0 or a required array is NULL");
+        return GP_ERR_ARG;
+    }
+    return GP_OK;
+}
+
+static DevGraph dev_graph(const gp_graph *g) {
+    DevGraph d;
+    d.n = g->n;
+    d.nnz = g->nnz;
+    d.xadj = g->xadj;
+    d.adjncy = g->adjncy;
+    d.adjwgt = g->adjwgt;
+    d.vwgt = g->vwgt;
+    return d;
+}
+
+static int64_t lmax_of(int64_t W, int32_t k, double eps) {
+    const int64_t q = W / k + (W % k != 0);
+    return (int64_t)std::floor((1.0 + eps) * (double)q);
+}
+
+struct Timer {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipStream_t s;
+    explicit Timer(hipStream_t st) : s(st) {
+        (void)hipEventCreate(&a);
+        (void)hipEventCreate(&b);
+        (void)hipEventRecord(a, s);
+    }
+    float stop() {
+        float ms = 0.f;
+        (void)hipEventRecord(b, s);
+        (void)hipEventSynchronize(b);
+        (void)hipEventElapsedTime(&ms, a, b);
+        return ms;
+    }
+    ~Timer() {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+    }
+};
+
+static int do_partition(const gp_graph *gin, int32_t k, double eps, const gp_params *p, int32_t *part_out,
+                        gp_result *res, hipStream_t s) {
+    Scratch sc(s);
+    Timer t_total(s);
+    const DevGraph g0 = dev_graph(gin);
+    GraphInfo gi;
+    GP_TRY(graph_info(g0, gi, sc));
+    const int64_t lmax = lmax_of(gi.W, k, eps);
+    const int64_t ceil_wk = gi.W / k + (gi.W % k != 0);
+    const int64_t ucl = std::max(gi.cmax, lmax - ceil_wk);
+    int64_t tw = 0;
+    GP_TRY(total_edge_weight(g0, &tw, sc));
+    const bool wide = tw >= (int64_t)INT_MAX;
+
+    std::vector<Level> lev;
+    lev.push_back(Level{g0, nullptr});
+    int32_t *rowof0 = nullptr;
+    if (g0.nnz > 0) {
+        GP_TRY(sc.alloc(&rowof0, g0.nnz));
+        GP_TRY(build_rowof(g0, rowof0, sc));
+    }
+    int64_t ev_c = 0, ev_r = 0;
+    int64_t cur_n = g0.n - gi.niso;
+
+    // ---- coarsening
+    Timer t_coarse(s);
+    while (cur_n > (int64_t)p->coarsest_per_k * k) {
+        const size_t L = lev.size() - 1;
+        const DevGraph &f = lev[L].g;
+        const bool skip = (L == 0);
+        int32_t *labels = nullptr;
+        int64_t *W = nullptr;
+        GP_TRY(sc.alloc(&labels, f.n));
+        GP_TRY(sc.alloc(&W, f.n));
+        hipLaunchKernelGGL(k_identity_labels, dim3(grid_for(f.n, 256, 65536)), dim3(256), 0, s, f.xadj, f.n, skip,
+                           f.vwgt, labels, W);
+        GP_LAUNCH_CHECK();
+        LPOut st;
+        GP_TRY(lp_run(f, labels, W, f.n, ucl, p->rounds_coarsen, p->dir_alternate, wide, &st, sc));
+        ev_c += (int64_t)st.rounds_run * f.nnz;
+        CoarseOut co;
+        GP_TRY(sc.alloc(&co.xadj, (size_t)f.n + 1));
+        GP_TRY(sc.alloc(&co.adjncy, f.nnz));
+        GP_TRY(sc.alloc(&co.adjwgt, f.nnz));
+        GP_TRY(sc.alloc(&co.vwgt, f.n));
+        GP_TRY(sc.alloc(&co.f2c, f.n));
+        GP_TRY(contract(f, labels, skip, skip ? rowof0 : nullptr, co, sc));
+        if (co.n == cur_n) break;  // no shrink: drop the level
+        lev[L].f2c = co.f2c;
+        DevGraph c;
+        c.n = co.n;
+        c.nnz = co.nnz;
+        c.xadj = co.xadj;
+        c.adjncy = co.adjncy;
+        c.adjwgt = co.adjwgt;
+        c.vwgt = co.vwgt;
+        lev.push_back(Level{c, nullptr});
+        const int64_t prev = cur_n;
+        cur_n = co.n;
+        if ((int64_t)p->stall_den * cur_n > (int64_t)p->stall_num * prev) break;
+    }
+    const float ms_coarse = t_coarse.stop();
+
+    // ---- initial partition of the coarsest graph
+    Timer t_init(s);
+    const size_t Lc = lev.size() - 1;
+    int32_t *P = nullptr;
+    GP_TRY(sc.alloc(&P, lev[Lc].g.n));
+    GP_TRY(initial_partition(lev[Lc].g, Lc == 0, k, lmax, p->seed, p->attempts, p->rounds_refine, p->dir_alternate,
+                             wide, P, nullptr, sc));
+    const float ms_init = t_init.stop();
+
+    // ---- uncoarsening
+    Timer t_ref(s);
+    int64_t *B = nullptr;
+    GP_TRY(sc.alloc(&B, k));
+    for (size_t l = Lc + 1; l-- > 0;) {
+        const DevGraph &gl = lev[l].g;
+        int32_t *Pl = P;
+        if (l < Lc) {
+            if (l == 0) Pl = part_out;
+            else GP_TRY(sc.alloc(&Pl, gl.n));
+            GP_TRY(project(gl.n, lev[l].f2c, P, Pl, s));
+        } else if (l == 0) {
+            GP_HIP(hipMemcpyAsync(part_out, P, sizeof(int32_t) * (size_t)gl.n, hipMemcpyDeviceToDevice, s));
+            Pl = part_out;
+        }
+        GP_TRY(label_weights(gl, Pl, B, k, sc));
+        LPOut st;
+        GP_TRY(lp_run(gl, Pl, B, k, lmax, p->rounds_refine, p->dir_alternate, wide, &st, sc));
+        ev_r += (int64_t)st.rounds_run * gl.nnz;
+        P = Pl;
+    }
+    const float ms_ref = t_ref.stop();
+
+    // ---- vertices without neighbours, final metrics
+    GP_TRY(label_weights(g0, part_out, B, k, sc));
+    int32_t niso = 0;
+    GP_TRY(fill_isolated(g0, k, part_out, B, &niso, sc));
+    GP_TRY(label_weights(g0, part_out, B, k, sc));
+    int64_t *dcut = nullptr;
+    GP_TRY(sc.alloc(&dcut, 1));
+    GP_TRY(cut_dev(g0, part_out, rowof0, dcut, sc));
+    std::vector<int64_t> hB(k);
+    int64_t cut = 0;
+    GP_HIP(hipMemcpyAsync(hB.data(), B, sizeof(int64_t) * k, hipMemcpyDeviceToHost, s));
+    GP_HIP(hipMemcpyAsync(&cut, dcut, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    const float ms_total = t_total.stop();
+    int64_t maxb = 0;
+    for (int b = 0; b < k; b++) maxb = std::max(maxb, hB[b]);
+    if (res) {
+        res->cut = cut;
+        res->max_block_w = maxb;
+        res->lmax = lmax;
+        res->ucl = ucl;
+        res->balanced = maxb <= lmax;
+        res->levels = (int32_t)lev.size();
+        res->coarsest_n = Lc == 0 ? (int32_t)(g0.n - gi.niso) : lev[Lc].g.n;
+        res->n_isolated = niso;
+        res->edge_visits_cluster = ev_c;
+        res->edge_visits_refine = ev_r;
+        res->ms_coarsen = ms_coarse;
+        res->ms_init = ms_init;
+        res->ms_refine = ms_ref;
+        res->ms_total = ms_total;
+    }
+    sc.release();
+    GP_HIP(hipStreamSynchronize(s));
+    return maxb <= lmax ? GP_OK : GP_WARN_IMBALANCED;
+}
+
+}  // namespace gp
+
+using namespace gp;
+
+extern "C" {
+
+void gp_default_params(gp_params *p) {
+    if (!p) return;
+    p->rounds_coarsen = 10;
+    p->rounds_refine = 25;
+    p->coarsest_per_k = 60;
+    p->attempts = 4;
+    p->stall_num = 19;
+    p->stall_den = 20;
+    p->dir_alternate = 1;
+    p->seed = 0;
+}
+
+int64_t gp_lmax(int64_t total_vwgt, int32_t k, double eps) {
+    if (k < 1 || total_vwgt < 0 || !(eps >= 0.0)) return -1;
+    return lmax_of(total_vwgt, k, eps);
+}
+
+int gp_lp_cluster(const gp_graph *g, int64_t U, int32_t rounds, int32_t dir_alternate, int32_t *labels_out,
+                  gp_lp_stats *st_host, hipStream_t stream) {
+    GP_TRY(check_graph_args(g));
+    if (U < 1 || rounds < 0 || !labels_out) {
+        set_error("lp_cluster: U < 1, rounds < 0 or labels_out is NULL");
+        return GP_ERR_ARG;
+    }
+    Scratch sc(stream);
+    Timer t(stream);
+    const DevGraph d = dev_graph(g);
+    GraphInfo gi;
+    GP_TRY(graph_info(d, gi, sc));
+    int64_t tw = 0;
+    GP_TRY(total_edge_weight(d, &tw, sc));
+    int64_t *W = nullptr;
+    GP_TRY(sc.alloc(&W, d.n));
+    if (d.n > 0) {
+        hipLaunchKernelGGL(k_identity_labels, dim3(grid_for(d.n, 256, 65536)), dim3(256), 0, stream, d.xadj, d.n,
+                           false, d.vwgt, labels_out, W);
+        GP_LAUNCH_CHECK();
+    }
+    LPOut o;
+    GP_TRY(lp_run(d, labels_out, W, d.n, U, rounds, dir_alternate, tw >= (int64_t)INT_MAX, &o, sc));
+    const float ms = t.stop();
+    if (st_host) {
+        st_host->rounds_run = o.rounds_run;
+        st_host->moves = o.moves;
+        st_host->edge_visits = (int64_t)o.rounds_run * d.nnz;
+        st_host->ms = ms;
+    }
+    sc.release();
+    GP_HIP(hipStreamSynchronize(stream));
+    return GP_OK;
+}
+
+int gp_lp_refine(const gp_graph *g, int32_t k, int64_t lmax, int32_t rounds, int32_t dir_alternate,
+                 int32_t *part_inout, gp_lp_stats *st_host, hipStream_t stream) {
+    GP_TRY(check_graph_args(g));
+    if (k < 1 || lmax < 1 || rounds < 0 || !part_inout) {
+        set_error("lp_refine: k < 1, lmax < 1, rounds < 0 or part is NULL");
+        return GP_ERR_ARG;
+    }
+    Scratch sc(stream);
+    Timer t(stream);
+    const DevGraph d = dev_graph(g);
+    GraphInfo gi;
+    GP_TRY(graph_info(d, gi, sc));
+    unsigned long long *bad = nullptr;
+    GP_TRY(sc.alloc(&bad, 1));
+    GP_HIP(hipMemsetAsync(bad, 0, sizeof(unsigned long long), stream));
+    if (d.n > 0) {
+        hipLaunchKernelGGL(k_check_labels, dim3(grid_for(d.n, 256, 4096)), dim3(256), 0, stream, part_inout, d.n, k,
+                           bad);
+        GP_LAUNCH_CHECK();
+    }
+    unsigned long long hb = 0;
+    GP_HIP(hipMemcpyAsync(&hb, bad, sizeof(hb), hipMemcpyDeviceToHost, stream));
+    GP_HIP(hipStreamSynchronize(stream));
+    if (hb) {
+        set_error("lp_refine: a block id is outside [0, k)");
+        return GP_ERR_GRAPH;
+    }
+    int64_t tw = 0;
+    GP_TRY(total_edge_weight(d, &tw, sc));
+    int64_t *W = nullptr;
+    GP_TRY(sc.alloc(&W, k));
+    GP_TRY(label_weights(d, part_inout, W, k, sc));
+    LPOut o;
+    GP_TRY(lp_run(d, part_inout, W, k, lmax, rounds, dir_alternate, tw >= (int64_t)INT_MAX, &o, sc));
+    const float ms = t.stop();
+    if (st_host) {
+        st_host->rounds_run = o.rounds_run;
+        st_host->moves = o.moves;
+        st_host->edge_visits = (int64_t)o.rounds_run * d.nnz;
+        st_host->ms = ms;
+    }
+    sc.release();
+    GP_HIP(hipStreamSynchronize(stream));
+    return GP_OK;
+}
+
+int gp_contract(const gp_graph *g, const int32_t *labels, int32_t *xadj_c, int32_t *adjncy_c, int32_t *adjwgt_c,
+                int32_t *vwgt_c, int32_t *f2c, int32_t *n_c_host, int32_t *nnz_c_host, hipStream_t stream) {
+    GP_TRY(check_graph_args(g));
+    if (!labels || !xadj_c || !vwgt_c || !f2c || (g->nnz > 0 && (!adjncy_c || !adjwgt_c))) {
+        set_error("contract: an output or the labels array is NULL");
+        return GP_ERR_ARG;
+    }
+    Scratch sc(stream);
+    const DevGraph d = dev_graph(g);
+    GraphInfo gi;
+    GP_TRY(graph_info(d, gi, sc));
+    unsigned long long *bad = nullptr;
+    GP_TRY(sc.alloc(&bad, 1));
+    GP_HIP(hipMemsetAsync(bad, 0, sizeof(unsigned long long), stream));
+    if (d.n > 0) {
+        hipLaunchKernelGGL(k_check_labels, dim3(grid_for(d.n, 256, 4096)), dim3(256), 0, stream, labels, d.n, d.n,
+                           bad);
+        GP_LAUNCH_CHECK();
+    }
+    unsigned long long hb = 0;
+    GP_HIP(hipMemcpyAsync(&hb, bad, sizeof(hb), hipMemcpyDeviceToHost, stream));
+    GP_HIP(hipStreamSynchronize(stream));
+    if (hb) {
+        set_error("contract: a label is outside [0, n)");
+        return GP_ERR_GRAPH;
+    }
+    CoarseOut co;
+    co.xadj = xadj_c;
+    co.adjncy = adjncy_c;
+    co.adjwgt = adjwgt_c;
+    co.vwgt = vwgt_c;
+    co.f2c = f2c;
+    GP_TRY(contract(d, labels, false, nullptr, co, sc));
+    if (n_c_host) *n_c_host = co.n;
+    if (nnz_c_host) *nnz_c_host = co.nnz;
+    sc.release();
+    GP_HIP(hipStreamSynchronize(stream));
+    return GP_OK;
+}
+
+int gp_project(int32_t n, const int32_t *f2c, const int32_t *part_coarse, int32_t *part_fine, hipStream_t stream) {
+    if (n < 0 || (n > 0 && (!f2c || !part_coarse || !part_fine))) {
+        set_error("project: n < 0 or an array is NULL");
+        return GP_ERR_ARG;
+    }
+    GP_TRY(project(n, f2c, part_coarse, part_fine, stream));
+    return GP_OK;
+}
+
+int gp_cut_and_blocks(const gp_graph *g, int32_t k, const int32_t *part, int64_t *cut_host, int64_t *block_w_dev,
+                      hipStream_t stream) {
+    GP_TRY(check_graph_args(g));
+    if (k < 1 || !part) {
+        set_error("cut_and_blocks: k < 1 or part is NULL");
+        return GP_ERR_ARG;
+    }
+    Scratch sc(stream);
+    const DevGraph d = dev_graph(g);
+    int64_t *dcut = nullptr;
+    GP_TRY(sc.alloc(&dcut, 1));
+    GP_TRY(cut_dev(d, part, nullptr, dcut, sc));
+    if (block_w_dev) GP_TRY(label_weights(d, part, block_w_dev, k, sc));
+    if (cut_host) GP_HIP(hipMemcpyAsync(cut_host, dcut, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+    sc.release();
+    GP_HIP(hipStreamSynchronize(stream));
+    return GP_OK;
+}
+
+int gp_partition(const gp_graph *g, int32_t k, double eps, const gp_params *p, int32_t *part_out,
+                 gp_result *res_host, hipStream_t stream) {
+    GP_TRY(check_graph_args(g));
+    if (k < 1 || !(eps >= 0.0) || !part_out) {
+        set_error("partition: k < 1, eps < 0 or part_out is NULL");
+        return GP_ERR_ARG;
+    }
+    gp_params dp;
+    gp_default_params(&dp);
+    const gp_params *pp = p ? p : &dp;
+    if (pp->rounds_coarsen < 0 || pp->rounds_refine < 0 || pp->attempts < 1 || pp->coarsest_per_k < 1 ||
+        pp->stall_den < 1 || pp->stall_num < 0) {
+        set_error("partition: invalid parameters");
+        return GP_ERR_ARG;
+    }
+    return do_partition(g, k, eps, pp, part_out, res_host, stream);
+}
+
+const char *gp_strerror(int code) {
+    switch (code) {
+        case GP_OK: return "ok";
+        case GP_WARN_IMBALANCED: return "partition is valid but a block exceeds L_max";
+        case GP_ERR_ARG: return "invalid argument";
+        case GP_ERR_GRAPH: return "invalid graph or labels";
+        case GP_ERR_WORKSPACE: return "workspace too small";
+        case GP_ERR_OVERFLOW: return "size or weight overflow";
+        case GP_ERR_HIP: return "HIP runtime error";
+        default: return "unknown error";
+    }
+}
+
+const char *gp_last_error(void) { return gp::last_error(); }
+
+}  // extern "C"

@@ -1,0 +1,262 @@
+// prims.hpp — device-wide building blocks for gfx950: reduce-then-scan prefix
+// sums with fused input/output functors (scan, stable compaction, segmented
+// scans), and a stable LSD radix sort with 8-bit digits.
+//
+// Item counts may live on the device (`n_dev`): grids are sized for `nmax`
+// and tiles past the live count do nothing, so no host round trip is needed.
+#pragma once
+#include "gp_common.hpp"
+
+namespace gp {
+
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanBlock * kScanItems;
+
+__device__ __forceinline__ int64_t live_count(int64_t nmax, const int32_t *n_dev) {
+    if (!n_dev) return nmax;
+    int64_t n = *n_dev;
+    return n < nmax ? n : nmax;
+}
+
+// ---------------------------------------------------------------- scan
+
+template <typename T, typename In>
+__global__ __launch_bounds__(kScanBlock) void k_tile_reduce(In in, int64_t nmax, const int32_t *n_dev,
+                                                            T *partial) {
+    __shared__ T tmp[kScanBlock / kWave + 1];
+    const int64_t n = live_count(nmax, n_dev);
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    T s = 0;
+    if (base < n) {
+#pragma unroll
+        for (int i = 0; i < kScanItems; i++) {
+            int64_t idx = base + (int64_t)i * kScanBlock + threadIdx.x;
+            if (idx < n) s += in(idx);
+        }
+    }
+    s = block_sum<kScanBlock>(s, tmp);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// Each thread owns kScanItems consecutive items (blocked layout) so the
+// output functor sees items in ascending order within the thread.
+template <typename T, typename In, typename Out>
+__global__ __launch_bounds__(kScanBlock) void k_tile_scan(In in, Out out, int64_t nmax,
+                                                          const int32_t *n_dev, const T *tile_off,
+                                                          T *total) {
+    __shared__ T tmp[kScanBlock / kWave + 1];
+    const int64_t n = live_count(nmax, n_dev);
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    if (base >= n && !(blockIdx.x == 0 && total)) return;
+    T v[kScanItems];
+    T s = 0;
+    const int64_t mine = base + (int64_t)threadIdx.x * kScanItems;
+#pragma unroll
+    for (int i = 0; i < kScanItems; i++) {
+        int64_t idx = mine + i;
+        v[i] = idx < n ? in(idx) : T(0);
+        s += v[i];
+    }
+    T tot;
+    T ex = block_excl_scan<kScanBlock>(s, tmp, &tot);
+    T off = tile_off ? tile_off[blockIdx.x] : T(0);
+    ex += off;
+#pragma unroll
+    for (int i = 0; i < kScanItems; i++) {
+        int64_t idx = mine + i;
+        if (idx < n) out(idx, ex, v[i]);
+        ex += v[i];
+    }
+    if (total && threadIdx.x == 0) {
+        const int64_t ntiles = (n + kScanTile - 1) / kScanTile;
+        if (n == 0 && blockIdx.x == 0) *total = 0;
+        else if ((int64_t)blockIdx.x == ntiles - 1) *total = off + tot;
+    }
+}
+
+template <typename T>
+struct LoadIn {
+    const T *p;
+    __device__ T operator()(int64_t i) const { return p[i]; }
+};
+template <typename T>
+struct StoreExcl {
+    T *p;
+    __device__ void operator()(int64_t i, T ex, T) const { p[i] = ex; }
+};
+
+// Exclusive scan of in(i), i < n (n = min(nmax, *n_dev) when n_dev is set);
+// out(i, exclusive_prefix, value) is called once per item; *total_dev (may be
+// NULL) receives the sum.
+template <typename T, typename In, typename Out>
+int scan(In in, Out out, int64_t nmax, const int32_t *n_dev, T *total_dev, Scratch &sc) {
+    hipStream_t s = sc.stream();
+    const int64_t ntiles = (nmax + kScanTile - 1) / kScanTile;
+    if (ntiles <= 1) {
+        hipLaunchKernelGGL((k_tile_scan<T, In, Out>), dim3(1), dim3(kScanBlock), 0, s, in, out, nmax,
+                           n_dev, (const T *)nullptr, total_dev);
+        GP_LAUNCH_CHECK();
+        return GP_OK;
+    }
+    T *partial = nullptr, *off = nullptr;
+    GP_TRY(sc.alloc(&partial, ntiles));
+    GP_TRY(sc.alloc(&off, ntiles));
+    hipLaunchKernelGGL((k_tile_reduce<T, In>), dim3(ntiles), dim3(kScanBlock), 0, s, in, nmax, n_dev,
+                       partial);
+    GP_LAUNCH_CHECK();
+    GP_TRY((scan<T>(LoadIn<T>{partial}, StoreExcl<T>{off}, ntiles, nullptr, (T *)nullptr, sc)));
+    hipLaunchKernelGGL((k_tile_scan<T, In, Out>), dim3(ntiles), dim3(kScanBlock), 0, s, in, out, nmax,
+                       n_dev, (const T *)off, total_dev);
+    GP_LAUNCH_CHECK();
+    return GP_OK;
+}
+
+// Stable compaction: writes idx-th kept item's index mapping through `emit`.
+template <typename Flag, typename Emit>
+struct CompactOut {
+    Flag flag;
+    Emit emit;
+    __device__ void operator()(int64_t i, int32_t ex, int32_t v) const {
+        if (v) emit(i, ex);
+    }
+};
+template <typename Flag>
+struct FlagIn {
+    Flag flag;
+    __device__ int32_t operator()(int64_t i) const { return flag(i) ? 1 : 0; }
+};
+
+template <typename Flag, typename Emit>
+int compact(Flag flag, Emit emit, int64_t nmax, const int32_t *n_dev, int32_t *count_dev,
+            Scratch &sc) {
+    return scan<int32_t>(FlagIn<Flag>{flag}, CompactOut<Flag, Emit>{flag, emit}, nmax, n_dev,
+                         count_dev, sc);
+}
+
+// ---------------------------------------------------------------- radix sort
+
+constexpr int kSortBlock = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortBlock * kSortItems;
+
+template <typename K>
+__global__ __launch_bounds__(kSortBlock) void k_radix_hist(const K *keys, int64_t nmax,
+                                                           const int32_t *n_dev, int shift,
+                                                           uint32_t mask, uint32_t *hist,
+                                                           int ntiles) {
+    __shared__ uint32_t h[256];
+    const int64_t n = live_count(nmax, n_dev);
+    for (int d = threadIdx.x; d < 256; d += kSortBlock) h[d] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    for (int i = 0; i < kSortItems; i++) {
+        int64_t idx = base + (int64_t)i * kSortBlock + threadIdx.x;
+        if (idx < n) atomicAdd(&h[(uint32_t)(keys[idx] >> shift) & mask], 1u);
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < 256; d += kSortBlock) hist[(int64_t)d * ntiles + blockIdx.x] = h[d];
+}
+
+// Stable scatter: items of a tile are ranked in their original order.
+template <typename K, typename V>
+__global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K *kin, const V *vin, K *kout,
+                                                              V *vout, int64_t nmax,
+                                                              const int32_t *n_dev, int shift,
+                                                              int nbits, const uint32_t *offs,
+                                                              int ntiles) {
+    constexpr int NW = kSortBlock / kWave;
+    __shared__ uint32_t wcnt[NW][256];
+    __shared__ uint32_t run[256];
+    const int64_t n = live_count(nmax, n_dev);
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    if (base >= n) return;
+    const uint32_t mask = (1u << nbits) - 1u;
+    const int lane = lane_id(), w = threadIdx.x / kWave;
+    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (kWave - lane));
+    for (int d = threadIdx.x; d < 256; d += kSortBlock)
+        run[d] = offs[(int64_t)d * ntiles + blockIdx.x];
+    for (int r = 0; r < kSortItems; r++) {
+        const int64_t idx = base + (int64_t)r * kSortBlock + threadIdx.x;
+        const bool valid = idx < n;
+        K key = valid ? kin[idx] : K(0);
+        uint32_t dig = valid ? ((uint32_t)(key >> shift) & mask) : 0u;
+        for (int i = threadIdx.x; i < NW * 256; i += kSortBlock) (&wcnt[0][0])[i] = 0;
+        __syncthreads();
+        uint64_t peers = __ballot(valid);
+        for (int b = 0; b < nbits; b++) {
+            const bool bit = (dig >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & lt);
+        if (valid && rank == 0) wcnt[w][dig] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        for (int d = threadIdx.x; d < 256; d += kSortBlock) {
+            uint32_t acc = run[d];
+            for (int q = 0; q < NW; q++) {
+                uint32_t t = wcnt[q][d];
+                wcnt[q][d] = acc;
+                acc += t;
+            }
+            run[d] = acc;
+        }
+        __syncthreads();
+        if (valid) {
+            const uint32_t pos = wcnt[w][dig] + rank;
+            kout[pos] = key;
+            vout[pos] = vin[idx];
+        }
+        __syncthreads();
+    }
+}
+
+// Stable LSD sort of (keys, vals) on the low `bits` bits of the key. The
+// result is in (*keys, *vals) on return; the pointers may be swapped with the
+// temporaries.
+template <typename K, typename V>
+int radix_sort(K **keys, V **vals, K **ktmp, V **vtmp, int64_t nmax, const int32_t *n_dev, int bits,
+               Scratch &sc) {
+    hipStream_t s = sc.stream();
+    if (nmax <= 0 || bits <= 0) return GP_OK;
+    const int ntiles = (int)((nmax + kSortTile - 1) / kSortTile);
+    uint32_t *hist = nullptr;
+    GP_TRY(sc.alloc(&hist, (size_t)256 * ntiles));
+    for (int shift = 0; shift < bits; shift += 8) {
+        const int nb = (bits - shift) < 8 ? (bits - shift) : 8;
+        hipLaunchKernelGGL((k_radix_hist<K>), dim3(ntiles), dim3(kSortBlock), 0, s, *keys, nmax, n_dev,
+                           shift, (1u << nb) - 1u, hist, ntiles);
+        GP_LAUNCH_CHECK();
+        GP_TRY((scan<uint32_t>(LoadIn<uint32_t>{hist}, StoreExcl<uint32_t>{hist}, (int64_t)256 * ntiles,
+                               nullptr, (uint32_t *)nullptr, sc)));
+        hipLaunchKernelGGL((k_radix_scatter<K, V>), dim3(ntiles), dim3(kSortBlock), 0, s, *keys, *vals,
+                           *ktmp, *vtmp, nmax, n_dev, shift, nb, hist, ntiles);
+        GP_LAUNCH_CHECK();
+        K *tk = *keys;
+        *keys = *ktmp;
+        *ktmp = tk;
+        V *tv = *vals;
+        *vals = *vtmp;
+        *vtmp = tv;
+    }
+    return GP_OK;
+}
+
+// ---------------------------------------------------------------- misc kernels
+
+template <typename T>
+__global__ void k_fill(T *p, int64_t n, T v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+template <typename T>
+int fill(T *p, int64_t n, T v, hipStream_t s) {
+    if (n <= 0) return GP_OK;
+    hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, p, n, v);
+    GP_LAUNCH_CHECK();
+    return GP_OK;
+}
+
+}  // namespace gp

@@ -1,0 +1,204 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, bit-exact.
+
+Inputs are seeded synthetic graphs from graphgen (shared input generator);
+expected values come from the oracle only. Sizes are small enough for the
+oracle to finish in seconds but span several tiles, every degree tier of the
+proposal kernels (including the global-table hub tier), ragged tails, empty
+inputs and isolated vertices.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+gp = pytest.importorskip("paper_1710_08231_amd")
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "lp_worked_vectors.json")
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _star(n_leaves, extra=()):
+    edges = [(0, i) for i in range(1, n_leaves + 1)] + list(extra)
+    return graphgen.from_edges(n_leaves + 1, edges)
+
+
+def _cases():
+    cases = {
+        "rgg2k": graphgen.rgg2d(2000, 3),
+        "rgg16k": graphgen.rgg2d(16384, 1),
+        "rmat12": graphgen.rmat(12, 12),
+        "rmat16": graphgen.rmat(16, 16),
+        "grid": graphgen.grid3d(20, 17, 9, seed=3, wmax=10),
+        "star_hub": _star(20000),
+        "star_wg": _star(3000),
+        "star_wg2": _star(6000),
+        "weighted": graphgen.random_small(300, 0.05, 9, wmax=9, vmax=5),
+    }
+    return cases
+
+
+CASES = _cases()
+
+
+@pytest.fixture(scope="module")
+def dev_cases():
+    return {k: gp.to_device(v) for k, v in CASES.items()}
+
+
+def test_library_exports():
+    lib = gp.load()
+    for name in gp.EXPORTS:
+        assert hasattr(lib, name)
+
+
+@pytest.mark.parametrize("case", json.load(open(GOLDEN))["cases"], ids=lambda c: c["name"])
+def test_worked_vectors_on_gpu(case):
+    g = graphgen.from_edges(case["n"], case["edges"], vwgt=case.get("vwgt"))
+    dg = gp.to_device(g)
+    if case["mode"] == "cluster":
+        lab, st = gp.lp_cluster(dg, case["U"], case["rounds"])
+    else:
+        part = torch.tensor(case["part_in"], dtype=torch.int32, device="cuda")
+        lab, st = gp.lp_refine(dg, part, case["k"], case["lmax"], case["rounds"])
+    assert _np(lab).tolist() == case["labels"]
+    assert st["rounds_run"] == case["rounds_run"] and st["moves"] == case["moves"]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("U", [3, 40, 1000])
+def test_lp_cluster_matches_oracle(dev_cases, name, U):
+    g = CASES[name]
+    vmax = int(g["vwgt"].max()) if "vwgt" in g else 1
+    U = max(U, vmax)
+    lab, st = gp.lp_cluster(dev_cases[name], U, 10)
+    olab, ost = oracle.lp_cluster(g, U, 10)
+    assert np.array_equal(_np(lab), olab)
+    assert (st["rounds_run"], st["moves"], st["edge_visits"]) == (ost["rounds_run"], ost["moves"], ost["edge_visits"])
+
+
+@pytest.mark.parametrize("name", ["rgg16k", "rmat12", "grid", "weighted"])
+def test_lp_cluster_without_direction_rule(dev_cases, name):
+    g = CASES[name]
+    lab, st = gp.lp_cluster(dev_cases[name], 30, 7, dir_alternate=0)
+    olab, ost = oracle.lp_cluster(g, 30, 7, dir_alternate=0)
+    assert np.array_equal(_np(lab), olab) and st["rounds_run"] == ost["rounds_run"]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("k", [2, 16, 64])
+def test_lp_refine_matches_oracle(dev_cases, name, k):
+    g = CASES[name]
+    n = len(g["xadj"]) - 1
+    part = np.array([graphgen.rand_u64(k, i) % k for i in range(n)], np.int32)
+    W = oracle.total_vwgt(g)
+    lm = oracle.lmax(W, k, 0.03)
+    dp = torch.from_numpy(part).cuda()
+    P, st = gp.lp_refine(dev_cases[name], dp, k, lm, 25)
+    oP, ost = oracle.lp_refine(g, part, k, lm, 25)
+    assert np.array_equal(_np(P), oP)
+    assert (st["rounds_run"], st["moves"]) == (ost["rounds_run"], ost["moves"])
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_contract_matches_oracle(dev_cases, name):
+    g = CASES[name]
+    olab, _ = oracle.lp_cluster(g, 50, 10)
+    ocg, of2c = oracle.contract(g, olab)
+    cg, f2c = gp.contract(dev_cases[name], torch.from_numpy(olab).cuda())
+    assert np.array_equal(_np(f2c), of2c)
+    for key in ("xadj", "adjncy", "adjwgt", "vwgt"):
+        assert np.array_equal(_np(cg[key]), ocg[key]), key
+
+
+def test_contract_arbitrary_labels():
+    g = graphgen.random_small(200, 0.1, 4, wmax=3, vmax=2)
+    n = 200
+    lab = np.array([graphgen.rand_u64(77, i) % 37 * 5 for i in range(n)], np.int32)
+    ocg, of2c = oracle.contract(g, lab)
+    cg, f2c = gp.contract(gp.to_device(g), torch.from_numpy(lab).cuda())
+    assert np.array_equal(_np(f2c), of2c)
+    for key in ("xadj", "adjncy", "adjwgt", "vwgt"):
+        assert np.array_equal(_np(cg[key]), ocg[key]), key
+
+
+def test_project_and_cut():
+    g = graphgen.rmat(12, 5)
+    dg = gp.to_device(g)
+    olab, _ = oracle.lp_cluster(g, 20, 10)
+    ocg, of2c = oracle.contract(g, olab)
+    nc = len(ocg["xadj"]) - 1
+    pc = np.array([graphgen.rand_u64(3, i) % 7 for i in range(nc)], np.int32)
+    pf = gp.project(torch.from_numpy(of2c).cuda(), torch.from_numpy(pc).cuda())
+    assert np.array_equal(_np(pf), oracle.project(of2c, pc))
+    cut, B = gp.cut_and_blocks(dg, pf, 7)
+    assert cut == oracle.cut(g, _np(pf))
+    assert np.array_equal(_np(B), oracle.block_weights(g, _np(pf), 7))
+
+
+PART_CASES = [
+    ("rgg16k", 2), ("rgg2k", 8), ("rmat12", 16), ("rmat16", 16), ("grid", 8), ("weighted", 5),
+    ("star_hub", 4), ("rgg16k", 64),
+]
+
+
+@pytest.mark.parametrize("name,k", PART_CASES)
+def test_partition_matches_oracle(dev_cases, name, k):
+    g = CASES[name]
+    part, res = gp.partition(dev_cases[name], k, 0.03)
+    opart, ores = oracle.partition(g, k, 0.03)
+    assert np.array_equal(_np(part), opart)
+    for key in ("cut", "max_block_w", "lmax", "ucl", "balanced", "levels", "coarsest_n", "n_isolated",
+                "edge_visits_cluster", "edge_visits_refine"):
+        assert res[key] == ores[key], key
+    assert res["code"] == ores["code"]
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_partition_seeds_and_attempts(dev_cases, seed):
+    g = CASES["rmat12"]
+    part, res = gp.partition(dev_cases["rmat12"], 8, 0.05, seed=seed, attempts=3)
+    opart, ores = oracle.partition(g, 8, 0.05, seed=seed, attempts=3)
+    assert np.array_equal(_np(part), opart) and res["cut"] == ores["cut"]
+
+
+def test_partition_edge_cases():
+    # empty graph, all-isolated, graph smaller than the coarsening threshold, k=1
+    for g, k in [(graphgen.from_edges(0, []), 2), (graphgen.from_edges(9, []), 4),
+                 (graphgen.from_edges(7, [(0, 1), (1, 2), (4, 5)]), 3),
+                 (graphgen.rgg2d(500, 2), 1), (graphgen.random_small(50, 0.1, 2, wmax=4, vmax=7), 3)]:
+        n = len(g["xadj"]) - 1
+        opart, ores = oracle.partition(g, k, 0.03)
+        part, res = gp.partition(gp.to_device(g), k, 0.03)
+        assert np.array_equal(_np(part)[:n], opart)
+        assert res["cut"] == ores["cut"] and res["code"] == ores["code"]
+
+
+def test_errors_are_reported():
+    g = gp.to_device(graphgen.rgg2d(100, 1))
+    with pytest.raises(gp.GPError):
+        gp.partition(g, 0, 0.03)
+    bad = dict(g)
+    bad["adjncy"] = g["adjncy"].clone()
+    bad["adjncy"][0] = 1000
+    with pytest.raises(gp.GPError):
+        gp.lp_cluster(bad, 5)
+    with pytest.raises(gp.GPError):
+        gp.lp_refine(g, torch.full((100,), 3, dtype=torch.int32, device="cuda"), 2, 60)
+
+
+def test_repeat_runs_identical(dev_cases):
+    a, _ = gp.partition(dev_cases["rmat16"], 16, 0.03)
+    b, _ = gp.partition(dev_cases["rmat16"], 16, 0.03)
+    assert torch.equal(a, b)
