@@ -1,0 +1,136 @@
+"""Benchmark: multilevel LP partition of a resident synthetic graph on one MI355X.
+
+One step = one gp_partition call (all hot-path steps: level setup, LP
+clustering, contraction, initial partitioning, projection, LP refinement,
+isolated-vertex placement, cut and balance) on a graph already in HBM.
+value = LP edge visits of the step (clustering + refinement, summed over
+levels and rounds) / step time; ms_per_step = end-to-end partition time.
+
+Prints one JSON line. Default workload: R-MAT scale 22, edge factor 16
+(a,b,c,d = .57,.19,.19,.05), k = 16, eps = 0.03.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOADS = {
+    "rmat22": dict(kind="rmat", scale=22, seed=22, k=16),
+    "rmat24": dict(kind="rmat", scale=24, seed=24, k=64),
+    "grid256": dict(kind="grid", side=256, seed=3, k=64),
+    "rgg16k": dict(kind="rgg", n=16384, seed=1, k=2),
+}
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def make_graph(w):
+    import graphgen
+    if w["kind"] == "rmat":
+        return graphgen.rmat(w["scale"], w["seed"])
+    if w["kind"] == "grid":
+        s = w["side"]
+        return graphgen.grid3d(s, s, s, seed=w["seed"], wmax=10)
+    return graphgen.rgg2d(w["n"], w["seed"])
+
+
+def cpu_baseline(g, w, budget_rounds):
+    """The oracle as it stands, on a bounded sample: LP clustering of level 0."""
+    import numpy as np
+    import oracle
+    n = len(g["xadj"]) - 1
+    k = w["k"]
+    W = oracle.total_vwgt(g)
+    lm = oracle.lmax(W, k, 0.03)
+    ucl = max(1, lm - (-(-W // k)))
+    d = np.diff(g["xadj"])
+    keep = np.nonzero(d > 0)[0]
+    newid = np.full(n, -1, np.int64)
+    newid[keep] = np.arange(len(keep))
+    g0 = {"xadj": np.concatenate([[0], np.cumsum(d[keep])]).astype(np.int32),
+          "adjncy": newid[g["adjncy"]].astype(np.int32)}
+    t = time.perf_counter()
+    _, st = oracle.lp_cluster(g0, ucl, budget_rounds)
+    dt = time.perf_counter() - t
+    return {"value": st["edge_visits"] / dt, "unit": "edge-visits/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle lp_cluster on level 0 of the same graph (isolated vertices removed), "
+                      f"U={ucl}, up to {budget_rounds} rounds: {st['edge_visits']} edge visits in {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rmat22", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-rounds", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is not built",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1710_08231_amd as gp
+
+    w = WORKLOADS[args.workload]
+    t0 = time.perf_counter()
+    g = make_graph(w)
+    gen_s = time.perf_counter() - t0
+    n, nnz = len(g["xadj"]) - 1, len(g["adjncy"])
+    print(f"[bench] workload={args.workload} n={n} nnz={nnz} generated in {gen_s:.1f}s", file=sys.stderr,
+          flush=True)
+    dg = gp.to_device(g)
+    torch.cuda.synchronize()
+    k = w["k"]
+    for i in range(args.warmup):
+        _, res = gp.partition(dg, k, 0.03)
+        print(f"[bench] warmup {i} ms={res['ms_total']:.2f}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    visits = 0
+    results = []
+    t = time.perf_counter()
+    for i in range(args.steps):
+        part, res = gp.partition(dg, k, 0.03)
+        visits += res["edge_visits_cluster"] + res["edge_visits_refine"]
+        results.append(res)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    ms = dt * 1000.0 / args.steps
+    last = results[-1]
+    print(f"[bench] timed {args.steps} steps: {ms:.2f} ms/step", file=sys.stderr, flush=True)
+    out = {
+        "metric": "LP edge-visits/sec + end-to-end k-way partition time; cut & balance vs oracle",
+        "value": visits / dt,
+        "unit": "edge-visits/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "nnz": nnz, "k": k, "eps": 0.03},
+        "partition_ms": ms,
+        "cut": last["cut"],
+        "balanced": bool(last["balanced"]),
+        "levels": last["levels"],
+        "coarsest_n": last["coarsest_n"],
+        "edge_visits_per_step": visits // args.steps,
+        "phase_ms": {"coarsen": last["ms_coarsen"], "init": last["ms_init"], "refine": last["ms_refine"]},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(g, w, args.cpu_rounds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

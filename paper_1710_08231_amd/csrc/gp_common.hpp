@@ -39,7 +39,7 @@ const char *last_error();
 // released (hipFreeAsync on the same stream) when the object goes out of scope.
 class Scratch {
   public:
-    explicit Scratch(hipStream_t s) : s_(s) {}
+    explicit Scratch(hipStream_t s) : s_(s) { keep_pool(); }
     ~Scratch() { release(); }
     Scratch(const Scratch &) = delete;
     Scratch &operator=(const Scratch &) = delete;
@@ -59,15 +59,55 @@ class Scratch {
         *out = static_cast<T *>(p);
         return GP_OK;
     }
+    // Reusable buffer `slot` of at least `count` elements, kept for the life of
+    // this object. Work is stream ordered, so successive users of one slot
+    // never overlap.
+    template <typename T>
+    int temp(T **out, size_t count, int slot) {
+        const size_t bytes = (count ? count : 1) * sizeof(T);
+        if (slot >= (int)tmp_.size()) tmp_.resize(slot + 1, {nullptr, 0});
+        if (tmp_[slot].second < bytes) {
+            if (tmp_[slot].first) (void)hipFreeAsync(tmp_[slot].first, s_);
+            void *p = nullptr;
+            const size_t grow = bytes + bytes / 4;
+            hipError_t e = hipMallocAsync(&p, grow, s_);
+            if (e != hipSuccess) {
+                set_error((std::string("hipMallocAsync(") + std::to_string(grow) + "): " +
+                           hipGetErrorString(e)).c_str());
+                tmp_[slot] = {nullptr, 0};
+                return GP_ERR_HIP;
+            }
+            tmp_[slot] = {p, grow};
+        }
+        *out = static_cast<T *>(tmp_[slot].first);
+        return GP_OK;
+    }
     void release() {
         for (void *p : ptrs_) (void)hipFreeAsync(p, s_);
         ptrs_.clear();
+        for (auto &t : tmp_)
+            if (t.first) (void)hipFreeAsync(t.first, s_);
+        tmp_.clear();
     }
     hipStream_t stream() const { return s_; }
 
   private:
+    // Keep freed blocks in the device's default pool instead of returning them
+    // to the driver at every synchronisation.
+    static void keep_pool() {
+        static bool done = false;
+        if (done) return;
+        int dev = 0;
+        hipMemPool_t pool;
+        if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+            uint64_t thr = UINT64_MAX;
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+        }
+        done = true;
+    }
     hipStream_t s_;
     std::vector<void *> ptrs_;
+    std::vector<std::pair<void *, size_t>> tmp_;
 };
 
 inline unsigned grid_for(int64_t items, int per_block, unsigned cap = 1u << 20) {

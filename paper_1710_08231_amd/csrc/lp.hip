@@ -142,6 +142,8 @@ __device__ __forceinline__ void block_best(AccT &bc, int32_t &bl, AccT *tc, int3
 }
 
 constexpr int kPropBlock = 256;
+constexpr int kSmallLabels = 4096;  // label counts handled with per-block LDS totals
+constexpr int kDenseLabels = 256;   // label counts handled with dense per-vertex tables
 
 // GL lanes per vertex (GL <= 64), TBL table slots per vertex.
 template <int GL, int TBL, typename AccT>
@@ -365,6 +367,297 @@ __global__ __launch_bounds__(BLOCK) void k_propose_hub(LPArgs a, const int32_t *
     }
 }
 
+// ---------------------------------------------------------------- hubs split over workgroups
+
+// A hub's edges are cut into chunks of kHubChunk entries, each inserted by
+// its own workgroup into the hub's global table; the table is then scanned in
+// slices of kHubSlice slots, each slice merging its best (conn, label) into a
+// packed 64-bit key with atomicMax: high word conn, low word INT_MAX - label,
+// so the maximum is the largest connection with the smallest label. Used for
+// 32-bit connection sums (the packed key needs conn < 2^31).
+constexpr int kHubChunk = 4096;
+constexpr int kHubSlice = 4096;
+
+struct HubPlan {
+    const int32_t *hubs;       // [nh] hub vertex ids
+    const int64_t *toff;       // [nh] table offset
+    const int32_t *tlog;       // [nh] log2 table capacity
+    const int32_t *chunk_hub;  // [nchunks]
+    const int32_t *chunk_first;  // [nh] first chunk of hub
+    const int32_t *slice_hub;  // [nslices]
+    const int32_t *slice_first;  // [nh]
+    int32_t *key;
+    int32_t *val;
+    unsigned long long *own;     // [nh]
+    unsigned long long *best1;   // [nh]
+    unsigned long long *best2;   // [nh]
+    int32_t *need2;              // [nh]
+};
+
+__device__ __forceinline__ unsigned long long pack_best(int32_t c, int32_t L) {
+    return ((unsigned long long)(uint32_t)c << 32) | (unsigned long long)(uint32_t)(INT_MAX - L);
+}
+
+__global__ __launch_bounds__(256) void k_hub_insert(LPArgs a, HubPlan hp) {
+    if (*a.done) return;
+    __shared__ int32_t tmp[256 / kWave + 1];
+    const int32_t h = hp.chunk_hub[blockIdx.x];
+    const int32_t v = hp.hubs[h];
+    const int32_t own = a.labels[v];
+    const int32_t beg = a.xadj[v] + (blockIdx.x - hp.chunk_first[h]) * kHubChunk;
+    const int32_t end = min(a.xadj[v + 1], beg + kHubChunk);
+    const int lg = hp.tlog[h];
+    int32_t *key = hp.key + hp.toff[h];
+    int32_t *val = hp.val + hp.toff[h];
+    int32_t oc = 0;
+    for (int32_t e = beg + threadIdx.x; e < end; e += 256) {
+        const int32_t u = a.adjncy[e];
+        const int32_t wgt = a.adjwgt ? a.adjwgt[e] : 1;
+        const int32_t L = a.labels[u];
+        if (L == own) oc += wgt;
+        else if (dir_ok(L, own, a.dirmode)) tbl_insert_global<int32_t>(key, val, (1u << lg) - 1, lg, L, wgt);
+    }
+    oc = block_sum<256>(oc, tmp);
+    if (threadIdx.x == 0 && oc) atomicAdd(&hp.own[h], (unsigned long long)oc);
+}
+
+// phase 1 (unfiltered best) or phase 2 (best among labels with room; only for
+// hubs flagged in need2); phase 2 also empties the slice for the next round.
+template <bool PHASE2>
+__global__ __launch_bounds__(256) void k_hub_scan(LPArgs a, HubPlan hp) {
+    if (*a.done) return;
+    __shared__ unsigned long long tmp[256 / kWave + 1];
+    const int32_t h = hp.slice_hub[blockIdx.x];
+    const uint32_t cap = 1u << hp.tlog[h];
+    const uint32_t s0 = (uint32_t)(blockIdx.x - hp.slice_first[h]) * kHubSlice;
+    const uint32_t s1 = min(cap, s0 + kHubSlice);
+    int32_t *key = hp.key + hp.toff[h];
+    int32_t *val = hp.val + hp.toff[h];
+    const bool active = !PHASE2 || hp.need2[h];
+    const int64_t cv = PHASE2 ? vweight(a.vwgt, hp.hubs[h]) : 0;
+    unsigned long long best = 0;
+    for (uint32_t i = s0 + threadIdx.x; i < s1; i += 256) {
+        const int32_t L = ld_agent(&key[i]);
+        if (active && L >= 0) {
+            const int32_t c = ld_agent(&val[i]);
+            if (!PHASE2 || a.W[L] + cv <= a.U) {
+                const unsigned long long pk = pack_best(c, L);
+                best = pk > best ? pk : best;
+            }
+        }
+        if (PHASE2 && L >= 0) {
+            key[i] = -1;
+            val[i] = 0;
+        }
+    }
+    best = block_max<256>(best, tmp);
+    if (threadIdx.x == 0 && best) atomicMax(PHASE2 ? &hp.best2[h] : &hp.best1[h], best);
+}
+
+template <bool FINAL>
+__global__ void k_hub_decide(LPArgs a, HubPlan hp, int32_t nh) {
+    if (*a.done) return;
+    for (int32_t h = blockIdx.x * blockDim.x + threadIdx.x; h < nh; h += gridDim.x * blockDim.x) {
+        const int32_t v = hp.hubs[h];
+        const int64_t oc = (int64_t)hp.own[h];
+        if (!FINAL) {
+            const unsigned long long b = hp.best1[h];
+            int32_t target = -1, need = 0;
+            if (b) {
+                const int64_t c = (int64_t)(b >> 32);
+                const int32_t L = INT_MAX - (int32_t)(uint32_t)(b & 0xFFFFFFFFull);
+                if (c > oc) {
+                    if (a.W[L] + vweight(a.vwgt, v) <= a.U) target = L;
+                    else need = 1;
+                }
+            }
+            a.prop[v] = target;
+            hp.need2[h] = need;
+        } else {
+            if (hp.need2[h]) {
+                const unsigned long long b = hp.best2[h];
+                int32_t target = -1;
+                if (b) {
+                    const int64_t c = (int64_t)(b >> 32);
+                    const int32_t L = INT_MAX - (int32_t)(uint32_t)(b & 0xFFFFFFFFull);
+                    if (c > oc) target = L;
+                }
+                a.prop[v] = target;
+            }
+            hp.own[h] = 0;
+            hp.best1[h] = 0;
+            hp.best2[h] = 0;
+            hp.need2[h] = 0;
+        }
+    }
+}
+
+__global__ void k_hub_plan(const int32_t *xadj, const int32_t *hubs, int32_t nh, int32_t *tlog, int64_t *tcap,
+                           int32_t *nchunk, int32_t *nslice) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nh; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = hubs[i];
+        const int64_t d = xadj[v + 1] - xadj[v];
+        int lg = 1;
+        while ((int64_t(1) << lg) < 2 * d) lg++;
+        tlog[i] = lg;
+        tcap[i] = int64_t(1) << lg;
+        nchunk[i] = (int32_t)((d + kHubChunk - 1) / kHubChunk);
+        nslice[i] = (int32_t)(((int64_t(1) << lg) + kHubSlice - 1) / kHubSlice);
+    }
+}
+
+__global__ void k_hub_expand(const int32_t *first, const int32_t *num, int32_t nh, int32_t *owner) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nh; i += (int64_t)gridDim.x * blockDim.x)
+        for (int32_t j = 0; j < num[i]; j++) owner[first[i] + j] = (int32_t)i;
+}
+
+// ---------------------------------------------------------------- dense tables (few labels)
+
+// Refinement of a k-way partition: labels are block ids < nlabels <= KT, so
+// the per-vertex table is a dense array of KT connection sums (no hashing)
+// and the k label weights of the round start sit in LDS, which lets the
+// capacity test run inside the single selection pass.
+template <int GL, int KT, typename AccT>
+__global__ __launch_bounds__(kPropBlock) void k_dense_group(LPArgs a, int32_t nlabels,
+                                                            const int32_t *__restrict__ verts, int32_t count) {
+    if (*a.done) return;
+    constexpr int GPW = kWave / GL;
+    constexpr int NW = kPropBlock / kWave;
+    __shared__ AccT sval[NW * GPW * KT];
+    __shared__ int64_t sW[KT];
+    const int lane = lane_id(), w = threadIdx.x / kWave;
+    const int gl = lane % GL, grp = lane / GL;
+    AccT *val = sval + (w * GPW + grp) * KT;
+    for (int i = threadIdx.x; i < KT; i += kPropBlock) sW[i] = i < nlabels ? a.W[i] : (int64_t(1) << 62);
+    for (int i = gl; i < KT; i += GL) val[i] = 0;
+    __syncthreads();
+    const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t stride = (int64_t)gridDim.x * NW * GPW;
+    for (int64_t wb = ((int64_t)b * NW + w) * GPW; wb < count; wb += stride) {
+        const int64_t idx = wb + grp;
+        const bool valid = idx < count;
+        const int32_t v = valid ? verts[idx] : 0;
+        const int32_t beg = valid ? a.xadj[v] : 0, end = valid ? a.xadj[v + 1] : 0;
+        const int32_t own = valid ? a.labels[v] : -1;
+        AccT oc = 0;
+        const int nch = (end - beg + GL - 1) / GL;
+        const int maxch = wave_max(nch);
+        for (int ch = 0; ch < maxch; ch++) {
+            const int32_t e = beg + ch * GL + gl;
+            if (e < end) {
+                const int32_t u = a.adjncy[e];
+                const AccT wgt = a.adjwgt ? (AccT)a.adjwgt[e] : (AccT)1;
+                const int32_t L = a.labels[u];
+                if (L == own) oc += wgt;
+                else if (dir_ok(L, own, a.dirmode)) lds_add<AccT>(&val[L], wgt);
+            }
+        }
+        wave_sync();
+        oc = group_sum<GL>(oc);
+        const int64_t cv = valid ? vweight(a.vwgt, v) : 0;
+        AccT bc = 0;
+        int32_t bl = INT_MAX;
+        for (int i = gl; i < KT; i += GL) {
+            const AccT c = val[i];
+            if (c > 0 && sW[i] + cv <= a.U && better(c, i, bc, bl)) {
+                bc = c;
+                bl = i;
+            }
+        }
+        group_best<GL, AccT>(bc, bl);
+        if (valid && gl == 0) a.prop[v] = (bl != INT_MAX && bc > oc) ? bl : -1;
+        wave_sync();
+        for (int i = gl; i < KT; i += GL) val[i] = 0;
+        wave_sync();
+    }
+}
+
+template <int BLOCK, int KT, typename AccT>
+__global__ __launch_bounds__(BLOCK) void k_dense_block(LPArgs a, int32_t nlabels, const int32_t *__restrict__ verts,
+                                                       int32_t count) {
+    if (*a.done) return;
+    constexpr int NW = BLOCK / kWave;
+    __shared__ AccT val[NW][KT];  // one table per wave limits same-address contention
+    __shared__ int64_t sW[KT];
+    __shared__ AccT tc[NW + 1];
+    __shared__ int32_t tl[NW + 1];
+    const int w = threadIdx.x / kWave;
+    for (int i = threadIdx.x; i < KT; i += BLOCK) sW[i] = i < nlabels ? a.W[i] : (int64_t(1) << 62);
+    for (int i = threadIdx.x; i < NW * KT; i += BLOCK) (&val[0][0])[i] = 0;
+    __syncthreads();
+    for (int64_t idx = xcd_block(blockIdx.x, gridDim.x); idx < count; idx += gridDim.x) {
+        const int32_t v = verts[idx];
+        const int32_t beg = a.xadj[v], end = a.xadj[v + 1];
+        const int32_t own = a.labels[v];
+        AccT oc = 0;
+        for (int32_t e = beg + threadIdx.x; e < end; e += BLOCK) {
+            const int32_t u = a.adjncy[e];
+            const AccT wgt = a.adjwgt ? (AccT)a.adjwgt[e] : (AccT)1;
+            const int32_t L = a.labels[u];
+            if (L == own) oc += wgt;
+            else if (dir_ok(L, own, a.dirmode)) lds_add<AccT>(&val[w][L], wgt);
+        }
+        __syncthreads();
+        oc = block_sum<BLOCK>(oc, tc);
+        const int64_t cv = vweight(a.vwgt, v);
+        AccT bc = 0;
+        int32_t bl = INT_MAX;
+        for (int i = threadIdx.x; i < KT; i += BLOCK) {
+            AccT c = 0;
+            for (int q = 0; q < NW; q++) c += val[q][i];
+            if (c > 0 && sW[i] + cv <= a.U && better(c, i, bc, bl)) {
+                bc = c;
+                bl = i;
+            }
+        }
+        block_best<BLOCK, AccT>(bc, bl, tc, tl);
+        if (threadIdx.x == 0) a.prop[v] = (bl != INT_MAX && bc > oc) ? bl : -1;
+        for (int i = threadIdx.x; i < NW * KT; i += BLOCK) (&val[0][0])[i] = 0;
+        __syncthreads();
+    }
+}
+
+template <int KT, typename AccT>
+int launch_dense(const LPArgs &a, int32_t nlabels, const int32_t *verts, const int64_t *tstart, hipStream_t s) {
+    auto cnt = [&](int t) { return (int32_t)(tstart[t + 1] - tstart[t]); };
+    auto lst = [&](int t) { return verts + tstart[t]; };
+    constexpr int NW = kPropBlock / kWave;
+    constexpr int G1 = KT >= 256 ? 16 : 4;
+    constexpr int G2 = KT >= 256 ? 16 : 8;
+    auto blocks_for = [&](int32_t c, int per_block) { return grid_for(c, per_block, 16384); };
+    int32_t c;
+    if ((c = cnt(1)) > 0)
+        hipLaunchKernelGGL((k_dense_group<G1, KT, AccT>), dim3(blocks_for(c, NW * (kWave / G1))), dim3(kPropBlock), 0,
+                           s, a, nlabels, lst(1), c);
+    if ((c = cnt(2)) > 0)
+        hipLaunchKernelGGL((k_dense_group<G2, KT, AccT>), dim3(blocks_for(c, NW * (kWave / G2))), dim3(kPropBlock), 0,
+                           s, a, nlabels, lst(2), c);
+    if ((c = cnt(3)) > 0)
+        hipLaunchKernelGGL((k_dense_group<16, KT, AccT>), dim3(blocks_for(c, NW * 4)), dim3(kPropBlock), 0, s, a,
+                           nlabels, lst(3), c);
+    if ((c = cnt(4)) > 0)
+        hipLaunchKernelGGL((k_dense_group<32, KT, AccT>), dim3(blocks_for(c, NW * 2)), dim3(kPropBlock), 0, s, a,
+                           nlabels, lst(4), c);
+    if ((c = cnt(5)) > 0)
+        hipLaunchKernelGGL((k_dense_group<64, KT, AccT>), dim3(blocks_for(c, NW)), dim3(kPropBlock), 0, s, a, nlabels,
+                           lst(5), c);
+    if ((c = cnt(6)) > 0)
+        hipLaunchKernelGGL((k_dense_block<256, KT, AccT>), dim3(grid_for(c, 1, 8192)), dim3(256), 0, s, a, nlabels,
+                           lst(6), c);
+    if ((c = cnt(7) + cnt(8)) > 0)
+        hipLaunchKernelGGL((k_dense_block<1024, KT, AccT>), dim3(grid_for(c, 1, 4096)), dim3(1024), 0, s, a, nlabels,
+                           lst(7), c);
+    GP_LAUNCH_CHECK();
+    return GP_OK;
+}
+
+template <typename AccT>
+int launch_dense_any(const LPArgs &a, int32_t nlabels, const int32_t *verts, const int64_t *tstart, hipStream_t s) {
+    if (nlabels <= 16) return launch_dense<16, AccT>(a, nlabels, verts, tstart, s);
+    if (nlabels <= 64) return launch_dense<64, AccT>(a, nlabels, verts, tstart, s);
+    return launch_dense<256, AccT>(a, nlabels, verts, tstart, s);
+}
+
 // ---------------------------------------------------------------- tiers
 
 // Degree tiers. Tier 0: no neighbours (never proposes). Tiers 1..5: GL lanes
@@ -497,6 +790,28 @@ __global__ void k_apply_w(const uint32_t *mk, const int32_t *mv, const int32_t *
     }
 }
 
+// Few labels: net weight change per label aggregated in LDS first.
+__global__ __launch_bounds__(256) void k_apply_w_small(const uint32_t *mk, const int32_t *mv, const int32_t *nmov,
+                                                       const int32_t *oldlab, const int32_t *vwgt, int32_t nl,
+                                                       int64_t *W) {
+    __shared__ unsigned long long h[kSmallLabels];
+    const int32_t n = *nmov;
+    if ((int64_t)blockIdx.x * blockDim.x >= n) return;
+    for (int i = threadIdx.x; i < nl; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t old = oldlab[p];
+        if (old < 0) continue;
+        const unsigned long long c = (unsigned long long)vweight(vwgt, mv[p]);
+        atomicAdd(&h[mk[p]], c);
+        atomicAdd(&h[old], (unsigned long long)(-(long long)c));
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nl; i += blockDim.x)
+        if (h[i]) atomicAdd((unsigned long long *)&W[i], h[i]);
+}
+
 __global__ void k_round_end(LPDev *dev, int32_t r) {
     if (dev->done) return;
     const int32_t m = dev->round_moves;
@@ -515,6 +830,22 @@ __global__ void k_label_weights(const int32_t *labels, const int32_t *vwgt, int3
     }
 }
 
+// Few labels (k-way partitions): per-block LDS totals, then one global atomic per label and block.
+__global__ __launch_bounds__(256) void k_label_weights_small(const int32_t *labels, const int32_t *vwgt, int32_t n,
+                                                             int32_t nl, int64_t *W) {
+    __shared__ unsigned long long h[kSmallLabels];
+    for (int i = threadIdx.x; i < nl; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t L = labels[v];
+        if (L >= 0) atomicAdd(&h[L], (unsigned long long)vweight(vwgt, (int32_t)v));
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nl; i += blockDim.x)
+        if (h[i]) atomicAdd((unsigned long long *)&W[i], h[i]);
+}
+
 struct EdgeWeightIn {
     const int32_t *w;
     __device__ int64_t operator()(int64_t i) const { return (int64_t)w[i]; }
@@ -525,7 +856,7 @@ struct NoOut64 {
 
 template <typename AccT>
 int launch_proposals(const LPArgs &a, const int32_t *verts, const int64_t *tstart, const int32_t *hub_log,
-                     const int64_t *hub_off, int32_t *gkey, AccT *gval, hipStream_t s) {
+                     const int64_t *hub_off, int32_t *gkey, AccT *gval, hipStream_t s, bool skip_hubs = false) {
     auto cnt = [&](int t) { return (int32_t)(tstart[t + 1] - tstart[t]); };
     auto lst = [&](int t) { return verts + tstart[t]; };
     constexpr int NW = kPropBlock / kWave;
@@ -561,7 +892,7 @@ int launch_proposals(const LPArgs &a, const int32_t *verts, const int64_t *tstar
         hipLaunchKernelGGL((k_propose_block<1024, T7, AccT>), dim3(grid_for(c, 1, 2048)), dim3(1024), 0, s, a,
                            lst(7), c);
     }
-    if ((c = cnt(8)) > 0) {
+    if (!skip_hubs && (c = cnt(8)) > 0) {
         hipLaunchKernelGGL((k_propose_hub<1024, AccT>), dim3(c), dim3(1024), 0, s, a, lst(8), c, hub_off,
                            hub_log, gkey, gval);
     }
@@ -587,8 +918,12 @@ int total_edge_weight(const DevGraph &g, int64_t *out, Scratch &sc) {
 int label_weights(const DevGraph &g, const int32_t *labels, int64_t *W, int32_t nlabels, Scratch &sc) {
     GP_HIP(hipMemsetAsync(W, 0, sizeof(int64_t) * (size_t)(nlabels > 0 ? nlabels : 1), sc.stream()));
     if (g.n > 0) {
-        hipLaunchKernelGGL(k_label_weights, dim3(grid_for(g.n, 256, 65536)), dim3(256), 0, sc.stream(), labels,
-                           g.vwgt, g.n, W);
+        if (nlabels <= kSmallLabels)
+            hipLaunchKernelGGL(k_label_weights_small, dim3(grid_for(g.n, 256, 1024)), dim3(256), 0, sc.stream(),
+                               labels, g.vwgt, g.n, nlabels, W);
+        else
+            hipLaunchKernelGGL(k_label_weights, dim3(grid_for(g.n, 256, 65536)), dim3(256), 0, sc.stream(), labels,
+                               g.vwgt, g.n, W);
         GP_LAUNCH_CHECK();
     }
     return GP_OK;
@@ -623,12 +958,63 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
     for (int t = 0; t < kTiers; t++) tstart[t + 1] = tstart[t] + hcnt[t];
     const int32_t *verts = tval;
 
-    // ---- hub tables
-    const int32_t nh = hcnt[kTiers - 1];
+    // ---- hub tables (hashed tables only; dense tables need none)
+    const bool dense = nlabels <= kDenseLabels;
+    const int32_t nh = dense ? 0 : hcnt[kTiers - 1];
+    const bool split_hubs = nh > 0 && !wide;
     int32_t *hub_log = nullptr, *gkey = nullptr;
     int64_t *hub_off = nullptr;
     void *gval = nullptr;
-    if (nh > 0) {
+    HubPlan hp{};
+    int32_t nchunks = 0, nslices = 0;
+    if (split_hubs) {
+        const int32_t *hubs = verts + tstart[kTiers - 1];
+        int32_t *tlog = nullptr, *nch = nullptr, *nsl = nullptr, *cfirst = nullptr, *sfirst = nullptr,
+                *d_tot = nullptr, *chub = nullptr, *shub = nullptr, *need2 = nullptr;
+        int64_t *tcap = nullptr, *toff = nullptr, *d_ttot = nullptr;
+        unsigned long long *own = nullptr, *b1 = nullptr, *b2 = nullptr;
+        GP_TRY(sc.alloc(&tlog, nh));
+        GP_TRY(sc.alloc(&nch, nh));
+        GP_TRY(sc.alloc(&nsl, nh));
+        GP_TRY(sc.alloc(&cfirst, nh));
+        GP_TRY(sc.alloc(&sfirst, nh));
+        GP_TRY(sc.alloc(&d_tot, 2));
+        GP_TRY(sc.alloc(&tcap, nh));
+        GP_TRY(sc.alloc(&toff, nh));
+        GP_TRY(sc.alloc(&d_ttot, 1));
+        GP_TRY(sc.alloc(&own, nh));
+        GP_TRY(sc.alloc(&b1, nh));
+        GP_TRY(sc.alloc(&b2, nh));
+        GP_TRY(sc.alloc(&need2, nh));
+        hipLaunchKernelGGL(k_hub_plan, dim3(grid_for(nh, 256, 1024)), dim3(256), 0, s, g.xadj, hubs, nh, tlog, tcap,
+                           nch, nsl);
+        GP_LAUNCH_CHECK();
+        GP_TRY((scan<int64_t>(LoadIn<int64_t>{tcap}, StoreExcl<int64_t>{toff}, nh, nullptr, d_ttot, sc)));
+        GP_TRY((scan<int32_t>(LoadIn<int32_t>{nch}, StoreExcl<int32_t>{cfirst}, nh, nullptr, d_tot, sc)));
+        GP_TRY((scan<int32_t>(LoadIn<int32_t>{nsl}, StoreExcl<int32_t>{sfirst}, nh, nullptr, d_tot + 1, sc)));
+        int32_t tots[2];
+        int64_t ttot = 0;
+        GP_HIP(hipMemcpyAsync(tots, d_tot, sizeof(tots), hipMemcpyDeviceToHost, s));
+        GP_HIP(hipMemcpyAsync(&ttot, d_ttot, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        GP_HIP(hipStreamSynchronize(s));
+        nchunks = tots[0];
+        nslices = tots[1];
+        GP_TRY(sc.alloc(&chub, nchunks));
+        GP_TRY(sc.alloc(&shub, nslices));
+        hipLaunchKernelGGL(k_hub_expand, dim3(grid_for(nh, 256, 1024)), dim3(256), 0, s, cfirst, nch, nh, chub);
+        hipLaunchKernelGGL(k_hub_expand, dim3(grid_for(nh, 256, 1024)), dim3(256), 0, s, sfirst, nsl, nh, shub);
+        GP_LAUNCH_CHECK();
+        int32_t *tk = nullptr, *tv = nullptr;
+        GP_TRY(sc.alloc(&tk, ttot));
+        GP_TRY(sc.alloc(&tv, ttot));
+        GP_HIP(hipMemsetAsync(tk, 0xFF, sizeof(int32_t) * (size_t)ttot, s));
+        GP_HIP(hipMemsetAsync(tv, 0, sizeof(int32_t) * (size_t)ttot, s));
+        GP_HIP(hipMemsetAsync(own, 0, sizeof(unsigned long long) * nh, s));
+        GP_HIP(hipMemsetAsync(b1, 0, sizeof(unsigned long long) * nh, s));
+        GP_HIP(hipMemsetAsync(b2, 0, sizeof(unsigned long long) * nh, s));
+        GP_HIP(hipMemsetAsync(need2, 0, sizeof(int32_t) * nh, s));
+        hp = HubPlan{hubs, toff, tlog, chub, cfirst, shub, sfirst, tk, tv, own, b1, b2, need2};
+    } else if (nh > 0) {
         int64_t *hcap = nullptr, *htot = nullptr;
         GP_TRY(sc.alloc(&hub_log, nh));
         GP_TRY(sc.alloc(&hcap, nh));
@@ -643,17 +1029,10 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
         GP_HIP(hipStreamSynchronize(s));
         GP_TRY(sc.alloc(&gkey, total));
         GP_HIP(hipMemsetAsync(gkey, 0xFF, sizeof(int32_t) * (size_t)total, s));
-        if (wide) {
-            int64_t *p = nullptr;
-            GP_TRY(sc.alloc(&p, total));
-            GP_HIP(hipMemsetAsync(p, 0, sizeof(int64_t) * (size_t)total, s));
-            gval = p;
-        } else {
-            int32_t *p = nullptr;
-            GP_TRY(sc.alloc(&p, total));
-            GP_HIP(hipMemsetAsync(p, 0, sizeof(int32_t) * (size_t)total, s));
-            gval = p;
-        }
+        int64_t *p = nullptr;
+        GP_TRY(sc.alloc(&p, total));
+        GP_HIP(hipMemsetAsync(p, 0, sizeof(int64_t) * (size_t)total, s));
+        gval = p;
     }
 
     // ---- per-round buffers
@@ -688,10 +1067,23 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
         a.dirmode = dir_alternate ? ((r % 2 == 0) ? 1 : 2) : 0;
         a.prop = prop;
         a.done = &dev->done;
-        if (wide)
+        if (dense && wide)
+            GP_TRY(launch_dense_any<int64_t>(a, nlabels, verts, tstart, s));
+        else if (dense)
+            GP_TRY(launch_dense_any<int32_t>(a, nlabels, verts, tstart, s));
+        else if (wide)
             GP_TRY(launch_proposals<int64_t>(a, verts, tstart, hub_log, hub_off, gkey, (int64_t *)gval, s));
         else
-            GP_TRY(launch_proposals<int32_t>(a, verts, tstart, hub_log, hub_off, gkey, (int32_t *)gval, s));
+            GP_TRY(launch_proposals<int32_t>(a, verts, tstart, hub_log, hub_off, gkey, (int32_t *)gval, s,
+                                             split_hubs));
+        if (split_hubs) {
+            hipLaunchKernelGGL(k_hub_insert, dim3(nchunks), dim3(256), 0, s, a, hp);
+            hipLaunchKernelGGL(k_hub_scan<false>, dim3(nslices), dim3(256), 0, s, a, hp);
+            hipLaunchKernelGGL(k_hub_decide<false>, dim3(grid_for(nh, 256, 1024)), dim3(256), 0, s, a, hp, nh);
+            hipLaunchKernelGGL(k_hub_scan<true>, dim3(nslices), dim3(256), 0, s, a, hp);
+            hipLaunchKernelGGL(k_hub_decide<true>, dim3(grid_for(nh, 256, 1024)), dim3(256), 0, s, a, hp, nh);
+            GP_LAUNCH_CHECK();
+        }
         // compaction of movers (ascending vertex id)
         GP_TRY(compact(MoverFlag{prop, &dev->done}, MoverEmit{prop, mk, mv}, n, nullptr, nmov, sc));
         uint32_t *k1 = mk, *k2 = mk2;
@@ -704,7 +1096,11 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
         hipLaunchKernelGGL(k_admit, dim3(gb), dim3(256), 0, s, k1, v1, nmov, headpos, S, W, U, labels, oldlab,
                            dev);
         GP_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_apply_w, dim3(gb), dim3(256), 0, s, k1, v1, nmov, oldlab, g.vwgt, W);
+        if (nlabels <= kSmallLabels)
+            hipLaunchKernelGGL(k_apply_w_small, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, k1, v1, nmov, oldlab,
+                               g.vwgt, nlabels, W);
+        else
+            hipLaunchKernelGGL(k_apply_w, dim3(gb), dim3(256), 0, s, k1, v1, nmov, oldlab, g.vwgt, W);
         GP_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_round_end, dim3(1), dim3(1), 0, s, dev, r);
         GP_LAUNCH_CHECK();

@@ -7,6 +7,8 @@
 // synchronise with the host.
 #include <climits>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <string>
 
 #include "contract.hpp"
@@ -171,6 +173,15 @@ struct Timer {
     }
 };
 
+// GP_TRACE=1 prints per-level device times to stderr (adds synchronisations).
+static bool tracing() {
+    static const bool on = [] {
+        const char *e = std::getenv("GP_TRACE");
+        return e && *e && *e != '0';
+    }();
+    return on;
+}
+
 static int do_partition(const gp_graph *gin, int32_t k, double eps, const gp_params *p, int32_t *part_out,
                         gp_result *res, hipStream_t s) {
     Scratch sc(s);
@@ -209,7 +220,9 @@ static int do_partition(const gp_graph *gin, int32_t k, double eps, const gp_par
                            f.vwgt, labels, W);
         GP_LAUNCH_CHECK();
         LPOut st;
+        Timer t_lp(s);
         GP_TRY(lp_run(f, labels, W, f.n, ucl, p->rounds_coarsen, p->dir_alternate, wide, &st, sc));
+        const float ms_lp = t_lp.stop();
         ev_c += (int64_t)st.rounds_run * f.nnz;
         CoarseOut co;
         GP_TRY(sc.alloc(&co.xadj, (size_t)f.n + 1));
@@ -217,7 +230,13 @@ static int do_partition(const gp_graph *gin, int32_t k, double eps, const gp_par
         GP_TRY(sc.alloc(&co.adjwgt, f.nnz));
         GP_TRY(sc.alloc(&co.vwgt, f.n));
         GP_TRY(sc.alloc(&co.f2c, f.n));
+        Timer t_ct(s);
         GP_TRY(contract(f, labels, skip, skip ? rowof0 : nullptr, co, sc));
+        if (tracing())
+            std::fprintf(stderr, "[gp] level %zu n=%d nnz=%d cluster %.3f ms (%d rounds, %.1f Gvisits/s) "
+                                 "contract %.3f ms -> n=%d nnz=%d\n",
+                         L, f.n, f.nnz, ms_lp, st.rounds_run,
+                         (double)st.rounds_run * f.nnz / (ms_lp * 1e6), t_ct.stop(), co.n, co.nnz);
         if (co.n == cur_n) break;  // no shrink: drop the level
         lev[L].f2c = co.f2c;
         DevGraph c;
@@ -242,6 +261,7 @@ static int do_partition(const gp_graph *gin, int32_t k, double eps, const gp_par
     GP_TRY(initial_partition(lev[Lc].g, Lc == 0, k, lmax, p->seed, p->attempts, p->rounds_refine, p->dir_alternate,
                              wide, P, nullptr, sc));
     const float ms_init = t_init.stop();
+    if (tracing()) std::fprintf(stderr, "[gp] initial partition n=%d nnz=%d %.3f ms\n", lev[Lc].g.n, lev[Lc].g.nnz, ms_init);
 
     // ---- uncoarsening
     Timer t_ref(s);
@@ -260,7 +280,14 @@ static int do_partition(const gp_graph *gin, int32_t k, double eps, const gp_par
         }
         GP_TRY(label_weights(gl, Pl, B, k, sc));
         LPOut st;
+        Timer t_lp(s);
         GP_TRY(lp_run(gl, Pl, B, k, lmax, p->rounds_refine, p->dir_alternate, wide, &st, sc));
+        if (tracing()) {
+            const float ms = t_lp.stop();
+            std::fprintf(stderr, "[gp] refine level %zu n=%d nnz=%d %.3f ms (%d rounds, %lld moves, %.1f Gvisits/s)\n",
+                         l, gl.n, gl.nnz, ms, st.rounds_run, (long long)st.moves,
+                         (double)st.rounds_run * gl.nnz / (ms * 1e6));
+        }
         ev_r += (int64_t)st.rounds_run * gl.nnz;
         P = Pl;
     }

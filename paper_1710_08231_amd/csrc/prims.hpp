@@ -90,7 +90,7 @@ struct StoreExcl {
 // out(i, exclusive_prefix, value) is called once per item; *total_dev (may be
 // NULL) receives the sum.
 template <typename T, typename In, typename Out>
-int scan(In in, Out out, int64_t nmax, const int32_t *n_dev, T *total_dev, Scratch &sc) {
+int scan(In in, Out out, int64_t nmax, const int32_t *n_dev, T *total_dev, Scratch &sc, int depth = 0) {
     hipStream_t s = sc.stream();
     const int64_t ntiles = (nmax + kScanTile - 1) / kScanTile;
     if (ntiles <= 1) {
@@ -100,12 +100,12 @@ int scan(In in, Out out, int64_t nmax, const int32_t *n_dev, T *total_dev, Scrat
         return GP_OK;
     }
     T *partial = nullptr, *off = nullptr;
-    GP_TRY(sc.alloc(&partial, ntiles));
-    GP_TRY(sc.alloc(&off, ntiles));
+    GP_TRY(sc.temp(&partial, ntiles, 2 * depth));
+    GP_TRY(sc.temp(&off, ntiles, 2 * depth + 1));
     hipLaunchKernelGGL((k_tile_reduce<T, In>), dim3(ntiles), dim3(kScanBlock), 0, s, in, nmax, n_dev,
                        partial);
     GP_LAUNCH_CHECK();
-    GP_TRY((scan<T>(LoadIn<T>{partial}, StoreExcl<T>{off}, ntiles, nullptr, (T *)nullptr, sc)));
+    GP_TRY((scan<T>(LoadIn<T>{partial}, StoreExcl<T>{off}, ntiles, nullptr, (T *)nullptr, sc, depth + 1)));
     hipLaunchKernelGGL((k_tile_scan<T, In, Out>), dim3(ntiles), dim3(kScanBlock), 0, s, in, out, nmax,
                        n_dev, (const T *)off, total_dev);
     GP_LAUNCH_CHECK();
@@ -136,6 +136,7 @@ int compact(Flag flag, Emit emit, int64_t nmax, const int32_t *n_dev, int32_t *c
 
 // ---------------------------------------------------------------- radix sort
 
+constexpr int kSortHistSlot = 16;  // scratch slots 0..15 belong to scan depths
 constexpr int kSortBlock = 256;
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortBlock * kSortItems;
@@ -221,7 +222,7 @@ int radix_sort(K **keys, V **vals, K **ktmp, V **vtmp, int64_t nmax, const int32
     if (nmax <= 0 || bits <= 0) return GP_OK;
     const int ntiles = (int)((nmax + kSortTile - 1) / kSortTile);
     uint32_t *hist = nullptr;
-    GP_TRY(sc.alloc(&hist, (size_t)256 * ntiles));
+    GP_TRY(sc.temp(&hist, (size_t)256 * ntiles, kSortHistSlot));
     for (int shift = 0; shift < bits; shift += 8) {
         const int nb = (bits - shift) < 8 ? (bits - shift) : 8;
         hipLaunchKernelGGL((k_radix_hist<K>), dim3(ntiles), dim3(kSortBlock), 0, s, *keys, nmax, n_dev,
