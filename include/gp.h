@@ -165,6 +165,23 @@ int gp_partition(const gp_graph *g, int32_t k, double eps, const gp_params *p, i
 const char *gp_strerror(int code);
 const char *gp_last_error(void);
 
+/*
+ * Instrumentation for measurement (not part of the method). When enabled,
+ * the proposal kernels of every LP round are bracketed by HIP events on the
+ * caller's stream; per kernel name the library accumulates the number of
+ * launches, their summed device time (ms) and their summed algorithmic bytes
+ * (CSR, weight and label bytes the kernel must move; see the kernel sources).
+ * gp_profile_enable(1) clears the counters and starts recording;
+ * gp_profile_enable(0) stops. gp_profile_get copies entry i (0 <=
+ * i < gp_profile_count()) into caller memory; name is NUL-terminated and
+ * truncated to name_len bytes. Host-only, not thread safe.
+ */
+void gp_profile_enable(int on);
+/* Restrict recording to launches of kernel `name` (NULL: record all). */
+void gp_profile_select(const char *name);
+int gp_profile_count(void);
+int gp_profile_get(int i, char *name, int name_len, int64_t *launches, double *ms, double *bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -69,7 +69,8 @@ class Result(ctypes.Structure):
 
 
 EXPORTS = ["gp_default_params", "gp_lmax", "gp_lp_cluster", "gp_lp_refine", "gp_contract",
-           "gp_project", "gp_cut_and_blocks", "gp_partition", "gp_strerror", "gp_last_error"]
+           "gp_project", "gp_cut_and_blocks", "gp_partition", "gp_strerror", "gp_last_error",
+           "gp_profile_enable", "gp_profile_select", "gp_profile_count", "gp_profile_get"]
 
 
 def load():
@@ -96,6 +97,11 @@ def load():
     lib.gp_strerror.argtypes = [ctypes.c_int]
     lib.gp_last_error.restype = ctypes.c_char_p
     lib.gp_last_error.argtypes = []
+    lib.gp_profile_enable.argtypes = [ctypes.c_int]
+    lib.gp_profile_select.argtypes = [ctypes.c_char_p]
+    lib.gp_profile_count.restype = ctypes.c_int
+    lib.gp_profile_get.argtypes = [ctypes.c_int, ctypes.c_char_p, ctypes.c_int, ctypes.POINTER(i64),
+                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     _lib = lib
     return lib
 
@@ -221,3 +227,25 @@ def partition(g, k, eps=0.03, **params):
     res = {f: getattr(r, f) for f, _ in Result._fields_}
     res["code"] = code
     return part[:gs.n], res
+
+
+def profile_enable(on=True):
+    """Start (clearing) or stop the library's per-kernel HIP-event timing."""
+    load().gp_profile_enable(1 if on else 0)
+
+
+def profile_select(name=None):
+    """Record only launches of kernel `name` (None: all)."""
+    load().gp_profile_select(None if name is None else name.encode())
+
+
+def profile_entries():
+    """[{name, launches, ms, bytes}] accumulated since profile_enable(True)."""
+    lib = load()
+    out = []
+    buf = ctypes.create_string_buffer(256)
+    for i in range(lib.gp_profile_count()):
+        n, ms, b = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+        _check(lib.gp_profile_get(i, buf, 256, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(b)))
+        out.append({"name": buf.value.decode(), "launches": n.value, "ms": ms.value, "bytes": b.value})
+    return out

@@ -110,6 +110,29 @@ class Scratch {
     std::vector<std::pair<void *, size_t>> tmp_;
 };
 
+// ---------------------------------------------------------------- instrumentation
+// When enabled (gp_profile_enable), selected kernel launches are bracketed by
+// HIP events on their stream; durations and the algorithmic bytes of each
+// launch accumulate per kernel name until read back (gp_profile_get).
+bool prof_on();
+bool prof_wants(const char *name);
+void prof_record(const char *name, hipEvent_t a, hipEvent_t b, double bytes);
+hipEvent_t prof_event();
+void prof_flush();  // resolves recorded events (the stream must be synchronised)
+
+#define GP_PROF_LAUNCH(name, bytes, stream, ...)                     \
+    do {                                                              \
+        if (::gp::prof_wants(name)) {                                 \
+            hipEvent_t _a = ::gp::prof_event(), _b = ::gp::prof_event(); \
+            (void)hipEventRecord(_a, stream);                         \
+            __VA_ARGS__;                                              \
+            (void)hipEventRecord(_b, stream);                         \
+            ::gp::prof_record(name, _a, _b, (double)(bytes));         \
+        } else {                                                      \
+            __VA_ARGS__;                                              \
+        }                                                             \
+    } while (0)
+
 inline unsigned grid_for(int64_t items, int per_block, unsigned cap = 1u << 20) {
     int64_t g = (items + per_block - 1) / per_block;
     if (g < 1) g = 1;

@@ -18,6 +18,7 @@
 // No host synchronisation happens between rounds; after the stop flag is set
 // every later kernel of the call returns immediately.
 #include <climits>
+#include <string>
 
 #include "lp.hpp"
 #include "prims.hpp"
@@ -83,13 +84,9 @@ template <typename AccT>
 __device__ __forceinline__ void tbl_insert_global(int32_t *key, AccT *val, uint32_t cap_mask, int log2cap,
                                                   int32_t L, AccT w) {
     uint32_t h = hash_label(L) >> (32 - log2cap);
-    for (;;) {
-        const int32_t k = ld_agent(&key[h]);
-        if (k == L) break;
-        if (k == -1) {
-            const int32_t prev = atomicCAS(&key[h], -1, L);
-            if (prev == -1 || prev == L) break;
-        }
+    for (;;) {  // one L2 round trip per probe: the CAS result says empty, ours, or taken
+        const int32_t prev = atomicCAS(&key[h], -1, L);
+        if (prev == -1 || prev == L) break;
         h = (h + 1) & cap_mask;
     }
     lds_add<AccT>(&val[h], w);
@@ -175,14 +172,19 @@ __global__ __launch_bounds__(kPropBlock) void k_propose_group(LPArgs a, const in
         AccT oc = 0;
         const int nch = (end - beg + GL - 1) / GL;
         const int maxch = wave_max(nch);
-        for (int ch = 0; ch < maxch; ch++) {
-            const int32_t e = beg + ch * GL + gl;
-            if (e < end) {
-                const int32_t u = a.adjncy[e];
-                const AccT wgt = a.adjwgt ? (AccT)a.adjwgt[e] : (AccT)1;
-                const int32_t L = a.labels[u];
-                if (L == own) oc += wgt;
-                else if (dir_ok(L, own, a.dirmode)) tbl_insert<AccT>(key, val, TBL - 1, LOG2, L, wgt);
+        for (int ch = 0; ch < maxch; ch += 2) {
+            const int32_t e0 = beg + ch * GL + gl, e1 = e0 + GL;
+            const int32_t u0 = e0 < end ? a.adjncy[e0] : -1, u1 = e1 < end ? a.adjncy[e1] : -1;
+            const AccT w0 = (e0 < end && a.adjwgt) ? (AccT)a.adjwgt[e0] : (AccT)1;
+            const AccT w1 = (e1 < end && a.adjwgt) ? (AccT)a.adjwgt[e1] : (AccT)1;
+            const int32_t L0 = u0 >= 0 ? a.labels[u0] : -1, L1 = u1 >= 0 ? a.labels[u1] : -1;
+            if (u0 >= 0) {
+                if (L0 == own) oc += w0;
+                else if (dir_ok(L0, own, a.dirmode)) tbl_insert<AccT>(key, val, TBL - 1, LOG2, L0, w0);
+            }
+            if (u1 >= 0) {
+                if (L1 == own) oc += w1;
+                else if (dir_ok(L1, own, a.dirmode)) tbl_insert<AccT>(key, val, TBL - 1, LOG2, L1, w1);
             }
         }
         wave_sync();
@@ -229,13 +231,14 @@ __global__ __launch_bounds__(kPropBlock) void k_propose_group(LPArgs a, const in
     }
 }
 
-// One workgroup per vertex, table in LDS.
+// One workgroup per vertex, table in LDS sized to the vertex: next power of
+// two >= 2*deg (at most TBL), so scanning and clearing cost O(deg).
 template <int BLOCK, int TBL, typename AccT>
 __global__ __launch_bounds__(BLOCK) void k_propose_block(LPArgs a, const int32_t *__restrict__ verts,
                                                          int32_t count) {
     if (*a.done) return;
-    constexpr int LOG2 = __builtin_ctz(TBL);
     constexpr int NW = BLOCK / kWave;
+    constexpr int U4 = 4;
     __shared__ int32_t key[TBL];
     __shared__ AccT val[TBL];
     __shared__ AccT tc[NW + 1];
@@ -249,19 +252,33 @@ __global__ __launch_bounds__(BLOCK) void k_propose_block(LPArgs a, const int32_t
         const int32_t v = verts[idx];
         const int32_t beg = a.xadj[v], end = a.xadj[v + 1];
         const int32_t own = a.labels[v];
+        int lg = 6;
+        while ((1 << lg) < 2 * (end - beg) && (1 << lg) < TBL) lg++;
+        const uint32_t cap = 1u << lg;
         AccT oc = 0;
-        for (int32_t e = beg + threadIdx.x; e < end; e += BLOCK) {
-            const int32_t u = a.adjncy[e];
-            const AccT wgt = a.adjwgt ? (AccT)a.adjwgt[e] : (AccT)1;
-            const int32_t L = a.labels[u];
-            if (L == own) oc += wgt;
-            else if (dir_ok(L, own, a.dirmode)) tbl_insert<AccT>(key, val, TBL - 1, LOG2, L, wgt);
+        for (int32_t e0 = beg + threadIdx.x; e0 < end; e0 += U4 * BLOCK) {
+            int32_t u[U4], L[U4];
+            AccT wv[U4];
+#pragma unroll
+            for (int j = 0; j < U4; j++) {
+                const int32_t e = e0 + j * BLOCK;
+                u[j] = e < end ? a.adjncy[e] : -1;
+                wv[j] = (e < end && a.adjwgt) ? (AccT)a.adjwgt[e] : (AccT)1;
+            }
+#pragma unroll
+            for (int j = 0; j < U4; j++) L[j] = u[j] >= 0 ? a.labels[u[j]] : -1;
+#pragma unroll
+            for (int j = 0; j < U4; j++) {
+                if (u[j] < 0) continue;
+                if (L[j] == own) oc += wv[j];
+                else if (dir_ok(L[j], own, a.dirmode)) tbl_insert<AccT>(key, val, cap - 1, lg, L[j], wv[j]);
+            }
         }
         __syncthreads();
         oc = block_sum<BLOCK>(oc, tc);
         AccT bc = 0;
         int32_t bl = INT_MAX;
-        for (int i = threadIdx.x; i < TBL; i += BLOCK) {
+        for (uint32_t i = threadIdx.x; i < cap; i += BLOCK) {
             const int32_t L = key[i];
             if (L >= 0 && better(val[i], L, bc, bl)) {
                 bc = val[i];
@@ -277,7 +294,7 @@ __global__ __launch_bounds__(BLOCK) void k_propose_block(LPArgs a, const int32_t
             } else {
                 AccT bc2 = 0;
                 int32_t bl2 = INT_MAX;
-                for (int i = threadIdx.x; i < TBL; i += BLOCK) {
+                for (uint32_t i = threadIdx.x; i < cap; i += BLOCK) {
                     const int32_t L = key[i];
                     if (L >= 0 && better(val[i], L, bc2, bl2) && a.W[L] + cv <= a.U) {
                         bc2 = val[i];
@@ -289,7 +306,7 @@ __global__ __launch_bounds__(BLOCK) void k_propose_block(LPArgs a, const int32_t
             }
         }
         if (threadIdx.x == 0) a.prop[v] = target;
-        for (int i = threadIdx.x; i < TBL; i += BLOCK) {
+        for (uint32_t i = threadIdx.x; i < cap; i += BLOCK) {
             key[i] = -1;
             val[i] = 0;
         }
@@ -542,14 +559,19 @@ __global__ __launch_bounds__(kPropBlock) void k_dense_group(LPArgs a, int32_t nl
         AccT oc = 0;
         const int nch = (end - beg + GL - 1) / GL;
         const int maxch = wave_max(nch);
-        for (int ch = 0; ch < maxch; ch++) {
-            const int32_t e = beg + ch * GL + gl;
-            if (e < end) {
-                const int32_t u = a.adjncy[e];
-                const AccT wgt = a.adjwgt ? (AccT)a.adjwgt[e] : (AccT)1;
-                const int32_t L = a.labels[u];
-                if (L == own) oc += wgt;
-                else if (dir_ok(L, own, a.dirmode)) lds_add<AccT>(&val[L], wgt);
+        for (int ch = 0; ch < maxch; ch += 2) {
+            const int32_t e0 = beg + ch * GL + gl, e1 = e0 + GL;
+            const int32_t u0 = e0 < end ? a.adjncy[e0] : -1, u1 = e1 < end ? a.adjncy[e1] : -1;
+            const AccT w0 = (e0 < end && a.adjwgt) ? (AccT)a.adjwgt[e0] : (AccT)1;
+            const AccT w1 = (e1 < end && a.adjwgt) ? (AccT)a.adjwgt[e1] : (AccT)1;
+            const int32_t L0 = u0 >= 0 ? a.labels[u0] : -1, L1 = u1 >= 0 ? a.labels[u1] : -1;
+            if (u0 >= 0) {
+                if (L0 == own) oc += w0;
+                else if (dir_ok(L0, own, a.dirmode)) lds_add<AccT>(&val[L0], w0);
+            }
+            if (u1 >= 0) {
+                if (L1 == own) oc += w1;
+                else if (dir_ok(L1, own, a.dirmode)) lds_add<AccT>(&val[L1], w1);
             }
         }
         wave_sync();
@@ -572,53 +594,107 @@ __global__ __launch_bounds__(kPropBlock) void k_dense_group(LPArgs a, int32_t nl
     }
 }
 
-template <int BLOCK, int KT, typename AccT>
-__global__ __launch_bounds__(BLOCK) void k_dense_block(LPArgs a, int32_t nlabels, const int32_t *__restrict__ verts,
-                                                       int32_t count) {
+// Vertices above the group tiers in dense mode: edges cut into chunks of
+// kDenseChunk entries, one workgroup per chunk; each chunk adds its k
+// connection sums into the vertex's row of a global [nbig x KT] array, then
+// one wave per vertex selects. No single workgroup walks a whole hub.
+constexpr int kDenseChunk = 2048;
+
+struct DenseBig {
+    const int32_t *verts;        // [nbig]
+    const int32_t *chunk_owner;  // [nchunks] index into verts
+    const int32_t *chunk_first;  // [nbig]
+    void *gconn;                 // [nbig * KT] AccT
+    unsigned long long *own;     // [nbig]
+    int32_t nbig;
+};
+
+template <typename AccT>
+__device__ __forceinline__ void gadd(AccT *p, AccT w);
+template <>
+__device__ __forceinline__ void gadd<int32_t>(int32_t *p, int32_t w) {
+    atomicAdd(p, w);
+}
+template <>
+__device__ __forceinline__ void gadd<int64_t>(int64_t *p, int64_t w) {
+    atomicAdd((unsigned long long *)p, (unsigned long long)w);
+}
+
+template <int KT, typename AccT>
+__global__ __launch_bounds__(256) void k_dense_chunk(LPArgs a, DenseBig db) {
     if (*a.done) return;
-    constexpr int NW = BLOCK / kWave;
-    __shared__ AccT val[NW][KT];  // one table per wave limits same-address contention
-    __shared__ int64_t sW[KT];
-    __shared__ AccT tc[NW + 1];
-    __shared__ int32_t tl[NW + 1];
+    constexpr int NW = 256 / kWave;
+    __shared__ AccT val[NW][KT];
+    __shared__ AccT tmp[NW + 1];
     const int w = threadIdx.x / kWave;
-    for (int i = threadIdx.x; i < KT; i += BLOCK) sW[i] = i < nlabels ? a.W[i] : (int64_t(1) << 62);
-    for (int i = threadIdx.x; i < NW * KT; i += BLOCK) (&val[0][0])[i] = 0;
+    for (int i = threadIdx.x; i < NW * KT; i += 256) (&val[0][0])[i] = 0;
     __syncthreads();
-    for (int64_t idx = xcd_block(blockIdx.x, gridDim.x); idx < count; idx += gridDim.x) {
-        const int32_t v = verts[idx];
-        const int32_t beg = a.xadj[v], end = a.xadj[v + 1];
-        const int32_t own = a.labels[v];
-        AccT oc = 0;
-        for (int32_t e = beg + threadIdx.x; e < end; e += BLOCK) {
-            const int32_t u = a.adjncy[e];
-            const AccT wgt = a.adjwgt ? (AccT)a.adjwgt[e] : (AccT)1;
-            const int32_t L = a.labels[u];
-            if (L == own) oc += wgt;
-            else if (dir_ok(L, own, a.dirmode)) lds_add<AccT>(&val[w][L], wgt);
+    const int32_t b = db.chunk_owner[blockIdx.x];
+    const int32_t v = db.verts[b];
+    const int32_t own = a.labels[v];
+    const int32_t beg = a.xadj[v] + (blockIdx.x - db.chunk_first[b]) * kDenseChunk;
+    const int32_t end = min(a.xadj[v + 1], beg + kDenseChunk);
+    AccT oc = 0;
+    for (int32_t e0 = beg + threadIdx.x; e0 < end; e0 += 4 * 256) {
+        int32_t u[4], L[4];
+        AccT wv[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int32_t e = e0 + j * 256;
+            u[j] = e < end ? a.adjncy[e] : -1;
+            wv[j] = (e < end && a.adjwgt) ? (AccT)a.adjwgt[e] : (AccT)1;
         }
-        __syncthreads();
-        oc = block_sum<BLOCK>(oc, tc);
-        const int64_t cv = vweight(a.vwgt, v);
-        AccT bc = 0;
-        int32_t bl = INT_MAX;
-        for (int i = threadIdx.x; i < KT; i += BLOCK) {
-            AccT c = 0;
-            for (int q = 0; q < NW; q++) c += val[q][i];
-            if (c > 0 && sW[i] + cv <= a.U && better(c, i, bc, bl)) {
-                bc = c;
-                bl = i;
-            }
+#pragma unroll
+        for (int j = 0; j < 4; j++) L[j] = u[j] >= 0 ? a.labels[u[j]] : -1;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            if (u[j] < 0) continue;
+            if (L[j] == own) oc += wv[j];
+            else if (dir_ok(L[j], own, a.dirmode)) lds_add<AccT>(&val[w][L[j]], wv[j]);
         }
-        block_best<BLOCK, AccT>(bc, bl, tc, tl);
-        if (threadIdx.x == 0) a.prop[v] = (bl != INT_MAX && bc > oc) ? bl : -1;
-        for (int i = threadIdx.x; i < NW * KT; i += BLOCK) (&val[0][0])[i] = 0;
-        __syncthreads();
+    }
+    __syncthreads();
+    AccT *row = (AccT *)db.gconn + (int64_t)b * KT;
+    for (int i = threadIdx.x; i < KT; i += 256) {
+        AccT c = 0;
+        for (int q = 0; q < NW; q++) c += val[q][i];
+        if (c) gadd<AccT>(&row[i], c);
+    }
+    oc = block_sum<256>(oc, tmp);
+    if (threadIdx.x == 0 && oc) atomicAdd(&db.own[b], (unsigned long long)oc);
+}
+
+template <int KT, typename AccT>
+__global__ __launch_bounds__(256) void k_dense_finish(LPArgs a, DenseBig db, int32_t nlabels) {
+    if (*a.done) return;
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    const int32_t b = blockIdx.x * (256 / kWave) + w;
+    if (b >= db.nbig) return;
+    const int32_t v = db.verts[b];
+    AccT *row = (AccT *)db.gconn + (int64_t)b * KT;
+    const int64_t cv = vweight(a.vwgt, v);
+    const int64_t oc = (int64_t)db.own[b];
+    AccT bc = 0;
+    int32_t bl = INT_MAX;
+    for (int i = lane; i < nlabels; i += kWave) {
+        const AccT c = row[i];
+        if (c > 0 && a.W[i] + cv <= a.U && better(c, i, bc, bl)) {
+            bc = c;
+            bl = i;
+        }
+        row[i] = 0;
+    }
+    group_best<kWave, AccT>(bc, bl);
+    if (lane == 0) {
+        a.prop[v] = (bl != INT_MAX && (int64_t)bc > oc) ? bl : -1;
+        db.own[b] = 0;
     }
 }
 
 template <int KT, typename AccT>
-int launch_dense(const LPArgs &a, int32_t nlabels, const int32_t *verts, const int64_t *tstart, hipStream_t s) {
+int launch_dense(const LPArgs &a, int32_t nlabels, const int32_t *verts, const int64_t *tstart, const DenseBig *db,
+                 int32_t nchunks, hipStream_t s, const double *tb) {
+    const std::string sfx = std::string(", ") + std::to_string(KT) + ", " + (sizeof(AccT) == 4 ? "int" : "long") + ">";
     auto cnt = [&](int t) { return (int32_t)(tstart[t + 1] - tstart[t]); };
     auto lst = [&](int t) { return verts + tstart[t]; };
     constexpr int NW = kPropBlock / kWave;
@@ -627,35 +703,41 @@ int launch_dense(const LPArgs &a, int32_t nlabels, const int32_t *verts, const i
     auto blocks_for = [&](int32_t c, int per_block) { return grid_for(c, per_block, 16384); };
     int32_t c;
     if ((c = cnt(1)) > 0)
-        hipLaunchKernelGGL((k_dense_group<G1, KT, AccT>), dim3(blocks_for(c, NW * (kWave / G1))), dim3(kPropBlock), 0,
-                           s, a, nlabels, lst(1), c);
+        GP_PROF_LAUNCH((std::string("k_dense_group<") + std::to_string(G1) + sfx).c_str(), tb[1], s, hipLaunchKernelGGL((k_dense_group<G1, KT, AccT>), dim3(blocks_for(c, NW * (kWave / G1))), dim3(kPropBlock), 0,
+                           s, a, nlabels, lst(1), c));
     if ((c = cnt(2)) > 0)
-        hipLaunchKernelGGL((k_dense_group<G2, KT, AccT>), dim3(blocks_for(c, NW * (kWave / G2))), dim3(kPropBlock), 0,
-                           s, a, nlabels, lst(2), c);
+        GP_PROF_LAUNCH((std::string("k_dense_group<") + std::to_string(G2) + sfx).c_str(), tb[2], s, hipLaunchKernelGGL((k_dense_group<G2, KT, AccT>), dim3(blocks_for(c, NW * (kWave / G2))), dim3(kPropBlock), 0,
+                           s, a, nlabels, lst(2), c));
     if ((c = cnt(3)) > 0)
-        hipLaunchKernelGGL((k_dense_group<16, KT, AccT>), dim3(blocks_for(c, NW * 4)), dim3(kPropBlock), 0, s, a,
-                           nlabels, lst(3), c);
+        GP_PROF_LAUNCH((std::string("k_dense_group<16") + sfx).c_str(), tb[3], s, hipLaunchKernelGGL((k_dense_group<16, KT, AccT>), dim3(blocks_for(c, NW * 4)), dim3(kPropBlock), 0, s, a,
+                           nlabels, lst(3), c));
     if ((c = cnt(4)) > 0)
-        hipLaunchKernelGGL((k_dense_group<32, KT, AccT>), dim3(blocks_for(c, NW * 2)), dim3(kPropBlock), 0, s, a,
-                           nlabels, lst(4), c);
+        GP_PROF_LAUNCH((std::string("k_dense_group<32") + sfx).c_str(), tb[4], s, hipLaunchKernelGGL((k_dense_group<32, KT, AccT>), dim3(blocks_for(c, NW * 2)), dim3(kPropBlock), 0, s, a,
+                           nlabels, lst(4), c));
     if ((c = cnt(5)) > 0)
-        hipLaunchKernelGGL((k_dense_group<64, KT, AccT>), dim3(blocks_for(c, NW)), dim3(kPropBlock), 0, s, a, nlabels,
-                           lst(5), c);
-    if ((c = cnt(6)) > 0)
-        hipLaunchKernelGGL((k_dense_block<256, KT, AccT>), dim3(grid_for(c, 1, 8192)), dim3(256), 0, s, a, nlabels,
-                           lst(6), c);
-    if ((c = cnt(7) + cnt(8)) > 0)
-        hipLaunchKernelGGL((k_dense_block<1024, KT, AccT>), dim3(grid_for(c, 1, 4096)), dim3(1024), 0, s, a, nlabels,
-                           lst(7), c);
+        GP_PROF_LAUNCH((std::string("k_dense_group<64") + sfx).c_str(), tb[5], s, hipLaunchKernelGGL((k_dense_group<64, KT, AccT>), dim3(blocks_for(c, NW)), dim3(kPropBlock), 0, s, a, nlabels,
+                           lst(5), c));
+    if (db && db->nbig > 0) {
+        GP_PROF_LAUNCH((std::string("k_dense_chunk<") + std::to_string(KT) + sfx.substr(std::to_string(KT).size() + 2)).c_str(), tb[6] + tb[7] + tb[8], s, hipLaunchKernelGGL((k_dense_chunk<KT, AccT>), dim3(nchunks), dim3(256), 0, s, a, *db));
+        hipLaunchKernelGGL((k_dense_finish<KT, AccT>), dim3((db->nbig + 3) / 4), dim3(256), 0, s, a, *db, nlabels);
+    }
     GP_LAUNCH_CHECK();
     return GP_OK;
 }
 
 template <typename AccT>
-int launch_dense_any(const LPArgs &a, int32_t nlabels, const int32_t *verts, const int64_t *tstart, hipStream_t s) {
-    if (nlabels <= 16) return launch_dense<16, AccT>(a, nlabels, verts, tstart, s);
-    if (nlabels <= 64) return launch_dense<64, AccT>(a, nlabels, verts, tstart, s);
-    return launch_dense<256, AccT>(a, nlabels, verts, tstart, s);
+int launch_dense_any(const LPArgs &a, int32_t nlabels, const int32_t *verts, const int64_t *tstart,
+                     const DenseBig *db, int32_t nchunks, hipStream_t s, const double *tb) {
+    if (nlabels <= 16) return launch_dense<16, AccT>(a, nlabels, verts, tstart, db, nchunks, s, tb);
+    if (nlabels <= 64) return launch_dense<64, AccT>(a, nlabels, verts, tstart, db, nchunks, s, tb);
+    return launch_dense<256, AccT>(a, nlabels, verts, tstart, db, nchunks, s, tb);
+}
+
+__global__ void k_chunk_counts(const int32_t *xadj, const int32_t *verts, int32_t nb, int32_t chunk, int32_t *num) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = verts[i];
+        num[i] = (xadj[v + 1] - xadj[v] + chunk - 1) / chunk;
+    }
 }
 
 // ---------------------------------------------------------------- tiers
@@ -687,9 +769,14 @@ struct TierKey {
     bool wide;
 };
 
-__global__ void k_tier_keys(TierKey tk, int32_t n, uint32_t *key, int32_t *val, int32_t *counts) {
+__global__ void k_tier_keys(TierKey tk, int32_t n, uint32_t *key, int32_t *val, int32_t *counts,
+                            unsigned long long *edges) {
     __shared__ int32_t h[kTiers];
-    if (threadIdx.x < kTiers) h[threadIdx.x] = 0;
+    __shared__ unsigned long long he[kTiers];
+    if (threadIdx.x < kTiers) {
+        h[threadIdx.x] = 0;
+        he[threadIdx.x] = 0;
+    }
     __syncthreads();
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
          v += (int64_t)gridDim.x * blockDim.x) {
@@ -702,9 +789,13 @@ __global__ void k_tier_keys(TierKey tk, int32_t n, uint32_t *key, int32_t *val, 
         key[v] = (uint32_t)t;
         val[v] = (int32_t)v;
         atomicAdd(&h[t], 1);
+        atomicAdd(&he[t], (unsigned long long)d);
     }
     __syncthreads();
-    if (threadIdx.x < kTiers && h[threadIdx.x]) atomicAdd(&counts[threadIdx.x], h[threadIdx.x]);
+    if (threadIdx.x < kTiers && h[threadIdx.x]) {
+        atomicAdd(&counts[threadIdx.x], h[threadIdx.x]);
+        atomicAdd(&edges[threadIdx.x], he[threadIdx.x]);
+    }
 }
 
 __global__ void k_hub_caps(const int32_t *xadj, const int32_t *hubs, int32_t nh, int32_t *hlog,
@@ -777,16 +868,25 @@ __global__ void k_admit(const uint32_t *mk, const int32_t *mv, const int32_t *nm
     if (lane_id() == 0 && cnt) atomicAdd(&dev->round_moves, cnt);
 }
 
+// Departures one atomic per mover (distinct labels in general); arrivals one
+// atomic per target: the last admitted mover of a target's segment adds the
+// segment's admitted weight (admitted movers form a prefix of the segment).
 __global__ void k_apply_w(const uint32_t *mk, const int32_t *mv, const int32_t *nmov, const int32_t *oldlab,
-                          const int32_t *vwgt, int64_t *W) {
+                          const int32_t *vwgt, const int32_t *headpos, const int64_t *S, int64_t *W) {
     const int32_t n = *nmov;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
          p += (int64_t)gridDim.x * blockDim.x) {
         const int32_t old = oldlab[p];
         if (old < 0) continue;
         const unsigned long long c = (unsigned long long)vweight(vwgt, mv[p]);
-        atomicAdd((unsigned long long *)&W[mk[p]], c);
         atomicAdd((unsigned long long *)&W[old], (unsigned long long)(-(long long)c));
+        const uint32_t t = mk[p];
+        const bool tail = (p + 1 == n) || mk[p + 1] != t || oldlab[p + 1] < 0;
+        if (tail) {
+            const int32_t h = headpos[t];
+            const int64_t in = S[p] - (h > 0 ? S[h - 1] : 0);
+            atomicAdd((unsigned long long *)&W[t], (unsigned long long)in);
+        }
     }
 }
 
@@ -856,7 +956,9 @@ struct NoOut64 {
 
 template <typename AccT>
 int launch_proposals(const LPArgs &a, const int32_t *verts, const int64_t *tstart, const int32_t *hub_log,
-                     const int64_t *hub_off, int32_t *gkey, AccT *gval, hipStream_t s, bool skip_hubs = false) {
+                     const int64_t *hub_off, int32_t *gkey, AccT *gval, hipStream_t s, const double *tb,
+                     bool skip_hubs = false) {
+    const char *acc = sizeof(AccT) == 4 ? "int" : "long";
     auto cnt = [&](int t) { return (int32_t)(tstart[t + 1] - tstart[t]); };
     auto lst = [&](int t) { return verts + tstart[t]; };
     constexpr int NW = kPropBlock / kWave;
@@ -864,37 +966,37 @@ int launch_proposals(const LPArgs &a, const int32_t *verts, const int64_t *tstar
     auto blocks_for = [&](int32_t c, int per_block) { return grid_for(c, per_block, 16384); };
     int32_t c;
     if ((c = cnt(1)) > 0) {
-        hipLaunchKernelGGL((k_propose_group<4, 8, AccT>), dim3(blocks_for(c, NW * 16)), dim3(kPropBlock), 0, s,
-                           a, lst(1), c);
+        GP_PROF_LAUNCH((std::string("k_propose_group<4, 8, ") + acc + ">").c_str(), tb[1], s, hipLaunchKernelGGL((k_propose_group<4, 8, AccT>), dim3(blocks_for(c, NW * 16)), dim3(kPropBlock), 0, s,
+                           a, lst(1), c));
     }
     if ((c = cnt(2)) > 0) {
-        hipLaunchKernelGGL((k_propose_group<8, 16, AccT>), dim3(blocks_for(c, NW * 8)), dim3(kPropBlock), 0, s,
-                           a, lst(2), c);
+        GP_PROF_LAUNCH((std::string("k_propose_group<8, 16, ") + acc + ">").c_str(), tb[2], s, hipLaunchKernelGGL((k_propose_group<8, 16, AccT>), dim3(blocks_for(c, NW * 8)), dim3(kPropBlock), 0, s,
+                           a, lst(2), c));
     }
     if ((c = cnt(3)) > 0) {
-        hipLaunchKernelGGL((k_propose_group<16, 32, AccT>), dim3(blocks_for(c, NW * 4)), dim3(kPropBlock), 0,
-                           s, a, lst(3), c);
+        GP_PROF_LAUNCH((std::string("k_propose_group<16, 32, ") + acc + ">").c_str(), tb[3], s, hipLaunchKernelGGL((k_propose_group<16, 32, AccT>), dim3(blocks_for(c, NW * 4)), dim3(kPropBlock), 0,
+                           s, a, lst(3), c));
     }
     if ((c = cnt(4)) > 0) {
-        hipLaunchKernelGGL((k_propose_group<32, 128, AccT>), dim3(blocks_for(c, NW * 2)), dim3(kPropBlock), 0,
-                           s, a, lst(4), c);
+        GP_PROF_LAUNCH((std::string("k_propose_group<32, 128, ") + acc + ">").c_str(), tb[4], s, hipLaunchKernelGGL((k_propose_group<32, 128, AccT>), dim3(blocks_for(c, NW * 2)), dim3(kPropBlock), 0,
+                           s, a, lst(4), c));
     }
     if ((c = cnt(5)) > 0) {
-        hipLaunchKernelGGL((k_propose_group<64, 512, AccT>), dim3(blocks_for(c, NW)), dim3(kPropBlock), 0, s,
-                           a, lst(5), c);
+        GP_PROF_LAUNCH((std::string("k_propose_group<64, 512, ") + acc + ">").c_str(), tb[5], s, hipLaunchKernelGGL((k_propose_group<64, 512, AccT>), dim3(blocks_for(c, NW)), dim3(kPropBlock), 0, s,
+                           a, lst(5), c));
     }
     if ((c = cnt(6)) > 0) {
-        hipLaunchKernelGGL((k_propose_block<256, 4096, AccT>), dim3(grid_for(c, 1, 8192)), dim3(256), 0, s, a,
-                           lst(6), c);
+        GP_PROF_LAUNCH((std::string("k_propose_block<256, 4096, ") + acc + ">").c_str(), tb[6], s, hipLaunchKernelGGL((k_propose_block<256, 4096, AccT>), dim3(grid_for(c, 1, 8192)), dim3(256), 0, s, a,
+                           lst(6), c));
     }
     if ((c = cnt(7)) > 0) {
         constexpr int T7 = sizeof(AccT) == 4 ? 16384 : 8192;
-        hipLaunchKernelGGL((k_propose_block<1024, T7, AccT>), dim3(grid_for(c, 1, 2048)), dim3(1024), 0, s, a,
-                           lst(7), c);
+        GP_PROF_LAUNCH((std::string("k_propose_block<1024, ") + std::to_string(T7) + ", " + acc + ">").c_str(), tb[7], s, hipLaunchKernelGGL((k_propose_block<1024, T7, AccT>), dim3(grid_for(c, 1, 2048)), dim3(1024), 0, s, a,
+                           lst(7), c));
     }
     if (!skip_hubs && (c = cnt(8)) > 0) {
-        hipLaunchKernelGGL((k_propose_hub<1024, AccT>), dim3(c), dim3(1024), 0, s, a, lst(8), c, hub_off,
-                           hub_log, gkey, gval);
+        GP_PROF_LAUNCH((std::string("k_propose_hub<1024, ") + acc + ">").c_str(), tb[8], s, hipLaunchKernelGGL((k_propose_hub<1024, AccT>), dim3(c), dim3(1024), 0, s, a, lst(8), c, hub_off,
+                           hub_log, gkey, gval));
     }
     GP_LAUNCH_CHECK();
     return GP_OK;
@@ -944,19 +1046,35 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
     GP_TRY(sc.alloc(&tkey2, n));
     GP_TRY(sc.alloc(&tval, n));
     GP_TRY(sc.alloc(&tval2, n));
+    unsigned long long *tedge = nullptr;
     GP_TRY(sc.alloc(&tcnt, kTiers));
+    GP_TRY(sc.alloc(&tedge, kTiers));
     GP_HIP(hipMemsetAsync(tcnt, 0, sizeof(int32_t) * kTiers, s));
+    GP_HIP(hipMemsetAsync(tedge, 0, sizeof(unsigned long long) * kTiers, s));
     TierKey tk{g.xadj, labels, wide};
-    hipLaunchKernelGGL(k_tier_keys, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, tk, n, tkey, tval, tcnt);
+    hipLaunchKernelGGL(k_tier_keys, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, tk, n, tkey, tval, tcnt, tedge);
     GP_LAUNCH_CHECK();
     GP_TRY((radix_sort<uint32_t, int32_t>(&tkey, &tval, &tkey2, &tval2, n, nullptr, 4, sc)));
     int32_t hcnt[kTiers];
+    unsigned long long hedge[kTiers];
     GP_HIP(hipMemcpyAsync(hcnt, tcnt, sizeof(hcnt), hipMemcpyDeviceToHost, s));
+    GP_HIP(hipMemcpyAsync(hedge, tedge, sizeof(hedge), hipMemcpyDeviceToHost, s));
     GP_HIP(hipStreamSynchronize(s));
     int64_t tstart[kTiers + 1];
     tstart[0] = 0;
     for (int t = 0; t < kTiers; t++) tstart[t + 1] = tstart[t] + hcnt[t];
     const int32_t *verts = tval;
+    const bool dense_mode = nlabels <= kDenseLabels;
+    // Algorithmic bytes of one proposal pass over tier t: per edge the
+    // neighbour id, its weight (when present) and its label; per vertex the
+    // tier-list entry, the two row offsets, the own label, the proposal
+    // write, the vertex weight (when present) and, for hashed tables, the
+    // weight of the chosen label.
+    const double per_edge = 4.0 + (g.adjwgt ? 4.0 : 0.0) + 4.0;
+    const double per_vertex = 4.0 + 8.0 + 4.0 + 4.0 + (g.vwgt ? 4.0 : 0.0) + (dense_mode ? 0.0 : 8.0);
+    double tbytes[kTiers + 1];
+    for (int t = 0; t < kTiers; t++) tbytes[t] = (double)hedge[t] * per_edge + (double)hcnt[t] * per_vertex;
+    tbytes[kTiers] = 0;
 
     // ---- hub tables (hashed tables only; dense tables need none)
     const bool dense = nlabels <= kDenseLabels;
@@ -1035,6 +1153,36 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
         gval = p;
     }
 
+    // ---- dense mode: chunk plan for vertices above the group tiers
+    DenseBig db{};
+    int32_t dchunks = 0;
+    const int32_t nbig = dense ? (int32_t)(tstart[kTiers] - tstart[6]) : 0;
+    if (nbig > 0) {
+        const int KT = nlabels <= 16 ? 16 : (nlabels <= 64 ? 64 : 256);
+        const int32_t *big = verts + tstart[6];
+        int32_t *num = nullptr, *first = nullptr, *owner = nullptr, *d_tot = nullptr;
+        unsigned long long *own = nullptr;
+        GP_TRY(sc.alloc(&num, nbig));
+        GP_TRY(sc.alloc(&first, nbig));
+        GP_TRY(sc.alloc(&d_tot, 1));
+        GP_TRY(sc.alloc(&own, nbig));
+        hipLaunchKernelGGL(k_chunk_counts, dim3(grid_for(nbig, 256, 4096)), dim3(256), 0, s, g.xadj, big, nbig,
+                           kDenseChunk, num);
+        GP_LAUNCH_CHECK();
+        GP_TRY((scan<int32_t>(LoadIn<int32_t>{num}, StoreExcl<int32_t>{first}, nbig, nullptr, d_tot, sc)));
+        GP_HIP(hipMemcpyAsync(&dchunks, d_tot, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        GP_HIP(hipStreamSynchronize(s));
+        GP_TRY(sc.alloc(&owner, dchunks));
+        hipLaunchKernelGGL(k_hub_expand, dim3(grid_for(nbig, 256, 4096)), dim3(256), 0, s, first, num, nbig, owner);
+        GP_LAUNCH_CHECK();
+        const size_t cb = (size_t)nbig * KT * (wide ? sizeof(int64_t) : sizeof(int32_t));
+        void *gconn = nullptr;
+        GP_TRY(sc.alloc((char **)&gconn, cb));
+        GP_HIP(hipMemsetAsync(gconn, 0, cb, s));
+        GP_HIP(hipMemsetAsync(own, 0, sizeof(unsigned long long) * nbig, s));
+        db = DenseBig{big, owner, first, gconn, own, nbig};
+    }
+
     // ---- per-round buffers
     int32_t *prop = nullptr, *mv = nullptr, *mv2 = nullptr, *nmov = nullptr, *headpos = nullptr,
             *oldlab = nullptr;
@@ -1068,16 +1216,16 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
         a.prop = prop;
         a.done = &dev->done;
         if (dense && wide)
-            GP_TRY(launch_dense_any<int64_t>(a, nlabels, verts, tstart, s));
+            GP_TRY(launch_dense_any<int64_t>(a, nlabels, verts, tstart, &db, dchunks, s, tbytes));
         else if (dense)
-            GP_TRY(launch_dense_any<int32_t>(a, nlabels, verts, tstart, s));
+            GP_TRY(launch_dense_any<int32_t>(a, nlabels, verts, tstart, &db, dchunks, s, tbytes));
         else if (wide)
-            GP_TRY(launch_proposals<int64_t>(a, verts, tstart, hub_log, hub_off, gkey, (int64_t *)gval, s));
+            GP_TRY(launch_proposals<int64_t>(a, verts, tstart, hub_log, hub_off, gkey, (int64_t *)gval, s, tbytes));
         else
-            GP_TRY(launch_proposals<int32_t>(a, verts, tstart, hub_log, hub_off, gkey, (int32_t *)gval, s,
+            GP_TRY(launch_proposals<int32_t>(a, verts, tstart, hub_log, hub_off, gkey, (int32_t *)gval, s, tbytes,
                                              split_hubs));
         if (split_hubs) {
-            hipLaunchKernelGGL(k_hub_insert, dim3(nchunks), dim3(256), 0, s, a, hp);
+            GP_PROF_LAUNCH("k_hub_insert", tbytes[8], s, hipLaunchKernelGGL(k_hub_insert, dim3(nchunks), dim3(256), 0, s, a, hp));
             hipLaunchKernelGGL(k_hub_scan<false>, dim3(nslices), dim3(256), 0, s, a, hp);
             hipLaunchKernelGGL(k_hub_decide<false>, dim3(grid_for(nh, 256, 1024)), dim3(256), 0, s, a, hp, nh);
             hipLaunchKernelGGL(k_hub_scan<true>, dim3(nslices), dim3(256), 0, s, a, hp);
@@ -1100,15 +1248,17 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
             hipLaunchKernelGGL(k_apply_w_small, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, k1, v1, nmov, oldlab,
                                g.vwgt, nlabels, W);
         else
-            hipLaunchKernelGGL(k_apply_w, dim3(gb), dim3(256), 0, s, k1, v1, nmov, oldlab, g.vwgt, W);
+            hipLaunchKernelGGL(k_apply_w, dim3(gb), dim3(256), 0, s, k1, v1, nmov, oldlab, g.vwgt, headpos, S, W);
         GP_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_round_end, dim3(1), dim3(1), 0, s, dev, r);
         GP_LAUNCH_CHECK();
     }
-    if (out) {
+    if (out || prof_on()) {
         LPDev h;
         GP_HIP(hipMemcpyAsync(&h, dev, sizeof(LPDev), hipMemcpyDeviceToHost, s));
         GP_HIP(hipStreamSynchronize(s));
+        prof_flush();
+        if (!out) return GP_OK;
         out->rounds_run = h.rounds_run;
         out->moves = h.total_moves;
     }

@@ -22,6 +22,63 @@ void set_error(const char *msg) { g_err = msg; }
 const char *last_error() { return g_err.c_str(); }
 
 namespace {
+struct ProfAcc {
+    std::string name;
+    int64_t launches = 0;
+    double ms = 0, bytes = 0;
+};
+struct ProfPending {
+    std::string name;
+    hipEvent_t a, b;
+    double bytes;
+};
+bool g_prof = false;
+std::string g_only;  // when non-empty, only launches of this kernel are recorded
+std::vector<ProfAcc> g_acc;
+std::vector<ProfPending> g_pending;
+std::vector<hipEvent_t> g_events;
+}  // namespace
+
+bool prof_on() { return g_prof; }
+bool prof_wants(const char *name) { return g_prof && (g_only.empty() || g_only == name); }
+
+hipEvent_t prof_event() {
+    if (!g_events.empty()) {
+        hipEvent_t e = g_events.back();
+        g_events.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+void prof_record(const char *name, hipEvent_t a, hipEvent_t b, double bytes) {
+    g_pending.push_back({name, a, b, bytes});
+}
+
+void prof_flush() {
+    for (auto &p : g_pending) {
+        float ms = 0.f;
+        (void)hipEventSynchronize(p.b);
+        (void)hipEventElapsedTime(&ms, p.a, p.b);
+        ProfAcc *acc = nullptr;
+        for (auto &x : g_acc)
+            if (x.name == p.name) acc = &x;
+        if (!acc) {
+            g_acc.push_back(ProfAcc{p.name});
+            acc = &g_acc.back();
+        }
+        acc->launches++;
+        acc->ms += ms;
+        acc->bytes += p.bytes;
+        g_events.push_back(p.a);
+        g_events.push_back(p.b);
+    }
+    g_pending.clear();
+}
+
+namespace {
 
 __global__ void k_identity_labels(const int32_t *xadj, int32_t n, bool skip_isolated, const int32_t *vwgt,
                                   int32_t *labels, int64_t *W) {
@@ -533,5 +590,31 @@ const char *gp_strerror(int code) {
 }
 
 const char *gp_last_error(void) { return gp::last_error(); }
+
+void gp_profile_enable(int on) {
+    gp::prof_flush();
+    gp::g_acc.clear();
+    gp::g_prof = on != 0;
+}
+
+void gp_profile_select(const char *name) { gp::g_only = name ? name : ""; }
+
+int gp_profile_count(void) {
+    gp::prof_flush();
+    return (int)gp::g_acc.size();
+}
+
+int gp_profile_get(int i, char *name, int name_len, int64_t *launches, double *ms, double *bytes) {
+    gp::prof_flush();
+    if (i < 0 || i >= (int)gp::g_acc.size()) return GP_ERR_ARG;
+    const auto &a = gp::g_acc[i];
+    if (name && name_len > 0) {
+        std::snprintf(name, (size_t)name_len, "%s", a.name.c_str());
+    }
+    if (launches) *launches = a.launches;
+    if (ms) *ms = a.ms;
+    if (bytes) *bytes = a.bytes;
+    return GP_OK;
+}
 
 }  // extern "C"
