@@ -1,14 +1,19 @@
 // contract.hip — contraction (§III-A quotient graph; §IV-A relabelling by a
 // prefix sum over used labels), projection (§III-C) and the cut (§II-A).
 //
-// Contraction is sort based instead of the paper's concurrent hash table:
-//   used[L] flags -> exclusive scan -> f2c[v] = id[C[v]], n'
-//   c'(i) by integer atomics (exact)
-//   every directed fine entry (v,u) with f2c[v] != f2c[u] becomes a 64-bit key
-//   (i << bits | j) with its weight; stable LSD radix sort of the keys; equal
-//   keys form runs whose weights are summed through an inclusive prefix sum;
-//   run heads become the coarse entries (rows and columns ascending), and the
-//   row offsets are filled from the run rows.
+// Contraction groups the fine vertices by coarse id instead of the paper's
+// concurrent hash table over all cut edges:
+//   used[L] flags -> exclusive scan -> f2c[v] = id[C[v]], n'; c'(i) by integer
+//   atomics; members of each coarse vertex (counting sort by f2c) and the
+//   prefix of their degrees, so coarse row i owns the flattened entry range
+//   [flat[mstart[i]], flat[mstart[i+1]]) of length D_i;
+//   row i's entries (j = f2c[u], w) with j != i are summed in a hash table
+//   keyed by j — in LDS for D_i <= 2048 (one wave per row up to 128 entries,
+//   one workgroup per row above), then the distinct columns are sorted in LDS;
+//   rows above 2048 entries are inserted chunk-wise into per-row global
+//   tables and only their distinct (row, column) pairs are radix sorted;
+//   a scan of the per-row column counts gives the coarse row offsets and a
+//   copy compacts the rows.
 #include <climits>
 
 #include "contract.hpp"
@@ -113,67 +118,6 @@ __global__ void k_cw_out(const int64_t *cw, const int32_t *nc, int32_t *vwgt_c, 
     }
 }
 
-struct CrossFlag {
-    const int32_t *rowof, *adjncy, *f2c;
-    __device__ bool operator()(int64_t e) const { return f2c[rowof[e]] != f2c[adjncy[e]]; }
-};
-struct CrossEmit {
-    const int32_t *rowof, *adjncy, *adjwgt, *f2c;
-    int bits;
-    uint64_t *key;
-    int32_t *val;
-    __device__ void operator()(int64_t e, int32_t pos) const {
-        const uint64_t i = (uint32_t)f2c[rowof[e]], j = (uint32_t)f2c[adjncy[e]];
-        key[pos] = (i << bits) | j;
-        val[pos] = adjwgt ? adjwgt[e] : 1;
-    }
-};
-
-struct ValIn {
-    const int32_t *w;
-    __device__ int64_t operator()(int64_t p) const { return (int64_t)w[p]; }
-};
-struct InclOut {
-    int64_t *S;
-    __device__ void operator()(int64_t p, int64_t ex, int64_t v) const { S[p] = ex + v; }
-};
-
-struct HeadFlag {
-    const uint64_t *key;
-    __device__ bool operator()(int64_t p) const { return p == 0 || key[p] != key[p - 1]; }
-};
-struct HeadEmit {
-    int32_t *head;
-    __device__ void operator()(int64_t p, int32_t r) const { head[r] = (int32_t)p; }
-};
-
-__global__ void k_runs(const uint64_t *key, const int64_t *S, const int32_t *head, const int32_t *nruns,
-                       const int32_t *m, int bits, int32_t *adjncy_c, int32_t *adjwgt_c, int32_t *overflow) {
-    const int32_t R = *nruns, M = *m;
-    const uint64_t jm = (uint64_t(1) << bits) - 1;
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R;
-         r += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t p0 = head[r];
-        const int32_t p1 = (r + 1 < R) ? head[r + 1] - 1 : M - 1;
-        const int64_t sum = S[p1] - (p0 > 0 ? S[p0 - 1] : 0);
-        if (sum > INT_MAX) *overflow = 1;
-        adjncy_c[r] = (int32_t)(key[p0] & jm);
-        adjwgt_c[r] = (int32_t)sum;
-    }
-}
-
-// xadj_c[i] = first run with row >= i, for i in [0, n']
-__global__ void k_row_offsets(const uint64_t *key, const int32_t *head, const int32_t *nruns, const int32_t *nc,
-                              int bits, int32_t *xadj_c) {
-    const int32_t R = *nruns, N = *nc;
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r <= R;
-         r += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t row = (r < R) ? (int64_t)(key[head[r]] >> bits) : (int64_t)N;
-        const int64_t prev = (r > 0) ? (int64_t)(key[head[r - 1]] >> bits) : -1;
-        for (int64_t i = prev + 1; i <= row; i++) xadj_c[i] = (int32_t)r;
-    }
-}
-
 __global__ void k_project(int32_t n, const int32_t *f2c, const int32_t *pc, int32_t *pf) {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
          v += (int64_t)gridDim.x * blockDim.x) {
@@ -193,6 +137,378 @@ struct NoOut {
 };
 
 __global__ void k_halve(int64_t *x) { *x /= 2; }
+
+// ---------------------------------------------------------------- row-grouped contraction
+
+constexpr int kRowWaveMax = 128;    // D_i <= 128: one wave per row
+constexpr int kRowBlockMax = 2048;  // D_i <= 2048: one workgroup per row
+constexpr int kRowChunk = 2048;     // larger rows: flattened entries per aggregating workgroup
+
+struct RowCtx {
+    const int32_t *xadj, *adjncy, *adjwgt, *f2c;
+    const int32_t *mstart;   // [nc+1]
+    const int32_t *members;  // [n_incl]
+    const int32_t *flat;     // [n_incl+1] exclusive prefix of member degrees
+    int32_t *tj;             // [nnz] sorted columns of row i at flat[mstart[i]]
+    long long *tw;           // [nnz] their weights
+    int32_t *rcnt;           // [nc] distinct columns of row i
+};
+
+__device__ __forceinline__ uint32_t col_hash(int32_t j) { return (uint32_t)j * 0x9E3779B1u; }
+
+template <typename KeyP, typename ValP>
+__device__ __forceinline__ void col_insert(KeyP key, ValP val, uint32_t mask, int lg, int32_t j, long long w) {
+    uint32_t h = col_hash(j) >> (32 - lg);
+    for (;;) {
+        const int32_t prev = atomicCAS(&key[h], -1, j);
+        if (prev == -1 || prev == j) break;
+        h = (h + 1) & mask;
+    }
+    atomicAdd((unsigned long long *)&val[h], (unsigned long long)w);
+}
+
+// largest p in [lo, hi] with F[p] <= t
+__device__ __forceinline__ int32_t upper_pos(const int32_t *F, int32_t lo, int32_t hi, int32_t t) {
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (F[mid] <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_crow_wave(RowCtx c, const int32_t *rows, int32_t count) {
+    constexpr int NW = 4, CAP = 2 * kRowWaveMax;
+    __shared__ int32_t skey[NW][CAP];
+    __shared__ long long sval[NW][CAP];
+    __shared__ int32_t sF[NW][kRowWaveMax + 1];
+    __shared__ int32_t lj[NW][kRowWaveMax];
+    __shared__ long long lw[NW][kRowWaveMax];
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
+    for (int q = lane; q < CAP; q += kWave) {
+        skey[w][q] = -1;
+        sval[w][q] = 0;
+    }
+    wave_sync();
+    for (int64_t idx = (int64_t)blockIdx.x * NW + w; idx < count; idx += (int64_t)gridDim.x * NW) {
+        const int32_t i = rows[idx];
+        const int32_t m0 = c.mstart[i], m1 = c.mstart[i + 1];
+        const int32_t base = c.flat[m0], D = c.flat[m1] - base, M = m1 - m0;
+        for (int q = lane; q <= M; q += kWave) sF[w][q] = c.flat[m0 + q] - base;
+        wave_sync();
+        int lg = 1;
+        while ((1 << lg) < 2 * D) lg++;
+        const uint32_t cap = 1u << lg;
+        int32_t p = 0;
+        for (int32_t t = lane; t < D; t += kWave) {
+            p = upper_pos(sF[w], p, M - 1, t);
+            const int32_t v = c.members[m0 + p];
+            const int32_t e = c.xadj[v] + (t - sF[w][p]);
+            const int32_t j = c.f2c[c.adjncy[e]];
+            if (j != i) col_insert(skey[w], sval[w], cap - 1, lg, j, c.adjwgt ? c.adjwgt[e] : 1);
+        }
+        wave_sync();
+        int32_t r = 0;
+        for (uint32_t s0 = 0; s0 < cap; s0 += kWave) {
+            const uint32_t sl = s0 + lane;
+            const bool occ = sl < cap && skey[w][sl] >= 0;
+            const uint64_t m = __ballot(occ);
+            if (occ) {
+                const int32_t pos = r + __popcll(m & lt);
+                lj[w][pos] = skey[w][sl];
+                lw[w][pos] = sval[w][sl];
+            }
+            r += __popcll(m);
+        }
+        wave_sync();
+        for (int32_t q = lane; q < r; q += kWave) {
+            const int32_t jj = lj[w][q];
+            int32_t rank = 0;
+            for (int32_t x = 0; x < r; x++) rank += lj[w][x] < jj;
+            c.tj[base + rank] = jj;
+            c.tw[base + rank] = lw[w][q];
+        }
+        if (lane == 0) c.rcnt[i] = r;
+        for (uint32_t q = lane; q < cap; q += kWave) {
+            skey[w][q] = -1;
+            sval[w][q] = 0;
+        }
+        wave_sync();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_crow_block(RowCtx c, const int32_t *rows, int32_t count) {
+    constexpr int CAP = 2 * kRowBlockMax;
+    __shared__ int32_t skey[CAP];
+    __shared__ long long sval[CAP];
+    __shared__ int32_t sF[kRowBlockMax + 1];
+    __shared__ int32_t lj[kRowBlockMax];
+    __shared__ long long lw[kRowBlockMax];
+    __shared__ int32_t t32[256 / kWave + 1];
+    for (int q = threadIdx.x; q < CAP; q += 256) {
+        skey[q] = -1;
+        sval[q] = 0;
+    }
+    __syncthreads();
+    for (int64_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
+        const int32_t i = rows[idx];
+        const int32_t m0 = c.mstart[i], m1 = c.mstart[i + 1];
+        const int32_t base = c.flat[m0], D = c.flat[m1] - base, M = m1 - m0;
+        for (int q = threadIdx.x; q <= M; q += 256) sF[q] = c.flat[m0 + q] - base;
+        __syncthreads();
+        int lg = 1;
+        while ((1 << lg) < 2 * D) lg++;
+        const uint32_t cap = 1u << lg;
+        int32_t p = 0;
+        for (int32_t t = threadIdx.x; t < D; t += 256) {
+            p = upper_pos(sF, p, M - 1, t);  // t grows per thread: search from the last member
+            const int32_t v = c.members[m0 + p];
+            const int32_t e = c.xadj[v] + (t - sF[p]);
+            const int32_t j = c.f2c[c.adjncy[e]];
+            if (j != i) col_insert(skey, sval, cap - 1, lg, j, c.adjwgt ? c.adjwgt[e] : 1);
+        }
+        __syncthreads();
+        int32_t r = 0;
+        for (uint32_t s0 = 0; s0 < cap; s0 += 256) {
+            const uint32_t sl = s0 + threadIdx.x;
+            const bool occ = sl < cap && skey[sl] >= 0;
+            int32_t tot;
+            const int32_t ex = block_excl_scan<256>((int32_t)occ, t32, &tot);
+            if (occ) {
+                lj[r + ex] = skey[sl];
+                lw[r + ex] = sval[sl];
+            }
+            r += tot;
+        }
+        int32_t P = 1;
+        while (P < r) P <<= 1;
+        for (int32_t q = r + threadIdx.x; q < P; q += 256) lj[q] = INT_MAX;
+        __syncthreads();
+        // bitonic sort of lj/lw[0, P) by column
+        for (int32_t kk = 2; kk <= P; kk <<= 1) {
+            for (int32_t jj = kk >> 1; jj > 0; jj >>= 1) {
+                for (int32_t q = threadIdx.x; q < P; q += 256) {
+                    const int32_t o = q ^ jj;
+                    if (o > q) {
+                        const bool up = (q & kk) == 0;
+                        const int32_t a = lj[q], b = lj[o];
+                        if ((a > b) == up) {
+                            lj[q] = b;
+                            lj[o] = a;
+                            const long long x = lw[q];
+                            lw[q] = lw[o];
+                            lw[o] = x;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (int32_t q = threadIdx.x; q < r; q += 256) {
+            c.tj[base + q] = lj[q];
+            c.tw[base + q] = lw[q];
+        }
+        if (threadIdx.x == 0) c.rcnt[i] = r;
+        for (uint32_t q = threadIdx.x; q < cap; q += 256) {
+            skey[q] = -1;
+            sval[q] = 0;
+        }
+        __syncthreads();
+    }
+}
+
+// Rows above the LDS classes: chunks of kRowChunk flattened entries, one
+// workgroup each, sum their entries per column in an LDS hash and append the
+// distinct (row rank, column) pairs through one reservation per chunk; a
+// radix sort then brings equal pairs together and a run reduction merges the
+// chunks of a row.
+struct BigRows {
+    const int32_t *rows;         // [nb] coarse row ids
+    const int32_t *chunk_owner;  // [nchunks] row rank of each chunk
+    const int32_t *chunk_first;  // [nb] first chunk of each row
+    uint64_t *key;               // [cap] (row rank << jbits) | column
+    long long *val;              // [cap]
+    int32_t *cursor;             // [1] append position
+    int jbits;
+};
+
+__global__ __launch_bounds__(256) void k_cbig_chunk(RowCtx c, BigRows b) {
+    constexpr int CAP = 2 * kRowChunk;
+    __shared__ int32_t skey[CAP];
+    __shared__ long long sval[CAP];
+    __shared__ int32_t rng[2];
+    __shared__ int32_t t32[256 / kWave + 1];
+    __shared__ int32_t resv;
+    for (int q = threadIdx.x; q < CAP; q += 256) {
+        skey[q] = -1;
+        sval[q] = 0;
+    }
+    const int32_t g = b.chunk_owner[blockIdx.x];
+    const int32_t i = b.rows[g];
+    const int32_t m0 = c.mstart[i], m1 = c.mstart[i + 1];
+    const int32_t base = c.flat[m0], D = c.flat[m1] - base;
+    const int32_t t0 = (blockIdx.x - b.chunk_first[g]) * kRowChunk;
+    const int32_t t1 = min(D, t0 + kRowChunk);
+    if (threadIdx.x == 0) {
+        rng[0] = upper_pos(c.flat, m0, m1 - 1, base + t0);
+        rng[1] = upper_pos(c.flat, m0, m1 - 1, base + t1 - 1);
+    }
+    __syncthreads();
+    const int32_t plo = rng[0], phi = rng[1];
+    int32_t p = plo;
+    for (int32_t t = t0 + threadIdx.x; t < t1; t += 256) {
+        p = upper_pos(c.flat, p, phi, base + t);  // t grows per thread: search from the last member
+        const int32_t v = c.members[p];
+        const int32_t e = c.xadj[v] + (base + t - c.flat[p]);
+        const int32_t j = c.f2c[c.adjncy[e]];
+        if (j != i) col_insert(skey, sval, CAP - 1, __builtin_ctz(CAP), j, c.adjwgt ? c.adjwgt[e] : 1);
+    }
+    __syncthreads();
+    int32_t cnt = 0;
+    for (int q = threadIdx.x; q < CAP; q += 256) cnt += skey[q] >= 0;
+    cnt = block_sum<256>(cnt, t32);
+    if (threadIdx.x == 0) resv = cnt ? atomicAdd(b.cursor, cnt) : 0;
+    __syncthreads();
+    int32_t r = resv;
+    for (int q0 = 0; q0 < CAP; q0 += 256) {
+        const int q = q0 + threadIdx.x;
+        const bool occ = skey[q] >= 0;
+        int32_t tot;
+        const int32_t ex = block_excl_scan<256>((int32_t)occ, t32, &tot);
+        if (occ) {
+            b.key[r + ex] = ((uint64_t)(uint32_t)g << b.jbits) | (uint64_t)(uint32_t)skey[q];
+            b.val[r + ex] = sval[q];
+        }
+        r += tot;
+    }
+}
+
+struct PairHead {
+    const uint64_t *key;
+    __device__ bool operator()(int64_t p) const { return p == 0 || key[p] != key[p - 1]; }
+};
+struct PairHeadEmit {
+    int32_t *head;
+    __device__ void operator()(int64_t p, int32_t r) const { head[r] = (int32_t)p; }
+};
+struct ValIn64 {
+    const long long *v;
+    __device__ long long operator()(int64_t p) const { return v[p]; }
+};
+struct InclOut64 {
+    long long *S;
+    __device__ void operator()(int64_t p, long long ex, long long v) const { S[p] = ex + v; }
+};
+
+// runs are sorted by row rank: roff[g] = first run of rank >= g, for g in [0, nb]
+__global__ void k_cbig_rowoff(const uint64_t *key, const int32_t *head, const int32_t *nruns, int jbits, int32_t nb,
+                              int32_t *roff) {
+    const int32_t R = *nruns;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r <= R; r += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t cur = r < R ? (int64_t)(key[head[r]] >> jbits) : (int64_t)nb;
+        const int64_t prev = r > 0 ? (int64_t)(key[head[r - 1]] >> jbits) : -1;
+        for (int64_t g = prev + 1; g <= cur; g++) roff[g] = (int32_t)r;
+    }
+}
+
+__global__ void k_cbig_place(RowCtx c, BigRows b, const int32_t *head, const int32_t *nruns, int32_t m,
+                             const long long *S, const int32_t *roff, int32_t nb) {
+    const int32_t R = *nruns;
+    const uint64_t jm = (uint64_t(1) << b.jbits) - 1;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R; r += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t p0 = head[r], p1 = (r + 1 < R) ? head[r + 1] - 1 : m - 1;
+        const uint64_t k = b.key[p0];
+        const int32_t g = (int32_t)(k >> b.jbits);
+        const int32_t i = b.rows[g];
+        const int32_t base = c.flat[c.mstart[i]];
+        const int64_t pos = r - roff[g];
+        c.tj[base + pos] = (int32_t)(k & jm);
+        c.tw[base + pos] = S[p1] - (p0 > 0 ? S[p0 - 1] : 0);
+    }
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < nb; g += (int64_t)gridDim.x * blockDim.x)
+        c.rcnt[b.rows[g]] = roff[g + 1] - roff[g];
+}
+
+__global__ void k_big_nchunk(RowCtx c, const int32_t *rows, int32_t nb, int32_t *nch) {
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < nb; g += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t i = rows[g];
+        const int32_t D = c.flat[c.mstart[i + 1]] - c.flat[c.mstart[i]];
+        nch[g] = (D + kRowChunk - 1) / kRowChunk;
+    }
+}
+
+__global__ void k_row_counts(const int32_t *f2c, const int32_t *xadj, int32_t n, int32_t *cnt) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t i = f2c[v];
+        if (i >= 0) atomicAdd(&cnt[i], 1);
+    }
+}
+
+__global__ void k_members(const int32_t *f2c, const int32_t *xadj, int32_t n, const int32_t *mstart, int32_t *fill,
+                          int32_t *members, int32_t *mdeg) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t i = f2c[v];
+        if (i < 0) continue;
+        const int32_t p = mstart[i] + atomicAdd(&fill[i], 1);
+        members[p] = (int32_t)v;
+        mdeg[p] = xadj[v + 1] - xadj[v];
+    }
+}
+
+__global__ void k_row_class(const int32_t *mstart, const int32_t *flat, int32_t nc, uint32_t *key, int32_t *val,
+                            int32_t *ccount) {
+    __shared__ int32_t h[3];
+    if (threadIdx.x < 3) h[threadIdx.x] = 0;
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += (int64_t)gridDim.x * blockDim.x) {
+        // size = max(entries, members): members without neighbours (possible for
+        // arbitrary caller labels) still occupy the LDS member-prefix array
+        const int32_t D = flat[mstart[i + 1]] - flat[mstart[i]];
+        const int32_t M = mstart[i + 1] - mstart[i];
+        const int32_t sz = D > M ? D : M;
+        const uint32_t k = sz <= kRowWaveMax ? 0u : (sz <= kRowBlockMax ? 1u : 2u);
+        key[i] = k;
+        val[i] = (int32_t)i;
+        atomicAdd(&h[k], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < 3 && h[threadIdx.x]) atomicAdd(&ccount[threadIdx.x], h[threadIdx.x]);
+}
+
+__global__ void k_expand_owner(const int32_t *first, const int32_t *num, int32_t nb, int32_t *owner) {
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < nb; g += (int64_t)gridDim.x * blockDim.x)
+        for (int32_t q = 0; q < num[g]; q++) owner[first[g] + q] = (int32_t)g;
+}
+
+// one wave per coarse row: copy its sorted columns to the output CSR
+__global__ void k_copy_rows(RowCtx c, const int32_t *xadj_c, int32_t nc, int32_t *adjncy_c, int32_t *adjwgt_c,
+                            int32_t *overflow) {
+    const int lane = lane_id();
+    const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    int bad = 0;
+    for (int64_t i = wid; i < nc; i += nwaves) {
+        const int32_t src = c.flat[c.mstart[i]];
+        const int32_t dst = xadj_c[i], r = xadj_c[i + 1] - dst;
+        for (int32_t q = lane; q < r; q += kWave) {
+            const long long wv = c.tw[src + q];
+            bad |= wv > INT_MAX;
+            adjncy_c[dst + q] = c.tj[src + q];
+            adjwgt_c[dst + q] = (int32_t)wv;
+        }
+    }
+    if (bad) *overflow = 1;
+}
+
+struct CountIn {
+    const int32_t *r;
+    __device__ int32_t operator()(int64_t i) const { return r[i]; }
+};
+struct CountOut {
+    int32_t *x;
+    __device__ void operator()(int64_t i, int32_t ex, int32_t) const { x[i] = ex; }
+};
 
 }  // namespace
 
@@ -228,8 +544,7 @@ int build_rowof(const DevGraph &g, int32_t *rowof, Scratch &sc) {
     return maxscan_inclusive(rowof, nnz, sc);
 }
 
-int contract(const DevGraph &g, const int32_t *labels, bool skip_isolated, const int32_t *rowof,
-             CoarseOut &out, Scratch &sc) {
+int contract(const DevGraph &g, const int32_t *labels, bool skip_isolated, CoarseOut &out, Scratch &sc) {
     hipStream_t s = sc.stream();
     const int32_t n = g.n;
     out.n = 0;
@@ -263,43 +578,124 @@ int contract(const DevGraph &g, const int32_t *labels, bool skip_isolated, const
 
     const int64_t nnz = g.nnz;
     int32_t nnz_c = 0;
-    if (nnz > 0) {
-        int32_t *ro = const_cast<int32_t *>(rowof);
-        if (!ro) {
-            GP_TRY(sc.alloc(&ro, nnz));
-            GP_TRY(build_rowof(g, ro, sc));
-        }
-        const int bits = bits_for(nc > 0 ? nc - 1 : 0) > 0 ? bits_for(nc - 1) : 1;
-        uint64_t *k1 = nullptr, *k2 = nullptr;
-        int32_t *v1 = nullptr, *v2 = nullptr, *d_m = nullptr, *head = nullptr, *d_runs = nullptr;
-        int64_t *S = nullptr;
-        GP_TRY(sc.alloc(&k1, nnz));
-        GP_TRY(sc.alloc(&k2, nnz));
-        GP_TRY(sc.alloc(&v1, nnz));
-        GP_TRY(sc.alloc(&v2, nnz));
-        GP_TRY(sc.alloc(&d_m, 1));
-        GP_TRY(sc.alloc(&d_runs, 1));
-        GP_TRY(compact(CrossFlag{ro, g.adjncy, out.f2c}, CrossEmit{ro, g.adjncy, g.adjwgt, out.f2c, bits, k1, v1},
-                       nnz, nullptr, d_m, sc));
-        int32_t m = 0;
-        GP_HIP(hipMemcpyAsync(&m, d_m, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    if (nnz > 0 && nc > 0) {
+        // ---- members of each coarse vertex and the prefix of their degrees
+        int32_t *cnt = nullptr, *mstart = nullptr, *fill = nullptr, *members = nullptr, *mdeg = nullptr,
+                *flat = nullptr, *d_ni = nullptr;
+        GP_TRY(sc.alloc(&cnt, nc));
+        GP_TRY(sc.alloc(&mstart, (size_t)nc + 1));
+        GP_TRY(sc.alloc(&fill, nc));
+        GP_TRY(sc.alloc(&members, n));
+        GP_TRY(sc.alloc(&mdeg, n));
+        GP_TRY(sc.alloc(&flat, (size_t)n + 1));
+        GP_TRY(sc.alloc(&d_ni, 1));
+        GP_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (size_t)nc, s));
+        GP_HIP(hipMemsetAsync(fill, 0, sizeof(int32_t) * (size_t)nc, s));
+        hipLaunchKernelGGL(k_row_counts, dim3(gv), dim3(256), 0, s, out.f2c, g.xadj, n, cnt);
+        GP_LAUNCH_CHECK();
+        GP_TRY((scan<int32_t>(LoadIn<int32_t>{cnt}, StoreExcl<int32_t>{mstart}, nc, nullptr, mstart + nc, sc)));
+        hipLaunchKernelGGL(k_members, dim3(gv), dim3(256), 0, s, out.f2c, g.xadj, n, mstart, fill, members, mdeg);
+        GP_LAUNCH_CHECK();
+        int32_t ni = 0;
+        GP_HIP(hipMemcpyAsync(&ni, mstart + nc, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         GP_HIP(hipStreamSynchronize(s));
-        if (m > 0) {
-            GP_TRY((radix_sort<uint64_t, int32_t>(&k1, &v1, &k2, &v2, m, nullptr, 2 * bits, sc)));
-            GP_TRY(sc.alloc(&S, m));
-            GP_TRY(sc.alloc(&head, m));
-            GP_TRY((scan<int64_t>(ValIn{v1}, InclOut{S}, m, nullptr, (int64_t *)nullptr, sc)));
-            GP_TRY(compact(HeadFlag{k1}, HeadEmit{head}, m, nullptr, d_runs, sc));
-            const unsigned gm = grid_for(m, 256, 65536);
-            hipLaunchKernelGGL(k_runs, dim3(gm), dim3(256), 0, s, k1, S, head, d_runs, d_m, bits, out.adjncy,
-                               out.adjwgt, flags);
+        GP_TRY((scan<int32_t>(LoadIn<int32_t>{mdeg}, StoreExcl<int32_t>{flat}, ni, nullptr, flat + ni, sc)));
+
+        int32_t *tj = nullptr, *rcnt = nullptr;
+        long long *tw = nullptr;
+        GP_TRY(sc.alloc(&tj, nnz));
+        GP_TRY(sc.alloc(&tw, nnz));
+        GP_TRY(sc.alloc(&rcnt, nc));
+        RowCtx c{g.xadj, g.adjncy, g.adjwgt, out.f2c, mstart, members, flat, tj, tw, rcnt};
+
+        // ---- rows by size class (stable, ascending ids inside a class)
+        uint32_t *ck = nullptr, *ck2 = nullptr;
+        int32_t *cv = nullptr, *cv2 = nullptr, *ccount = nullptr;
+        GP_TRY(sc.alloc(&ck, nc));
+        GP_TRY(sc.alloc(&ck2, nc));
+        GP_TRY(sc.alloc(&cv, nc));
+        GP_TRY(sc.alloc(&cv2, nc));
+        GP_TRY(sc.alloc(&ccount, 3));
+        GP_HIP(hipMemsetAsync(ccount, 0, sizeof(int32_t) * 3, s));
+        hipLaunchKernelGGL(k_row_class, dim3(grid_for(nc, 256, 4096)), dim3(256), 0, s, mstart, flat, nc, ck, cv,
+                           ccount);
+        GP_LAUNCH_CHECK();
+        GP_TRY((radix_sort<uint32_t, int32_t>(&ck, &cv, &ck2, &cv2, nc, nullptr, 2, sc)));
+        int32_t hc[3];
+        GP_HIP(hipMemcpyAsync(hc, ccount, sizeof(hc), hipMemcpyDeviceToHost, s));
+        GP_HIP(hipStreamSynchronize(s));
+        const int32_t *rows_w = cv, *rows_b = cv + hc[0], *rows_g = cv + hc[0] + hc[1];
+        if (hc[0] > 0) {
+            hipLaunchKernelGGL(k_crow_wave, dim3(grid_for(hc[0], 4, 65536)), dim3(256), 0, s, c, rows_w, hc[0]);
             GP_LAUNCH_CHECK();
-            hipLaunchKernelGGL(k_row_offsets, dim3(gm), dim3(256), 0, s, k1, head, d_runs, d_nc, bits, out.xadj);
-            GP_LAUNCH_CHECK();
-            GP_HIP(hipMemcpyAsync(&nnz_c, d_runs, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        } else {
-            GP_HIP(hipMemsetAsync(out.xadj, 0, sizeof(int32_t) * (size_t)(nc + 1), s));
         }
+        if (hc[1] > 0) {
+            hipLaunchKernelGGL(k_crow_block, dim3(grid_for(hc[1], 1, 8192)), dim3(256), 0, s, c, rows_b, hc[1]);
+            GP_LAUNCH_CHECK();
+        }
+        const int32_t nb = hc[2];
+        if (nb > 0) {
+            int32_t *nch = nullptr, *cfirst = nullptr, *d_tot = nullptr, *cown = nullptr, *cursor = nullptr,
+                    *head = nullptr, *d_runs = nullptr, *roff = nullptr;
+            GP_TRY(sc.alloc(&nch, nb));
+            GP_TRY(sc.alloc(&cfirst, nb));
+            GP_TRY(sc.alloc(&d_tot, 1));
+            GP_TRY(sc.alloc(&cursor, 1));
+            GP_TRY(sc.alloc(&d_runs, 1));
+            GP_TRY(sc.alloc(&roff, (size_t)nb + 1));
+            hipLaunchKernelGGL(k_big_nchunk, dim3(grid_for(nb, 256, 1024)), dim3(256), 0, s, c, rows_g, nb, nch);
+            GP_LAUNCH_CHECK();
+            GP_TRY((scan<int32_t>(LoadIn<int32_t>{nch}, StoreExcl<int32_t>{cfirst}, nb, nullptr, d_tot, sc)));
+            int32_t nchunks = 0;
+            GP_HIP(hipMemcpyAsync(&nchunks, d_tot, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            GP_HIP(hipStreamSynchronize(s));
+            const int64_t bcap = (int64_t)nchunks * kRowChunk;
+            uint64_t *bk = nullptr, *bk2 = nullptr;
+            long long *bv = nullptr, *bv2 = nullptr, *S = nullptr;
+            GP_TRY(sc.alloc(&bk, bcap));
+            GP_TRY(sc.alloc(&bk2, bcap));
+            GP_TRY(sc.alloc(&bv, bcap));
+            GP_TRY(sc.alloc(&bv2, bcap));
+            GP_HIP(hipMemsetAsync(cursor, 0, sizeof(int32_t), s));
+            GP_HIP(hipMemsetAsync(d_runs, 0, sizeof(int32_t), s));
+            const int jbits = bits_for(nc - 1) > 0 ? bits_for(nc - 1) : 1;
+            const int gbits = bits_for(nb - 1) > 0 ? bits_for(nb - 1) : 1;
+            int32_t m = 0;
+            if (nchunks > 0) {  // rows whose members have no neighbours have no chunks
+                GP_TRY(sc.alloc(&cown, nchunks));
+                hipLaunchKernelGGL(k_expand_owner, dim3(grid_for(nb, 256, 1024)), dim3(256), 0, s, cfirst, nch, nb,
+                                   cown);
+                GP_LAUNCH_CHECK();
+                BigRows br{rows_g, cown, cfirst, bk, bv, cursor, jbits};
+                hipLaunchKernelGGL(k_cbig_chunk, dim3(nchunks), dim3(256), 0, s, c, br);
+                GP_LAUNCH_CHECK();
+                GP_HIP(hipMemcpyAsync(&m, cursor, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+                GP_HIP(hipStreamSynchronize(s));
+            }
+            if (m > 0) {
+                GP_TRY((radix_sort<uint64_t, long long>(&bk, &bv, &bk2, &bv2, m, nullptr, jbits + gbits, sc)));
+                GP_TRY(sc.alloc(&S, m));
+                GP_TRY(sc.alloc(&head, m));
+                GP_TRY((scan<long long>(ValIn64{bv}, InclOut64{S}, m, nullptr, (long long *)nullptr, sc)));
+                GP_TRY(compact(PairHead{bk}, PairHeadEmit{head}, m, nullptr, d_runs, sc));
+            }
+            hipLaunchKernelGGL(k_cbig_rowoff, dim3(grid_for((int64_t)m + 1, 256, 65536)), dim3(256), 0, s, bk, head,
+                               d_runs, jbits, nb, roff);
+            GP_LAUNCH_CHECK();
+            BigRows br{rows_g, cown, cfirst, bk, bv, cursor, jbits};
+            hipLaunchKernelGGL(k_cbig_place, dim3(grid_for((int64_t)m + nb, 256, 65536)), dim3(256), 0, s, c, br,
+                               head, d_runs, m, S, roff, nb);
+            GP_LAUNCH_CHECK();
+        }
+        // ---- coarse row offsets and the compacted rows
+        int32_t *d_nnzc = nullptr;
+        GP_TRY(sc.alloc(&d_nnzc, 1));
+        GP_TRY((scan<int32_t>(CountIn{rcnt}, CountOut{out.xadj}, nc, nullptr, d_nnzc, sc)));
+        GP_HIP(hipMemcpyAsync(out.xadj + nc, d_nnzc, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        hipLaunchKernelGGL(k_copy_rows, dim3(grid_for((int64_t)nc * kWave, 256, 65536)), dim3(256), 0, s, c, out.xadj,
+                           nc, out.adjncy, out.adjwgt, flags);
+        GP_LAUNCH_CHECK();
+        GP_HIP(hipMemcpyAsync(&nnz_c, d_nnzc, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     } else {
         GP_HIP(hipMemsetAsync(out.xadj, 0, sizeof(int32_t) * (size_t)(nc + 1), s));
     }

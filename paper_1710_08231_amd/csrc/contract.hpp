@@ -14,9 +14,8 @@ struct CoarseOut {
 
 // Contraction of `labels` (values in [0, n)). When skip_isolated is set,
 // vertices without neighbours are left out (f2c = -1) and no label of theirs
-// is counted as used. rowof may be null (then built here).
-int contract(const DevGraph &g, const int32_t *labels, bool skip_isolated, const int32_t *rowof,
-             CoarseOut &out, Scratch &sc);
+// is counted as used.
+int contract(const DevGraph &g, const int32_t *labels, bool skip_isolated, CoarseOut &out, Scratch &sc);
 
 // part_fine[v] = f2c[v] >= 0 ? part_coarse[f2c[v]] : -1
 int project(int32_t n, const int32_t *f2c, const int32_t *part_coarse, int32_t *part_fine, hipStream_t s);

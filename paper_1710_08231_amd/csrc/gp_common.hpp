@@ -65,8 +65,12 @@ class Scratch {
     template <typename T>
     int temp(T **out, size_t count, int slot) {
         const size_t bytes = (count ? count : 1) * sizeof(T);
-        if (slot >= (int)tmp_.size()) tmp_.resize(slot + 1, {nullptr, 0});
+        if (slot >= (int)tmp_.size()) {
+            if (frozen_) return frozen_fail();
+            tmp_.resize(slot + 1, {nullptr, 0});
+        }
         if (tmp_[slot].second < bytes) {
+            if (frozen_) return frozen_fail();
             if (tmp_[slot].first) (void)hipFreeAsync(tmp_[slot].first, s_);
             void *p = nullptr;
             const size_t grow = bytes + bytes / 4;
@@ -89,9 +93,19 @@ class Scratch {
             if (t.first) (void)hipFreeAsync(t.first, s_);
         tmp_.clear();
     }
-    hipStream_t stream() const { return s_; }
+    hipStream_t stream() const { return launch_ ? launch_ : s_; }
+    // Launch subsequent work on `st` (for recording a launch sequence); while
+    // `frozen`, scratch slots may not grow, so nothing is allocated.
+    void set_stream(hipStream_t st, bool frozen) {
+        launch_ = st == s_ ? nullptr : st;
+        frozen_ = frozen;
+    }
 
   private:
+    int frozen_fail() {
+        set_error("scratch slot would grow while a launch sequence is recorded");
+        return GP_ERR_HIP;
+    }
     // Keep freed blocks in the device's default pool instead of returning them
     // to the driver at every synchronisation.
     static void keep_pool() {
@@ -106,6 +120,8 @@ class Scratch {
         done = true;
     }
     hipStream_t s_;
+    hipStream_t launch_ = nullptr;
+    bool frozen_ = false;
     std::vector<void *> ptrs_;
     std::vector<std::pair<void *, size_t>> tmp_;
 };

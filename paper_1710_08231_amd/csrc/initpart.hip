@@ -16,6 +16,8 @@
 // a component that went idle twice stays idle, so each try gets exactly the
 // result it would get alone. Then each try is greedily rebalanced by one
 // workgroup, and the best try by (imbalanced, cut, index) is kept.
+#include <algorithm>
+#include <array>
 #include <climits>
 
 #include "contract.hpp"
@@ -41,13 +43,16 @@ __device__ __forceinline__ int64_t vw(const int32_t *vwgt, int32_t v) { return v
 struct BisectArgs {
     int32_t n;
     const int32_t *xadj, *adjncy, *vwgt;
-    int32_t *blk;    // [attempts * n], -1 = not taking part
+    int32_t *blk;    // [attempts * n] global block ids (graph block base + local), -1 = not taking part
     int32_t *mark;   // [attempts * n]
     int32_t *claim;  // [attempts * n]
-    int32_t *slist;  // [nblocks * n]
-    int32_t *order;  // [nblocks * n]
-    int32_t *pre;    // [nblocks * (n + 1)] frontier degree prefix
-    const int32_t *sub_base, *sub_ks;
+    int32_t *slist;  // per workgroup region (its graph's size)
+    int32_t *order;  // per workgroup region
+    int32_t *pre;    // per workgroup region (+1) frontier degree prefix
+    const int64_t *reg;  // [nsub] region offset of subproblem (per attempt: + attempt * regtot)
+    int64_t regtot;
+    const int32_t *sub_g, *sub_base, *sub_ks;  // graph, local block base, blocks of each subproblem
+    const int32_t *voff, *kbase;               // graph vertex ranges and block bases
     int32_t nsub;
     uint64_t seed;
 };
@@ -68,21 +73,25 @@ __global__ __launch_bounds__(kBB) void k_bisect(BisectArgs a) {
     __shared__ int32_t t32[kBB / kWave + 1];
     __shared__ int32_t sh_tail, sh_stop, sh_found;
     const int attempt = blockIdx.x / a.nsub, sp = blockIdx.x % a.nsub;
-    const int32_t base = a.sub_base[sp], ks = a.sub_ks[sp], kl = (ks + 1) / 2;
+    const int32_t gr = a.sub_g[sp];
+    const int32_t lbase = a.sub_base[sp], ks = a.sub_ks[sp], kl = (ks + 1) / 2;
+    const int32_t base = a.kbase[gr] + lbase;  // global block id of this subproblem
     const int32_t n = a.n;
+    const int32_t vlo = a.voff[gr], vhi = a.voff[gr + 1];
     int32_t *blk = a.blk + (int64_t)attempt * n;
     int32_t *mark = a.mark + (int64_t)attempt * n;
     int32_t *claim = a.claim + (int64_t)attempt * n;
-    int32_t *slist = a.slist + (int64_t)blockIdx.x * n;
-    int32_t *order = a.order + (int64_t)blockIdx.x * n;
-    int32_t *pre = a.pre + (int64_t)blockIdx.x * (n + 1);
+    const int64_t rg = (int64_t)attempt * a.regtot + a.reg[sp];
+    int32_t *slist = a.slist + rg;
+    int32_t *order = a.order + rg;
+    int32_t *pre = a.pre + rg + sp + (int64_t)attempt * a.nsub;
 
     // ---- S in ascending order, its weight; reset marks and claims
     int32_t size = 0;
     int64_t cs = 0;
-    for (int32_t v0 = 0; v0 < n; v0 += kBB) {
+    for (int32_t v0 = vlo; v0 < vhi; v0 += kBB) {
         const int32_t v = v0 + threadIdx.x;
-        const bool in = v < n && blk[v] == base;
+        const bool in = v < vhi && blk[v] == base;
         int32_t tot;
         const int32_t ex = block_excl_scan<kBB>((int32_t)in, t32, &tot);
         if (in) {
@@ -97,7 +106,7 @@ __global__ __launch_bounds__(kBB) void k_bisect(BisectArgs a) {
     if (size == 0) return;
     const int64_t q = cs / ks, rm = cs % ks;
     const int64_t target = q * kl + (rm * kl + ks - 1) / ks;
-    const uint64_t h = splitmix(splitmix(splitmix(splitmix(a.seed) ^ (uint64_t)attempt) ^ (uint64_t)base) ^
+    const uint64_t h = splitmix(splitmix(splitmix(splitmix(a.seed) ^ (uint64_t)attempt) ^ (uint64_t)lbase) ^
                                 (uint64_t)ks);
     const int32_t start = slist[h % (uint64_t)size];
     __syncthreads();
@@ -195,15 +204,17 @@ __global__ __launch_bounds__(kBB) void k_bisect(BisectArgs a) {
     for (int32_t p = threadIdx.x; p <= stop; p += kBB) blk[order[p]] = base;
 }
 
-__global__ void k_init_blk(int32_t n, int32_t attempts, const int32_t *xadj, bool skip_isolated, int32_t *blk) {
+__global__ void k_init_blk(int32_t n, int32_t attempts, const int32_t *xadj, bool skip_isolated, const int32_t *gid,
+                           const int32_t *kbase, int32_t *blk) {
     const int64_t N = (int64_t)n * attempts;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t v = (int32_t)(i % n);
-        blk[i] = (skip_isolated && xadj[v + 1] == xadj[v]) ? -1 : 0;
+        blk[i] = (skip_isolated && xadj[v + 1] == xadj[v]) ? -1 : kbase[gid[v]];
     }
 }
 
-__global__ void k_union(int32_t n, int32_t nnz, int32_t attempts, int32_t k, const int32_t *xadj,
+// Disjoint union of the tries: try c owns vertices c*n.. and labels c*Ktot..
+__global__ void k_union(int32_t n, int32_t nnz, int32_t attempts, int32_t ktot, const int32_t *xadj,
                         const int32_t *adjncy, const int32_t *adjwgt, const int32_t *vwgt, const int32_t *blk,
                         int32_t *uxadj, int32_t *uadj, int32_t *uw, int32_t *uvw, int32_t *ulab) {
     const int64_t NV = (int64_t)n * attempts, NE = (int64_t)nnz * attempts;
@@ -217,7 +228,7 @@ __global__ void k_union(int32_t n, int32_t nnz, int32_t attempts, int32_t k, con
         uxadj[i] = (int32_t)(c * nnz + xadj[v]);
         if (uvw) uvw[i] = vwgt[v];
         const int32_t b = blk[i];
-        ulab[i] = b >= 0 ? (int32_t)(c * k + b) : -1;
+        ulab[i] = b >= 0 ? (int32_t)(c * ktot + b) : -1;
     }
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < NE; e += stride) {
         const int64_t c = e / nnz, ee = e % nnz;
@@ -226,29 +237,50 @@ __global__ void k_union(int32_t n, int32_t nnz, int32_t attempts, int32_t k, con
     }
 }
 
-// One workgroup per try: while a block exceeds lmax apply the move (v, t) of
-// maximum gain conn(v,t) - conn(v,P(v)) with v in an overloaded block and
-// B[t] + c(v) <= lmax; ties -> lowest v, then lowest t.
+// capacity of union label c*Ktot + kbase[g] + b is lmax[g]
+__global__ void k_label_caps(int32_t attempts, int32_t ktot, int32_t G, const int32_t *kbase, const int64_t *lmax,
+                             int64_t *cap) {
+    const int64_t N = (int64_t)attempts * ktot;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t b = (int32_t)(i % ktot);
+        int32_t lo = 0, hi = G - 1;  // graph with kbase[g] <= b < kbase[g+1]
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (kbase[mid] <= b) lo = mid;
+            else hi = mid - 1;
+        }
+        cap[i] = lmax[lo];
+    }
+}
+
+// One workgroup per (try, graph): while a block exceeds lmax apply the move
+// (v, t) of maximum gain conn(v,t) - conn(v,P(v)) with v in an overloaded
+// block and B[t] + c(v) <= lmax; ties -> lowest v, then lowest t.
 constexpr int kRB = 512;
-__global__ __launch_bounds__(kRB) void k_rebalance(int32_t n, int32_t k, int64_t lmax, const int32_t *xadj,
+__global__ __launch_bounds__(kRB) void k_rebalance(int32_t n, int32_t G, int32_t ktot, const int32_t *voff,
+                                                   const int32_t *kbase, const int64_t *lmaxv, const int32_t *xadj,
                                                    const int32_t *adjncy, const int32_t *adjwgt,
-                                                   const int32_t *vwgt, int32_t *ulab, int32_t *balanced) {
+                                                   const int32_t *vwgt, int32_t *ulab, int32_t *balanced,
+                                                   int32_t kmax) {
     extern __shared__ int64_t dyn[];
     constexpr int NW = kRB / kWave;
-    int64_t *B = dyn;              // [k]
-    int64_t *conn = dyn + k;       // [NW][k]
+    const int a = blockIdx.x / G, gr = blockIdx.x % G;
+    const int32_t k = kbase[gr + 1] - kbase[gr];
+    const int64_t lmax = lmaxv[gr];
+    int64_t *B = dyn;                 // [k]
+    int64_t *conn = dyn + kmax;       // [NW][kmax]
     __shared__ int64_t bg[NW];
     __shared__ int32_t bv[NW], bt[NW];
     __shared__ int32_t s_over;
-    const int a = blockIdx.x;
-    const int32_t *ux = xadj;  // union graph: copy a is vertices [a*n, (a+1)*n)
+    const int32_t *ux = xadj;  // union graph: try a is vertices [a*n, (a+1)*n)
     int32_t *lab = ulab;
-    const int32_t v0 = a * n, l0 = a * k;
+    const int32_t v0 = a * n + voff[gr], nv = voff[gr + 1] - voff[gr];
+    const int32_t l0 = a * ktot + kbase[gr];
     const int lane = lane_id(), w = threadIdx.x / kWave;
-    int64_t *cw = conn + (int64_t)w * k;
+    int64_t *cw = conn + (int64_t)w * kmax;
     for (int b = threadIdx.x; b < k; b += kRB) B[b] = 0;
     __syncthreads();
-    for (int32_t v = threadIdx.x; v < n; v += kRB) {
+    for (int32_t v = threadIdx.x; v < nv; v += kRB) {
         const int32_t L = lab[v0 + v];
         if (L >= 0) atomicAdd((unsigned long long *)&B[L - l0], (unsigned long long)vw(vwgt, v0 + v));
     }
@@ -261,12 +293,12 @@ __global__ __launch_bounds__(kRB) void k_rebalance(int32_t n, int32_t k, int64_t
         }
         __syncthreads();
         if (!s_over) {
-            if (threadIdx.x == 0) balanced[a] = 1;
+            if (threadIdx.x == 0) balanced[blockIdx.x] = 1;
             return;
         }
         int64_t best_g = LLONG_MIN;
         int32_t best_v = INT_MAX, best_t = INT_MAX;
-        for (int32_t v = w; v < n; v += NW) {
+        for (int32_t v = w; v < nv; v += NW) {
             const int32_t L = lab[v0 + v];
             if (L < 0 || B[L - l0] <= lmax) continue;  // wave-uniform
             const int32_t pv = L - l0;
@@ -329,41 +361,59 @@ __global__ __launch_bounds__(kRB) void k_rebalance(int32_t n, int32_t k, int64_t
         }
         __syncthreads();
         if (s_over < 0) {
-            if (threadIdx.x == 0) balanced[a] = 0;
+            if (threadIdx.x == 0) balanced[blockIdx.x] = 0;
             return;
         }
     }
 }
 
-__global__ void k_copy_cut(int32_t n, int32_t attempts, const int32_t *uxadj, const int32_t *uadj,
-                           const int32_t *uw, const int32_t *ulab, unsigned long long *cuts) {
+// cut of every (try, graph): cuts[try * G + graph]
+__global__ void k_copy_cut(int32_t n, int32_t attempts, int32_t G, const int32_t *gid, const int32_t *uxadj,
+                           const int32_t *uadj, const int32_t *uw, const int32_t *ulab, unsigned long long *cuts) {
     const int64_t NV = (int64_t)n * attempts;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < NV; i += (int64_t)gridDim.x * blockDim.x) {
         int64_t s = 0;
         const int32_t L = ulab[i];
         for (int32_t e = uxadj[i]; e < uxadj[i + 1]; e++)
             if (ulab[uadj[e]] != L) s += uw ? uw[e] : 1;
-        if (s) atomicAdd(&cuts[i / n], (unsigned long long)s);
+        if (s) atomicAdd(&cuts[(i / n) * G + gid[i % n]], (unsigned long long)s);
     }
 }
 
-__global__ void k_pick(int32_t n, int32_t k, int32_t attempts, const unsigned long long *cuts,
-                       const int32_t *balanced, const int32_t *ulab, int32_t *part, int32_t *chosen) {
-    __shared__ int32_t best;
-    if (threadIdx.x == 0) {
+// best try per graph by (imbalanced, cut, try index)
+__global__ void k_pick_tries(int32_t G, int32_t attempts, const unsigned long long *cuts, const int32_t *balanced,
+                             int32_t *chosen) {
+    for (int32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < G; g += gridDim.x * blockDim.x) {
         int32_t b = 0;
         for (int a = 1; a < attempts; a++) {
-            const bool better = (balanced[a] && !balanced[b]) || (balanced[a] == balanced[b] && cuts[a] < cuts[b]);
+            const int64_t ia = (int64_t)a * G + g, ib = (int64_t)b * G + g;
+            const bool better = (balanced[ia] && !balanced[ib]) || (balanced[ia] == balanced[ib] && cuts[ia] < cuts[ib]);
             if (better) b = a;
         }
-        best = b;
-        if (chosen) *chosen = b;
+        chosen[g] = b;
     }
-    __syncthreads();
-    const int32_t b = best;
+}
+
+__global__ void k_pick_write(int32_t n, int32_t ktot, const int32_t *gid, const int32_t *chosen, const int32_t *ulab,
+                             int32_t *part) {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t b = chosen[gid[v]];
         const int32_t L = ulab[(int64_t)b * n + v];
-        part[v] = L >= 0 ? L - b * k : -1;
+        part[v] = L >= 0 ? L - b * ktot : -1;
+    }
+}
+
+// out[v] = q with first[q] <= v < first[q+1] (binary search per vertex)
+__global__ void k_fill_range(int32_t *out, const int32_t *first, int32_t G) {
+    const int32_t n = first[G];
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        int32_t lo = 0, hi = G - 1;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (first[mid] <= v) lo = mid;
+            else hi = mid - 1;
+        }
+        out[v] = lo;
     }
 }
 
@@ -471,71 +521,94 @@ __global__ void k_iso_serial(const int32_t *iso, const int32_t *niso, const int6
 
 }  // namespace
 
-int initial_partition(const DevGraph &g, bool skip_isolated, int32_t k, int64_t lmax, uint64_t seed,
-                      int32_t attempts, int32_t rounds_refine, int32_t dir_alternate, bool wide, int32_t *part,
-                      int32_t *chosen_host, Scratch &sc) {
+int initial_partition_batch(const DevGraph &g, bool skip_isolated, const BatchInfo &bi, uint64_t seed,
+                            int32_t attempts, int32_t rounds_refine, int32_t dir_alternate, bool wide, int32_t *part,
+                            Scratch &sc) {
     hipStream_t s = sc.stream();
-    const int32_t n = g.n, nnz = g.nnz;
+    const int32_t n = g.n, nnz = g.nnz, G = bi.G;
     if (n == 0) return GP_OK;
-    if ((int64_t)n * attempts >= INT_MAX || (int64_t)nnz * attempts >= INT_MAX || (int64_t)k * attempts >= INT_MAX) {
+    const int32_t ktot = bi.kbase[G];
+    int32_t kmax = 1;
+    for (int32_t q = 0; q < G; q++) kmax = std::max(kmax, bi.k[q]);
+    if ((int64_t)n * attempts >= INT_MAX || (int64_t)nnz * attempts >= INT_MAX ||
+        (int64_t)ktot * attempts >= INT_MAX) {
         set_error("initial partition: coarsest graph times attempts exceeds int32 indexing");
         return GP_ERR_OVERFLOW;
     }
-    if (k > 2048) {
+    if (kmax > 2048) {
         set_error("initial partition: k > 2048 is not supported by the rebalance kernel");
         return GP_ERR_ARG;
     }
-    // ---- recursion tree of (base, k_S) per depth (depends only on k)
-    std::vector<std::vector<std::pair<int32_t, int32_t>>> depth;
-    {
-        std::vector<std::pair<int32_t, int32_t>> cur{{0, k}};
-        while (!cur.empty()) {
-            std::vector<std::pair<int32_t, int32_t>> work, next;
+    // ---- recursion trees of (graph, local base, k_S) per depth (each depends only on k_g)
+    std::vector<std::vector<std::array<int32_t, 3>>> depth;
+    for (int32_t q = 0; q < G; q++) {
+        std::vector<std::pair<int32_t, int32_t>> cur{{0, bi.k[q]}};
+        for (size_t d = 0; !cur.empty(); d++) {
+            std::vector<std::pair<int32_t, int32_t>> next;
             for (auto &p : cur)
                 if (p.second > 1) {
-                    work.push_back(p);
+                    if (depth.size() <= d) depth.resize(d + 1);
+                    depth[d].push_back({q, p.first, p.second});
                     const int32_t kl = (p.second + 1) / 2;
                     next.push_back({p.first, kl});
                     next.push_back({p.first + kl, p.second - kl});
                 }
-            if (!work.empty()) depth.push_back(work);
             cur = next;
         }
     }
+    // per-workgroup regions sized by the subproblem's graph
+    int64_t regmax = 1;
     size_t maxsub = 1;
-    for (auto &d : depth) maxsub = d.size() > maxsub ? d.size() : maxsub;
+    for (auto &d : depth) {
+        int64_t t = 0;
+        for (auto &e : d) t += bi.voff[e[0] + 1] - bi.voff[e[0]];
+        regmax = std::max(regmax, t);
+        maxsub = std::max(maxsub, d.size());
+    }
     int32_t *blk = nullptr, *mark = nullptr, *claim = nullptr, *slist = nullptr, *order = nullptr, *pre = nullptr,
-            *sb = nullptr, *sk = nullptr;
-    const int64_t nb = (int64_t)maxsub * attempts;
+            *sg = nullptr, *sb = nullptr, *sk = nullptr;
+    int64_t *reg = nullptr;
     GP_TRY(sc.alloc(&blk, (size_t)n * attempts));
     GP_TRY(sc.alloc(&mark, (size_t)n * attempts));
     GP_TRY(sc.alloc(&claim, (size_t)n * attempts));
-    GP_TRY(sc.alloc(&slist, (size_t)n * nb));
-    GP_TRY(sc.alloc(&order, (size_t)n * nb));
-    GP_TRY(sc.alloc(&pre, (size_t)(n + 1) * nb));
+    GP_TRY(sc.alloc(&slist, (size_t)regmax * attempts));
+    GP_TRY(sc.alloc(&order, (size_t)regmax * attempts));
+    GP_TRY(sc.alloc(&pre, (size_t)(regmax + maxsub) * attempts));
+    GP_TRY(sc.alloc(&sg, maxsub));
     GP_TRY(sc.alloc(&sb, maxsub));
     GP_TRY(sc.alloc(&sk, maxsub));
+    GP_TRY(sc.alloc(&reg, maxsub));
     hipLaunchKernelGGL(k_init_blk, dim3(grid_for((int64_t)n * attempts, 256, 65536)), dim3(256), 0, s, n, attempts,
-                       g.xadj, skip_isolated, blk);
+                       g.xadj, skip_isolated, bi.d_gid, bi.d_kbase, blk);
     GP_LAUNCH_CHECK();
-    std::vector<int32_t> hb, hk;
+    std::vector<int32_t> hg, hb, hk;
+    std::vector<int64_t> hr;
     for (auto &d : depth) {
+        hg.clear();
         hb.clear();
         hk.clear();
-        for (auto &p : d) {
-            hb.push_back(p.first);
-            hk.push_back(p.second);
+        hr.clear();
+        int64_t off = 0;
+        for (auto &e : d) {
+            hg.push_back(e[0]);
+            hb.push_back(e[1]);
+            hk.push_back(e[2]);
+            hr.push_back(off);
+            off += bi.voff[e[0] + 1] - bi.voff[e[0]];
         }
+        GP_HIP(hipMemcpyAsync(sg, hg.data(), sizeof(int32_t) * hg.size(), hipMemcpyHostToDevice, s));
         GP_HIP(hipMemcpyAsync(sb, hb.data(), sizeof(int32_t) * hb.size(), hipMemcpyHostToDevice, s));
         GP_HIP(hipMemcpyAsync(sk, hk.data(), sizeof(int32_t) * hk.size(), hipMemcpyHostToDevice, s));
-        BisectArgs a{n, g.xadj, g.adjncy, g.vwgt, blk, mark, claim, slist, order, pre, sb, sk, (int32_t)d.size(), seed};
+        GP_HIP(hipMemcpyAsync(reg, hr.data(), sizeof(int64_t) * hr.size(), hipMemcpyHostToDevice, s));
+        BisectArgs a{n,    g.xadj, g.adjncy, g.vwgt, blk,        mark,       claim,           slist,
+                     order, pre,   reg,      off,    sg,   sb, sk, bi.d_voff, bi.d_kbase, (int32_t)d.size(), seed};
         hipLaunchKernelGGL(k_bisect, dim3((unsigned)(d.size() * attempts)), dim3(kBB), 0, s, a);
         GP_LAUNCH_CHECK();
         // host vectors are reused next depth: make sure the copies have been consumed
         GP_HIP(hipStreamSynchronize(s));
     }
 
-    // ---- refine all tries at once on the disjoint union
+    // ---- refine all tries of all graphs at once on the disjoint union
     const int32_t NV = n * attempts, NE = nnz * attempts;
     int32_t *ux = nullptr, *ua = nullptr, *uw = nullptr, *uv = nullptr, *ul = nullptr;
     GP_TRY(sc.alloc(&ux, (size_t)NV + 1));
@@ -543,7 +616,7 @@ int initial_partition(const DevGraph &g, bool skip_isolated, int32_t k, int64_t 
     if (g.adjwgt) GP_TRY(sc.alloc(&uw, NE));
     if (g.vwgt) GP_TRY(sc.alloc(&uv, NV));
     GP_TRY(sc.alloc(&ul, NV));
-    hipLaunchKernelGGL(k_union, dim3(grid_for((int64_t)NE + NV, 256, 65536)), dim3(256), 0, s, n, nnz, attempts, k,
+    hipLaunchKernelGGL(k_union, dim3(grid_for((int64_t)NE + NV, 256, 65536)), dim3(256), 0, s, n, nnz, attempts, ktot,
                        g.xadj, g.adjncy, g.adjwgt, g.vwgt, blk, ux, ua, uw, uv, ul);
     GP_LAUNCH_CHECK();
     DevGraph ug;
@@ -553,33 +626,72 @@ int initial_partition(const DevGraph &g, bool skip_isolated, int32_t k, int64_t 
     ug.adjncy = ua;
     ug.adjwgt = uw;
     ug.vwgt = uv;
-    int64_t *W = nullptr;
-    GP_TRY(sc.alloc(&W, (size_t)k * attempts));
-    GP_TRY(label_weights(ug, ul, W, k * attempts, sc));
-    GP_TRY(lp_run(ug, ul, W, k * attempts, lmax, rounds_refine, dir_alternate, wide, nullptr, sc));
+    const int32_t NL = ktot * attempts;
+    int64_t *W = nullptr, *cap = nullptr;
+    GP_TRY(sc.alloc(&W, NL));
+    GP_TRY(label_weights(ug, ul, W, NL, sc));
+    if (G > 1) {
+        GP_TRY(sc.alloc(&cap, NL));
+        hipLaunchKernelGGL(k_label_caps, dim3(grid_for(NL, 256, 4096)), dim3(256), 0, s, attempts, ktot, G,
+                           bi.d_kbase, bi.d_lmax, cap);
+        GP_LAUNCH_CHECK();
+    }
+    GP_TRY(lp_run(ug, ul, W, NL, bi.lmax[0], rounds_refine, dir_alternate, wide, nullptr, sc, cap));
 
-    // ---- rebalance each try, pick the best
+    // ---- rebalance each (try, graph), pick the best try per graph
     int32_t *bal = nullptr, *ch = nullptr;
     unsigned long long *cuts = nullptr;
-    GP_TRY(sc.alloc(&bal, attempts));
-    GP_TRY(sc.alloc(&cuts, attempts));
-    GP_TRY(sc.alloc(&ch, 1));
-    GP_HIP(hipMemsetAsync(cuts, 0, sizeof(unsigned long long) * attempts, s));
-    const size_t dyn = sizeof(int64_t) * (size_t)k * (1 + kRB / kWave);
+    const int64_t TG = (int64_t)attempts * G;
+    GP_TRY(sc.alloc(&bal, TG));
+    GP_TRY(sc.alloc(&cuts, TG));
+    GP_TRY(sc.alloc(&ch, G));
+    GP_HIP(hipMemsetAsync(cuts, 0, sizeof(unsigned long long) * TG, s));
+    const size_t dyn = sizeof(int64_t) * (size_t)kmax * (1 + kRB / kWave);
     GP_HIP(hipFuncSetAttribute((const void *)k_rebalance, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
-    hipLaunchKernelGGL(k_rebalance, dim3(attempts), dim3(kRB), dyn, s, n, k, lmax, ux, ua, uw, uv, ul, bal);
+    hipLaunchKernelGGL(k_rebalance, dim3((unsigned)TG), dim3(kRB), dyn, s, n, G, ktot, bi.d_voff, bi.d_kbase,
+                       bi.d_lmax, ux, ua, uw, uv, ul, bal, kmax);
     GP_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_copy_cut, dim3(grid_for(NV, 256, 65536)), dim3(256), 0, s, n, attempts, ux, ua, uw, ul,
-                       cuts);
+    hipLaunchKernelGGL(k_copy_cut, dim3(grid_for(NV, 256, 65536)), dim3(256), 0, s, n, attempts, G, bi.d_gid, ux, ua,
+                       uw, ul, cuts);
     GP_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_pick, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, n, k, attempts, cuts, bal, ul, part,
-                       ch);
+    hipLaunchKernelGGL(k_pick_tries, dim3(grid_for(G, 256, 1024)), dim3(256), 0, s, G, attempts, cuts, bal, ch);
+    hipLaunchKernelGGL(k_pick_write, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, n, ktot, bi.d_gid, ch, ul, part);
     GP_LAUNCH_CHECK();
-    if (chosen_host) {
-        GP_HIP(hipMemcpyAsync(chosen_host, ch, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        GP_HIP(hipStreamSynchronize(s));
-    }
     return GP_OK;
+}
+
+int graph_ids(int32_t G, int32_t n, const int32_t *d_voff, int32_t *gid, hipStream_t s) {
+    if (n <= 0) return GP_OK;
+    hipLaunchKernelGGL(k_fill_range, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, gid, d_voff, G);
+    GP_LAUNCH_CHECK();
+    return GP_OK;
+}
+
+int initial_partition(const DevGraph &g, bool skip_isolated, int32_t k, int64_t lmax, uint64_t seed,
+                      int32_t attempts, int32_t rounds_refine, int32_t dir_alternate, bool wide, int32_t *part,
+                      Scratch &sc) {
+    if (g.n == 0) return GP_OK;
+    BatchInfo bi;
+    bi.G = 1;
+    bi.voff = {0, g.n};
+    bi.k = {k};
+    bi.kbase = {0, k};
+    bi.lmax = {lmax};
+    int32_t *dv = nullptr, *dk = nullptr, *gid = nullptr;
+    int64_t *dl = nullptr;
+    GP_TRY(sc.alloc(&dv, 2));
+    GP_TRY(sc.alloc(&dk, 2));
+    GP_TRY(sc.alloc(&dl, 1));
+    GP_TRY(sc.alloc(&gid, g.n));
+    GP_HIP(hipMemcpyAsync(dv, bi.voff.data(), sizeof(int32_t) * 2, hipMemcpyHostToDevice, sc.stream()));
+    GP_HIP(hipMemcpyAsync(dk, bi.kbase.data(), sizeof(int32_t) * 2, hipMemcpyHostToDevice, sc.stream()));
+    GP_HIP(hipMemcpyAsync(dl, bi.lmax.data(), sizeof(int64_t), hipMemcpyHostToDevice, sc.stream()));
+    GP_HIP(hipMemsetAsync(gid, 0, sizeof(int32_t) * (size_t)g.n, sc.stream()));
+    bi.d_voff = dv;
+    bi.d_kbase = dk;
+    bi.d_lmax = dl;
+    bi.d_gid = gid;
+    return initial_partition_batch(g, skip_isolated, bi, seed, attempts, rounds_refine, dir_alternate, wide, part, sc);
 }
 
 int fill_isolated(const DevGraph &g, int32_t k, int32_t *part, const int64_t *B, int32_t *niso_host, Scratch &sc) {

@@ -1,16 +1,36 @@
 // initpart.hpp — initial partitioning and isolated-vertex placement (internal).
 #pragma once
+#include <vector>
+
 #include "lp.hpp"
 
 namespace gp {
 
+// G graphs side by side in one union graph: graph q owns vertices
+// [voff[q], voff[q+1]) and blocks [kbase[q], kbase[q+1]) of k[q] blocks.
+struct BatchInfo {
+    int32_t G = 0;
+    std::vector<int32_t> voff, k, kbase;  // host copies
+    std::vector<int64_t> lmax;
+    const int32_t *d_voff = nullptr, *d_kbase = nullptr, *d_gid = nullptr;  // device; gid[v] = graph of v
+    const int64_t *d_lmax = nullptr;
+};
+
 // Best of `attempts` tries (recursive BFS bisection -> LP refinement ->
-// greedy rebalance) on g. part: [n] device output in [0, k) (-1 for vertices
-// left out when skip_isolated is set). chosen_host (may be null) receives the
-// index of the kept try.
+// greedy rebalance) for every graph of the batch. part: [n] device output,
+// global block ids kbase[q] + b (-1 for vertices left out when
+// skip_isolated is set).
+int initial_partition_batch(const DevGraph &g, bool skip_isolated, const BatchInfo &bi, uint64_t seed,
+                            int32_t attempts, int32_t rounds_refine, int32_t dir_alternate, bool wide, int32_t *part,
+                            Scratch &sc);
+
+// The same for one graph (blocks [0, k)).
 int initial_partition(const DevGraph &g, bool skip_isolated, int32_t k, int64_t lmax, uint64_t seed,
                       int32_t attempts, int32_t rounds_refine, int32_t dir_alternate, bool wide, int32_t *part,
-                      int32_t *chosen_host, Scratch &sc);
+                      Scratch &sc);
+
+// gid[v] = q for v in [voff[q], voff[q+1]) (device arrays).
+int graph_ids(int32_t G, int32_t n, const int32_t *d_voff, int32_t *gid, hipStream_t s);
 
 // Vertices without neighbours, in ascending id, each into the block that is
 // lightest at that moment (ties -> lowest block id), starting from block

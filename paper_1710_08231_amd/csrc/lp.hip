@@ -18,6 +18,7 @@
 // No host synchronisation happens between rounds; after the stop flag is set
 // every later kernel of the call returns immediately.
 #include <climits>
+#include <cstdlib>
 #include <string>
 
 #include "lp.hpp"
@@ -32,10 +33,19 @@ struct LPArgs {
     const int32_t *labels;
     const int64_t *W;
     int64_t U;
-    int32_t dirmode;  // 0: any direction, 1: only smaller labels, 2: only larger labels
+    int32_t dir_alternate;  // even rounds: only smaller labels; odd rounds: only larger labels
     int32_t *prop;
     const int32_t *done;
+    const int32_t *round;  // device round counter (rounds replay one captured launch sequence)
+    const int64_t *capv;   // optional per-label capacity (batched graphs); null: every label has U
 };
+
+__device__ __forceinline__ int64_t capof(const LPArgs &a, int32_t L) { return a.capv ? a.capv[L] : a.U; }
+
+// 0: any direction, 1: only smaller labels, 2: only larger labels
+__device__ __forceinline__ int32_t cur_dirmode(const LPArgs &a) {
+    return a.dir_alternate ? (((*a.round) & 1) == 0 ? 1 : 2) : 0;
+}
 
 __device__ __forceinline__ bool dir_ok(int32_t L, int32_t own, int32_t dirmode) {
     return dirmode == 0 || (dirmode == 1 ? (L < own) : (L > own));
@@ -147,6 +157,7 @@ template <int GL, int TBL, typename AccT>
 __global__ __launch_bounds__(kPropBlock) void k_propose_group(LPArgs a, const int32_t *__restrict__ verts,
                                                               int32_t count) {
     if (*a.done) return;
+    const int32_t dmode = cur_dirmode(a);
     constexpr int GPW = kWave / GL;
     constexpr int NW = kPropBlock / kWave;
     constexpr int LOG2 = __builtin_ctz(TBL);
@@ -180,11 +191,11 @@ __global__ __launch_bounds__(kPropBlock) void k_propose_group(LPArgs a, const in
             const int32_t L0 = u0 >= 0 ? a.labels[u0] : -1, L1 = u1 >= 0 ? a.labels[u1] : -1;
             if (u0 >= 0) {
                 if (L0 == own) oc += w0;
-                else if (dir_ok(L0, own, a.dirmode)) tbl_insert<AccT>(key, val, TBL - 1, LOG2, L0, w0);
+                else if (dir_ok(L0, own, dmode)) tbl_insert<AccT>(key, val, TBL - 1, LOG2, L0, w0);
             }
             if (u1 >= 0) {
                 if (L1 == own) oc += w1;
-                else if (dir_ok(L1, own, a.dirmode)) tbl_insert<AccT>(key, val, TBL - 1, LOG2, L1, w1);
+                else if (dir_ok(L1, own, dmode)) tbl_insert<AccT>(key, val, TBL - 1, LOG2, L1, w1);
             }
         }
         wave_sync();
@@ -203,7 +214,7 @@ __global__ __launch_bounds__(kPropBlock) void k_propose_group(LPArgs a, const in
         int32_t target = -1;
         bool need2 = false;
         if (valid && bl != INT_MAX && bc > oc) {
-            if (a.W[bl] + cv <= a.U) target = bl;
+            if (a.W[bl] + cv <= capof(a, bl)) target = bl;
             else need2 = true;
         }
         if (__ballot(need2)) {
@@ -212,7 +223,7 @@ __global__ __launch_bounds__(kPropBlock) void k_propose_group(LPArgs a, const in
             if (need2) {
                 for (int i = gl; i < TBL; i += GL) {
                     const int32_t L = key[i];
-                    if (L >= 0 && better(val[i], L, bc2, bl2) && a.W[L] + cv <= a.U) {
+                    if (L >= 0 && better(val[i], L, bc2, bl2) && a.W[L] + cv <= capof(a, L)) {
                         bc2 = val[i];
                         bl2 = L;
                     }
@@ -237,6 +248,7 @@ template <int BLOCK, int TBL, typename AccT>
 __global__ __launch_bounds__(BLOCK) void k_propose_block(LPArgs a, const int32_t *__restrict__ verts,
                                                          int32_t count) {
     if (*a.done) return;
+    const int32_t dmode = cur_dirmode(a);
     constexpr int NW = BLOCK / kWave;
     constexpr int U4 = 4;
     __shared__ int32_t key[TBL];
@@ -271,7 +283,7 @@ __global__ __launch_bounds__(BLOCK) void k_propose_block(LPArgs a, const int32_t
             for (int j = 0; j < U4; j++) {
                 if (u[j] < 0) continue;
                 if (L[j] == own) oc += wv[j];
-                else if (dir_ok(L[j], own, a.dirmode)) tbl_insert<AccT>(key, val, cap - 1, lg, L[j], wv[j]);
+                else if (dir_ok(L[j], own, dmode)) tbl_insert<AccT>(key, val, cap - 1, lg, L[j], wv[j]);
             }
         }
         __syncthreads();
@@ -289,14 +301,14 @@ __global__ __launch_bounds__(BLOCK) void k_propose_block(LPArgs a, const int32_t
         const int64_t cv = vweight(a.vwgt, v);
         int32_t target = -1;
         if (bl != INT_MAX && bc > oc) {
-            if (a.W[bl] + cv <= a.U) {
+            if (a.W[bl] + cv <= capof(a, bl)) {
                 target = bl;
             } else {
                 AccT bc2 = 0;
                 int32_t bl2 = INT_MAX;
                 for (uint32_t i = threadIdx.x; i < cap; i += BLOCK) {
                     const int32_t L = key[i];
-                    if (L >= 0 && better(val[i], L, bc2, bl2) && a.W[L] + cv <= a.U) {
+                    if (L >= 0 && better(val[i], L, bc2, bl2) && a.W[L] + cv <= capof(a, L)) {
                         bc2 = val[i];
                         bl2 = L;
                     }
@@ -321,6 +333,7 @@ __global__ __launch_bounds__(BLOCK) void k_propose_hub(LPArgs a, const int32_t *
                                                        int32_t count, const int64_t *hoff,
                                                        const int32_t *hlog, int32_t *gkey, AccT *gval) {
     if (*a.done) return;
+    const int32_t dmode = cur_dirmode(a);
     constexpr int NW = BLOCK / kWave;
     __shared__ AccT tc[NW + 1];
     __shared__ int32_t tl[NW + 1];
@@ -338,7 +351,7 @@ __global__ __launch_bounds__(BLOCK) void k_propose_hub(LPArgs a, const int32_t *
             const AccT wgt = a.adjwgt ? (AccT)a.adjwgt[e] : (AccT)1;
             const int32_t L = a.labels[u];
             if (L == own) oc += wgt;
-            else if (dir_ok(L, own, a.dirmode)) tbl_insert_global<AccT>(key, val, cap - 1, lg, L, wgt);
+            else if (dir_ok(L, own, dmode)) tbl_insert_global<AccT>(key, val, cap - 1, lg, L, wgt);
         }
         __threadfence_block();
         __syncthreads();
@@ -357,7 +370,7 @@ __global__ __launch_bounds__(BLOCK) void k_propose_hub(LPArgs a, const int32_t *
         const int64_t cv = vweight(a.vwgt, v);
         int32_t target = -1;
         if (bl != INT_MAX && bc > oc) {
-            if (a.W[bl] + cv <= a.U) {
+            if (a.W[bl] + cv <= capof(a, bl)) {
                 target = bl;
             } else {
                 AccT bc2 = 0;
@@ -365,7 +378,7 @@ __global__ __launch_bounds__(BLOCK) void k_propose_hub(LPArgs a, const int32_t *
                 for (uint32_t i = threadIdx.x; i < cap; i += BLOCK) {
                     const int32_t L = ld_agent(&key[i]);
                     const AccT c = L >= 0 ? ld_agent(&val[i]) : AccT(0);
-                    if (L >= 0 && better(c, L, bc2, bl2) && a.W[L] + cv <= a.U) {
+                    if (L >= 0 && better(c, L, bc2, bl2) && a.W[L] + cv <= capof(a, L)) {
                         bc2 = c;
                         bl2 = L;
                     }
@@ -417,6 +430,7 @@ __device__ __forceinline__ unsigned long long pack_best(int32_t c, int32_t L) {
 
 __global__ __launch_bounds__(256) void k_hub_insert(LPArgs a, HubPlan hp) {
     if (*a.done) return;
+    const int32_t dmode = cur_dirmode(a);
     __shared__ int32_t tmp[256 / kWave + 1];
     const int32_t h = hp.chunk_hub[blockIdx.x];
     const int32_t v = hp.hubs[h];
@@ -432,7 +446,7 @@ __global__ __launch_bounds__(256) void k_hub_insert(LPArgs a, HubPlan hp) {
         const int32_t wgt = a.adjwgt ? a.adjwgt[e] : 1;
         const int32_t L = a.labels[u];
         if (L == own) oc += wgt;
-        else if (dir_ok(L, own, a.dirmode)) tbl_insert_global<int32_t>(key, val, (1u << lg) - 1, lg, L, wgt);
+        else if (dir_ok(L, own, dmode)) tbl_insert_global<int32_t>(key, val, (1u << lg) - 1, lg, L, wgt);
     }
     oc = block_sum<256>(oc, tmp);
     if (threadIdx.x == 0 && oc) atomicAdd(&hp.own[h], (unsigned long long)oc);
@@ -443,6 +457,7 @@ __global__ __launch_bounds__(256) void k_hub_insert(LPArgs a, HubPlan hp) {
 template <bool PHASE2>
 __global__ __launch_bounds__(256) void k_hub_scan(LPArgs a, HubPlan hp) {
     if (*a.done) return;
+    const int32_t dmode = cur_dirmode(a);
     __shared__ unsigned long long tmp[256 / kWave + 1];
     const int32_t h = hp.slice_hub[blockIdx.x];
     const uint32_t cap = 1u << hp.tlog[h];
@@ -457,7 +472,7 @@ __global__ __launch_bounds__(256) void k_hub_scan(LPArgs a, HubPlan hp) {
         const int32_t L = ld_agent(&key[i]);
         if (active && L >= 0) {
             const int32_t c = ld_agent(&val[i]);
-            if (!PHASE2 || a.W[L] + cv <= a.U) {
+            if (!PHASE2 || a.W[L] + cv <= capof(a, L)) {
                 const unsigned long long pk = pack_best(c, L);
                 best = pk > best ? pk : best;
             }
@@ -474,6 +489,7 @@ __global__ __launch_bounds__(256) void k_hub_scan(LPArgs a, HubPlan hp) {
 template <bool FINAL>
 __global__ void k_hub_decide(LPArgs a, HubPlan hp, int32_t nh) {
     if (*a.done) return;
+    const int32_t dmode = cur_dirmode(a);
     for (int32_t h = blockIdx.x * blockDim.x + threadIdx.x; h < nh; h += gridDim.x * blockDim.x) {
         const int32_t v = hp.hubs[h];
         const int64_t oc = (int64_t)hp.own[h];
@@ -484,7 +500,7 @@ __global__ void k_hub_decide(LPArgs a, HubPlan hp, int32_t nh) {
                 const int64_t c = (int64_t)(b >> 32);
                 const int32_t L = INT_MAX - (int32_t)(uint32_t)(b & 0xFFFFFFFFull);
                 if (c > oc) {
-                    if (a.W[L] + vweight(a.vwgt, v) <= a.U) target = L;
+                    if (a.W[L] + vweight(a.vwgt, v) <= capof(a, L)) target = L;
                     else need = 1;
                 }
             }
@@ -538,6 +554,7 @@ template <int GL, int KT, typename AccT>
 __global__ __launch_bounds__(kPropBlock) void k_dense_group(LPArgs a, int32_t nlabels,
                                                             const int32_t *__restrict__ verts, int32_t count) {
     if (*a.done) return;
+    const int32_t dmode = cur_dirmode(a);
     constexpr int GPW = kWave / GL;
     constexpr int NW = kPropBlock / kWave;
     __shared__ AccT sval[NW * GPW * KT];
@@ -545,7 +562,8 @@ __global__ __launch_bounds__(kPropBlock) void k_dense_group(LPArgs a, int32_t nl
     const int lane = lane_id(), w = threadIdx.x / kWave;
     const int gl = lane % GL, grp = lane / GL;
     AccT *val = sval + (w * GPW + grp) * KT;
-    for (int i = threadIdx.x; i < KT; i += kPropBlock) sW[i] = i < nlabels ? a.W[i] : (int64_t(1) << 62);
+    // slack of each label at the round start: W - capacity (> 0 never eligible)
+    for (int i = threadIdx.x; i < KT; i += kPropBlock) sW[i] = i < nlabels ? a.W[i] - capof(a, i) : (int64_t(1) << 62);
     for (int i = gl; i < KT; i += GL) val[i] = 0;
     __syncthreads();
     const unsigned b = xcd_block(blockIdx.x, gridDim.x);
@@ -567,11 +585,11 @@ __global__ __launch_bounds__(kPropBlock) void k_dense_group(LPArgs a, int32_t nl
             const int32_t L0 = u0 >= 0 ? a.labels[u0] : -1, L1 = u1 >= 0 ? a.labels[u1] : -1;
             if (u0 >= 0) {
                 if (L0 == own) oc += w0;
-                else if (dir_ok(L0, own, a.dirmode)) lds_add<AccT>(&val[L0], w0);
+                else if (dir_ok(L0, own, dmode)) lds_add<AccT>(&val[L0], w0);
             }
             if (u1 >= 0) {
                 if (L1 == own) oc += w1;
-                else if (dir_ok(L1, own, a.dirmode)) lds_add<AccT>(&val[L1], w1);
+                else if (dir_ok(L1, own, dmode)) lds_add<AccT>(&val[L1], w1);
             }
         }
         wave_sync();
@@ -581,7 +599,7 @@ __global__ __launch_bounds__(kPropBlock) void k_dense_group(LPArgs a, int32_t nl
         int32_t bl = INT_MAX;
         for (int i = gl; i < KT; i += GL) {
             const AccT c = val[i];
-            if (c > 0 && sW[i] + cv <= a.U && better(c, i, bc, bl)) {
+            if (c > 0 && sW[i] + cv <= 0 && better(c, i, bc, bl)) {
                 bc = c;
                 bl = i;
             }
@@ -623,6 +641,7 @@ __device__ __forceinline__ void gadd<int64_t>(int64_t *p, int64_t w) {
 template <int KT, typename AccT>
 __global__ __launch_bounds__(256) void k_dense_chunk(LPArgs a, DenseBig db) {
     if (*a.done) return;
+    const int32_t dmode = cur_dirmode(a);
     constexpr int NW = 256 / kWave;
     __shared__ AccT val[NW][KT];
     __shared__ AccT tmp[NW + 1];
@@ -650,7 +669,7 @@ __global__ __launch_bounds__(256) void k_dense_chunk(LPArgs a, DenseBig db) {
         for (int j = 0; j < 4; j++) {
             if (u[j] < 0) continue;
             if (L[j] == own) oc += wv[j];
-            else if (dir_ok(L[j], own, a.dirmode)) lds_add<AccT>(&val[w][L[j]], wv[j]);
+            else if (dir_ok(L[j], own, dmode)) lds_add<AccT>(&val[w][L[j]], wv[j]);
         }
     }
     __syncthreads();
@@ -667,6 +686,7 @@ __global__ __launch_bounds__(256) void k_dense_chunk(LPArgs a, DenseBig db) {
 template <int KT, typename AccT>
 __global__ __launch_bounds__(256) void k_dense_finish(LPArgs a, DenseBig db, int32_t nlabels) {
     if (*a.done) return;
+    const int32_t dmode = cur_dirmode(a);
     const int w = threadIdx.x / kWave, lane = lane_id();
     const int32_t b = blockIdx.x * (256 / kWave) + w;
     if (b >= db.nbig) return;
@@ -678,7 +698,7 @@ __global__ __launch_bounds__(256) void k_dense_finish(LPArgs a, DenseBig db, int
     int32_t bl = INT_MAX;
     for (int i = lane; i < nlabels; i += kWave) {
         const AccT c = row[i];
-        if (c > 0 && a.W[i] + cv <= a.U && better(c, i, bc, bl)) {
+        if (c > 0 && a.W[i] + cv <= capof(a, i) && better(c, i, bc, bl)) {
             bc = c;
             bl = i;
         }
@@ -766,6 +786,7 @@ __host__ __device__ inline int32_t tier_max(int t, bool wide) {
 struct TierKey {
     const int32_t *xadj;
     const int32_t *active;  // optional: labels array, vertices with label < 0 go to tier 0
+    const uint8_t *frozen;  // optional: vertices with frozen[v] != 0 go to tier 0 (keep their label)
     bool wide;
 };
 
@@ -782,7 +803,7 @@ __global__ void k_tier_keys(TierKey tk, int32_t n, uint32_t *key, int32_t *val, 
          v += (int64_t)gridDim.x * blockDim.x) {
         const int32_t d = tk.xadj[v + 1] - tk.xadj[v];
         int t = 0;
-        if (d > 0 && !(tk.active && tk.active[v] < 0)) {
+        if (d > 0 && !(tk.active && tk.active[v] < 0) && !(tk.frozen && tk.frozen[v])) {
             t = 1;
             while (t < kTiers - 1 && d > tier_max(t, tk.wide)) t++;
         }
@@ -846,8 +867,8 @@ __global__ void k_heads(const uint32_t *mk, const int32_t *nmov, int32_t *headpo
 }
 
 __global__ void k_admit(const uint32_t *mk, const int32_t *mv, const int32_t *nmov, const int32_t *headpos,
-                        const int64_t *S, const int64_t *W, int64_t U, int32_t *labels, int32_t *oldlab,
-                        LPDev *dev) {
+                        const int64_t *S, const int64_t *W, int64_t U, const int64_t *capv, int32_t *labels,
+                        int32_t *oldlab, LPDev *dev) {
     const int32_t n = *nmov;
     int32_t cnt = 0;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
@@ -855,7 +876,7 @@ __global__ void k_admit(const uint32_t *mk, const int32_t *mv, const int32_t *nm
         const int32_t t = (int32_t)mk[p];
         const int32_t h = headpos[t];
         const int64_t pre = S[p] - (h > 0 ? S[h - 1] : 0);
-        if (W[t] + pre <= U) {
+        if (W[t] + pre <= (capv ? capv[t] : U)) {
             const int32_t v = mv[p];
             oldlab[p] = labels[v];
             labels[v] = t;
@@ -912,7 +933,9 @@ __global__ __launch_bounds__(256) void k_apply_w_small(const uint32_t *mk, const
         if (h[i]) atomicAdd((unsigned long long *)&W[i], h[i]);
 }
 
-__global__ void k_round_end(LPDev *dev, int32_t r) {
+__global__ void k_round_end(LPDev *dev) {
+    const int32_t r = dev->round;
+    dev->round = r + 1;
     if (dev->done) return;
     const int32_t m = dev->round_moves;
     dev->rounds_run = r + 1;
@@ -1002,6 +1025,23 @@ int launch_proposals(const LPArgs &a, const int32_t *verts, const int64_t *tstar
     return GP_OK;
 }
 
+// GP_ROUND_GRAPHS=0 disables graph replay of rounds (eager launches every round).
+bool use_round_graphs() {
+    static const bool on = [] {
+        const char *e = std::getenv("GP_ROUND_GRAPHS");
+        return !(e && e[0] == '0');
+    }();
+    return on;
+}
+
+// A library-owned stream (default priority) used only to record launch
+// sequences; recorded graphs are launched on the caller's stream.
+hipStream_t capture_stream() {
+    static thread_local hipStream_t cs = nullptr;
+    if (!cs && hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) cs = nullptr;
+    return cs;
+}
+
 }  // namespace
 
 int total_edge_weight(const DevGraph &g, int64_t *out, Scratch &sc) {
@@ -1032,7 +1072,7 @@ int label_weights(const DevGraph &g, const int32_t *labels, int64_t *W, int32_t 
 }
 
 int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int64_t U, int32_t rounds,
-           int32_t dir_alternate, bool wide, LPOut *out, Scratch &sc) {
+           int32_t dir_alternate, bool wide, LPOut *out, Scratch &sc, const int64_t *capv, const uint8_t *frozen) {
     hipStream_t s = sc.stream();
     const int32_t n = g.n;
     if (n == 0 || rounds == 0) {
@@ -1051,7 +1091,7 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
     GP_TRY(sc.alloc(&tedge, kTiers));
     GP_HIP(hipMemsetAsync(tcnt, 0, sizeof(int32_t) * kTiers, s));
     GP_HIP(hipMemsetAsync(tedge, 0, sizeof(unsigned long long) * kTiers, s));
-    TierKey tk{g.xadj, labels, wide};
+    TierKey tk{g.xadj, labels, frozen, wide};
     hipLaunchKernelGGL(k_tier_keys, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, tk, n, tkey, tval, tcnt, tedge);
     GP_LAUNCH_CHECK();
     GP_TRY((radix_sort<uint32_t, int32_t>(&tkey, &tval, &tkey2, &tval2, n, nullptr, 4, sc)));
@@ -1203,7 +1243,16 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
     GP_HIP(hipMemsetAsync(dev, 0, sizeof(LPDev), s));
     const int key_bits = bits_for(nlabels > 0 ? nlabels - 1 : 0);
 
-    for (int32_t r = 0; r < rounds; r++) {
+    // One round = one fixed launch sequence; the round index lives on the
+    // device. Round 0 runs eagerly (it also sizes every scratch slot), then
+    // the sequence is captured once as a HIP graph and replayed, which removes
+    // the per-kernel host launch cost from every later round.
+    auto emit_round = [&](hipStream_t s) -> int {
+#define RT_TRY(expr)             \
+    do {                         \
+        int _r = (expr);         \
+        if (_r < 0) return _r;   \
+    } while (0)
         LPArgs a;
         a.xadj = g.xadj;
         a.adjncy = g.adjncy;
@@ -1212,17 +1261,19 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
         a.labels = labels;
         a.W = W;
         a.U = U;
-        a.dirmode = dir_alternate ? ((r % 2 == 0) ? 1 : 2) : 0;
+        a.dir_alternate = dir_alternate;
         a.prop = prop;
         a.done = &dev->done;
+        a.round = &dev->round;
+        a.capv = capv;
         if (dense && wide)
-            GP_TRY(launch_dense_any<int64_t>(a, nlabels, verts, tstart, &db, dchunks, s, tbytes));
+            RT_TRY(launch_dense_any<int64_t>(a, nlabels, verts, tstart, &db, dchunks, s, tbytes));
         else if (dense)
-            GP_TRY(launch_dense_any<int32_t>(a, nlabels, verts, tstart, &db, dchunks, s, tbytes));
+            RT_TRY(launch_dense_any<int32_t>(a, nlabels, verts, tstart, &db, dchunks, s, tbytes));
         else if (wide)
-            GP_TRY(launch_proposals<int64_t>(a, verts, tstart, hub_log, hub_off, gkey, (int64_t *)gval, s, tbytes));
+            RT_TRY(launch_proposals<int64_t>(a, verts, tstart, hub_log, hub_off, gkey, (int64_t *)gval, s, tbytes));
         else
-            GP_TRY(launch_proposals<int32_t>(a, verts, tstart, hub_log, hub_off, gkey, (int32_t *)gval, s, tbytes,
+            RT_TRY(launch_proposals<int32_t>(a, verts, tstart, hub_log, hub_off, gkey, (int32_t *)gval, s, tbytes,
                                              split_hubs));
         if (split_hubs) {
             GP_PROF_LAUNCH("k_hub_insert", tbytes[8], s, hipLaunchKernelGGL(k_hub_insert, dim3(nchunks), dim3(256), 0, s, a, hp));
@@ -1233,15 +1284,15 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
             GP_LAUNCH_CHECK();
         }
         // compaction of movers (ascending vertex id)
-        GP_TRY(compact(MoverFlag{prop, &dev->done}, MoverEmit{prop, mk, mv}, n, nullptr, nmov, sc));
+        RT_TRY(compact(MoverFlag{prop, &dev->done}, MoverEmit{prop, mk, mv}, n, nullptr, nmov, sc));
         uint32_t *k1 = mk, *k2 = mk2;
         int32_t *v1 = mv, *v2 = mv2;
-        GP_TRY((radix_sort<uint32_t, int32_t>(&k1, &v1, &k2, &v2, n, nmov, key_bits, sc)));
+        RT_TRY((radix_sort<uint32_t, int32_t>(&k1, &v1, &k2, &v2, n, nmov, key_bits, sc)));
         const unsigned gb = grid_for(n, 256, 8192);
         hipLaunchKernelGGL(k_heads, dim3(gb), dim3(256), 0, s, k1, nmov, headpos);
         GP_LAUNCH_CHECK();
-        GP_TRY((scan<int64_t>(MoverWeight{v1, g.vwgt}, StoreIncl{S}, n, nmov, (int64_t *)nullptr, sc)));
-        hipLaunchKernelGGL(k_admit, dim3(gb), dim3(256), 0, s, k1, v1, nmov, headpos, S, W, U, labels, oldlab,
+        RT_TRY((scan<int64_t>(MoverWeight{v1, g.vwgt}, StoreIncl{S}, n, nmov, (int64_t *)nullptr, sc)));
+        hipLaunchKernelGGL(k_admit, dim3(gb), dim3(256), 0, s, k1, v1, nmov, headpos, S, W, U, capv, labels, oldlab,
                            dev);
         GP_LAUNCH_CHECK();
         if (nlabels <= kSmallLabels)
@@ -1250,8 +1301,36 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
         else
             hipLaunchKernelGGL(k_apply_w, dim3(gb), dim3(256), 0, s, k1, v1, nmov, oldlab, g.vwgt, headpos, S, W);
         GP_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_round_end, dim3(1), dim3(1), 0, s, dev, r);
+        hipLaunchKernelGGL(k_round_end, dim3(1), dim3(1), 0, s, dev);
         GP_LAUNCH_CHECK();
+    #undef RT_TRY
+        return GP_OK;
+    };
+    GP_TRY(emit_round(s));
+    if (rounds > 1) {
+        bool replayed = false;
+        if (use_round_graphs() && !prof_on()) {
+            hipStream_t cs = capture_stream();
+            hipGraph_t graph = nullptr;
+            hipGraphExec_t exec = nullptr;
+            if (cs && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+                sc.set_stream(cs, true);
+                const int rc = emit_round(cs);
+                sc.set_stream(s, false);
+                const hipError_t ec = hipStreamEndCapture(cs, &graph);
+                if (rc == GP_OK && ec == hipSuccess && graph &&
+                    hipGraphInstantiateWithFlags(&exec, graph, 0) == hipSuccess) {
+                    for (int32_t r = 1; r < rounds; r++) GP_HIP(hipGraphLaunch(exec, s));
+                    replayed = true;
+                }
+                (void)hipGetLastError();
+            }
+            if (replayed) GP_HIP(hipStreamSynchronize(s));  // the executable graph is released below
+            if (exec) (void)hipGraphExecDestroy(exec);
+            if (graph) (void)hipGraphDestroy(graph);
+        }
+        if (!replayed)
+            for (int32_t r = 1; r < rounds; r++) GP_TRY(emit_round(s));
     }
     if (out || prof_on()) {
         LPDev h;

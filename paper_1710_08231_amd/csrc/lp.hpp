@@ -12,6 +12,7 @@ struct DevGraph {
 
 // Per-call LP bookkeeping kept on the device so rounds need no host sync.
 struct LPDev {
+    int32_t round;  // index of the round the next launch sequence executes
     int32_t done;
     int32_t rounds_run;
     int32_t prev_moves;
@@ -29,10 +30,14 @@ struct LPOut {
 //              neither proposes nor counts toward W; such vertices must have
 //              no neighbours).
 //  W [nlabels]: label weights consistent with labels.
-//  U: capacity of every label. wide: use 64-bit connection sums.
+//  U: capacity of every label, or capv[L] per label when capv is given.
+//  frozen (optional): vertices with frozen[v] != 0 keep their label and make
+//  no proposal (their label weight still counts).
+//  wide: use 64-bit connection sums.
 // When `out` is non-null the stream is synchronised and statistics copied.
 int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int64_t U, int32_t rounds,
-           int32_t dir_alternate, bool wide, LPOut *out, Scratch &sc);
+           int32_t dir_alternate, bool wide, LPOut *out, Scratch &sc, const int64_t *capv = nullptr,
+           const uint8_t *frozen = nullptr);
 
 // Sum of edge weights (nnz if adjwgt is null); synchronises the stream.
 int total_edge_weight(const DevGraph &g, int64_t *out, Scratch &sc);

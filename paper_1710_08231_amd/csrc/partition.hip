@@ -288,7 +288,7 @@ static int do_partition(const gp_graph *gin, int32_t k, double eps, const gp_par
         GP_TRY(sc.alloc(&co.vwgt, f.n));
         GP_TRY(sc.alloc(&co.f2c, f.n));
         Timer t_ct(s);
-        GP_TRY(contract(f, labels, skip, skip ? rowof0 : nullptr, co, sc));
+        GP_TRY(contract(f, labels, skip, co, sc));
         if (tracing())
             std::fprintf(stderr, "[gp] level %zu n=%d nnz=%d cluster %.3f ms (%d rounds, %.1f Gvisits/s) "
                                  "contract %.3f ms -> n=%d nnz=%d\n",
@@ -316,7 +316,7 @@ static int do_partition(const gp_graph *gin, int32_t k, double eps, const gp_par
     int32_t *P = nullptr;
     GP_TRY(sc.alloc(&P, lev[Lc].g.n));
     GP_TRY(initial_partition(lev[Lc].g, Lc == 0, k, lmax, p->seed, p->attempts, p->rounds_refine, p->dir_alternate,
-                             wide, P, nullptr, sc));
+                             wide, P, sc));
     const float ms_init = t_init.stop();
     if (tracing()) std::fprintf(stderr, "[gp] initial partition n=%d nnz=%d %.3f ms\n", lev[Lc].g.n, lev[Lc].g.nnz, ms_init);
 
@@ -522,7 +522,7 @@ int gp_contract(const gp_graph *g, const int32_t *labels, int32_t *xadj_c, int32
     co.adjwgt = adjwgt_c;
     co.vwgt = vwgt_c;
     co.f2c = f2c;
-    GP_TRY(contract(d, labels, false, nullptr, co, sc));
+    GP_TRY(contract(d, labels, false, co, sc));
     if (n_c_host) *n_c_host = co.n;
     if (nnz_c_host) *nnz_c_host = co.nnz;
     sc.release();

@@ -133,6 +133,35 @@ def test_contract_arbitrary_labels():
         assert np.array_equal(_np(cg[key]), ocg[key]), key
 
 
+def test_contract_label_groups_without_edges():
+    # many vertices without neighbours share labels: rows with more members than entries,
+    # in each size class (wave, workgroup, global)
+    edges = [(i, i + 1) for i in range(0, 400, 2)]
+    g = graphgen.from_edges(7000, edges)
+    lab = np.zeros(7000, np.int32)
+    lab[:400] = np.arange(400) // 2 * 2
+    lab[400:500] = 401
+    lab[500:3000] = 403
+    lab[3000:] = 405
+    ocg, of2c = oracle.contract(g, lab)
+    cg, f2c = gp.contract(gp.to_device(g), torch.from_numpy(lab).cuda())
+    assert np.array_equal(_np(f2c), of2c)
+    for key in ("xadj", "adjncy", "adjwgt", "vwgt"):
+        assert np.array_equal(_np(cg[key]), ocg[key]), key
+
+
+def test_contract_large_rows():
+    # a coarse row with > 2048 entries and many distinct columns (global class) next to small rows
+    g = graphgen.rmat(14, 3)
+    n = len(g["xadj"]) - 1
+    lab = np.array([(v // 64) * 64 if v < 4096 else v for v in range(n)], np.int32)
+    ocg, of2c = oracle.contract(g, lab)
+    cg, f2c = gp.contract(gp.to_device(g), torch.from_numpy(lab).cuda())
+    assert np.array_equal(_np(f2c), of2c)
+    for key in ("xadj", "adjncy", "adjwgt", "vwgt"):
+        assert np.array_equal(_np(cg[key]), ocg[key]), key
+
+
 def test_project_and_cut():
     g = graphgen.rmat(12, 5)
     dg = gp.to_device(g)
