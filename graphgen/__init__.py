@@ -46,6 +46,9 @@ def _load():
     lib.gg_rmat.restype = ctypes.c_int64
     lib.gg_rmat.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                             ctypes.c_double, ctypes.c_uint64, P32, P32]
+    lib.gg_rmat_m.restype = ctypes.c_int64
+    lib.gg_rmat_m.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                              ctypes.c_double, ctypes.c_uint64, P32, P32]
     lib.gg_grid3d.restype = ctypes.c_int64
     lib.gg_grid3d.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
                               ctypes.c_int32, P32, P32, P32]
@@ -91,6 +94,45 @@ def rmat(scale, seed, edge_factor=16, a=0.57, b=0.19, c=0.19):
     if nnz < 0:
         raise RuntimeError("gg_rmat failed")
     return {"xadj": _take(px, (1 << scale) + 1), "adjncy": _take(pa, nnz)}
+
+
+def rmat_m(scale, m, seed, a=0.57, b=0.19, c=0.19):
+    """R-MAT with exactly m edge draws (before symmetrisation and deduplication)."""
+    lib = _load()
+    px, pa = ctypes.POINTER(ctypes.c_int32)(), ctypes.POINTER(ctypes.c_int32)()
+    nnz = lib.gg_rmat_m(scale, m, a, b, c, seed, ctypes.byref(px), ctypes.byref(pa))
+    if nnz < 0:
+        raise RuntimeError("gg_rmat_m failed")
+    return {"xadj": _take(px, (1 << scale) + 1), "adjncy": _take(pa, nnz)}
+
+
+def _u01(seed, i):
+    return (rand_u64(seed, i) >> 11) * (1.0 / 9007199254740992.0)
+
+
+def batch(master_seed=4, count=512, log2_min=10, log2_max=18):
+    """Batch of `count` uneven graphs: the first half 2-D random geometric, the
+    second half R-MAT (.57,.19,.19,.05). Graph i draws u1,u2,u3 from the master
+    stream (counters 3i..3i+2): n = floor(2^(lo+(hi-lo)u1)) (R-MAT: 2^round(..)),
+    average degree d = 8 + 8 u2 (rgg radius sqrt(d/(pi n)); R-MAT draws d n / 2
+    edges), k = (2, 8, 32)[floor(3 u3)]; graph seed = R(master, 3 count + i).
+    Returns (list of CSR dicts, list of k)."""
+    graphs, ks = [], []
+    span = log2_max - log2_min
+    for i in range(count):
+        u1, u2, u3 = (_u01(master_seed, 3 * i + j) for j in range(3))
+        d = 8.0 + 8.0 * u2
+        k = (2, 8, 32)[min(2, int(3 * u3))]
+        gseed = rand_u64(master_seed, 3 * count + i)
+        if i < count // 2:
+            n = int(math.floor(2.0 ** (log2_min + span * u1)))
+            g = rgg2d(n, gseed, radius=math.sqrt(d / (math.pi * n)))
+        else:
+            scale = int(round(log2_min + span * u1))
+            g = rmat_m(scale, int(round(d * (1 << scale) / 2)), gseed)
+        graphs.append(g)
+        ks.append(k)
+    return graphs, ks
 
 
 def grid3d(X, Y, Z, seed=3, wmax=10):

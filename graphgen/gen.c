@@ -208,14 +208,13 @@ int64_t gg_rgg2d(int64_t n, uint64_t seed, double r, int32_t **xadj, int32_t **a
     return nnz;
 }
 
-/* R-MAT with (a, b, c, 1-a-b-c), m = edge_factor * 2^scale draws. */
-int64_t gg_rmat(int32_t scale, int32_t edge_factor, double a, double b, double c, uint64_t seed,
-                int32_t **xadj, int32_t **adj) {
-    if (scale < 1 || scale > 30 || edge_factor < 1) return -1;
+/* R-MAT with (a, b, c, 1-a-b-c) and m edge draws on 2^scale vertices. */
+int64_t gg_rmat_m(int32_t scale, int64_t m, double a, double b, double c, uint64_t seed, int32_t **xadj,
+                  int32_t **adj) {
+    if (scale < 1 || scale > 30 || m < 0) return -1;
     int64_t n = (int64_t)1 << scale;
-    int64_t m = (int64_t)edge_factor * n;
-    int32_t *src = (int32_t *)malloc((size_t)m * sizeof(int32_t));
-    int32_t *dst = (int32_t *)malloc((size_t)m * sizeof(int32_t));
+    int32_t *src = (int32_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int32_t));
+    int32_t *dst = (int32_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int32_t));
     if (!src || !dst) { free(src); free(dst); return -1; }
     double ab = a + b, abc = a + b + c;
 #pragma omp parallel for schedule(static)
@@ -237,6 +236,13 @@ int64_t gg_rmat(int32_t scale, int32_t edge_factor, double a, double b, double c
     int64_t nnz = build_csr(n, m, src, dst, xadj, adj);
     free(src); free(dst);
     return nnz;
+}
+
+/* R-MAT with m = edge_factor * 2^scale draws. */
+int64_t gg_rmat(int32_t scale, int32_t edge_factor, double a, double b, double c, uint64_t seed,
+                int32_t **xadj, int32_t **adj) {
+    if (edge_factor < 1) return -1;
+    return gg_rmat_m(scale, (int64_t)edge_factor << scale, a, b, c, seed, xadj, adj);
 }
 
 /* Six-neighbour grid. If wmax > 0, *adjwgt receives weights 1 + (R mod wmax). */

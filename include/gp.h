@@ -162,6 +162,23 @@ int gp_cut_and_blocks(const gp_graph *g, int32_t k, const int32_t *part, int64_t
 int gp_partition(const gp_graph *g, int32_t k, double eps, const gp_params *p, int32_t *part_out,
                  gp_result *res_host, hipStream_t stream);
 
+/*
+ * Batched form (a project addition; §III scheme per graph): G independent
+ * graphs stored side by side as one disjoint-union graph g — graph q owns
+ * vertices [vtx_off_host[q], vtx_off_host[q+1]) and no edge joins two graphs
+ * (GP_ERR_GRAPH otherwise). Graph q is cut into k_host[q] blocks with the
+ * balance bound of its own total weight. All graphs are coarsened and refined
+ * together level by level through the same kernels (per-label capacities,
+ * graphs that stopped coarsening are carried along unchanged), and one
+ * batched initial partitioning runs on the coarsest level. The result for
+ * every graph equals gp_partition on that graph alone (same parameters).
+ * part_out: [n] device int32, block ids local to each graph (0 <= b < k[q]).
+ * res_host: [G] host results (may be NULL); the ms_* fields are batch totals.
+ * Returns GP_OK, GP_WARN_IMBALANCED (some graph imbalanced), or an error.
+ */
+int gp_partition_batch(const gp_graph *g, int32_t G, const int32_t *vtx_off_host, const int32_t *k_host, double eps,
+                       const gp_params *p, int32_t *part_out, gp_result *res_host, hipStream_t stream);
+
 const char *gp_strerror(int code);
 const char *gp_last_error(void);
 

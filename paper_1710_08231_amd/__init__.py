@@ -20,7 +20,7 @@ import subprocess
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _ROOT = os.path.dirname(_HERE)
 LIB_PATH = os.path.join(_HERE, "libgp.so")
-SOURCES = ["lp.hip", "contract.hip", "initpart.hip", "partition.hip"]
+SOURCES = ["lp.hip", "contract.hip", "initpart.hip", "partition.hip", "batch.hip"]
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
@@ -69,7 +69,7 @@ class Result(ctypes.Structure):
 
 
 EXPORTS = ["gp_default_params", "gp_lmax", "gp_lp_cluster", "gp_lp_refine", "gp_contract",
-           "gp_project", "gp_cut_and_blocks", "gp_partition", "gp_strerror", "gp_last_error",
+           "gp_project", "gp_cut_and_blocks", "gp_partition", "gp_partition_batch", "gp_strerror", "gp_last_error",
            "gp_profile_enable", "gp_profile_select", "gp_profile_count", "gp_profile_get"]
 
 
@@ -93,6 +93,8 @@ def load():
     lib.gp_cut_and_blocks.argtypes = [G, i32, vp, ctypes.POINTER(i64), vp, vp]
     lib.gp_partition.argtypes = [G, i32, ctypes.c_double, ctypes.POINTER(Params), vp,
                                  ctypes.POINTER(Result), vp]
+    lib.gp_partition_batch.argtypes = [G, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.c_double,
+                                       ctypes.POINTER(Params), vp, ctypes.POINTER(Result), vp]
     lib.gp_strerror.restype = ctypes.c_char_p
     lib.gp_strerror.argtypes = [ctypes.c_int]
     lib.gp_last_error.restype = ctypes.c_char_p
@@ -227,6 +229,52 @@ def partition(g, k, eps=0.03, **params):
     res = {f: getattr(r, f) for f, _ in Result._fields_}
     res["code"] = code
     return part[:gs.n], res
+
+
+def union_graph(graphs):
+    """Disjoint union of numpy CSR graphs -> (numpy CSR dict, vtx_off list). Input plumbing only."""
+    import numpy as np
+    xs, adj, aw, vw, off, eoff = [np.zeros(1, np.int32)], [], [], [], [0], 0
+    any_w = any(g.get("adjwgt") is not None for g in graphs)
+    any_v = any(g.get("vwgt") is not None for g in graphs)
+    for g in graphs:
+        n = len(g["xadj"]) - 1
+        xs.append((g["xadj"][1:] + eoff).astype(np.int32))
+        adj.append((g["adjncy"] + off[-1]).astype(np.int32))
+        if any_w:
+            aw.append(g["adjwgt"] if g.get("adjwgt") is not None else np.ones(len(g["adjncy"]), np.int32))
+        if any_v:
+            vw.append(g["vwgt"] if g.get("vwgt") is not None else np.ones(n, np.int32))
+        off.append(off[-1] + n)
+        eoff += len(g["adjncy"])
+    u = {"xadj": np.concatenate(xs).astype(np.int32),
+         "adjncy": np.concatenate(adj).astype(np.int32) if adj else np.zeros(0, np.int32)}
+    if any_w:
+        u["adjwgt"] = np.concatenate(aw).astype(np.int32)
+    if any_v:
+        u["vwgt"] = np.concatenate(vw).astype(np.int32)
+    return u, off
+
+
+def partition_batch(g, vtx_off, ks, eps=0.03, **params):
+    """Partition the graphs of a disjoint-union graph together (see gp_partition_batch)."""
+    torch = _torch()
+    gs = _gstruct(g)
+    G = len(ks)
+    p = default_params()
+    for key, val in params.items():
+        setattr(p, key, val)
+    part = torch.empty(max(gs.n, 1), dtype=torch.int32, device=g["xadj"].device)
+    off = (ctypes.c_int32 * (G + 1))(*vtx_off)
+    kk = (ctypes.c_int32 * G)(*ks)
+    res = (Result * G)()
+    code = _check(load().gp_partition_batch(ctypes.byref(gs), G, off, kk, eps, ctypes.byref(p), _ptr(part), res,
+                                            _stream()))
+    out = []
+    for r in res:
+        d = {f: getattr(r, f) for f, _ in Result._fields_}
+        out.append(d)
+    return part[:gs.n], out, code
 
 
 def profile_enable(on=True):

@@ -519,6 +519,96 @@ __global__ void k_iso_serial(const int32_t *iso, const int32_t *niso, const int6
     }
 }
 
+// Batched placement of vertices without neighbours. The list iso[] is in
+// ascending id, hence grouped by graph; vertex iso[i] belongs to graph
+// q = gid[iso[i]] and is the (i - iso_first[q])-th of its graph.
+__global__ void k_iso_uniform_batch(const int32_t *iso, const int32_t *niso, const int32_t *gid,
+                                    const int32_t *iso_first, const int32_t *kbase, const int64_t *Ball, int64_t c,
+                                    int32_t *part) {
+    const int32_t m = *niso;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t q = gid[iso[i]];
+        const int64_t r = i - iso_first[q];
+        const int32_t k = kbase[q + 1] - kbase[q];
+        const int64_t *B = Ball + kbase[q];
+        int64_t bmin = LLONG_MAX;
+        for (int b = 0; b < k; b++) bmin = B[b] < bmin ? B[b] : bmin;
+        int64_t lo = bmin, hi = bmin + r * c;
+        while (lo < hi) {
+            const int64_t mid = lo + (hi - lo) / 2;
+            int64_t f = 0;
+            for (int b = 0; b < k; b++)
+                if (B[b] <= mid) f += (mid - B[b]) / c + 1;
+            if (f >= r + 1) hi = mid;
+            else lo = mid + 1;
+        }
+        const int64_t x = lo;
+        int64_t below = 0;
+        for (int b = 0; b < k; b++)
+            if (B[b] <= x - 1) below += (x - 1 - B[b]) / c + 1;
+        int64_t rank = r - below;
+        int32_t pick = -1;
+        for (int b = 0; b < k; b++) {
+            if (B[b] <= x && (x - B[b]) % c == 0) {
+                if (rank == 0) {
+                    pick = b;
+                    break;
+                }
+                rank--;
+            }
+        }
+        part[iso[i]] = pick >= 0 ? kbase[q] + pick : -1;
+    }
+}
+
+// General weights: one thread per graph, binary heap of (B_b, b) in hv/hb at kbase[q].
+__global__ void k_iso_serial_batch(const int32_t *iso, const int32_t *iso_first, int32_t G, const int32_t *kbase,
+                                   const int64_t *Ball, const int32_t *vwgt, int64_t *hvall, int32_t *hball,
+                                   int32_t *part) {
+    for (int32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < G; q += gridDim.x * blockDim.x) {
+        const int32_t k = kbase[q + 1] - kbase[q];
+        int64_t *hv = hvall + kbase[q];
+        int32_t *hb = hball + kbase[q];
+        auto less = [&](int i, int j) { return hv[i] < hv[j] || (hv[i] == hv[j] && hb[i] < hb[j]); };
+        for (int b = 0; b < k; b++) {
+            hv[b] = Ball[kbase[q] + b];
+            hb[b] = b;
+            int i = b;
+            while (i > 0) {
+                const int p = (i - 1) / 2;
+                if (!less(i, p)) break;
+                const int64_t tv = hv[i];
+                hv[i] = hv[p];
+                hv[p] = tv;
+                const int32_t tb = hb[i];
+                hb[i] = hb[p];
+                hb[p] = tb;
+                i = p;
+            }
+        }
+        for (int32_t x = iso_first[q]; x < iso_first[q + 1]; x++) {
+            const int32_t v = iso[x];
+            part[v] = kbase[q] + hb[0];
+            hv[0] += vwgt ? vwgt[v] : 1;
+            int i = 0;
+            for (;;) {
+                const int l = 2 * i + 1, r = l + 1;
+                int sm = i;
+                if (l < k && less(l, sm)) sm = l;
+                if (r < k && less(r, sm)) sm = r;
+                if (sm == i) break;
+                const int64_t tv = hv[i];
+                hv[i] = hv[sm];
+                hv[sm] = tv;
+                const int32_t tb = hb[i];
+                hb[i] = hb[sm];
+                hb[sm] = tb;
+                i = sm;
+            }
+        }
+    }
+}
+
 }  // namespace
 
 int initial_partition_batch(const DevGraph &g, bool skip_isolated, const BatchInfo &bi, uint64_t seed,
@@ -724,6 +814,47 @@ int fill_isolated(const DevGraph &g, int32_t k, int32_t *part, const int64_t *B,
         GP_TRY(sc.alloc(&hv, k));
         GP_TRY(sc.alloc(&hbk, k));
         hipLaunchKernelGGL(k_iso_serial, dim3(1), dim3(64), 0, s, iso, d_niso, B, k, g.vwgt, hv, hbk, part);
+        GP_LAUNCH_CHECK();
+    }
+    return GP_OK;
+}
+
+}  // namespace gp
+
+namespace gp {
+
+int fill_isolated_batch(const DevGraph &g, const BatchInfo &bi, const int32_t *d_iso_first, int32_t *part,
+                        const int64_t *B, Scratch &sc) {
+    hipStream_t s = sc.stream();
+    const int32_t n = g.n;
+    if (n == 0) return GP_OK;
+    int32_t *iso = nullptr, *d_niso = nullptr, *mm = nullptr;
+    GP_TRY(sc.alloc(&iso, n));
+    GP_TRY(sc.alloc(&d_niso, 1));
+    GP_TRY(sc.alloc(&mm, 2));
+    GP_TRY(compact(IsoFlag{g.xadj}, IsoEmit{iso}, n, nullptr, d_niso, sc));
+    int32_t h[2] = {1, 1}, niso = 0;
+    GP_HIP(hipMemcpyAsync(&niso, d_niso, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    if (g.vwgt) {
+        const int32_t init[2] = {INT_MAX, INT_MIN};
+        GP_HIP(hipMemcpyAsync(mm, init, sizeof(init), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_iso_minmax, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, iso, d_niso, g.vwgt, mm);
+        GP_LAUNCH_CHECK();
+        GP_HIP(hipMemcpyAsync(h, mm, sizeof(h), hipMemcpyDeviceToHost, s));
+    }
+    GP_HIP(hipStreamSynchronize(s));
+    if (niso == 0) return GP_OK;
+    if (h[0] == h[1]) {
+        hipLaunchKernelGGL(k_iso_uniform_batch, dim3(grid_for(niso, 256, 8192)), dim3(256), 0, s, iso, d_niso,
+                           bi.d_gid, d_iso_first, bi.d_kbase, B, (int64_t)h[0], part);
+        GP_LAUNCH_CHECK();
+    } else {
+        int64_t *hv = nullptr;
+        int32_t *hb = nullptr;
+        GP_TRY(sc.alloc(&hv, bi.kbase[bi.G]));
+        GP_TRY(sc.alloc(&hb, bi.kbase[bi.G]));
+        hipLaunchKernelGGL(k_iso_serial_batch, dim3(grid_for(bi.G, 64, 4096)), dim3(64), 0, s, iso, d_iso_first, bi.G,
+                           bi.d_kbase, B, g.vwgt, hv, hb, part);
         GP_LAUNCH_CHECK();
     }
     return GP_OK;

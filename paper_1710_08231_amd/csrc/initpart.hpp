@@ -29,6 +29,13 @@ int initial_partition(const DevGraph &g, bool skip_isolated, int32_t k, int64_t 
                       int32_t attempts, int32_t rounds_refine, int32_t dir_alternate, bool wide, int32_t *part,
                       Scratch &sc);
 
+// Batched placement of vertices without neighbours: per graph q, its
+// isolated vertices (iso_first[q].. in the ascending list of all isolated
+// vertices) go one by one to graph q's lightest block (global ids kbase[q]+b),
+// starting from block weights B (device int64 [kbase[G]], not modified).
+int fill_isolated_batch(const DevGraph &g, const BatchInfo &bi, const int32_t *d_iso_first, int32_t *part,
+                        const int64_t *B, Scratch &sc);
+
 // gid[v] = q for v in [voff[q], voff[q+1]) (device arrays).
 int graph_ids(int32_t G, int32_t n, const int32_t *d_voff, int32_t *gid, hipStream_t s);
 

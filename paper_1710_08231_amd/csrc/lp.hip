@@ -859,6 +859,12 @@ struct StoreIncl {
     __device__ void operator()(int64_t p, int64_t ex, int64_t v) const { S[p] = ex + v; }
 };
 
+// per-group round bookkeeping: gs[q] = {moves this round, previous moves, done, rounds_run, rounds seen}
+struct GroupState {
+    int32_t moves, prev, done, rounds_run, seen;
+    int64_t total;
+};
+
 __global__ void k_heads(const uint32_t *mk, const int32_t *nmov, int32_t *headpos) {
     const int32_t n = *nmov;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
@@ -868,7 +874,7 @@ __global__ void k_heads(const uint32_t *mk, const int32_t *nmov, int32_t *headpo
 
 __global__ void k_admit(const uint32_t *mk, const int32_t *mv, const int32_t *nmov, const int32_t *headpos,
                         const int64_t *S, const int64_t *W, int64_t U, const int64_t *capv, int32_t *labels,
-                        int32_t *oldlab, LPDev *dev) {
+                        int32_t *oldlab, LPDev *dev, const int32_t *group, GroupState *gs) {
     const int32_t n = *nmov;
     int32_t cnt = 0;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
@@ -881,6 +887,7 @@ __global__ void k_admit(const uint32_t *mk, const int32_t *mv, const int32_t *nm
             oldlab[p] = labels[v];
             labels[v] = t;
             cnt++;
+            if (group) atomicAdd(&gs[group[v]].moves, 1);
         } else {
             oldlab[p] = -1;
         }
@@ -931,6 +938,22 @@ __global__ __launch_bounds__(256) void k_apply_w_small(const uint32_t *mk, const
     __syncthreads();
     for (int i = threadIdx.x; i < nl; i += blockDim.x)
         if (h[i]) atomicAdd((unsigned long long *)&W[i], h[i]);
+}
+
+__global__ void k_round_end_groups(GroupState *gs, int32_t ng) {
+    for (int32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < ng; q += gridDim.x * blockDim.x) {
+        GroupState st = gs[q];
+        const int32_t r = st.seen;
+        st.seen = r + 1;
+        if (!st.done) {
+            st.rounds_run = r + 1;
+            st.total += st.moves;
+            if (r >= 1 && st.moves == 0 && st.prev == 0) st.done = 1;
+            st.prev = st.moves;
+        }
+        st.moves = 0;
+        gs[q] = st;
+    }
 }
 
 __global__ void k_round_end(LPDev *dev) {
@@ -1072,7 +1095,8 @@ int label_weights(const DevGraph &g, const int32_t *labels, int64_t *W, int32_t 
 }
 
 int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int64_t U, int32_t rounds,
-           int32_t dir_alternate, bool wide, LPOut *out, Scratch &sc, const int64_t *capv, const uint8_t *frozen) {
+           int32_t dir_alternate, bool wide, LPOut *out, Scratch &sc, const int64_t *capv, const uint8_t *frozen,
+           const int32_t *group, int32_t ngroups) {
     hipStream_t s = sc.stream();
     const int32_t n = g.n;
     if (n == 0 || rounds == 0) {
@@ -1241,6 +1265,13 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
     GP_TRY(sc.alloc(&dev, 1));
     GP_HIP(hipMemsetAsync(prop, 0xFF, sizeof(int32_t) * (size_t)n, s));
     GP_HIP(hipMemsetAsync(dev, 0, sizeof(LPDev), s));
+    GroupState *gstate = nullptr;
+    if (group && ngroups > 0) {
+        GP_TRY(sc.alloc(&gstate, ngroups));
+        GP_HIP(hipMemsetAsync(gstate, 0, sizeof(GroupState) * (size_t)ngroups, s));
+    } else {
+        group = nullptr;
+    }
     const int key_bits = bits_for(nlabels > 0 ? nlabels - 1 : 0);
 
     // One round = one fixed launch sequence; the round index lives on the
@@ -1293,7 +1324,7 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
         GP_LAUNCH_CHECK();
         RT_TRY((scan<int64_t>(MoverWeight{v1, g.vwgt}, StoreIncl{S}, n, nmov, (int64_t *)nullptr, sc)));
         hipLaunchKernelGGL(k_admit, dim3(gb), dim3(256), 0, s, k1, v1, nmov, headpos, S, W, U, capv, labels, oldlab,
-                           dev);
+                           dev, group, gstate);
         GP_LAUNCH_CHECK();
         if (nlabels <= kSmallLabels)
             hipLaunchKernelGGL(k_apply_w_small, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, k1, v1, nmov, oldlab,
@@ -1301,6 +1332,7 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
         else
             hipLaunchKernelGGL(k_apply_w, dim3(gb), dim3(256), 0, s, k1, v1, nmov, oldlab, g.vwgt, headpos, S, W);
         GP_LAUNCH_CHECK();
+        if (group) hipLaunchKernelGGL(k_round_end_groups, dim3(grid_for(ngroups, 256, 1024)), dim3(256), 0, s, gstate, ngroups);
         hipLaunchKernelGGL(k_round_end, dim3(1), dim3(1), 0, s, dev);
         GP_LAUNCH_CHECK();
     #undef RT_TRY
@@ -1340,6 +1372,16 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
         if (!out) return GP_OK;
         out->rounds_run = h.rounds_run;
         out->moves = h.total_moves;
+        out->group_rounds.clear();
+        out->group_moves.clear();
+        if (group) {
+            std::vector<GroupState> hs(ngroups);
+            GP_HIP(hipMemcpy(hs.data(), gstate, sizeof(GroupState) * (size_t)ngroups, hipMemcpyDeviceToHost));
+            for (const auto &x : hs) {
+                out->group_rounds.push_back(x.rounds_run);
+                out->group_moves.push_back(x.total);
+            }
+        }
     }
     return GP_OK;
 }

@@ -1,5 +1,7 @@
 // lp.hpp — host-side interface of the label-propagation rounds (internal).
 #pragma once
+#include <vector>
+
 #include "gp_common.hpp"
 
 namespace gp {
@@ -23,6 +25,8 @@ struct LPDev {
 struct LPOut {
     int32_t rounds_run = 0;
     int64_t moves = 0;
+    std::vector<int32_t> group_rounds;  // per group (when groups are given): its own rounds_run
+    std::vector<int64_t> group_moves;
 };
 
 // Runs up to `rounds` synchronous LP rounds on (labels, W) in place.
@@ -35,9 +39,12 @@ struct LPOut {
 //  no proposal (their label weight still counts).
 //  wide: use 64-bit connection sums.
 // When `out` is non-null the stream is synchronised and statistics copied.
+//  group/ngroups (optional): vertex groups (independent graphs of a batch);
+//  out->group_rounds[q] then holds the rounds group q alone would have run
+//  (two idle rounds in a row end a group; a group that went idle stays idle).
 int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int64_t U, int32_t rounds,
            int32_t dir_alternate, bool wide, LPOut *out, Scratch &sc, const int64_t *capv = nullptr,
-           const uint8_t *frozen = nullptr);
+           const uint8_t *frozen = nullptr, const int32_t *group = nullptr, int32_t ngroups = 0);
 
 // Sum of edge weights (nnz if adjwgt is null); synchronises the stream.
 int total_edge_weight(const DevGraph &g, int64_t *out, Scratch &sc);

@@ -146,6 +146,9 @@ struct GraphInfo {
     int64_t W = 0, cmax = 0, niso = 0;
 };
 
+int partition_batch(const DevGraph &g0, int32_t G, const int32_t *voff_host, const int32_t *k_host, double eps,
+                    const gp_params *p, int32_t *part_out, gp_result *res, Scratch &sc);
+
 static int graph_info(const DevGraph &g, GraphInfo &gi, Scratch &sc) {
     hipStream_t s = sc.stream();
     unsigned long long *acc = nullptr;
@@ -574,6 +577,40 @@ int gp_partition(const gp_graph *g, int32_t k, double eps, const gp_params *p, i
         return GP_ERR_ARG;
     }
     return do_partition(g, k, eps, pp, part_out, res_host, stream);
+}
+
+int gp_partition_batch(const gp_graph *g, int32_t G, const int32_t *vtx_off_host, const int32_t *k_host, double eps,
+                       const gp_params *p, int32_t *part_out, gp_result *res_host, hipStream_t stream) {
+    GP_TRY(check_graph_args(g));
+    if (G < 1 || !vtx_off_host || !k_host || !(eps >= 0.0) || (g->n > 0 && !part_out)) {
+        set_error("partition_batch: G < 1, eps < 0 or a required array is NULL");
+        return GP_ERR_ARG;
+    }
+    if (vtx_off_host[0] != 0 || vtx_off_host[G] != g->n) {
+        set_error("partition_batch: vtx_off must start at 0 and end at n");
+        return GP_ERR_ARG;
+    }
+    for (int32_t q = 0; q < G; q++)
+        if (vtx_off_host[q + 1] < vtx_off_host[q] || k_host[q] < 1) {
+            set_error("partition_batch: vtx_off must be non-decreasing and every k >= 1");
+            return GP_ERR_ARG;
+        }
+    gp_params dp;
+    gp_default_params(&dp);
+    const gp_params *pp = p ? p : &dp;
+    if (pp->rounds_coarsen < 0 || pp->rounds_refine < 0 || pp->attempts < 1 || pp->coarsest_per_k < 1 ||
+        pp->stall_den < 1 || pp->stall_num < 0) {
+        set_error("partition_batch: invalid parameters");
+        return GP_ERR_ARG;
+    }
+    Scratch sc(stream);
+    const DevGraph d = dev_graph(g);
+    GraphInfo gi;
+    GP_TRY(graph_info(d, gi, sc));
+    const int rc = partition_batch(d, G, vtx_off_host, k_host, eps, pp, part_out, res_host, sc);
+    sc.release();
+    GP_HIP(hipStreamSynchronize(stream));
+    return rc;
 }
 
 const char *gp_strerror(int code) {
