@@ -36,7 +36,9 @@ class _Params(ctypes.Structure):
     _fields_ = [("rounds_coarsen", ctypes.c_int32), ("rounds_refine", ctypes.c_int32),
                 ("coarsest_per_k", ctypes.c_int32), ("attempts", ctypes.c_int32),
                 ("stall_num", ctypes.c_int32), ("stall_den", ctypes.c_int32),
-                ("dir_alternate", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("dir_alternate", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("init_mode", ctypes.c_int32), ("mpnn_max_n", ctypes.c_int32),
+                ("mpnn_seed", ctypes.c_uint64), ("mpnn_params", ctypes.POINTER(ctypes.c_float))]
 
 
 class _Result(ctypes.Structure):
@@ -44,14 +46,19 @@ class _Result(ctypes.Structure):
                 ("lmax", ctypes.c_int64), ("ucl", ctypes.c_int64),
                 ("balanced", ctypes.c_int32), ("levels", ctypes.c_int32),
                 ("edge_visits_cluster", ctypes.c_int64), ("edge_visits_refine", ctypes.c_int64),
-                ("coarsest_n", ctypes.c_int32), ("n_isolated", ctypes.c_int32)]
+                ("coarsest_n", ctypes.c_int32), ("n_isolated", ctypes.c_int32),
+                ("learned_tried", ctypes.c_int32), ("learned_kept", ctypes.c_int32),
+                ("plain_cut_coarsest", ctypes.c_int64), ("learned_cut_coarsest", ctypes.c_int64)]
 
 
 def build_lib():
-    """Compile oracle.c with gcc (always rebuilds). Building the checker is not using it."""
+    """Compile oracle.c and mpnn.c with gcc (always rebuilds). Building the checker is not
+    using it. -ffp-contract=off keeps every binary32 product and sum that mpnn.c does not
+    write as fmaf rounded on its own."""
     tmp = _LIB_PATH + ".tmp"
     subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-Wall", "-std=gnu11",
-                           "-o", tmp, os.path.join(_HERE, "oracle.c"), "-lm"])
+                           "-ffp-contract=off", "-o", tmp, os.path.join(_HERE, "oracle.c"),
+                           os.path.join(_HERE, "mpnn.c"), "-lm"])
     os.replace(tmp, _LIB_PATH)
 
 
@@ -87,6 +94,15 @@ def _load():
     lib.orc_fill_isolated.argtypes = [G, ctypes.c_int32, I32P, I64P]
     lib.orc_partition.argtypes = [G, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(_Params),
                                   I32P, ctypes.POINTER(_Result)]
+    lib.orc_coarsest.argtypes = [G, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(_Params),
+                                 I32P, I32P, I32P, I32P, I32P, I32P, I32P]
+    F32P = ctypes.POINTER(ctypes.c_float)
+    lib.orc_mpnn_param_count.restype = ctypes.c_int32
+    lib.orc_mpnn_param_count.argtypes = [ctypes.c_int32]
+    lib.orc_bf16.restype = ctypes.c_float
+    lib.orc_bf16.argtypes = [ctypes.c_float]
+    lib.orc_mpnn_features.argtypes = [G, ctypes.c_uint64, F32P]
+    lib.orc_mpnn_infer.argtypes = [G, ctypes.c_int32, F32P, ctypes.c_uint64, F32P, I32P]
     _lib = lib
     return lib
 
@@ -226,14 +242,74 @@ def fill_isolated(g, k, part, B):
 
 
 DEFAULT_PARAMS = dict(rounds_coarsen=10, rounds_refine=25, coarsest_per_k=60, attempts=4,
-                      stall_num=19, stall_den=20, dir_alternate=1, seed=0)
+                      stall_num=19, stall_den=20, dir_alternate=1, seed=0, init_mode=0,
+                      mpnn_max_n=65536, mpnn_seed=0, mpnn_params=None)
+
+
+def _params(params):
+    """(_Params, keep-alive) from keyword overrides; mpnn_params is a float array or None."""
+    prm = dict(DEFAULT_PARAMS)
+    prm.update(params)
+    w = prm.pop("mpnn_params")
+    keep = None
+    if w is not None:
+        keep = np.ascontiguousarray(w, dtype=np.float32)
+        prm["mpnn_params"] = keep.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    return _Params(**prm), keep
+
+
+def mpnn_param_count(k):
+    return int(_load().orc_mpnn_param_count(k))
+
+
+def bf16(x):
+    """Round binary32 values to bfloat16 (nearest, ties to even); returns float32 array."""
+    x = np.asarray(x, dtype=np.float32)
+    lib = _load()
+    return np.array([lib.orc_bf16(float(v)) for v in x.ravel()], dtype=np.float32).reshape(x.shape)
+
+
+def mpnn_features(g, seed=0):
+    G = _G(g)
+    X = np.zeros((G.n, 18), np.float32)
+    _load().orc_mpnn_features(G.ref, seed, X.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
+    return X
+
+
+def mpnn_infer(g, k, params, seed=0):
+    """Binary32 inference: (logits [n, k], argmax blocks [n])."""
+    G = _G(g)
+    w = np.ascontiguousarray(params, dtype=np.float32)
+    assert w.size == mpnn_param_count(k)
+    F32P = ctypes.POINTER(ctypes.c_float)
+    Z = np.zeros((G.n, k), np.float32)
+    P = np.zeros(G.n, np.int32)
+    _load().orc_mpnn_infer(G.ref, k, w.ctypes.data_as(F32P), seed, Z.ctypes.data_as(F32P), _p32(P))
+    return Z, P
+
+
+def coarsest(g, k, eps=0.03, **params):
+    """Coarsest graph (CSR dict with weights) and its initial partition."""
+    G = _G(g)
+    p, keep = _params(params)
+    n, nnz = G.n, len(G.adjncy)
+    xc = np.zeros(n + 1, np.int32)
+    ac = np.zeros(max(nnz, 1), np.int32)
+    wc = np.zeros(max(nnz, 1), np.int32)
+    vc = np.zeros(max(n, 1), np.int32)
+    pc = np.zeros(max(n, 1), np.int32)
+    nc, nnzc = ctypes.c_int32(), ctypes.c_int32()
+    _load().orc_coarsest(G.ref, k, eps, ctypes.byref(p), _p32(xc), _p32(ac), _p32(wc), _p32(vc),
+                         _p32(pc), ctypes.byref(nc), ctypes.byref(nnzc))
+    nc, nnzc = nc.value, nnzc.value
+    cg = {"xadj": xc[:nc + 1].copy(), "adjncy": ac[:nnzc].copy(), "adjwgt": wc[:nnzc].copy(),
+          "vwgt": vc[:nc].copy()}
+    return cg, pc[:nc].copy()
 
 
 def partition(g, k, eps=0.03, **params):
     G = _G(g)
-    prm = dict(DEFAULT_PARAMS)
-    prm.update(params)
-    p = _Params(**prm)
+    p, keep = _params(params)
     P = np.zeros(G.n, np.int32)
     r = _Result()
     code = _load().orc_partition(G.ref, k, eps, ctypes.byref(p), _p32(P), ctypes.byref(r))

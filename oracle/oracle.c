@@ -442,17 +442,23 @@ typedef struct {
     int32_t *xadj, *adjncy, *adjwgt, *vwgt, *f2c; /* f2c maps this level to the next */
 } level_t;
 
+typedef struct {
+    level_t *lev;
+    int32_t L; /* index of the coarsest level */
+    int32_t *newid;
+    int64_t lmax, ucl, ev_cluster;
+} hierarchy_t;
+
 /*
- * §III multilevel scheme with the project's stop rules:
+ * §III-A coarsening with the project's stop rules:
  *  - U_c = max(c_max, L_max - ceil(W/k)) during coarsening (the paper only
- *    names "a given upper bound U"); U = L_max during refinement (§III-C).
- *  - vertices without neighbours are set aside before coarsening and filled
- *    in at the end;
+ *    names "a given upper bound U");
+ *  - vertices without neighbours are set aside before coarsening (level 0 is
+ *    the graph of the other vertices, renumbered in ascending order);
  *  - coarsen while n > coarsest_per_k * k; discard a level that did not
  *    shrink; stop after a level with stall_den * n' > stall_num * n.
  */
-int orc_partition(const orc_graph *g, int32_t k, double eps, const orc_params *p,
-                  int32_t *part_out, orc_result *res) {
+static void coarsen(const orc_graph *g, int32_t k, double eps, const orc_params *p, hierarchy_t *h) {
     int32_t n = g->n;
     int64_t W = orc_total_vwgt(g);
     int64_t lmax = orc_lmax(W, k, eps);
@@ -462,7 +468,6 @@ int orc_partition(const orc_graph *g, int32_t k, double eps, const orc_params *p
     int64_t ucl = lmax - ceil_wk;
     if (ucl < cmax) ucl = cmax;
 
-    /* level 0: vertices with at least one neighbour, renumbered ascending */
     int32_t *newid = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
     int32_t n0 = 0;
     for (int32_t v = 0; v < n; v++) newid[v] = (g->xadj[v + 1] > g->xadj[v]) ? n0++ : -1;
@@ -490,7 +495,7 @@ int orc_partition(const orc_graph *g, int32_t k, double eps, const orc_params *p
     }
     lev[0].g = (orc_graph){n0, lev[0].xadj, lev[0].adjncy, lev[0].adjwgt, lev[0].vwgt};
 
-    int64_t ev_cluster = 0, ev_refine = 0;
+    int64_t ev_cluster = 0;
     int32_t L = 0;
     while (lev[L].g.n > (int64_t)p->coarsest_per_k * k && L + 1 < maxlev) {
         level_t *f = &lev[L], *c = &lev[L + 1];
@@ -510,18 +515,115 @@ int orc_partition(const orc_graph *g, int32_t k, double eps, const orc_params *p
         c->g = (orc_graph){nc, c->xadj, c->adjncy, c->adjwgt, c->vwgt};
         if (nc == fn) {
             free(c->xadj); free(c->adjncy); free(c->adjwgt); free(c->vwgt); free(f->f2c);
+            memset(c, 0, sizeof(*c));
             f->f2c = NULL;
             break;
         }
         L++;
         if ((int64_t)p->stall_den * nc > (int64_t)p->stall_num * fn) break;
     }
+    h->lev = lev;
+    h->L = L;
+    h->newid = newid;
+    h->lmax = lmax;
+    h->ucl = ucl;
+    h->ev_cluster = ev_cluster;
+}
 
-    /* initial partition on the coarsest level, then refine every level */
+static void free_hierarchy(hierarchy_t *h) {
+    for (int32_t l = 0; l <= h->L; l++) {
+        free(h->lev[l].xadj); free(h->lev[l].adjncy); free(h->lev[l].adjwgt); free(h->lev[l].vwgt);
+        free(h->lev[l].f2c);
+    }
+    free(h->lev);
+    free(h->newid);
+}
+
+/*
+ * Initial partition of the coarsest graph (§III-B), with the project's
+ * learned proposal when asked for: the network's argmax assignment goes
+ * through the same LP refinement and rebalance as every bisection try and is
+ * kept iff it is balanced and either the plain result is not balanced or the
+ * proposal cuts no more edge weight (ties keep the proposal). A proposal with
+ * a non-finite logit is discarded before refinement.
+ */
+static void initial_with_judge(const orc_graph *gc, int32_t k, int64_t lmax, const orc_params *p, int32_t *P,
+                               orc_result *res) {
+    int32_t nc = gc->n;
+    if (nc > 0)
+        orc_initial_partition(gc, k, lmax, p->seed, p->attempts, p->rounds_refine, p->dir_alternate, P);
+    int32_t tried = 0, kept = 0;
+    int64_t pcut = -1, lcut = -1;
+    if (p->init_mode == 1 && nc > 0 && nc <= p->mpnn_max_n && p->mpnn_params) {
+        tried = 1;
+        pcut = orc_cut(gc, P);
+        int64_t *B = (int64_t *)xcalloc((size_t)k, sizeof(int64_t));
+        orc_block_weights(gc, P, k, B);
+        int pbal = 1;
+        for (int32_t b = 0; b < k; b++) if (B[b] > lmax) pbal = 0;
+        free(B);
+        float *Z = (float *)xcalloc((size_t)nc * k, sizeof(float));
+        int32_t *Pl = (int32_t *)xcalloc((size_t)nc, sizeof(int32_t));
+        orc_mpnn_infer(gc, k, p->mpnn_params, p->mpnn_seed, Z, Pl);
+        int finite = 1;
+        for (int64_t i = 0; i < (int64_t)nc * k; i++) if (!isfinite(Z[i])) finite = 0;
+        if (finite) {
+            orc_lp_refine(gc, k, lmax, p->rounds_refine, p->dir_alternate, Pl, NULL);
+            int lbal = orc_rebalance(gc, k, lmax, Pl);
+            lcut = orc_cut(gc, Pl);
+            if (lbal && (!pbal || lcut <= pcut)) {
+                kept = 1;
+                memcpy(P, Pl, sizeof(int32_t) * (size_t)nc);
+            }
+        }
+        free(Z);
+        free(Pl);
+    }
+    if (res) {
+        res->learned_tried = tried;
+        res->learned_kept = kept;
+        res->plain_cut_coarsest = pcut;
+        res->learned_cut_coarsest = lcut;
+    }
+}
+
+int orc_coarsest(const orc_graph *g, int32_t k, double eps, const orc_params *p, int32_t *xadj_c,
+                 int32_t *adjncy_c, int32_t *adjwgt_c, int32_t *vwgt_c, int32_t *part_c, int32_t *n_c,
+                 int32_t *nnz_c) {
+    hierarchy_t h;
+    coarsen(g, k, eps, p, &h);
+    const orc_graph *gc = &h.lev[h.L].g;
+    int32_t nc = gc->n, nnzc = gc->xadj[nc];
+    memcpy(xadj_c, gc->xadj, sizeof(int32_t) * ((size_t)nc + 1));
+    memcpy(adjncy_c, gc->adjncy, sizeof(int32_t) * (size_t)nnzc);
+    memcpy(adjwgt_c, gc->adjwgt, sizeof(int32_t) * (size_t)nnzc);
+    memcpy(vwgt_c, gc->vwgt, sizeof(int32_t) * (size_t)nc);
+    initial_with_judge(gc, k, h.lmax, p, part_c, NULL);
+    *n_c = nc;
+    *nnz_c = nnzc;
+    free_hierarchy(&h);
+    return 0;
+}
+
+/*
+ * §III multilevel scheme: coarsen (above), initial partition of the coarsest
+ * level, then project and refine every level with U = L_max (§III-C); the
+ * vertices without neighbours are filled in at the end.
+ */
+int orc_partition(const orc_graph *g, int32_t k, double eps, const orc_params *p,
+                  int32_t *part_out, orc_result *res) {
+    int32_t n = g->n;
+    hierarchy_t h;
+    coarsen(g, k, eps, p, &h);
+    level_t *lev = h.lev;
+    int32_t L = h.L;
+    int64_t lmax = h.lmax;
+
     int32_t *P = (int32_t *)xcalloc((size_t)lev[L].g.n, sizeof(int32_t));
-    if (lev[L].g.n > 0)
-        orc_initial_partition(&lev[L].g, k, lmax, p->seed, p->attempts, p->rounds_refine,
-                              p->dir_alternate, P);
+    orc_result tmp;
+    memset(&tmp, 0, sizeof(tmp));
+    initial_with_judge(&lev[L].g, k, lmax, p, P, &tmp);
+    int64_t ev_refine = 0;
     for (int32_t l = L; l >= 0; l--) {
         if (l < L) {
             int32_t *Pf = (int32_t *)xcalloc((size_t)lev[l].g.n, sizeof(int32_t));
@@ -538,7 +640,8 @@ int orc_partition(const orc_graph *g, int32_t k, double eps, const orc_params *p
     int64_t *B = (int64_t *)xcalloc((size_t)k, sizeof(int64_t));
     int32_t niso = 0;
     for (int32_t v = 0; v < n; v++) {
-        if (newid[v] >= 0) { part_out[v] = P[newid[v]]; B[P[newid[v]]] += VW(g, v); }
+        int32_t i = h.newid[v];
+        if (i >= 0) { part_out[v] = P[i]; B[P[i]] += VW(g, v); }
         else { part_out[v] = -1; niso++; }
     }
     orc_fill_isolated(g, k, part_out, B);
@@ -546,24 +649,20 @@ int orc_partition(const orc_graph *g, int32_t k, double eps, const orc_params *p
     int64_t maxb = 0;
     for (int32_t b = 0; b < k; b++) if (B[b] > maxb) maxb = B[b];
     if (res) {
+        *res = tmp;
         res->cut = orc_cut(g, part_out);
         res->max_block_w = maxb;
         res->lmax = lmax;
-        res->ucl = ucl;
+        res->ucl = h.ucl;
         res->balanced = maxb <= lmax;
         res->levels = L + 1;
-        res->edge_visits_cluster = ev_cluster;
+        res->edge_visits_cluster = h.ev_cluster;
         res->edge_visits_refine = ev_refine;
         res->coarsest_n = lev[L].g.n;
         res->n_isolated = niso;
     }
-    for (int32_t l = 0; l <= L; l++) {
-        free(lev[l].xadj); free(lev[l].adjncy); free(lev[l].adjwgt); free(lev[l].vwgt);
-        free(lev[l].f2c);
-    }
-    free(lev);
+    free_hierarchy(&h);
     free(P);
     free(B);
-    free(newid);
     return (maxb <= lmax) ? 0 : 1;
 }

@@ -46,6 +46,10 @@ typedef struct {
     int32_t stall_den;        /* 20 */
     int32_t dir_alternate;    /* 1 */
     uint64_t seed;
+    int32_t init_mode;        /* 0 plain, 1 learned proposal judged against the plain one */
+    int32_t mpnn_max_n;       /* learned proposal only when the coarsest graph has <= this many vertices */
+    uint64_t mpnn_seed;       /* probe features */
+    const float *mpnn_params; /* fp32 master weights (see orc_mpnn_param_count) */
 } orc_params;
 
 typedef struct {
@@ -53,6 +57,8 @@ typedef struct {
     int32_t balanced, levels;
     int64_t edge_visits_cluster, edge_visits_refine;
     int32_t coarsest_n, n_isolated;
+    int32_t learned_tried, learned_kept;
+    int64_t plain_cut_coarsest, learned_cut_coarsest;
 } orc_result;
 
 int64_t orc_lmax(int64_t total_vwgt, int32_t k, double eps);
@@ -93,6 +99,28 @@ void orc_fill_isolated(const orc_graph *g, int32_t k, int32_t *part, int64_t *B)
 
 int orc_partition(const orc_graph *g, int32_t k, double eps, const orc_params *p,
                   int32_t *part_out, orc_result *res);
+
+/* Coarsest graph of the multilevel scheme (renumbered, without the vertices
+ * that have no neighbour) and its initial partition, as orc_partition computes
+ * them. Buffers sized as the input graph (n+1, nnz, nnz, n, n). */
+int orc_coarsest(const orc_graph *g, int32_t k, double eps, const orc_params *p, int32_t *xadj_c,
+                 int32_t *adjncy_c, int32_t *adjwgt_c, int32_t *vwgt_c, int32_t *part_c, int32_t *n_c,
+                 int32_t *nnz_c);
+
+/* Message-passing network for the learned initial partition (project addition;
+ * it proposes the k-way assignment of the coarsest graph, §III-B's slot).
+ * Features (18 per vertex): c(v)/c_max, deg(v)/max degree, 16 seeded +-1
+ * probes smoothed by 8 lazy random-walk steps y <- (y + D^-1 A y) / 2.
+ * Three layers h' = ReLU(b + Ws h + Wn m), m = (sum_u w(v,u) h_u) / sum_u w(v,u),
+ * widths 18 -> 64 -> 64 -> 64, then z = bh + Wh h (k logits); block = argmax
+ * (ties -> lowest). Weights are used rounded to bfloat16 (nearest-even);
+ * sums are binary32 fused multiply-add chains in a fixed order (neighbours in
+ * CSR order, inputs in index order). */
+int32_t orc_mpnn_param_count(int32_t k);
+float orc_bf16(float x);
+void orc_mpnn_features(const orc_graph *g, uint64_t seed, float *X /* [n*18] */);
+void orc_mpnn_infer(const orc_graph *g, int32_t k, const float *params, uint64_t seed, float *Z /* [n*k] */,
+                    int32_t *part);
 
 #ifdef __cplusplus
 }
