@@ -59,6 +59,10 @@ extern "C" {
 #define GP_ERR_OVERFLOW (-4)  /* nnz >= 2^31 or a weight sum that does not fit its type */
 #define GP_ERR_HIP (-5)       /* a HIP runtime call failed */
 
+/* Initial partitioning of the coarsest graph (gp_params.init_mode). */
+#define GP_INIT_PLAIN 0   /* best of `attempts` recursive bisections (§III-B) */
+#define GP_INIT_LEARNED 1 /* plus the network's proposal, judged against them */
+
 /* G = (V, E, c, w) of §II-A. n vertices, nnz = 2|E| directed CSR entries. */
 typedef struct {
     int32_t n;
@@ -86,6 +90,10 @@ typedef struct {
     int32_t stall_den;      /* 20 */
     int32_t dir_alternate;  /* 1: direction alternation of synchronous rounds */
     uint64_t seed;          /* start-vertex hash of the initial bisections */
+    int32_t init_mode;      /* GP_INIT_PLAIN; GP_INIT_LEARNED adds the network's proposal */
+    int32_t mpnn_max_n;     /* 65536: the proposal is tried only on coarsest graphs this small */
+    uint64_t mpnn_seed;     /* 0: seed of the network's probe features */
+    const float *mpnn_params; /* NULL: device fp32 master weights, gp_mpnn_param_count(k) of them */
 } gp_params;
 
 typedef struct {
@@ -100,6 +108,10 @@ typedef struct {
     int64_t edge_visits_cluster; /* sum over levels of rounds_run * nnz in clustering */
     int64_t edge_visits_refine;  /* same for refinement */
     float ms_coarsen, ms_init, ms_refine, ms_total; /* device-timed phases */
+    int32_t learned_tried;        /* GP_INIT_LEARNED and the coarsest graph within mpnn_max_n */
+    int32_t learned_kept;         /* the proposal replaced the plain initial partition */
+    int64_t plain_cut_coarsest;   /* cut of the best plain try on the coarsest graph (-1: not tried) */
+    int64_t learned_cut_coarsest; /* cut of the refined proposal (-1: not tried or discarded) */
 } gp_result;
 
 void gp_default_params(gp_params *p);
@@ -156,11 +168,80 @@ int gp_cut_and_blocks(const gp_graph *g, int32_t k, const int32_t *part, int64_t
  * refinement and a greedy rebalance), then project and refine every level
  * with U = L_max, and place vertices without neighbours, in ascending id,
  * into the currently lightest block.
+ * With init_mode = GP_INIT_LEARNED (a project addition in the slot of §III-B)
+ * and a coarsest graph of at most mpnn_max_n vertices, the network of
+ * gp_mpnn_forward also proposes an assignment of the coarsest graph (its
+ * argmax); the proposal goes through the same LP refinement and rebalance as
+ * every bisection try and replaces the best plain try iff it is balanced and
+ * either the plain try is not or it cuts no more edge weight (ties keep the
+ * proposal). A proposal with a NaN or infinite logit is discarded. Requires
+ * k <= 64 and mpnn_params.
  * part_out: [n] device int32 in [0, k). res_host may be NULL.
  * Returns GP_OK, GP_WARN_IMBALANCED, or an error.
  */
 int gp_partition(const gp_graph *g, int32_t k, double eps, const gp_params *p, int32_t *part_out,
                  gp_result *res_host, hipStream_t stream);
+
+/*
+ * The coarsest graph of gp_partition's hierarchy and its initial partition
+ * (the pairs the learned proposal is trained on). Vertices without
+ * neighbours are left out and the others renumbered in ascending order when
+ * no coarsening happened. Outputs (device, sized as the input graph): xadj_c
+ * [n+1], adjncy_c [nnz], adjwgt_c [nnz], vwgt_c [n], part_c [n] in [0, k);
+ * n_c_host / nnz_c_host receive the sizes.
+ */
+int gp_coarsest(const gp_graph *g, int32_t k, double eps, const gp_params *p, int32_t *xadj_c, int32_t *adjncy_c,
+                int32_t *adjwgt_c, int32_t *vwgt_c, int32_t *part_c, int32_t *n_c_host, int32_t *nnz_c_host,
+                hipStream_t stream);
+
+/*
+ * The learned initial partition's network (a project addition; it fills the
+ * slot of §III-B's initial partitioning). Per vertex v:
+ *   features  X[v] = (c(v)/c_max, deg(v)/max deg, y_8[v][0..15]); y_0 = 16
+ *             seeded +-1 probes (splitmix64 of splitmix64(seed) ^ (16 v + j),
+ *             sign from the top bit), y_{t+1}[v] = (y_t[v] + sum_u w(v,u) y_t[u] / d(v)) / 2
+ *             with d(v) the weighted degree (a vertex without neighbours keeps y);
+ *   layers    h_l = ReLU(b_l + Ws_l h_{l-1}[v] + Wn_l m_l[v]), m_l[v] = sum_u w(v,u) h_{l-1}[u] / d(v)
+ *             (0 without neighbours), widths 18 -> 64 -> 64 -> 64;
+ *   head      z[v] = bh + Wh h_3[v] (k logits), block = argmax, ties -> lowest.
+ * Parameters (fp32 master weights, flat, device): per layer Ws [64][d_in],
+ * Wn [64][d_in], b [64]; then Wh [k][64], bh [k]; row-major, output index
+ * first. gp_mpnn_param_count(k) of them (19,920 for k = 16), 1 <= k <= 64
+ * (returns -1 otherwise). The forward pass uses them rounded to bfloat16
+ * (nearest, ties to even) and is bit-reproducible: sums are binary32 fused
+ * multiply-add chains in a fixed order (neighbours in CSR order, inputs in
+ * index order after the bias, self before aggregated inputs); 1/d(v) and the
+ * two ratio features are binary64 divisions rounded once.
+ */
+int32_t gp_mpnn_param_count(int32_t k);
+
+/* Features X: [n*18] device float (row-major per vertex). */
+int gp_mpnn_features(const gp_graph *g, uint64_t seed, float *X, hipStream_t stream);
+
+/* Logits Z [n*k] and argmax blocks part [n] (device; either may be NULL). */
+int gp_mpnn_forward(const gp_graph *g, int32_t k, const float *params, uint64_t seed, float *Z, int32_t *part,
+                    hipStream_t stream);
+
+/*
+ * Training loss and gradient (binary32, within tolerance of the exact
+ * gradient). With S = softmax(z) per vertex, target t [n] in [0, k) (device):
+ *   edge  = (1/Omega) sum over directed CSR entries (v,u) of w(v,u) BCE(p, [t_v == t_u]),
+ *           p = <S_v, S_u> clipped to [1e-6, 1 - 1e-6] (zero gradient outside),
+ *           Omega = sum of all entries of adjwgt;
+ *   bal   = lam * k * sum_c (Q_c - 1/k)^2, Q_c = sum_v c(v) S_v[c] / c(V).
+ * grad: [P] device float, overwritten with d(edge + bal)/d(weights) taken at
+ * the bfloat16-rounded weights. loss_host (may be NULL): {edge, bal}.
+ */
+int gp_mpnn_backward(const gp_graph *g, int32_t k, const float *params, uint64_t seed, const int32_t *target,
+                     float lam, float *grad, double *loss_host, hipStream_t stream);
+
+/*
+ * Adam on the master weights (device arrays of `count` floats): m = b1 m +
+ * (1-b1) g, v = b2 v + (1-b2) g^2, w -= lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps).
+ * step >= 1 counts the updates made so far including this one.
+ */
+int gp_mpnn_adam_step(float *params, float *m, float *v, const float *grad, int32_t count, int32_t step, float lr,
+                      float beta1, float beta2, float eps, hipStream_t stream);
 
 /*
  * Batched form (a project addition; §III scheme per graph): G independent

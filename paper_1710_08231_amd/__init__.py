@@ -20,7 +20,7 @@ import subprocess
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _ROOT = os.path.dirname(_HERE)
 LIB_PATH = os.path.join(_HERE, "libgp.so")
-SOURCES = ["lp.hip", "contract.hip", "initpart.hip", "partition.hip", "batch.hip"]
+SOURCES = ["lp.hip", "contract.hip", "initpart.hip", "partition.hip", "batch.hip", "mpnn.hip"]
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
@@ -56,7 +56,9 @@ class Params(ctypes.Structure):
     _fields_ = [("rounds_coarsen", ctypes.c_int32), ("rounds_refine", ctypes.c_int32),
                 ("coarsest_per_k", ctypes.c_int32), ("attempts", ctypes.c_int32),
                 ("stall_num", ctypes.c_int32), ("stall_den", ctypes.c_int32),
-                ("dir_alternate", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("dir_alternate", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("init_mode", ctypes.c_int32), ("mpnn_max_n", ctypes.c_int32),
+                ("mpnn_seed", ctypes.c_uint64), ("mpnn_params", ctypes.c_void_p)]
 
 
 class Result(ctypes.Structure):
@@ -65,12 +67,15 @@ class Result(ctypes.Structure):
                 ("coarsest_n", ctypes.c_int32), ("n_isolated", ctypes.c_int32),
                 ("edge_visits_cluster", ctypes.c_int64), ("edge_visits_refine", ctypes.c_int64),
                 ("ms_coarsen", ctypes.c_float), ("ms_init", ctypes.c_float),
-                ("ms_refine", ctypes.c_float), ("ms_total", ctypes.c_float)]
+                ("ms_refine", ctypes.c_float), ("ms_total", ctypes.c_float),
+                ("learned_tried", ctypes.c_int32), ("learned_kept", ctypes.c_int32),
+                ("plain_cut_coarsest", ctypes.c_int64), ("learned_cut_coarsest", ctypes.c_int64)]
 
 
 EXPORTS = ["gp_default_params", "gp_lmax", "gp_lp_cluster", "gp_lp_refine", "gp_contract",
            "gp_project", "gp_cut_and_blocks", "gp_partition", "gp_partition_batch", "gp_strerror", "gp_last_error",
-           "gp_profile_enable", "gp_profile_select", "gp_profile_count", "gp_profile_get"]
+           "gp_profile_enable", "gp_profile_select", "gp_profile_count", "gp_profile_get", "gp_coarsest",
+           "gp_mpnn_param_count", "gp_mpnn_features", "gp_mpnn_forward", "gp_mpnn_backward", "gp_mpnn_adam_step"]
 
 
 def load():
@@ -95,6 +100,16 @@ def load():
                                  ctypes.POINTER(Result), vp]
     lib.gp_partition_batch.argtypes = [G, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.c_double,
                                        ctypes.POINTER(Params), vp, ctypes.POINTER(Result), vp]
+    lib.gp_coarsest.argtypes = [G, i32, ctypes.c_double, ctypes.POINTER(Params), vp, vp, vp, vp, vp,
+                                ctypes.POINTER(i32), ctypes.POINTER(i32), vp]
+    lib.gp_mpnn_param_count.restype = i32
+    lib.gp_mpnn_param_count.argtypes = [i32]
+    lib.gp_mpnn_features.argtypes = [G, ctypes.c_uint64, vp, vp]
+    lib.gp_mpnn_forward.argtypes = [G, i32, vp, ctypes.c_uint64, vp, vp, vp]
+    lib.gp_mpnn_backward.argtypes = [G, i32, vp, ctypes.c_uint64, vp, ctypes.c_float, vp,
+                                     ctypes.POINTER(ctypes.c_double), vp]
+    lib.gp_mpnn_adam_step.argtypes = [vp, vp, vp, vp, i32, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                      ctypes.c_float, vp]
     lib.gp_strerror.restype = ctypes.c_char_p
     lib.gp_strerror.argtypes = [ctypes.c_int]
     lib.gp_last_error.restype = ctypes.c_char_p
@@ -216,12 +231,23 @@ def cut_and_blocks(g, part, k):
     return cut.value, B
 
 
+def _params(params):
+    """gp_params from keyword overrides; mpnn_params is a float32 CUDA tensor (kept alive by the caller)."""
+    torch = _torch()
+    p = default_params()
+    for key, val in params.items():
+        if key == "mpnn_params":
+            if val is not None and (val.dtype != torch.float32 or not val.is_cuda or not val.is_contiguous()):
+                raise GPError("mpnn_params must be a contiguous float32 CUDA tensor")
+            val = None if val is None else val.data_ptr()
+        setattr(p, key, val)
+    return p
+
+
 def partition(g, k, eps=0.03, **params):
     torch = _torch()
     gs = _gstruct(g)
-    p = default_params()
-    for key, val in params.items():
-        setattr(p, key, val)
+    p = _params(params)
     part = torch.empty(max(gs.n, 1), dtype=torch.int32, device=g["xadj"].device)
     r = Result()
     code = _check(load().gp_partition(ctypes.byref(gs), k, eps, ctypes.byref(p), _ptr(part), ctypes.byref(r),
@@ -261,9 +287,7 @@ def partition_batch(g, vtx_off, ks, eps=0.03, **params):
     torch = _torch()
     gs = _gstruct(g)
     G = len(ks)
-    p = default_params()
-    for key, val in params.items():
-        setattr(p, key, val)
+    p = _params(params)
     part = torch.empty(max(gs.n, 1), dtype=torch.int32, device=g["xadj"].device)
     off = (ctypes.c_int32 * (G + 1))(*vtx_off)
     kk = (ctypes.c_int32 * G)(*ks)
@@ -275,6 +299,81 @@ def partition_batch(g, vtx_off, ks, eps=0.03, **params):
         d = {f: getattr(r, f) for f, _ in Result._fields_}
         out.append(d)
     return part[:gs.n], out, code
+
+
+def coarsest(g, k, eps=0.03, **params):
+    """Coarsest graph of the hierarchy (CSR dict of device tensors) and its initial partition."""
+    torch = _torch()
+    gs = _gstruct(g)
+    p = _params(params)
+    dev = g["xadj"].device
+    xc = torch.empty(gs.n + 1, dtype=torch.int32, device=dev)
+    ac = torch.empty(max(gs.nnz, 1), dtype=torch.int32, device=dev)
+    wc = torch.empty(max(gs.nnz, 1), dtype=torch.int32, device=dev)
+    vc = torch.empty(max(gs.n, 1), dtype=torch.int32, device=dev)
+    pc = torch.empty(max(gs.n, 1), dtype=torch.int32, device=dev)
+    nc, nnzc = ctypes.c_int32(), ctypes.c_int32()
+    _check(load().gp_coarsest(ctypes.byref(gs), k, eps, ctypes.byref(p), _ptr(xc), _ptr(ac), _ptr(wc), _ptr(vc),
+                              _ptr(pc), ctypes.byref(nc), ctypes.byref(nnzc), _stream()))
+    nc, nnzc = nc.value, nnzc.value
+    return {"xadj": xc[:nc + 1], "adjncy": ac[:nnzc], "adjwgt": wc[:nnzc], "vwgt": vc[:nc]}, pc[:nc]
+
+
+def mpnn_param_count(k):
+    n = int(load().gp_mpnn_param_count(k))
+    if n < 0:
+        raise GPError("the network's head supports 1 <= k <= 64")
+    return n
+
+
+def _fparams(params, k):
+    torch = _torch()
+    if params.dtype != torch.float32 or not params.is_cuda or not params.is_contiguous():
+        raise GPError("params must be a contiguous float32 CUDA tensor")
+    if params.numel() != mpnn_param_count(k):
+        raise GPError(f"params must hold {mpnn_param_count(k)} floats for k={k}")
+    return _ptr(params)
+
+
+def mpnn_features(g, seed=0):
+    torch = _torch()
+    gs = _gstruct(g)
+    X = torch.empty((max(gs.n, 1), 18), dtype=torch.float32, device=g["xadj"].device)
+    _check(load().gp_mpnn_features(ctypes.byref(gs), seed, _ptr(X), _stream()))
+    return X[:gs.n]
+
+
+def mpnn_forward(g, k, params, seed=0):
+    """(logits [n, k], argmax blocks [n]) of the network with bfloat16-rounded weights."""
+    torch = _torch()
+    gs = _gstruct(g)
+    dev = g["xadj"].device
+    Z = torch.empty((max(gs.n, 1), k), dtype=torch.float32, device=dev)
+    P = torch.empty(max(gs.n, 1), dtype=torch.int32, device=dev)
+    _check(load().gp_mpnn_forward(ctypes.byref(gs), k, _fparams(params, k), seed, _ptr(Z), _ptr(P), _stream()))
+    return Z[:gs.n], P[:gs.n]
+
+
+def mpnn_backward(g, k, params, target, seed=0, lam=1.0, grad=None):
+    """(gradient [P] float32, (edge loss, balance loss)) for a target partition."""
+    torch = _torch()
+    gs = _gstruct(g)
+    if grad is None:
+        grad = torch.empty(mpnn_param_count(k), dtype=torch.float32, device=params.device)
+    t = target.to(dtype=torch.int32).contiguous()
+    loss = (ctypes.c_double * 2)()
+    _check(load().gp_mpnn_backward(ctypes.byref(gs), k, _fparams(params, k), seed, _ptr(t), lam, _ptr(grad), loss,
+                                   _stream()))
+    return grad, (loss[0], loss[1])
+
+
+def mpnn_adam_step(params, m, v, grad, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update of params in place (m, v: moment tensors of the same size)."""
+    for t in (params, m, v, grad):
+        if t.numel() != params.numel() or not t.is_contiguous():
+            raise GPError("params, m, v and grad must be contiguous and of one size")
+    _check(load().gp_mpnn_adam_step(_ptr(params), _ptr(m), _ptr(v), _ptr(grad), params.numel(), step, lr, beta1,
+                                    beta2, eps, _stream()))
 
 
 def profile_enable(on=True):

@@ -420,6 +420,10 @@ int partition_batch(const DevGraph &g0, int32_t G, const int32_t *voff_host, con
         r.ms_init = ms_init;
         r.ms_refine = ms_ref;
         r.ms_total = ms_total;
+        r.learned_tried = 0;
+        r.learned_kept = 0;
+        r.plain_cut_coarsest = -1;
+        r.learned_cut_coarsest = -1;
     }
     return all_bal ? GP_OK : GP_WARN_IMBALANCED;
 }

@@ -380,9 +380,11 @@ __global__ void k_copy_cut(int32_t n, int32_t attempts, int32_t G, const int32_t
     }
 }
 
-// best try per graph by (imbalanced, cut, try index)
-__global__ void k_pick_tries(int32_t G, int32_t attempts, const unsigned long long *cuts, const int32_t *balanced,
-                             int32_t *chosen) {
+// best plain try per graph by (imbalanced, cut, try index); with an extra
+// proposal (try index `attempts`), it replaces the best plain try iff it is
+// balanced and the plain one is not, or it cuts no more edge weight.
+__global__ void k_pick_tries(int32_t G, int32_t attempts, bool has_extra, const unsigned long long *cuts,
+                             const int32_t *balanced, int32_t *chosen, int32_t *best_plain) {
     for (int32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < G; g += gridDim.x * blockDim.x) {
         int32_t b = 0;
         for (int a = 1; a < attempts; a++) {
@@ -390,8 +392,21 @@ __global__ void k_pick_tries(int32_t G, int32_t attempts, const unsigned long lo
             const bool better = (balanced[ia] && !balanced[ib]) || (balanced[ia] == balanced[ib] && cuts[ia] < cuts[ib]);
             if (better) b = a;
         }
+        best_plain[g] = b;
+        if (has_extra) {
+            const int64_t ie = (int64_t)attempts * G + g, ib = (int64_t)b * G + g;
+            if (balanced[ie] && (!balanced[ib] || cuts[ie] <= cuts[ib])) b = attempts;
+        }
         chosen[g] = b;
     }
+}
+
+// the extra proposal becomes try `attempts`: global block ids kbase[q] + b
+__global__ void k_inject(int32_t n, int32_t attempts, const int32_t *xadj, bool skip_isolated, const int32_t *gid,
+                         const int32_t *kbase, const int32_t *extra, int32_t *blk) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        blk[(int64_t)attempts * n + v] =
+            (skip_isolated && xadj[v + 1] == xadj[v]) ? -1 : kbase[gid[v]] + extra[v];
 }
 
 __global__ void k_pick_write(int32_t n, int32_t ktot, const int32_t *gid, const int32_t *chosen, const int32_t *ulab,
@@ -613,10 +628,12 @@ __global__ void k_iso_serial_batch(const int32_t *iso, const int32_t *iso_first,
 
 int initial_partition_batch(const DevGraph &g, bool skip_isolated, const BatchInfo &bi, uint64_t seed,
                             int32_t attempts, int32_t rounds_refine, int32_t dir_alternate, bool wide, int32_t *part,
-                            Scratch &sc) {
+                            Scratch &sc, const int32_t *extra, ProposalOut *po) {
     hipStream_t s = sc.stream();
     const int32_t n = g.n, nnz = g.nnz, G = bi.G;
     if (n == 0) return GP_OK;
+    const int32_t bis = attempts;             // bisection tries
+    if (extra) attempts += 1;                 // the proposal is one more try
     const int32_t ktot = bi.kbase[G];
     int32_t kmax = 1;
     for (int32_t q = 0; q < G; q++) kmax = std::max(kmax, bi.k[q]);
@@ -692,10 +709,15 @@ int initial_partition_batch(const DevGraph &g, bool skip_isolated, const BatchIn
         GP_HIP(hipMemcpyAsync(reg, hr.data(), sizeof(int64_t) * hr.size(), hipMemcpyHostToDevice, s));
         BisectArgs a{n,    g.xadj, g.adjncy, g.vwgt, blk,        mark,       claim,           slist,
                      order, pre,   reg,      off,    sg,   sb, sk, bi.d_voff, bi.d_kbase, (int32_t)d.size(), seed};
-        hipLaunchKernelGGL(k_bisect, dim3((unsigned)(d.size() * attempts)), dim3(kBB), 0, s, a);
+        hipLaunchKernelGGL(k_bisect, dim3((unsigned)(d.size() * bis)), dim3(kBB), 0, s, a);
         GP_LAUNCH_CHECK();
         // host vectors are reused next depth: make sure the copies have been consumed
         GP_HIP(hipStreamSynchronize(s));
+    }
+    if (extra) {
+        hipLaunchKernelGGL(k_inject, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, n, bis, g.xadj, skip_isolated,
+                           bi.d_gid, bi.d_kbase, extra, blk);
+        GP_LAUNCH_CHECK();
     }
 
     // ---- refine all tries of all graphs at once on the disjoint union
@@ -729,12 +751,13 @@ int initial_partition_batch(const DevGraph &g, bool skip_isolated, const BatchIn
     GP_TRY(lp_run(ug, ul, W, NL, bi.lmax[0], rounds_refine, dir_alternate, wide, nullptr, sc, cap));
 
     // ---- rebalance each (try, graph), pick the best try per graph
-    int32_t *bal = nullptr, *ch = nullptr;
+    int32_t *bal = nullptr, *ch = nullptr, *bp = nullptr;
     unsigned long long *cuts = nullptr;
     const int64_t TG = (int64_t)attempts * G;
     GP_TRY(sc.alloc(&bal, TG));
     GP_TRY(sc.alloc(&cuts, TG));
     GP_TRY(sc.alloc(&ch, G));
+    GP_TRY(sc.alloc(&bp, G));
     GP_HIP(hipMemsetAsync(cuts, 0, sizeof(unsigned long long) * TG, s));
     const size_t dyn = sizeof(int64_t) * (size_t)kmax * (1 + kRB / kWave);
     GP_HIP(hipFuncSetAttribute((const void *)k_rebalance, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
@@ -744,9 +767,26 @@ int initial_partition_batch(const DevGraph &g, bool skip_isolated, const BatchIn
     hipLaunchKernelGGL(k_copy_cut, dim3(grid_for(NV, 256, 65536)), dim3(256), 0, s, n, attempts, G, bi.d_gid, ux, ua,
                        uw, ul, cuts);
     GP_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_pick_tries, dim3(grid_for(G, 256, 1024)), dim3(256), 0, s, G, attempts, cuts, bal, ch);
+    hipLaunchKernelGGL(k_pick_tries, dim3(grid_for(G, 256, 1024)), dim3(256), 0, s, G, bis, extra != nullptr, cuts,
+                       bal, ch, bp);
     hipLaunchKernelGGL(k_pick_write, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, n, ktot, bi.d_gid, ch, ul, part);
     GP_LAUNCH_CHECK();
+    if (extra && po) {
+        std::vector<unsigned long long> hc(TG);
+        std::vector<int32_t> hch(G), hbp(G);
+        GP_HIP(hipMemcpyAsync(hc.data(), cuts, sizeof(unsigned long long) * TG, hipMemcpyDeviceToHost, s));
+        GP_HIP(hipMemcpyAsync(hch.data(), ch, sizeof(int32_t) * G, hipMemcpyDeviceToHost, s));
+        GP_HIP(hipMemcpyAsync(hbp.data(), bp, sizeof(int32_t) * G, hipMemcpyDeviceToHost, s));
+        GP_HIP(hipStreamSynchronize(s));
+        po->plain_cut.resize(G);
+        po->prop_cut.resize(G);
+        po->kept.resize(G);
+        for (int32_t q = 0; q < G; q++) {  // k_copy_cut counts each edge from both ends
+            po->plain_cut[q] = (int64_t)(hc[(size_t)hbp[q] * G + q] / 2);
+            po->prop_cut[q] = (int64_t)(hc[(size_t)bis * G + q] / 2);
+            po->kept[q] = hch[q] == bis;
+        }
+    }
     return GP_OK;
 }
 
@@ -759,7 +799,7 @@ int graph_ids(int32_t G, int32_t n, const int32_t *d_voff, int32_t *gid, hipStre
 
 int initial_partition(const DevGraph &g, bool skip_isolated, int32_t k, int64_t lmax, uint64_t seed,
                       int32_t attempts, int32_t rounds_refine, int32_t dir_alternate, bool wide, int32_t *part,
-                      Scratch &sc) {
+                      Scratch &sc, const int32_t *extra, ProposalOut *po) {
     if (g.n == 0) return GP_OK;
     BatchInfo bi;
     bi.G = 1;
@@ -781,7 +821,8 @@ int initial_partition(const DevGraph &g, bool skip_isolated, int32_t k, int64_t 
     bi.d_kbase = dk;
     bi.d_lmax = dl;
     bi.d_gid = gid;
-    return initial_partition_batch(g, skip_isolated, bi, seed, attempts, rounds_refine, dir_alternate, wide, part, sc);
+    return initial_partition_batch(g, skip_isolated, bi, seed, attempts, rounds_refine, dir_alternate, wide, part, sc,
+                                   extra, po);
 }
 
 int fill_isolated(const DevGraph &g, int32_t k, int32_t *part, const int64_t *B, int32_t *niso_host, Scratch &sc) {

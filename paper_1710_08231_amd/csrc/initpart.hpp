@@ -16,18 +16,30 @@ struct BatchInfo {
     const int64_t *d_lmax = nullptr;
 };
 
+// Outcome of an extra (learned) proposal per graph: the cuts (edge weight,
+// each edge once) of the best plain try and of the proposal after the same
+// refinement and rebalance, and whether the proposal was kept.
+struct ProposalOut {
+    std::vector<int64_t> plain_cut, prop_cut;
+    std::vector<int32_t> kept;
+};
+
 // Best of `attempts` tries (recursive BFS bisection -> LP refinement ->
 // greedy rebalance) for every graph of the batch. part: [n] device output,
 // global block ids kbase[q] + b (-1 for vertices left out when
 // skip_isolated is set).
+// extra (optional, device [n], graph-local block ids): one more proposal that
+// goes through the same refinement and rebalance and is kept iff it is
+// balanced and either the best plain try is not balanced or the proposal cuts
+// no more edge weight (ties keep the proposal). `po` receives the outcome.
 int initial_partition_batch(const DevGraph &g, bool skip_isolated, const BatchInfo &bi, uint64_t seed,
                             int32_t attempts, int32_t rounds_refine, int32_t dir_alternate, bool wide, int32_t *part,
-                            Scratch &sc);
+                            Scratch &sc, const int32_t *extra = nullptr, ProposalOut *po = nullptr);
 
 // The same for one graph (blocks [0, k)).
 int initial_partition(const DevGraph &g, bool skip_isolated, int32_t k, int64_t lmax, uint64_t seed,
                       int32_t attempts, int32_t rounds_refine, int32_t dir_alternate, bool wide, int32_t *part,
-                      Scratch &sc);
+                      Scratch &sc, const int32_t *extra = nullptr, ProposalOut *po = nullptr);
 
 // Batched placement of vertices without neighbours: per graph q, its
 // isolated vertices (iso_first[q].. in the ascending list of all isolated

@@ -13,6 +13,7 @@
 
 #include "contract.hpp"
 #include "initpart.hpp"
+#include "mpnn.hpp"
 #include "prims.hpp"
 
 namespace gp {
@@ -138,6 +139,39 @@ struct Level {
     int32_t *f2c = nullptr;  // this level -> next level
 };
 
+// Level-0 graph without its isolated vertices, renumbered in ascending order
+// (rank[v] = new id of a vertex with neighbours).
+__global__ void k_compact_graph(int32_t n, const int32_t *xadj, const int32_t *adjncy, const int32_t *adjwgt,
+                                const int32_t *vwgt, const int32_t *part, const int32_t *rank, int32_t nnz,
+                                int32_t *xc, int32_t *ac, int32_t *wc, int32_t *vc, int32_t *pc) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+        if (xadj[v + 1] == xadj[v]) continue;
+        const int32_t r = rank[v];
+        xc[r] = xadj[v];
+        vc[r] = vwgt ? vwgt[v] : 1;
+        pc[r] = part[v];
+    }
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += stride) {
+        ac[e] = rank[adjncy[e]];
+        wc[e] = adjwgt ? adjwgt[e] : 1;
+    }
+}
+
+__global__ void k_fill_ones(int32_t *a, int64_t count) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = 1;
+}
+
+struct HasNbr {
+    const int32_t *xadj;
+    __device__ bool operator()(int64_t v) const { return xadj[v + 1] > xadj[v]; }
+};
+struct RankOf {
+    int32_t *rank;
+    __device__ void operator()(int64_t v, int32_t pos) const { rank[v] = pos; }
+};
+
 }  // namespace
 
 // Host-side summary of a graph: total vertex weight, max vertex weight,
@@ -207,6 +241,20 @@ static DevGraph dev_graph(const gp_graph *g) {
     return d;
 }
 
+static int check_params(const gp_params *pp, int32_t k, const char *who) {
+    if (pp->rounds_coarsen < 0 || pp->rounds_refine < 0 || pp->attempts < 1 || pp->coarsest_per_k < 1 ||
+        pp->stall_den < 1 || pp->stall_num < 0 || (pp->init_mode != GP_INIT_PLAIN && pp->init_mode != GP_INIT_LEARNED)) {
+        set_error((std::string(who) + ": invalid parameters").c_str());
+        return GP_ERR_ARG;
+    }
+    if (pp->init_mode == GP_INIT_LEARNED && (!pp->mpnn_params || k > kMpMaxK || pp->mpnn_max_n < 0)) {
+        set_error((std::string(who) + ": learned initial partition needs mpnn_params, k <= 64 and mpnn_max_n >= 0")
+                      .c_str());
+        return GP_ERR_ARG;
+    }
+    return GP_OK;
+}
+
 static int64_t lmax_of(int64_t W, int32_t k, double eps) {
     const int64_t q = W / k + (W % k != 0);
     return (int64_t)std::floor((1.0 + eps) * (double)q);
@@ -242,8 +290,48 @@ static bool tracing() {
     return on;
 }
 
+// Caller buffers for the coarsest graph and its initial partition (sized as
+// the input graph); when given, the driver stops after the initial partition.
+struct CoarsestOut {
+    int32_t *xadj, *adjncy, *adjwgt, *vwgt, *part;
+    int32_t n = 0, nnz = 0;
+};
+
+static int write_coarsest(const DevGraph &gc, bool level0, const int32_t *P, CoarsestOut &co, Scratch &sc) {
+    hipStream_t s = sc.stream();
+    const int32_t n = gc.n, nnz = gc.nnz;
+    if (!level0) {  // coarse levels carry explicit weights
+        GP_HIP(hipMemcpyAsync(co.xadj, gc.xadj, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToDevice, s));
+        GP_HIP(hipMemcpyAsync(co.adjncy, gc.adjncy, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToDevice, s));
+        GP_HIP(hipMemcpyAsync(co.adjwgt, gc.adjwgt, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToDevice, s));
+        GP_HIP(hipMemcpyAsync(co.vwgt, gc.vwgt, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
+        GP_HIP(hipMemcpyAsync(co.part, P, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
+        co.n = n;
+        co.nnz = nnz;
+        return GP_OK;
+    }
+    int32_t *rank = nullptr, *cnt = nullptr;
+    GP_TRY(sc.alloc(&rank, n));
+    GP_TRY(sc.alloc(&cnt, 1));
+    GP_TRY(compact(HasNbr{gc.xadj}, RankOf{rank}, n, nullptr, cnt, sc));
+    int32_t n0 = 0;
+    GP_HIP(hipMemcpyAsync(&n0, cnt, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    GP_HIP(hipStreamSynchronize(s));
+    if (n > 0) {
+        hipLaunchKernelGGL(k_compact_graph, dim3(grid_for(std::max(n, nnz), 256, 65536)), dim3(256), 0, s, n, gc.xadj,
+                           gc.adjncy, gc.adjwgt, gc.vwgt, P, rank, nnz, co.xadj, co.adjncy, co.adjwgt, co.vwgt,
+                           co.part);
+        GP_LAUNCH_CHECK();
+    }
+    GP_HIP(hipMemcpyAsync(co.xadj + n0, &nnz, sizeof(int32_t), hipMemcpyHostToDevice, s));
+    GP_HIP(hipStreamSynchronize(s));
+    co.n = n0;
+    co.nnz = nnz;
+    return GP_OK;
+}
+
 static int do_partition(const gp_graph *gin, int32_t k, double eps, const gp_params *p, int32_t *part_out,
-                        gp_result *res, hipStream_t s) {
+                        gp_result *res, hipStream_t s, CoarsestOut *cout = nullptr) {
     Scratch sc(s);
     Timer t_total(s);
     const DevGraph g0 = dev_graph(gin);
@@ -313,15 +401,52 @@ static int do_partition(const gp_graph *gin, int32_t k, double eps, const gp_par
     }
     const float ms_coarse = t_coarse.stop();
 
-    // ---- initial partition of the coarsest graph
+    // ---- initial partition of the coarsest graph, with the learned proposal
+    // (the network's argmax) judged against the plain tries when asked for
     Timer t_init(s);
     const size_t Lc = lev.size() - 1;
-    int32_t *P = nullptr;
-    GP_TRY(sc.alloc(&P, lev[Lc].g.n));
-    GP_TRY(initial_partition(lev[Lc].g, Lc == 0, k, lmax, p->seed, p->attempts, p->rounds_refine, p->dir_alternate,
-                             wide, P, sc));
+    const DevGraph &gc = lev[Lc].g;
+    const int32_t nc_active = Lc == 0 ? (int32_t)(g0.n - gi.niso) : gc.n;
+    int32_t *P = nullptr, *prop = nullptr;
+    GP_TRY(sc.alloc(&P, gc.n));
+    const bool tried = p->init_mode == GP_INIT_LEARNED && nc_active > 0 && nc_active <= p->mpnn_max_n;
+    if (tried) {
+        int32_t *nf = nullptr, hnf = 0;
+        GP_TRY(sc.alloc(&prop, gc.n));
+        GP_TRY(sc.alloc(&nf, 1));
+        GP_HIP(hipMemsetAsync(nf, 0, sizeof(int32_t), s));
+        GP_TRY(mpnn_forward(gc, k, p->mpnn_params, p->mpnn_seed, Lc == 0, nullptr, prop, nf, sc));
+        GP_HIP(hipMemcpyAsync(&hnf, nf, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        GP_HIP(hipStreamSynchronize(s));
+        if (hnf) prop = nullptr;  // a non-finite logit discards the proposal
+    }
+    ProposalOut po;
+    GP_TRY(initial_partition(gc, Lc == 0, k, lmax, p->seed, p->attempts, p->rounds_refine, p->dir_alternate, wide, P,
+                             sc, prop, prop ? &po : nullptr));
+    int64_t plain_cut_c = -1, prop_cut_c = -1;
+    int32_t kept = 0;
+    if (prop) {
+        plain_cut_c = po.plain_cut[0];
+        prop_cut_c = po.prop_cut[0];
+        kept = po.kept[0];
+    } else if (tried) {
+        int32_t *rowc = nullptr;
+        int64_t *dcut = nullptr;
+        GP_TRY(sc.alloc(&rowc, gc.nnz));
+        GP_TRY(sc.alloc(&dcut, 1));
+        if (gc.nnz > 0) GP_TRY(build_rowof(gc, rowc, sc));
+        GP_TRY(cut_dev(gc, P, rowc, dcut, sc));
+        GP_HIP(hipMemcpyAsync(&plain_cut_c, dcut, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        GP_HIP(hipStreamSynchronize(s));
+    }
     const float ms_init = t_init.stop();
-    if (tracing()) std::fprintf(stderr, "[gp] initial partition n=%d nnz=%d %.3f ms\n", lev[Lc].g.n, lev[Lc].g.nnz, ms_init);
+    if (tracing()) std::fprintf(stderr, "[gp] initial partition n=%d nnz=%d %.3f ms\n", gc.n, gc.nnz, ms_init);
+    if (cout) {
+        GP_TRY(write_coarsest(gc, Lc == 0, P, *cout, sc));
+        sc.release();
+        GP_HIP(hipStreamSynchronize(s));
+        return GP_OK;
+    }
 
     // ---- uncoarsening
     Timer t_ref(s);
@@ -383,6 +508,10 @@ static int do_partition(const gp_graph *gin, int32_t k, double eps, const gp_par
         res->ms_init = ms_init;
         res->ms_refine = ms_ref;
         res->ms_total = ms_total;
+        res->learned_tried = tried;
+        res->learned_kept = kept;
+        res->plain_cut_coarsest = plain_cut_c;
+        res->learned_cut_coarsest = prop_cut_c;
     }
     sc.release();
     GP_HIP(hipStreamSynchronize(s));
@@ -405,6 +534,10 @@ void gp_default_params(gp_params *p) {
     p->stall_den = 20;
     p->dir_alternate = 1;
     p->seed = 0;
+    p->init_mode = GP_INIT_PLAIN;
+    p->mpnn_max_n = 65536;
+    p->mpnn_seed = 0;
+    p->mpnn_params = nullptr;
 }
 
 int64_t gp_lmax(int64_t total_vwgt, int32_t k, double eps) {
@@ -571,12 +704,105 @@ int gp_partition(const gp_graph *g, int32_t k, double eps, const gp_params *p, i
     gp_params dp;
     gp_default_params(&dp);
     const gp_params *pp = p ? p : &dp;
-    if (pp->rounds_coarsen < 0 || pp->rounds_refine < 0 || pp->attempts < 1 || pp->coarsest_per_k < 1 ||
-        pp->stall_den < 1 || pp->stall_num < 0) {
-        set_error("partition: invalid parameters");
+    GP_TRY(check_params(pp, k, "partition"));
+    return do_partition(g, k, eps, pp, part_out, res_host, stream);
+}
+
+int gp_coarsest(const gp_graph *g, int32_t k, double eps, const gp_params *p, int32_t *xadj_c, int32_t *adjncy_c,
+                int32_t *adjwgt_c, int32_t *vwgt_c, int32_t *part_c, int32_t *n_c_host, int32_t *nnz_c_host,
+                hipStream_t stream) {
+    GP_TRY(check_graph_args(g));
+    if (k < 1 || !(eps >= 0.0) || !xadj_c || !n_c_host || !nnz_c_host ||
+        (g->n > 0 && (!vwgt_c || !part_c)) || (g->nnz > 0 && (!adjncy_c || !adjwgt_c))) {
+        set_error("coarsest: k < 1, eps < 0 or an output is NULL");
         return GP_ERR_ARG;
     }
-    return do_partition(g, k, eps, pp, part_out, res_host, stream);
+    gp_params dp;
+    gp_default_params(&dp);
+    const gp_params *pp = p ? p : &dp;
+    GP_TRY(check_params(pp, k, "coarsest"));
+    CoarsestOut co{xadj_c, adjncy_c, adjwgt_c, vwgt_c, part_c};
+    GP_TRY(do_partition(g, k, eps, pp, nullptr, nullptr, stream, &co));
+    *n_c_host = co.n;
+    *nnz_c_host = co.nnz;
+    return GP_OK;
+}
+
+int32_t gp_mpnn_param_count(int32_t k) { return k >= 1 && k <= kMpMaxK ? mpnn_param_count(k) : -1; }
+
+int gp_mpnn_features(const gp_graph *g, uint64_t seed, float *X, hipStream_t stream) {
+    GP_TRY(check_graph_args(g));
+    if (g->n > 0 && !X) {
+        set_error("mpnn_features: X is NULL");
+        return GP_ERR_ARG;
+    }
+    Scratch sc(stream);
+    const DevGraph d = dev_graph(g);
+    GraphInfo gi;
+    GP_TRY(graph_info(d, gi, sc));
+    GP_TRY(mpnn_features(d, seed, false, X, nullptr, sc));
+    sc.release();
+    GP_HIP(hipStreamSynchronize(stream));
+    return GP_OK;
+}
+
+int gp_mpnn_forward(const gp_graph *g, int32_t k, const float *params, uint64_t seed, float *Z, int32_t *part,
+                    hipStream_t stream) {
+    GP_TRY(check_graph_args(g));
+    if (k < 1 || k > kMpMaxK || !params || (g->n > 0 && !Z && !part)) {
+        set_error("mpnn_forward: k outside [1, 64], params NULL, or both outputs NULL");
+        return GP_ERR_ARG;
+    }
+    Scratch sc(stream);
+    const DevGraph d = dev_graph(g);
+    GraphInfo gi;
+    GP_TRY(graph_info(d, gi, sc));
+    GP_TRY(mpnn_forward(d, k, params, seed, false, Z, part, nullptr, sc));
+    sc.release();
+    GP_HIP(hipStreamSynchronize(stream));
+    return GP_OK;
+}
+
+int gp_mpnn_backward(const gp_graph *g, int32_t k, const float *params, uint64_t seed, const int32_t *target,
+                     float lam, float *grad, double *loss_host, hipStream_t stream) {
+    GP_TRY(check_graph_args(g));
+    if (k < 1 || k > kMpMaxK || !params || !grad || (g->n > 0 && !target) || !(lam >= 0.0f)) {
+        set_error("mpnn_backward: k outside [1, 64], lam < 0 or a required array is NULL");
+        return GP_ERR_ARG;
+    }
+    Scratch sc(stream);
+    const DevGraph d = dev_graph(g);
+    GraphInfo gi;
+    GP_TRY(graph_info(d, gi, sc));
+    unsigned long long *bad = nullptr;
+    GP_TRY(sc.alloc(&bad, 1));
+    GP_HIP(hipMemsetAsync(bad, 0, sizeof(unsigned long long), stream));
+    if (d.n > 0) {
+        hipLaunchKernelGGL(k_check_labels, dim3(grid_for(d.n, 256, 4096)), dim3(256), 0, stream, target, d.n, k, bad);
+        GP_LAUNCH_CHECK();
+    }
+    unsigned long long hb = 0;
+    GP_HIP(hipMemcpyAsync(&hb, bad, sizeof(hb), hipMemcpyDeviceToHost, stream));
+    GP_HIP(hipStreamSynchronize(stream));
+    if (hb) {
+        set_error("mpnn_backward: a target block id is outside [0, k)");
+        return GP_ERR_GRAPH;
+    }
+    GP_TRY(mpnn_backward(d, k, params, seed, target, lam, grad, loss_host, sc));
+    sc.release();
+    GP_HIP(hipStreamSynchronize(stream));
+    return GP_OK;
+}
+
+int gp_mpnn_adam_step(float *params, float *m, float *v, const float *grad, int32_t count, int32_t step, float lr,
+                      float beta1, float beta2, float eps, hipStream_t stream) {
+    if (!params || !m || !v || !grad || count < 1 || step < 1 || !(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) ||
+        !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f)) {
+        set_error("mpnn_adam_step: NULL array, count < 1, step < 1 or a hyper-parameter out of range");
+        return GP_ERR_ARG;
+    }
+    GP_TRY(mpnn_adam(params, m, v, grad, count, step, lr, beta1, beta2, eps, stream));
+    return GP_OK;
 }
 
 int gp_partition_batch(const gp_graph *g, int32_t G, const int32_t *vtx_off_host, const int32_t *k_host, double eps,
@@ -598,9 +824,9 @@ int gp_partition_batch(const gp_graph *g, int32_t G, const int32_t *vtx_off_host
     gp_params dp;
     gp_default_params(&dp);
     const gp_params *pp = p ? p : &dp;
-    if (pp->rounds_coarsen < 0 || pp->rounds_refine < 0 || pp->attempts < 1 || pp->coarsest_per_k < 1 ||
-        pp->stall_den < 1 || pp->stall_num < 0) {
-        set_error("partition_batch: invalid parameters");
+    GP_TRY(check_params(pp, 1, "partition_batch"));
+    if (pp->init_mode != GP_INIT_PLAIN) {
+        set_error("partition_batch: the learned initial partition is available for single graphs only");
         return GP_ERR_ARG;
     }
     Scratch sc(stream);
