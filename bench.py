@@ -24,6 +24,7 @@ WORKLOADS = {
     "grid256": dict(kind="grid", side=256, seed=3, k=64),
     "rgg16k": dict(kind="rgg", n=16384, seed=1, k=2),
     "batch512": dict(kind="batch", seed=4, count=512, k=None),
+    "learned24": dict(kind="learned", scale=24, k=16),
 }
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
@@ -143,6 +144,60 @@ def bench_batch(args, w):
     print(json.dumps(out), flush=True)
 
 
+def bench_learned(args, w):
+    """R-MAT scale 24, k = 16: the learned initial partition (judged against the
+    plain one) beside the plain form, one seeded graph per step (seeds 0..steps-1)."""
+    import numpy as np
+    import torch
+    import graphgen
+    import paper_1710_08231_amd as gp
+    wpath = os.path.join(ROOT, "paper_1710_08231_amd", "mpnn_k16.npy")
+    params = torch.from_numpy(np.load(wpath).astype(np.float32)).cuda()
+    k = w["k"]
+    rows, visits, t_learned, t_plain = [], 0, 0.0, 0.0
+    for seed in range(args.steps):
+        t0 = time.perf_counter()
+        g = graphgen.rmat(w["scale"], seed)
+        dg = gp.to_device(g)
+        print(f"[bench] seed {seed} generated in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+        if seed == 0:
+            for _ in range(max(1, args.warmup)):
+                gp.partition(dg, k, 0.03)
+                gp.partition(dg, k, 0.03, init_mode=1, mpnn_params=params)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, r0 = gp.partition(dg, k, 0.03)
+        torch.cuda.synchronize()
+        t_plain += time.perf_counter() - t
+        t = time.perf_counter()
+        _, r1 = gp.partition(dg, k, 0.03, init_mode=1, mpnn_params=params)
+        torch.cuda.synchronize()
+        t_learned += time.perf_counter() - t
+        visits += r1["edge_visits_cluster"] + r1["edge_visits_refine"]
+        rows.append({"seed": seed, "plain_cut": r0["cut"], "learned_cut": r1["cut"], "kept": r1["learned_kept"],
+                     "tried": r1["learned_tried"], "coarsest_n": r1["coarsest_n"],
+                     "coarse_cut_plain": r1["plain_cut_coarsest"], "coarse_cut_learned": r1["learned_cut_coarsest"],
+                     "plain_ms": r0["ms_total"], "learned_ms": r1["ms_total"], "init_ms_plain": r0["ms_init"],
+                     "init_ms_learned": r1["ms_init"], "balanced": bool(r1["balanced"])})
+        print(f"[bench] {json.dumps(rows[-1])}", file=sys.stderr, flush=True)
+        del dg
+    ms = t_learned * 1000.0 / args.steps
+    out = {
+        "metric": "LP edge-visits/sec + end-to-end k-way partition time; cut & balance vs oracle",
+        "value": visits / t_learned, "unit": "edge-visits/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": max(1, args.warmup), "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32+fp32", "data": "synthetic",
+        "config": {"workload": "learned24", "graph": "rmat scale 24 ef 16, seeds 0..steps-1", "k": k, "eps": 0.03,
+                   "init": "learned proposal judged against best of 4 bisections"},
+        "partition_ms": ms, "plain_form_ms": t_plain * 1000.0 / args.steps,
+        "cut_total_learned": sum(r["learned_cut"] for r in rows),
+        "cut_total_plain": sum(r["plain_cut"] for r in rows),
+        "proposals_kept": sum(r["kept"] for r in rows),
+        "per_seed": rows,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -163,6 +218,8 @@ def main():
     w = WORKLOADS[args.workload]
     if w["kind"] == "batch":
         return bench_batch(args, w)
+    if w["kind"] == "learned":
+        return bench_learned(args, w)
     t0 = time.perf_counter()
     g = make_graph(w)
     gen_s = time.perf_counter() - t0

@@ -171,7 +171,8 @@ int gp_cut_and_blocks(const gp_graph *g, int32_t k, const int32_t *part, int64_t
  * With init_mode = GP_INIT_LEARNED (a project addition in the slot of §III-B)
  * and a coarsest graph of at most mpnn_max_n vertices, the network of
  * gp_mpnn_forward also proposes an assignment of the coarsest graph (its
- * argmax); the proposal goes through the same LP refinement and rebalance as
+ * logits decoded by gp_mpnn_decode with L_max); the proposal goes through the
+ * same LP refinement and rebalance as
  * every bisection try and replaces the best plain try iff it is balanced and
  * either the plain try is not or it cuts no more edge weight (ties keep the
  * proposal). A proposal with a NaN or infinite logit is discarded. Requires
@@ -193,6 +194,18 @@ int gp_partition(const gp_graph *g, int32_t k, double eps, const gp_params *p, i
 int gp_coarsest(const gp_graph *g, int32_t k, double eps, const gp_params *p, int32_t *xadj_c, int32_t *adjncy_c,
                 int32_t *adjwgt_c, int32_t *vwgt_c, int32_t *part_c, int32_t *n_c_host, int32_t *nnz_c_host,
                 hipStream_t stream);
+
+/*
+ * gp_coarsest for the G graphs of a disjoint-union graph at once (layout as in
+ * gp_partition_batch), through the batched form. The coarsest graphs are
+ * written side by side: graph q owns coarse vertices [vtx_off_c_host[q],
+ * vtx_off_c_host[q+1]) (G+1 host entries) and only edges among them;
+ * part_c holds graph-local block ids. Every graph's result equals gp_coarsest
+ * on that graph alone.
+ */
+int gp_coarsest_batch(const gp_graph *g, int32_t G, const int32_t *vtx_off_host, const int32_t *k_host, double eps,
+                      const gp_params *p, int32_t *xadj_c, int32_t *adjncy_c, int32_t *adjwgt_c, int32_t *vwgt_c,
+                      int32_t *part_c, int32_t *vtx_off_c_host, int32_t *nnz_c_host, hipStream_t stream);
 
 /*
  * The learned initial partition's network (a project addition; it fills the
@@ -221,6 +234,18 @@ int gp_mpnn_features(const gp_graph *g, uint64_t seed, float *X, hipStream_t str
 /* Logits Z [n*k] and argmax blocks part [n] (device; either may be NULL). */
 int gp_mpnn_forward(const gp_graph *g, int32_t k, const float *params, uint64_t seed, float *Z, int32_t *part,
                     hipStream_t stream);
+
+/*
+ * Capacity-respecting decoding of finite logits Z [n*k] (device) into blocks
+ * part [n] (device), under the block bound lmax (the admission rule of an LP
+ * move, §IV-A): every vertex ranks the blocks by logit, highest first (ties
+ * -> lower block); in round r = 0..k-1 every vertex not yet placed offers its
+ * r-th block, and the offers to block t are admitted in ascending vertex id
+ * while B[t] + (weight of all offers to t up to and including v) <= lmax;
+ * vertices still unplaced after k rounds go, in ascending id, to the block
+ * that is lightest at that moment (ties -> lower block). 1 <= k <= 64.
+ */
+int gp_mpnn_decode(const gp_graph *g, int32_t k, const float *Z, int64_t lmax, int32_t *part, hipStream_t stream);
 
 /*
  * Training loss and gradient (binary32, within tolerance of the exact

@@ -103,6 +103,7 @@ def _load():
     lib.orc_bf16.argtypes = [ctypes.c_float]
     lib.orc_mpnn_features.argtypes = [G, ctypes.c_uint64, F32P]
     lib.orc_mpnn_infer.argtypes = [G, ctypes.c_int32, F32P, ctypes.c_uint64, F32P, I32P]
+    lib.orc_mpnn_decode.argtypes = [G, ctypes.c_int32, F32P, ctypes.c_int64, I32P]
     _lib = lib
     return lib
 
@@ -286,6 +287,15 @@ def mpnn_infer(g, k, params, seed=0):
     P = np.zeros(G.n, np.int32)
     _load().orc_mpnn_infer(G.ref, k, w.ctypes.data_as(F32P), seed, Z.ctypes.data_as(F32P), _p32(P))
     return Z, P
+
+
+def mpnn_decode(g, k, Z, lmax_):
+    """Capacity-respecting decoding of logits Z [n, k] under block bound lmax_."""
+    G = _G(g)
+    z = np.ascontiguousarray(Z, dtype=np.float32)
+    P = np.zeros(G.n, np.int32)
+    _load().orc_mpnn_decode(G.ref, k, z.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), lmax_, _p32(P))
+    return P
 
 
 def coarsest(g, k, eps=0.03, **params):

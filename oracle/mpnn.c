@@ -176,3 +176,58 @@ void orc_mpnn_infer(const orc_graph *g, int32_t k, const float *params, uint64_t
     free(Ha);
     free(Hb);
 }
+
+/*
+ * Capacity-respecting decoding of the logits (project-defined): the network's
+ * preferences are admitted under the same rule as a label-propagation move
+ * (§IV-A: a vertex joins a block only while the block stays within its
+ * bound). Every vertex ranks the blocks by logit, highest first (ties ->
+ * lower block). In round r = 0..k-1 every vertex not yet placed proposes its
+ * r-th block; the proposers to block t are admitted in ascending vertex id
+ * while B[t] + (weight of all proposers to t up to and including v) <= L_max.
+ * Vertices still unplaced after k rounds go, in ascending id, to the block
+ * that is lightest at that moment (ties -> lowest block).
+ */
+void orc_mpnn_decode(const orc_graph *g, int32_t k, const float *Z, int64_t lmax, int32_t *part) {
+    const int32_t n = g->n;
+    int32_t *pref = (int32_t *)xmalloc(sizeof(int32_t) * (size_t)n * (size_t)k);
+    for (int32_t v = 0; v < n; v++) {
+        const float *z = Z + (size_t)v * k;
+        for (int32_t c = 0; c < k; c++) {
+            int32_t rank = 0;
+            for (int32_t d = 0; d < k; d++)
+                if (z[d] > z[c] || (z[d] == z[c] && d < c)) rank++;
+            pref[(size_t)v * k + rank] = c;
+        }
+        part[v] = -1;
+    }
+    int64_t *B = (int64_t *)calloc((size_t)k, sizeof(int64_t));
+    int64_t *run = (int64_t *)calloc((size_t)k, sizeof(int64_t));
+    if (!B || !run) abort();
+    for (int32_t r = 0; r < k; r++) {
+        for (int32_t t = 0; t < k; t++) run[t] = B[t];
+        for (int32_t v = 0; v < n; v++) {
+            if (part[v] >= 0) continue;
+            const int32_t t = pref[(size_t)v * k + r];
+            const int64_t c = g->vwgt ? g->vwgt[v] : 1;
+            run[t] += c;
+            if (run[t] <= lmax) part[v] = -2 - t; /* admitted this round, applied below */
+        }
+        for (int32_t v = 0; v < n; v++)
+            if (part[v] <= -2) {
+                part[v] = -2 - part[v];
+                B[part[v]] += g->vwgt ? g->vwgt[v] : 1;
+            }
+    }
+    for (int32_t v = 0; v < n; v++) {
+        if (part[v] >= 0) continue;
+        int32_t b = 0;
+        for (int32_t t = 1; t < k; t++)
+            if (B[t] < B[b]) b = t;
+        part[v] = b;
+        B[b] += g->vwgt ? g->vwgt[v] : 1;
+    }
+    free(pref);
+    free(B);
+    free(run);
+}

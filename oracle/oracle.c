@@ -541,11 +541,12 @@ static void free_hierarchy(hierarchy_t *h) {
 
 /*
  * Initial partition of the coarsest graph (§III-B), with the project's
- * learned proposal when asked for: the network's argmax assignment goes
- * through the same LP refinement and rebalance as every bisection try and is
- * kept iff it is balanced and either the plain result is not balanced or the
- * proposal cuts no more edge weight (ties keep the proposal). A proposal with
- * a non-finite logit is discarded before refinement.
+ * learned proposal when asked for: the network's logits are decoded under
+ * the block bound (orc_mpnn_decode); that proposal goes through the same LP
+ * refinement and rebalance as every bisection try and is kept iff it is
+ * balanced and either the plain result is not balanced or it cuts no more
+ * edge weight (ties keep the proposal). A proposal with a non-finite logit is
+ * discarded before decoding.
  */
 static void initial_with_judge(const orc_graph *gc, int32_t k, int64_t lmax, const orc_params *p, int32_t *P,
                                orc_result *res) {
@@ -568,6 +569,7 @@ static void initial_with_judge(const orc_graph *gc, int32_t k, int64_t lmax, con
         int finite = 1;
         for (int64_t i = 0; i < (int64_t)nc * k; i++) if (!isfinite(Z[i])) finite = 0;
         if (finite) {
+            orc_mpnn_decode(gc, k, Z, lmax, Pl);
             orc_lp_refine(gc, k, lmax, p->rounds_refine, p->dir_alternate, Pl, NULL);
             int lbal = orc_rebalance(gc, k, lmax, Pl);
             lcut = orc_cut(gc, Pl);

@@ -121,6 +121,8 @@ float orc_bf16(float x);
 void orc_mpnn_features(const orc_graph *g, uint64_t seed, float *X /* [n*18] */);
 void orc_mpnn_infer(const orc_graph *g, int32_t k, const float *params, uint64_t seed, float *Z /* [n*k] */,
                     int32_t *part);
+/* Capacity-respecting decoding of finite logits Z into blocks (see mpnn.c). */
+void orc_mpnn_decode(const orc_graph *g, int32_t k, const float *Z, int64_t lmax, int32_t *part);
 
 #ifdef __cplusplus
 }

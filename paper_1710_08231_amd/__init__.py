@@ -74,8 +74,8 @@ class Result(ctypes.Structure):
 
 EXPORTS = ["gp_default_params", "gp_lmax", "gp_lp_cluster", "gp_lp_refine", "gp_contract",
            "gp_project", "gp_cut_and_blocks", "gp_partition", "gp_partition_batch", "gp_strerror", "gp_last_error",
-           "gp_profile_enable", "gp_profile_select", "gp_profile_count", "gp_profile_get", "gp_coarsest",
-           "gp_mpnn_param_count", "gp_mpnn_features", "gp_mpnn_forward", "gp_mpnn_backward", "gp_mpnn_adam_step"]
+           "gp_profile_enable", "gp_profile_select", "gp_profile_count", "gp_profile_get", "gp_coarsest", "gp_coarsest_batch",
+           "gp_mpnn_param_count", "gp_mpnn_features", "gp_mpnn_forward", "gp_mpnn_decode", "gp_mpnn_backward", "gp_mpnn_adam_step"]
 
 
 def load():
@@ -102,10 +102,14 @@ def load():
                                        ctypes.POINTER(Params), vp, ctypes.POINTER(Result), vp]
     lib.gp_coarsest.argtypes = [G, i32, ctypes.c_double, ctypes.POINTER(Params), vp, vp, vp, vp, vp,
                                 ctypes.POINTER(i32), ctypes.POINTER(i32), vp]
+    lib.gp_coarsest_batch.argtypes = [G, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.c_double,
+                                      ctypes.POINTER(Params), vp, vp, vp, vp, vp, ctypes.POINTER(i32),
+                                      ctypes.POINTER(i32), vp]
     lib.gp_mpnn_param_count.restype = i32
     lib.gp_mpnn_param_count.argtypes = [i32]
     lib.gp_mpnn_features.argtypes = [G, ctypes.c_uint64, vp, vp]
     lib.gp_mpnn_forward.argtypes = [G, i32, vp, ctypes.c_uint64, vp, vp, vp]
+    lib.gp_mpnn_decode.argtypes = [G, i32, vp, i64, vp, vp]
     lib.gp_mpnn_backward.argtypes = [G, i32, vp, ctypes.c_uint64, vp, ctypes.c_float, vp,
                                      ctypes.POINTER(ctypes.c_double), vp]
     lib.gp_mpnn_adam_step.argtypes = [vp, vp, vp, vp, i32, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
@@ -319,6 +323,30 @@ def coarsest(g, k, eps=0.03, **params):
     return {"xadj": xc[:nc + 1], "adjncy": ac[:nnzc], "adjwgt": wc[:nnzc], "vwgt": vc[:nc]}, pc[:nc]
 
 
+def coarsest_batch(g, vtx_off, ks, eps=0.03, **params):
+    """Coarsest graphs of the graphs of a disjoint-union graph, side by side.
+    Returns (CSR dict of device tensors, coarse vertex offsets [G+1], graph-local partition)."""
+    torch = _torch()
+    gs = _gstruct(g)
+    G = len(ks)
+    p = _params(params)
+    dev = g["xadj"].device
+    xc = torch.empty(gs.n + 1, dtype=torch.int32, device=dev)
+    ac = torch.empty(max(gs.nnz, 1), dtype=torch.int32, device=dev)
+    wc = torch.empty(max(gs.nnz, 1), dtype=torch.int32, device=dev)
+    vc = torch.empty(max(gs.n, 1), dtype=torch.int32, device=dev)
+    pc = torch.empty(max(gs.n, 1), dtype=torch.int32, device=dev)
+    off = (ctypes.c_int32 * (G + 1))(*vtx_off)
+    kk = (ctypes.c_int32 * G)(*ks)
+    offc = (ctypes.c_int32 * (G + 1))()
+    nnzc = ctypes.c_int32()
+    _check(load().gp_coarsest_batch(ctypes.byref(gs), G, off, kk, eps, ctypes.byref(p), _ptr(xc), _ptr(ac), _ptr(wc),
+                                    _ptr(vc), _ptr(pc), offc, ctypes.byref(nnzc), _stream()))
+    nc, nnzc = offc[G], nnzc.value
+    cg = {"xadj": xc[:nc + 1], "adjncy": ac[:nnzc], "adjwgt": wc[:nnzc], "vwgt": vc[:nc]}
+    return cg, list(offc), pc[:nc]
+
+
 def mpnn_param_count(k):
     n = int(load().gp_mpnn_param_count(k))
     if n < 0:
@@ -352,6 +380,18 @@ def mpnn_forward(g, k, params, seed=0):
     P = torch.empty(max(gs.n, 1), dtype=torch.int32, device=dev)
     _check(load().gp_mpnn_forward(ctypes.byref(gs), k, _fparams(params, k), seed, _ptr(Z), _ptr(P), _stream()))
     return Z[:gs.n], P[:gs.n]
+
+
+def mpnn_decode(g, k, Z, lmax_):
+    """Blocks [n] from logits Z [n, k] (float32 CUDA) under the block bound lmax_."""
+    torch = _torch()
+    gs = _gstruct(g)
+    z = Z.to(dtype=torch.float32).contiguous()
+    if z.numel() != gs.n * k:
+        raise GPError("Z must hold n * k logits")
+    P = torch.empty(max(gs.n, 1), dtype=torch.int32, device=g["xadj"].device)
+    _check(load().gp_mpnn_decode(ctypes.byref(gs), k, _ptr(z), lmax_, _ptr(P), _stream()))
+    return P[:gs.n]
 
 
 def mpnn_backward(g, k, params, target, seed=0, lam=1.0, grad=None):

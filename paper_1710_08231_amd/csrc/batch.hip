@@ -150,10 +150,82 @@ int graph_nnz(const BLevel &L, int32_t G, std::vector<int64_t> &out, Scratch &sc
     return GP_OK;
 }
 
+// Level-0 graph without its vertices that have no neighbour, renumbered in
+// ascending order (rank[v] = new id); blocks made graph-local.
+__global__ void k_compact_graph(int32_t n, const int32_t *xadj, const int32_t *adjncy, const int32_t *adjwgt,
+                                const int32_t *vwgt, const int32_t *part, const int32_t *gid, const int32_t *kbase,
+                                const int32_t *rank, int32_t nnz, int32_t *xc, int32_t *ac, int32_t *wc, int32_t *vc,
+                                int32_t *pc) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+        if (xadj[v + 1] == xadj[v]) continue;
+        const int32_t r = rank[v];
+        xc[r] = xadj[v];
+        vc[r] = vwgt ? vwgt[v] : 1;
+        pc[r] = part[v] - (gid ? kbase[gid[v]] : 0);
+    }
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += stride) {
+        ac[e] = rank[adjncy[e]];
+        wc[e] = adjwgt ? adjwgt[e] : 1;
+    }
+}
+
+__global__ void k_local_blocks(int32_t n, const int32_t *part, const int32_t *gid, const int32_t *kbase,
+                               int32_t *out) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        out[v] = part[v] - (gid ? kbase[gid[v]] : 0);
+}
+
+struct HasNbr {
+    const int32_t *xadj;
+    __device__ bool operator()(int64_t v) const { return xadj[v + 1] > xadj[v]; }
+};
+struct RankOf {
+    int32_t *rank;
+    __device__ void operator()(int64_t v, int32_t pos) const { rank[v] = pos; }
+};
+
 }  // namespace
 
+int write_coarsest(const DevGraph &gc, bool level0, const int32_t *P, const int32_t *gid, const int32_t *d_kbase,
+                   const std::vector<int32_t> &hvoff, const std::vector<int32_t> &niso, CoarsestOut &co,
+                   Scratch &sc) {
+    hipStream_t s = sc.stream();
+    const int32_t n = gc.n, nnz = gc.nnz, G = (int32_t)hvoff.size() - 1;
+    co.nnz = nnz;
+    co.voff.assign(G + 1, 0);
+    if (!level0) {  // coarse levels carry explicit weights
+        GP_HIP(hipMemcpyAsync(co.xadj, gc.xadj, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToDevice, s));
+        GP_HIP(hipMemcpyAsync(co.adjncy, gc.adjncy, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToDevice, s));
+        GP_HIP(hipMemcpyAsync(co.adjwgt, gc.adjwgt, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToDevice, s));
+        GP_HIP(hipMemcpyAsync(co.vwgt, gc.vwgt, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
+        if (n > 0) {
+            hipLaunchKernelGGL(k_local_blocks, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, n, P, gid, d_kbase,
+                               co.part);
+            GP_LAUNCH_CHECK();
+        }
+        co.voff = hvoff;
+        return GP_OK;
+    }
+    int32_t *rank = nullptr, *cnt = nullptr;
+    GP_TRY(sc.alloc(&rank, n));
+    GP_TRY(sc.alloc(&cnt, 1));
+    GP_TRY(compact(HasNbr{gc.xadj}, RankOf{rank}, n, nullptr, cnt, sc));
+    if (n > 0) {
+        hipLaunchKernelGGL(k_compact_graph, dim3(grid_for(std::max(n, nnz), 256, 65536)), dim3(256), 0, s, n, gc.xadj,
+                           gc.adjncy, gc.adjwgt, gc.vwgt, P, gid, d_kbase, rank, nnz, co.xadj, co.adjncy, co.adjwgt,
+                           co.vwgt, co.part);
+        GP_LAUNCH_CHECK();
+    }
+    for (int32_t q = 0; q < G; q++) co.voff[q + 1] = co.voff[q] + (hvoff[q + 1] - hvoff[q]) - niso[q];
+    const int32_t n0 = co.voff[G];
+    GP_HIP(hipMemcpyAsync(co.xadj + n0, &co.nnz, sizeof(int32_t), hipMemcpyHostToDevice, s));
+    GP_HIP(hipStreamSynchronize(s));
+    return GP_OK;
+}
+
 int partition_batch(const DevGraph &g0, int32_t G, const int32_t *voff_host, const int32_t *k_host, double eps,
-                    const gp_params *p, int32_t *part_out, gp_result *res, Scratch &sc) {
+                    const gp_params *p, int32_t *part_out, gp_result *res, Scratch &sc, CoarsestOut *cout) {
     hipStream_t s = sc.stream();
     Timer t_total(s);
     const int32_t n = g0.n;
@@ -328,6 +400,7 @@ int partition_batch(const DevGraph &g0, int32_t G, const int32_t *voff_host, con
     GP_TRY(initial_partition_batch(lev[T].g, T == 0, bi, p->seed, p->attempts, p->rounds_refine, p->dir_alternate,
                                    wide, P, sc));
     const float ms_init = t_init.stop();
+    if (cout) return write_coarsest(lev[T].g, T == 0, P, lev[T].gid, d_kbase, lev[T].hvoff, hI, *cout, sc);
 
     // ---- uncoarsening: graph q is refined at the top and below its own coarsest level
     Timer t_ref(s);

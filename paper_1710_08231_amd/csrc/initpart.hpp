@@ -48,6 +48,24 @@ int initial_partition(const DevGraph &g, bool skip_isolated, int32_t k, int64_t 
 int fill_isolated_batch(const DevGraph &g, const BatchInfo &bi, const int32_t *d_iso_first, int32_t *part,
                         const int64_t *B, Scratch &sc);
 
+// Caller buffers for the coarsest graph(s) and the initial partition (sized as
+// the input graph). voff receives the per-graph vertex offsets (G+1), nnz the
+// edge entries.
+struct CoarsestOut {
+    int32_t *xadj, *adjncy, *adjwgt, *vwgt, *part;
+    std::vector<int32_t> voff;
+    int32_t nnz = 0;
+};
+
+// Writes the top level gc (G graphs side by side, vertex offsets hvoff) with
+// explicit weights and graph-local blocks. When level0 is set, gc is an input
+// graph: its vertices without neighbours (niso[q] of graph q) are left out
+// and the others renumbered in ascending order. P holds global block ids
+// (kbase[gid[v]] + b; gid/d_kbase null for one graph).
+int write_coarsest(const DevGraph &gc, bool level0, const int32_t *P, const int32_t *gid, const int32_t *d_kbase,
+                   const std::vector<int32_t> &hvoff, const std::vector<int32_t> &niso, CoarsestOut &co,
+                   Scratch &sc);
+
 // gid[v] = q for v in [voff[q], voff[q+1]) (device arrays).
 int graph_ids(int32_t G, int32_t n, const int32_t *d_voff, int32_t *gid, hipStream_t s);
 

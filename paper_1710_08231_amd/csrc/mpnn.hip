@@ -192,6 +192,70 @@ __global__ void k_argmax(int32_t n, int32_t k, const float *__restrict__ Z, cons
     }
 }
 
+// ------------------------------------------------------------------ decoding
+// Every vertex ranks the blocks by logit (highest first, ties -> lower block);
+// round r offers each unplaced vertex's r-th block, and the offers to block t
+// are admitted in ascending vertex id while B[t] + (weight of all offers to t
+// up to and including v) <= lmax; leftovers go one by one, ascending, to the
+// lightest block.
+
+// pref[v][rank] = block; part[v] = -1 (unplaced) or -2 (takes no part)
+__global__ void k_prefs(int32_t n, int32_t k, const float *__restrict__ Z, const int32_t *__restrict__ xadj,
+                        bool active_only, uint8_t *__restrict__ pref, int32_t *__restrict__ part) {
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const float *z = Z + (int64_t)v * k;
+        for (int32_t c = 0; c < k; c++) {
+            const float zc = z[c];
+            int32_t rank = 0;
+            for (int32_t d = 0; d < k; d++) rank += (z[d] > zc) || (z[d] == zc && d < c);
+            pref[(int64_t)v * k + rank] = (uint8_t)c;
+        }
+        part[v] = (active_only && xadj[v + 1] == xadj[v]) ? -2 : -1;
+    }
+}
+
+constexpr int kDB = 1024;
+
+// one workgroup per block t: admit round r's offers to t in ascending id
+__global__ __launch_bounds__(kDB) void k_decode_round(int32_t n, int32_t k, int32_t r, const uint8_t *__restrict__ pref,
+                                                      const int32_t *__restrict__ vwgt, int64_t lmax,
+                                                      int64_t *__restrict__ B, int32_t *__restrict__ part) {
+    __shared__ int64_t tmp[kDB / kWave + 1];
+    const int32_t t = blockIdx.x;
+    int64_t run = B[t], admitted = 0;
+    for (int32_t base = 0; base < n; base += kDB) {
+        const int32_t v = base + threadIdx.x;
+        int64_t c = 0;
+        // only this workgroup changes part[v] for offers to t in this round
+        if (v < n && part[v] == -1 && pref[(int64_t)v * k + r] == t) c = vwgt ? vwgt[v] : 1;
+        int64_t total;
+        const int64_t excl = block_excl_scan<kDB>(c, tmp, &total);
+        const bool ok = c > 0 && run + excl + c <= lmax;
+        if (ok) part[v] = t;
+        admitted += block_sum<kDB>(ok ? c : (int64_t)0, tmp);
+        run += total;
+    }
+    if (threadIdx.x == 0) B[t] += admitted;
+}
+
+// unplaced vertices, ascending, each into the currently lightest block
+__global__ void k_decode_leftover(int32_t n, int32_t k, const int32_t *__restrict__ vwgt, int64_t *__restrict__ B,
+                                  int32_t *__restrict__ part) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    for (int32_t v = 0; v < n; v++) {
+        if (part[v] == -2) {
+            part[v] = 0;  // takes no part: any valid block id
+            continue;
+        }
+        if (part[v] >= 0) continue;
+        int32_t b = 0;
+        for (int32_t t = 1; t < k; t++)
+            if (B[t] < B[b]) b = t;
+        part[v] = b;
+        B[b] += vwgt ? vwgt[v] : 1;
+    }
+}
+
 // ------------------------------------------------------------------ training
 
 __global__ void k_softmax(int32_t n, int32_t k, const float *__restrict__ Z, float *__restrict__ S) {
@@ -497,6 +561,28 @@ int mpnn_forward(const DevGraph &g, int32_t k, const float *params, uint64_t see
                            active_only, part, nonfinite_dev);
         GP_LAUNCH_CHECK();
     }
+    return GP_OK;
+}
+
+int mpnn_decode(const DevGraph &g, int32_t k, const float *Z, int64_t lmax, bool active_only, int32_t *part,
+                Scratch &sc) {
+    hipStream_t s = sc.stream();
+    const int32_t n = g.n;
+    if (n == 0) return GP_OK;
+    uint8_t *pref = nullptr;
+    int64_t *B = nullptr;
+    GP_TRY(sc.alloc(&pref, (size_t)n * k));
+    GP_TRY(sc.alloc(&B, k));
+    GP_HIP(hipMemsetAsync(B, 0, sizeof(int64_t) * (size_t)k, s));
+    hipLaunchKernelGGL(k_prefs, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, n, k, Z, g.xadj, active_only, pref,
+                       part);
+    GP_LAUNCH_CHECK();
+    for (int32_t r = 0; r < k; r++) {
+        hipLaunchKernelGGL(k_decode_round, dim3(k), dim3(kDB), 0, s, n, k, r, pref, g.vwgt, lmax, B, part);
+        GP_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_decode_leftover, dim3(1), dim3(64), 0, s, n, k, g.vwgt, B, part);
+    GP_LAUNCH_CHECK();
     return GP_OK;
 }
 

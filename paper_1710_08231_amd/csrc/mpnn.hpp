@@ -26,6 +26,13 @@ int mpnn_features(const DevGraph &g, uint64_t seed, bool active_only, float *X, 
 int mpnn_forward(const DevGraph &g, int32_t k, const float *params, uint64_t seed, bool active_only, float *Z,
                  int32_t *part, int32_t *nonfinite_dev, Scratch &sc);
 
+// Capacity-respecting decoding of finite logits Z [n][k] into blocks part [n]
+// (vertices ranked by logit per block; round r admits each unplaced vertex's
+// r-th block in ascending id while the block stays within lmax; leftovers to
+// the lightest block). active_only: vertices without neighbours take no part.
+int mpnn_decode(const DevGraph &g, int32_t k, const float *Z, int64_t lmax, bool active_only, int32_t *part,
+                Scratch &sc);
+
 // Training loss (edge term, balance term) and its gradient w.r.t. the master
 // weights (straight through the bfloat16 rounding), grad: device [P].
 int mpnn_backward(const DevGraph &g, int32_t k, const float *params, uint64_t seed, const int32_t *target,

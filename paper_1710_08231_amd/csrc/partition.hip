@@ -139,38 +139,6 @@ struct Level {
     int32_t *f2c = nullptr;  // this level -> next level
 };
 
-// Level-0 graph without its isolated vertices, renumbered in ascending order
-// (rank[v] = new id of a vertex with neighbours).
-__global__ void k_compact_graph(int32_t n, const int32_t *xadj, const int32_t *adjncy, const int32_t *adjwgt,
-                                const int32_t *vwgt, const int32_t *part, const int32_t *rank, int32_t nnz,
-                                int32_t *xc, int32_t *ac, int32_t *wc, int32_t *vc, int32_t *pc) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
-        if (xadj[v + 1] == xadj[v]) continue;
-        const int32_t r = rank[v];
-        xc[r] = xadj[v];
-        vc[r] = vwgt ? vwgt[v] : 1;
-        pc[r] = part[v];
-    }
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += stride) {
-        ac[e] = rank[adjncy[e]];
-        wc[e] = adjwgt ? adjwgt[e] : 1;
-    }
-}
-
-__global__ void k_fill_ones(int32_t *a, int64_t count) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
-        a[i] = 1;
-}
-
-struct HasNbr {
-    const int32_t *xadj;
-    __device__ bool operator()(int64_t v) const { return xadj[v + 1] > xadj[v]; }
-};
-struct RankOf {
-    int32_t *rank;
-    __device__ void operator()(int64_t v, int32_t pos) const { rank[v] = pos; }
-};
 
 }  // namespace
 
@@ -181,7 +149,7 @@ struct GraphInfo {
 };
 
 int partition_batch(const DevGraph &g0, int32_t G, const int32_t *voff_host, const int32_t *k_host, double eps,
-                    const gp_params *p, int32_t *part_out, gp_result *res, Scratch &sc);
+                    const gp_params *p, int32_t *part_out, gp_result *res, Scratch &sc, CoarsestOut *cout);
 
 static int graph_info(const DevGraph &g, GraphInfo &gi, Scratch &sc) {
     hipStream_t s = sc.stream();
@@ -255,6 +223,20 @@ static int check_params(const gp_params *pp, int32_t k, const char *who) {
     return GP_OK;
 }
 
+static int check_batch_layout(const gp_graph *g, int32_t G, const int32_t *vtx_off_host, const int32_t *k_host,
+                              const char *who) {
+    if (vtx_off_host[0] != 0 || vtx_off_host[G] != g->n) {
+        set_error((std::string(who) + ": vtx_off must start at 0 and end at n").c_str());
+        return GP_ERR_ARG;
+    }
+    for (int32_t q = 0; q < G; q++)
+        if (vtx_off_host[q + 1] < vtx_off_host[q] || k_host[q] < 1) {
+            set_error((std::string(who) + ": vtx_off must be non-decreasing and every k >= 1").c_str());
+            return GP_ERR_ARG;
+        }
+    return GP_OK;
+}
+
 static int64_t lmax_of(int64_t W, int32_t k, double eps) {
     const int64_t q = W / k + (W % k != 0);
     return (int64_t)std::floor((1.0 + eps) * (double)q);
@@ -288,46 +270,6 @@ static bool tracing() {
         return e && *e && *e != '0';
     }();
     return on;
-}
-
-// Caller buffers for the coarsest graph and its initial partition (sized as
-// the input graph); when given, the driver stops after the initial partition.
-struct CoarsestOut {
-    int32_t *xadj, *adjncy, *adjwgt, *vwgt, *part;
-    int32_t n = 0, nnz = 0;
-};
-
-static int write_coarsest(const DevGraph &gc, bool level0, const int32_t *P, CoarsestOut &co, Scratch &sc) {
-    hipStream_t s = sc.stream();
-    const int32_t n = gc.n, nnz = gc.nnz;
-    if (!level0) {  // coarse levels carry explicit weights
-        GP_HIP(hipMemcpyAsync(co.xadj, gc.xadj, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToDevice, s));
-        GP_HIP(hipMemcpyAsync(co.adjncy, gc.adjncy, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToDevice, s));
-        GP_HIP(hipMemcpyAsync(co.adjwgt, gc.adjwgt, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToDevice, s));
-        GP_HIP(hipMemcpyAsync(co.vwgt, gc.vwgt, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
-        GP_HIP(hipMemcpyAsync(co.part, P, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
-        co.n = n;
-        co.nnz = nnz;
-        return GP_OK;
-    }
-    int32_t *rank = nullptr, *cnt = nullptr;
-    GP_TRY(sc.alloc(&rank, n));
-    GP_TRY(sc.alloc(&cnt, 1));
-    GP_TRY(compact(HasNbr{gc.xadj}, RankOf{rank}, n, nullptr, cnt, sc));
-    int32_t n0 = 0;
-    GP_HIP(hipMemcpyAsync(&n0, cnt, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    GP_HIP(hipStreamSynchronize(s));
-    if (n > 0) {
-        hipLaunchKernelGGL(k_compact_graph, dim3(grid_for(std::max(n, nnz), 256, 65536)), dim3(256), 0, s, n, gc.xadj,
-                           gc.adjncy, gc.adjwgt, gc.vwgt, P, rank, nnz, co.xadj, co.adjncy, co.adjwgt, co.vwgt,
-                           co.part);
-        GP_LAUNCH_CHECK();
-    }
-    GP_HIP(hipMemcpyAsync(co.xadj + n0, &nnz, sizeof(int32_t), hipMemcpyHostToDevice, s));
-    GP_HIP(hipStreamSynchronize(s));
-    co.n = n0;
-    co.nnz = nnz;
-    return GP_OK;
 }
 
 static int do_partition(const gp_graph *gin, int32_t k, double eps, const gp_params *p, int32_t *part_out,
@@ -412,13 +354,16 @@ static int do_partition(const gp_graph *gin, int32_t k, double eps, const gp_par
     const bool tried = p->init_mode == GP_INIT_LEARNED && nc_active > 0 && nc_active <= p->mpnn_max_n;
     if (tried) {
         int32_t *nf = nullptr, hnf = 0;
+        float *Z = nullptr;
         GP_TRY(sc.alloc(&prop, gc.n));
+        GP_TRY(sc.alloc(&Z, (size_t)gc.n * k));
         GP_TRY(sc.alloc(&nf, 1));
         GP_HIP(hipMemsetAsync(nf, 0, sizeof(int32_t), s));
-        GP_TRY(mpnn_forward(gc, k, p->mpnn_params, p->mpnn_seed, Lc == 0, nullptr, prop, nf, sc));
+        GP_TRY(mpnn_forward(gc, k, p->mpnn_params, p->mpnn_seed, Lc == 0, Z, nullptr, nf, sc));
         GP_HIP(hipMemcpyAsync(&hnf, nf, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         GP_HIP(hipStreamSynchronize(s));
         if (hnf) prop = nullptr;  // a non-finite logit discards the proposal
+        else GP_TRY(mpnn_decode(gc, k, Z, lmax, Lc == 0, prop, sc));
     }
     ProposalOut po;
     GP_TRY(initial_partition(gc, Lc == 0, k, lmax, p->seed, p->attempts, p->rounds_refine, p->dir_alternate, wide, P,
@@ -442,7 +387,7 @@ static int do_partition(const gp_graph *gin, int32_t k, double eps, const gp_par
     const float ms_init = t_init.stop();
     if (tracing()) std::fprintf(stderr, "[gp] initial partition n=%d nnz=%d %.3f ms\n", gc.n, gc.nnz, ms_init);
     if (cout) {
-        GP_TRY(write_coarsest(gc, Lc == 0, P, *cout, sc));
+        GP_TRY(write_coarsest(gc, Lc == 0, P, nullptr, nullptr, {0, gc.n}, {(int32_t)gi.niso}, *cout, sc));
         sc.release();
         GP_HIP(hipStreamSynchronize(s));
         return GP_OK;
@@ -723,8 +668,39 @@ int gp_coarsest(const gp_graph *g, int32_t k, double eps, const gp_params *p, in
     GP_TRY(check_params(pp, k, "coarsest"));
     CoarsestOut co{xadj_c, adjncy_c, adjwgt_c, vwgt_c, part_c};
     GP_TRY(do_partition(g, k, eps, pp, nullptr, nullptr, stream, &co));
-    *n_c_host = co.n;
+    *n_c_host = co.voff[1];
     *nnz_c_host = co.nnz;
+    return GP_OK;
+}
+
+int gp_coarsest_batch(const gp_graph *g, int32_t G, const int32_t *vtx_off_host, const int32_t *k_host, double eps,
+                      const gp_params *p, int32_t *xadj_c, int32_t *adjncy_c, int32_t *adjwgt_c, int32_t *vwgt_c,
+                      int32_t *part_c, int32_t *vtx_off_c_host, int32_t *nnz_c_host, hipStream_t stream) {
+    GP_TRY(check_graph_args(g));
+    if (G < 1 || !vtx_off_host || !k_host || !(eps >= 0.0) || !xadj_c || !vtx_off_c_host || !nnz_c_host ||
+        (g->n > 0 && (!vwgt_c || !part_c)) || (g->nnz > 0 && (!adjncy_c || !adjwgt_c))) {
+        set_error("coarsest_batch: G < 1, eps < 0 or a required array is NULL");
+        return GP_ERR_ARG;
+    }
+    GP_TRY(check_batch_layout(g, G, vtx_off_host, k_host, "coarsest_batch"));
+    gp_params dp;
+    gp_default_params(&dp);
+    const gp_params *pp = p ? p : &dp;
+    GP_TRY(check_params(pp, 1, "coarsest_batch"));
+    if (pp->init_mode != GP_INIT_PLAIN) {
+        set_error("coarsest_batch: the learned initial partition is available for single graphs only");
+        return GP_ERR_ARG;
+    }
+    Scratch sc(stream);
+    const DevGraph d = dev_graph(g);
+    GraphInfo gi;
+    GP_TRY(graph_info(d, gi, sc));
+    CoarsestOut co{xadj_c, adjncy_c, adjwgt_c, vwgt_c, part_c};
+    GP_TRY(partition_batch(d, G, vtx_off_host, k_host, eps, pp, nullptr, nullptr, sc, &co));
+    for (int32_t q = 0; q <= G; q++) vtx_off_c_host[q] = co.voff[q];
+    *nnz_c_host = co.nnz;
+    sc.release();
+    GP_HIP(hipStreamSynchronize(stream));
     return GP_OK;
 }
 
@@ -758,6 +734,22 @@ int gp_mpnn_forward(const gp_graph *g, int32_t k, const float *params, uint64_t 
     GraphInfo gi;
     GP_TRY(graph_info(d, gi, sc));
     GP_TRY(mpnn_forward(d, k, params, seed, false, Z, part, nullptr, sc));
+    sc.release();
+    GP_HIP(hipStreamSynchronize(stream));
+    return GP_OK;
+}
+
+int gp_mpnn_decode(const gp_graph *g, int32_t k, const float *Z, int64_t lmax, int32_t *part, hipStream_t stream) {
+    GP_TRY(check_graph_args(g));
+    if (k < 1 || k > kMpMaxK || lmax < 1 || (g->n > 0 && (!Z || !part))) {
+        set_error("mpnn_decode: k outside [1, 64], lmax < 1, or an array is NULL");
+        return GP_ERR_ARG;
+    }
+    Scratch sc(stream);
+    const DevGraph d = dev_graph(g);
+    GraphInfo gi;
+    GP_TRY(graph_info(d, gi, sc));
+    GP_TRY(mpnn_decode(d, k, Z, lmax, false, part, sc));
     sc.release();
     GP_HIP(hipStreamSynchronize(stream));
     return GP_OK;
@@ -812,15 +804,7 @@ int gp_partition_batch(const gp_graph *g, int32_t G, const int32_t *vtx_off_host
         set_error("partition_batch: G < 1, eps < 0 or a required array is NULL");
         return GP_ERR_ARG;
     }
-    if (vtx_off_host[0] != 0 || vtx_off_host[G] != g->n) {
-        set_error("partition_batch: vtx_off must start at 0 and end at n");
-        return GP_ERR_ARG;
-    }
-    for (int32_t q = 0; q < G; q++)
-        if (vtx_off_host[q + 1] < vtx_off_host[q] || k_host[q] < 1) {
-            set_error("partition_batch: vtx_off must be non-decreasing and every k >= 1");
-            return GP_ERR_ARG;
-        }
+    GP_TRY(check_batch_layout(g, G, vtx_off_host, k_host, "partition_batch"));
     gp_params dp;
     gp_default_params(&dp);
     const gp_params *pp = p ? p : &dp;
@@ -833,7 +817,7 @@ int gp_partition_batch(const gp_graph *g, int32_t G, const int32_t *vtx_off_host
     const DevGraph d = dev_graph(g);
     GraphInfo gi;
     GP_TRY(graph_info(d, gi, sc));
-    const int rc = partition_batch(d, G, vtx_off_host, k_host, eps, pp, part_out, res_host, sc);
+    const int rc = partition_batch(d, G, vtx_off_host, k_host, eps, pp, part_out, res_host, sc, nullptr);
     sc.release();
     GP_HIP(hipStreamSynchronize(stream));
     return rc;

@@ -180,3 +180,41 @@ def test_learned_errors():
     u, off = gp.union_graph([graphgen.rgg2d(300, 1), graphgen.rgg2d(300, 2)])
     with pytest.raises(gp.GPError):
         gp.partition_batch(gp.to_device(u), off, [2, 2], init_mode=1, mpnn_params=w)
+
+
+@pytest.mark.parametrize("case", ["mixed", "none_coarsen"])
+def test_coarsest_batch_matches_oracle(case):
+    if case == "mixed":
+        graphs, ks = graphgen.batch(master_seed=5, count=12, log2_min=8, log2_max=12)
+        graphs += [graphgen.rmat(9, 6), graphgen.grid3d(9, 8, 7, seed=1, wmax=5)]
+        ks += [16, 4]
+    else:  # no graph is coarsened: the input graphs without their isolated vertices
+        graphs, ks = [graphgen.rmat(9, 6), graphgen.from_edges(6, [(0, 1), (2, 3)]), graphgen.rgg2d(300, 4)], [16, 2, 8]
+    u, off = gp.union_graph(graphs)
+    cg, offc, pc = gp.coarsest_batch(gp.to_device(u), off, ks)
+    x = cg["xadj"].cpu().numpy()
+    a, w, vw, pcn = (t.cpu().numpy() for t in (cg["adjncy"], cg["adjwgt"], cg["vwgt"], pc))
+    for q, (g, k) in enumerate(zip(graphs, ks)):
+        ocg, opc = oracle.coarsest(g, k)
+        lo, hi = offc[q], offc[q + 1]
+        assert hi - lo == len(ocg["xadj"]) - 1, q
+        e0, e1 = x[lo], x[hi]
+        assert np.array_equal(x[lo:hi + 1] - e0, ocg["xadj"]), q
+        assert np.array_equal(a[e0:e1] - lo, ocg["adjncy"]), q
+        assert np.array_equal(w[e0:e1], ocg["adjwgt"]), q
+        assert np.array_equal(vw[lo:hi], ocg["vwgt"]), q
+        assert np.array_equal(pcn[lo:hi], opc), q
+
+
+@pytest.mark.parametrize("k,weighted,ties", [(2, False, False), (16, True, True), (64, True, False), (5, False, True)])
+def test_decode_bit_exact(k, weighted, ties):
+    g = graphgen.random_small(1500, 0.004, 8, wmax=3, vmax=9 if weighted else 1)
+    n = len(g["xadj"]) - 1
+    rng = np.random.default_rng(k)
+    Z = rng.normal(0, 1, (n, k)).astype(np.float32)
+    if ties:
+        Z = np.round(Z, 0).astype(np.float32)
+    W = int(g["vwgt"].sum()) if weighted else n
+    for lm in (oracle.lmax(W, k, 0.03), oracle.lmax(W, k, 0.5), 10 ** 9):
+        P = gp.mpnn_decode(gp.to_device(g), k, torch.from_numpy(Z).cuda(), lm)
+        assert np.array_equal(P.cpu().numpy(), oracle.mpnn_decode(g, k, Z, lm)), lm

@@ -226,3 +226,48 @@ def test_coarsest_graph_and_partition():
     w = np.full(mpnn.param_count(k), np.nan, np.float32)
     _, r1 = oracle.partition(g, k, init_mode=1, mpnn_params=w)
     assert oracle.cut(cg, pc) == r1["plain_cut_coarsest"]
+
+
+def test_decode_worked_examples():
+    # hand-derived: five unit vertices, k=2, L_max=3; four prefer block 0.
+    # round 0 admits v0, v1, v2 to block 0 (v3 would make it 4) and v4 to block 1;
+    # round 1 offers v3 its second choice, block 1 (weight 2 <= 3).
+    g = graphgen.from_edges(5, [(0, 1), (1, 2), (2, 3), (3, 4)])
+    Z = np.array([[1, 0], [1, 0], [1, 0], [1, 0], [0, 1]], np.float32)
+    assert oracle.mpnn_decode(g, 2, Z, 3).tolist() == [0, 0, 0, 1, 1]
+    # equal logits rank the lower block first
+    assert oracle.mpnn_decode(g, 2, np.zeros((5, 2), np.float32), 3).tolist() == [0, 0, 0, 1, 1]
+    # weights 3,3,3, L_max=4: v0 -> 0; v1 -> 1 in round 1; v2 fits nowhere and
+    # goes to the lighter block, a tie between 3 and 3 -> block 0
+    g3 = graphgen.from_edges(3, [(0, 1), (1, 2)], vwgt=[3, 3, 3])
+    assert oracle.mpnn_decode(g3, 2, np.array([[1, 0]] * 3, np.float32), 4).tolist() == [0, 1, 0]
+    # an early heavy offer that is rejected still counts against the later ones:
+    # weights 1,5,1, L_max=5, all prefer block 0. Round 0: v0 in (1), v1 out (6),
+    # v2 out (7 > 5 although 1+1 would fit). Round 1: v1 -> block 1 (5), v2 out
+    # (6). Leftover v2 -> lighter block 0 (1 < 5).
+    g4 = graphgen.from_edges(3, [(0, 1), (1, 2)], vwgt=[1, 5, 1])
+    assert oracle.mpnn_decode(g4, 2, np.array([[1, 0]] * 3, np.float32), 5).tolist() == [0, 1, 0]
+
+
+def test_decode_reduces_to_argmax_within_capacity():
+    g = graphgen.rgg2d(800, 3)
+    rng = np.random.default_rng(0)
+    Z = rng.normal(0, 1, (800, 8)).astype(np.float32)
+    # a bound no block can reach: decoding is the argmax (ties -> lowest)
+    assert np.array_equal(oracle.mpnn_decode(g, 8, Z, 10 ** 9), Z.argmax(axis=1))
+
+
+@pytest.mark.parametrize("k", [2, 7, 16])
+def test_decode_unit_weights_always_balanced(k):
+    # unit weights and k * L_max >= n: every vertex is placed within k rounds,
+    # no block exceeds L_max, and a vertex only sits outside its first choice
+    # when that block is full
+    g = graphgen.rgg2d(1500, k)
+    rng = np.random.default_rng(k)
+    Z = np.round(rng.normal(0, 1, (1500, k)), 1).astype(np.float32)  # many ties
+    lm = oracle.lmax(1500, k, 0.03)
+    P = oracle.mpnn_decode(g, k, Z, lm)
+    B = np.bincount(P, minlength=k)
+    assert B.max() <= lm and B.sum() == 1500
+    first = np.array([min(range(k), key=lambda c: (-z[c], c)) for z in Z])
+    assert np.all(B[first[P != first]] == lm)
