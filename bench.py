@@ -24,7 +24,7 @@ WORKLOADS = {
     "grid256": dict(kind="grid", side=256, seed=3, k=64),
     "rgg16k": dict(kind="rgg", n=16384, seed=1, k=2),
     "batch512": dict(kind="batch", seed=4, count=512, k=None),
-    "learned24": dict(kind="learned", scale=24, k=16),
+    "learned24": dict(kind="learned", scale=24, seed=24, k=16),
 }
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
@@ -145,8 +145,9 @@ def bench_batch(args, w):
 
 
 def bench_learned(args, w):
-    """R-MAT scale 24, k = 16: the learned initial partition (judged against the
-    plain one) beside the plain form, one seeded graph per step (seeds 0..steps-1)."""
+    """R-MAT scale 24 (graph seed 24), k = 16: the learned initial partition
+    (judged against the plain one) beside the plain form, with partition seeds
+    0..steps-1 (bisection start hash and probe seed)."""
     import numpy as np
     import torch
     import graphgen
@@ -154,23 +155,24 @@ def bench_learned(args, w):
     wpath = os.path.join(ROOT, "paper_1710_08231_amd", "mpnn_k16.npy")
     params = torch.from_numpy(np.load(wpath).astype(np.float32)).cuda()
     k = w["k"]
+    t0 = time.perf_counter()
+    g = graphgen.rmat(w["scale"], w["seed"])
+    dg = gp.to_device(g)
+    n, nnz = len(g["xadj"]) - 1, len(g["adjncy"])
+    print(f"[bench] learned24 n={n} nnz={nnz} generated in {time.perf_counter() - t0:.1f}s", file=sys.stderr,
+          flush=True)
+    for _ in range(max(1, args.warmup)):
+        gp.partition(dg, k, 0.03)
+        gp.partition(dg, k, 0.03, init_mode=1, mpnn_params=params)
     rows, visits, t_learned, t_plain = [], 0, 0.0, 0.0
     for seed in range(args.steps):
-        t0 = time.perf_counter()
-        g = graphgen.rmat(w["scale"], seed)
-        dg = gp.to_device(g)
-        print(f"[bench] seed {seed} generated in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
-        if seed == 0:
-            for _ in range(max(1, args.warmup)):
-                gp.partition(dg, k, 0.03)
-                gp.partition(dg, k, 0.03, init_mode=1, mpnn_params=params)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        _, r0 = gp.partition(dg, k, 0.03)
+        _, r0 = gp.partition(dg, k, 0.03, seed=seed)
         torch.cuda.synchronize()
         t_plain += time.perf_counter() - t
         t = time.perf_counter()
-        _, r1 = gp.partition(dg, k, 0.03, init_mode=1, mpnn_params=params)
+        _, r1 = gp.partition(dg, k, 0.03, seed=seed, init_mode=1, mpnn_params=params, mpnn_seed=seed)
         torch.cuda.synchronize()
         t_learned += time.perf_counter() - t
         visits += r1["edge_visits_cluster"] + r1["edge_visits_refine"]
@@ -178,24 +180,39 @@ def bench_learned(args, w):
                      "tried": r1["learned_tried"], "coarsest_n": r1["coarsest_n"],
                      "coarse_cut_plain": r1["plain_cut_coarsest"], "coarse_cut_learned": r1["learned_cut_coarsest"],
                      "plain_ms": r0["ms_total"], "learned_ms": r1["ms_total"], "init_ms_plain": r0["ms_init"],
-                     "init_ms_learned": r1["ms_init"], "balanced": bool(r1["balanced"])})
+                     "init_ms_learned": r1["ms_init"], "balanced": bool(r1["balanced"] and r0["balanced"])})
         print(f"[bench] {json.dumps(rows[-1])}", file=sys.stderr, flush=True)
-        del dg
     ms = t_learned * 1000.0 / args.steps
+    geo = float(np.exp(np.mean([np.log(r["learned_cut"] / r["plain_cut"]) for r in rows])))
     out = {
         "metric": "LP edge-visits/sec + end-to-end k-way partition time; cut & balance vs oracle",
         "value": visits / t_learned, "unit": "edge-visits/s", "n_gpus": 1, "steps": args.steps,
         "warmup": max(1, args.warmup), "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int32+fp32", "data": "synthetic",
-        "config": {"workload": "learned24", "graph": "rmat scale 24 ef 16, seeds 0..steps-1", "k": k, "eps": 0.03,
+        "config": {"workload": "learned24", "graph": "rmat scale 24 ef 16 seed 24", "n": n, "nnz": nnz, "k": k,
+                   "eps": 0.03, "partition_seeds": f"0..{args.steps - 1}",
                    "init": "learned proposal judged against best of 4 bisections"},
         "partition_ms": ms, "plain_form_ms": t_plain * 1000.0 / args.steps,
-        "cut_total_learned": sum(r["learned_cut"] for r in rows),
-        "cut_total_plain": sum(r["plain_cut"] for r in rows),
+        "cut_geomean_learned_over_plain": geo,
+        "proposals_tried": sum(r["tried"] for r in rows),
         "proposals_kept": sum(r["kept"] for r in rows),
         "per_seed": rows,
     }
     print(json.dumps(out), flush=True)
+
+
+def calibrate_copy(args):
+    """A plain device copy of known size (one read and one write of 1 GiB per
+    launch), the reference for HBM byte counters."""
+    import torch
+    n = (1 << 30) // 4
+    src = torch.ones(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(max(1, args.steps)):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "torch.neg int32", "bytes_read_per_launch": n * 4,
+                      "bytes_written_per_launch": n * 4, "launches": max(1, args.steps)}), flush=True)
 
 
 def main():
@@ -206,6 +223,8 @@ def main():
     ap.add_argument("--workload", default="rmat22", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-rounds", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is not built",
@@ -215,6 +234,8 @@ def main():
     import torch
     import paper_1710_08231_amd as gp
 
+    if args.calibrate_copy:
+        return calibrate_copy(args)
     w = WORKLOADS[args.workload]
     if w["kind"] == "batch":
         return bench_batch(args, w)
@@ -231,6 +252,7 @@ def main():
     k = w["k"]
     # warmup; the last warmup step also times every instrumented kernel once to find the dominant one
     dominant = None
+    dom_launches = 0
     warm_table = {}
     for i in range(max(1, args.warmup)):
         last_warm = i == max(1, args.warmup) - 1
@@ -242,17 +264,23 @@ def main():
             entries = gp.profile_entries()
             gp.profile_enable(False)
             dominant = max(entries, key=lambda e: e["ms"])["name"] if entries else None
+            dom_launches = max(entries, key=lambda e: e["ms"])["launches"] if entries else 0
             warm_table = {e["name"]: round(e["ms"], 3) for e in sorted(entries, key=lambda e: -e["ms"])[:10]}
         print(f"[bench] warmup {i} ms={res['ms_total']:.2f}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     visits = 0
     results = []
-    # timed region: HIP events around the dominant kernel's launches only, on the library's stream
+    # timed region: HIP events around the dominant kernel's launches only, on the
+    # library's stream (created beforehand, so none is created while timing)
     gp.profile_select(dominant)
     gp.profile_enable(True)
+    gp.profile_reserve(dom_launches * args.steps + 64)
+    step_ms = []
     t = time.perf_counter()
     for i in range(args.steps):
+        ts = time.perf_counter()
         part, res = gp.partition(dg, k, 0.03)
+        step_ms.append((time.perf_counter() - ts) * 1000.0)
         visits += res["edge_visits_cluster"] + res["edge_visits_refine"]
         results.append(res)
     torch.cuda.synchronize()
@@ -262,7 +290,8 @@ def main():
     gp.profile_select(None)
     ms = dt * 1000.0 / args.steps
     last = results[-1]
-    print(f"[bench] timed {args.steps} steps: {ms:.2f} ms/step", file=sys.stderr, flush=True)
+    print(f"[bench] timed {args.steps} steps: {ms:.2f} ms/step (wall per step {[round(x, 1) for x in step_ms]}, "
+          f"device {[round(r['ms_total'], 1) for r in results]})", file=sys.stderr, flush=True)
     out = {
         "metric": "LP edge-visits/sec + end-to-end k-way partition time; cut & balance vs oracle",
         "value": visits / dt,
@@ -284,6 +313,8 @@ def main():
         "coarsest_n": last["coarsest_n"],
         "edge_visits_per_step": visits // args.steps,
         "phase_ms": {"coarsen": last["ms_coarsen"], "init": last["ms_init"], "refine": last["ms_refine"]},
+        "step_wall_ms": [round(x, 2) for x in step_ms],
+        "step_device_ms": [round(r["ms_total"], 2) for r in results],
     }
     out["roofline"] = roofline(prof, args.workload)
     out["proposal_kernel_ms_warmup_step"] = warm_table

@@ -91,7 +91,7 @@ typedef struct {
     int32_t dir_alternate;  /* 1: direction alternation of synchronous rounds */
     uint64_t seed;          /* start-vertex hash of the initial bisections */
     int32_t init_mode;      /* GP_INIT_PLAIN; GP_INIT_LEARNED adds the network's proposal */
-    int32_t mpnn_max_n;     /* 65536: the proposal is tried only on coarsest graphs this small */
+    int32_t mpnn_max_n;     /* 131072: the proposal is tried only on coarsest graphs this small */
     uint64_t mpnn_seed;     /* 0: seed of the network's probe features */
     const float *mpnn_params; /* NULL: device fp32 master weights, gp_mpnn_param_count(k) of them */
 } gp_params;
@@ -302,6 +302,9 @@ const char *gp_last_error(void);
 void gp_profile_enable(int on);
 /* Restrict recording to launches of kernel `name` (NULL: record all). */
 void gp_profile_select(const char *name);
+/* Create the HIP events for `launches` recorded launches ahead of time, so
+ * that recording inside a timed region creates none. */
+int gp_profile_reserve(int launches);
 int gp_profile_count(void);
 int gp_profile_get(int i, char *name, int name_len, int64_t *launches, double *ms, double *bytes);
 

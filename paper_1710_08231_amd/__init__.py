@@ -74,7 +74,7 @@ class Result(ctypes.Structure):
 
 EXPORTS = ["gp_default_params", "gp_lmax", "gp_lp_cluster", "gp_lp_refine", "gp_contract",
            "gp_project", "gp_cut_and_blocks", "gp_partition", "gp_partition_batch", "gp_strerror", "gp_last_error",
-           "gp_profile_enable", "gp_profile_select", "gp_profile_count", "gp_profile_get", "gp_coarsest", "gp_coarsest_batch",
+           "gp_profile_enable", "gp_profile_select", "gp_profile_reserve", "gp_profile_count", "gp_profile_get", "gp_coarsest", "gp_coarsest_batch",
            "gp_mpnn_param_count", "gp_mpnn_features", "gp_mpnn_forward", "gp_mpnn_decode", "gp_mpnn_backward", "gp_mpnn_adam_step"]
 
 
@@ -120,6 +120,7 @@ def load():
     lib.gp_last_error.argtypes = []
     lib.gp_profile_enable.argtypes = [ctypes.c_int]
     lib.gp_profile_select.argtypes = [ctypes.c_char_p]
+    lib.gp_profile_reserve.argtypes = [ctypes.c_int]
     lib.gp_profile_count.restype = ctypes.c_int
     lib.gp_profile_get.argtypes = [ctypes.c_int, ctypes.c_char_p, ctypes.c_int, ctypes.POINTER(i64),
                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
@@ -424,6 +425,11 @@ def profile_enable(on=True):
 def profile_select(name=None):
     """Record only launches of kernel `name` (None: all)."""
     load().gp_profile_select(None if name is None else name.encode())
+
+
+def profile_reserve(launches):
+    """Pre-create the events of `launches` recorded launches (none are created while timing)."""
+    _check(load().gp_profile_reserve(int(launches)))
 
 
 def profile_entries():

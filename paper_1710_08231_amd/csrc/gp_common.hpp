@@ -4,6 +4,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -16,6 +17,23 @@ constexpr int kWave = 64;
 
 void set_error(const char *msg);
 const char *last_error();
+
+// Host time spent in stream-ordered allocation calls (reported by GP_TRACE=1).
+struct AllocStats {
+    double host_ms = 0;
+    int64_t calls = 0, bytes = 0;
+};
+AllocStats &alloc_stats();
+
+inline hipError_t timed_malloc_async(void **p, size_t bytes, hipStream_t s) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const hipError_t e = hipMallocAsync(p, bytes, s);
+    AllocStats &a = alloc_stats();
+    a.host_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    a.calls++;
+    a.bytes += (int64_t)bytes;
+    return e;
+}
 
 // Returns GP_ERR_HIP (with a message) when a HIP call fails.
 #define GP_HIP(expr)                                                              \
@@ -48,7 +66,7 @@ class Scratch {
     int alloc(T **out, size_t count) {
         void *p = nullptr;
         size_t bytes = (count ? count : 1) * sizeof(T);
-        hipError_t e = hipMallocAsync(&p, bytes, s_);
+        hipError_t e = timed_malloc_async(&p, bytes, s_);
         if (e != hipSuccess) {
             set_error((std::string("hipMallocAsync(") + std::to_string(bytes) + "): " +
                        hipGetErrorString(e)).c_str());
@@ -74,7 +92,7 @@ class Scratch {
             if (tmp_[slot].first) (void)hipFreeAsync(tmp_[slot].first, s_);
             void *p = nullptr;
             const size_t grow = bytes + bytes / 4;
-            hipError_t e = hipMallocAsync(&p, grow, s_);
+            hipError_t e = timed_malloc_async(&p, grow, s_);
             if (e != hipSuccess) {
                 set_error((std::string("hipMallocAsync(") + std::to_string(grow) + "): " +
                            hipGetErrorString(e)).c_str());

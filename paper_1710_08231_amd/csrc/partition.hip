@@ -5,6 +5,7 @@
 // of lp.hip, contract.hip and initpart.hip. The host reads back two integers
 // per level (coarse n and nnz) and small tier counts; rounds of LP never
 // synchronise with the host.
+#include <chrono>
 #include <climits>
 #include <cmath>
 #include <cstdio>
@@ -21,6 +22,10 @@ namespace gp {
 static thread_local std::string g_err;
 void set_error(const char *msg) { g_err = msg; }
 const char *last_error() { return g_err.c_str(); }
+AllocStats &alloc_stats() {
+    static AllocStats a;
+    return a;
+}
 
 namespace {
 struct ProfAcc {
@@ -276,6 +281,8 @@ static int do_partition(const gp_graph *gin, int32_t k, double eps, const gp_par
                         gp_result *res, hipStream_t s, CoarsestOut *cout = nullptr) {
     Scratch sc(s);
     Timer t_total(s);
+    const auto host_t0 = std::chrono::steady_clock::now();
+    const AllocStats alloc0 = alloc_stats();
     const DevGraph g0 = dev_graph(gin);
     GraphInfo gi;
     GP_TRY(graph_info(g0, gi, sc));
@@ -436,6 +443,13 @@ static int do_partition(const gp_graph *gin, int32_t k, double eps, const gp_par
     GP_HIP(hipMemcpyAsync(hB.data(), B, sizeof(int64_t) * k, hipMemcpyDeviceToHost, s));
     GP_HIP(hipMemcpyAsync(&cut, dcut, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     const float ms_total = t_total.stop();
+    if (tracing()) {
+        const AllocStats &a = alloc_stats();
+        std::fprintf(stderr, "[gp] partition device %.3f ms, host %.3f ms; %lld allocations (%.1f MB) took %.3f ms of host time\n",
+                     ms_total,
+                     std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - host_t0).count(),
+                     (long long)(a.calls - alloc0.calls), (a.bytes - alloc0.bytes) / 1e6, a.host_ms - alloc0.host_ms);
+    }
     int64_t maxb = 0;
     for (int b = 0; b < k; b++) maxb = std::max(maxb, hB[b]);
     if (res) {
@@ -480,7 +494,7 @@ void gp_default_params(gp_params *p) {
     p->dir_alternate = 1;
     p->seed = 0;
     p->init_mode = GP_INIT_PLAIN;
-    p->mpnn_max_n = 65536;
+    p->mpnn_max_n = 131072;
     p->mpnn_seed = 0;
     p->mpnn_params = nullptr;
 }
@@ -845,6 +859,16 @@ void gp_profile_enable(int on) {
 }
 
 void gp_profile_select(const char *name) { gp::g_only = name ? name : ""; }
+
+int gp_profile_reserve(int launches) {
+    gp::prof_flush();
+    while ((int)gp::g_events.size() < 2 * launches) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return GP_ERR_HIP;
+        gp::g_events.push_back(e);
+    }
+    return GP_OK;
+}
 
 int gp_profile_count(void) {
     gp::prof_flush();
