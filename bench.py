@@ -223,6 +223,8 @@ def main():
     ap.add_argument("--workload", default="rmat22", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-rounds", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="time without the per-kernel HIP events (roofline is then null)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -272,9 +274,10 @@ def main():
     results = []
     # timed region: HIP events around the dominant kernel's launches only, on the
     # library's stream (created beforehand, so none is created while timing)
-    gp.profile_select(dominant)
-    gp.profile_enable(True)
-    gp.profile_reserve(dom_launches * args.steps + 64)
+    if not args.no_profile:
+        gp.profile_select(dominant)
+        gp.profile_enable(True)
+        gp.profile_reserve(dom_launches * args.steps + 64)
     step_ms = []
     t = time.perf_counter()
     for i in range(args.steps):
@@ -285,7 +288,7 @@ def main():
         results.append(res)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
-    prof = gp.profile_entries()
+    prof = gp.profile_entries() if not args.no_profile else []
     gp.profile_enable(False)
     gp.profile_select(None)
     ms = dt * 1000.0 / args.steps

@@ -30,9 +30,12 @@
  *  - Outputs named *_host are host pointers; every other array is a device
  *    pointer supplied and owned by the caller.
  *  - Work is ordered on `stream`. Calls that return host values synchronise
- *    the stream before returning. The library allocates its own temporary
- *    device memory stream-ordered (hipMallocAsync on `stream`) and frees it
- *    before returning; it never frees caller memory.
+ *    the stream before returning. The library takes its temporary device
+ *    memory from a cache it keeps per (device, stream): blocks allocated
+ *    stream-ordered (hipMallocAsync on `stream`) the first time a call needs
+ *    them and reused by later calls on that stream; gp_release_cache() frees
+ *    them. It never frees caller memory. Concurrent calls on one stream from
+ *    several host threads are not supported.
  *  - Return value: GP_OK (0), GP_WARN_IMBALANCED (1, valid result whose
  *    largest block exceeds L_max), or a negative error code; gp_strerror()
  *    and gp_last_error() describe it. On error the outputs are unspecified.
@@ -287,6 +290,10 @@ int gp_partition_batch(const gp_graph *g, int32_t G, const int32_t *vtx_off_host
 
 const char *gp_strerror(int code);
 const char *gp_last_error(void);
+
+/* Frees the library's cached device memory of every (device, stream) after
+ * synchronising those streams. Must not run while a library call is active. */
+int gp_release_cache(void);
 
 /*
  * Instrumentation for measurement (not part of the method). When enabled,

@@ -73,7 +73,7 @@ class Result(ctypes.Structure):
 
 
 EXPORTS = ["gp_default_params", "gp_lmax", "gp_lp_cluster", "gp_lp_refine", "gp_contract",
-           "gp_project", "gp_cut_and_blocks", "gp_partition", "gp_partition_batch", "gp_strerror", "gp_last_error",
+           "gp_project", "gp_cut_and_blocks", "gp_partition", "gp_partition_batch", "gp_strerror", "gp_last_error", "gp_release_cache",
            "gp_profile_enable", "gp_profile_select", "gp_profile_reserve", "gp_profile_count", "gp_profile_get", "gp_coarsest", "gp_coarsest_batch",
            "gp_mpnn_param_count", "gp_mpnn_features", "gp_mpnn_forward", "gp_mpnn_decode", "gp_mpnn_backward", "gp_mpnn_adam_step"]
 
@@ -114,6 +114,7 @@ def load():
                                      ctypes.POINTER(ctypes.c_double), vp]
     lib.gp_mpnn_adam_step.argtypes = [vp, vp, vp, vp, i32, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                       ctypes.c_float, vp]
+    lib.gp_release_cache.argtypes = []
     lib.gp_strerror.restype = ctypes.c_char_p
     lib.gp_strerror.argtypes = [ctypes.c_int]
     lib.gp_last_error.restype = ctypes.c_char_p
@@ -415,6 +416,11 @@ def mpnn_adam_step(params, m, v, grad, step, lr=1e-3, beta1=0.9, beta2=0.999, ep
             raise GPError("params, m, v and grad must be contiguous and of one size")
     _check(load().gp_mpnn_adam_step(_ptr(params), _ptr(m), _ptr(v), _ptr(grad), params.numel(), step, lr, beta1,
                                     beta2, eps, _stream()))
+
+
+def release_cache():
+    """Free the device memory the library keeps for reuse between calls."""
+    _check(load().gp_release_cache())
 
 
 def profile_enable(on=True):

@@ -53,11 +53,40 @@ inline hipError_t timed_malloc_async(void **p, size_t bytes, hipStream_t s) {
 
 #define GP_LAUNCH_CHECK() GP_HIP(hipGetLastError())
 
-// Stream-ordered scratch memory for one library call. Every buffer is
-// released (hipFreeAsync on the same stream) when the object goes out of scope.
+// Per-(device, stream) cache of device memory reused by successive library
+// calls on that stream: a list of large blocks served as a bump allocator by
+// one call at a time and rewound when the call ends. Work is ordered on the
+// stream, so a later call may reuse the memory of an earlier one at once.
+// Blocks are allocated stream-ordered and kept until gp_release_cache().
+struct Arena {
+    struct Block {
+        char *p;
+        size_t size;
+    };
+    std::vector<Block> blocks;
+    size_t cur = 0, off = 0;
+    bool busy = false;
+};
+// The arena of (current device, s), created on first use; null on failure.
+Arena *arena_for(hipStream_t s);
+
+// Scratch memory for one library call, taken from the stream's arena (or,
+// if that arena is already serving another live Scratch, allocated with
+// hipMallocAsync and freed on release). Everything is given back when the
+// object goes out of scope.
 class Scratch {
   public:
-    explicit Scratch(hipStream_t s) : s_(s) { keep_pool(); }
+    explicit Scratch(hipStream_t s) : s_(s) {
+        keep_pool();
+        a_ = arena_for(s);
+        if (a_ && !a_->busy) {
+            a_->busy = true;
+            a_->cur = 0;
+            a_->off = 0;
+        } else {
+            a_ = nullptr;
+        }
+    }
     ~Scratch() { release(); }
     Scratch(const Scratch &) = delete;
     Scratch &operator=(const Scratch &) = delete;
@@ -65,7 +94,12 @@ class Scratch {
     template <typename T>
     int alloc(T **out, size_t count) {
         void *p = nullptr;
-        size_t bytes = (count ? count : 1) * sizeof(T);
+        const size_t bytes = ((count ? count : 1) * sizeof(T) + 255) & ~(size_t)255;
+        if (a_) {
+            const int rc = take(bytes, &p);
+            *out = static_cast<T *>(p);
+            return rc;
+        }
         hipError_t e = timed_malloc_async(&p, bytes, s_);
         if (e != hipSuccess) {
             set_error((std::string("hipMallocAsync(") + std::to_string(bytes) + "): " +
@@ -89,16 +123,9 @@ class Scratch {
         }
         if (tmp_[slot].second < bytes) {
             if (frozen_) return frozen_fail();
-            if (tmp_[slot].first) (void)hipFreeAsync(tmp_[slot].first, s_);
-            void *p = nullptr;
             const size_t grow = bytes + bytes / 4;
-            hipError_t e = timed_malloc_async(&p, grow, s_);
-            if (e != hipSuccess) {
-                set_error((std::string("hipMallocAsync(") + std::to_string(grow) + "): " +
-                           hipGetErrorString(e)).c_str());
-                tmp_[slot] = {nullptr, 0};
-                return GP_ERR_HIP;
-            }
+            char *p = nullptr;
+            GP_TRY(alloc(&p, grow));  // the outgrown buffer returns with the rest at release
             tmp_[slot] = {p, grow};
         }
         *out = static_cast<T *>(tmp_[slot].first);
@@ -107,9 +134,13 @@ class Scratch {
     void release() {
         for (void *p : ptrs_) (void)hipFreeAsync(p, s_);
         ptrs_.clear();
-        for (auto &t : tmp_)
-            if (t.first) (void)hipFreeAsync(t.first, s_);
         tmp_.clear();
+        if (a_) {
+            a_->cur = 0;
+            a_->off = 0;
+            a_->busy = false;
+            a_ = nullptr;
+        }
     }
     hipStream_t stream() const { return launch_ ? launch_ : s_; }
     // Launch subsequent work on `st` (for recording a launch sequence); while
@@ -120,6 +151,32 @@ class Scratch {
     }
 
   private:
+    static constexpr size_t kMinBlock = size_t(512) << 20;
+    int take(size_t bytes, void **p) {
+        while (a_->cur < a_->blocks.size()) {
+            Arena::Block &b = a_->blocks[a_->cur];
+            if (a_->off + bytes <= b.size) {
+                *p = b.p + a_->off;
+                a_->off += bytes;
+                return GP_OK;
+            }
+            a_->cur++;
+            a_->off = 0;
+        }
+        void *q = nullptr;
+        const size_t size = bytes > kMinBlock ? bytes : kMinBlock;
+        hipError_t e = timed_malloc_async(&q, size, s_);
+        if (e != hipSuccess) {
+            set_error((std::string("hipMallocAsync(") + std::to_string(size) + "): " + hipGetErrorString(e)).c_str());
+            *p = nullptr;
+            return GP_ERR_HIP;
+        }
+        a_->blocks.push_back({static_cast<char *>(q), size});
+        a_->cur = a_->blocks.size() - 1;
+        a_->off = bytes;
+        *p = q;
+        return GP_OK;
+    }
     int frozen_fail() {
         set_error("scratch slot would grow while a launch sequence is recorded");
         return GP_ERR_HIP;
@@ -140,6 +197,7 @@ class Scratch {
     hipStream_t s_;
     hipStream_t launch_ = nullptr;
     bool frozen_ = false;
+    Arena *a_ = nullptr;
     std::vector<void *> ptrs_;
     std::vector<std::pair<void *, size_t>> tmp_;
 };

@@ -10,6 +10,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <map>
+#include <mutex>
 #include <string>
 
 #include "contract.hpp"
@@ -24,6 +26,20 @@ void set_error(const char *msg) { g_err = msg; }
 const char *last_error() { return g_err.c_str(); }
 AllocStats &alloc_stats() {
     static AllocStats a;
+    return a;
+}
+
+namespace {
+std::mutex g_arena_mu;
+std::map<std::pair<int, hipStream_t>, Arena *> g_arenas;
+}  // namespace
+
+Arena *arena_for(hipStream_t s) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(g_arena_mu);
+    Arena *&a = g_arenas[{dev, s}];
+    if (!a) a = new Arena();
     return a;
 }
 
@@ -859,6 +875,28 @@ void gp_profile_enable(int on) {
 }
 
 void gp_profile_select(const char *name) { gp::g_only = name ? name : ""; }
+
+int gp_release_cache(void) {
+    std::lock_guard<std::mutex> lk(gp::g_arena_mu);
+    int dev0 = 0;
+    GP_HIP(hipGetDevice(&dev0));
+    for (auto &kv : gp::g_arenas) {
+        gp::Arena *a = kv.second;
+        if (a->busy) {
+            set_error("release_cache: a library call is still using the cache");
+            return GP_ERR_ARG;
+        }
+    }
+    for (auto &kv : gp::g_arenas) {
+        GP_HIP(hipSetDevice(kv.first.first));
+        GP_HIP(hipStreamSynchronize(kv.first.second));
+        for (auto &b : kv.second->blocks) GP_HIP(hipFree(b.p));
+        delete kv.second;
+    }
+    gp::g_arenas.clear();
+    GP_HIP(hipSetDevice(dev0));
+    return GP_OK;
+}
 
 int gp_profile_reserve(int launches) {
     gp::prof_flush();

@@ -231,3 +231,19 @@ def test_repeat_runs_identical(dev_cases):
     a, _ = gp.partition(dev_cases["rmat16"], 16, 0.03)
     b, _ = gp.partition(dev_cases["rmat16"], 16, 0.03)
     assert torch.equal(a, b)
+
+
+def test_cached_memory_reuse_and_release():
+    # successive calls reuse the library's cached device memory; releasing it
+    # in between changes nothing
+    g1, g2 = graphgen.rmat(12, 8), graphgen.rgg2d(3000, 9)
+    d1, d2 = gp.to_device(g1), gp.to_device(g2)
+    p1, r1 = gp.partition(d1, 8)
+    p2, r2 = gp.partition(d2, 4)
+    gp.release_cache()
+    q1, s1 = gp.partition(d1, 8)
+    q2, s2 = gp.partition(d2, 4)
+    assert torch.equal(p1, q1) and torch.equal(p2, q2)
+    assert r1["cut"] == s1["cut"] and r2["cut"] == s2["cut"]
+    op, _ = oracle.partition(g2, 4)
+    assert np.array_equal(q2.cpu().numpy(), op)
