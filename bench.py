@@ -61,11 +61,13 @@ def cpu_baseline(g, w, budget_rounds):
     g0 = {"xadj": np.concatenate([[0], np.cumsum(d[keep])]).astype(np.int32),
           "adjncy": newid[g["adjncy"]].astype(np.int32)}
     t = time.perf_counter()
-    _, st = oracle.lp_cluster(g0, ucl, budget_rounds)
+    # bounded sample: at most `budget_rounds` rounds and about 1.5e9 edge visits (10-30 s on one core)
+    rounds = max(1, min(budget_rounds, int(1.5e9 // max(1, len(g0["adjncy"])))))
+    _, st = oracle.lp_cluster(g0, ucl, rounds)
     dt = time.perf_counter() - t
     return {"value": st["edge_visits"] / dt, "unit": "edge-visits/s", "cores": 1, "kind": "oracle",
             "sample": f"oracle lp_cluster on level 0 of the same graph (isolated vertices removed), "
-                      f"U={ucl}, up to {budget_rounds} rounds: {st['edge_visits']} edge visits in {dt:.1f} s"}
+                      f"U={ucl}, up to {rounds} rounds: {st['edge_visits']} edge visits in {dt:.1f} s"}
 
 
 def roofline(prof, workload):
@@ -91,6 +93,24 @@ def lp_source_sha1():
     import hashlib
     with open(os.path.join(ROOT, "paper_1710_08231_amd", "csrc", "lp.hip"), "rb") as f:
         return hashlib.sha1(f.read()).hexdigest()
+
+
+TUNING = {"source": "defaults"}
+
+
+def apply_tuning(args):
+    """Apply the autotuned LP thresholds of this workload, when present (they
+    change speed only, never a result)."""
+    import paper_1710_08231_amd as gp
+    path = os.path.join(ROOT, "paper_1710_08231_amd", "tuning", f"{args.workload}.json")
+    if args.no_tuning or not os.path.exists(path):
+        return
+    with open(path) as f:
+        t = json.load(f)["tuning"]
+    gp.set_tuning(t)
+    TUNING.clear()
+    TUNING.update(t)
+    TUNING["source"] = os.path.relpath(path, ROOT)
 
 
 def bench_batch(args, w):
@@ -133,7 +153,7 @@ def bench_batch(args, w):
         "warmup": max(1, args.warmup), "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": "batch512", "graphs": len(ks), "n": n, "nnz": nnz, "k": "per graph {2,8,32}",
-                   "eps": 0.03},
+                   "eps": 0.03, "tuning": TUNING},
         "partition_ms": ms,
         "cut_total": sum(r["cut"] for r in res),
         "balanced_graphs": sum(r["balanced"] for r in res),
@@ -191,7 +211,7 @@ def bench_learned(args, w):
         "vs_baseline": None, "dtype": "int32+fp32", "data": "synthetic",
         "config": {"workload": "learned24", "graph": "rmat scale 24 ef 16 seed 24", "n": n, "nnz": nnz, "k": k,
                    "eps": 0.03, "partition_seeds": f"0..{args.steps - 1}",
-                   "init": "learned proposal judged against best of 4 bisections"},
+                   "init": "learned proposal judged against best of 4 bisections", "tuning": TUNING},
         "partition_ms": ms, "plain_form_ms": t_plain * 1000.0 / args.steps,
         "cut_geomean_learned_over_plain": geo,
         "proposals_tried": sum(r["tried"] for r in rows),
@@ -223,6 +243,8 @@ def main():
     ap.add_argument("--workload", default="rmat22", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-rounds", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tuning", action="store_true",
+                    help="ignore paper_1710_08231_amd/tuning/<workload>.json (use the default thresholds)")
     ap.add_argument("--no-profile", action="store_true",
                     help="time without the per-kernel HIP events (roofline is then null)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -239,6 +261,7 @@ def main():
     if args.calibrate_copy:
         return calibrate_copy(args)
     w = WORKLOADS[args.workload]
+    apply_tuning(args)
     if w["kind"] == "batch":
         return bench_batch(args, w)
     if w["kind"] == "learned":
@@ -308,7 +331,7 @@ def main():
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": args.workload, "n": n, "nnz": nnz, "k": k, "eps": 0.03},
+        "config": {"workload": args.workload, "n": n, "nnz": nnz, "k": k, "eps": 0.03, "tuning": TUNING},
         "partition_ms": ms,
         "cut": last["cut"],
         "balanced": bool(last["balanced"]),

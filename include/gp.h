@@ -291,6 +291,26 @@ int gp_partition_batch(const gp_graph *g, int32_t G, const int32_t *vtx_off_host
 const char *gp_strerror(int code);
 const char *gp_last_error(void);
 
+/*
+ * Execution thresholds of the LP kernels (process-wide; results never depend
+ * on them, only speed). tier_max: upper degree bounds of the hashed-table
+ * tiers served by 32 lanes, 64 lanes, a 256-thread and a 1024-thread
+ * workgroup (defaults 64, 256, 2048, 8192 — also the largest allowed, as each
+ * tier's table holds twice its bound; non-decreasing, tier_max[0] >= 16);
+ * vertices above the last bound take the multi-workgroup path. dense_split:
+ * with k <= 256 labels, rows above this degree are split into chunks of
+ * dense_chunk entries, one workgroup each (defaults 256 and 2048).
+ * gp_set_tuning(NULL) restores the defaults; invalid values give GP_ERR_ARG.
+ * Chosen per workload by paper_1710_08231_amd/autotune.py.
+ */
+typedef struct {
+    int32_t tier_max[4];
+    int32_t dense_split;
+    int32_t dense_chunk;
+} gp_tuning;
+void gp_get_tuning(gp_tuning *t);
+int gp_set_tuning(const gp_tuning *t);
+
 /* Frees the library's cached device memory of every (device, stream) after
  * synchronising those streams. Must not run while a library call is active. */
 int gp_release_cache(void);

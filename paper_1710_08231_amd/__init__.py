@@ -61,6 +61,10 @@ class Params(ctypes.Structure):
                 ("mpnn_seed", ctypes.c_uint64), ("mpnn_params", ctypes.c_void_p)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("tier_max", ctypes.c_int32 * 4), ("dense_split", ctypes.c_int32), ("dense_chunk", ctypes.c_int32)]
+
+
 class Result(ctypes.Structure):
     _fields_ = [("cut", ctypes.c_int64), ("max_block_w", ctypes.c_int64), ("lmax", ctypes.c_int64),
                 ("ucl", ctypes.c_int64), ("balanced", ctypes.c_int32), ("levels", ctypes.c_int32),
@@ -73,7 +77,7 @@ class Result(ctypes.Structure):
 
 
 EXPORTS = ["gp_default_params", "gp_lmax", "gp_lp_cluster", "gp_lp_refine", "gp_contract",
-           "gp_project", "gp_cut_and_blocks", "gp_partition", "gp_partition_batch", "gp_strerror", "gp_last_error", "gp_release_cache",
+           "gp_project", "gp_cut_and_blocks", "gp_partition", "gp_partition_batch", "gp_strerror", "gp_last_error", "gp_release_cache", "gp_get_tuning", "gp_set_tuning",
            "gp_profile_enable", "gp_profile_select", "gp_profile_reserve", "gp_profile_count", "gp_profile_get", "gp_coarsest", "gp_coarsest_batch",
            "gp_mpnn_param_count", "gp_mpnn_features", "gp_mpnn_forward", "gp_mpnn_decode", "gp_mpnn_backward", "gp_mpnn_adam_step"]
 
@@ -115,6 +119,8 @@ def load():
     lib.gp_mpnn_adam_step.argtypes = [vp, vp, vp, vp, i32, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                       ctypes.c_float, vp]
     lib.gp_release_cache.argtypes = []
+    lib.gp_get_tuning.argtypes = [ctypes.POINTER(Tuning)]
+    lib.gp_set_tuning.argtypes = [ctypes.POINTER(Tuning)]
     lib.gp_strerror.restype = ctypes.c_char_p
     lib.gp_strerror.argtypes = [ctypes.c_int]
     lib.gp_last_error.restype = ctypes.c_char_p
@@ -416,6 +422,23 @@ def mpnn_adam_step(params, m, v, grad, step, lr=1e-3, beta1=0.9, beta2=0.999, ep
             raise GPError("params, m, v and grad must be contiguous and of one size")
     _check(load().gp_mpnn_adam_step(_ptr(params), _ptr(m), _ptr(v), _ptr(grad), params.numel(), step, lr, beta1,
                                     beta2, eps, _stream()))
+
+
+def get_tuning():
+    """Current LP execution thresholds as a dict."""
+    t = Tuning()
+    load().gp_get_tuning(ctypes.byref(t))
+    return {"tier_max": list(t.tier_max), "dense_split": t.dense_split, "dense_chunk": t.dense_chunk}
+
+
+def set_tuning(tuning=None):
+    """Set the LP execution thresholds (dict as from get_tuning; None restores the defaults)."""
+    lib = load()
+    if tuning is None:
+        _check(lib.gp_set_tuning(None))
+        return
+    t = Tuning((ctypes.c_int32 * 4)(*tuning["tier_max"]), tuning["dense_split"], tuning["dense_chunk"])
+    _check(lib.gp_set_tuning(ctypes.byref(t)))
 
 
 def release_cache():

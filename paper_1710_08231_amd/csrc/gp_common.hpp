@@ -65,6 +65,8 @@ struct Arena {
     };
     std::vector<Block> blocks;
     size_t cur = 0, off = 0;
+    size_t need = 0;    // bytes taken by the current call
+    bool grew = false;  // the current call had to add a block
     bool busy = false;
 };
 // The arena of (current device, s), created on first use; null on failure.
@@ -136,8 +138,11 @@ class Scratch {
         ptrs_.clear();
         tmp_.clear();
         if (a_) {
+            if (a_->grew && a_->blocks.size() > 1) consolidate();
             a_->cur = 0;
             a_->off = 0;
+            a_->need = 0;
+            a_->grew = false;
             a_->busy = false;
             a_ = nullptr;
         }
@@ -152,7 +157,23 @@ class Scratch {
 
   private:
     static constexpr size_t kMinBlock = size_t(512) << 20;
+    // After a call that had to grow the cache, replace its blocks by one block
+    // of the call's total, so a call with the same needs fits without gaps and
+    // the cache stays at one high-water mark instead of accumulating blocks.
+    void consolidate() {
+        for (auto &b : a_->blocks) (void)hipFreeAsync(b.p, s_);
+        a_->blocks.clear();
+        (void)hipStreamSynchronize(s_);
+        int dev = 0;
+        hipMemPool_t pool;
+        if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess)
+            (void)hipMemPoolTrimTo(pool, 0);
+        void *q = nullptr;
+        if (timed_malloc_async(&q, a_->need, s_) == hipSuccess) a_->blocks.push_back({static_cast<char *>(q), a_->need});
+        else (void)hipGetLastError();  // the next call grows the cache again
+    }
     int take(size_t bytes, void **p) {
+        a_->need += bytes;
         while (a_->cur < a_->blocks.size()) {
             Arena::Block &b = a_->blocks[a_->cur];
             if (a_->off + bytes <= b.size) {
@@ -172,6 +193,7 @@ class Scratch {
             return GP_ERR_HIP;
         }
         a_->blocks.push_back({static_cast<char *>(q), size});
+        a_->grew = true;
         a_->cur = a_->blocks.size() - 1;
         a_->off = bytes;
         *p = q;

@@ -17,6 +17,7 @@
 //      order independent), count moves, update the device stop flag.
 // No host synchronisation happens between rounds; after the stop flag is set
 // every later kernel of the call returns immediately.
+#include <algorithm>
 #include <climits>
 #include <cstdlib>
 #include <string>
@@ -616,8 +617,6 @@ __global__ __launch_bounds__(kPropBlock) void k_dense_group(LPArgs a, int32_t nl
 // kDenseChunk entries, one workgroup per chunk; each chunk adds its k
 // connection sums into the vertex's row of a global [nbig x KT] array, then
 // one wave per vertex selects. No single workgroup walks a whole hub.
-constexpr int kDenseChunk = 2048;
-
 struct DenseBig {
     const int32_t *verts;        // [nbig]
     const int32_t *chunk_owner;  // [nchunks] index into verts
@@ -625,6 +624,7 @@ struct DenseBig {
     void *gconn;                 // [nbig * KT] AccT
     unsigned long long *own;     // [nbig]
     int32_t nbig;
+    int32_t chunk;               // entries per chunk workgroup
 };
 
 template <typename AccT>
@@ -651,8 +651,8 @@ __global__ __launch_bounds__(256) void k_dense_chunk(LPArgs a, DenseBig db) {
     const int32_t b = db.chunk_owner[blockIdx.x];
     const int32_t v = db.verts[b];
     const int32_t own = a.labels[v];
-    const int32_t beg = a.xadj[v] + (blockIdx.x - db.chunk_first[b]) * kDenseChunk;
-    const int32_t end = min(a.xadj[v + 1], beg + kDenseChunk);
+    const int32_t beg = a.xadj[v] + (blockIdx.x - db.chunk_first[b]) * db.chunk;
+    const int32_t end = min(a.xadj[v + 1], beg + db.chunk);
     AccT oc = 0;
     for (int32_t e0 = beg + threadIdx.x; e0 < end; e0 += 4 * 256) {
         int32_t u[4], L[4];
@@ -765,11 +765,10 @@ __global__ void k_chunk_counts(const int32_t *xadj, const int32_t *verts, int32_
 // Degree tiers. Tier 0: no neighbours (never proposes). Tiers 1..5: GL lanes
 // per vertex. Tier 6, 7: one workgroup per vertex. Tier 8: hub (global table).
 constexpr int kTiers = 9;
-struct TierSpec {
-    int32_t maxdeg;
-};
-// Upper degree bound per tier for narrow (int32) / wide (int64) sums.
-__host__ __device__ inline int32_t tier_max(int t, bool wide) {
+
+// Largest degree each hashed-table tier can hold (its table has 2x slots);
+// the tuned bounds may only be lower.
+__host__ __device__ inline int32_t tier_cap(int t, bool wide) {
     switch (t) {
         case 0: return 0;
         case 1: return 4;
@@ -788,6 +787,7 @@ struct TierKey {
     const int32_t *active;  // optional: labels array, vertices with label < 0 go to tier 0
     const uint8_t *frozen;  // optional: vertices with frozen[v] != 0 go to tier 0 (keep their label)
     bool wide;
+    int32_t bound[kTiers];  // upper degree bound of each tier (non-decreasing, bound[8] = INT_MAX)
 };
 
 __global__ void k_tier_keys(TierKey tk, int32_t n, uint32_t *key, int32_t *val, int32_t *counts,
@@ -805,7 +805,7 @@ __global__ void k_tier_keys(TierKey tk, int32_t n, uint32_t *key, int32_t *val, 
         int t = 0;
         if (d > 0 && !(tk.active && tk.active[v] < 0) && !(tk.frozen && tk.frozen[v])) {
             t = 1;
-            while (t < kTiers - 1 && d > tier_max(t, tk.wide)) t++;
+            while (t < kTiers - 1 && d > tk.bound[t]) t++;
         }
         key[v] = (uint32_t)t;
         val[v] = (int32_t)v;
@@ -1067,6 +1067,26 @@ hipStream_t capture_stream() {
 
 }  // namespace
 
+Tuning &tuning() {
+    static Tuning t;
+    return t;
+}
+
+int set_tuning(const Tuning &t) {
+    const int32_t *b = t.tier_max;
+    const bool ok = b[0] >= tier_cap(3, false) && b[0] <= tier_cap(4, false) && b[1] >= b[0] &&
+                    b[1] <= tier_cap(5, false) && b[2] >= b[1] && b[2] <= tier_cap(6, false) && b[3] >= b[2] &&
+                    b[3] <= tier_cap(7, false) && t.dense_split >= 16 && t.dense_split <= (1 << 30) &&
+                    t.dense_chunk >= 256 && t.dense_chunk <= 65536 && t.dense_chunk % 256 == 0;
+    if (!ok) {
+        set_error("tuning: tier bounds must be non-decreasing within 16..64, ..256, ..2048, ..8192; dense_split in "
+                  "16..2^30; dense_chunk a multiple of 256 in 256..65536");
+        return GP_ERR_ARG;
+    }
+    tuning() = t;
+    return GP_OK;
+}
+
 int total_edge_weight(const DevGraph &g, int64_t *out, Scratch &sc) {
     if (!g.adjwgt) {
         *out = g.nnz;
@@ -1115,7 +1135,18 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
     GP_TRY(sc.alloc(&tedge, kTiers));
     GP_HIP(hipMemsetAsync(tcnt, 0, sizeof(int32_t) * kTiers, s));
     GP_HIP(hipMemsetAsync(tedge, 0, sizeof(unsigned long long) * kTiers, s));
-    TierKey tk{g.xadj, labels, frozen, wide};
+    TierKey tk{g.xadj, labels, frozen, wide, {}};
+    {
+        const Tuning &tu = tuning();
+        const bool dense_tiers = nlabels <= kDenseLabels;
+        for (int t = 0; t < kTiers; t++) tk.bound[t] = tier_cap(t, wide);
+        for (int t = 4; t <= 7; t++) tk.bound[t] = std::min(tu.tier_max[t - 4], tier_cap(t, wide));
+        if (dense_tiers) {  // dense tables have no degree limit: rows above the split are chunked
+            tk.bound[5] = std::max(tk.bound[4], tu.dense_split);
+            tk.bound[6] = tk.bound[7] = tk.bound[5];
+        }
+        for (int t = 1; t < kTiers - 1; t++) tk.bound[t] = std::max(tk.bound[t], tk.bound[t - 1]);
+    }
     hipLaunchKernelGGL(k_tier_keys, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, tk, n, tkey, tval, tcnt, tedge);
     GP_LAUNCH_CHECK();
     GP_TRY((radix_sort<uint32_t, int32_t>(&tkey, &tval, &tkey2, &tval2, n, nullptr, 4, sc)));
@@ -1230,8 +1261,9 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
         GP_TRY(sc.alloc(&first, nbig));
         GP_TRY(sc.alloc(&d_tot, 1));
         GP_TRY(sc.alloc(&own, nbig));
+        const int32_t chunk = tuning().dense_chunk;
         hipLaunchKernelGGL(k_chunk_counts, dim3(grid_for(nbig, 256, 4096)), dim3(256), 0, s, g.xadj, big, nbig,
-                           kDenseChunk, num);
+                           chunk, num);
         GP_LAUNCH_CHECK();
         GP_TRY((scan<int32_t>(LoadIn<int32_t>{num}, StoreExcl<int32_t>{first}, nbig, nullptr, d_tot, sc)));
         GP_HIP(hipMemcpyAsync(&dchunks, d_tot, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -1244,7 +1276,7 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
         GP_TRY(sc.alloc((char **)&gconn, cb));
         GP_HIP(hipMemsetAsync(gconn, 0, cb, s));
         GP_HIP(hipMemsetAsync(own, 0, sizeof(unsigned long long) * nbig, s));
-        db = DenseBig{big, owner, first, gconn, own, nbig};
+        db = DenseBig{big, owner, first, gconn, own, nbig, chunk};
     }
 
     // ---- per-round buffers

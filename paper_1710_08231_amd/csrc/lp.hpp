@@ -46,6 +46,17 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
            int32_t dir_alternate, bool wide, LPOut *out, Scratch &sc, const int64_t *capv = nullptr,
            const uint8_t *frozen = nullptr, const int32_t *group = nullptr, int32_t ngroups = 0);
 
+// Execution thresholds of the LP kernels. They choose which kernel serves a
+// vertex and how big vertices are split; results never depend on them.
+struct Tuning {
+    int32_t tier_max[4] = {64, 256, 2048, 8192};  // hashed tables: degree bounds of the 32-lane,
+                                                  // 64-lane, 256-thread and 1024-thread tiers
+    int32_t dense_split = 256;                    // dense tables (k <= 256): rows above are chunked
+    int32_t dense_chunk = 2048;                   // entries per chunk workgroup
+};
+Tuning &tuning();                  // process-wide, read at the start of every LP call
+int set_tuning(const Tuning &t);   // validates against the table capacities
+
 // Sum of edge weights (nnz if adjwgt is null); synchronises the stream.
 int total_edge_weight(const DevGraph &g, int64_t *out, Scratch &sc);
 

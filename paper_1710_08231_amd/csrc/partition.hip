@@ -876,6 +876,24 @@ void gp_profile_enable(int on) {
 
 void gp_profile_select(const char *name) { gp::g_only = name ? name : ""; }
 
+void gp_get_tuning(gp_tuning *t) {
+    if (!t) return;
+    const gp::Tuning &u = gp::tuning();
+    for (int i = 0; i < 4; i++) t->tier_max[i] = u.tier_max[i];
+    t->dense_split = u.dense_split;
+    t->dense_chunk = u.dense_chunk;
+}
+
+int gp_set_tuning(const gp_tuning *t) {
+    gp::Tuning u;
+    if (t) {
+        for (int i = 0; i < 4; i++) u.tier_max[i] = t->tier_max[i];
+        u.dense_split = t->dense_split;
+        u.dense_chunk = t->dense_chunk;
+    }
+    return gp::set_tuning(u);
+}
+
 int gp_release_cache(void) {
     std::lock_guard<std::mutex> lk(gp::g_arena_mu);
     int dev0 = 0;

@@ -247,3 +247,38 @@ def test_cached_memory_reuse_and_release():
     assert r1["cut"] == s1["cut"] and r2["cut"] == s2["cut"]
     op, _ = oracle.partition(g2, 4)
     assert np.array_equal(q2.cpu().numpy(), op)
+
+
+@pytest.mark.parametrize("tuning", [
+    {"tier_max": [16, 16, 16, 16], "dense_split": 16, "dense_chunk": 256},
+    {"tier_max": [32, 128, 1024, 4096], "dense_split": 1024, "dense_chunk": 8192},
+    {"tier_max": [64, 64, 2048, 2048], "dense_split": 100000, "dense_chunk": 65536},
+])
+def test_tuning_changes_no_result(tuning):
+    # execution thresholds move vertices between kernels; labels must not change
+    gs = [(graphgen.rmat(13, 4), 16), (graphgen.grid3d(14, 12, 10, seed=4, wmax=9), 4),
+          (graphgen.rmat_m(12, 60000, 9), 300)]
+    try:
+        gp.set_tuning(tuning)
+        assert gp.get_tuning() == tuning
+        for g, k in gs:
+            p, r = gp.partition(gp.to_device(g), k)
+            op, ores = oracle.partition(g, k)
+            assert np.array_equal(p.cpu().numpy(), op)
+            assert r["cut"] == ores["cut"]
+        g = graphgen.rmat(14, 5)
+        lab, _ = gp.lp_cluster(gp.to_device(g), 500, 10)
+        olab, _ = oracle.lp_cluster(g, 500, 10)
+        assert np.array_equal(lab.cpu().numpy(), olab)
+    finally:
+        gp.set_tuning(None)
+
+
+def test_tuning_rejects_values_beyond_table_capacity():
+    with pytest.raises(gp.GPError):
+        gp.set_tuning({"tier_max": [128, 256, 2048, 8192], "dense_split": 256, "dense_chunk": 2048})
+    with pytest.raises(gp.GPError):
+        gp.set_tuning({"tier_max": [64, 32, 2048, 8192], "dense_split": 256, "dense_chunk": 2048})
+    with pytest.raises(gp.GPError):
+        gp.set_tuning({"tier_max": [64, 256, 2048, 8192], "dense_split": 256, "dense_chunk": 1000})
+    assert gp.get_tuning()["tier_max"] == [64, 256, 2048, 8192]
