@@ -39,6 +39,7 @@ struct LPArgs {
     const int32_t *done;
     const int32_t *round;  // device round counter (rounds replay one captured launch sequence)
     const int64_t *capv;   // optional per-label capacity (batched graphs); null: every label has U
+    const uint8_t *lab8;   // dense mode (<= 256 labels): byte copy of labels for the neighbour gathers
 };
 
 __device__ __forceinline__ int64_t capof(const LPArgs &a, int32_t L) { return a.capv ? a.capv[L] : a.U; }
@@ -429,10 +430,26 @@ __device__ __forceinline__ unsigned long long pack_best(int32_t c, int32_t L) {
     return ((unsigned long long)(uint32_t)c << 32) | (unsigned long long)(uint32_t)(INT_MAX - L);
 }
 
-__global__ __launch_bounds__(256) void k_hub_insert(LPArgs a, HubPlan hp) {
+// One workgroup per chunk of a hub's edges. The chunk's (label, weight) pairs
+// are first summed in an LDS table (at most kHubChunk distinct labels, so the
+// table is at most half full); only the distinct labels then go to the hub's
+// global table, one global insert each instead of one per edge.
+constexpr int kHubLds = 2 * kHubChunk;
+constexpr int kHubLdsLog = 13;
+static_assert((1 << kHubLdsLog) == kHubLds, "LDS table size");
+constexpr int kHubBlock = 1024;
+
+__global__ __launch_bounds__(kHubBlock) void k_hub_insert(LPArgs a, HubPlan hp) {
     if (*a.done) return;
     const int32_t dmode = cur_dirmode(a);
-    __shared__ int32_t tmp[256 / kWave + 1];
+    __shared__ int32_t skey[kHubLds];
+    __shared__ int32_t sval[kHubLds];
+    __shared__ int32_t tmp[kHubBlock / kWave + 1];
+    for (int i = threadIdx.x; i < kHubLds; i += kHubBlock) {
+        skey[i] = -1;
+        sval[i] = 0;
+    }
+    __syncthreads();
     const int32_t h = hp.chunk_hub[blockIdx.x];
     const int32_t v = hp.hubs[h];
     const int32_t own = a.labels[v];
@@ -442,14 +459,19 @@ __global__ __launch_bounds__(256) void k_hub_insert(LPArgs a, HubPlan hp) {
     int32_t *key = hp.key + hp.toff[h];
     int32_t *val = hp.val + hp.toff[h];
     int32_t oc = 0;
-    for (int32_t e = beg + threadIdx.x; e < end; e += 256) {
+    for (int32_t e = beg + threadIdx.x; e < end; e += kHubBlock) {
         const int32_t u = a.adjncy[e];
         const int32_t wgt = a.adjwgt ? a.adjwgt[e] : 1;
         const int32_t L = a.labels[u];
         if (L == own) oc += wgt;
-        else if (dir_ok(L, own, dmode)) tbl_insert_global<int32_t>(key, val, (1u << lg) - 1, lg, L, wgt);
+        else if (dir_ok(L, own, dmode)) tbl_insert<int32_t>(skey, sval, kHubLds - 1, kHubLdsLog, L, wgt);
     }
-    oc = block_sum<256>(oc, tmp);
+    __syncthreads();
+    for (int i = threadIdx.x; i < kHubLds; i += kHubBlock) {
+        const int32_t L = skey[i];
+        if (L >= 0) tbl_insert_global<int32_t>(key, val, (1u << lg) - 1, lg, L, sval[i]);
+    }
+    oc = block_sum<kHubBlock>(oc, tmp);
     if (threadIdx.x == 0 && oc) atomicAdd(&hp.own[h], (unsigned long long)oc);
 }
 
@@ -583,7 +605,7 @@ __global__ __launch_bounds__(kPropBlock) void k_dense_group(LPArgs a, int32_t nl
             const int32_t u0 = e0 < end ? a.adjncy[e0] : -1, u1 = e1 < end ? a.adjncy[e1] : -1;
             const AccT w0 = (e0 < end && a.adjwgt) ? (AccT)a.adjwgt[e0] : (AccT)1;
             const AccT w1 = (e1 < end && a.adjwgt) ? (AccT)a.adjwgt[e1] : (AccT)1;
-            const int32_t L0 = u0 >= 0 ? a.labels[u0] : -1, L1 = u1 >= 0 ? a.labels[u1] : -1;
+            const int32_t L0 = u0 >= 0 ? (int32_t)a.lab8[u0] : -1, L1 = u1 >= 0 ? (int32_t)a.lab8[u1] : -1;
             if (u0 >= 0) {
                 if (L0 == own) oc += w0;
                 else if (dir_ok(L0, own, dmode)) lds_add<AccT>(&val[L0], w0);
@@ -643,10 +665,13 @@ __global__ __launch_bounds__(256) void k_dense_chunk(LPArgs a, DenseBig db) {
     if (*a.done) return;
     const int32_t dmode = cur_dirmode(a);
     constexpr int NW = 256 / kWave;
-    __shared__ AccT val[NW][KT];
+    // SUB tables per wave (lanes split evenly) spread the LDS atomics of a
+    // wave over SUB x KT addresses when k is small
+    constexpr int SUB = KT <= 16 ? 8 : (KT <= 64 ? 4 : 1);
+    __shared__ AccT val[NW * SUB][KT];
     __shared__ AccT tmp[NW + 1];
-    const int w = threadIdx.x / kWave;
-    for (int i = threadIdx.x; i < NW * KT; i += 256) (&val[0][0])[i] = 0;
+    const int w = (threadIdx.x / kWave) * SUB + lane_id() / (kWave / SUB);
+    for (int i = threadIdx.x; i < NW * SUB * KT; i += 256) (&val[0][0])[i] = 0;
     __syncthreads();
     const int32_t b = db.chunk_owner[blockIdx.x];
     const int32_t v = db.verts[b];
@@ -664,7 +689,7 @@ __global__ __launch_bounds__(256) void k_dense_chunk(LPArgs a, DenseBig db) {
             wv[j] = (e < end && a.adjwgt) ? (AccT)a.adjwgt[e] : (AccT)1;
         }
 #pragma unroll
-        for (int j = 0; j < 4; j++) L[j] = u[j] >= 0 ? a.labels[u[j]] : -1;
+        for (int j = 0; j < 4; j++) L[j] = u[j] >= 0 ? (int32_t)a.lab8[u[j]] : -1;
 #pragma unroll
         for (int j = 0; j < 4; j++) {
             if (u[j] < 0) continue;
@@ -676,7 +701,7 @@ __global__ __launch_bounds__(256) void k_dense_chunk(LPArgs a, DenseBig db) {
     AccT *row = (AccT *)db.gconn + (int64_t)b * KT;
     for (int i = threadIdx.x; i < KT; i += 256) {
         AccT c = 0;
-        for (int q = 0; q < NW; q++) c += val[q][i];
+        for (int q = 0; q < NW * SUB; q++) c += val[q][i];
         if (c) gadd<AccT>(&row[i], c);
     }
     oc = block_sum<256>(oc, tmp);
@@ -751,6 +776,11 @@ int launch_dense_any(const LPArgs &a, int32_t nlabels, const int32_t *verts, con
     if (nlabels <= 16) return launch_dense<16, AccT>(a, nlabels, verts, tstart, db, nchunks, s, tb);
     if (nlabels <= 64) return launch_dense<64, AccT>(a, nlabels, verts, tstart, db, nchunks, s, tb);
     return launch_dense<256, AccT>(a, nlabels, verts, tstart, db, nchunks, s, tb);
+}
+
+__global__ void k_labels_u8(const int32_t *labels, int32_t n, uint8_t *lab8) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        lab8[v] = (uint8_t)labels[v];
 }
 
 __global__ void k_chunk_counts(const int32_t *xadj, const int32_t *verts, int32_t nb, int32_t chunk, int32_t *num) {
@@ -874,7 +904,7 @@ __global__ void k_heads(const uint32_t *mk, const int32_t *nmov, int32_t *headpo
 
 __global__ void k_admit(const uint32_t *mk, const int32_t *mv, const int32_t *nmov, const int32_t *headpos,
                         const int64_t *S, const int64_t *W, int64_t U, const int64_t *capv, int32_t *labels,
-                        int32_t *oldlab, LPDev *dev, const int32_t *group, GroupState *gs) {
+                        uint8_t *lab8, int32_t *oldlab, LPDev *dev, const int32_t *group, GroupState *gs) {
     const int32_t n = *nmov;
     int32_t cnt = 0;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
@@ -886,6 +916,7 @@ __global__ void k_admit(const uint32_t *mk, const int32_t *mv, const int32_t *nm
             const int32_t v = mv[p];
             oldlab[p] = labels[v];
             labels[v] = t;
+            if (lab8) lab8[v] = (uint8_t)t;
             cnt++;
             if (group) atomicAdd(&gs[group[v]].moves, 1);
         } else {
@@ -1161,11 +1192,12 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
     const int32_t *verts = tval;
     const bool dense_mode = nlabels <= kDenseLabels;
     // Algorithmic bytes of one proposal pass over tier t: per edge the
-    // neighbour id, its weight (when present) and its label; per vertex the
+    // neighbour id, its weight (when present) and its label (one byte with
+    // dense tables); per vertex the
     // tier-list entry, the two row offsets, the own label, the proposal
     // write, the vertex weight (when present) and, for hashed tables, the
     // weight of the chosen label.
-    const double per_edge = 4.0 + (g.adjwgt ? 4.0 : 0.0) + 4.0;
+    const double per_edge = 4.0 + (g.adjwgt ? 4.0 : 0.0) + (dense_mode ? 1.0 : 4.0);
     const double per_vertex = 4.0 + 8.0 + 4.0 + 4.0 + (g.vwgt ? 4.0 : 0.0) + (dense_mode ? 0.0 : 8.0);
     double tbytes[kTiers + 1];
     for (int t = 0; t < kTiers; t++) tbytes[t] = (double)hedge[t] * per_edge + (double)hcnt[t] * per_vertex;
@@ -1279,6 +1311,16 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
         db = DenseBig{big, owner, first, gconn, own, nbig, chunk};
     }
 
+    // ---- dense mode: byte copy of the labels (block ids < 256) for the
+    // neighbour gathers, a quarter of the int32 footprint in L2; labels that
+    // take no part (-1) belong to vertices without neighbours, never gathered
+    uint8_t *lab8 = nullptr;
+    if (dense) {
+        GP_TRY(sc.alloc(&lab8, n));
+        hipLaunchKernelGGL(k_labels_u8, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, labels, n, lab8);
+        GP_LAUNCH_CHECK();
+    }
+
     // ---- per-round buffers
     int32_t *prop = nullptr, *mv = nullptr, *mv2 = nullptr, *nmov = nullptr, *headpos = nullptr,
             *oldlab = nullptr;
@@ -1329,6 +1371,7 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
         a.done = &dev->done;
         a.round = &dev->round;
         a.capv = capv;
+        a.lab8 = lab8;
         if (dense && wide)
             RT_TRY(launch_dense_any<int64_t>(a, nlabels, verts, tstart, &db, dchunks, s, tbytes));
         else if (dense)
@@ -1339,7 +1382,7 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
             RT_TRY(launch_proposals<int32_t>(a, verts, tstart, hub_log, hub_off, gkey, (int32_t *)gval, s, tbytes,
                                              split_hubs));
         if (split_hubs) {
-            GP_PROF_LAUNCH("k_hub_insert", tbytes[8], s, hipLaunchKernelGGL(k_hub_insert, dim3(nchunks), dim3(256), 0, s, a, hp));
+            GP_PROF_LAUNCH("k_hub_insert", tbytes[8], s, hipLaunchKernelGGL(k_hub_insert, dim3(nchunks), dim3(kHubBlock), 0, s, a, hp));
             hipLaunchKernelGGL(k_hub_scan<false>, dim3(nslices), dim3(256), 0, s, a, hp);
             hipLaunchKernelGGL(k_hub_decide<false>, dim3(grid_for(nh, 256, 1024)), dim3(256), 0, s, a, hp, nh);
             hipLaunchKernelGGL(k_hub_scan<true>, dim3(nslices), dim3(256), 0, s, a, hp);
@@ -1355,7 +1398,7 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
         hipLaunchKernelGGL(k_heads, dim3(gb), dim3(256), 0, s, k1, nmov, headpos);
         GP_LAUNCH_CHECK();
         RT_TRY((scan<int64_t>(MoverWeight{v1, g.vwgt}, StoreIncl{S}, n, nmov, (int64_t *)nullptr, sc)));
-        hipLaunchKernelGGL(k_admit, dim3(gb), dim3(256), 0, s, k1, v1, nmov, headpos, S, W, U, capv, labels, oldlab,
+        hipLaunchKernelGGL(k_admit, dim3(gb), dim3(256), 0, s, k1, v1, nmov, headpos, S, W, U, capv, labels, lab8, oldlab,
                            dev, group, gstate);
         GP_LAUNCH_CHECK();
         if (nlabels <= kSmallLabels)
