@@ -459,12 +459,23 @@ __global__ __launch_bounds__(kHubBlock) void k_hub_insert(LPArgs a, HubPlan hp) 
     int32_t *key = hp.key + hp.toff[h];
     int32_t *val = hp.val + hp.toff[h];
     int32_t oc = 0;
-    for (int32_t e = beg + threadIdx.x; e < end; e += kHubBlock) {
-        const int32_t u = a.adjncy[e];
-        const int32_t wgt = a.adjwgt ? a.adjwgt[e] : 1;
-        const int32_t L = a.labels[u];
-        if (L == own) oc += wgt;
-        else if (dir_ok(L, own, dmode)) tbl_insert<int32_t>(skey, sval, kHubLds - 1, kHubLdsLog, L, wgt);
+    constexpr int UH = 1;
+    for (int32_t e0 = beg + threadIdx.x; e0 < end; e0 += UH * kHubBlock) {
+        int32_t u[UH], L[UH], wv[UH];
+#pragma unroll
+        for (int j = 0; j < UH; j++) {
+            const int32_t e = e0 + j * kHubBlock;
+            u[j] = e < end ? a.adjncy[e] : -1;
+            wv[j] = (e < end && a.adjwgt) ? a.adjwgt[e] : 1;
+        }
+#pragma unroll
+        for (int j = 0; j < UH; j++) L[j] = u[j] >= 0 ? a.labels[u[j]] : -1;
+#pragma unroll
+        for (int j = 0; j < UH; j++) {
+            if (u[j] < 0) continue;
+            if (L[j] == own) oc += wv[j];
+            else if (dir_ok(L[j], own, dmode)) tbl_insert<int32_t>(skey, sval, kHubLds - 1, kHubLdsLog, L[j], wv[j]);
+        }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < kHubLds; i += kHubBlock) {
@@ -679,19 +690,20 @@ __global__ __launch_bounds__(256) void k_dense_chunk(LPArgs a, DenseBig db) {
     const int32_t beg = a.xadj[v] + (blockIdx.x - db.chunk_first[b]) * db.chunk;
     const int32_t end = min(a.xadj[v + 1], beg + db.chunk);
     AccT oc = 0;
-    for (int32_t e0 = beg + threadIdx.x; e0 < end; e0 += 4 * 256) {
-        int32_t u[4], L[4];
-        AccT wv[4];
+    constexpr int UC = 4;
+    for (int32_t e0 = beg + threadIdx.x; e0 < end; e0 += UC * 256) {
+        int32_t u[UC], L[UC];
+        AccT wv[UC];
 #pragma unroll
-        for (int j = 0; j < 4; j++) {
+        for (int j = 0; j < UC; j++) {
             const int32_t e = e0 + j * 256;
             u[j] = e < end ? a.adjncy[e] : -1;
             wv[j] = (e < end && a.adjwgt) ? (AccT)a.adjwgt[e] : (AccT)1;
         }
 #pragma unroll
-        for (int j = 0; j < 4; j++) L[j] = u[j] >= 0 ? (int32_t)a.lab8[u[j]] : -1;
+        for (int j = 0; j < UC; j++) L[j] = u[j] >= 0 ? (int32_t)a.lab8[u[j]] : -1;
 #pragma unroll
-        for (int j = 0; j < 4; j++) {
+        for (int j = 0; j < UC; j++) {
             if (u[j] < 0) continue;
             if (L[j] == own) oc += wv[j];
             else if (dir_ok(L[j], own, dmode)) lds_add<AccT>(&val[w][L[j]], wv[j]);
