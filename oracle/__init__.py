@@ -244,7 +244,7 @@ def fill_isolated(g, k, part, B):
 
 DEFAULT_PARAMS = dict(rounds_coarsen=10, rounds_refine=25, coarsest_per_k=60, attempts=4,
                       stall_num=19, stall_den=20, dir_alternate=1, seed=0, init_mode=0,
-                      mpnn_max_n=65536, mpnn_seed=0, mpnn_params=None)
+                      mpnn_max_n=131072, mpnn_seed=0, mpnn_params=None)
 
 
 def _params(params):

@@ -47,12 +47,23 @@ def _cut_numpy(g, part):
 
 
 def test_rmat22_cluster_rounds_full(rmat22):
+    # ten rounds: hub tables are built once and then follow the moves
     g, dg = rmat22
     U = _ucl(g, 16)
-    lab, st = gp.lp_cluster(dg, U, 2)
-    olab, ost = oracle.lp_cluster(g, U, 2)
+    lab, st = gp.lp_cluster(dg, U, 10)
+    olab, ost = oracle.lp_cluster(g, U, 10)
     assert np.array_equal(lab.cpu().numpy(), olab)
-    assert st["moves"] == ost["moves"]
+    assert st["moves"] == ost["moves"] and st["rounds_run"] == ost["rounds_run"]
+
+
+@pytest.mark.parametrize("scale,U,dirs", [(18, 300, 1), (18, 40, 0), (17, 5000, 1)])
+def test_rmat_hub_rounds(scale, U, dirs):
+    # many hubs, many rounds, small and large cluster bounds, both direction rules
+    g = graphgen.rmat(scale, scale + 3)
+    lab, st = gp.lp_cluster(gp.to_device(g), U, 25, dirs)
+    olab, ost = oracle.lp_cluster(g, U, 25, dirs)
+    assert np.array_equal(lab.cpu().numpy(), olab)
+    assert st["rounds_run"] == ost["rounds_run"]
 
 
 def test_rmat22_contract_full(rmat22):
