@@ -238,15 +238,19 @@ __global__ __launch_bounds__(256) void k_crow_wave(RowCtx c, const int32_t *rows
     }
 }
 
-__global__ __launch_bounds__(256) void k_crow_block(RowCtx c, const int32_t *rows, int32_t count) {
+// One workgroup per row. 80 KB of LDS fits two workgroups per CU, so the
+// workgroup is wide (kCB threads) to keep enough waves in flight for the
+// gathers.
+constexpr int kCB = 512;
+__global__ __launch_bounds__(kCB) void k_crow_block(RowCtx c, const int32_t *rows, int32_t count) {
     constexpr int CAP = 2 * kRowBlockMax;
     __shared__ int32_t skey[CAP];
     __shared__ long long sval[CAP];
     __shared__ int32_t sF[kRowBlockMax + 1];
     __shared__ int32_t lj[kRowBlockMax];
     __shared__ long long lw[kRowBlockMax];
-    __shared__ int32_t t32[256 / kWave + 1];
-    for (int q = threadIdx.x; q < CAP; q += 256) {
+    __shared__ int32_t t32[kCB / kWave + 1];
+    for (int q = threadIdx.x; q < CAP; q += kCB) {
         skey[q] = -1;
         sval[q] = 0;
     }
@@ -255,13 +259,13 @@ __global__ __launch_bounds__(256) void k_crow_block(RowCtx c, const int32_t *row
         const int32_t i = rows[idx];
         const int32_t m0 = c.mstart[i], m1 = c.mstart[i + 1];
         const int32_t base = c.flat[m0], D = c.flat[m1] - base, M = m1 - m0;
-        for (int q = threadIdx.x; q <= M; q += 256) sF[q] = c.flat[m0 + q] - base;
+        for (int q = threadIdx.x; q <= M; q += kCB) sF[q] = c.flat[m0 + q] - base;
         __syncthreads();
         int lg = 1;
         while ((1 << lg) < 2 * D) lg++;
         const uint32_t cap = 1u << lg;
         int32_t p = 0;
-        for (int32_t t = threadIdx.x; t < D; t += 256) {
+        for (int32_t t = threadIdx.x; t < D; t += kCB) {
             p = upper_pos(sF, p, M - 1, t);  // t grows per thread: search from the last member
             const int32_t v = c.members[m0 + p];
             const int32_t e = c.xadj[v] + (t - sF[p]);
@@ -270,11 +274,11 @@ __global__ __launch_bounds__(256) void k_crow_block(RowCtx c, const int32_t *row
         }
         __syncthreads();
         int32_t r = 0;
-        for (uint32_t s0 = 0; s0 < cap; s0 += 256) {
+        for (uint32_t s0 = 0; s0 < cap; s0 += kCB) {
             const uint32_t sl = s0 + threadIdx.x;
             const bool occ = sl < cap && skey[sl] >= 0;
             int32_t tot;
-            const int32_t ex = block_excl_scan<256>((int32_t)occ, t32, &tot);
+            const int32_t ex = block_excl_scan<kCB>((int32_t)occ, t32, &tot);
             if (occ) {
                 lj[r + ex] = skey[sl];
                 lw[r + ex] = sval[sl];
@@ -283,12 +287,12 @@ __global__ __launch_bounds__(256) void k_crow_block(RowCtx c, const int32_t *row
         }
         int32_t P = 1;
         while (P < r) P <<= 1;
-        for (int32_t q = r + threadIdx.x; q < P; q += 256) lj[q] = INT_MAX;
+        for (int32_t q = r + threadIdx.x; q < P; q += kCB) lj[q] = INT_MAX;
         __syncthreads();
         // bitonic sort of lj/lw[0, P) by column
         for (int32_t kk = 2; kk <= P; kk <<= 1) {
             for (int32_t jj = kk >> 1; jj > 0; jj >>= 1) {
-                for (int32_t q = threadIdx.x; q < P; q += 256) {
+                for (int32_t q = threadIdx.x; q < P; q += kCB) {
                     const int32_t o = q ^ jj;
                     if (o > q) {
                         const bool up = (q & kk) == 0;
@@ -305,12 +309,12 @@ __global__ __launch_bounds__(256) void k_crow_block(RowCtx c, const int32_t *row
                 __syncthreads();
             }
         }
-        for (int32_t q = threadIdx.x; q < r; q += 256) {
+        for (int32_t q = threadIdx.x; q < r; q += kCB) {
             c.tj[base + q] = lj[q];
             c.tw[base + q] = lw[q];
         }
         if (threadIdx.x == 0) c.rcnt[i] = r;
-        for (uint32_t q = threadIdx.x; q < cap; q += 256) {
+        for (uint32_t q = threadIdx.x; q < cap; q += kCB) {
             skey[q] = -1;
             sval[q] = 0;
         }
@@ -333,14 +337,14 @@ struct BigRows {
     int jbits;
 };
 
-__global__ __launch_bounds__(256) void k_cbig_chunk(RowCtx c, BigRows b) {
+__global__ __launch_bounds__(kCB) void k_cbig_chunk(RowCtx c, BigRows b) {
     constexpr int CAP = 2 * kRowChunk;
     __shared__ int32_t skey[CAP];
     __shared__ long long sval[CAP];
     __shared__ int32_t rng[2];
-    __shared__ int32_t t32[256 / kWave + 1];
+    __shared__ int32_t t32[kCB / kWave + 1];
     __shared__ int32_t resv;
-    for (int q = threadIdx.x; q < CAP; q += 256) {
+    for (int q = threadIdx.x; q < CAP; q += kCB) {
         skey[q] = -1;
         sval[q] = 0;
     }
@@ -357,7 +361,7 @@ __global__ __launch_bounds__(256) void k_cbig_chunk(RowCtx c, BigRows b) {
     __syncthreads();
     const int32_t plo = rng[0], phi = rng[1];
     int32_t p = plo;
-    for (int32_t t = t0 + threadIdx.x; t < t1; t += 256) {
+    for (int32_t t = t0 + threadIdx.x; t < t1; t += kCB) {
         p = upper_pos(c.flat, p, phi, base + t);  // t grows per thread: search from the last member
         const int32_t v = c.members[p];
         const int32_t e = c.xadj[v] + (base + t - c.flat[p]);
@@ -366,16 +370,16 @@ __global__ __launch_bounds__(256) void k_cbig_chunk(RowCtx c, BigRows b) {
     }
     __syncthreads();
     int32_t cnt = 0;
-    for (int q = threadIdx.x; q < CAP; q += 256) cnt += skey[q] >= 0;
-    cnt = block_sum<256>(cnt, t32);
+    for (int q = threadIdx.x; q < CAP; q += kCB) cnt += skey[q] >= 0;
+    cnt = block_sum<kCB>(cnt, t32);
     if (threadIdx.x == 0) resv = cnt ? atomicAdd(b.cursor, cnt) : 0;
     __syncthreads();
     int32_t r = resv;
-    for (int q0 = 0; q0 < CAP; q0 += 256) {
+    for (int q0 = 0; q0 < CAP; q0 += kCB) {
         const int q = q0 + threadIdx.x;
         const bool occ = skey[q] >= 0;
         int32_t tot;
-        const int32_t ex = block_excl_scan<256>((int32_t)occ, t32, &tot);
+        const int32_t ex = block_excl_scan<kCB>((int32_t)occ, t32, &tot);
         if (occ) {
             b.key[r + ex] = ((uint64_t)(uint32_t)g << b.jbits) | (uint64_t)(uint32_t)skey[q];
             b.val[r + ex] = sval[q];
@@ -630,7 +634,7 @@ int contract(const DevGraph &g, const int32_t *labels, bool skip_isolated, Coars
             GP_LAUNCH_CHECK();
         }
         if (hc[1] > 0) {
-            hipLaunchKernelGGL(k_crow_block, dim3(grid_for(hc[1], 1, 8192)), dim3(256), 0, s, c, rows_b, hc[1]);
+            hipLaunchKernelGGL(k_crow_block, dim3(grid_for(hc[1], 1, 8192)), dim3(kCB), 0, s, c, rows_b, hc[1]);
             GP_LAUNCH_CHECK();
         }
         const int32_t nb = hc[2];
@@ -667,7 +671,7 @@ int contract(const DevGraph &g, const int32_t *labels, bool skip_isolated, Coars
                                    cown);
                 GP_LAUNCH_CHECK();
                 BigRows br{rows_g, cown, cfirst, bk, bv, cursor, jbits};
-                hipLaunchKernelGGL(k_cbig_chunk, dim3(nchunks), dim3(256), 0, s, c, br);
+                hipLaunchKernelGGL(k_cbig_chunk, dim3(nchunks), dim3(kCB), 0, s, c, br);
                 GP_LAUNCH_CHECK();
                 GP_HIP(hipMemcpyAsync(&m, cursor, sizeof(int32_t), hipMemcpyDeviceToHost, s));
                 GP_HIP(hipStreamSynchronize(s));
