@@ -332,9 +332,10 @@ struct BigRows {
     const int32_t *chunk_owner;  // [nchunks] row rank of each chunk
     const int32_t *chunk_first;  // [nb] first chunk of each row
     uint64_t *key;               // [cap] (row rank << jbits) | column
-    long long *val;              // [cap]
+    int32_t *val;                // [cap] a chunk's partial sum (a coarse weight must fit int32 anyway)
     int32_t *cursor;             // [1] append position
     int jbits;
+    int32_t *ovf;                // set when a partial sum exceeds int32
 };
 
 __global__ __launch_bounds__(kCB) void k_cbig_chunk(RowCtx c, BigRows b) {
@@ -382,7 +383,9 @@ __global__ __launch_bounds__(kCB) void k_cbig_chunk(RowCtx c, BigRows b) {
         const int32_t ex = block_excl_scan<kCB>((int32_t)occ, t32, &tot);
         if (occ) {
             b.key[r + ex] = ((uint64_t)(uint32_t)g << b.jbits) | (uint64_t)(uint32_t)skey[q];
-            b.val[r + ex] = sval[q];
+            const long long w = sval[q];
+            if (w > INT_MAX) atomicOr(b.ovf, 1);  // the row's total would overflow too
+            b.val[r + ex] = (int32_t)(w > INT_MAX ? INT_MAX : w);
         }
         r += tot;
     }
@@ -397,8 +400,8 @@ struct PairHeadEmit {
     __device__ void operator()(int64_t p, int32_t r) const { head[r] = (int32_t)p; }
 };
 struct ValIn64 {
-    const long long *v;
-    __device__ long long operator()(int64_t p) const { return v[p]; }
+    const int32_t *v;
+    __device__ long long operator()(int64_t p) const { return (long long)v[p]; }
 };
 struct InclOut64 {
     long long *S;
@@ -655,7 +658,8 @@ int contract(const DevGraph &g, const int32_t *labels, bool skip_isolated, Coars
             GP_HIP(hipStreamSynchronize(s));
             const int64_t bcap = (int64_t)nchunks * kRowChunk;
             uint64_t *bk = nullptr, *bk2 = nullptr;
-            long long *bv = nullptr, *bv2 = nullptr, *S = nullptr;
+            int32_t *bv = nullptr, *bv2 = nullptr;
+            long long *S = nullptr;
             GP_TRY(sc.alloc(&bk, bcap));
             GP_TRY(sc.alloc(&bk2, bcap));
             GP_TRY(sc.alloc(&bv, bcap));
@@ -670,14 +674,14 @@ int contract(const DevGraph &g, const int32_t *labels, bool skip_isolated, Coars
                 hipLaunchKernelGGL(k_expand_owner, dim3(grid_for(nb, 256, 1024)), dim3(256), 0, s, cfirst, nch, nb,
                                    cown);
                 GP_LAUNCH_CHECK();
-                BigRows br{rows_g, cown, cfirst, bk, bv, cursor, jbits};
+                BigRows br{rows_g, cown, cfirst, bk, bv, cursor, jbits, flags};
                 hipLaunchKernelGGL(k_cbig_chunk, dim3(nchunks), dim3(kCB), 0, s, c, br);
                 GP_LAUNCH_CHECK();
                 GP_HIP(hipMemcpyAsync(&m, cursor, sizeof(int32_t), hipMemcpyDeviceToHost, s));
                 GP_HIP(hipStreamSynchronize(s));
             }
             if (m > 0) {
-                GP_TRY((radix_sort<uint64_t, long long>(&bk, &bv, &bk2, &bv2, m, nullptr, jbits + gbits, sc)));
+                GP_TRY((radix_sort<uint64_t, int32_t>(&bk, &bv, &bk2, &bv2, m, nullptr, jbits + gbits, sc)));
                 GP_TRY(sc.alloc(&S, m));
                 GP_TRY(sc.alloc(&head, m));
                 GP_TRY((scan<long long>(ValIn64{bv}, InclOut64{S}, m, nullptr, (long long *)nullptr, sc)));
@@ -686,7 +690,7 @@ int contract(const DevGraph &g, const int32_t *labels, bool skip_isolated, Coars
             hipLaunchKernelGGL(k_cbig_rowoff, dim3(grid_for((int64_t)m + 1, 256, 65536)), dim3(256), 0, s, bk, head,
                                d_runs, jbits, nb, roff);
             GP_LAUNCH_CHECK();
-            BigRows br{rows_g, cown, cfirst, bk, bv, cursor, jbits};
+            BigRows br{rows_g, cown, cfirst, bk, bv, cursor, jbits, flags};
             hipLaunchKernelGGL(k_cbig_place, dim3(grid_for((int64_t)m + nb, 256, 65536)), dim3(256), 0, s, c, br,
                                head, d_runs, m, S, roff, nb);
             GP_LAUNCH_CHECK();
