@@ -282,3 +282,40 @@ def test_tuning_rejects_values_beyond_table_capacity():
     with pytest.raises(gp.GPError):
         gp.set_tuning({"tier_max": [64, 256, 2048, 8192], "dense_split": 256, "dense_chunk": 1000})
     assert gp.get_tuning()["tier_max"] == [64, 256, 2048, 8192]
+
+
+def _heavy(g, scale, seed):
+    """Same graph with edge weights large enough that sums need 64 bits."""
+    rng = np.random.default_rng(seed)
+    h = dict(g)
+    n = len(g["xadj"]) - 1
+    rows = np.repeat(np.arange(n), np.diff(g["xadj"]))
+    lo, hi = np.minimum(rows, g["adjncy"]), np.maximum(rows, g["adjncy"])
+    # symmetric weights from the undirected edge's ends
+    w = (((lo.astype(np.int64) * 1000003 + hi) * 2654435761) % scale) + scale // 2
+    h["adjwgt"] = w.astype(np.int32)
+    assert int(h["adjwgt"].astype(np.int64).sum()) >= 2 ** 31
+    return h
+
+
+@pytest.mark.parametrize("case", ["rmat13", "star", "grid"])
+def test_lp_with_64bit_sums(case):
+    if case == "rmat13":
+        g = _heavy(graphgen.rmat(13, 3), 1 << 22, 1)
+    elif case == "star":
+        g = _heavy(_star(20000, extra=[(1, 2), (3, 4)]), 1 << 20, 2)
+    else:
+        g = _heavy(graphgen.grid3d(16, 15, 14, seed=1, wmax=0), 1 << 24, 3)
+    dg = gp.to_device(g)
+    for U in (5, 400):
+        lab, st = gp.lp_cluster(dg, U, 10)
+        olab, ost = oracle.lp_cluster(g, U, 10)
+        assert np.array_equal(_np(lab), olab), U
+        assert st["moves"] == ost["moves"]
+    n = len(g["xadj"]) - 1
+    for k in (16, 300):
+        part = (np.arange(n) * 7919 % k).astype(np.int32)
+        lm = oracle.lmax(n, k, 0.03)
+        p, _ = gp.lp_refine(dg, torch.from_numpy(part).cuda(), k, lm, 10)
+        op, _ = oracle.lp_refine(g, part, k, lm, 10)
+        assert np.array_equal(_np(p), op), k
