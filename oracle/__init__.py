@@ -38,7 +38,8 @@ class _Params(ctypes.Structure):
                 ("stall_num", ctypes.c_int32), ("stall_den", ctypes.c_int32),
                 ("dir_alternate", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("init_mode", ctypes.c_int32), ("mpnn_max_n", ctypes.c_int32),
-                ("mpnn_seed", ctypes.c_uint64), ("mpnn_params", ctypes.POINTER(ctypes.c_float))]
+                ("mpnn_seed", ctypes.c_uint64), ("mpnn_params", ctypes.POINTER(ctypes.c_float)),
+                ("lp_async", ctypes.c_int32)]
 
 
 class _Result(ctypes.Structure):
@@ -94,6 +95,9 @@ def _load():
     lib.orc_fill_isolated.argtypes = [G, ctypes.c_int32, I32P, I64P]
     lib.orc_partition.argtypes = [G, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(_Params),
                                   I32P, ctypes.POINTER(_Result)]
+    lib.orc_lp_cluster_async.argtypes = [G, ctypes.c_int64, ctypes.c_int32, I32P, ctypes.POINTER(_LPStats)]
+    lib.orc_lp_refine_async.argtypes = [G, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, I32P,
+                                        ctypes.POINTER(_LPStats)]
     lib.orc_coarsest.argtypes = [G, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(_Params),
                                  I32P, I32P, I32P, I32P, I32P, I32P, I32P]
     F32P = ctypes.POINTER(ctypes.c_float)
@@ -165,6 +169,23 @@ def lp_refine(g, part, k, lmax_, rounds=25, dir_alternate=1):
     P = _i32(part).copy()
     st = _LPStats()
     _load().orc_lp_refine(G.ref, k, lmax_, rounds, dir_alternate, _p32(P), ctypes.byref(st))
+    return P, {"rounds_run": st.rounds_run, "moves": st.moves, "edge_visits": st.edge_visits}
+
+
+def lp_cluster_async(g, U, rounds=10):
+    """The paper's sequential LP clustering (oracle-only comparison mode)."""
+    G = _G(g)
+    out = np.zeros(G.n, dtype=np.int32)
+    st = _LPStats()
+    _load().orc_lp_cluster_async(G.ref, U, rounds, _p32(out), ctypes.byref(st))
+    return out, {"rounds_run": st.rounds_run, "moves": st.moves, "edge_visits": st.edge_visits}
+
+
+def lp_refine_async(g, part, k, lmax_, rounds=25):
+    G = _G(g)
+    P = _i32(part).copy()
+    st = _LPStats()
+    _load().orc_lp_refine_async(G.ref, k, lmax_, rounds, _p32(P), ctypes.byref(st))
     return P, {"rounds_run": st.rounds_run, "moves": st.moves, "edge_visits": st.edge_visits}
 
 
@@ -244,7 +265,7 @@ def fill_isolated(g, k, part, B):
 
 DEFAULT_PARAMS = dict(rounds_coarsen=10, rounds_refine=25, coarsest_per_k=60, attempts=4,
                       stall_num=19, stall_den=20, dir_alternate=1, seed=0, init_mode=0,
-                      mpnn_max_n=131072, mpnn_seed=0, mpnn_params=None)
+                      mpnn_max_n=131072, mpnn_seed=0, mpnn_params=None, lp_async=0)
 
 
 def _params(params):

@@ -162,6 +162,113 @@ int orc_lp_refine(const orc_graph *g, int32_t k, int64_t lmax, int32_t rounds,
 }
 
 /*
+ * §III-A sequential size-constrained LP in the paper's own form (oracle-only,
+ * to measure what the round-synchronous reading costs in quality):
+ *  - all vertices start in queue Q in increasing order of degree (ties: id);
+ *  - visiting v moves it at once to the eligible cluster (W[L] + c(v) <= U)
+ *    with the strongest connection; its own cluster competes and wins ties,
+ *    other ties go to the smallest label (the paper leaves ties open);
+ *  - when v changes cluster, every neighbour not yet queued for the next
+ *    iteration is appended to Q' (in the order they are met);
+ *  - Q and Q' swap after each iteration; stop after `rounds` iterations or
+ *    when Q is empty.
+ * C and W are updated in place.
+ */
+static void lp_async(const orc_graph *g, int32_t *C, int64_t *W, int32_t nlabels, int64_t U, int32_t rounds,
+                     orc_lp_stats *st) {
+    int32_t n = g->n;
+    int32_t *Q = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
+    int32_t *Q2 = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
+    uint8_t *queued = (uint8_t *)xcalloc((size_t)n, 1);
+    int64_t *conn = (int64_t *)xcalloc((size_t)nlabels, sizeof(int64_t));
+    int32_t *touched = (int32_t *)xcalloc((size_t)(n > 0 ? n : 1), sizeof(int32_t));
+    /* counting sort by degree keeps ascending ids inside a degree */
+    int32_t dmax = 0;
+    for (int32_t v = 0; v < n; v++) if (g->xadj[v + 1] - g->xadj[v] > dmax) dmax = g->xadj[v + 1] - g->xadj[v];
+    int32_t *cnt = (int32_t *)xcalloc((size_t)dmax + 2, sizeof(int32_t));
+    for (int32_t v = 0; v < n; v++) cnt[g->xadj[v + 1] - g->xadj[v] + 1]++;
+    for (int32_t d = 0; d <= dmax; d++) cnt[d + 1] += cnt[d];
+    for (int32_t v = 0; v < n; v++) Q[cnt[g->xadj[v + 1] - g->xadj[v]]++] = v;
+    free(cnt);
+    int32_t qn = n, it = 0;
+    int64_t moves = 0, visits = 0;
+    for (; it < rounds && qn > 0; it++) {
+        int32_t q2n = 0;
+        for (int32_t qi = 0; qi < qn; qi++) {
+            const int32_t v = Q[qi];
+            if (C[v] < 0) continue; /* takes no part */
+            const int32_t own = C[v];
+            const int64_t cv = VW(g, v);
+            int32_t nt = 0;
+            for (int32_t e = g->xadj[v]; e < g->xadj[v + 1]; e++) {
+                const int32_t L = C[g->adjncy[e]];
+                if (L < 0) continue;
+                if (conn[L] == 0) touched[nt++] = L;
+                conn[L] += EW(g, e);
+            }
+            visits += g->xadj[v + 1] - g->xadj[v];
+            int32_t best = own;
+            int64_t bc = conn[own];
+            for (int32_t i = 0; i < nt; i++) {
+                const int32_t L = touched[i];
+                if (L == own || W[L] + cv > U) continue;
+                if (conn[L] > bc || (conn[L] == bc && best != own && L < best)) {
+                    best = L;
+                    bc = conn[L];
+                }
+            }
+            for (int32_t i = 0; i < nt; i++) conn[touched[i]] = 0;
+            if (best != own) {
+                C[v] = best;
+                W[own] -= cv;
+                W[best] += cv;
+                moves++;
+                for (int32_t e = g->xadj[v]; e < g->xadj[v + 1]; e++) {
+                    const int32_t u = g->adjncy[e];
+                    if (!queued[u]) {
+                        queued[u] = 1;
+                        Q2[q2n++] = u;
+                    }
+                }
+            }
+        }
+        for (int32_t i = 0; i < q2n; i++) queued[Q2[i]] = 0;
+        int32_t *t = Q;
+        Q = Q2;
+        Q2 = t;
+        qn = q2n;
+    }
+    if (st) {
+        st->rounds_run = it;
+        st->moves = moves;
+        st->edge_visits = visits;
+    }
+    free(Q);
+    free(Q2);
+    free(queued);
+    free(conn);
+    free(touched);
+}
+
+int orc_lp_cluster_async(const orc_graph *g, int64_t U, int32_t rounds, int32_t *labels_out, orc_lp_stats *st) {
+    int32_t n = g->n;
+    int64_t *W = (int64_t *)xcalloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+    for (int32_t v = 0; v < n; v++) { labels_out[v] = v; W[v] = VW(g, v); }
+    lp_async(g, labels_out, W, n, U, rounds, st);
+    free(W);
+    return 0;
+}
+
+int orc_lp_refine_async(const orc_graph *g, int32_t k, int64_t lmax, int32_t rounds, int32_t *part,
+                        orc_lp_stats *st) {
+    int64_t *W = (int64_t *)xcalloc((size_t)k, sizeof(int64_t));
+    for (int32_t v = 0; v < g->n; v++) if (part[v] >= 0) W[part[v]] += VW(g, v);
+    lp_async(g, part, W, k, lmax, rounds, st);
+    free(W);
+    return 0;
+}
+
+/*
  * §III-A / §IV-A contraction. Coarse ids: prefix sum over "label is used"
  * indicators, so coarse id = rank of the label among the used labels.
  * c'(i) = sum of c over cluster i; w'(i,j) = sum of w over fine edges between
@@ -502,7 +609,8 @@ static void coarsen(const orc_graph *g, int32_t k, double eps, const orc_params 
         int32_t fn = f->g.n, fnnz = f->g.xadj[fn];
         int32_t *labels = (int32_t *)xcalloc((size_t)fn, sizeof(int32_t));
         orc_lp_stats st;
-        orc_lp_cluster(&f->g, ucl, p->rounds_coarsen, p->dir_alternate, labels, &st);
+        if (p->lp_async) orc_lp_cluster_async(&f->g, ucl, p->rounds_coarsen, labels, &st);
+        else orc_lp_cluster(&f->g, ucl, p->rounds_coarsen, p->dir_alternate, labels, &st);
         ev_cluster += st.edge_visits;
         c->xadj = (int32_t *)xcalloc((size_t)fn + 1, sizeof(int32_t));
         c->adjncy = (int32_t *)xcalloc((size_t)fnnz, sizeof(int32_t));
@@ -634,7 +742,8 @@ int orc_partition(const orc_graph *g, int32_t k, double eps, const orc_params *p
             P = Pf;
         }
         orc_lp_stats st;
-        orc_lp_refine(&lev[l].g, k, lmax, p->rounds_refine, p->dir_alternate, P, &st);
+        if (p->lp_async) orc_lp_refine_async(&lev[l].g, k, lmax, p->rounds_refine, P, &st);
+        else orc_lp_refine(&lev[l].g, k, lmax, p->rounds_refine, p->dir_alternate, P, &st);
         ev_refine += st.edge_visits;
     }
 

@@ -50,6 +50,7 @@ typedef struct {
     int32_t mpnn_max_n;       /* learned proposal only when the coarsest graph has <= this many vertices */
     uint64_t mpnn_seed;       /* probe features */
     const float *mpnn_params; /* fp32 master weights (see orc_mpnn_param_count) */
+    int32_t lp_async;         /* 0; 1: the paper's sequential LP (oracle-only comparison mode) */
 } orc_params;
 
 typedef struct {
@@ -72,6 +73,12 @@ int orc_lp_cluster(const orc_graph *g, int64_t U, int32_t rounds, int32_t dir_al
                    int32_t *labels_out, orc_lp_stats *st);
 int orc_lp_refine(const orc_graph *g, int32_t k, int64_t lmax, int32_t rounds,
                   int32_t dir_alternate, int32_t *part_inout, orc_lp_stats *st);
+
+/* §III-A sequential LP as the paper states it (queue by increasing degree,
+ * in-place moves, neighbours of movers re-queued); an oracle-only mode. */
+int orc_lp_cluster_async(const orc_graph *g, int64_t U, int32_t rounds, int32_t *labels_out, orc_lp_stats *st);
+int orc_lp_refine_async(const orc_graph *g, int32_t k, int64_t lmax, int32_t rounds, int32_t *part,
+                        orc_lp_stats *st);
 
 /* Coarse graph into caller buffers sized for the fine graph (n+1, nnz, nnz, n, n). */
 int orc_contract(const orc_graph *g, const int32_t *labels, int32_t *xadj_c, int32_t *adjncy_c,
