@@ -243,6 +243,8 @@ def main():
     ap.add_argument("--workload", default="rmat22", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-rounds", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--attempts", type=int, default=4,
+                    help="initial bisection tries (the paper's configuration uses 4)")
     ap.add_argument("--no-tuning", action="store_true",
                     help="ignore paper_1710_08231_amd/tuning/<workload>.json (use the default thresholds)")
     ap.add_argument("--no-profile", action="store_true",
@@ -284,7 +286,7 @@ def main():
         if last_warm:
             gp.profile_select(None)
             gp.profile_enable(True)
-        _, res = gp.partition(dg, k, 0.03)
+        _, res = gp.partition(dg, k, 0.03, attempts=args.attempts)
         if last_warm:
             entries = gp.profile_entries()
             gp.profile_enable(False)
@@ -305,7 +307,7 @@ def main():
     t = time.perf_counter()
     for i in range(args.steps):
         ts = time.perf_counter()
-        part, res = gp.partition(dg, k, 0.03)
+        part, res = gp.partition(dg, k, 0.03, attempts=args.attempts)
         step_ms.append((time.perf_counter() - ts) * 1000.0)
         visits += res["edge_visits_cluster"] + res["edge_visits_refine"]
         results.append(res)
@@ -331,7 +333,8 @@ def main():
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": args.workload, "n": n, "nnz": nnz, "k": k, "eps": 0.03, "tuning": TUNING},
+        "config": {"workload": args.workload, "n": n, "nnz": nnz, "k": k, "eps": 0.03, "attempts": args.attempts,
+                   "tuning": TUNING},
         "partition_ms": ms,
         "cut": last["cut"],
         "balanced": bool(last["balanced"]),
