@@ -143,6 +143,7 @@ __global__ void k_halve(int64_t *x) { *x /= 2; }
 constexpr int kRowWaveMax = 128;    // D_i <= 128: one wave per row
 constexpr int kRowBlockMax = 2048;  // D_i <= 2048: one workgroup per row
 constexpr int kRowChunk = 2048;     // larger rows: flattened entries per aggregating workgroup
+static_assert(kRowWaveMax % kWave == 0, "wave rows: whole entries per lane");
 
 struct RowCtx {
     const int32_t *xadj, *adjncy, *adjwgt, *f2c;
@@ -177,6 +178,45 @@ __device__ __forceinline__ int32_t upper_pos(const int32_t *F, int32_t lo, int32
     return lo;
 }
 
+// Entries t = first, first + STRIDE, ... (< tend, at most UB of them) of a
+// row. F is the member degree prefix in LDS, relative to the row's first
+// entry, for the members members[mbase + p], p in [0, pmax]. Each entry's
+// chain of dependent loads (member, its row start, neighbour, neighbour's
+// coarse id) is issued as one batch over the UB entries, so a thread waits on
+// memory four times, not four times per entry; the columns other than the
+// row itself then go into the row's LDS hash table.
+template <int UB, int STRIDE>
+__device__ __forceinline__ void gather_insert(const RowCtx &c, const int32_t *F, int32_t mbase, int32_t pmax,
+                                              int32_t first, int32_t tend, int32_t i, int32_t *skey,
+                                              long long *sval, uint32_t mask, int lg) {
+    int32_t x[UB], off[UB], wt[UB];
+    int32_t p = 0;
+#pragma unroll
+    for (int q = 0; q < UB; q++) {
+        const int32_t t = first + q * STRIDE;
+        if (t < tend) {
+            p = upper_pos(F, p, pmax, t);  // t grows: search from the last member
+            x[q] = c.members[mbase + p];
+            off[q] = t - F[p];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < UB; q++)
+        if (first + q * STRIDE < tend) x[q] = c.xadj[x[q]] + off[q];  // entry index
+#pragma unroll
+    for (int q = 0; q < UB; q++)
+        if (first + q * STRIDE < tend) {
+            wt[q] = c.adjwgt ? c.adjwgt[x[q]] : 1;
+            x[q] = c.adjncy[x[q]];
+        }
+#pragma unroll
+    for (int q = 0; q < UB; q++)
+        if (first + q * STRIDE < tend) x[q] = c.f2c[x[q]];
+#pragma unroll
+    for (int q = 0; q < UB; q++)
+        if (first + q * STRIDE < tend && x[q] != i) col_insert(skey, sval, mask, lg, x[q], wt[q]);
+}
+
 __global__ __launch_bounds__(256) void k_crow_wave(RowCtx c, const int32_t *rows, int32_t count) {
     constexpr int NW = 4, CAP = 2 * kRowWaveMax;
     __shared__ int32_t skey[NW][CAP];
@@ -200,14 +240,7 @@ __global__ __launch_bounds__(256) void k_crow_wave(RowCtx c, const int32_t *rows
         int lg = 1;
         while ((1 << lg) < 2 * D) lg++;
         const uint32_t cap = 1u << lg;
-        int32_t p = 0;
-        for (int32_t t = lane; t < D; t += kWave) {
-            p = upper_pos(sF[w], p, M - 1, t);
-            const int32_t v = c.members[m0 + p];
-            const int32_t e = c.xadj[v] + (t - sF[w][p]);
-            const int32_t j = c.f2c[c.adjncy[e]];
-            if (j != i) col_insert(skey[w], sval[w], cap - 1, lg, j, c.adjwgt ? c.adjwgt[e] : 1);
-        }
+        gather_insert<kRowWaveMax / kWave, kWave>(c, sF[w], m0, M - 1, lane, D, i, skey[w], sval[w], cap - 1, lg);
         wave_sync();
         int32_t r = 0;
         for (uint32_t s0 = 0; s0 < cap; s0 += kWave) {
@@ -242,14 +275,24 @@ __global__ __launch_bounds__(256) void k_crow_wave(RowCtx c, const int32_t *rows
 // workgroup is wide (kCB threads) to keep enough waves in flight for the
 // gathers.
 constexpr int kCB = 512;
+constexpr int kRankMax = 1024;  // rows with at most this many distinct columns are sorted by counting ranks
+static_assert(kRankMax % kCB == 0, "rank sort: whole columns per thread");
+static_assert(kRowBlockMax % kCB == 0 && kRowChunk % kCB == 0, "block rows: whole entries per thread");
 __global__ __launch_bounds__(kCB) void k_crow_block(RowCtx c, const int32_t *rows, int32_t count) {
     constexpr int CAP = 2 * kRowBlockMax;
     __shared__ int32_t skey[CAP];
     __shared__ long long sval[CAP];
-    __shared__ int32_t sF[kRowBlockMax + 1];
-    __shared__ int32_t lj[kRowBlockMax];
-    __shared__ long long lw[kRowBlockMax];
-    __shared__ int32_t t32[kCB / kWave + 1];
+    // sF (member prefix) is only read while gathering and lj (the distinct
+    // columns) only written after that, so they share one array; li holds
+    // each column's table slot, whose weight is read at the output. This
+    // keeps the workgroup under 80 KB: two per CU.
+    __shared__ __align__(16) int32_t sFlj[kRowBlockMax + 4];
+    __shared__ uint16_t li[kRowBlockMax];
+    __shared__ int32_t s_r;
+    int32_t *const sF = sFlj, *const lj = sFlj;
+    static_assert(2 * kRowBlockMax <= 65536, "slot index fits 16 bits");
+    const int lane = lane_id();
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
     for (int q = threadIdx.x; q < CAP; q += kCB) {
         skey[q] = -1;
         sval[q] = 0;
@@ -260,60 +303,93 @@ __global__ __launch_bounds__(kCB) void k_crow_block(RowCtx c, const int32_t *row
         const int32_t m0 = c.mstart[i], m1 = c.mstart[i + 1];
         const int32_t base = c.flat[m0], D = c.flat[m1] - base, M = m1 - m0;
         for (int q = threadIdx.x; q <= M; q += kCB) sF[q] = c.flat[m0 + q] - base;
+        if (threadIdx.x == 0) s_r = 0;
         __syncthreads();
         int lg = 1;
         while ((1 << lg) < 2 * D) lg++;
         const uint32_t cap = 1u << lg;
-        int32_t p = 0;
-        for (int32_t t = threadIdx.x; t < D; t += kCB) {
-            p = upper_pos(sF, p, M - 1, t);  // t grows per thread: search from the last member
-            const int32_t v = c.members[m0 + p];
-            const int32_t e = c.xadj[v] + (t - sF[p]);
-            const int32_t j = c.f2c[c.adjncy[e]];
-            if (j != i) col_insert(skey, sval, cap - 1, lg, j, c.adjwgt ? c.adjwgt[e] : 1);
-        }
+        gather_insert<kRowBlockMax / kCB, kCB>(c, sF, m0, M - 1, threadIdx.x, D, i, skey, sval, cap - 1, lg);
         __syncthreads();
-        int32_t r = 0;
+        // compaction of the occupied slots, in any order (the columns are
+        // sorted next): one LDS reservation per wave
         for (uint32_t s0 = 0; s0 < cap; s0 += kCB) {
             const uint32_t sl = s0 + threadIdx.x;
             const bool occ = sl < cap && skey[sl] >= 0;
-            int32_t tot;
-            const int32_t ex = block_excl_scan<kCB>((int32_t)occ, t32, &tot);
+            const uint64_t m = __ballot(occ);
+            int32_t wb = 0;
+            if (lane == 0 && m) wb = atomicAdd(&s_r, (int32_t)__popcll(m));
+            wb = __shfl(wb, 0);
             if (occ) {
-                lj[r + ex] = skey[sl];
-                lw[r + ex] = sval[sl];
+                const int32_t pos = wb + (int32_t)__popcll(m & lt);
+                lj[pos] = skey[sl];
+                li[pos] = (uint16_t)sl;
             }
-            r += tot;
         }
-        int32_t P = 1;
-        while (P < r) P <<= 1;
-        for (int32_t q = r + threadIdx.x; q < P; q += kCB) lj[q] = INT_MAX;
         __syncthreads();
-        // bitonic sort of lj/lw[0, P) by column
-        for (int32_t kk = 2; kk <= P; kk <<= 1) {
-            for (int32_t jj = kk >> 1; jj > 0; jj >>= 1) {
-                for (int32_t q = threadIdx.x; q < P; q += kCB) {
-                    const int32_t o = q ^ jj;
-                    if (o > q) {
-                        const bool up = (q & kk) == 0;
-                        const int32_t a = lj[q], b = lj[o];
-                        if ((a > b) == up) {
-                            lj[q] = b;
-                            lj[o] = a;
-                            const long long x = lw[q];
-                            lw[q] = lw[o];
-                            lw[o] = x;
+        const int32_t r = s_r;
+        if (r <= kRankMax) {
+            // the columns are distinct: each one's rank is the number of
+            // smaller ones, counted over broadcast LDS reads (no barriers)
+            int32_t jv[kRankMax / kCB], rk[kRankMax / kCB];
+#pragma unroll
+            for (int q = 0; q < kRankMax / kCB; q++) {
+                jv[q] = threadIdx.x + q * kCB < r ? lj[threadIdx.x + q * kCB] : INT_MAX;
+                rk[q] = 0;
+            }
+            const int4 *l4 = reinterpret_cast<const int4 *>(lj);
+            int32_t x = 0;
+            for (; x + 4 <= r; x += 4) {
+                const int4 y = l4[x >> 2];
+#pragma unroll
+                for (int q = 0; q < kRankMax / kCB; q++)
+                    rk[q] += (int32_t)(y.x < jv[q]) + (int32_t)(y.y < jv[q]) + (int32_t)(y.z < jv[q]) +
+                             (int32_t)(y.w < jv[q]);
+            }
+            for (; x < r; x++) {
+                const int32_t y = lj[x];
+#pragma unroll
+                for (int q = 0; q < kRankMax / kCB; q++) rk[q] += (int32_t)(y < jv[q]);
+            }
+#pragma unroll
+            for (int q = 0; q < kRankMax / kCB; q++) {
+                const int32_t t = threadIdx.x + q * kCB;
+                if (t < r) {
+                    c.tj[base + rk[q]] = jv[q];
+                    c.tw[base + rk[q]] = sval[li[t]];
+                }
+            }
+        } else {
+            int32_t P = 1;
+            while (P < r) P <<= 1;
+            for (int32_t q = r + threadIdx.x; q < P; q += kCB) lj[q] = INT_MAX;
+            __syncthreads();
+            // bitonic sort of lj/lw[0, P) by column
+            for (int32_t kk = 2; kk <= P; kk <<= 1) {
+                for (int32_t jj = kk >> 1; jj > 0; jj >>= 1) {
+                    for (int32_t q = threadIdx.x; q < P; q += kCB) {
+                        const int32_t o = q ^ jj;
+                        if (o > q) {
+                            const bool up = (q & kk) == 0;
+                            const int32_t a = lj[q], b = lj[o];
+                            if ((a > b) == up) {
+                                lj[q] = b;
+                                lj[o] = a;
+                                const uint16_t x = li[q];
+                                li[q] = li[o];
+                                li[o] = x;
+                            }
                         }
                     }
+                    __syncthreads();
                 }
-                __syncthreads();
+            }
+            for (int32_t q = threadIdx.x; q < r; q += kCB) {
+                c.tj[base + q] = lj[q];
+                c.tw[base + q] = sval[li[q]];
             }
         }
-        for (int32_t q = threadIdx.x; q < r; q += kCB) {
-            c.tj[base + q] = lj[q];
-            c.tw[base + q] = lw[q];
-        }
         if (threadIdx.x == 0) c.rcnt[i] = r;
+        __syncthreads();  // every weight is read before the table is emptied
         for (uint32_t q = threadIdx.x; q < cap; q += kCB) {
             skey[q] = -1;
             sval[q] = 0;
@@ -342,9 +418,10 @@ __global__ __launch_bounds__(kCB) void k_cbig_chunk(RowCtx c, BigRows b) {
     constexpr int CAP = 2 * kRowChunk;
     __shared__ int32_t skey[CAP];
     __shared__ long long sval[CAP];
+    __shared__ int32_t sF[kRowChunk + 1];
     __shared__ int32_t rng[2];
     __shared__ int32_t t32[kCB / kWave + 1];
-    __shared__ int32_t resv;
+    __shared__ int32_t resv, spos;
     for (int q = threadIdx.x; q < CAP; q += kCB) {
         skey[q] = -1;
         sval[q] = 0;
@@ -361,33 +438,50 @@ __global__ __launch_bounds__(kCB) void k_cbig_chunk(RowCtx c, BigRows b) {
     }
     __syncthreads();
     const int32_t plo = rng[0], phi = rng[1];
-    int32_t p = plo;
-    for (int32_t t = t0 + threadIdx.x; t < t1; t += kCB) {
-        p = upper_pos(c.flat, p, phi, base + t);  // t grows per thread: search from the last member
-        const int32_t v = c.members[p];
-        const int32_t e = c.xadj[v] + (base + t - c.flat[p]);
-        const int32_t j = c.f2c[c.adjncy[e]];
-        if (j != i) col_insert(skey, sval, CAP - 1, __builtin_ctz(CAP), j, c.adjwgt ? c.adjwgt[e] : 1);
+    if (phi - plo < kRowChunk + 1) {
+        // the chunk's members (at most one per entry, unless members without
+        // neighbours sit among them) have their prefix staged in LDS
+        for (int q = threadIdx.x; q <= phi - plo; q += kCB) sF[q] = c.flat[plo + q] - base;
+        __syncthreads();
+        gather_insert<kRowChunk / kCB, kCB>(c, sF, plo, phi - plo, t0 + threadIdx.x, t1, i, skey, sval, CAP - 1,
+                                            __builtin_ctz(CAP));
+    } else {
+        int32_t p = plo;
+        for (int32_t t = t0 + threadIdx.x; t < t1; t += kCB) {
+            p = upper_pos(c.flat, p, phi, base + t);  // t grows per thread: search from the last member
+            const int32_t v = c.members[p];
+            const int32_t e = c.xadj[v] + (base + t - c.flat[p]);
+            const int32_t j = c.f2c[c.adjncy[e]];
+            if (j != i) col_insert(skey, sval, CAP - 1, __builtin_ctz(CAP), j, c.adjwgt ? c.adjwgt[e] : 1);
+        }
     }
     __syncthreads();
     int32_t cnt = 0;
     for (int q = threadIdx.x; q < CAP; q += kCB) cnt += skey[q] >= 0;
     cnt = block_sum<kCB>(cnt, t32);
-    if (threadIdx.x == 0) resv = cnt ? atomicAdd(b.cursor, cnt) : 0;
+    if (threadIdx.x == 0) {
+        resv = cnt ? atomicAdd(b.cursor, cnt) : 0;
+        spos = 0;
+    }
     __syncthreads();
-    int32_t r = resv;
+    // the pairs go out in any order (a radix sort follows): one LDS
+    // reservation per wave within the chunk's range
+    const int lane = lane_id();
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
     for (int q0 = 0; q0 < CAP; q0 += kCB) {
         const int q = q0 + threadIdx.x;
         const bool occ = skey[q] >= 0;
-        int32_t tot;
-        const int32_t ex = block_excl_scan<kCB>((int32_t)occ, t32, &tot);
+        const uint64_t m = __ballot(occ);
+        int32_t wb = 0;
+        if (lane == 0 && m) wb = atomicAdd(&spos, (int32_t)__popcll(m));
+        wb = __shfl(wb, 0);
         if (occ) {
-            b.key[r + ex] = ((uint64_t)(uint32_t)g << b.jbits) | (uint64_t)(uint32_t)skey[q];
+            const int32_t pos = resv + wb + (int32_t)__popcll(m & lt);
+            b.key[pos] = ((uint64_t)(uint32_t)g << b.jbits) | (uint64_t)(uint32_t)skey[q];
             const long long w = sval[q];
             if (w > INT_MAX) atomicOr(b.ovf, 1);  // the row's total would overflow too
-            b.val[r + ex] = (int32_t)(w > INT_MAX ? INT_MAX : w);
+            b.val[pos] = (int32_t)(w > INT_MAX ? INT_MAX : w);
         }
-        r += tot;
     }
 }
 

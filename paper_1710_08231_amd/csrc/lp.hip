@@ -262,10 +262,16 @@ __global__ __launch_bounds__(BLOCK) void k_propose_block(LPArgs a, const int32_t
         val[i] = 0;
     }
     __syncthreads();
-    for (int64_t idx = xcd_block(blockIdx.x, gridDim.x); idx < count; idx += gridDim.x) {
-        const int32_t v = verts[idx];
-        const int32_t beg = a.xadj[v], end = a.xadj[v + 1];
-        const int32_t own = a.labels[v];
+    // the next vertex's id is loaded with the current vertex's edges, and its
+    // row range and label during the current selection, so each vertex
+    // starts with its edge loads
+    int64_t idx = xcd_block(blockIdx.x, gridDim.x);
+    int32_t v = idx < count ? verts[idx] : 0;
+    int32_t beg = idx < count ? a.xadj[v] : 0, end = idx < count ? a.xadj[v + 1] : 0;
+    int32_t own = idx < count ? a.labels[v] : -1;
+    for (; idx < count; idx += gridDim.x) {
+        const int64_t nidx = idx + gridDim.x;
+        const int32_t nv = nidx < count ? verts[nidx] : 0;
         int lg = 6;
         while ((1 << lg) < 2 * (end - beg) && (1 << lg) < TBL) lg++;
         const uint32_t cap = 1u << lg;
@@ -289,6 +295,8 @@ __global__ __launch_bounds__(BLOCK) void k_propose_block(LPArgs a, const int32_t
             }
         }
         __syncthreads();
+        const int32_t nbeg = nidx < count ? a.xadj[nv] : 0, nend = nidx < count ? a.xadj[nv + 1] : 0;
+        const int32_t nown = nidx < count ? a.labels[nv] : -1;
         oc = block_sum<BLOCK>(oc, tc);
         AccT bc = 0;
         int32_t bl = INT_MAX;
@@ -325,6 +333,10 @@ __global__ __launch_bounds__(BLOCK) void k_propose_block(LPArgs a, const int32_t
             val[i] = 0;
         }
         __syncthreads();
+        v = nv;
+        beg = nbeg;
+        end = nend;
+        own = nown;
     }
 }
 
@@ -652,8 +664,7 @@ __global__ __launch_bounds__(kPropBlock) void k_dense_group(LPArgs a, int32_t nl
 // one wave per vertex selects. No single workgroup walks a whole hub.
 struct DenseBig {
     const int32_t *verts;        // [nbig]
-    const int32_t *chunk_owner;  // [nchunks] index into verts
-    const int32_t *chunk_first;  // [nbig]
+    const int4 *desc;            // [nchunks] (vertex, first entry, end entry, index into verts)
     void *gconn;                 // [nbig * KT] AccT
     unsigned long long *own;     // [nbig]
     int32_t nbig;
@@ -684,11 +695,11 @@ __global__ __launch_bounds__(256) void k_dense_chunk(LPArgs a, DenseBig db) {
     const int w = (threadIdx.x / kWave) * SUB + lane_id() / (kWave / SUB);
     for (int i = threadIdx.x; i < NW * SUB * KT; i += 256) (&val[0][0])[i] = 0;
     __syncthreads();
-    const int32_t b = db.chunk_owner[blockIdx.x];
-    const int32_t v = db.verts[b];
+    // the chunk's vertex and entry range come in one load (planned once per
+    // call), so the edge loads wait on one load, not on three dependent ones
+    const int4 d = db.desc[blockIdx.x];
+    const int32_t v = d.x, beg = d.y, end = d.z, b = d.w;
     const int32_t own = a.labels[v];
-    const int32_t beg = a.xadj[v] + (blockIdx.x - db.chunk_first[b]) * db.chunk;
-    const int32_t end = min(a.xadj[v + 1], beg + db.chunk);
     AccT oc = 0;
     constexpr int UC = 4;
     for (int32_t e0 = beg + threadIdx.x; e0 < end; e0 += UC * 256) {
@@ -799,6 +810,19 @@ __global__ void k_chunk_counts(const int32_t *xadj, const int32_t *verts, int32_
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t v = verts[i];
         num[i] = (xadj[v + 1] - xadj[v] + chunk - 1) / chunk;
+    }
+}
+
+// chunk descriptors of the dense big-vertex plan: chunk q of vertex verts[i]
+// covers entries [xadj[v] + q * chunk, min(xadj[v + 1], that + chunk))
+__global__ void k_chunk_desc(const int32_t *xadj, const int32_t *verts, const int32_t *first, const int32_t *num,
+                             int32_t nb, int32_t chunk, int4 *desc) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = verts[i], e1 = xadj[v + 1];
+        for (int32_t q = 0; q < num[i]; q++) {
+            const int32_t b0 = xadj[v] + q * chunk;
+            desc[first[i] + q] = make_int4(v, b0, min(e1, b0 + chunk), (int32_t)i);
+        }
     }
 }
 
@@ -1299,7 +1323,8 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
     if (nbig > 0) {
         const int KT = nlabels <= 16 ? 16 : (nlabels <= 64 ? 64 : 256);
         const int32_t *big = verts + tstart[6];
-        int32_t *num = nullptr, *first = nullptr, *owner = nullptr, *d_tot = nullptr;
+        int32_t *num = nullptr, *first = nullptr, *d_tot = nullptr;
+        int4 *desc = nullptr;
         unsigned long long *own = nullptr;
         GP_TRY(sc.alloc(&num, nbig));
         GP_TRY(sc.alloc(&first, nbig));
@@ -1312,15 +1337,16 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
         GP_TRY((scan<int32_t>(LoadIn<int32_t>{num}, StoreExcl<int32_t>{first}, nbig, nullptr, d_tot, sc)));
         GP_HIP(hipMemcpyAsync(&dchunks, d_tot, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         GP_HIP(hipStreamSynchronize(s));
-        GP_TRY(sc.alloc(&owner, dchunks));
-        hipLaunchKernelGGL(k_hub_expand, dim3(grid_for(nbig, 256, 4096)), dim3(256), 0, s, first, num, nbig, owner);
+        GP_TRY(sc.alloc(&desc, dchunks));
+        hipLaunchKernelGGL(k_chunk_desc, dim3(grid_for(nbig, 256, 4096)), dim3(256), 0, s, g.xadj, big, first, num,
+                           nbig, chunk, desc);
         GP_LAUNCH_CHECK();
         const size_t cb = (size_t)nbig * KT * (wide ? sizeof(int64_t) : sizeof(int32_t));
         void *gconn = nullptr;
         GP_TRY(sc.alloc((char **)&gconn, cb));
         GP_HIP(hipMemsetAsync(gconn, 0, cb, s));
         GP_HIP(hipMemsetAsync(own, 0, sizeof(unsigned long long) * nbig, s));
-        db = DenseBig{big, owner, first, gconn, own, nbig, chunk};
+        db = DenseBig{big, desc, gconn, own, nbig, chunk};
     }
 
     // ---- dense mode: byte copy of the labels (block ids < 256) for the

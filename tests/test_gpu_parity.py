@@ -150,6 +150,21 @@ def test_contract_label_groups_without_edges():
         assert np.array_equal(_np(cg[key]), ocg[key]), key
 
 
+def test_contract_large_row_with_members_without_edges():
+    # one coarse row of 3000 entries (two hubs of 1500 distinct neighbours) whose
+    # 6002 members are mostly vertices without neighbours, listed between the two
+    # hubs: a chunk of the row then spans more members than it has entries
+    edges = [(0, 6002 + j) for j in range(1500)] + [(6001, 7502 + j) for j in range(1500)]
+    g = graphgen.from_edges(9002, edges)
+    lab = np.arange(9002, dtype=np.int32)
+    lab[:6002] = 0
+    ocg, of2c = oracle.contract(g, lab)
+    cg, f2c = gp.contract(gp.to_device(g), torch.from_numpy(lab).cuda())
+    assert np.array_equal(_np(f2c), of2c)
+    for key in ("xadj", "adjncy", "adjwgt", "vwgt"):
+        assert np.array_equal(_np(cg[key]), ocg[key]), key
+
+
 def test_contract_large_rows():
     # a coarse row with > 2048 entries and many distinct columns (global class) next to small rows
     g = graphgen.rmat(14, 3)
