@@ -1070,7 +1070,7 @@ struct NoOut64 {
 template <typename AccT>
 int launch_proposals(const LPArgs &a, const int32_t *verts, const int64_t *tstart, const int32_t *hub_log,
                      const int64_t *hub_off, int32_t *gkey, AccT *gval, hipStream_t s, const double *tb,
-                     bool skip_hubs = false) {
+                     int32_t bound6, bool skip_hubs = false) {
     const char *acc = sizeof(AccT) == 4 ? "int" : "long";
     auto cnt = [&](int t) { return (int32_t)(tstart[t + 1] - tstart[t]); };
     auto lst = [&](int t) { return verts + tstart[t]; };
@@ -1099,8 +1099,15 @@ int launch_proposals(const LPArgs &a, const int32_t *verts, const int64_t *tstar
                            a, lst(5), c));
     }
     if ((c = cnt(6)) > 0) {
-        GP_PROF_LAUNCH((std::string("k_propose_block<256, 4096, ") + acc + ">").c_str(), tb[6], s, hipLaunchKernelGGL((k_propose_block<256, 4096, AccT>), dim3(grid_for(c, 1, 8192)), dim3(256), 0, s, a,
-                           lst(6), c));
+        // a bound of at most 1024 fits 2048-slot tables: 128-thread
+        // workgroups of a quarter of the LDS, so more vertices are in flight
+        if (bound6 <= 1024) {
+            GP_PROF_LAUNCH((std::string("k_propose_block<128, 2048, ") + acc + ">").c_str(), tb[6], s, hipLaunchKernelGGL((k_propose_block<128, 2048, AccT>), dim3(grid_for(c, 1, 16384)), dim3(128), 0, s, a,
+                               lst(6), c));
+        } else {
+            GP_PROF_LAUNCH((std::string("k_propose_block<256, 4096, ") + acc + ">").c_str(), tb[6], s, hipLaunchKernelGGL((k_propose_block<256, 4096, AccT>), dim3(grid_for(c, 1, 8192)), dim3(256), 0, s, a,
+                               lst(6), c));
+        }
     }
     if ((c = cnt(7)) > 0) {
         constexpr int T7 = sizeof(AccT) == 4 ? 16384 : 8192;
@@ -1415,10 +1422,11 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
         else if (dense)
             RT_TRY(launch_dense_any<int32_t>(a, nlabels, verts, tstart, &db, dchunks, s, tbytes));
         else if (wide)
-            RT_TRY(launch_proposals<int64_t>(a, verts, tstart, hub_log, hub_off, gkey, (int64_t *)gval, s, tbytes));
+            RT_TRY(launch_proposals<int64_t>(a, verts, tstart, hub_log, hub_off, gkey, (int64_t *)gval, s, tbytes,
+                                             tk.bound[6]));
         else
             RT_TRY(launch_proposals<int32_t>(a, verts, tstart, hub_log, hub_off, gkey, (int32_t *)gval, s, tbytes,
-                                             split_hubs));
+                                             tk.bound[6], split_hubs));
         if (split_hubs) {
             GP_PROF_LAUNCH("k_hub_insert", tbytes[8], s, hipLaunchKernelGGL(k_hub_insert, dim3(nchunks), dim3(kHubBlock), 0, s, a, hp));
             hipLaunchKernelGGL(k_hub_scan<false>, dim3(nslices), dim3(256), 0, s, a, hp);

@@ -159,56 +159,105 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_hist(const K *keys, int64_
     for (int d = threadIdx.x; d < 256; d += kSortBlock) hist[(int64_t)d * ntiles + blockIdx.x] = h[d];
 }
 
-// Stable scatter: items of a tile are ranked in their original order.
+// Stable scatter of one tile. Each wave owns a contiguous quarter of the
+// tile and ranks its items round by round (64 at a time, peers of a digit
+// found by ballots over the digit bits) against wave-private digit counters,
+// so ranks follow the original order. The tile is then placed in LDS in
+// digit order and written out from there: consecutive threads write
+// consecutive positions of each digit's run.
 template <typename K, typename V>
 __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K *kin, const V *vin, K *kout,
                                                               V *vout, int64_t nmax,
                                                               const int32_t *n_dev, int shift,
                                                               int nbits, const uint32_t *offs,
                                                               int ntiles) {
+    static_assert(kSortBlock == 256, "one thread per digit");
     constexpr int NW = kSortBlock / kWave;
-    __shared__ uint32_t wcnt[NW][256];
-    __shared__ uint32_t run[256];
+    constexpr int PER_W = kSortTile / NW;
+    constexpr int R = PER_W / kWave;
+    __shared__ uint32_t wc[NW][256];
+    __shared__ uint32_t dstart[256];
+    __shared__ uint32_t goff[256];
+    __shared__ uint32_t tmp[NW + 1];
+    // the tile passes through LDS twice, keys then values, in one buffer
+    constexpr size_t kItem = sizeof(K) > sizeof(V) ? sizeof(K) : sizeof(V);
+    __shared__ __align__(16) unsigned char stage[kSortTile * kItem];
+    K *sk = reinterpret_cast<K *>(stage);
+    V *sv = reinterpret_cast<V *>(stage);
     const int64_t n = live_count(nmax, n_dev);
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     if (base >= n) return;
     const uint32_t mask = (1u << nbits) - 1u;
     const int lane = lane_id(), w = threadIdx.x / kWave;
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (kWave - lane));
-    for (int d = threadIdx.x; d < 256; d += kSortBlock)
-        run[d] = offs[(int64_t)d * ntiles + blockIdx.x];
-    for (int r = 0; r < kSortItems; r++) {
-        const int64_t idx = base + (int64_t)r * kSortBlock + threadIdx.x;
-        const bool valid = idx < n;
-        K key = valid ? kin[idx] : K(0);
-        uint32_t dig = valid ? ((uint32_t)(key >> shift) & mask) : 0u;
-        for (int i = threadIdx.x; i < NW * 256; i += kSortBlock) (&wcnt[0][0])[i] = 0;
-        __syncthreads();
+    for (int d = threadIdx.x; d < NW * 256; d += kSortBlock) (&wc[0][0])[d] = 0;
+    goff[threadIdx.x] = offs[(int64_t)threadIdx.x * ntiles + blockIdx.x];
+    __syncthreads();
+    const int64_t wbase = base + (int64_t)w * PER_W;
+    K key[R];
+    V val[R];
+    uint32_t rk[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int64_t idx = wbase + r * kWave + lane;
+        key[r] = idx < n ? kin[idx] : K(0);
+        val[r] = idx < n ? vin[idx] : V(0);
+    }
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const bool valid = wbase + r * kWave + lane < n;
+        const uint32_t dig = (uint32_t)(key[r] >> shift) & mask;
         uint64_t peers = __ballot(valid);
-        for (int b = 0; b < nbits; b++) {
-            const bool bit = (dig >> b) & 1u;
+        for (int bt = 0; bt < nbits; bt++) {
+            const bool bit = (dig >> bt) & 1u;
             const uint64_t m = __ballot(bit);
             peers &= bit ? m : ~m;
         }
-        const uint32_t rank = (uint32_t)__popcll(peers & lt);
-        if (valid && rank == 0) wcnt[w][dig] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        for (int d = threadIdx.x; d < 256; d += kSortBlock) {
-            uint32_t acc = run[d];
-            for (int q = 0; q < NW; q++) {
-                uint32_t t = wcnt[q][d];
-                wcnt[q][d] = acc;
-                acc += t;
-            }
-            run[d] = acc;
+        const uint32_t before = valid ? wc[w][dig] : 0u;
+        const uint32_t pr = (uint32_t)__popcll(peers & lt);
+        rk[r] = before + pr;
+        // every lane has read the counter before the group's first lane
+        // advances it (one wave: LDS operations complete in program order)
+        if (valid && pr == 0) wc[w][dig] = before + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    uint32_t acc = 0;
+    for (int q = 0; q < NW; q++) {
+        const uint32_t t = wc[q][threadIdx.x];
+        wc[q][threadIdx.x] = acc;
+        acc += t;
+    }
+    dstart[threadIdx.x] = block_excl_scan<kSortBlock>(acc, tmp, (uint32_t *)nullptr);
+    __syncthreads();
+    // local position of each item; its digit is kept for the value pass
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const uint32_t dig = (uint32_t)(key[r] >> shift) & mask;
+        rk[r] += dstart[dig] + wc[w][dig];
+        if (wbase + r * kWave + lane < n) sk[rk[r]] = key[r];
+    }
+    __syncthreads();
+    const int32_t cnt = (int32_t)((n - base) < kSortTile ? (n - base) : kSortTile);
+    uint8_t pd[kSortTile / kSortBlock];  // digit of each output slot of this thread
+#pragma unroll
+    for (int q = 0; q < kSortTile / kSortBlock; q++) {
+        const int32_t p = threadIdx.x + q * kSortBlock;
+        if (p < cnt) {
+            const K kk = sk[p];
+            const uint32_t dig = (uint32_t)(kk >> shift) & mask;
+            pd[q] = (uint8_t)dig;
+            kout[goff[dig] + ((uint32_t)p - dstart[dig])] = kk;
         }
-        __syncthreads();
-        if (valid) {
-            const uint32_t pos = wcnt[w][dig] + rank;
-            kout[pos] = key;
-            vout[pos] = vin[idx];
-        }
-        __syncthreads();
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; r++)
+        if (wbase + r * kWave + lane < n) sv[rk[r]] = val[r];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kSortTile / kSortBlock; q++) {
+        const int32_t p = threadIdx.x + q * kSortBlock;
+        if (p < cnt) vout[goff[pd[q]] + ((uint32_t)p - dstart[pd[q]])] = sv[p];
     }
 }
 

@@ -334,3 +334,20 @@ def test_lp_with_64bit_sums(case):
         p, _ = gp.lp_refine(dg, torch.from_numpy(part).cuda(), k, lm, 10)
         op, _ = oracle.lp_refine(g, part, k, lm, 10)
         assert np.array_equal(_np(p), op), k
+
+
+def test_lp_with_64bit_sums_small_block_tier():
+    # a block-tier bound of 1024 selects the 128-thread workgroups with
+    # 2048-slot tables, here with 64-bit connection sums
+    g = _heavy(graphgen.rmat(13, 3), 1 << 22, 1)
+    deg = np.diff(g["xadj"])
+    assert np.count_nonzero((deg > 128) & (deg <= 1024)) > 10
+    try:
+        gp.set_tuning({"tier_max": [32, 128, 1024, 4096], "dense_split": 256, "dense_chunk": 2048})
+        for U in (5, 400):
+            lab, st = gp.lp_cluster(gp.to_device(g), U, 10)
+            olab, ost = oracle.lp_cluster(g, U, 10)
+            assert np.array_equal(_np(lab), olab), U
+            assert st["moves"] == ost["moves"]
+    finally:
+        gp.set_tuning(None)
