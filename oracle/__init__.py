@@ -39,7 +39,7 @@ class _Params(ctypes.Structure):
                 ("dir_alternate", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("init_mode", ctypes.c_int32), ("mpnn_max_n", ctypes.c_int32),
                 ("mpnn_seed", ctypes.c_uint64), ("mpnn_params", ctypes.POINTER(ctypes.c_float)),
-                ("lp_async", ctypes.c_int32)]
+                ("lp_async", ctypes.c_int32), ("active_set", ctypes.c_int32)]
 
 
 class _Result(ctypes.Structure):
@@ -156,19 +156,26 @@ def lp_round(g, C, W, U, r, dir_alternate=1):
     return C, W, int(m), prop
 
 
-def lp_cluster(g, U, rounds=10, dir_alternate=1):
+LP_DIR_ALTERNATE, LP_ACTIVE_SET = 1, 2
+
+
+def _flags(dir_alternate, active):
+    return (LP_DIR_ALTERNATE if dir_alternate else 0) | (LP_ACTIVE_SET if active else 0)
+
+
+def lp_cluster(g, U, rounds=10, dir_alternate=1, active=False):
     G = _G(g)
     out = np.zeros(G.n, dtype=np.int32)
     st = _LPStats()
-    _load().orc_lp_cluster(G.ref, U, rounds, dir_alternate, _p32(out), ctypes.byref(st))
+    _load().orc_lp_cluster(G.ref, U, rounds, _flags(dir_alternate, active), _p32(out), ctypes.byref(st))
     return out, {"rounds_run": st.rounds_run, "moves": st.moves, "edge_visits": st.edge_visits}
 
 
-def lp_refine(g, part, k, lmax_, rounds=25, dir_alternate=1):
+def lp_refine(g, part, k, lmax_, rounds=25, dir_alternate=1, active=False):
     G = _G(g)
     P = _i32(part).copy()
     st = _LPStats()
-    _load().orc_lp_refine(G.ref, k, lmax_, rounds, dir_alternate, _p32(P), ctypes.byref(st))
+    _load().orc_lp_refine(G.ref, k, lmax_, rounds, _flags(dir_alternate, active), _p32(P), ctypes.byref(st))
     return P, {"rounds_run": st.rounds_run, "moves": st.moves, "edge_visits": st.edge_visits}
 
 
@@ -265,7 +272,7 @@ def fill_isolated(g, k, part, B):
 
 DEFAULT_PARAMS = dict(rounds_coarsen=10, rounds_refine=25, coarsest_per_k=60, attempts=4,
                       stall_num=19, stall_den=20, dir_alternate=1, seed=0, init_mode=0,
-                      mpnn_max_n=131072, mpnn_seed=0, mpnn_params=None, lp_async=0)
+                      mpnn_max_n=131072, mpnn_seed=0, mpnn_params=None, lp_async=0, active_set=0)
 
 
 def _params(params):

@@ -59,15 +59,32 @@ int64_t orc_total_vwgt(const orc_graph *g) {
  *      the proposers to t up to and including v) <= U.
  *   5. apply all admitted moves; W follows.
  */
-int64_t orc_lp_round(const orc_graph *g, int32_t *C, int64_t *W, int32_t nlabels, int64_t U,
-                     int32_t r, int32_t dir_alternate, int32_t *prop_out) {
+/*
+ * Active-set rounds (the paper's Q/Q' of §III-A and §IV-A, made synchronous):
+ * act[v] counts the evaluations v still owes. A vertex with act[v] == 0 makes
+ * no proposal and its edges are not visited. Every evaluated vertex owes one
+ * evaluation less afterwards. A vertex whose proposal is refused by the
+ * admission owes at least one more (it is blocked by capacity, not
+ * settled). Every neighbour of an admitted mover owes `renew` evaluations:
+ * 2 with direction alternation (one per direction, since a round sees only
+ * one direction), else 1. All vertices start owing `renew`.
+ */
+static int64_t lp_round_act(const orc_graph *g, int32_t *C, int64_t *W, int32_t nlabels, int64_t U,
+                            int32_t r, int32_t dir_alternate, int32_t *prop_out, uint8_t *act, int64_t *visits) {
     int32_t n = g->n;
     int64_t *conn = (int64_t *)xcalloc((size_t)nlabels, sizeof(int64_t));
     int32_t *seen = (int32_t *)xcalloc((size_t)nlabels, sizeof(int32_t));
     int32_t *touched = (int32_t *)xcalloc((size_t)nlabels, sizeof(int32_t));
     int32_t *prop = prop_out ? prop_out : (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
+    const uint8_t renew = dir_alternate ? 2 : 1;
 
     for (int32_t v = 0; v < n; v++) {
+        if (act && act[v] == 0) {
+            prop[v] = -1;
+            continue;
+        }
+        if (act) act[v]--;
+        if (visits) *visits += g->xadj[v + 1] - g->xadj[v];
         int32_t ntouched = 0;
         for (int32_t e = g->xadj[v]; e < g->xadj[v + 1]; e++) {
             int32_t L = C[g->adjncy[e]];
@@ -103,6 +120,7 @@ int64_t orc_lp_round(const orc_graph *g, int32_t *C, int64_t *W, int32_t nlabels
         int32_t t = prop[v];
         acc[t] += VW(g, v);
         admitted[v] = (W[t] + acc[t] <= U);
+        if (act && !admitted[v] && act[v] < 1) act[v] = 1;
     }
     int64_t moves = 0;
     for (int32_t v = 0; v < n; v++) {
@@ -112,6 +130,8 @@ int64_t orc_lp_round(const orc_graph *g, int32_t *C, int64_t *W, int32_t nlabels
         W[C[v]] -= VW(g, v);
         C[v] = t;
         moves++;
+        if (act)
+            for (int32_t e = g->xadj[v]; e < g->xadj[v + 1]; e++) act[g->adjncy[e]] = renew;
     }
     free(admitted);
     free(conn);
@@ -121,42 +141,55 @@ int64_t orc_lp_round(const orc_graph *g, int32_t *C, int64_t *W, int32_t nlabels
     return moves;
 }
 
-/* Round loop shared by clustering and refinement; stop after two idle rounds in a row. */
+int64_t orc_lp_round(const orc_graph *g, int32_t *C, int64_t *W, int32_t nlabels, int64_t U,
+                     int32_t r, int32_t dir_alternate, int32_t *prop_out) {
+    return lp_round_act(g, C, W, nlabels, U, r, dir_alternate, prop_out, NULL, NULL);
+}
+
+/* Round loop shared by clustering and refinement; stop after two idle rounds
+ * in a row. flags: ORC_LP_DIR_ALTERNATE, ORC_LP_ACTIVE_SET. */
 static void lp_rounds(const orc_graph *g, int32_t *C, int64_t *W, int32_t nlabels, int64_t U,
-                      int32_t rounds, int32_t dir_alternate, orc_lp_stats *st) {
-    int64_t prev = -1, total = 0;
+                      int32_t rounds, int32_t flags, orc_lp_stats *st) {
+    const int32_t dirs = (flags & ORC_LP_DIR_ALTERNATE) != 0;
+    uint8_t *act = NULL;
+    if (flags & ORC_LP_ACTIVE_SET) {
+        act = (uint8_t *)xcalloc((size_t)g->n + 1, 1);
+        memset(act, dirs ? 2 : 1, (size_t)g->n);
+    }
+    int64_t prev = -1, total = 0, visits = 0;
     int32_t run = 0;
     for (int32_t r = 0; r < rounds; r++) {
-        int64_t m = orc_lp_round(g, C, W, nlabels, U, r, dir_alternate, NULL);
+        int64_t m = lp_round_act(g, C, W, nlabels, U, r, dirs, NULL, act, &visits);
         total += m;
         run = r + 1;
         if (r >= 1 && m == 0 && prev == 0) break;
         prev = m;
     }
+    free(act);
     if (st) {
         st->rounds_run = run;
         st->moves = total;
-        st->edge_visits = (int64_t)run * (int64_t)g->xadj[g->n];
+        st->edge_visits = visits;
     }
 }
 
 /* §III-A: size-constrained LP clustering from singletons, C[v] = v, bound U. */
-int orc_lp_cluster(const orc_graph *g, int64_t U, int32_t rounds, int32_t dir_alternate,
+int orc_lp_cluster(const orc_graph *g, int64_t U, int32_t rounds, int32_t flags,
                    int32_t *labels_out, orc_lp_stats *st) {
     int32_t n = g->n;
     int64_t *W = (int64_t *)xcalloc((size_t)n, sizeof(int64_t));
     for (int32_t v = 0; v < n; v++) { labels_out[v] = v; W[v] = VW(g, v); }
-    lp_rounds(g, labels_out, W, n, U, rounds, dir_alternate, st);
+    lp_rounds(g, labels_out, W, n, U, rounds, flags, st);
     free(W);
     return 0;
 }
 
 /* §III-C: LP as local search from a k-way partition with U = L_max. */
 int orc_lp_refine(const orc_graph *g, int32_t k, int64_t lmax, int32_t rounds,
-                  int32_t dir_alternate, int32_t *part, orc_lp_stats *st) {
+                  int32_t flags, int32_t *part, orc_lp_stats *st) {
     int64_t *W = (int64_t *)xcalloc((size_t)k, sizeof(int64_t));
     for (int32_t v = 0; v < g->n; v++) W[part[v]] += VW(g, v);
-    lp_rounds(g, part, W, k, lmax, rounds, dir_alternate, st);
+    lp_rounds(g, part, W, k, lmax, rounds, flags, st);
     free(W);
     return 0;
 }
@@ -565,6 +598,12 @@ typedef struct {
  *  - coarsen while n > coarsest_per_k * k; discard a level that did not
  *    shrink; stop after a level with stall_den * n' > stall_num * n.
  */
+/* LP flags of the coarsening and uncoarsening rounds (initial partitioning
+ * always runs full rounds) */
+static int32_t lp_flags(const orc_params *p) {
+    return (p->dir_alternate ? ORC_LP_DIR_ALTERNATE : 0) | (p->active_set ? ORC_LP_ACTIVE_SET : 0);
+}
+
 static void coarsen(const orc_graph *g, int32_t k, double eps, const orc_params *p, hierarchy_t *h) {
     int32_t n = g->n;
     int64_t W = orc_total_vwgt(g);
@@ -610,7 +649,7 @@ static void coarsen(const orc_graph *g, int32_t k, double eps, const orc_params 
         int32_t *labels = (int32_t *)xcalloc((size_t)fn, sizeof(int32_t));
         orc_lp_stats st;
         if (p->lp_async) orc_lp_cluster_async(&f->g, ucl, p->rounds_coarsen, labels, &st);
-        else orc_lp_cluster(&f->g, ucl, p->rounds_coarsen, p->dir_alternate, labels, &st);
+        else orc_lp_cluster(&f->g, ucl, p->rounds_coarsen, lp_flags(p), labels, &st);
         ev_cluster += st.edge_visits;
         c->xadj = (int32_t *)xcalloc((size_t)fn + 1, sizeof(int32_t));
         c->adjncy = (int32_t *)xcalloc((size_t)fnnz, sizeof(int32_t));
@@ -743,7 +782,7 @@ int orc_partition(const orc_graph *g, int32_t k, double eps, const orc_params *p
         }
         orc_lp_stats st;
         if (p->lp_async) orc_lp_refine_async(&lev[l].g, k, lmax, p->rounds_refine, P, &st);
-        else orc_lp_refine(&lev[l].g, k, lmax, p->rounds_refine, p->dir_alternate, P, &st);
+        else orc_lp_refine(&lev[l].g, k, lmax, p->rounds_refine, lp_flags(p), P, &st);
         ev_refine += st.edge_visits;
     }
 

@@ -51,7 +51,12 @@ typedef struct {
     uint64_t mpnn_seed;       /* probe features */
     const float *mpnn_params; /* fp32 master weights (see orc_mpnn_param_count) */
     int32_t lp_async;         /* 0; 1: the paper's sequential LP (oracle-only comparison mode) */
+    int32_t active_set;       /* 0; 1: coarsening and uncoarsening LP in active-set rounds */
 } orc_params;
+
+/* LP flags (the former 0/1 direction argument is flag bit 0) */
+#define ORC_LP_DIR_ALTERNATE 1
+#define ORC_LP_ACTIVE_SET 2
 
 typedef struct {
     int64_t cut, max_block_w, lmax, ucl;
@@ -69,10 +74,12 @@ int64_t orc_total_vwgt(const orc_graph *g);
 int64_t orc_lp_round(const orc_graph *g, int32_t *C, int64_t *W, int32_t nlabels, int64_t U,
                      int32_t r, int32_t dir_alternate, int32_t *prop_out);
 
-int orc_lp_cluster(const orc_graph *g, int64_t U, int32_t rounds, int32_t dir_alternate,
+/* flags: ORC_LP_DIR_ALTERNATE | ORC_LP_ACTIVE_SET; edge_visits counts the
+ * edges of the vertices evaluated (rounds_run * nnz without active sets) */
+int orc_lp_cluster(const orc_graph *g, int64_t U, int32_t rounds, int32_t flags,
                    int32_t *labels_out, orc_lp_stats *st);
 int orc_lp_refine(const orc_graph *g, int32_t k, int64_t lmax, int32_t rounds,
-                  int32_t dir_alternate, int32_t *part_inout, orc_lp_stats *st);
+                  int32_t flags, int32_t *part_inout, orc_lp_stats *st);
 
 /* §III-A sequential LP as the paper states it (queue by increasing degree,
  * in-place moves, neighbours of movers re-queued); an oracle-only mode. */
