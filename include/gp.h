@@ -79,7 +79,7 @@ typedef struct {
 typedef struct {
     int32_t rounds_run;  /* rounds executed before the two-idle-rounds stop (<= rounds) */
     int64_t moves;       /* admitted moves summed over the rounds */
-    int64_t edge_visits; /* rounds_run * nnz */
+    int64_t edge_visits; /* rounds_run * nnz; with GP_LP_ACTIVE_SET the edges of the vertices evaluated */
     float ms;            /* device time of the call (HIP events on `stream`) */
 } gp_lp_stats;
 
@@ -97,6 +97,8 @@ typedef struct {
     int32_t mpnn_max_n;     /* 131072: the proposal is tried only on coarsest graphs this small */
     uint64_t mpnn_seed;     /* 0: seed of the network's probe features */
     const float *mpnn_params; /* NULL: device fp32 master weights, gp_mpnn_param_count(k) of them */
+    int32_t active_set;     /* 0; 1: coarsening and uncoarsening LP in active-set rounds (GP_LP_ACTIVE_SET);
+                               single graphs only */
 } gp_params;
 
 typedef struct {
@@ -108,7 +110,7 @@ typedef struct {
     int32_t levels;       /* graphs in the hierarchy, level 0 included */
     int32_t coarsest_n;   /* vertices of the coarsest graph */
     int32_t n_isolated;   /* vertices without neighbours (placed at the end) */
-    int64_t edge_visits_cluster; /* sum over levels of rounds_run * nnz in clustering */
+    int64_t edge_visits_cluster; /* sum over levels of the clustering edge visits (gp_lp_stats) */
     int64_t edge_visits_refine;  /* same for refinement */
     float ms_coarsen, ms_init, ms_refine, ms_total; /* device-timed phases */
     int32_t learned_tried;        /* GP_INIT_LEARNED and the coarsest graph within mpnn_max_n */
@@ -123,12 +125,27 @@ void gp_default_params(gp_params *p);
 int64_t gp_lmax(int64_t total_vwgt, int32_t k, double eps);
 
 /*
+ * Flags of the LP calls (a plain 0/1 direction argument is flag bit 0).
+ * GP_LP_DIR_ALTERNATE: even rounds consider only smaller labels, odd rounds
+ * only larger ones. GP_LP_ACTIVE_SET: active-set rounds, the synchronous form
+ * of the queues Q/Q' of §III-A and §IV-A. A vertex is evaluated (and its
+ * edges visited) only while it owes evaluations. Every vertex starts owing
+ * one per direction (2 with GP_LP_DIR_ALTERNATE, else 1). Each evaluation
+ * pays one. A proposal refused by the admission leaves at least one owed.
+ * Every neighbour of an admitted mover owes one per direction again. The
+ * results differ from full rounds.
+ */
+#define GP_LP_DIR_ALTERNATE 1
+#define GP_LP_ACTIVE_SET 2
+
+/*
  * Size-constrained LP clustering (§III-A, §IV-A). Starts from singletons
  * (C[v] = v, W[v] = c(v)) and runs up to `rounds` rounds with bound U >= 1.
+ * flags: GP_LP_DIR_ALTERNATE | GP_LP_ACTIVE_SET (other bits: GP_ERR_ARG).
  * labels_out: [n] device int32, receives cluster labels in [0, n) (leader ids,
  * not compacted). st_host (may be NULL) receives the statistics.
  */
-int gp_lp_cluster(const gp_graph *g, int64_t U, int32_t rounds, int32_t dir_alternate,
+int gp_lp_cluster(const gp_graph *g, int64_t U, int32_t rounds, int32_t flags,
                   int32_t *labels_out, gp_lp_stats *st_host, hipStream_t stream);
 
 /*
@@ -136,7 +153,7 @@ int gp_lp_cluster(const gp_graph *g, int64_t U, int32_t rounds, int32_t dir_alte
  * part_inout: [n] device int32 with 0 <= part[v] < k; overwritten with the
  * refined partition. lmax >= 1 bounds every block.
  */
-int gp_lp_refine(const gp_graph *g, int32_t k, int64_t lmax, int32_t rounds, int32_t dir_alternate,
+int gp_lp_refine(const gp_graph *g, int32_t k, int64_t lmax, int32_t rounds, int32_t flags,
                  int32_t *part_inout, gp_lp_stats *st_host, hipStream_t stream);
 
 /*

@@ -58,7 +58,7 @@ class Params(ctypes.Structure):
                 ("stall_num", ctypes.c_int32), ("stall_den", ctypes.c_int32),
                 ("dir_alternate", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("init_mode", ctypes.c_int32), ("mpnn_max_n", ctypes.c_int32),
-                ("mpnn_seed", ctypes.c_uint64), ("mpnn_params", ctypes.c_void_p)]
+                ("mpnn_seed", ctypes.c_uint64), ("mpnn_params", ctypes.c_void_p), ("active_set", ctypes.c_int32)]
 
 
 class Tuning(ctypes.Structure):
@@ -188,23 +188,30 @@ def default_params():
     return p
 
 
-def lp_cluster(g, U, rounds=10, dir_alternate=1):
+LP_DIR_ALTERNATE, LP_ACTIVE_SET = 1, 2
+
+
+def _lp_flags(dir_alternate, active):
+    return (LP_DIR_ALTERNATE if dir_alternate else 0) | (LP_ACTIVE_SET if active else 0)
+
+
+def lp_cluster(g, U, rounds=10, dir_alternate=1, active=False):
     torch = _torch()
     gs = _gstruct(g)
     labels = torch.empty(gs.n, dtype=torch.int32, device=g["xadj"].device)
     st = LPStats()
-    _check(load().gp_lp_cluster(ctypes.byref(gs), U, rounds, dir_alternate, _ptr(labels), ctypes.byref(st),
-                                _stream()))
+    _check(load().gp_lp_cluster(ctypes.byref(gs), U, rounds, _lp_flags(dir_alternate, active), _ptr(labels),
+                                ctypes.byref(st), _stream()))
     return labels, {"rounds_run": st.rounds_run, "moves": st.moves, "edge_visits": st.edge_visits, "ms": st.ms}
 
 
-def lp_refine(g, part, k, lmax_, rounds=25, dir_alternate=1):
+def lp_refine(g, part, k, lmax_, rounds=25, dir_alternate=1, active=False):
     torch = _torch()
     gs = _gstruct(g)
     P = part.to(dtype=torch.int32).clone().contiguous()
     st = LPStats()
-    _check(load().gp_lp_refine(ctypes.byref(gs), k, lmax_, rounds, dir_alternate, _ptr(P), ctypes.byref(st),
-                               _stream()))
+    _check(load().gp_lp_refine(ctypes.byref(gs), k, lmax_, rounds, _lp_flags(dir_alternate, active), _ptr(P),
+                               ctypes.byref(st), _stream()))
     return P, {"rounds_run": st.rounds_run, "moves": st.moves, "edge_visits": st.edge_visits, "ms": st.ms}
 
 

@@ -40,7 +40,11 @@ struct LPArgs {
     const int32_t *round;  // device round counter (rounds replay one captured launch sequence)
     const int64_t *capv;   // optional per-label capacity (batched graphs); null: every label has U
     const uint8_t *lab8;   // dense mode (<= 256 labels): byte copy of labels for the neighbour gathers
+    const uint8_t *act;    // active-set rounds: evaluations each vertex still owes (0: no proposal); null: all
 };
+
+// an inactive vertex makes no proposal: its edge range is taken as empty
+__device__ __forceinline__ bool inactive(const LPArgs &a, int32_t v) { return a.act && a.act[v] == 0; }
 
 __device__ __forceinline__ int64_t capof(const LPArgs &a, int32_t L) { return a.capv ? a.capv[L] : a.U; }
 
@@ -180,7 +184,8 @@ __global__ __launch_bounds__(kPropBlock) void k_propose_group(LPArgs a, const in
         const int64_t idx = wb + grp;
         const bool valid = idx < count;
         const int32_t v = valid ? verts[idx] : 0;
-        const int32_t beg = valid ? a.xadj[v] : 0, end = valid ? a.xadj[v + 1] : 0;
+        const int32_t beg = valid ? a.xadj[v] : 0;
+        const int32_t end = (valid && !inactive(a, v)) ? a.xadj[v + 1] : beg;
         const int32_t own = valid ? a.labels[v] : -1;
         AccT oc = 0;
         const int nch = (end - beg + GL - 1) / GL;
@@ -272,6 +277,7 @@ __global__ __launch_bounds__(BLOCK) void k_propose_block(LPArgs a, const int32_t
     for (; idx < count; idx += gridDim.x) {
         const int64_t nidx = idx + gridDim.x;
         const int32_t nv = nidx < count ? verts[nidx] : 0;
+        if (inactive(a, v)) end = beg;
         int lg = 6;
         while ((1 << lg) < 2 * (end - beg) && (1 << lg) < TBL) lg++;
         const uint32_t cap = 1u << lg;
@@ -353,6 +359,10 @@ __global__ __launch_bounds__(BLOCK) void k_propose_hub(LPArgs a, const int32_t *
     __shared__ int32_t tl[NW + 1];
     for (int64_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
         const int32_t v = verts[idx];
+        if (inactive(a, v)) {  // uniform per workgroup: its table stays empty
+            if (threadIdx.x == 0) a.prop[v] = -1;
+            continue;
+        }
         const int32_t beg = a.xadj[v], end = a.xadj[v + 1];
         const int32_t own = a.labels[v];
         const int lg = hlog[idx];
@@ -464,6 +474,7 @@ __global__ __launch_bounds__(kHubBlock) void k_hub_insert(LPArgs a, HubPlan hp) 
     __syncthreads();
     const int32_t h = hp.chunk_hub[blockIdx.x];
     const int32_t v = hp.hubs[h];
+    if (inactive(a, v)) return;  // uniform: nothing goes into the hub's table
     const int32_t own = a.labels[v];
     const int32_t beg = a.xadj[v] + (blockIdx.x - hp.chunk_first[h]) * kHubChunk;
     const int32_t end = min(a.xadj[v + 1], beg + kHubChunk);
@@ -506,6 +517,7 @@ __global__ __launch_bounds__(256) void k_hub_scan(LPArgs a, HubPlan hp) {
     const int32_t dmode = cur_dirmode(a);
     __shared__ unsigned long long tmp[256 / kWave + 1];
     const int32_t h = hp.slice_hub[blockIdx.x];
+    if (inactive(a, hp.hubs[h])) return;  // nothing was inserted; the table is already empty
     const uint32_t cap = 1u << hp.tlog[h];
     const uint32_t s0 = (uint32_t)(blockIdx.x - hp.slice_first[h]) * kHubSlice;
     const uint32_t s1 = min(cap, s0 + kHubSlice);
@@ -618,7 +630,8 @@ __global__ __launch_bounds__(kPropBlock) void k_dense_group(LPArgs a, int32_t nl
         const int64_t idx = wb + grp;
         const bool valid = idx < count;
         const int32_t v = valid ? verts[idx] : 0;
-        const int32_t beg = valid ? a.xadj[v] : 0, end = valid ? a.xadj[v + 1] : 0;
+        const int32_t beg = valid ? a.xadj[v] : 0;
+        const int32_t end = (valid && !inactive(a, v)) ? a.xadj[v + 1] : beg;
         const int32_t own = valid ? a.labels[v] : -1;
         AccT oc = 0;
         const int nch = (end - beg + GL - 1) / GL;
@@ -698,7 +711,9 @@ __global__ __launch_bounds__(256) void k_dense_chunk(LPArgs a, DenseBig db) {
     // the chunk's vertex and entry range come in one load (planned once per
     // call), so the edge loads wait on one load, not on three dependent ones
     const int4 d = db.desc[blockIdx.x];
-    const int32_t v = d.x, beg = d.y, end = d.z, b = d.w;
+    const int32_t v = d.x, beg = d.y, b = d.w;
+    if (inactive(a, v)) return;  // uniform: the vertex's row stays zero
+    const int32_t end = d.z;
     const int32_t own = a.labels[v];
     AccT oc = 0;
     constexpr int UC = 4;
@@ -786,7 +801,7 @@ int launch_dense(const LPArgs &a, int32_t nlabels, const int32_t *verts, const i
         GP_PROF_LAUNCH((std::string("k_dense_group<64") + sfx).c_str(), tb[5], s, hipLaunchKernelGGL((k_dense_group<64, KT, AccT>), dim3(blocks_for(c, NW)), dim3(kPropBlock), 0, s, a, nlabels,
                            lst(5), c));
     if (db && db->nbig > 0) {
-        GP_PROF_LAUNCH((std::string("k_dense_chunk<") + std::to_string(KT) + sfx.substr(std::to_string(KT).size() + 2)).c_str(), tb[6] + tb[7] + tb[8], s, hipLaunchKernelGGL((k_dense_chunk<KT, AccT>), dim3(nchunks), dim3(256), 0, s, a, *db));
+        GP_PROF_LAUNCH((std::string("k_dense_chunk<") + std::to_string(KT) + sfx.substr(std::to_string(KT).size() + 2)).c_str(), tb[6] + tb[7] + tb[8] + tb[9], s, hipLaunchKernelGGL((k_dense_chunk<KT, AccT>), dim3(nchunks), dim3(256), 0, s, a, *db));
         hipLaunchKernelGGL((k_dense_finish<KT, AccT>), dim3((db->nbig + 3) / 4), dim3(256), 0, s, a, *db, nlabels);
     }
     GP_LAUNCH_CHECK();
@@ -829,8 +844,10 @@ __global__ void k_chunk_desc(const int32_t *xadj, const int32_t *verts, const in
 // ---------------------------------------------------------------- tiers
 
 // Degree tiers. Tier 0: no neighbours (never proposes). Tiers 1..5: GL lanes
-// per vertex. Tier 6, 7: one workgroup per vertex. Tier 8: hub (global table).
-constexpr int kTiers = 9;
+// per vertex. Tiers 6, 7, 8: one workgroup per vertex (128, 256 and 1024
+// threads; the smaller ones fit more workgroups per CU). Tier 9: hub
+// (global table).
+constexpr int kTiers = 10;
 
 // Largest degree each hashed-table tier can hold (its table has 2x slots);
 // the tuned bounds may only be lower.
@@ -842,8 +859,9 @@ __host__ __device__ inline int32_t tier_cap(int t, bool wide) {
         case 3: return 16;
         case 4: return 64;
         case 5: return 256;
-        case 6: return 2048;
-        case 7: return wide ? 4096 : 8192;
+        case 6: return 1024;
+        case 7: return 2048;
+        case 8: return wide ? 4096 : 8192;
         default: return INT_MAX;
     }
 }
@@ -853,7 +871,7 @@ struct TierKey {
     const int32_t *active;  // optional: labels array, vertices with label < 0 go to tier 0
     const uint8_t *frozen;  // optional: vertices with frozen[v] != 0 go to tier 0 (keep their label)
     bool wide;
-    int32_t bound[kTiers];  // upper degree bound of each tier (non-decreasing, bound[8] = INT_MAX)
+    int32_t bound[kTiers];  // upper degree bound of each tier (non-decreasing, the last is INT_MAX)
 };
 
 __global__ void k_tier_keys(TierKey tk, int32_t n, uint32_t *key, int32_t *val, int32_t *counts,
@@ -940,7 +958,8 @@ __global__ void k_heads(const uint32_t *mk, const int32_t *nmov, int32_t *headpo
 
 __global__ void k_admit(const uint32_t *mk, const int32_t *mv, const int32_t *nmov, const int32_t *headpos,
                         const int64_t *S, const int64_t *W, int64_t U, const int64_t *capv, int32_t *labels,
-                        uint8_t *lab8, int32_t *oldlab, LPDev *dev, const int32_t *group, GroupState *gs) {
+                        uint8_t *lab8, int32_t *oldlab, LPDev *dev, const int32_t *group, GroupState *gs,
+                        uint8_t *act) {
     const int32_t n = *nmov;
     int32_t cnt = 0;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
@@ -957,6 +976,7 @@ __global__ void k_admit(const uint32_t *mk, const int32_t *mv, const int32_t *nm
             if (group) atomicAdd(&gs[group[v]].moves, 1);
         } else {
             oldlab[p] = -1;
+            if (act && act[mv[p]] == 0) act[mv[p]] = 1;  // refused by capacity: evaluated again
         }
     }
     cnt = wave_sum(cnt);
@@ -1005,6 +1025,48 @@ __global__ __launch_bounds__(256) void k_apply_w_small(const uint32_t *mk, const
     __syncthreads();
     for (int i = threadIdx.x; i < nl; i += blockDim.x)
         if (h[i]) atomicAdd((unsigned long long *)&W[i], h[i]);
+}
+
+// ---------------------------------------------------------------- active-set rounds
+// act[v] = evaluations v still owes (see k_act_step, k_admit, k_act_mark).
+
+__global__ void k_act_fill(uint8_t *act, int32_t n, uint8_t c) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        act[v] = c;
+}
+
+// After the proposals: count the edges of the vertices evaluated this round
+// and take one owed evaluation off each of them.
+__global__ __launch_bounds__(256) void k_act_step(const int32_t *xadj, int32_t n, uint8_t *act, LPDev *dev) {
+    __shared__ long long tmp[256 / kWave + 1];
+    if (dev->done) return;
+    long long vis = 0;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const uint8_t c = act[v];
+        if (c) {
+            vis += xadj[v + 1] - xadj[v];
+            act[v] = (uint8_t)(c - 1);
+        }
+    }
+    vis = block_sum<256>(vis, tmp);
+    if (threadIdx.x == 0 && vis) atomicAdd((unsigned long long *)&dev->visits, (unsigned long long)vis);
+}
+
+// After the admission: every neighbour of an admitted mover owes `renew`
+// evaluations. 16 lanes per mover.
+__global__ __launch_bounds__(256) void k_act_mark(const int32_t *mv, const int32_t *oldlab, const int32_t *nmov,
+                                                  const int32_t *xadj, const int32_t *adjncy, uint8_t *act,
+                                                  uint8_t renew) {
+    constexpr int GL = 16;
+    const int32_t n = *nmov;
+    const int gl = threadIdx.x % GL;
+    const int64_t step = (int64_t)gridDim.x * blockDim.x / GL;
+    for (int64_t p = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GL; p < n; p += step) {
+        if (oldlab[p] < 0) continue;
+        const int32_t v = mv[p];
+        const int32_t e1 = xadj[v + 1];
+        for (int32_t e = xadj[v] + gl; e < e1; e += GL) act[adjncy[e]] = renew;
+    }
 }
 
 __global__ void k_round_end_groups(GroupState *gs, int32_t ng) {
@@ -1070,7 +1132,7 @@ struct NoOut64 {
 template <typename AccT>
 int launch_proposals(const LPArgs &a, const int32_t *verts, const int64_t *tstart, const int32_t *hub_log,
                      const int64_t *hub_off, int32_t *gkey, AccT *gval, hipStream_t s, const double *tb,
-                     int32_t bound6, bool skip_hubs = false) {
+                     bool skip_hubs = false) {
     const char *acc = sizeof(AccT) == 4 ? "int" : "long";
     auto cnt = [&](int t) { return (int32_t)(tstart[t + 1] - tstart[t]); };
     auto lst = [&](int t) { return verts + tstart[t]; };
@@ -1099,23 +1161,20 @@ int launch_proposals(const LPArgs &a, const int32_t *verts, const int64_t *tstar
                            a, lst(5), c));
     }
     if ((c = cnt(6)) > 0) {
-        // a bound of at most 1024 fits 2048-slot tables: 128-thread
-        // workgroups of a quarter of the LDS, so more vertices are in flight
-        if (bound6 <= 1024) {
-            GP_PROF_LAUNCH((std::string("k_propose_block<128, 2048, ") + acc + ">").c_str(), tb[6], s, hipLaunchKernelGGL((k_propose_block<128, 2048, AccT>), dim3(grid_for(c, 1, 16384)), dim3(128), 0, s, a,
-                               lst(6), c));
-        } else {
-            GP_PROF_LAUNCH((std::string("k_propose_block<256, 4096, ") + acc + ">").c_str(), tb[6], s, hipLaunchKernelGGL((k_propose_block<256, 4096, AccT>), dim3(grid_for(c, 1, 8192)), dim3(256), 0, s, a,
-                               lst(6), c));
-        }
+        GP_PROF_LAUNCH((std::string("k_propose_block<128, 2048, ") + acc + ">").c_str(), tb[6], s, hipLaunchKernelGGL((k_propose_block<128, 2048, AccT>), dim3(grid_for(c, 1, 16384)), dim3(128), 0, s, a,
+                           lst(6), c));
     }
     if ((c = cnt(7)) > 0) {
-        constexpr int T7 = sizeof(AccT) == 4 ? 16384 : 8192;
-        GP_PROF_LAUNCH((std::string("k_propose_block<1024, ") + std::to_string(T7) + ", " + acc + ">").c_str(), tb[7], s, hipLaunchKernelGGL((k_propose_block<1024, T7, AccT>), dim3(grid_for(c, 1, 2048)), dim3(1024), 0, s, a,
+        GP_PROF_LAUNCH((std::string("k_propose_block<256, 4096, ") + acc + ">").c_str(), tb[7], s, hipLaunchKernelGGL((k_propose_block<256, 4096, AccT>), dim3(grid_for(c, 1, 8192)), dim3(256), 0, s, a,
                            lst(7), c));
     }
-    if (!skip_hubs && (c = cnt(8)) > 0) {
-        GP_PROF_LAUNCH((std::string("k_propose_hub<1024, ") + acc + ">").c_str(), tb[8], s, hipLaunchKernelGGL((k_propose_hub<1024, AccT>), dim3(c), dim3(1024), 0, s, a, lst(8), c, hub_off,
+    if ((c = cnt(8)) > 0) {
+        constexpr int T8 = sizeof(AccT) == 4 ? 16384 : 8192;
+        GP_PROF_LAUNCH((std::string("k_propose_block<1024, ") + std::to_string(T8) + ", " + acc + ">").c_str(), tb[8], s, hipLaunchKernelGGL((k_propose_block<1024, T8, AccT>), dim3(grid_for(c, 1, 2048)), dim3(1024), 0, s, a,
+                           lst(8), c));
+    }
+    if (!skip_hubs && (c = cnt(9)) > 0) {
+        GP_PROF_LAUNCH((std::string("k_propose_hub<1024, ") + acc + ">").c_str(), tb[9], s, hipLaunchKernelGGL((k_propose_hub<1024, AccT>), dim3(c), dim3(1024), 0, s, a, lst(9), c, hub_off,
                            hub_log, gkey, gval));
     }
     GP_LAUNCH_CHECK();
@@ -1149,8 +1208,8 @@ Tuning &tuning() {
 int set_tuning(const Tuning &t) {
     const int32_t *b = t.tier_max;
     const bool ok = b[0] >= tier_cap(3, false) && b[0] <= tier_cap(4, false) && b[1] >= b[0] &&
-                    b[1] <= tier_cap(5, false) && b[2] >= b[1] && b[2] <= tier_cap(6, false) && b[3] >= b[2] &&
-                    b[3] <= tier_cap(7, false) && t.dense_split >= 16 && t.dense_split <= (1 << 30) &&
+                    b[1] <= tier_cap(5, false) && b[2] >= b[1] && b[2] <= tier_cap(7, false) && b[3] >= b[2] &&
+                    b[3] <= tier_cap(8, false) && t.dense_split >= 16 && t.dense_split <= (1 << 30) &&
                     t.dense_chunk >= 256 && t.dense_chunk <= 65536 && t.dense_chunk % 256 == 0;
     if (!ok) {
         set_error("tuning: tier bounds must be non-decreasing within 16..64, ..256, ..2048, ..8192; dense_split in "
@@ -1190,7 +1249,7 @@ int label_weights(const DevGraph &g, const int32_t *labels, int64_t *W, int32_t 
 
 int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int64_t U, int32_t rounds,
            int32_t dir_alternate, bool wide, LPOut *out, Scratch &sc, const int64_t *capv, const uint8_t *frozen,
-           const int32_t *group, int32_t ngroups) {
+           const int32_t *group, int32_t ngroups, bool active) {
     hipStream_t s = sc.stream();
     const int32_t n = g.n;
     if (n == 0 || rounds == 0) {
@@ -1214,10 +1273,16 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
         const Tuning &tu = tuning();
         const bool dense_tiers = nlabels <= kDenseLabels;
         for (int t = 0; t < kTiers; t++) tk.bound[t] = tier_cap(t, wide);
-        for (int t = 4; t <= 7; t++) tk.bound[t] = std::min(tu.tier_max[t - 4], tier_cap(t, wide));
+        // tuned bounds: 32 lanes, 64 lanes, workgroups (split at 1024 between
+        // the 128- and 256-thread kernels), 1024-thread workgroups
+        tk.bound[4] = std::min(tu.tier_max[0], tier_cap(4, wide));
+        tk.bound[5] = std::min(tu.tier_max[1], tier_cap(5, wide));
+        tk.bound[6] = std::min(tu.tier_max[2], tier_cap(6, wide));
+        tk.bound[7] = std::min(tu.tier_max[2], tier_cap(7, wide));
+        tk.bound[8] = std::min(tu.tier_max[3], tier_cap(8, wide));
         if (dense_tiers) {  // dense tables have no degree limit: rows above the split are chunked
             tk.bound[5] = std::max(tk.bound[4], tu.dense_split);
-            tk.bound[6] = tk.bound[7] = tk.bound[5];
+            tk.bound[6] = tk.bound[7] = tk.bound[8] = tk.bound[5];
         }
         for (int t = 1; t < kTiers - 1; t++) tk.bound[t] = std::max(tk.bound[t], tk.bound[t - 1]);
     }
@@ -1392,6 +1457,14 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
         group = nullptr;
     }
     const int key_bits = bits_for(nlabels > 0 ? nlabels - 1 : 0);
+    // active-set rounds: every vertex starts owing one evaluation per direction
+    const uint8_t renew = dir_alternate ? 2 : 1;
+    uint8_t *act = nullptr;
+    if (active) {
+        GP_TRY(sc.alloc(&act, n));
+        hipLaunchKernelGGL(k_act_fill, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, act, n, renew);
+        GP_LAUNCH_CHECK();
+    }
 
     // One round = one fixed launch sequence; the round index lives on the
     // device. Round 0 runs eagerly (it also sizes every scratch slot), then
@@ -1417,22 +1490,27 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
         a.round = &dev->round;
         a.capv = capv;
         a.lab8 = lab8;
+        a.act = act;
         if (dense && wide)
             RT_TRY(launch_dense_any<int64_t>(a, nlabels, verts, tstart, &db, dchunks, s, tbytes));
         else if (dense)
             RT_TRY(launch_dense_any<int32_t>(a, nlabels, verts, tstart, &db, dchunks, s, tbytes));
         else if (wide)
             RT_TRY(launch_proposals<int64_t>(a, verts, tstart, hub_log, hub_off, gkey, (int64_t *)gval, s, tbytes,
-                                             tk.bound[6]));
+                                             false));
         else
             RT_TRY(launch_proposals<int32_t>(a, verts, tstart, hub_log, hub_off, gkey, (int32_t *)gval, s, tbytes,
-                                             tk.bound[6], split_hubs));
+                                             split_hubs));
         if (split_hubs) {
-            GP_PROF_LAUNCH("k_hub_insert", tbytes[8], s, hipLaunchKernelGGL(k_hub_insert, dim3(nchunks), dim3(kHubBlock), 0, s, a, hp));
+            GP_PROF_LAUNCH("k_hub_insert", tbytes[kTiers - 1], s, hipLaunchKernelGGL(k_hub_insert, dim3(nchunks), dim3(kHubBlock), 0, s, a, hp));
             hipLaunchKernelGGL(k_hub_scan<false>, dim3(nslices), dim3(256), 0, s, a, hp);
             hipLaunchKernelGGL(k_hub_decide<false>, dim3(grid_for(nh, 256, 1024)), dim3(256), 0, s, a, hp, nh);
             hipLaunchKernelGGL(k_hub_scan<true>, dim3(nslices), dim3(256), 0, s, a, hp);
             hipLaunchKernelGGL(k_hub_decide<true>, dim3(grid_for(nh, 256, 1024)), dim3(256), 0, s, a, hp, nh);
+            GP_LAUNCH_CHECK();
+        }
+        if (act) {
+            hipLaunchKernelGGL(k_act_step, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, g.xadj, n, act, dev);
             GP_LAUNCH_CHECK();
         }
         // compaction of movers (ascending vertex id)
@@ -1445,8 +1523,12 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
         GP_LAUNCH_CHECK();
         RT_TRY((scan<int64_t>(MoverWeight{v1, g.vwgt}, StoreIncl{S}, n, nmov, (int64_t *)nullptr, sc)));
         hipLaunchKernelGGL(k_admit, dim3(gb), dim3(256), 0, s, k1, v1, nmov, headpos, S, W, U, capv, labels, lab8, oldlab,
-                           dev, group, gstate);
+                           dev, group, gstate, act);
         GP_LAUNCH_CHECK();
+        if (act) {
+            hipLaunchKernelGGL(k_act_mark, dim3(gb), dim3(256), 0, s, v1, oldlab, nmov, g.xadj, g.adjncy, act, renew);
+            GP_LAUNCH_CHECK();
+        }
         if (nlabels <= kSmallLabels)
             hipLaunchKernelGGL(k_apply_w_small, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, k1, v1, nmov, oldlab,
                                g.vwgt, nlabels, W);
@@ -1493,6 +1575,7 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
         if (!out) return GP_OK;
         out->rounds_run = h.rounds_run;
         out->moves = h.total_moves;
+        out->visits = act ? h.visits : (int64_t)h.rounds_run * g.nnz;
         out->group_rounds.clear();
         out->group_moves.clear();
         if (group) {

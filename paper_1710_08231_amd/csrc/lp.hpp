@@ -20,11 +20,13 @@ struct LPDev {
     int32_t prev_moves;
     int32_t round_moves;
     int64_t total_moves;
+    int64_t visits;  // active-set rounds: edges of the evaluated vertices
 };
 
 struct LPOut {
     int32_t rounds_run = 0;
     int64_t moves = 0;
+    int64_t visits = 0;  // edge visits: rounds_run * nnz, or the active vertices' edges
     std::vector<int32_t> group_rounds;  // per group (when groups are given): its own rounds_run
     std::vector<int64_t> group_moves;
 };
@@ -42,9 +44,15 @@ struct LPOut {
 //  group/ngroups (optional): vertex groups (independent graphs of a batch);
 //  out->group_rounds[q] then holds the rounds group q alone would have run
 //  (two idle rounds in a row end a group; a group that went idle stays idle).
+//  active: active-set rounds (§III-A/§IV-A queues, made synchronous): a
+//  vertex is evaluated only while it owes evaluations; all start owing one
+//  per direction (2 with dir_alternate, else 1), each evaluation pays one,
+//  a proposal refused by capacity owes at least one more, and every
+//  neighbour of an admitted mover owes one per direction again.
 int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int64_t U, int32_t rounds,
            int32_t dir_alternate, bool wide, LPOut *out, Scratch &sc, const int64_t *capv = nullptr,
-           const uint8_t *frozen = nullptr, const int32_t *group = nullptr, int32_t ngroups = 0);
+           const uint8_t *frozen = nullptr, const int32_t *group = nullptr, int32_t ngroups = 0,
+           bool active = false);
 
 // Execution thresholds of the LP kernels. They choose which kernel serves a
 // vertex and how big vertices are split; results never depend on them.

@@ -232,7 +232,8 @@ static DevGraph dev_graph(const gp_graph *g) {
 
 static int check_params(const gp_params *pp, int32_t k, const char *who) {
     if (pp->rounds_coarsen < 0 || pp->rounds_refine < 0 || pp->attempts < 1 || pp->coarsest_per_k < 1 ||
-        pp->stall_den < 1 || pp->stall_num < 0 || (pp->init_mode != GP_INIT_PLAIN && pp->init_mode != GP_INIT_LEARNED)) {
+        pp->stall_den < 1 || pp->stall_num < 0 || (pp->init_mode != GP_INIT_PLAIN && pp->init_mode != GP_INIT_LEARNED) ||
+        (pp->active_set != 0 && pp->active_set != 1)) {
         set_error((std::string(who) + ": invalid parameters").c_str());
         return GP_ERR_ARG;
     }
@@ -334,9 +335,10 @@ static int do_partition(const gp_graph *gin, int32_t k, double eps, const gp_par
         GP_LAUNCH_CHECK();
         LPOut st;
         Timer t_lp(s);
-        GP_TRY(lp_run(f, labels, W, f.n, ucl, p->rounds_coarsen, p->dir_alternate, wide, &st, sc));
+        GP_TRY(lp_run(f, labels, W, f.n, ucl, p->rounds_coarsen, p->dir_alternate, wide, &st, sc, nullptr, nullptr,
+                      nullptr, 0, p->active_set != 0));
         const float ms_lp = t_lp.stop();
-        ev_c += (int64_t)st.rounds_run * f.nnz;
+        ev_c += st.visits;
         CoarseOut co;
         GP_TRY(sc.alloc(&co.xadj, (size_t)f.n + 1));
         GP_TRY(sc.alloc(&co.adjncy, f.nnz));
@@ -434,14 +436,14 @@ static int do_partition(const gp_graph *gin, int32_t k, double eps, const gp_par
         GP_TRY(label_weights(gl, Pl, B, k, sc));
         LPOut st;
         Timer t_lp(s);
-        GP_TRY(lp_run(gl, Pl, B, k, lmax, p->rounds_refine, p->dir_alternate, wide, &st, sc));
+        GP_TRY(lp_run(gl, Pl, B, k, lmax, p->rounds_refine, p->dir_alternate, wide, &st, sc, nullptr, nullptr, nullptr,
+                      0, p->active_set != 0));
         if (tracing()) {
             const float ms = t_lp.stop();
             std::fprintf(stderr, "[gp] refine level %zu n=%d nnz=%d %.3f ms (%d rounds, %lld moves, %.1f Gvisits/s)\n",
-                         l, gl.n, gl.nnz, ms, st.rounds_run, (long long)st.moves,
-                         (double)st.rounds_run * gl.nnz / (ms * 1e6));
+                         l, gl.n, gl.nnz, ms, st.rounds_run, (long long)st.moves, (double)st.visits / (ms * 1e6));
         }
-        ev_r += (int64_t)st.rounds_run * gl.nnz;
+        ev_r += st.visits;
         P = Pl;
     }
     const float ms_ref = t_ref.stop();
@@ -513,6 +515,7 @@ void gp_default_params(gp_params *p) {
     p->mpnn_max_n = 131072;
     p->mpnn_seed = 0;
     p->mpnn_params = nullptr;
+    p->active_set = 0;
 }
 
 int64_t gp_lmax(int64_t total_vwgt, int32_t k, double eps) {
@@ -520,11 +523,11 @@ int64_t gp_lmax(int64_t total_vwgt, int32_t k, double eps) {
     return lmax_of(total_vwgt, k, eps);
 }
 
-int gp_lp_cluster(const gp_graph *g, int64_t U, int32_t rounds, int32_t dir_alternate, int32_t *labels_out,
+int gp_lp_cluster(const gp_graph *g, int64_t U, int32_t rounds, int32_t flags, int32_t *labels_out,
                   gp_lp_stats *st_host, hipStream_t stream) {
     GP_TRY(check_graph_args(g));
-    if (U < 1 || rounds < 0 || !labels_out) {
-        set_error("lp_cluster: U < 1, rounds < 0 or labels_out is NULL");
+    if (U < 1 || rounds < 0 || !labels_out || (flags & ~(GP_LP_DIR_ALTERNATE | GP_LP_ACTIVE_SET))) {
+        set_error("lp_cluster: U < 1, rounds < 0, labels_out is NULL or unknown flags");
         return GP_ERR_ARG;
     }
     Scratch sc(stream);
@@ -542,12 +545,13 @@ int gp_lp_cluster(const gp_graph *g, int64_t U, int32_t rounds, int32_t dir_alte
         GP_LAUNCH_CHECK();
     }
     LPOut o;
-    GP_TRY(lp_run(d, labels_out, W, d.n, U, rounds, dir_alternate, tw >= (int64_t)INT_MAX, &o, sc));
+    GP_TRY(lp_run(d, labels_out, W, d.n, U, rounds, (flags & GP_LP_DIR_ALTERNATE) ? 1 : 0, tw >= (int64_t)INT_MAX, &o,
+                  sc, nullptr, nullptr, nullptr, 0, (flags & GP_LP_ACTIVE_SET) != 0));
     const float ms = t.stop();
     if (st_host) {
         st_host->rounds_run = o.rounds_run;
         st_host->moves = o.moves;
-        st_host->edge_visits = (int64_t)o.rounds_run * d.nnz;
+        st_host->edge_visits = o.visits;
         st_host->ms = ms;
     }
     sc.release();
@@ -555,11 +559,11 @@ int gp_lp_cluster(const gp_graph *g, int64_t U, int32_t rounds, int32_t dir_alte
     return GP_OK;
 }
 
-int gp_lp_refine(const gp_graph *g, int32_t k, int64_t lmax, int32_t rounds, int32_t dir_alternate,
+int gp_lp_refine(const gp_graph *g, int32_t k, int64_t lmax, int32_t rounds, int32_t flags,
                  int32_t *part_inout, gp_lp_stats *st_host, hipStream_t stream) {
     GP_TRY(check_graph_args(g));
-    if (k < 1 || lmax < 1 || rounds < 0 || !part_inout) {
-        set_error("lp_refine: k < 1, lmax < 1, rounds < 0 or part is NULL");
+    if (k < 1 || lmax < 1 || rounds < 0 || !part_inout || (flags & ~(GP_LP_DIR_ALTERNATE | GP_LP_ACTIVE_SET))) {
+        set_error("lp_refine: k < 1, lmax < 1, rounds < 0, part is NULL or unknown flags");
         return GP_ERR_ARG;
     }
     Scratch sc(stream);
@@ -588,12 +592,13 @@ int gp_lp_refine(const gp_graph *g, int32_t k, int64_t lmax, int32_t rounds, int
     GP_TRY(sc.alloc(&W, k));
     GP_TRY(label_weights(d, part_inout, W, k, sc));
     LPOut o;
-    GP_TRY(lp_run(d, part_inout, W, k, lmax, rounds, dir_alternate, tw >= (int64_t)INT_MAX, &o, sc));
+    GP_TRY(lp_run(d, part_inout, W, k, lmax, rounds, (flags & GP_LP_DIR_ALTERNATE) ? 1 : 0, tw >= (int64_t)INT_MAX, &o,
+                  sc, nullptr, nullptr, nullptr, 0, (flags & GP_LP_ACTIVE_SET) != 0));
     const float ms = t.stop();
     if (st_host) {
         st_host->rounds_run = o.rounds_run;
         st_host->moves = o.moves;
-        st_host->edge_visits = (int64_t)o.rounds_run * d.nnz;
+        st_host->edge_visits = o.visits;
         st_host->ms = ms;
     }
     sc.release();
@@ -721,6 +726,10 @@ int gp_coarsest_batch(const gp_graph *g, int32_t G, const int32_t *vtx_off_host,
         set_error("coarsest_batch: the learned initial partition is available for single graphs only");
         return GP_ERR_ARG;
     }
+    if (pp->active_set) {
+        set_error("coarsest_batch: active-set rounds are available for single graphs only");
+        return GP_ERR_ARG;
+    }
     Scratch sc(stream);
     const DevGraph d = dev_graph(g);
     GraphInfo gi;
@@ -841,6 +850,10 @@ int gp_partition_batch(const gp_graph *g, int32_t G, const int32_t *vtx_off_host
     GP_TRY(check_params(pp, 1, "partition_batch"));
     if (pp->init_mode != GP_INIT_PLAIN) {
         set_error("partition_batch: the learned initial partition is available for single graphs only");
+        return GP_ERR_ARG;
+    }
+    if (pp->active_set) {
+        set_error("partition_batch: active-set rounds are available for single graphs only");
         return GP_ERR_ARG;
     }
     Scratch sc(stream);
