@@ -97,8 +97,8 @@ typedef struct {
     int32_t mpnn_max_n;     /* 131072: the proposal is tried only on coarsest graphs this small */
     uint64_t mpnn_seed;     /* 0: seed of the network's probe features */
     const float *mpnn_params; /* NULL: device fp32 master weights, gp_mpnn_param_count(k) of them */
-    int32_t active_set;     /* 0; 1: coarsening and uncoarsening LP in active-set rounds (GP_LP_ACTIVE_SET);
-                               single graphs only */
+    int32_t active_set;     /* 0; bit 0: coarsening LP in active-set rounds (GP_LP_ACTIVE_SET), bit 1:
+                               uncoarsening LP (3: both); single graphs only */
 } gp_params;
 
 typedef struct {

@@ -598,10 +598,10 @@ typedef struct {
  *  - coarsen while n > coarsest_per_k * k; discard a level that did not
  *    shrink; stop after a level with stall_den * n' > stall_num * n.
  */
-/* LP flags of the coarsening and uncoarsening rounds (initial partitioning
- * always runs full rounds) */
+/* direction flag of the coarsening and uncoarsening rounds; active-set rounds
+ * are added per phase (initial partitioning always runs full rounds) */
 static int32_t lp_flags(const orc_params *p) {
-    return (p->dir_alternate ? ORC_LP_DIR_ALTERNATE : 0) | (p->active_set ? ORC_LP_ACTIVE_SET : 0);
+    return p->dir_alternate ? ORC_LP_DIR_ALTERNATE : 0;
 }
 
 static void coarsen(const orc_graph *g, int32_t k, double eps, const orc_params *p, hierarchy_t *h) {
@@ -649,7 +649,8 @@ static void coarsen(const orc_graph *g, int32_t k, double eps, const orc_params 
         int32_t *labels = (int32_t *)xcalloc((size_t)fn, sizeof(int32_t));
         orc_lp_stats st;
         if (p->lp_async) orc_lp_cluster_async(&f->g, ucl, p->rounds_coarsen, labels, &st);
-        else orc_lp_cluster(&f->g, ucl, p->rounds_coarsen, lp_flags(p), labels, &st);
+        else orc_lp_cluster(&f->g, ucl, p->rounds_coarsen,
+                            lp_flags(p) | ((p->active_set & 1) ? ORC_LP_ACTIVE_SET : 0), labels, &st);
         ev_cluster += st.edge_visits;
         c->xadj = (int32_t *)xcalloc((size_t)fn + 1, sizeof(int32_t));
         c->adjncy = (int32_t *)xcalloc((size_t)fnnz, sizeof(int32_t));
@@ -782,7 +783,8 @@ int orc_partition(const orc_graph *g, int32_t k, double eps, const orc_params *p
         }
         orc_lp_stats st;
         if (p->lp_async) orc_lp_refine_async(&lev[l].g, k, lmax, p->rounds_refine, P, &st);
-        else orc_lp_refine(&lev[l].g, k, lmax, p->rounds_refine, lp_flags(p), P, &st);
+        else orc_lp_refine(&lev[l].g, k, lmax, p->rounds_refine,
+                           lp_flags(p) | ((p->active_set & 2) ? ORC_LP_ACTIVE_SET : 0), P, &st);
         ev_refine += st.edge_visits;
     }
 

@@ -51,7 +51,7 @@ typedef struct {
     uint64_t mpnn_seed;       /* probe features */
     const float *mpnn_params; /* fp32 master weights (see orc_mpnn_param_count) */
     int32_t lp_async;         /* 0; 1: the paper's sequential LP (oracle-only comparison mode) */
-    int32_t active_set;       /* 0; 1: coarsening and uncoarsening LP in active-set rounds */
+    int32_t active_set;       /* 0; bit 0: coarsening LP in active-set rounds, bit 1: uncoarsening LP */
 } orc_params;
 
 /* LP flags (the former 0/1 direction argument is flag bit 0) */

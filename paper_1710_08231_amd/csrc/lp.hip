@@ -46,6 +46,14 @@ struct LPArgs {
 // an inactive vertex makes no proposal: its edge range is taken as empty
 __device__ __forceinline__ bool inactive(const LPArgs &a, int32_t v) { return a.act && a.act[v] == 0; }
 
+// Vertices of the degree tiers: tier t is verts[ts[t] .. ts[t+1]), both on the
+// device, so a recorded round can read lists rebuilt every round (active-set
+// rounds keep only the vertices that owe an evaluation).
+struct TierList {
+    const int32_t *verts;
+    const int64_t *ts;
+};
+
 __device__ __forceinline__ int64_t capof(const LPArgs &a, int32_t L) { return a.capv ? a.capv[L] : a.U; }
 
 // 0: any direction, 1: only smaller labels, 2: only larger labels
@@ -160,9 +168,11 @@ constexpr int kDenseLabels = 256;   // label counts handled with dense per-verte
 
 // GL lanes per vertex (GL <= 64), TBL table slots per vertex.
 template <int GL, int TBL, typename AccT>
-__global__ __launch_bounds__(kPropBlock) void k_propose_group(LPArgs a, const int32_t *__restrict__ verts,
-                                                              int32_t count) {
+__global__ __launch_bounds__(kPropBlock) void k_propose_group(LPArgs a, TierList lists, int tier) {
     if (*a.done) return;
+    const int64_t t0 = lists.ts[tier];
+    const int32_t count = (int32_t)(lists.ts[tier + 1] - t0);
+    const int32_t *__restrict__ verts = lists.verts + t0;
     const int32_t dmode = cur_dirmode(a);
     constexpr int GPW = kWave / GL;
     constexpr int NW = kPropBlock / kWave;
@@ -252,9 +262,11 @@ __global__ __launch_bounds__(kPropBlock) void k_propose_group(LPArgs a, const in
 // One workgroup per vertex, table in LDS sized to the vertex: next power of
 // two >= 2*deg (at most TBL), so scanning and clearing cost O(deg).
 template <int BLOCK, int TBL, typename AccT>
-__global__ __launch_bounds__(BLOCK) void k_propose_block(LPArgs a, const int32_t *__restrict__ verts,
-                                                         int32_t count) {
+__global__ __launch_bounds__(BLOCK) void k_propose_block(LPArgs a, TierList lists, int tier) {
     if (*a.done) return;
+    const int64_t t0 = lists.ts[tier];
+    const int32_t count = (int32_t)(lists.ts[tier + 1] - t0);
+    const int32_t *__restrict__ verts = lists.verts + t0;
     const int32_t dmode = cur_dirmode(a);
     constexpr int NW = BLOCK / kWave;
     constexpr int U4 = 4;
@@ -609,9 +621,11 @@ __global__ void k_hub_expand(const int32_t *first, const int32_t *num, int32_t n
 // and the k label weights of the round start sit in LDS, which lets the
 // capacity test run inside the single selection pass.
 template <int GL, int KT, typename AccT>
-__global__ __launch_bounds__(kPropBlock) void k_dense_group(LPArgs a, int32_t nlabels,
-                                                            const int32_t *__restrict__ verts, int32_t count) {
+__global__ __launch_bounds__(kPropBlock) void k_dense_group(LPArgs a, int32_t nlabels, TierList lists, int tier) {
     if (*a.done) return;
+    const int64_t t0 = lists.ts[tier];
+    const int32_t count = (int32_t)(lists.ts[tier + 1] - t0);
+    const int32_t *__restrict__ verts = lists.verts + t0;
     const int32_t dmode = cur_dirmode(a);
     constexpr int GPW = kWave / GL;
     constexpr int NW = kPropBlock / kWave;
@@ -775,11 +789,11 @@ __global__ __launch_bounds__(256) void k_dense_finish(LPArgs a, DenseBig db, int
 }
 
 template <int KT, typename AccT>
-int launch_dense(const LPArgs &a, int32_t nlabels, const int32_t *verts, const int64_t *tstart, const DenseBig *db,
+int launch_dense(const LPArgs &a, int32_t nlabels, const int64_t *tstart, TierList tl, const DenseBig *db,
                  int32_t nchunks, hipStream_t s, const double *tb) {
     const std::string sfx = std::string(", ") + std::to_string(KT) + ", " + (sizeof(AccT) == 4 ? "int" : "long") + ">";
+    // grids are sized by the full tier (an upper bound of the list the kernel reads)
     auto cnt = [&](int t) { return (int32_t)(tstart[t + 1] - tstart[t]); };
-    auto lst = [&](int t) { return verts + tstart[t]; };
     constexpr int NW = kPropBlock / kWave;
     constexpr int G1 = KT >= 256 ? 16 : 4;
     constexpr int G2 = KT >= 256 ? 16 : 8;
@@ -787,19 +801,19 @@ int launch_dense(const LPArgs &a, int32_t nlabels, const int32_t *verts, const i
     int32_t c;
     if ((c = cnt(1)) > 0)
         GP_PROF_LAUNCH((std::string("k_dense_group<") + std::to_string(G1) + sfx).c_str(), tb[1], s, hipLaunchKernelGGL((k_dense_group<G1, KT, AccT>), dim3(blocks_for(c, NW * (kWave / G1))), dim3(kPropBlock), 0,
-                           s, a, nlabels, lst(1), c));
+                           s, a, nlabels, tl, 1));
     if ((c = cnt(2)) > 0)
         GP_PROF_LAUNCH((std::string("k_dense_group<") + std::to_string(G2) + sfx).c_str(), tb[2], s, hipLaunchKernelGGL((k_dense_group<G2, KT, AccT>), dim3(blocks_for(c, NW * (kWave / G2))), dim3(kPropBlock), 0,
-                           s, a, nlabels, lst(2), c));
+                           s, a, nlabels, tl, 2));
     if ((c = cnt(3)) > 0)
         GP_PROF_LAUNCH((std::string("k_dense_group<16") + sfx).c_str(), tb[3], s, hipLaunchKernelGGL((k_dense_group<16, KT, AccT>), dim3(blocks_for(c, NW * 4)), dim3(kPropBlock), 0, s, a,
-                           nlabels, lst(3), c));
+                           nlabels, tl, 3));
     if ((c = cnt(4)) > 0)
         GP_PROF_LAUNCH((std::string("k_dense_group<32") + sfx).c_str(), tb[4], s, hipLaunchKernelGGL((k_dense_group<32, KT, AccT>), dim3(blocks_for(c, NW * 2)), dim3(kPropBlock), 0, s, a,
-                           nlabels, lst(4), c));
+                           nlabels, tl, 4));
     if ((c = cnt(5)) > 0)
         GP_PROF_LAUNCH((std::string("k_dense_group<64") + sfx).c_str(), tb[5], s, hipLaunchKernelGGL((k_dense_group<64, KT, AccT>), dim3(blocks_for(c, NW)), dim3(kPropBlock), 0, s, a, nlabels,
-                           lst(5), c));
+                           tl, 5));
     if (db && db->nbig > 0) {
         GP_PROF_LAUNCH((std::string("k_dense_chunk<") + std::to_string(KT) + sfx.substr(std::to_string(KT).size() + 2)).c_str(), tb[6] + tb[7] + tb[8] + tb[9], s, hipLaunchKernelGGL((k_dense_chunk<KT, AccT>), dim3(nchunks), dim3(256), 0, s, a, *db));
         hipLaunchKernelGGL((k_dense_finish<KT, AccT>), dim3((db->nbig + 3) / 4), dim3(256), 0, s, a, *db, nlabels);
@@ -809,11 +823,11 @@ int launch_dense(const LPArgs &a, int32_t nlabels, const int32_t *verts, const i
 }
 
 template <typename AccT>
-int launch_dense_any(const LPArgs &a, int32_t nlabels, const int32_t *verts, const int64_t *tstart,
-                     const DenseBig *db, int32_t nchunks, hipStream_t s, const double *tb) {
-    if (nlabels <= 16) return launch_dense<16, AccT>(a, nlabels, verts, tstart, db, nchunks, s, tb);
-    if (nlabels <= 64) return launch_dense<64, AccT>(a, nlabels, verts, tstart, db, nchunks, s, tb);
-    return launch_dense<256, AccT>(a, nlabels, verts, tstart, db, nchunks, s, tb);
+int launch_dense_any(const LPArgs &a, int32_t nlabels, const int64_t *tstart, TierList tl, const DenseBig *db,
+                     int32_t nchunks, hipStream_t s, const double *tb) {
+    if (nlabels <= 16) return launch_dense<16, AccT>(a, nlabels, tstart, tl, db, nchunks, s, tb);
+    if (nlabels <= 64) return launch_dense<64, AccT>(a, nlabels, tstart, tl, db, nchunks, s, tb);
+    return launch_dense<256, AccT>(a, nlabels, tstart, tl, db, nchunks, s, tb);
 }
 
 __global__ void k_labels_u8(const int32_t *labels, int32_t n, uint8_t *lab8) {
@@ -1036,9 +1050,12 @@ __global__ void k_act_fill(uint8_t *act, int32_t n, uint8_t c) {
 }
 
 // After the proposals: count the edges of the vertices evaluated this round
-// and take one owed evaluation off each of them.
-__global__ __launch_bounds__(256) void k_act_step(const int32_t *xadj, int32_t n, uint8_t *act, LPDev *dev) {
+// and take one owed evaluation off each of them. The others were not in the
+// round's lists: their proposal is cleared here.
+__global__ __launch_bounds__(256) void k_act_step(const int32_t *xadj, int32_t n, uint8_t *act, int32_t *prop,
+                                                  LPDev *dev, int32_t *nbig) {
     __shared__ long long tmp[256 / kWave + 1];
+    if (blockIdx.x == 0 && threadIdx.x == 0) *nbig = 0;  // the round's list of big movers starts empty
     if (dev->done) return;
     long long vis = 0;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
@@ -1046,6 +1063,8 @@ __global__ __launch_bounds__(256) void k_act_step(const int32_t *xadj, int32_t n
         if (c) {
             vis += xadj[v + 1] - xadj[v];
             act[v] = (uint8_t)(c - 1);
+        } else {
+            prop[v] = -1;
         }
     }
     vis = block_sum<256>(vis, tmp);
@@ -1053,10 +1072,14 @@ __global__ __launch_bounds__(256) void k_act_step(const int32_t *xadj, int32_t n
 }
 
 // After the admission: every neighbour of an admitted mover owes `renew`
-// evaluations. 16 lanes per mover.
+// evaluations. 16 lanes per mover; a mover above kMarkSplit neighbours is
+// queued instead as chunks of kMarkChunk entries (list `big`, count `nbig`),
+// which k_act_mark_big spreads over whole workgroups.
+constexpr int kMarkSplit = 256;
+constexpr int kMarkChunk = 4096;
 __global__ __launch_bounds__(256) void k_act_mark(const int32_t *mv, const int32_t *oldlab, const int32_t *nmov,
                                                   const int32_t *xadj, const int32_t *adjncy, uint8_t *act,
-                                                  uint8_t renew) {
+                                                  uint8_t renew, int2 *big, int32_t *nbig) {
     constexpr int GL = 16;
     const int32_t n = *nmov;
     const int gl = threadIdx.x % GL;
@@ -1064,9 +1087,72 @@ __global__ __launch_bounds__(256) void k_act_mark(const int32_t *mv, const int32
     for (int64_t p = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GL; p < n; p += step) {
         if (oldlab[p] < 0) continue;
         const int32_t v = mv[p];
-        const int32_t e1 = xadj[v + 1];
-        for (int32_t e = xadj[v] + gl; e < e1; e += GL) act[adjncy[e]] = renew;
+        const int32_t e0 = xadj[v], e1 = xadj[v + 1];
+        if (e1 - e0 > kMarkSplit) {
+            if (gl == 0) {
+                const int32_t nc = (e1 - e0 + kMarkChunk - 1) / kMarkChunk;
+                const int32_t at = atomicAdd(nbig, nc);
+                for (int32_t q = 0; q < nc; q++) big[at + q] = make_int2(v, e0 + q * kMarkChunk);
+            }
+            continue;
+        }
+        for (int32_t e = e0 + gl; e < e1; e += GL) act[adjncy[e]] = renew;
     }
+}
+
+__global__ __launch_bounds__(256) void k_act_mark_big(const int2 *big, const int32_t *nbig, const int32_t *xadj,
+                                                      const int32_t *adjncy, uint8_t *act, uint8_t renew) {
+    const int32_t nb = *nbig;
+    for (int64_t i = blockIdx.x; i < nb; i += gridDim.x) {
+        const int2 c = big[i];
+        const int32_t e1 = min(xadj[c.x + 1], c.y + kMarkChunk);
+        for (int32_t e = c.y + threadIdx.x; e < e1; e += 256) act[adjncy[e]] = renew;
+    }
+}
+
+// Active-set rounds: each round's tier lists keep the vertices that owe an
+// evaluation (compaction in tier order, then the tier starts by binary search).
+struct TierStarts {
+    int64_t s[kTiers + 1];
+};
+__global__ void k_set_starts(TierStarts h, int64_t *ts) {
+    if (threadIdx.x <= kTiers) ts[threadIdx.x] = h.s[threadIdx.x];
+}
+struct ActFlag {
+    const int32_t *verts;
+    const uint8_t *act;
+    const int32_t *done;
+    __device__ bool operator()(int64_t i) const { return !*done && act[verts[i]] > 0; }
+};
+struct ActEmit {
+    const int32_t *verts;  // full tier-ordered list
+    int32_t *averts;
+    uint8_t *atier;
+    TierStarts ts;
+    int64_t first;  // list entries before `first` (tier 0) are not scanned
+    __device__ void operator()(int64_t i, int32_t pos) const {
+        const int64_t j = first + i;
+        averts[pos] = verts[j];
+        int t = 1;
+        while (t < kTiers - 1 && j >= ts.s[t + 1]) t++;
+        atier[pos] = (uint8_t)t;
+    }
+};
+__global__ void k_act_bounds(const uint8_t *atier, const int32_t *count, int64_t *ts) {
+    const int t = threadIdx.x;
+    if (t > kTiers) return;
+    const int32_t c = *count;
+    if (t == kTiers) {
+        ts[t] = c;
+        return;
+    }
+    int32_t lo = 0, hi = c;  // first position whose tier is >= t
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if ((int)atier[mid] < t) lo = mid + 1;
+        else hi = mid;
+    }
+    ts[t] = lo;
 }
 
 __global__ void k_round_end_groups(GroupState *gs, int32_t ng) {
@@ -1130,9 +1216,9 @@ struct NoOut64 {
 };
 
 template <typename AccT>
-int launch_proposals(const LPArgs &a, const int32_t *verts, const int64_t *tstart, const int32_t *hub_log,
-                     const int64_t *hub_off, int32_t *gkey, AccT *gval, hipStream_t s, const double *tb,
-                     bool skip_hubs = false) {
+int launch_proposals(const LPArgs &a, const int32_t *verts, const int64_t *tstart, TierList tl,
+                     const int32_t *hub_log, const int64_t *hub_off, int32_t *gkey, AccT *gval, hipStream_t s,
+                     const double *tb, bool skip_hubs = false) {
     const char *acc = sizeof(AccT) == 4 ? "int" : "long";
     auto cnt = [&](int t) { return (int32_t)(tstart[t + 1] - tstart[t]); };
     auto lst = [&](int t) { return verts + tstart[t]; };
@@ -1142,36 +1228,36 @@ int launch_proposals(const LPArgs &a, const int32_t *verts, const int64_t *tstar
     int32_t c;
     if ((c = cnt(1)) > 0) {
         GP_PROF_LAUNCH((std::string("k_propose_group<4, 8, ") + acc + ">").c_str(), tb[1], s, hipLaunchKernelGGL((k_propose_group<4, 8, AccT>), dim3(blocks_for(c, NW * 16)), dim3(kPropBlock), 0, s,
-                           a, lst(1), c));
+                           a, tl, 1));
     }
     if ((c = cnt(2)) > 0) {
         GP_PROF_LAUNCH((std::string("k_propose_group<8, 16, ") + acc + ">").c_str(), tb[2], s, hipLaunchKernelGGL((k_propose_group<8, 16, AccT>), dim3(blocks_for(c, NW * 8)), dim3(kPropBlock), 0, s,
-                           a, lst(2), c));
+                           a, tl, 2));
     }
     if ((c = cnt(3)) > 0) {
         GP_PROF_LAUNCH((std::string("k_propose_group<16, 32, ") + acc + ">").c_str(), tb[3], s, hipLaunchKernelGGL((k_propose_group<16, 32, AccT>), dim3(blocks_for(c, NW * 4)), dim3(kPropBlock), 0,
-                           s, a, lst(3), c));
+                           s, a, tl, 3));
     }
     if ((c = cnt(4)) > 0) {
         GP_PROF_LAUNCH((std::string("k_propose_group<32, 128, ") + acc + ">").c_str(), tb[4], s, hipLaunchKernelGGL((k_propose_group<32, 128, AccT>), dim3(blocks_for(c, NW * 2)), dim3(kPropBlock), 0,
-                           s, a, lst(4), c));
+                           s, a, tl, 4));
     }
     if ((c = cnt(5)) > 0) {
         GP_PROF_LAUNCH((std::string("k_propose_group<64, 512, ") + acc + ">").c_str(), tb[5], s, hipLaunchKernelGGL((k_propose_group<64, 512, AccT>), dim3(blocks_for(c, NW)), dim3(kPropBlock), 0, s,
-                           a, lst(5), c));
+                           a, tl, 5));
     }
     if ((c = cnt(6)) > 0) {
         GP_PROF_LAUNCH((std::string("k_propose_block<128, 2048, ") + acc + ">").c_str(), tb[6], s, hipLaunchKernelGGL((k_propose_block<128, 2048, AccT>), dim3(grid_for(c, 1, 16384)), dim3(128), 0, s, a,
-                           lst(6), c));
+                           tl, 6));
     }
     if ((c = cnt(7)) > 0) {
         GP_PROF_LAUNCH((std::string("k_propose_block<256, 4096, ") + acc + ">").c_str(), tb[7], s, hipLaunchKernelGGL((k_propose_block<256, 4096, AccT>), dim3(grid_for(c, 1, 8192)), dim3(256), 0, s, a,
-                           lst(7), c));
+                           tl, 7));
     }
     if ((c = cnt(8)) > 0) {
         constexpr int T8 = sizeof(AccT) == 4 ? 16384 : 8192;
         GP_PROF_LAUNCH((std::string("k_propose_block<1024, ") + std::to_string(T8) + ", " + acc + ">").c_str(), tb[8], s, hipLaunchKernelGGL((k_propose_block<1024, T8, AccT>), dim3(grid_for(c, 1, 2048)), dim3(1024), 0, s, a,
-                           lst(8), c));
+                           tl, 8));
     }
     if (!skip_hubs && (c = cnt(9)) > 0) {
         GP_PROF_LAUNCH((std::string("k_propose_hub<1024, ") + acc + ">").c_str(), tb[9], s, hipLaunchKernelGGL((k_propose_hub<1024, AccT>), dim3(c), dim3(1024), 0, s, a, lst(9), c, hub_off,
@@ -1310,6 +1396,28 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
     double tbytes[kTiers + 1];
     for (int t = 0; t < kTiers; t++) tbytes[t] = (double)hedge[t] * per_edge + (double)hcnt[t] * per_vertex;
     tbytes[kTiers] = 0;
+
+    // the tier starts on the device; in active-set rounds the kernels read
+    // per-round lists of the vertices that owe an evaluation instead
+    int64_t *ts_dev = nullptr;
+    GP_TRY(sc.alloc(&ts_dev, kTiers + 1));
+    TierStarts tsh;
+    for (int t = 0; t <= kTiers; t++) tsh.s[t] = tstart[t];
+    hipLaunchKernelGGL(k_set_starts, dim3(1), dim3(64), 0, s, tsh, ts_dev);
+    GP_LAUNCH_CHECK();
+    TierList tl{verts, ts_dev};
+    int32_t *averts = nullptr, *acount = nullptr;
+    uint8_t *atier = nullptr;
+    int64_t *ats = nullptr;
+    const int64_t afirst = tstart[1];
+    if (active) {
+        GP_TRY(sc.alloc(&averts, n));
+        GP_TRY(sc.alloc(&atier, n));
+        GP_TRY(sc.alloc(&acount, 1));
+        GP_TRY(sc.alloc(&ats, kTiers + 1));
+        GP_HIP(hipMemsetAsync(ats, 0, sizeof(int64_t) * (kTiers + 1), s));
+        tl = TierList{averts, ats};
+    }
 
     // ---- hub tables (hashed tables only; dense tables need none)
     const bool dense = nlabels <= kDenseLabels;
@@ -1460,8 +1568,15 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
     // active-set rounds: every vertex starts owing one evaluation per direction
     const uint8_t renew = dir_alternate ? 2 : 1;
     uint8_t *act = nullptr;
+    int2 *mbig = nullptr;
+    int32_t *nmbig = nullptr;
     if (active) {
         GP_TRY(sc.alloc(&act, n));
+        // chunks of the movers above kMarkSplit neighbours: at most
+        // nnz / kMarkChunk + nnz / kMarkSplit of them
+        GP_TRY(sc.alloc(&mbig, (size_t)g.nnz / kMarkChunk + (size_t)g.nnz / kMarkSplit + 1));
+        GP_TRY(sc.alloc(&nmbig, 1));
+        GP_HIP(hipMemsetAsync(nmbig, 0, sizeof(int32_t), s));
         hipLaunchKernelGGL(k_act_fill, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, act, n, renew);
         GP_LAUNCH_CHECK();
     }
@@ -1491,16 +1606,22 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
         a.capv = capv;
         a.lab8 = lab8;
         a.act = act;
+        if (act && afirst < n) {
+            RT_TRY(compact(ActFlag{verts + afirst, act, &dev->done}, ActEmit{verts, averts, atier, tsh, afirst},
+                           n - afirst, nullptr, acount, sc));
+            hipLaunchKernelGGL(k_act_bounds, dim3(1), dim3(64), 0, s, atier, acount, ats);
+            GP_LAUNCH_CHECK();
+        }
         if (dense && wide)
-            RT_TRY(launch_dense_any<int64_t>(a, nlabels, verts, tstart, &db, dchunks, s, tbytes));
+            RT_TRY(launch_dense_any<int64_t>(a, nlabels, tstart, tl, &db, dchunks, s, tbytes));
         else if (dense)
-            RT_TRY(launch_dense_any<int32_t>(a, nlabels, verts, tstart, &db, dchunks, s, tbytes));
+            RT_TRY(launch_dense_any<int32_t>(a, nlabels, tstart, tl, &db, dchunks, s, tbytes));
         else if (wide)
-            RT_TRY(launch_proposals<int64_t>(a, verts, tstart, hub_log, hub_off, gkey, (int64_t *)gval, s, tbytes,
-                                             false));
+            RT_TRY(launch_proposals<int64_t>(a, verts, tstart, tl, hub_log, hub_off, gkey, (int64_t *)gval, s,
+                                             tbytes, false));
         else
-            RT_TRY(launch_proposals<int32_t>(a, verts, tstart, hub_log, hub_off, gkey, (int32_t *)gval, s, tbytes,
-                                             split_hubs));
+            RT_TRY(launch_proposals<int32_t>(a, verts, tstart, tl, hub_log, hub_off, gkey, (int32_t *)gval, s,
+                                             tbytes, split_hubs));
         if (split_hubs) {
             GP_PROF_LAUNCH("k_hub_insert", tbytes[kTiers - 1], s, hipLaunchKernelGGL(k_hub_insert, dim3(nchunks), dim3(kHubBlock), 0, s, a, hp));
             hipLaunchKernelGGL(k_hub_scan<false>, dim3(nslices), dim3(256), 0, s, a, hp);
@@ -1510,7 +1631,8 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
             GP_LAUNCH_CHECK();
         }
         if (act) {
-            hipLaunchKernelGGL(k_act_step, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, g.xadj, n, act, dev);
+            hipLaunchKernelGGL(k_act_step, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, g.xadj, n, act, prop, dev,
+                               nmbig);
             GP_LAUNCH_CHECK();
         }
         // compaction of movers (ascending vertex id)
@@ -1526,7 +1648,10 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
                            dev, group, gstate, act);
         GP_LAUNCH_CHECK();
         if (act) {
-            hipLaunchKernelGGL(k_act_mark, dim3(gb), dim3(256), 0, s, v1, oldlab, nmov, g.xadj, g.adjncy, act, renew);
+            hipLaunchKernelGGL(k_act_mark, dim3(gb), dim3(256), 0, s, v1, oldlab, nmov, g.xadj, g.adjncy, act, renew,
+                               mbig, nmbig);
+            hipLaunchKernelGGL(k_act_mark_big, dim3(grid_for(g.nnz / kMarkChunk + 1, 1, 4096)), dim3(256), 0, s, mbig,
+                               nmbig, g.xadj, g.adjncy, act, renew);
             GP_LAUNCH_CHECK();
         }
         if (nlabels <= kSmallLabels)

@@ -233,7 +233,7 @@ static DevGraph dev_graph(const gp_graph *g) {
 static int check_params(const gp_params *pp, int32_t k, const char *who) {
     if (pp->rounds_coarsen < 0 || pp->rounds_refine < 0 || pp->attempts < 1 || pp->coarsest_per_k < 1 ||
         pp->stall_den < 1 || pp->stall_num < 0 || (pp->init_mode != GP_INIT_PLAIN && pp->init_mode != GP_INIT_LEARNED) ||
-        (pp->active_set != 0 && pp->active_set != 1)) {
+        pp->active_set < 0 || pp->active_set > 3) {
         set_error((std::string(who) + ": invalid parameters").c_str());
         return GP_ERR_ARG;
     }
@@ -336,7 +336,7 @@ static int do_partition(const gp_graph *gin, int32_t k, double eps, const gp_par
         LPOut st;
         Timer t_lp(s);
         GP_TRY(lp_run(f, labels, W, f.n, ucl, p->rounds_coarsen, p->dir_alternate, wide, &st, sc, nullptr, nullptr,
-                      nullptr, 0, p->active_set != 0));
+                      nullptr, 0, (p->active_set & 1) != 0));
         const float ms_lp = t_lp.stop();
         ev_c += st.visits;
         CoarseOut co;
@@ -437,7 +437,7 @@ static int do_partition(const gp_graph *gin, int32_t k, double eps, const gp_par
         LPOut st;
         Timer t_lp(s);
         GP_TRY(lp_run(gl, Pl, B, k, lmax, p->rounds_refine, p->dir_alternate, wide, &st, sc, nullptr, nullptr, nullptr,
-                      0, p->active_set != 0));
+                      0, (p->active_set & 2) != 0));
         if (tracing()) {
             const float ms = t_lp.stop();
             std::fprintf(stderr, "[gp] refine level %zu n=%d nnz=%d %.3f ms (%d rounds, %lld moves, %.1f Gvisits/s)\n",

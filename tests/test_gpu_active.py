@@ -127,12 +127,14 @@ def test_active_under_tuning(tuning):
         gp.set_tuning(None)
 
 
+@pytest.mark.parametrize("mode", [1, 2, 3])
 @pytest.mark.parametrize("name,k", [("rgg16k", 2), ("rmat12", 16), ("rmat16", 16), ("grid", 8), ("weighted", 5),
                                     ("star_hub", 4), ("rgg16k", 64)])
-def test_active_partition_matches_oracle(dev_cases, name, k):
+def test_active_partition_matches_oracle(dev_cases, name, k, mode):
+    # mode: bit 0 coarsening, bit 1 refinement in active-set rounds
     g = CASES[name]
-    p, r = gp.partition(dev_cases[name], k, 0.03, active_set=1)
-    op, ores = oracle.partition(g, k, active_set=1)
+    p, r = gp.partition(dev_cases[name], k, 0.03, active_set=mode)
+    op, ores = oracle.partition(g, k, active_set=mode)
     assert np.array_equal(_np(p), op)
     for key in ("cut", "max_block_w", "levels", "coarsest_n", "edge_visits_cluster", "edge_visits_refine"):
         assert r[key] == ores[key], key

@@ -105,6 +105,11 @@ def test_active_invariants(dirs):
     B = np.bincount(P, minlength=8)
     assert B.sum() == n and B.max() <= max(lm, np.bincount(part, minlength=8).max())
     assert st["edge_visits"] <= st["rounds_run"] * nnz
-    # a partition in active-set mode is valid and balanced
-    p, r = oracle.partition(g, 8, active_set=1)
-    assert r["balanced"] == 1 and oracle.cut(g, p) == r["cut"]
+    # a partition in active-set mode (coarsening, refinement, both) is valid and balanced
+    full = oracle.partition(g, 8)[1]
+    for mode in (1, 2, 3):
+        p, r = oracle.partition(g, 8, active_set=mode)
+        assert r["balanced"] == 1 and oracle.cut(g, p) == r["cut"]
+        if mode == 2:  # coarsening unchanged, so the hierarchy is the same
+            assert (r["levels"], r["edge_visits_cluster"]) == (full["levels"], full["edge_visits_cluster"])
+            assert r["edge_visits_refine"] <= full["edge_visits_refine"]
