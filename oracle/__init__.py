@@ -39,7 +39,7 @@ class _Params(ctypes.Structure):
                 ("dir_alternate", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("init_mode", ctypes.c_int32), ("mpnn_max_n", ctypes.c_int32),
                 ("mpnn_seed", ctypes.c_uint64), ("mpnn_params", ctypes.POINTER(ctypes.c_float)),
-                ("lp_async", ctypes.c_int32), ("active_set", ctypes.c_int32)]
+                ("lp_async", ctypes.c_int32), ("active_set", ctypes.c_int32), ("mls", ctypes.c_int32)]
 
 
 class _Result(ctypes.Structure):
@@ -59,7 +59,7 @@ def build_lib():
     tmp = _LIB_PATH + ".tmp"
     subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-Wall", "-std=gnu11",
                            "-ffp-contract=off", "-o", tmp, os.path.join(_HERE, "oracle.c"),
-                           os.path.join(_HERE, "mpnn.c"), "-lm"])
+                           os.path.join(_HERE, "mpnn.c"), os.path.join(_HERE, "mls.c"), "-lm"])
     os.replace(tmp, _LIB_PATH)
 
 
@@ -179,6 +179,41 @@ def lp_refine(g, part, k, lmax_, rounds=25, dir_alternate=1, active=False):
     return P, {"rounds_run": st.rounds_run, "moves": st.moves, "edge_visits": st.edge_visits}
 
 
+class _MLSStats(ctypes.Structure):
+    _fields_ = [("gain", ctypes.c_int64), ("searches", ctypes.c_int64), ("moves", ctypes.c_int64),
+                ("local_iters", ctypes.c_int64)]
+
+
+def mls(g, part, k, lmax_, seed=0, global_iters=3, alpha=0.1, max_idle=50):
+    """§III-C multi-try local search from a partition (oracle-only); returns (part', stats)."""
+    G = _G(g)
+    P = _i32(part).copy()
+    st = _MLSStats()
+    lib = _load()
+    lib.orc_mls.restype = ctypes.c_int64
+    lib.orc_mls.argtypes = [ctypes.POINTER(_Graph), ctypes.c_int32, ctypes.c_int64, I32P, ctypes.c_uint64,
+                            ctypes.c_int32, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(_MLSStats)]
+    lib.orc_mls(G.ref, k, lmax_, _p32(P), seed, global_iters, alpha, max_idle, ctypes.byref(st))
+    return P, {f: getattr(st, f) for f, _ in _MLSStats._fields_}
+
+
+def mls_gain(g, part, k, lmax_, v):
+    """(gain, target) of moving v to its best feasible adjacent block (target -1: none)."""
+    G = _G(g)
+    P = _i32(part)
+    B = np.zeros(k, np.int64)
+    vw = g.get("vwgt")
+    np.add.at(B, P, vw.astype(np.int64) if vw is not None else 1)
+    t = ctypes.c_int32(-1)
+    lib = _load()
+    lib.orc_mls_gain.restype = ctypes.c_int64
+    lib.orc_mls_gain.argtypes = [ctypes.POINTER(_Graph), I32P, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32,
+                                 ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    gn = lib.orc_mls_gain(G.ref, _p32(P), B.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), k, lmax_, v,
+                          ctypes.byref(t))
+    return int(gn), int(t.value)
+
+
 def lp_cluster_async(g, U, rounds=10):
     """The paper's sequential LP clustering (oracle-only comparison mode)."""
     G = _G(g)
@@ -272,7 +307,7 @@ def fill_isolated(g, k, part, B):
 
 DEFAULT_PARAMS = dict(rounds_coarsen=10, rounds_refine=25, coarsest_per_k=60, attempts=4,
                       stall_num=19, stall_den=20, dir_alternate=1, seed=0, init_mode=0,
-                      mpnn_max_n=131072, mpnn_seed=0, mpnn_params=None, lp_async=0, active_set=0)
+                      mpnn_max_n=131072, mpnn_seed=0, mpnn_params=None, lp_async=0, active_set=0, mls=0)
 
 
 def _params(params):

@@ -52,7 +52,22 @@ typedef struct {
     const float *mpnn_params; /* fp32 master weights (see orc_mpnn_param_count) */
     int32_t lp_async;         /* 0; 1: the paper's sequential LP (oracle-only comparison mode) */
     int32_t active_set;       /* 0; bit 0: coarsening LP in active-set rounds, bit 1: uncoarsening LP */
+    int32_t mls;              /* 0; g > 0: multi-try local search (g global iterations) after each level's
+                                 LP refinement (oracle-only comparison mode) */
 } orc_params;
+
+/* §III-C multi-try k-way local search (sequential, oracle-only; readings in mls.c) */
+typedef struct {
+    int64_t gain;        /* cut reduction */
+    int64_t searches;    /* searches started */
+    int64_t moves;       /* moves kept (best prefixes) */
+    int64_t local_iters; /* local iterations over all global iterations */
+} orc_mls_stats;
+int64_t orc_mls(const orc_graph *g, int32_t k, int64_t lmax, int32_t *part, uint64_t seed, int32_t global_iters,
+                double alpha, int32_t max_idle, orc_mls_stats *st);
+/* gain of moving v to its best feasible adjacent block (*target, -1 if none) */
+int64_t orc_mls_gain(const orc_graph *g, const int32_t *part, const int64_t *B, int32_t k, int64_t lmax, int32_t v,
+                     int32_t *target);
 
 /* LP flags (the former 0/1 direction argument is flag bit 0) */
 #define ORC_LP_DIR_ALTERNATE 1

@@ -1,0 +1,96 @@
+"""Pins of the oracle-only multi-try k-way local search (§III-C): searches
+started at single boundary vertices, moves by largest gain under L_max, the
+best prefix of each search kept, local iterations around moved vertices and
+three global iterations. It measures what the GPU path's LP-only refinement
+leaves on the table."""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+
+def _bridge():
+    # a = 0 and b = 1 (block 0) are tied by an edge of weight 5; a has unit
+    # edges to 2, 3, 4 and b to 5, 6, 7, all in block 1, where each of them
+    # has a weight-3 edge to the centre 8. 9-10 (weight 10) stay in block 0.
+    edges = [(0, 1), (0, 2), (0, 3), (0, 4), (1, 5), (1, 6), (1, 7)] + [(i, 8) for i in range(2, 8)] + [(9, 10)]
+    w = [5, 1, 1, 1, 1, 1, 1] + [3] * 6 + [10]
+    g = graphgen.from_edges(11, edges, weights=w)
+    part = np.array([0, 0, 1, 1, 1, 1, 1, 1, 1, 0, 0], np.int32)
+    return g, part
+
+
+def test_mls_worked_negative_first_move():
+    g, part = _bridge()
+    assert oracle.cut(g, part) == 6
+    # every single move loses: a and b have gain 3 - 5 = -2, the block-1
+    # leaves 1 - 3 = -2, so label propagation keeps the partition
+    P, st = oracle.lp_refine(g, part, 2, 100, 25)
+    assert P.tolist() == part.tolist() and st["moves"] == 0
+    assert oracle.mls_gain(g, part, 2, 100, 0) == (-2, 1)
+    assert oracle.mls_gain(g, part, 2, 100, 8) == (0, -1)  # no adjacent other block
+    # a search moves a first (gain -2, lowest id among the -2 ties); b's gain
+    # becomes 3 + 5 = +8 and b follows: the prefix of both moves gains 6
+    P, st = oracle.mls(g, part, 2, 100)
+    assert P.tolist() == [1, 1, 1, 1, 1, 1, 1, 1, 1, 0, 0]
+    assert oracle.cut(g, P) == 0 and st["gain"] == 6 and st["moves"] == 2
+
+
+def test_mls_respects_lmax():
+    # with L_max = 8 block 1 (weight 7) takes one more vertex only: a moves
+    # (gain -2) but b cannot follow, so the search keeps nothing
+    g, part = _bridge()
+    P, st = oracle.mls(g, part, 2, 8)
+    assert P.tolist() == part.tolist() and st["gain"] == 0 and st["moves"] == 0
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 4])
+def test_mls_invariants(seed):
+    g = graphgen.random_small(200, 0.05, seed, wmax=6, vmax=3)
+    n = len(g["xadj"]) - 1
+    k = 4
+    W = int(g["vwgt"].sum())
+    lm = oracle.lmax(W, k, 0.03)
+    part, _ = oracle.partition(g, k)
+    c0 = oracle.cut(g, part)
+    P, st = oracle.mls(g, part, k, lm, seed=seed)
+    B = np.bincount(P, weights=g["vwgt"], minlength=k)
+    assert B.max() <= lm  # the start partition is balanced and no move breaks L_max
+    assert oracle.cut(g, P) == c0 - st["gain"] and st["gain"] >= 0
+    # deterministic, and a second run from the result gains no more than it finds
+    P2, st2 = oracle.mls(g, part, k, lm, seed=seed)
+    assert np.array_equal(P, P2)
+    P3, st3 = oracle.mls(g, P, k, lm, seed=seed)
+    assert oracle.cut(g, P3) == oracle.cut(g, P) - st3["gain"]
+
+
+def test_mls_gain_matches_definition():
+    # gain(v) = max over adjacent blocks b != block(v) with B[b] + c(v) <= L_max
+    # of conn(v, b) - conn(v, block(v)); ties -> lowest b; spot checks
+    g = graphgen.random_small(60, 0.1, 7, wmax=5, vmax=2)
+    n = len(g["xadj"]) - 1
+    k = 3
+    part = (np.arange(n) % k).astype(np.int32)
+    B = np.bincount(part, weights=g["vwgt"], minlength=k)
+    lm = int(B.max()) + 1
+    for v in range(n):
+        conn = np.zeros(k, np.int64)
+        for e in range(g["xadj"][v], g["xadj"][v + 1]):
+            conn[part[g["adjncy"][e]]] += g["adjwgt"][e]
+        cands = [b for b in range(k) if b != part[v] and conn[b] > 0 and B[b] + g["vwgt"][v] <= lm]
+        gn, t = oracle.mls_gain(g, part, k, lm, v)
+        if not cands:
+            assert t == -1
+        else:
+            best = max(cands, key=lambda b: (conn[b], -b))
+            assert (gn, t) == (int(conn[best] - conn[part[v]]), best)
+
+
+def test_partition_with_mls_is_balanced_and_better():
+    # MLS after every level's LP refinement: balanced, and a lower cut here
+    for g, k in ((graphgen.rgg2d(4000, 5), 8), (graphgen.rmat(11, 4), 8)):
+        p0, r0 = oracle.partition(g, k)
+        p1, r1 = oracle.partition(g, k, mls=3)
+        assert r1["balanced"] == 1 and oracle.cut(g, p1) == r1["cut"]
+        assert r1["cut"] < r0["cut"]
