@@ -102,6 +102,61 @@ __device__ __forceinline__ float row_fma(int32_t b, int32_t e, const int32_t *__
     return acc;
 }
 
+// Rows above kBigRow entries: one workgroup per row. The workgroup stages a
+// chunk of neighbours' values in LDS and the first `cols` threads run the same
+// sequential FMA chains as row_fma, fed from LDS, chunk after chunk; a
+// lane-per-output thread would otherwise wait on memory for the whole row.
+constexpr int kBigRow = 2048;
+constexpr int kBigStage = 16384;  // staged floats per chunk (64 KB)
+
+struct BigFlag {
+    const int32_t *xadj;
+    __device__ bool operator()(int64_t v) const { return xadj[v + 1] - xadj[v] > kBigRow; }
+};
+struct BigEmit {
+    int32_t *big;
+    __device__ void operator()(int64_t v, int32_t pos) const { big[pos] = (int32_t)v; }
+};
+
+// WALK: out[v][c] = (X[v][c] + acc * rinv[v]) / 2, else out[v][c] = acc * rinv[v]
+template <bool WALK>
+__global__ __launch_bounds__(256) void k_rows_big(const int32_t *__restrict__ big, const int32_t *__restrict__ nbig,
+                                                  int32_t cols, const int32_t *__restrict__ xadj,
+                                                  const int32_t *__restrict__ adjncy,
+                                                  const int32_t *__restrict__ adjwgt, const float *__restrict__ rinv,
+                                                  const float *__restrict__ X, float *__restrict__ out) {
+    __shared__ float sx[kBigStage];
+    __shared__ float sw[kBigStage / 16];
+    __shared__ int32_t su[kBigStage / 16];
+    const int32_t chunk = kBigStage / cols;  // cols <= 64: at least 256 neighbours per chunk
+    const int32_t nb = *nbig;
+    for (int32_t r = blockIdx.x; r < nb; r += gridDim.x) {
+        const int32_t v = big[r];
+        const int32_t b = xadj[v], e = xadj[v + 1];
+        float acc = 0.0f;
+        for (int32_t q0 = b; q0 < e; q0 += chunk) {
+            const int32_t len = min(chunk, e - q0);
+            for (int32_t q = threadIdx.x; q < len; q += 256) {
+                su[q] = adjncy[q0 + q];
+                sw[q] = adjwgt ? (float)adjwgt[q0 + q] : 1.0f;
+            }
+            __syncthreads();
+            for (int32_t i = threadIdx.x; i < len * cols; i += 256) {
+                const int32_t q = i / cols, c = i - q * cols;
+                sx[i] = X[(int64_t)su[q] * cols + c];
+            }
+            __syncthreads();
+            if (threadIdx.x < cols)
+                for (int32_t q = 0; q < len; q++) acc = __builtin_fmaf(sw[q], sx[q * cols + threadIdx.x], acc);
+            __syncthreads();
+        }
+        if (threadIdx.x < cols) {
+            const int64_t i = (int64_t)v * cols + threadIdx.x;
+            out[i] = WALK ? (X[i] + acc * rinv[v]) * 0.5f : acc * rinv[v];
+        }
+    }
+}
+
 struct ActiveFlag {
     const int32_t *xadj;
     __device__ bool operator()(int64_t v) const { return xadj[v + 1] > xadj[v]; }
@@ -130,6 +185,7 @@ __global__ void k_walk(int32_t n, const int32_t *__restrict__ xadj, const int32_
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t v = (int32_t)(i / kMpProbe), j = (int32_t)(i % kMpProbe);
         const int32_t b = xadj[v], e = xadj[v + 1];
+        if (e - b > kBigRow) continue;  // k_rows_big
         const float acc = row_fma(b, e, adjncy, adjwgt, Yin, kMpProbe, j, 0.0f);
         const float self = Yin[i];
         Yout[i] = e > b ? (self + acc * rinv[v]) * 0.5f : self;
@@ -160,6 +216,7 @@ __global__ void k_aggregate(int32_t n, int32_t din, const int32_t *__restrict__ 
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t v = (int32_t)(i / din), c = (int32_t)(i % din);
         const int32_t b = xadj[v], e = xadj[v + 1];
+        if (e - b > kBigRow) continue;  // k_rows_big
         const float acc = row_fma(b, e, adjncy, adjwgt, H, din, c, 0.0f);
         M[i] = e > b ? acc * rinv[v] : 0.0f;
     }
@@ -256,22 +313,40 @@ __global__ __launch_bounds__(kDB) void k_decode_round(int32_t n, int32_t k, int3
     if (threadIdx.x == 0) B[t] += admitted;
 }
 
-// unplaced vertices, ascending, each into the currently lightest block
-__global__ void k_decode_leftover(int32_t n, int32_t k, const int32_t *__restrict__ vwgt, int64_t *__restrict__ B,
-                                  int32_t *__restrict__ part) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    for (int32_t v = 0; v < n; v++) {
-        if (part[v] == -2) {
-            part[v] = 0;  // takes no part: any valid block id
-            continue;
+// unplaced vertices, ascending, each into the currently lightest block. One
+// workgroup reads the assignment in 256-vertex chunks; thread 0 then places
+// that chunk's unplaced vertices in order (block weights in LDS).
+constexpr int kLeftBlock = 256;
+__global__ __launch_bounds__(kLeftBlock) void k_decode_leftover(int32_t n, int32_t k,
+                                                                const int32_t *__restrict__ vwgt,
+                                                                int64_t *__restrict__ B, int32_t *__restrict__ part) {
+    __shared__ int64_t sB[kMpMaxK];
+    __shared__ uint8_t sleft[kLeftBlock];
+    if (blockIdx.x != 0) return;
+    for (int32_t t = threadIdx.x; t < k; t += kLeftBlock) sB[t] = B[t];
+    for (int32_t v0 = 0; v0 < n; v0 += kLeftBlock) {
+        const int32_t v = v0 + threadIdx.x;
+        uint8_t left = 0;
+        if (v < n) {
+            const int32_t p = part[v];
+            if (p == -2) part[v] = 0;  // takes no part: any valid block id
+            left = p == -1;
         }
-        if (part[v] >= 0) continue;
-        int32_t b = 0;
-        for (int32_t t = 1; t < k; t++)
-            if (B[t] < B[b]) b = t;
-        part[v] = b;
-        B[b] += vwgt ? vwgt[v] : 1;
+        sleft[threadIdx.x] = left;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int32_t i = 0; i < kLeftBlock; i++) {
+                if (!sleft[i]) continue;
+                int32_t b = 0;
+                for (int32_t t = 1; t < k; t++)
+                    if (sB[t] < sB[b]) b = t;
+                part[v0 + i] = b;
+                sB[b] += vwgt ? vwgt[v0 + i] : 1;
+            }
+        }
+        __syncthreads();
     }
+    for (int32_t t = threadIdx.x; t < k; t += kLeftBlock) B[t] = sB[t];
 }
 
 // ------------------------------------------------------------------ training
@@ -493,6 +568,14 @@ struct Net {  // offsets of the parameter blocks
     }
 };
 
+// the rows above kBigRow entries (device list and count)
+int big_rows(const DevGraph &g, int32_t **big, int32_t **nbig, Scratch &sc) {
+    GP_TRY(sc.alloc(big, g.n));
+    GP_TRY(sc.alloc(nbig, 1));
+    GP_HIP(hipMemsetAsync(*nbig, 0, sizeof(int32_t), sc.stream()));
+    return compact(BigFlag{g.xadj}, BigEmit{*big}, g.n, nullptr, *nbig, sc);
+}
+
 struct Acts {  // forward activations kept for the backward pass
     float *X = nullptr, *rinv = nullptr, *H[3] = {}, *M[3] = {}, *Z = nullptr, *Wt = nullptr;
 };
@@ -514,10 +597,14 @@ int run_forward(const DevGraph &g, int32_t k, const float *params, uint64_t seed
     GP_TRY(mpnn_features(g, seed, active_only, a.X, a.rinv, sc));
     const Net net(k);
     const float *in = a.X;
+    int32_t *big = nullptr, *nbig = nullptr;
+    GP_TRY(big_rows(g, &big, &nbig, sc));
     for (int l = 0; l < 3; l++) {
         const int32_t din = l == 0 ? kMpFeat : kMpHid;
         hipLaunchKernelGGL(k_aggregate, dim3(grid_for((int64_t)n * din, 256, 1 << 16)), dim3(256), 0, s, n, din,
                            g.xadj, g.adjncy, g.adjwgt, a.rinv, in, a.M[l]);
+        hipLaunchKernelGGL(k_rows_big<false>, dim3(grid_for(n, 1, 1024)), dim3(256), 0, s, big, nbig, din, g.xadj,
+                           g.adjncy, g.adjwgt, a.rinv, in, a.M[l]);
         GP_LAUNCH_CHECK();
         hipLaunchKernelGGL((k_dense<true, true>), dim3(grid_for(n, kMB / kMpHid, 2048)), dim3(kMB), 0, s, n, din,
                            kMpHid, kMpHid, in, a.M[l], a.Wt + net.ws[l], a.Wt + net.wn[l], a.Wt + net.b[l], a.H[l]);
@@ -553,11 +640,15 @@ int mpnn_features(const DevGraph &g, uint64_t seed, bool active_only, float *X, 
         GP_HIP(hipMemsetAsync(rank, 0, sizeof(int32_t) * (size_t)n, s));
         GP_TRY(compact(ActiveFlag{g.xadj}, RankEmit{rank}, n, nullptr, cnt, sc));
     }
+    int32_t *big = nullptr, *nbig = nullptr;
+    GP_TRY(big_rows(g, &big, &nbig, sc));
     const unsigned gp16 = grid_for((int64_t)n * kMpProbe, 256, 1 << 16);
     hipLaunchKernelGGL(k_probes, dim3(gp16), dim3(256), 0, s, n, seed, rank, Ya);
     GP_LAUNCH_CHECK();
     for (int t = 0; t < kMpWalk; t++) {
         hipLaunchKernelGGL(k_walk, dim3(gp16), dim3(256), 0, s, n, g.xadj, g.adjncy, g.adjwgt, r, Ya, Yb);
+        hipLaunchKernelGGL(k_rows_big<true>, dim3(grid_for(n, 1, 1024)), dim3(256), 0, s, big, nbig, kMpProbe,
+                           g.xadj, g.adjncy, g.adjwgt, r, Ya, Yb);
         GP_LAUNCH_CHECK();
         std::swap(Ya, Yb);
     }
@@ -599,7 +690,7 @@ int mpnn_decode(const DevGraph &g, int32_t k, const float *Z, int64_t lmax, bool
         hipLaunchKernelGGL(k_decode_round, dim3(k), dim3(kDB), 0, s, n, k, r, pref, g.vwgt, lmax, B, part);
         GP_LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL(k_decode_leftover, dim3(1), dim3(64), 0, s, n, k, g.vwgt, B, part);
+    hipLaunchKernelGGL(k_decode_leftover, dim3(1), dim3(kLeftBlock), 0, s, n, k, g.vwgt, B, part);
     GP_LAUNCH_CHECK();
     return GP_OK;
 }

@@ -21,8 +21,20 @@ if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
 
+def _hubs():
+    # two weighted hubs with 5000 and 3000 leaves (rows above the 2048-entry
+    # threshold of the staged-row kernels) and a ring through the leaves
+    n = 8002
+    edges = [(0, i) for i in range(2, 5002)] + [(1, i) for i in range(5002, 8002)]
+    edges += [(i, i + 1) for i in range(2, 8001)] + [(0, 1)]
+    w = [1 + (i * 7919) % 50 for i in range(len(edges))]
+    vw = [1 + (i * 31) % 5 for i in range(n)]
+    return graphgen.from_edges(n, edges, weights=w, vwgt=vw)
+
+
 def _graphs():
     return {
+        "hubs": _hubs(),
         "rgg3000": graphgen.rgg2d(3000, 5),
         "weighted": graphgen.random_small(150, 0.05, 9, wmax=50, vmax=7),
         "rmat11": graphgen.rmat(11, 3),
