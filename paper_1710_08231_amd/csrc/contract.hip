@@ -831,7 +831,7 @@ int cut_dev(const DevGraph &g, const int32_t *part, const int32_t *rowof, int64_
         GP_TRY(sc.alloc(&ro, g.nnz));
         GP_TRY(build_rowof(g, ro, sc));
     }
-    GP_TRY((scan<int64_t>(CutIn{ro, g.adjncy, g.adjwgt, part}, NoOut{}, g.nnz, nullptr, cut_out, sc)));
+    GP_TRY((reduce<int64_t>(CutIn{ro, g.adjncy, g.adjwgt, part}, g.nnz, nullptr, cut_out, sc)));
     hipLaunchKernelGGL(k_halve, dim3(1), dim3(1), 0, s, cut_out);
     GP_LAUNCH_CHECK();
     return GP_OK;

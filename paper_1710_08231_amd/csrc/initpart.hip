@@ -367,16 +367,22 @@ __global__ __launch_bounds__(kRB) void k_rebalance(int32_t n, int32_t G, int32_t
     }
 }
 
-// cut of every (try, graph): cuts[try * G + graph]
-__global__ void k_copy_cut(int32_t n, int32_t attempts, int32_t G, const int32_t *gid, const int32_t *uxadj,
-                           const int32_t *uadj, const int32_t *uw, const int32_t *ulab, unsigned long long *cuts) {
+// cut of every (try, graph): cuts[try * G + graph]; one wave per vertex copy,
+// lanes over its edges (the coarsest graph can hold rows of many thousands)
+__global__ __launch_bounds__(256) void k_copy_cut(int32_t n, int32_t attempts, int32_t G, const int32_t *gid,
+                                                  const int32_t *uxadj, const int32_t *uadj, const int32_t *uw,
+                                                  const int32_t *ulab, unsigned long long *cuts) {
     const int64_t NV = (int64_t)n * attempts;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < NV; i += (int64_t)gridDim.x * blockDim.x) {
+    const int lane = lane_id();
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; i < NV; i += waves) {
         int64_t s = 0;
         const int32_t L = ulab[i];
-        for (int32_t e = uxadj[i]; e < uxadj[i + 1]; e++)
+        const int32_t e1 = uxadj[i + 1];
+        for (int32_t e = uxadj[i] + lane; e < e1; e += kWave)
             if (ulab[uadj[e]] != L) s += uw ? uw[e] : 1;
-        if (s) atomicAdd(&cuts[(i / n) * G + gid[i % n]], (unsigned long long)s);
+        s = wave_sum(s);
+        if (lane == 0 && s) atomicAdd(&cuts[(i / n) * G + gid[i % n]], (unsigned long long)s);
     }
 }
 
@@ -764,7 +770,7 @@ int initial_partition_batch(const DevGraph &g, bool skip_isolated, const BatchIn
     hipLaunchKernelGGL(k_rebalance, dim3((unsigned)TG), dim3(kRB), dyn, s, n, G, ktot, bi.d_voff, bi.d_kbase,
                        bi.d_lmax, ux, ua, uw, uv, ul, bal, kmax);
     GP_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_copy_cut, dim3(grid_for(NV, 256, 65536)), dim3(256), 0, s, n, attempts, G, bi.d_gid, ux, ua,
+    hipLaunchKernelGGL(k_copy_cut, dim3(grid_for(NV, 4, 65536)), dim3(256), 0, s, n, attempts, G, bi.d_gid, ux, ua,
                        uw, ul, cuts);
     GP_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_pick_tries, dim3(grid_for(G, 256, 1024)), dim3(256), 0, s, G, bis, extra != nullptr, cuts,

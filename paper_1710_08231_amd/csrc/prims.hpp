@@ -112,6 +112,30 @@ int scan(In in, Out out, int64_t nmax, const int32_t *n_dev, T *total_dev, Scrat
     return GP_OK;
 }
 
+struct DiscardOut {
+    template <typename T>
+    __device__ void operator()(int64_t, T, T) const {}
+};
+
+// Sum of in(i), i < n, into *total_dev: one pass of tile sums, then the same
+// over the tile sums until one tile is left.
+template <typename T, typename In>
+int reduce(In in, int64_t nmax, const int32_t *n_dev, T *total_dev, Scratch &sc, int depth = 0) {
+    hipStream_t s = sc.stream();
+    const int64_t ntiles = (nmax + kScanTile - 1) / kScanTile;
+    if (ntiles <= 1) {
+        hipLaunchKernelGGL((k_tile_scan<T, In, DiscardOut>), dim3(1), dim3(kScanBlock), 0, s, in, DiscardOut{}, nmax,
+                           n_dev, (const T *)nullptr, total_dev);
+        GP_LAUNCH_CHECK();
+        return GP_OK;
+    }
+    T *partial = nullptr;
+    GP_TRY(sc.temp(&partial, ntiles, 2 * depth));
+    hipLaunchKernelGGL((k_tile_reduce<T, In>), dim3(ntiles), dim3(kScanBlock), 0, s, in, nmax, n_dev, partial);
+    GP_LAUNCH_CHECK();
+    return reduce<T>(LoadIn<T>{partial}, ntiles, nullptr, total_dev, sc, depth + 1);
+}
+
 // Stable compaction: writes idx-th kept item's index mapping through `emit`.
 template <typename Flag, typename Emit>
 struct CompactOut {
