@@ -577,9 +577,15 @@ __global__ void k_row_class(const int32_t *mstart, const int32_t *flat, int32_t 
     if (threadIdx.x < 3 && h[threadIdx.x]) atomicAdd(&ccount[threadIdx.x], h[threadIdx.x]);
 }
 
-__global__ void k_expand_owner(const int32_t *first, const int32_t *num, int32_t nb, int32_t *owner) {
-    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < nb; g += (int64_t)gridDim.x * blockDim.x)
-        for (int32_t q = 0; q < num[g]; q++) owner[first[g] + q] = (int32_t)g;
+// one wave per big row: its lanes write the row's (possibly thousands of) chunk owners
+__global__ __launch_bounds__(256) void k_expand_owner(const int32_t *first, const int32_t *num, int32_t nb,
+                                                      int32_t *owner) {
+    const int lane = lane_id();
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    for (int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; g < nb; g += waves) {
+        const int32_t f = first[g], m = num[g];
+        for (int32_t q = lane; q < m; q += kWave) owner[f + q] = (int32_t)g;
+    }
 }
 
 // one wave per coarse row: copy its sorted columns to the output CSR
@@ -765,7 +771,7 @@ int contract(const DevGraph &g, const int32_t *labels, bool skip_isolated, Coars
             int32_t m = 0;
             if (nchunks > 0) {  // rows whose members have no neighbours have no chunks
                 GP_TRY(sc.alloc(&cown, nchunks));
-                hipLaunchKernelGGL(k_expand_owner, dim3(grid_for(nb, 256, 1024)), dim3(256), 0, s, cfirst, nch, nb,
+                hipLaunchKernelGGL(k_expand_owner, dim3(grid_for(nb, 4, 4096)), dim3(256), 0, s, cfirst, nch, nb,
                                    cown);
                 GP_LAUNCH_CHECK();
                 BigRows br{rows_g, cown, cfirst, bk, bv, cursor, jbits, flags};

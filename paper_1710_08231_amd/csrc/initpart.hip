@@ -462,12 +462,46 @@ __global__ void k_iso_minmax(const int32_t *iso, const int32_t *niso, const int3
 // the sorted merge of the sequences (B_b + j c, b), j >= 0. The i-th isolated
 // vertex takes the i-th smallest element: binary search its value x, then the
 // rank among blocks that reach exactly x.
+//
+// Past the heaviest block M = max B_b every block has one element in each
+// span [M + s c, M + (s + 1) c), ordered by ((B_b - M) mod c, b); so element
+// i >= T (T = number of elements below M) is block perm[(i - T) mod k], with
+// perm the blocks in that order (k_iso_plan). Only i < T needs the search.
+__global__ void k_iso_plan(const int64_t *B, int32_t k, int64_t c, int64_t *MT, int32_t *perm) {
+    __shared__ int64_t sM;
+    if (threadIdx.x == 0) {
+        int64_t M = LLONG_MIN;
+        for (int b = 0; b < k; b++) M = B[b] > M ? B[b] : M;
+        int64_t T = 0;
+        for (int b = 0; b < k; b++) T += (M - B[b] + c - 1) / c;
+        MT[0] = M;
+        MT[1] = T;
+        sM = M;
+    }
+    __syncthreads();
+    const int64_t M = sM;
+    for (int b = threadIdx.x; b < k; b += blockDim.x) {
+        const int64_t ob = ((B[b] - M) % c + c) % c;
+        int32_t rank = 0;
+        for (int q = 0; q < k; q++) {
+            const int64_t oq = ((B[q] - M) % c + c) % c;
+            rank += oq < ob || (oq == ob && q < b);
+        }
+        perm[rank] = b;
+    }
+}
+
 __global__ void k_iso_uniform(const int32_t *iso, const int32_t *niso, const int64_t *B, int32_t k, int64_t c,
-                              int32_t *part) {
+                              const int64_t *MT, const int32_t *perm, int32_t *part) {
     const int32_t m = *niso;
+    const int64_t T = MT[1];
     int64_t bmin = LLONG_MAX;
     for (int b = 0; b < k; b++) bmin = B[b] < bmin ? B[b] : bmin;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        if (i >= T) {
+            part[iso[i]] = perm[(i - T) % k];
+            continue;
+        }
         // f(x) = #elements <= x
         int64_t lo = bmin, hi = bmin + i * c;
         while (lo < hi) {
@@ -852,8 +886,13 @@ int fill_isolated(const DevGraph &g, int32_t k, int32_t *part, const int64_t *B,
     if (niso_host) *niso_host = niso;
     if (niso == 0) return GP_OK;
     if (h[0] == h[1]) {
+        int64_t *MT = nullptr;
+        int32_t *perm = nullptr;
+        GP_TRY(sc.alloc(&MT, 2));
+        GP_TRY(sc.alloc(&perm, k));
+        hipLaunchKernelGGL(k_iso_plan, dim3(1), dim3(256), 0, s, B, k, (int64_t)h[0], MT, perm);
         hipLaunchKernelGGL(k_iso_uniform, dim3(grid_for(niso, 256, 8192)), dim3(256), 0, s, iso, d_niso, B, k,
-                           (int64_t)h[0], part);
+                           (int64_t)h[0], MT, perm, part);
         GP_LAUNCH_CHECK();
     } else {
         int64_t *hv = nullptr;
