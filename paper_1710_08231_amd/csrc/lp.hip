@@ -435,39 +435,64 @@ __global__ __launch_bounds__(BLOCK) void k_propose_hub(LPArgs a, const int32_t *
 
 // ---------------------------------------------------------------- hubs split over workgroups
 
-// A hub's edges are cut into chunks of kHubChunk entries, each inserted by
-// its own workgroup into the hub's global table; the table is then scanned in
-// slices of kHubSlice slots, each slice merging its best (conn, label) into a
-// packed 64-bit key with atomicMax: high word conn, low word INT_MAX - label,
-// so the maximum is the largest connection with the smallest label. Used for
-// 32-bit connection sums (the packed key needs conn < 2^31).
+// A hub's edges are cut into chunks of kHubChunk entries. Each chunk's
+// workgroup sums its (label, weight) pairs in an LDS table and deals the
+// distinct labels into the hub's buckets (a hash of the label picks one),
+// writing each bucket's pairs as one contiguous run of that bucket's region.
+// One workgroup per bucket then sums the bucket's pairs in LDS and offers the
+// best label with room, packed into a 64-bit key merged with atomicMax: high
+// word conn, low word INT_MAX - label, so the maximum is the largest
+// connection with the smallest label. Used for 32-bit connection sums (the
+// packed key needs conn < 2^31). Nothing is hashed into global memory unless a
+// bucket's region overflows: its pairs then go to the hub's overflow table,
+// which a third kernel scans (and empties) only for such hubs.
 constexpr int kHubChunk = 4096;
 constexpr int kHubSlice = 4096;
+constexpr int kHubPer = 2048;       // buckets per hub: degree / kHubPer, rounded up
+constexpr int kHubMaxBuck = 2048;   // at most (the insert kernel's LDS histogram)
+constexpr int kBucketCap = 4096;    // pairs a bucket region holds
+constexpr int kRedLds = 2 * kBucketCap;
+constexpr int kRedBlock = 512;
 
 struct HubPlan {
     const int32_t *hubs;       // [nh] hub vertex ids
-    const int64_t *toff;       // [nh] table offset
-    const int32_t *tlog;       // [nh] log2 table capacity
+    const int64_t *toff;       // [nh] overflow table offset
+    const int32_t *tlog;       // [nh] log2 overflow table capacity
     const int32_t *chunk_hub;  // [nchunks]
     const int32_t *chunk_first;  // [nh] first chunk of hub
-    const int32_t *slice_hub;  // [nslices]
+    const int32_t *slice_hub;  // [nslices] overflow table slices
     const int32_t *slice_first;  // [nh]
-    int32_t *key;
-    int32_t *val;
-    unsigned long long *own;     // [nh]
-    unsigned long long *best1;   // [nh]
-    unsigned long long *best2;   // [nh]
-    int32_t *need2;              // [nh]
+    const int32_t *nbk;        // [nh] buckets of hub
+    const int32_t *bk_first;   // [nh] first bucket of hub
+    const int32_t *bk_hub;     // [nbuckets]
+    int32_t *fill;             // [nbuckets] pairs reserved in the bucket's region this round
+    int2 *pairs;               // [nbuckets * kBucketCap] (label, conn)
+    int32_t *key;              // overflow tables (all -1 between rounds)
+    int32_t *val;              //   (all 0 between rounds)
+    int32_t *ovf;              // [nh] a pair of the hub went to its overflow table
+    unsigned long long *own;   // [nh] connection to the hub's own label
+    unsigned long long *best;  // [nh] best packed (conn, label) with room
 };
 
 __device__ __forceinline__ unsigned long long pack_best(int32_t c, int32_t L) {
     return ((unsigned long long)(uint32_t)c << 32) | (unsigned long long)(uint32_t)(INT_MAX - L);
 }
 
-// One workgroup per chunk of a hub's edges. The chunk's (label, weight) pairs
-// are first summed in an LDS table (at most kHubChunk distinct labels, so the
-// table is at most half full); only the distinct labels then go to the hub's
-// global table, one global insert each instead of one per edge.
+// Bucket of a label: MurmurHash3's 32-bit finaliser (fmix32), scaled to nb by a
+// multiply-high. Independent of the top bits of hash_label that place the
+// label in the LDS tables, so a bucket's labels still spread over its table.
+__device__ __forceinline__ uint32_t bucket_of(int32_t L, uint32_t nb) {
+    uint32_t x = (uint32_t)L;
+    x ^= x >> 16;
+    x *= 0x85EBCA6Bu;
+    x ^= x >> 13;
+    x *= 0xC2B2AE35u;
+    x ^= x >> 16;
+    return (uint32_t)(((uint64_t)x * nb) >> 32);
+}
+
+// One workgroup per chunk of a hub's edges: at most kHubChunk distinct labels,
+// so the LDS table is at most half full.
 constexpr int kHubLds = 2 * kHubChunk;
 constexpr int kHubLdsLog = 13;
 static_assert((1 << kHubLdsLog) == kHubLds, "LDS table size");
@@ -478,125 +503,172 @@ __global__ __launch_bounds__(kHubBlock) void k_hub_insert(LPArgs a, HubPlan hp) 
     const int32_t dmode = cur_dirmode(a);
     __shared__ int32_t skey[kHubLds];
     __shared__ int32_t sval[kHubLds];
+    __shared__ int32_t scur[kHubMaxBuck];
     __shared__ int32_t tmp[kHubBlock / kWave + 1];
+    const int32_t h = hp.chunk_hub[blockIdx.x];
+    const int32_t v = hp.hubs[h];
+    if (inactive(a, v)) return;  // uniform: nothing goes into the hub's buckets
+    const int32_t nb = hp.nbk[h];
     for (int i = threadIdx.x; i < kHubLds; i += kHubBlock) {
         skey[i] = -1;
         sval[i] = 0;
     }
+    for (int i = threadIdx.x; i < nb; i += kHubBlock) scur[i] = 0;
     __syncthreads();
-    const int32_t h = hp.chunk_hub[blockIdx.x];
-    const int32_t v = hp.hubs[h];
-    if (inactive(a, v)) return;  // uniform: nothing goes into the hub's table
     const int32_t own = a.labels[v];
     const int32_t beg = a.xadj[v] + (blockIdx.x - hp.chunk_first[h]) * kHubChunk;
     const int32_t end = min(a.xadj[v + 1], beg + kHubChunk);
+    int32_t oc = 0;
+    for (int32_t e = beg + threadIdx.x; e < end; e += kHubBlock) {
+        const int32_t u = a.adjncy[e];
+        const int32_t wv = a.adjwgt ? a.adjwgt[e] : 1;
+        const int32_t L = a.labels[u];
+        if (L == own) oc += wv;
+        else if (dir_ok(L, own, dmode)) tbl_insert<int32_t>(skey, sval, kHubLds - 1, kHubLdsLog, L, wv);
+    }
+    __syncthreads();
+    // pairs per bucket, then one reservation per non-empty bucket in its region
+    for (int i = threadIdx.x; i < kHubLds; i += kHubBlock) {
+        const int32_t L = skey[i];
+        if (L >= 0) atomicAdd(&scur[bucket_of(L, (uint32_t)nb)], 1);
+    }
+    __syncthreads();
+    const int32_t gb0 = hp.bk_first[h];
+    for (int b = threadIdx.x; b < nb; b += kHubBlock) {
+        const int32_t c = scur[b];
+        if (c) scur[b] = atomicAdd(&hp.fill[gb0 + b], c);
+    }
+    __syncthreads();
     const int lg = hp.tlog[h];
     int32_t *key = hp.key + hp.toff[h];
     int32_t *val = hp.val + hp.toff[h];
-    int32_t oc = 0;
-    constexpr int UH = 1;
-    for (int32_t e0 = beg + threadIdx.x; e0 < end; e0 += UH * kHubBlock) {
-        int32_t u[UH], L[UH], wv[UH];
-#pragma unroll
-        for (int j = 0; j < UH; j++) {
-            const int32_t e = e0 + j * kHubBlock;
-            u[j] = e < end ? a.adjncy[e] : -1;
-            wv[j] = (e < end && a.adjwgt) ? a.adjwgt[e] : 1;
-        }
-#pragma unroll
-        for (int j = 0; j < UH; j++) L[j] = u[j] >= 0 ? a.labels[u[j]] : -1;
-#pragma unroll
-        for (int j = 0; j < UH; j++) {
-            if (u[j] < 0) continue;
-            if (L[j] == own) oc += wv[j];
-            else if (dir_ok(L[j], own, dmode)) tbl_insert<int32_t>(skey, sval, kHubLds - 1, kHubLdsLog, L[j], wv[j]);
-        }
-    }
-    __syncthreads();
     for (int i = threadIdx.x; i < kHubLds; i += kHubBlock) {
         const int32_t L = skey[i];
-        if (L >= 0) tbl_insert_global<int32_t>(key, val, (1u << lg) - 1, lg, L, sval[i]);
+        if (L < 0) continue;
+        const uint32_t b = bucket_of(L, (uint32_t)nb);
+        const int32_t pos = atomicAdd(&scur[b], 1);
+        if (pos < kBucketCap) {
+            hp.pairs[(int64_t)(gb0 + (int32_t)b) * kBucketCap + pos] = make_int2(L, sval[i]);
+        } else {  // region full: this pair goes to the hub's overflow table
+            tbl_insert_global<int32_t>(key, val, (1u << lg) - 1, lg, L, sval[i]);
+            hp.ovf[h] = 1;
+        }
     }
     oc = block_sum<kHubBlock>(oc, tmp);
     if (threadIdx.x == 0 && oc) atomicAdd(&hp.own[h], (unsigned long long)oc);
 }
 
-// phase 1 (unfiltered best) or phase 2 (best among labels with room; only for
-// hubs flagged in need2); phase 2 also empties the slice for the next round.
-template <bool PHASE2>
-__global__ __launch_bounds__(256) void k_hub_scan(LPArgs a, HubPlan hp) {
+// One workgroup per bucket: sum its pairs in an LDS table sized to them and
+// offer the best label with room (W at the round start, as every proposal
+// kernel tests it). An overflowed bucket instead moves the pairs of its region
+// to the hub's overflow table, where the rest of them already are. Empties the
+// bucket for the next round.
+__global__ __launch_bounds__(kRedBlock) void k_hub_reduce(LPArgs a, HubPlan hp) {
     if (*a.done) return;
-    const int32_t dmode = cur_dirmode(a);
-    __shared__ unsigned long long tmp[256 / kWave + 1];
-    const int32_t h = hp.slice_hub[blockIdx.x];
-    if (inactive(a, hp.hubs[h])) return;  // nothing was inserted; the table is already empty
-    const uint32_t cap = 1u << hp.tlog[h];
-    const uint32_t s0 = (uint32_t)(blockIdx.x - hp.slice_first[h]) * kHubSlice;
-    const uint32_t s1 = min(cap, s0 + kHubSlice);
-    int32_t *key = hp.key + hp.toff[h];
-    int32_t *val = hp.val + hp.toff[h];
-    const bool active = !PHASE2 || hp.need2[h];
-    const int64_t cv = PHASE2 ? vweight(a.vwgt, hp.hubs[h]) : 0;
-    unsigned long long best = 0;
-    for (uint32_t i = s0 + threadIdx.x; i < s1; i += 256) {
-        const int32_t L = ld_agent(&key[i]);
-        if (active && L >= 0) {
-            const int32_t c = ld_agent(&val[i]);
-            if (!PHASE2 || a.W[L] + cv <= capof(a, L)) {
-                const unsigned long long pk = pack_best(c, L);
-                best = pk > best ? pk : best;
-            }
+    __shared__ int32_t skey[kRedLds];
+    __shared__ int32_t sval[kRedLds];
+    __shared__ unsigned long long tmp[kRedBlock / kWave + 1];
+    const int32_t gb = blockIdx.x;
+    const int32_t f = hp.fill[gb];
+    if (f == 0) return;  // uniform
+    const int32_t h = hp.bk_hub[gb];
+    const int2 *pr = hp.pairs + (int64_t)gb * kBucketCap;
+    if (f > kBucketCap) {
+        const int lg = hp.tlog[h];
+        int32_t *key = hp.key + hp.toff[h];
+        int32_t *val = hp.val + hp.toff[h];
+        for (int i = threadIdx.x; i < kBucketCap; i += kRedBlock) {
+            const int2 p = pr[i];
+            tbl_insert_global<int32_t>(key, val, (1u << lg) - 1, lg, p.x, p.y);
         }
-        if (PHASE2 && L >= 0) {
-            key[i] = -1;
-            val[i] = 0;
+        __syncthreads();
+        if (threadIdx.x == 0) hp.fill[gb] = 0;
+        return;
+    }
+    int lg = 8;
+    while ((1 << lg) < 2 * f) lg++;  // f <= kBucketCap, so lg <= log2(kRedLds)
+    const int cap = 1 << lg;
+    for (int i = threadIdx.x; i < cap; i += kRedBlock) {
+        skey[i] = -1;
+        sval[i] = 0;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < f; i += kRedBlock) {
+        const int2 p = pr[i];
+        tbl_insert<int32_t>(skey, sval, cap - 1, lg, p.x, p.y);
+    }
+    __syncthreads();
+    const int64_t cv = vweight(a.vwgt, hp.hubs[h]);
+    unsigned long long best = 0;
+    for (int i = threadIdx.x; i < cap; i += kRedBlock) {
+        const int32_t L = skey[i];
+        if (L >= 0 && a.W[L] + cv <= capof(a, L)) {
+            const unsigned long long pk = pack_best(sval[i], L);
+            best = pk > best ? pk : best;
         }
     }
-    best = block_max<256>(best, tmp);
-    if (threadIdx.x == 0 && best) atomicMax(PHASE2 ? &hp.best2[h] : &hp.best1[h], best);
+    best = block_max<kRedBlock>(best, tmp);
+    if (threadIdx.x == 0) {
+        if (best) atomicMax(&hp.best[h], best);
+        hp.fill[gb] = 0;
+    }
 }
 
-template <bool FINAL>
+// Overflow tables of the hubs flagged in ovf: best label with room over each
+// slice, then the slice is emptied for the next round. Hubs without overflow
+// cost one flag load per slice.
+__global__ __launch_bounds__(256) void k_hub_scan(LPArgs a, HubPlan hp, int32_t nslices) {
+    if (*a.done) return;
+    __shared__ unsigned long long tmp[256 / kWave + 1];
+    for (int32_t sl = blockIdx.x; sl < nslices; sl += gridDim.x) {
+        const int32_t h = hp.slice_hub[sl];
+        if (!hp.ovf[h]) continue;  // uniform
+        const uint32_t tcap = 1u << hp.tlog[h];
+        const uint32_t s0 = (uint32_t)(sl - hp.slice_first[h]) * kHubSlice;
+        const uint32_t s1 = min(tcap, s0 + kHubSlice);
+        int32_t *key = hp.key + hp.toff[h];
+        int32_t *val = hp.val + hp.toff[h];
+        const int64_t cv = vweight(a.vwgt, hp.hubs[h]);
+        unsigned long long best = 0;
+        for (uint32_t i = s0 + threadIdx.x; i < s1; i += 256) {
+            const int32_t L = key[i];
+            if (L >= 0) {
+                if (a.W[L] + cv <= capof(a, L)) {
+                    const unsigned long long pk = pack_best(val[i], L);
+                    best = pk > best ? pk : best;
+                }
+                key[i] = -1;
+                val[i] = 0;
+            }
+        }
+        best = block_max<256>(best, tmp);
+        if (threadIdx.x == 0 && best) atomicMax(&hp.best[h], best);
+    }
+}
+
+// The hub proposes its best label with room if that connection beats the one
+// to its own label (the same rule as the other tiers: the strongest eligible
+// label, ties to the smaller label); resets the per-hub state.
 __global__ void k_hub_decide(LPArgs a, HubPlan hp, int32_t nh) {
     if (*a.done) return;
-    const int32_t dmode = cur_dirmode(a);
     for (int32_t h = blockIdx.x * blockDim.x + threadIdx.x; h < nh; h += gridDim.x * blockDim.x) {
-        const int32_t v = hp.hubs[h];
         const int64_t oc = (int64_t)hp.own[h];
-        if (!FINAL) {
-            const unsigned long long b = hp.best1[h];
-            int32_t target = -1, need = 0;
-            if (b) {
-                const int64_t c = (int64_t)(b >> 32);
-                const int32_t L = INT_MAX - (int32_t)(uint32_t)(b & 0xFFFFFFFFull);
-                if (c > oc) {
-                    if (a.W[L] + vweight(a.vwgt, v) <= capof(a, L)) target = L;
-                    else need = 1;
-                }
-            }
-            a.prop[v] = target;
-            hp.need2[h] = need;
-        } else {
-            if (hp.need2[h]) {
-                const unsigned long long b = hp.best2[h];
-                int32_t target = -1;
-                if (b) {
-                    const int64_t c = (int64_t)(b >> 32);
-                    const int32_t L = INT_MAX - (int32_t)(uint32_t)(b & 0xFFFFFFFFull);
-                    if (c > oc) target = L;
-                }
-                a.prop[v] = target;
-            }
-            hp.own[h] = 0;
-            hp.best1[h] = 0;
-            hp.best2[h] = 0;
-            hp.need2[h] = 0;
+        const unsigned long long b = hp.best[h];
+        int32_t target = -1;
+        if (b) {
+            const int64_t c = (int64_t)(b >> 32);
+            const int32_t L = INT_MAX - (int32_t)(uint32_t)(b & 0xFFFFFFFFull);
+            if (c > oc) target = L;
         }
+        a.prop[hp.hubs[h]] = target;
+        hp.own[h] = 0;
+        hp.best[h] = 0;
+        hp.ovf[h] = 0;
     }
 }
 
 __global__ void k_hub_plan(const int32_t *xadj, const int32_t *hubs, int32_t nh, int32_t *tlog, int64_t *tcap,
-                           int32_t *nchunk, int32_t *nslice) {
+                           int32_t *nchunk, int32_t *nslice, int32_t *nbk) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nh; i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t v = hubs[i];
         const int64_t d = xadj[v + 1] - xadj[v];
@@ -606,6 +678,7 @@ __global__ void k_hub_plan(const int32_t *xadj, const int32_t *hubs, int32_t nh,
         tcap[i] = int64_t(1) << lg;
         nchunk[i] = (int32_t)((d + kHubChunk - 1) / kHubChunk);
         nslice[i] = (int32_t)(((int64_t(1) << lg) + kHubSlice - 1) / kHubSlice);
+        nbk[i] = (int32_t)min<int64_t>(max<int64_t>((d + kHubPer - 1) / kHubPer, 1), kHubMaxBuck);
     }
 }
 
@@ -1427,54 +1500,64 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
     int64_t *hub_off = nullptr;
     void *gval = nullptr;
     HubPlan hp{};
-    int32_t nchunks = 0, nslices = 0;
+    int32_t nchunks = 0, nslices = 0, nbuckets = 0;
     if (split_hubs) {
         const int32_t *hubs = verts + tstart[kTiers - 1];
-        int32_t *tlog = nullptr, *nch = nullptr, *nsl = nullptr, *cfirst = nullptr, *sfirst = nullptr,
-                *d_tot = nullptr, *chub = nullptr, *shub = nullptr, *need2 = nullptr;
+        int32_t *tlog = nullptr, *nch = nullptr, *nsl = nullptr, *nbk = nullptr, *cfirst = nullptr,
+                *sfirst = nullptr, *bfirst = nullptr, *d_tot = nullptr, *chub = nullptr, *shub = nullptr,
+                *bhub = nullptr, *fill = nullptr, *ovf = nullptr;
         int64_t *tcap = nullptr, *toff = nullptr, *d_ttot = nullptr;
-        unsigned long long *own = nullptr, *b1 = nullptr, *b2 = nullptr;
+        unsigned long long *own = nullptr, *best = nullptr;
         GP_TRY(sc.alloc(&tlog, nh));
         GP_TRY(sc.alloc(&nch, nh));
         GP_TRY(sc.alloc(&nsl, nh));
+        GP_TRY(sc.alloc(&nbk, nh));
         GP_TRY(sc.alloc(&cfirst, nh));
         GP_TRY(sc.alloc(&sfirst, nh));
-        GP_TRY(sc.alloc(&d_tot, 2));
+        GP_TRY(sc.alloc(&bfirst, nh));
+        GP_TRY(sc.alloc(&d_tot, 3));
         GP_TRY(sc.alloc(&tcap, nh));
         GP_TRY(sc.alloc(&toff, nh));
         GP_TRY(sc.alloc(&d_ttot, 1));
         GP_TRY(sc.alloc(&own, nh));
-        GP_TRY(sc.alloc(&b1, nh));
-        GP_TRY(sc.alloc(&b2, nh));
-        GP_TRY(sc.alloc(&need2, nh));
+        GP_TRY(sc.alloc(&best, nh));
+        GP_TRY(sc.alloc(&ovf, nh));
         hipLaunchKernelGGL(k_hub_plan, dim3(grid_for(nh, 256, 1024)), dim3(256), 0, s, g.xadj, hubs, nh, tlog, tcap,
-                           nch, nsl);
+                           nch, nsl, nbk);
         GP_LAUNCH_CHECK();
         GP_TRY((scan<int64_t>(LoadIn<int64_t>{tcap}, StoreExcl<int64_t>{toff}, nh, nullptr, d_ttot, sc)));
         GP_TRY((scan<int32_t>(LoadIn<int32_t>{nch}, StoreExcl<int32_t>{cfirst}, nh, nullptr, d_tot, sc)));
         GP_TRY((scan<int32_t>(LoadIn<int32_t>{nsl}, StoreExcl<int32_t>{sfirst}, nh, nullptr, d_tot + 1, sc)));
-        int32_t tots[2];
+        GP_TRY((scan<int32_t>(LoadIn<int32_t>{nbk}, StoreExcl<int32_t>{bfirst}, nh, nullptr, d_tot + 2, sc)));
+        int32_t tots[3];
         int64_t ttot = 0;
         GP_HIP(hipMemcpyAsync(tots, d_tot, sizeof(tots), hipMemcpyDeviceToHost, s));
         GP_HIP(hipMemcpyAsync(&ttot, d_ttot, sizeof(int64_t), hipMemcpyDeviceToHost, s));
         GP_HIP(hipStreamSynchronize(s));
         nchunks = tots[0];
         nslices = tots[1];
+        nbuckets = tots[2];
         GP_TRY(sc.alloc(&chub, nchunks));
         GP_TRY(sc.alloc(&shub, nslices));
+        GP_TRY(sc.alloc(&bhub, nbuckets));
+        GP_TRY(sc.alloc(&fill, nbuckets));
         hipLaunchKernelGGL(k_hub_expand, dim3(grid_for(nh, 256, 1024)), dim3(256), 0, s, cfirst, nch, nh, chub);
         hipLaunchKernelGGL(k_hub_expand, dim3(grid_for(nh, 256, 1024)), dim3(256), 0, s, sfirst, nsl, nh, shub);
+        hipLaunchKernelGGL(k_hub_expand, dim3(grid_for(nh, 256, 1024)), dim3(256), 0, s, bfirst, nbk, nh, bhub);
         GP_LAUNCH_CHECK();
         int32_t *tk = nullptr, *tv = nullptr;
+        int2 *pairs = nullptr;
         GP_TRY(sc.alloc(&tk, ttot));
         GP_TRY(sc.alloc(&tv, ttot));
+        GP_TRY(sc.alloc(&pairs, (int64_t)nbuckets * kBucketCap));
         GP_HIP(hipMemsetAsync(tk, 0xFF, sizeof(int32_t) * (size_t)ttot, s));
         GP_HIP(hipMemsetAsync(tv, 0, sizeof(int32_t) * (size_t)ttot, s));
+        GP_HIP(hipMemsetAsync(fill, 0, sizeof(int32_t) * nbuckets, s));
         GP_HIP(hipMemsetAsync(own, 0, sizeof(unsigned long long) * nh, s));
-        GP_HIP(hipMemsetAsync(b1, 0, sizeof(unsigned long long) * nh, s));
-        GP_HIP(hipMemsetAsync(b2, 0, sizeof(unsigned long long) * nh, s));
-        GP_HIP(hipMemsetAsync(need2, 0, sizeof(int32_t) * nh, s));
-        hp = HubPlan{hubs, toff, tlog, chub, cfirst, shub, sfirst, tk, tv, own, b1, b2, need2};
+        GP_HIP(hipMemsetAsync(best, 0, sizeof(unsigned long long) * nh, s));
+        GP_HIP(hipMemsetAsync(ovf, 0, sizeof(int32_t) * nh, s));
+        hp = HubPlan{hubs, toff, tlog, chub, cfirst, shub, sfirst, nbk, bfirst, bhub, fill, pairs, tk, tv, ovf, own,
+                     best};
     } else if (nh > 0) {
         int64_t *hcap = nullptr, *htot = nullptr;
         GP_TRY(sc.alloc(&hub_log, nh));
@@ -1624,10 +1707,9 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
                                              tbytes, split_hubs));
         if (split_hubs) {
             GP_PROF_LAUNCH("k_hub_insert", tbytes[kTiers - 1], s, hipLaunchKernelGGL(k_hub_insert, dim3(nchunks), dim3(kHubBlock), 0, s, a, hp));
-            hipLaunchKernelGGL(k_hub_scan<false>, dim3(nslices), dim3(256), 0, s, a, hp);
-            hipLaunchKernelGGL(k_hub_decide<false>, dim3(grid_for(nh, 256, 1024)), dim3(256), 0, s, a, hp, nh);
-            hipLaunchKernelGGL(k_hub_scan<true>, dim3(nslices), dim3(256), 0, s, a, hp);
-            hipLaunchKernelGGL(k_hub_decide<true>, dim3(grid_for(nh, 256, 1024)), dim3(256), 0, s, a, hp, nh);
+            hipLaunchKernelGGL(k_hub_reduce, dim3(nbuckets), dim3(kRedBlock), 0, s, a, hp);
+            hipLaunchKernelGGL(k_hub_scan, dim3(grid_for(nslices, 1, 2048)), dim3(256), 0, s, a, hp, nslices);
+            hipLaunchKernelGGL(k_hub_decide, dim3(grid_for(nh, 256, 1024)), dim3(256), 0, s, a, hp, nh);
             GP_LAUNCH_CHECK();
         }
         if (act) {

@@ -351,3 +351,54 @@ def test_lp_with_64bit_sums_small_block_tier():
             assert st["moves"] == ost["moves"]
     finally:
         gp.set_tuning(None)
+
+
+def _fmix32(x):
+    # MurmurHash3's 32-bit finaliser, the hub path's bucket hash
+    x = x.astype(np.uint64)
+    m = np.uint64(0xFFFFFFFF)
+    x ^= x >> np.uint64(16)
+    x = (x * np.uint64(0x85EBCA6B)) & m
+    x ^= x >> np.uint64(13)
+    x = (x * np.uint64(0xC2B2AE35)) & m
+    x ^= x >> np.uint64(16)
+    return x
+
+
+def _colliding_hub(d, n, seed):
+    # hub = vertex n - 1 (the largest label, so the direction rule lets it see
+    # all its neighbours in even rounds) with d neighbours whose labels (their
+    # ids in round 0) all fall into bucket 0 of the hub's ceil(d / 2048)
+    # buckets: more pairs than a bucket region holds (4096), so the overflow
+    # table is used. A second hub, vertex n - 2, has ordinary neighbours.
+    nb = -(-d // 2048)
+    ids = np.arange(n - 2, dtype=np.int64)
+    b = (_fmix32(ids) * np.uint64(nb)) >> np.uint64(32)
+    nbr = ids[b == 0][:d]
+    assert len(nbr) == d
+    rng = np.random.default_rng(seed)
+    other = rng.choice(n - 2, 12000, replace=False)
+    extra = rng.integers(0, n - 2, size=(3 * n, 2))
+    edges = [(n - 1, int(u)) for u in nbr] + [(n - 2, int(u)) for u in other]
+    edges += [(int(u), int(v)) for u, v in extra if u != v]
+    return graphgen.from_edges(n, edges)
+
+
+@pytest.mark.parametrize("dirs", [0, 1])
+def test_hub_bucket_overflow(dirs):
+    g = _colliding_hub(9000, 60000, 5)
+    deg = np.diff(g["xadj"])
+    assert deg[-1] >= 9000 and deg[-2] > 8192  # both in the hub tier
+    dg = gp.to_device(g)
+    for U in (3, 50, 5000):
+        lab, st = gp.lp_cluster(dg, U, 6, dirs)
+        olab, ost = oracle.lp_cluster(g, U, 6, dirs)
+        assert np.array_equal(_np(lab), olab), U
+        assert {k: st[k] for k in ost} == ost
+    # the same hubs with many labels in refinement (hashed tables, no overflow)
+    n = len(deg)
+    part = (np.arange(n) * 7919 % 300).astype(np.int32)
+    lm = oracle.lmax(n, 300, 0.03)
+    p, st = gp.lp_refine(dg, torch.from_numpy(part).cuda(), 300, lm, 6, dirs)
+    op, ost = oracle.lp_refine(g, part, 300, lm, 6, dirs)
+    assert np.array_equal(_np(p), op) and {k: st[k] for k in ost} == ost
