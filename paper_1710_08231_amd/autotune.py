@@ -19,7 +19,7 @@ import sys
 
 import paper_1710_08231_amd as gp
 
-TIER_CANDIDATES = list(itertools.product((32, 64), (128, 256), (1024, 2048), (4096, 8192)))
+TIER_CANDIDATES = list(itertools.product((32, 64), (128, 256), (1024, 2048), (2048, 4096, 8192)))
 DENSE_CANDIDATES = list(itertools.product((128, 256, 512, 1024), (1024, 2048, 4096, 8192)))
 DEFAULT = {"tier_max": [64, 256, 2048, 8192], "dense_split": 256, "dense_chunk": 2048}
 

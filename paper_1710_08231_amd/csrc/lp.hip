@@ -491,8 +491,8 @@ __device__ __forceinline__ uint32_t bucket_of(int32_t L, uint32_t nb) {
     return (uint32_t)(((uint64_t)x * nb) >> 32);
 }
 
-// One workgroup per chunk of a hub's edges: at most kHubChunk distinct labels,
-// so the LDS table is at most half full.
+// One workgroup per chunk of a hub's edges; its LDS table (at most kHubLds
+// slots) is sized to the chunk, so it is at most half full.
 constexpr int kHubLds = 2 * kHubChunk;
 constexpr int kHubLdsLog = 13;
 static_assert((1 << kHubLdsLog) == kHubLds, "LDS table size");
@@ -509,26 +509,29 @@ __global__ __launch_bounds__(kHubBlock) void k_hub_insert(LPArgs a, HubPlan hp) 
     const int32_t v = hp.hubs[h];
     if (inactive(a, v)) return;  // uniform: nothing goes into the hub's buckets
     const int32_t nb = hp.nbk[h];
-    for (int i = threadIdx.x; i < kHubLds; i += kHubBlock) {
+    const int32_t beg = a.xadj[v] + (blockIdx.x - hp.chunk_first[h]) * kHubChunk;
+    const int32_t end = min(a.xadj[v + 1], beg + kHubChunk);
+    int tlg = 6;  // table sized to the chunk: next power of two >= 2 * entries
+    while ((1 << tlg) < 2 * (end - beg)) tlg++;
+    const int tcap = 1 << tlg;
+    for (int i = threadIdx.x; i < tcap; i += kHubBlock) {
         skey[i] = -1;
         sval[i] = 0;
     }
     for (int i = threadIdx.x; i < nb; i += kHubBlock) scur[i] = 0;
     __syncthreads();
     const int32_t own = a.labels[v];
-    const int32_t beg = a.xadj[v] + (blockIdx.x - hp.chunk_first[h]) * kHubChunk;
-    const int32_t end = min(a.xadj[v + 1], beg + kHubChunk);
     int32_t oc = 0;
     for (int32_t e = beg + threadIdx.x; e < end; e += kHubBlock) {
         const int32_t u = a.adjncy[e];
         const int32_t wv = a.adjwgt ? a.adjwgt[e] : 1;
         const int32_t L = a.labels[u];
         if (L == own) oc += wv;
-        else if (dir_ok(L, own, dmode)) tbl_insert<int32_t>(skey, sval, kHubLds - 1, kHubLdsLog, L, wv);
+        else if (dir_ok(L, own, dmode)) tbl_insert<int32_t>(skey, sval, tcap - 1, tlg, L, wv);
     }
     __syncthreads();
     // pairs per bucket, then one reservation per non-empty bucket in its region
-    for (int i = threadIdx.x; i < kHubLds; i += kHubBlock) {
+    for (int i = threadIdx.x; i < tcap; i += kHubBlock) {
         const int32_t L = skey[i];
         if (L >= 0) atomicAdd(&scur[bucket_of(L, (uint32_t)nb)], 1);
     }
@@ -542,7 +545,7 @@ __global__ __launch_bounds__(kHubBlock) void k_hub_insert(LPArgs a, HubPlan hp) 
     const int lg = hp.tlog[h];
     int32_t *key = hp.key + hp.toff[h];
     int32_t *val = hp.val + hp.toff[h];
-    for (int i = threadIdx.x; i < kHubLds; i += kHubBlock) {
+    for (int i = threadIdx.x; i < tcap; i += kHubBlock) {
         const int32_t L = skey[i];
         if (L < 0) continue;
         const uint32_t b = bucket_of(L, (uint32_t)nb);
