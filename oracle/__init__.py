@@ -39,7 +39,8 @@ class _Params(ctypes.Structure):
                 ("dir_alternate", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("init_mode", ctypes.c_int32), ("mpnn_max_n", ctypes.c_int32),
                 ("mpnn_seed", ctypes.c_uint64), ("mpnn_params", ctypes.POINTER(ctypes.c_float)),
-                ("lp_async", ctypes.c_int32), ("active_set", ctypes.c_int32), ("mls", ctypes.c_int32)]
+                ("lp_async", ctypes.c_int32), ("active_set", ctypes.c_int32), ("mls", ctypes.c_int32),
+                ("init_fm", ctypes.c_int32)]
 
 
 class _Result(ctypes.Structure):
@@ -88,10 +89,11 @@ def _load():
     lib.orc_mix4.restype = ctypes.c_uint64
     lib.orc_mix4.argtypes = [ctypes.c_uint64] * 4
     lib.orc_recursive_bisection.argtypes = [G, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32,
-                                            I32P]
+                                            ctypes.c_int64, ctypes.c_int32, I32P]
     lib.orc_rebalance.argtypes = [G, ctypes.c_int32, ctypes.c_int64, I32P]
     lib.orc_initial_partition.argtypes = [G, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
-                                          ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, I32P]
+                                          ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                          I32P]
     lib.orc_fill_isolated.argtypes = [G, ctypes.c_int32, I32P, I64P]
     lib.orc_partition.argtypes = [G, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(_Params),
                                   I32P, ctypes.POINTER(_Result)]
@@ -275,10 +277,12 @@ def mix4(seed, a, base, ks):
     return int(_load().orc_mix4(seed, a, base, ks))
 
 
-def recursive_bisection(g, k, seed=0, attempt=0):
+def recursive_bisection(g, k, seed=0, attempt=0, lmax_=0, fm=0):
+    """BFS-grow recursive bisection; fm > 0: at most fm 2-way FM passes after every
+    bisection, a side that will hold j blocks weighing at most j * lmax_."""
     G = _G(g)
     P = np.zeros(G.n, np.int32)
-    _load().orc_recursive_bisection(G.ref, k, seed, attempt, _p32(P))
+    _load().orc_recursive_bisection(G.ref, k, seed, attempt, lmax_, fm, _p32(P))
     return P
 
 
@@ -289,11 +293,11 @@ def rebalance(g, k, lmax_, part):
     return P, bool(bal)
 
 
-def initial_partition(g, k, lmax_, seed=0, attempts=4, rounds_refine=25, dir_alternate=1):
+def initial_partition(g, k, lmax_, seed=0, attempts=4, rounds_refine=25, dir_alternate=1, fm=0):
     G = _G(g)
     P = np.zeros(G.n, np.int32)
     a = _load().orc_initial_partition(G.ref, k, lmax_, seed, attempts, rounds_refine,
-                                      dir_alternate, _p32(P))
+                                      dir_alternate, fm, _p32(P))
     return P, int(a)
 
 
@@ -307,7 +311,8 @@ def fill_isolated(g, k, part, B):
 
 DEFAULT_PARAMS = dict(rounds_coarsen=10, rounds_refine=25, coarsest_per_k=60, attempts=4,
                       stall_num=19, stall_den=20, dir_alternate=1, seed=0, init_mode=0,
-                      mpnn_max_n=131072, mpnn_seed=0, mpnn_params=None, lp_async=0, active_set=0, mls=0)
+                      mpnn_max_n=131072, mpnn_seed=0, mpnn_params=None, lp_async=0, active_set=0, mls=0,
+                      init_fm=0)
 
 
 def _params(params):

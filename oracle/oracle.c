@@ -419,11 +419,79 @@ typedef struct {
     int32_t *marked;
     int32_t *queue;
     int32_t tag;
+    int64_t lmax;      /* block bound; a side that will hold j blocks may weigh j * lmax */
+    int32_t fm_passes; /* 0: no local search after a bisection */
+    int32_t *side;     /* 0 left, 1 right, for the vertices of the current S */
+    int32_t *locked;
+    int32_t *log;
+    int64_t *gain;
 } rb_ctx;
 
-static int cmp_i32(const void *a, const void *b) {
-    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
-    return (x > y) - (x < y);
+/*
+ * 2-way FM local search after a bisection (§III-B: the bisection is improved
+ * by local search; the paper's KaHIP uses Fiduccia-Mattheyses). Only edges
+ * with both ends in S count. One pass: every vertex of S unlocked, gain(v) =
+ * (weight of v's edges to the other side) - (weight to its own side); move the
+ * unlocked vertex of largest gain whose move keeps the receiving side within
+ * its bound (ties -> lowest id), lock it, update its neighbours' gains; stop
+ * when no vertex may move or after ORC_FM_IDLE moves without a new best
+ * running gain; keep the shortest prefix of moves with the best running gain
+ * and undo the rest. Passes repeat until one gains nothing (at most
+ * fm_passes).
+ */
+#define ORC_FM_IDLE 50
+
+static void fm2(rb_ctx *cx, const int32_t *S, int32_t size, int32_t tag, int64_t U0, int64_t U1) {
+    const orc_graph *g = cx->g;
+    const int64_t U[2] = {U0, U1};
+    int32_t *side = cx->side;
+    for (int32_t pass = 0; pass < cx->fm_passes; pass++) {
+        int64_t Wt[2] = {0, 0};
+        for (int32_t i = 0; i < size; i++) {
+            int32_t v = S[i];
+            Wt[side[v]] += VW(g, v);
+            cx->locked[v] = 0;
+            int64_t gn = 0;
+            for (int32_t e = g->xadj[v]; e < g->xadj[v + 1]; e++) {
+                int32_t u = g->adjncy[e];
+                if (u == v || cx->inset[u] != tag) continue;
+                gn += side[u] != side[v] ? EW(g, e) : -EW(g, e);
+            }
+            cx->gain[v] = gn;
+        }
+        int64_t run = 0, best = 0;
+        int32_t len = 0, best_len = 0, idle = 0;
+        for (;;) {
+            int32_t bv = -1;
+            for (int32_t i = 0; i < size; i++) {
+                int32_t v = S[i];
+                if (cx->locked[v] || Wt[1 - side[v]] + VW(g, v) > U[1 - side[v]]) continue;
+                if (bv < 0 || cx->gain[v] > cx->gain[bv]) bv = v;
+            }
+            if (bv < 0) break;
+            int32_t to = 1 - side[bv];
+            Wt[side[bv]] -= VW(g, bv);
+            Wt[to] += VW(g, bv);
+            side[bv] = to;
+            cx->locked[bv] = 1;
+            run += cx->gain[bv];
+            cx->log[len++] = bv;
+            for (int32_t e = g->xadj[bv]; e < g->xadj[bv + 1]; e++) {
+                int32_t u = g->adjncy[e];
+                if (u == bv || cx->inset[u] != tag) continue;
+                cx->gain[u] += side[u] == to ? -2 * EW(g, e) : 2 * EW(g, e);
+            }
+            if (run > best) {
+                best = run;
+                best_len = len;
+                idle = 0;
+            } else if (++idle >= ORC_FM_IDLE) {
+                break;
+            }
+        }
+        for (int32_t i = len - 1; i >= best_len; i--) side[cx->log[i]] ^= 1;
+        if (best <= 0) break;
+    }
 }
 
 static void rb(rb_ctx *cx, int32_t *S, int32_t size, int32_t ks, int32_t base) {
@@ -468,21 +536,26 @@ static void rb(rb_ctx *cx, int32_t *S, int32_t size, int32_t ks, int32_t base) {
             }
         }
     }
-    /* right side: S minus left, ascending */
-    for (int32_t i = 0; i < nleft; i++) cx->marked[left[i]] = 2;
+    /* sides: the grown part is the left side; optional local search; both
+       sides in ascending order */
+    for (int32_t i = 0; i < size; i++) cx->side[S[i]] = 1;
+    for (int32_t i = 0; i < nleft; i++) cx->side[left[i]] = 0;
+    if (cx->fm_passes > 0) fm2(cx, S, size, tag, (int64_t)kl * cx->lmax, (int64_t)(ks - kl) * cx->lmax);
     int32_t *right = (int32_t *)xcalloc((size_t)size, sizeof(int32_t));
     int32_t nright = 0;
-    for (int32_t i = 0; i < size; i++)
-        if (cx->marked[S[i]] != 2) right[nright++] = S[i];
-    qsort(left, (size_t)nleft, sizeof(int32_t), cmp_i32);
+    nleft = 0;
+    for (int32_t i = 0; i < size; i++) {
+        if (cx->side[S[i]] == 0) left[nleft++] = S[i];
+        else right[nright++] = S[i];
+    }
     rb(cx, left, nleft, kl, base);
     rb(cx, right, nright, ks - kl, base + kl);
     free(left);
     free(right);
 }
 
-void orc_recursive_bisection(const orc_graph *g, int32_t k, uint64_t seed, int32_t attempt,
-                             int32_t *part_out) {
+void orc_recursive_bisection(const orc_graph *g, int32_t k, uint64_t seed, int32_t attempt, int64_t lmax,
+                             int32_t fm_passes, int32_t *part_out) {
     int32_t n = g->n;
     rb_ctx cx;
     cx.g = g;
@@ -493,6 +566,12 @@ void orc_recursive_bisection(const orc_graph *g, int32_t k, uint64_t seed, int32
     cx.marked = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
     cx.queue = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
     cx.tag = 0;
+    cx.lmax = lmax;
+    cx.fm_passes = fm_passes;
+    cx.side = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
+    cx.locked = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
+    cx.log = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
+    cx.gain = (int64_t *)xcalloc((size_t)n, sizeof(int64_t));
     int32_t *S = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
     for (int32_t v = 0; v < n; v++) S[v] = v;
     rb(&cx, S, n, k, 0);
@@ -500,6 +579,10 @@ void orc_recursive_bisection(const orc_graph *g, int32_t k, uint64_t seed, int32
     free(cx.inset);
     free(cx.marked);
     free(cx.queue);
+    free(cx.side);
+    free(cx.locked);
+    free(cx.log);
+    free(cx.gain);
 }
 
 /*
@@ -542,14 +625,14 @@ int orc_rebalance(const orc_graph *g, int32_t k, int64_t lmax, int32_t *part) {
 
 /* §III-B / §IV-B: best of `attempts` tries by (imbalanced, cut, attempt index). */
 int orc_initial_partition(const orc_graph *g, int32_t k, int64_t lmax, uint64_t seed,
-                          int32_t attempts, int32_t rounds_refine, int32_t dir_alternate,
+                          int32_t attempts, int32_t rounds_refine, int32_t dir_alternate, int32_t fm_passes,
                           int32_t *part_out) {
     int32_t n = g->n;
     int32_t *P = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
     int best = -1, best_bal = 0;
     int64_t best_cut = 0;
     for (int32_t a = 0; a < attempts; a++) {
-        orc_recursive_bisection(g, k, seed, a, P);
+        orc_recursive_bisection(g, k, seed, a, lmax, fm_passes, P);
         orc_lp_refine(g, k, lmax, rounds_refine, dir_alternate, P, NULL);
         int bal = orc_rebalance(g, k, lmax, P);
         int64_t cut = orc_cut(g, P);
@@ -700,7 +783,8 @@ static void initial_with_judge(const orc_graph *gc, int32_t k, int64_t lmax, con
                                orc_result *res) {
     int32_t nc = gc->n;
     if (nc > 0)
-        orc_initial_partition(gc, k, lmax, p->seed, p->attempts, p->rounds_refine, p->dir_alternate, P);
+        orc_initial_partition(gc, k, lmax, p->seed, p->attempts, p->rounds_refine, p->dir_alternate, p->init_fm,
+                              P);
     int32_t tried = 0, kept = 0;
     int64_t pcut = -1, lcut = -1;
     if (p->init_mode == 1 && nc > 0 && nc <= p->mpnn_max_n && p->mpnn_params) {

@@ -54,6 +54,7 @@ typedef struct {
     int32_t active_set;       /* 0; bit 0: coarsening LP in active-set rounds, bit 1: uncoarsening LP */
     int32_t mls;              /* 0; g > 0: multi-try local search (g global iterations) after each level's
                                  LP refinement (oracle-only comparison mode) */
+    int32_t init_fm;          /* 0; p > 0: at most p 2-way FM passes after every initial bisection */
 } orc_params;
 
 /* §III-C multi-try k-way local search (sequential, oracle-only; readings in mls.c) */
@@ -113,14 +114,16 @@ void orc_block_weights(const orc_graph *g, const int32_t *part, int32_t k, int64
 
 uint64_t orc_mix4(uint64_t seed, uint64_t a, uint64_t base, uint64_t ks);
 
-/* Recursive BFS-grow bisection of the whole graph (one attempt). */
-void orc_recursive_bisection(const orc_graph *g, int32_t k, uint64_t seed, int32_t attempt,
-                             int32_t *part_out);
+/* Recursive BFS-grow bisection of the whole graph (one attempt); fm_passes > 0
+   runs at most that many 2-way FM passes after every bisection, a side that
+   will hold j blocks weighing at most j * lmax (F4). */
+void orc_recursive_bisection(const orc_graph *g, int32_t k, uint64_t seed, int32_t attempt, int64_t lmax,
+                             int32_t fm_passes, int32_t *part_out);
 /* Greedy rebalance; returns 1 if balanced afterwards, 0 if no move remained. */
 int orc_rebalance(const orc_graph *g, int32_t k, int64_t lmax, int32_t *part);
 /* Best of `attempts` (bisection -> lp_refine -> rebalance). Returns chosen attempt. */
 int orc_initial_partition(const orc_graph *g, int32_t k, int64_t lmax, uint64_t seed,
-                          int32_t attempts, int32_t rounds_refine, int32_t dir_alternate,
+                          int32_t attempts, int32_t rounds_refine, int32_t dir_alternate, int32_t fm_passes,
                           int32_t *part_out);
 
 /* Isolated-vertex fill; returns nothing, updates part and B. */
