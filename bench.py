@@ -247,6 +247,8 @@ def main():
                     help="initial bisection tries (the paper's configuration uses 4)")
     ap.add_argument("--active-set", type=int, default=0, choices=[0, 1, 2, 3],
                     help="active-set LP rounds: 1 coarsening, 2 refinement, 3 both (results differ from full rounds)")
+    ap.add_argument("--init-fm", type=int, default=0,
+                    help="2-way FM passes after every initial bisection (0: none; results differ)")
     ap.add_argument("--no-tuning", action="store_true",
                     help="ignore paper_1710_08231_amd/tuning/<workload>.json (use the default thresholds)")
     ap.add_argument("--no-profile", action="store_true",
@@ -288,7 +290,8 @@ def main():
         if last_warm:
             gp.profile_select(None)
             gp.profile_enable(True)
-        _, res = gp.partition(dg, k, 0.03, attempts=args.attempts, active_set=args.active_set)
+        _, res = gp.partition(dg, k, 0.03, attempts=args.attempts, active_set=args.active_set,
+                              init_fm=args.init_fm)
         if last_warm:
             entries = gp.profile_entries()
             gp.profile_enable(False)
@@ -309,7 +312,8 @@ def main():
     t = time.perf_counter()
     for i in range(args.steps):
         ts = time.perf_counter()
-        part, res = gp.partition(dg, k, 0.03, attempts=args.attempts, active_set=args.active_set)
+        part, res = gp.partition(dg, k, 0.03, attempts=args.attempts, active_set=args.active_set,
+                                 init_fm=args.init_fm)
         step_ms.append((time.perf_counter() - ts) * 1000.0)
         visits += res["edge_visits_cluster"] + res["edge_visits_refine"]
         results.append(res)
@@ -336,7 +340,7 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "nnz": nnz, "k": k, "eps": 0.03, "attempts": args.attempts,
-                   "active_set": args.active_set,
+                   "active_set": args.active_set, "init_fm": args.init_fm,
                    "tuning": TUNING},
         "partition_ms": ms,
         "cut": last["cut"],

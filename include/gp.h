@@ -99,6 +99,12 @@ typedef struct {
     const float *mpnn_params; /* NULL: device fp32 master weights, gp_mpnn_param_count(k) of them */
     int32_t active_set;     /* 0; bit 0: coarsening LP in active-set rounds (GP_LP_ACTIVE_SET), bit 1:
                                uncoarsening LP (3: both); single graphs only */
+    int32_t init_fm;        /* 0; p > 0: after every bisection of the initial partitioning, at most p passes
+                               of 2-way FM local search (§III-B: the bisection is improved by local search).
+                               Only edges inside the bisected set count; a side that will hold j blocks may
+                               weigh at most j * L_max; each pass keeps its shortest best prefix of moves
+                               and stops after 50 moves without a new best; passes end early once one
+                               gains nothing. Single graphs and batches. */
 } gp_params;
 
 typedef struct {

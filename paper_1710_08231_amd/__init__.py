@@ -58,7 +58,8 @@ class Params(ctypes.Structure):
                 ("stall_num", ctypes.c_int32), ("stall_den", ctypes.c_int32),
                 ("dir_alternate", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("init_mode", ctypes.c_int32), ("mpnn_max_n", ctypes.c_int32),
-                ("mpnn_seed", ctypes.c_uint64), ("mpnn_params", ctypes.c_void_p), ("active_set", ctypes.c_int32)]
+                ("mpnn_seed", ctypes.c_uint64), ("mpnn_params", ctypes.c_void_p), ("active_set", ctypes.c_int32),
+                ("init_fm", ctypes.c_int32)]
 
 
 class Tuning(ctypes.Structure):

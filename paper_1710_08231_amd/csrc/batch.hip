@@ -398,7 +398,7 @@ int partition_batch(const DevGraph &g0, int32_t G, const int32_t *voff_host, con
     int32_t *P = nullptr;
     GP_TRY(sc.alloc(&P, std::max(lev[T].g.n, 1)));
     GP_TRY(initial_partition_batch(lev[T].g, T == 0, bi, p->seed, p->attempts, p->rounds_refine, p->dir_alternate,
-                                   wide, P, sc));
+                                   p->init_fm, wide, P, sc));
     const float ms_init = t_init.stop();
     if (cout) return write_coarsest(lev[T].g, T == 0, P, lev[T].gid, d_kbase, lev[T].hvoff, hI, *cout, sc);
 

@@ -204,6 +204,273 @@ __global__ __launch_bounds__(kBB) void k_bisect(BisectArgs a) {
     for (int32_t p = threadIdx.x; p <= stop; p += kBB) blk[order[p]] = base;
 }
 
+// ---- 2-way FM after a bisection (§III-B: the bisection is improved by local
+// search). One workgroup per (try, subproblem), over S = the vertices of both
+// new sides (base: left, base + kl: right); only edges inside S count. A pass:
+// gains from scratch (edge-parallel over S, integer atomics), then moves one
+// at a time: the unlocked vertex of largest gain whose receiving side stays
+// within (blocks it will hold) * L_max, ties to the lowest id, found by a
+// block-wide max over S; its neighbours' gains change by -/+2w. A pass stops
+// when nothing may move or after kFmIdle moves without a new best running
+// gain; moves past the shortest best prefix are undone. Passes repeat until
+// one gains nothing. Side, lock and gain words are read with agent-scope loads
+// (they are written by this workgroup's atomics and stores within the pass).
+constexpr int kFmIdle = 50;
+
+struct FmArgs {
+    const int32_t *xadj, *adjncy, *adjwgt, *vwgt;
+    int32_t n;
+    int32_t *blk;      // [attempts * n]
+    int32_t *lock;     // [attempts * n]
+    int64_t *gain;     // [attempts * n]
+    int32_t *pos;      // [attempts * n] index in S (valid only for vertices of S)
+    int32_t *slist;    // per workgroup region: S ascending
+    int32_t *log;      // per workgroup region: moves of the pass
+    const int64_t *reg;
+    int64_t regtot;
+    const int32_t *sub_g, *sub_base, *sub_ks;
+    const int32_t *voff, *kbase;
+    const int64_t *lmax;  // [G]
+    int32_t nsub;
+    int32_t passes;
+    int32_t wide;  // connection sums may exceed 32 bits: gains stay in global int64 words
+};
+
+template <typename T>
+__device__ __forceinline__ T ld_dev(const T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+constexpr int kFmLds = 16384;  // largest S searched in LDS (9 bytes per vertex)
+
+__global__ __launch_bounds__(kBB) void k_fm(FmArgs a) {
+    __shared__ int64_t t64[kBB / kWave + 1];
+    __shared__ int32_t t32[kBB / kWave + 1];
+    __shared__ int32_t sg_[kFmLds];  // gain
+    __shared__ int32_t sw_[kFmLds];  // vertex weight
+    __shared__ uint8_t sf_[kFmLds];  // bit 0: right side, bit 1: locked
+    const int attempt = blockIdx.x / a.nsub, sp = blockIdx.x % a.nsub;
+    const int32_t gr = a.sub_g[sp];
+    const int32_t ks = a.sub_ks[sp], kl = (ks + 1) / 2;
+    const int32_t base = a.kbase[gr] + a.sub_base[sp], right = base + kl;
+    const int64_t U0 = (int64_t)kl * a.lmax[gr], U1 = (int64_t)(ks - kl) * a.lmax[gr];
+    const int32_t n = a.n;
+    const int32_t vlo = a.voff[gr], vhi = a.voff[gr + 1];
+    int32_t *blk = a.blk + (int64_t)attempt * n;
+    int32_t *lock = a.lock + (int64_t)attempt * n;
+    int64_t *gain = a.gain + (int64_t)attempt * n;
+    const int64_t rg = (int64_t)attempt * a.regtot + a.reg[sp];
+    int32_t *slist = a.slist + rg;
+    int32_t *log = a.log + rg;
+    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+
+    // ---- S ascending
+    int32_t size = 0;
+    for (int32_t v0 = vlo; v0 < vhi; v0 += kBB) {
+        const int32_t v = v0 + threadIdx.x;
+        const bool in = v < vhi && (blk[v] == base || blk[v] == right);
+        int32_t tot;
+        const int32_t ex = block_excl_scan<kBB>((int32_t)in, t32, &tot);
+        if (in) slist[size + ex] = v;
+        size += tot;
+    }
+    if (size == 0) return;
+    __syncthreads();
+
+    if (size <= kFmLds && !a.wide) {
+        // ---- the same search with gains, weights and side/lock flags in LDS,
+        // indexed by position in S (ascending ids, so the lowest position is
+        // the lowest id); neighbours are found through pos[] once blk[] says
+        // they belong to S.
+        const int32_t *pos = a.pos + (int64_t)attempt * n;
+        for (int32_t i = threadIdx.x; i < size; i += kBB) {
+            const int32_t v = slist[i];
+            a.pos[(int64_t)attempt * n + v] = i;
+            sw_[i] = (int32_t)vw(a.vwgt, v);
+            sf_[i] = blk[v] == right ? 1 : 0;
+        }
+        __syncthreads();
+        for (int32_t pass = 0; pass < a.passes; pass++) {
+            int64_t w0 = 0, wall = 0;
+            for (int32_t i = threadIdx.x; i < size; i += kBB) {
+                wall += sw_[i];
+                if (!(sf_[i] & 1)) w0 += sw_[i];
+                sf_[i] &= 1;
+                sg_[i] = 0;
+            }
+            w0 = block_sum<kBB>(w0, t64);
+            wall = block_sum<kBB>(wall, t64);
+            int64_t W0 = w0, W1 = wall - w0;
+            __syncthreads();
+            for (int32_t i = wid; i < size; i += kBB / kWave) {  // one wave per vertex
+                const int32_t v = slist[i];
+                const uint8_t sv = sf_[i] & 1;
+                int32_t acc = 0;
+                for (int32_t e = a.xadj[v] + lane; e < a.xadj[v + 1]; e += kWave) {
+                    const int32_t u = a.adjncy[e];
+                    const int32_t bu = blk[u];
+                    if (u == v || (bu != base && bu != right)) continue;
+                    const int32_t w = a.adjwgt ? a.adjwgt[e] : 1;
+                    acc += (sf_[pos[u]] & 1) != sv ? w : -w;
+                }
+                acc = wave_sum(acc);
+                if (lane == 0) sg_[i] = acc;
+            }
+            __syncthreads();
+            int64_t run = 0, best = 0;
+            int32_t len = 0, best_len = 0, idle = 0;
+            for (;;) {
+                int64_t bg = INT64_MIN;
+                int32_t bi = INT_MAX;
+                for (int32_t i = threadIdx.x; i < size; i += kBB) {
+                    const uint8_t f = sf_[i];
+                    const bool left = !(f & 1);
+                    if ((f & 2) || (left ? W1 : W0) + sw_[i] > (left ? U1 : U0)) continue;
+                    if (sg_[i] > bg) {
+                        bg = sg_[i];
+                        bi = i;
+                    }
+                }
+                const int64_t gmax = block_max<kBB>(bg, t64);
+                if (gmax == INT64_MIN) break;
+                const int32_t i = block_min<kBB>(bg == gmax ? bi : INT_MAX, t32);
+                const int32_t v = slist[i];
+                const uint8_t to = (sf_[i] & 1) ^ 1;
+                if (to) {
+                    W0 -= sw_[i];
+                    W1 += sw_[i];
+                } else {
+                    W1 -= sw_[i];
+                    W0 += sw_[i];
+                }
+                __syncthreads();  // every thread has read v's side
+                if (threadIdx.x == 0) {
+                    sf_[i] = to | 2;
+                    log[len] = i;
+                }
+                for (int32_t e = a.xadj[v] + threadIdx.x; e < a.xadj[v + 1]; e += kBB) {
+                    const int32_t u = a.adjncy[e];
+                    const int32_t bu = blk[u];
+                    if (u == v || (bu != base && bu != right)) continue;
+                    const int32_t j = pos[u];
+                    const int32_t w = a.adjwgt ? a.adjwgt[e] : 1;
+                    atomicAdd(&sg_[j], (sf_[j] & 1) == to ? -2 * w : 2 * w);
+                }
+                __syncthreads();
+                len++;
+                run += gmax;
+                if (run > best) {
+                    best = run;
+                    best_len = len;
+                    idle = 0;
+                } else if (++idle >= kFmIdle) {
+                    break;
+                }
+            }
+            for (int32_t q = best_len + threadIdx.x; q < len; q += kBB) sf_[log[q]] ^= 1;
+            __syncthreads();
+            if (best <= 0) break;
+        }
+        for (int32_t i = threadIdx.x; i < size; i += kBB) blk[slist[i]] = (sf_[i] & 1) ? right : base;
+        return;
+    }
+
+    for (int32_t pass = 0; pass < a.passes; pass++) {
+        // ---- side weights, locks and gains from scratch
+        int64_t w0 = 0, wall = 0;
+        for (int32_t i = threadIdx.x; i < size; i += kBB) {
+            const int32_t v = slist[i];
+            const int64_t c = vw(a.vwgt, v);
+            wall += c;
+            if (ld_dev(&blk[v]) == base) w0 += c;
+            lock[v] = 0;
+        }
+        w0 = block_sum<kBB>(w0, t64);
+        wall = block_sum<kBB>(wall, t64);
+        int64_t W0 = w0, W1 = wall - w0;
+        for (int32_t i = wid; i < size; i += kBB / kWave) {  // one wave per vertex
+            const int32_t v = slist[i];
+            const int32_t bv = ld_dev(&blk[v]);
+            int64_t acc = 0;
+            for (int32_t e = a.xadj[v] + lane; e < a.xadj[v + 1]; e += kWave) {
+                const int32_t u = a.adjncy[e];
+                const int32_t bu = ld_dev(&blk[u]);
+                if (u == v || (bu != base && bu != right)) continue;
+                const int64_t w = a.adjwgt ? a.adjwgt[e] : 1;
+                acc += bu != bv ? w : -w;
+            }
+            acc = wave_sum(acc);
+            if (lane == 0) gain[v] = acc;
+        }
+        __threadfence();  // locks and gains reach L2 before the agent-scope loads below
+        __syncthreads();
+
+        int64_t run = 0, best = 0;
+        int32_t len = 0, best_len = 0, idle = 0;
+        for (;;) {
+            // ---- the unlocked vertex of largest gain that fits, lowest id on ties
+            int64_t bg = INT64_MIN;
+            int32_t bv = INT_MAX;
+            for (int32_t i = threadIdx.x; i < size; i += kBB) {
+                const int32_t v = slist[i];
+                if (ld_dev(&lock[v])) continue;
+                const bool left = ld_dev(&blk[v]) == base;
+                if ((left ? W1 : W0) + vw(a.vwgt, v) > (left ? U1 : U0)) continue;
+                const int64_t gv = ld_dev(&gain[v]);
+                if (gv > bg) {  // ascending v per thread: the first of equal gains is the lowest
+                    bg = gv;
+                    bv = v;
+                }
+            }
+            const int64_t gmax = block_max<kBB>(bg, t64);
+            if (gmax == INT64_MIN) break;
+            const int32_t v = block_min<kBB>(bg == gmax ? bv : INT_MAX, t32);
+            const bool left = ld_dev(&blk[v]) == base;
+            const int32_t to = left ? right : base;
+            const int64_t c = vw(a.vwgt, v);
+            if (left) {
+                W0 -= c;
+                W1 += c;
+            } else {
+                W1 -= c;
+                W0 += c;
+            }
+            __syncthreads();  // every thread has read v's side
+            if (threadIdx.x == 0) {
+                blk[v] = to;
+                lock[v] = 1;
+                log[len] = v;
+            }
+            for (int32_t e = a.xadj[v] + threadIdx.x; e < a.xadj[v + 1]; e += kBB) {
+                const int32_t u = a.adjncy[e];
+                const int32_t bu = ld_dev(&blk[u]);
+                if (u == v || (bu != base && bu != right)) continue;
+                const int64_t w = a.adjwgt ? a.adjwgt[e] : 1;
+                atomicAdd((unsigned long long *)&gain[u], (unsigned long long)(bu == to ? -2 * w : 2 * w));
+            }
+            __threadfence();
+            __syncthreads();
+            len++;
+            run += gmax;
+            if (run > best) {
+                best = run;
+                best_len = len;
+                idle = 0;
+            } else if (++idle >= kFmIdle) {
+                break;
+            }
+        }
+        // ---- undo the moves past the best prefix (each vertex moved at most once)
+        for (int32_t i = best_len + threadIdx.x; i < len; i += kBB) {
+            const int32_t v = ld_dev(&log[i]);
+            blk[v] = ld_dev(&blk[v]) == base ? right : base;
+        }
+        __threadfence();
+        __syncthreads();
+        if (best <= 0) break;
+    }
+}
+
 __global__ void k_init_blk(int32_t n, int32_t attempts, const int32_t *xadj, bool skip_isolated, const int32_t *gid,
                            const int32_t *kbase, int32_t *blk) {
     const int64_t N = (int64_t)n * attempts;
@@ -667,8 +934,8 @@ __global__ void k_iso_serial_batch(const int32_t *iso, const int32_t *iso_first,
 }  // namespace
 
 int initial_partition_batch(const DevGraph &g, bool skip_isolated, const BatchInfo &bi, uint64_t seed,
-                            int32_t attempts, int32_t rounds_refine, int32_t dir_alternate, bool wide, int32_t *part,
-                            Scratch &sc, const int32_t *extra, ProposalOut *po) {
+                            int32_t attempts, int32_t rounds_refine, int32_t dir_alternate, int32_t fm_passes,
+                            bool wide, int32_t *part, Scratch &sc, const int32_t *extra, ProposalOut *po) {
     hipStream_t s = sc.stream();
     const int32_t n = g.n, nnz = g.nnz, G = bi.G;
     if (n == 0) return GP_OK;
@@ -725,6 +992,8 @@ int initial_partition_batch(const DevGraph &g, bool skip_isolated, const BatchIn
     GP_TRY(sc.alloc(&sb, maxsub));
     GP_TRY(sc.alloc(&sk, maxsub));
     GP_TRY(sc.alloc(&reg, maxsub));
+    int64_t *gain = nullptr;
+    if (fm_passes > 0) GP_TRY(sc.alloc(&gain, (size_t)n * attempts));
     hipLaunchKernelGGL(k_init_blk, dim3(grid_for((int64_t)n * attempts, 256, 65536)), dim3(256), 0, s, n, attempts,
                        g.xadj, skip_isolated, bi.d_gid, bi.d_kbase, blk);
     GP_LAUNCH_CHECK();
@@ -751,6 +1020,13 @@ int initial_partition_batch(const DevGraph &g, bool skip_isolated, const BatchIn
                      order, pre,   reg,      off,    sg,   sb, sk, bi.d_voff, bi.d_kbase, (int32_t)d.size(), seed};
         hipLaunchKernelGGL(k_bisect, dim3((unsigned)(d.size() * bis)), dim3(kBB), 0, s, a);
         GP_LAUNCH_CHECK();
+        if (fm_passes > 0) {
+            FmArgs fa{g.xadj, g.adjncy, g.adjwgt, g.vwgt, n,   blk,        mark,       gain,
+                      claim,  slist,    order,    reg,     off,    sg,  sb,         sk,
+                      bi.d_voff, bi.d_kbase, bi.d_lmax, (int32_t)d.size(), fm_passes, (int32_t)wide};
+            hipLaunchKernelGGL(k_fm, dim3((unsigned)(d.size() * bis)), dim3(kBB), 0, s, fa);
+            GP_LAUNCH_CHECK();
+        }
         // host vectors are reused next depth: make sure the copies have been consumed
         GP_HIP(hipStreamSynchronize(s));
     }
@@ -838,8 +1114,8 @@ int graph_ids(int32_t G, int32_t n, const int32_t *d_voff, int32_t *gid, hipStre
 }
 
 int initial_partition(const DevGraph &g, bool skip_isolated, int32_t k, int64_t lmax, uint64_t seed,
-                      int32_t attempts, int32_t rounds_refine, int32_t dir_alternate, bool wide, int32_t *part,
-                      Scratch &sc, const int32_t *extra, ProposalOut *po) {
+                      int32_t attempts, int32_t rounds_refine, int32_t dir_alternate, int32_t fm_passes, bool wide,
+                      int32_t *part, Scratch &sc, const int32_t *extra, ProposalOut *po) {
     if (g.n == 0) return GP_OK;
     BatchInfo bi;
     bi.G = 1;
@@ -861,8 +1137,8 @@ int initial_partition(const DevGraph &g, bool skip_isolated, int32_t k, int64_t 
     bi.d_kbase = dk;
     bi.d_lmax = dl;
     bi.d_gid = gid;
-    return initial_partition_batch(g, skip_isolated, bi, seed, attempts, rounds_refine, dir_alternate, wide, part, sc,
-                                   extra, po);
+    return initial_partition_batch(g, skip_isolated, bi, seed, attempts, rounds_refine, dir_alternate, fm_passes,
+                                   wide, part, sc, extra, po);
 }
 
 int fill_isolated(const DevGraph &g, int32_t k, int32_t *part, const int64_t *B, int32_t *niso_host, Scratch &sc) {

@@ -24,8 +24,9 @@ struct ProposalOut {
     std::vector<int32_t> kept;
 };
 
-// Best of `attempts` tries (recursive BFS bisection -> LP refinement ->
-// greedy rebalance) for every graph of the batch. part: [n] device output,
+// Best of `attempts` tries (recursive BFS bisection, each bisection followed
+// by at most fm_passes 2-way FM passes -> LP refinement -> greedy rebalance)
+// for every graph of the batch. part: [n] device output,
 // global block ids kbase[q] + b (-1 for vertices left out when
 // skip_isolated is set).
 // extra (optional, device [n], graph-local block ids): one more proposal that
@@ -33,13 +34,14 @@ struct ProposalOut {
 // balanced and either the best plain try is not balanced or the proposal cuts
 // no more edge weight (ties keep the proposal). `po` receives the outcome.
 int initial_partition_batch(const DevGraph &g, bool skip_isolated, const BatchInfo &bi, uint64_t seed,
-                            int32_t attempts, int32_t rounds_refine, int32_t dir_alternate, bool wide, int32_t *part,
-                            Scratch &sc, const int32_t *extra = nullptr, ProposalOut *po = nullptr);
+                            int32_t attempts, int32_t rounds_refine, int32_t dir_alternate, int32_t fm_passes,
+                            bool wide, int32_t *part, Scratch &sc, const int32_t *extra = nullptr,
+                            ProposalOut *po = nullptr);
 
 // The same for one graph (blocks [0, k)).
 int initial_partition(const DevGraph &g, bool skip_isolated, int32_t k, int64_t lmax, uint64_t seed,
-                      int32_t attempts, int32_t rounds_refine, int32_t dir_alternate, bool wide, int32_t *part,
-                      Scratch &sc, const int32_t *extra = nullptr, ProposalOut *po = nullptr);
+                      int32_t attempts, int32_t rounds_refine, int32_t dir_alternate, int32_t fm_passes, bool wide,
+                      int32_t *part, Scratch &sc, const int32_t *extra = nullptr, ProposalOut *po = nullptr);
 
 // Batched placement of vertices without neighbours: per graph q, its
 // isolated vertices (iso_first[q].. in the ascending list of all isolated

@@ -233,7 +233,7 @@ static DevGraph dev_graph(const gp_graph *g) {
 static int check_params(const gp_params *pp, int32_t k, const char *who) {
     if (pp->rounds_coarsen < 0 || pp->rounds_refine < 0 || pp->attempts < 1 || pp->coarsest_per_k < 1 ||
         pp->stall_den < 1 || pp->stall_num < 0 || (pp->init_mode != GP_INIT_PLAIN && pp->init_mode != GP_INIT_LEARNED) ||
-        pp->active_set < 0 || pp->active_set > 3) {
+        pp->active_set < 0 || pp->active_set > 3 || pp->init_fm < 0) {
         set_error((std::string(who) + ": invalid parameters").c_str());
         return GP_ERR_ARG;
     }
@@ -391,8 +391,8 @@ static int do_partition(const gp_graph *gin, int32_t k, double eps, const gp_par
         else GP_TRY(mpnn_decode(gc, k, Z, lmax, Lc == 0, prop, sc));
     }
     ProposalOut po;
-    GP_TRY(initial_partition(gc, Lc == 0, k, lmax, p->seed, p->attempts, p->rounds_refine, p->dir_alternate, wide, P,
-                             sc, prop, prop ? &po : nullptr));
+    GP_TRY(initial_partition(gc, Lc == 0, k, lmax, p->seed, p->attempts, p->rounds_refine, p->dir_alternate,
+                             p->init_fm, wide, P, sc, prop, prop ? &po : nullptr));
     int64_t plain_cut_c = -1, prop_cut_c = -1;
     int32_t kept = 0;
     if (prop) {
@@ -516,6 +516,7 @@ void gp_default_params(gp_params *p) {
     p->mpnn_seed = 0;
     p->mpnn_params = nullptr;
     p->active_set = 0;
+    p->init_fm = 0;
 }
 
 int64_t gp_lmax(int64_t total_vwgt, int32_t k, double eps) {
