@@ -65,7 +65,8 @@ struct Arena {
     };
     std::vector<Block> blocks;
     size_t cur = 0, off = 0;
-    size_t need = 0;    // bytes taken by the current call
+    size_t used = 0;    // bytes the current call holds (less what it rewound)
+    size_t need = 0;    // the current call's high-water mark of `used`
     bool grew = false;  // the current call had to add a block
     bool busy = false;
 };
@@ -85,6 +86,8 @@ class Scratch {
             a_->busy = true;
             a_->cur = 0;
             a_->off = 0;
+            a_->used = 0;
+            a_->need = 0;
         } else {
             a_ = nullptr;
         }
@@ -133,6 +136,33 @@ class Scratch {
         *out = static_cast<T *>(tmp_[slot].first);
         return GP_OK;
     }
+    // A point to come back to: everything taken after mark() is given back to
+    // this call's arena by rewind(mark), so later allocations of the same call
+    // reuse it (work is stream ordered). Reusable slots grown after the mark
+    // return to their earlier buffers.
+    struct Mark {
+        size_t cur = 0, off = 0, used = 0;
+        bool arena = false;
+        std::vector<std::pair<void *, size_t>> tmp;
+    };
+    Mark mark() const {
+        Mark m;
+        m.tmp = tmp_;
+        if (a_) {
+            m.arena = true;
+            m.cur = a_->cur;
+            m.off = a_->off;
+            m.used = a_->used;
+        }
+        return m;
+    }
+    void rewind(const Mark &m) {
+        if (!a_ || !m.arena) return;
+        a_->cur = m.cur;
+        a_->off = m.off;
+        a_->used = m.used;
+        tmp_ = m.tmp;
+    }
     void release() {
         for (void *p : ptrs_) (void)hipFreeAsync(p, s_);
         ptrs_.clear();
@@ -141,6 +171,7 @@ class Scratch {
             if (a_->grew && a_->blocks.size() > 1) consolidate();
             a_->cur = 0;
             a_->off = 0;
+            a_->used = 0;
             a_->need = 0;
             a_->grew = false;
             a_->busy = false;
@@ -173,7 +204,8 @@ class Scratch {
         else (void)hipGetLastError();  // the next call grows the cache again
     }
     int take(size_t bytes, void **p) {
-        a_->need += bytes;
+        a_->used += bytes;
+        if (a_->used > a_->need) a_->need = a_->used;
         while (a_->cur < a_->blocks.size()) {
             Arena::Block &b = a_->blocks[a_->cur];
             if (a_->off + bytes <= b.size) {

@@ -1412,6 +1412,13 @@ int label_weights(const DevGraph &g, const int32_t *labels, int64_t *W, int32_t 
 int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int64_t U, int32_t rounds,
            int32_t dir_alternate, bool wide, LPOut *out, Scratch &sc, const int64_t *capv, const uint8_t *frozen,
            const int32_t *group, int32_t ngroups, bool active) {
+    // everything below is internal to the call (results are written in place
+    // or read back to the host): its scratch is given back on every return
+    struct Rewind {
+        Scratch &sc;
+        Scratch::Mark m;
+        ~Rewind() { sc.rewind(m); }
+    } rewind_on_return{sc, sc.mark()};
     hipStream_t s = sc.stream();
     const int32_t n = g.n;
     if (n == 0 || rounds == 0) {
