@@ -652,6 +652,7 @@ int build_rowof(const DevGraph &g, int32_t *rowof, Scratch &sc) {
 }
 
 int contract(const DevGraph &g, const int32_t *labels, bool skip_isolated, CoarseOut &out, Scratch &sc) {
+    ScratchScope scope(sc);  // the outputs are caller buffers: all scratch below is internal
     hipStream_t s = sc.stream();
     const int32_t n = g.n;
     out.n = 0;

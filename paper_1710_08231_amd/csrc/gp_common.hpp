@@ -256,6 +256,18 @@ class Scratch {
     std::vector<std::pair<void *, size_t>> tmp_;
 };
 
+// Gives back, when it goes out of scope, everything its Scratch handed out
+// since the scope began (for calls whose scratch is all internal: results in
+// caller buffers or on the host).
+struct ScratchScope {
+    Scratch &sc;
+    Scratch::Mark m;
+    explicit ScratchScope(Scratch &s) : sc(s), m(s.mark()) {}
+    ~ScratchScope() { sc.rewind(m); }
+    ScratchScope(const ScratchScope &) = delete;
+    ScratchScope &operator=(const ScratchScope &) = delete;
+};
+
 // ---------------------------------------------------------------- instrumentation
 // When enabled (gp_profile_enable), selected kernel launches are bracketed by
 // HIP events on their stream; durations and the algorithmic bytes of each

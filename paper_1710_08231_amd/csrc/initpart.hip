@@ -936,6 +936,7 @@ __global__ void k_iso_serial_batch(const int32_t *iso, const int32_t *iso_first,
 int initial_partition_batch(const DevGraph &g, bool skip_isolated, const BatchInfo &bi, uint64_t seed,
                             int32_t attempts, int32_t rounds_refine, int32_t dir_alternate, int32_t fm_passes,
                             bool wide, int32_t *part, Scratch &sc, const int32_t *extra, ProposalOut *po) {
+    ScratchScope scope(sc);  // part and po are the outputs: all scratch below is internal
     hipStream_t s = sc.stream();
     const int32_t n = g.n, nnz = g.nnz, G = bi.G;
     if (n == 0) return GP_OK;

@@ -1414,11 +1414,7 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
            const int32_t *group, int32_t ngroups, bool active) {
     // everything below is internal to the call (results are written in place
     // or read back to the host): its scratch is given back on every return
-    struct Rewind {
-        Scratch &sc;
-        Scratch::Mark m;
-        ~Rewind() { sc.rewind(m); }
-    } rewind_on_return{sc, sc.mark()};
+    ScratchScope scope(sc);
     hipStream_t s = sc.stream();
     const int32_t n = g.n;
     if (n == 0 || rounds == 0) {
