@@ -178,6 +178,8 @@ class Scratch {
             a_ = nullptr;
         }
     }
+    // bytes of the stream's cache this call has held at once so far (0 without a cache)
+    size_t high_water() const { return a_ ? a_->need : 0; }
     hipStream_t stream() const { return launch_ ? launch_ : s_; }
     // Launch subsequent work on `st` (for recording a launch sequence); while
     // `frozen`, scratch slots may not grow, so nothing is allocated.

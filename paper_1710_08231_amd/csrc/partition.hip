@@ -463,10 +463,11 @@ static int do_partition(const gp_graph *gin, int32_t k, double eps, const gp_par
     const float ms_total = t_total.stop();
     if (tracing()) {
         const AllocStats &a = alloc_stats();
-        std::fprintf(stderr, "[gp] partition device %.3f ms, host %.3f ms; %lld allocations (%.1f MB) took %.3f ms of host time\n",
+        std::fprintf(stderr, "[gp] partition device %.3f ms, host %.3f ms; %lld allocations (%.1f MB) took %.3f ms of host time; scratch high-water %.1f MB\n",
                      ms_total,
                      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - host_t0).count(),
-                     (long long)(a.calls - alloc0.calls), (a.bytes - alloc0.bytes) / 1e6, a.host_ms - alloc0.host_ms);
+                     (long long)(a.calls - alloc0.calls), (a.bytes - alloc0.bytes) / 1e6, a.host_ms - alloc0.host_ms,
+                     sc.high_water() / 1e6);
     }
     int64_t maxb = 0;
     for (int b = 0; b < k; b++) maxb = std::max(maxb, hB[b]);
