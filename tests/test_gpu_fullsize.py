@@ -47,7 +47,7 @@ def _cut_numpy(g, part):
 
 
 def test_rmat22_cluster_rounds_full(rmat22):
-    # ten rounds: hub tables are built once and then follow the moves
+    # ten rounds of clustering at full size: every tier, the hub buckets, admission by radix sort
     g, dg = rmat22
     U = _ucl(g, 16)
     lab, st = gp.lp_cluster(dg, U, 10)
