@@ -191,8 +191,10 @@ class Scratch {
   private:
     static constexpr size_t kMinBlock = size_t(512) << 20;
     // After a call that had to grow the cache, replace its blocks by one block
-    // of the call's total, so a call with the same needs fits without gaps and
-    // the cache stays at one high-water mark instead of accumulating blocks.
+    // of the call's high-water mark plus 1/16, so a call with the same needs
+    // fits without gaps (also when its needs vary by a little: growing again
+    // means freeing, trimming and mapping the whole cache anew, seconds of host
+    // time for tens of GB) and the cache does not accumulate blocks.
     void consolidate() {
         for (auto &b : a_->blocks) (void)hipFreeAsync(b.p, s_);
         a_->blocks.clear();
@@ -202,7 +204,8 @@ class Scratch {
         if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess)
             (void)hipMemPoolTrimTo(pool, 0);
         void *q = nullptr;
-        if (timed_malloc_async(&q, a_->need, s_) == hipSuccess) a_->blocks.push_back({static_cast<char *>(q), a_->need});
+        const size_t size = a_->need + a_->need / 16;
+        if (timed_malloc_async(&q, size, s_) == hipSuccess) a_->blocks.push_back({static_cast<char *>(q), size});
         else (void)hipGetLastError();  // the next call grows the cache again
     }
     int take(size_t bytes, void **p) {
