@@ -51,3 +51,34 @@ def test_strerror_messages(lib):
     lib.gp_strerror.restype = ctypes.c_char_p
     assert b"argument" in lib.gp_strerror(-1)
     assert b"overflow" in lib.gp_strerror(-4)
+
+
+def _header_struct_fields(name):
+    src = open(os.path.join(ROOT, "include", "gp.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    body = re.search(r"typedef struct\s*\{([^}]*)\}\s*" + name + r"\s*;", src).group(1)
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if decl:  # "type a" or "type a, b, c" (array bounds allowed)
+            for part in decl.split(","):
+                fields.append(re.search(r"(\w+)\s*(\[\s*\d+\s*\])?$", part.strip()).group(1))
+    return fields
+
+
+@pytest.mark.parametrize("cls,name", [(gp.Graph, "gp_graph"), (gp.LPStats, "gp_lp_stats"),
+                                      (gp.Params, "gp_params"), (gp.Result, "gp_result"),
+                                      (gp.Tuning, "gp_tuning")])
+def test_binding_structs_match_header(cls, name):
+    # the ctypes mirrors list the header's fields in the header's order
+    assert [f for f, _ in cls._fields_] == _header_struct_fields(name)
+
+
+def test_default_params_host_function(lib):
+    p = gp.Params()
+    lib.gp_default_params.argtypes = [ctypes.POINTER(gp.Params)]
+    lib.gp_default_params(ctypes.byref(p))
+    assert (p.rounds_coarsen, p.rounds_refine, p.coarsest_per_k, p.attempts) == (10, 25, 60, 4)
+    assert (p.stall_num, p.stall_den, p.dir_alternate, p.seed) == (19, 20, 1, 0)
+    assert (p.init_mode, p.mpnn_max_n, p.mpnn_seed, p.mpnn_params) == (0, 131072, 0, None)
+    assert (p.active_set, p.init_fm) == (0, 0)
