@@ -249,6 +249,8 @@ __global__ __launch_bounds__(kBB) void k_fm(FmArgs a) {
     __shared__ int32_t sg_[kFmLds];  // gain
     __shared__ int32_t sw_[kFmLds];  // vertex weight
     __shared__ uint8_t sf_[kFmLds];  // bit 0: right side, bit 1: locked
+    __shared__ unsigned long long tu[kBB / kWave + 1];
+    static_assert(kFmLds <= 0xFFFF + 1, "positions are packed into 16 bits");
     const int attempt = blockIdx.x / a.nsub, sp = blockIdx.x % a.nsub;
     const int32_t gr = a.sub_g[sp];
     const int32_t ks = a.sub_ks[sp], kl = (ks + 1) / 2;
@@ -320,22 +322,25 @@ __global__ __launch_bounds__(kBB) void k_fm(FmArgs a) {
             int64_t run = 0, best = 0;
             int32_t len = 0, best_len = 0, idle = 0;
             for (;;) {
-                int64_t bg = INT64_MIN;
-                int32_t bi = INT_MAX;
+                // one key per candidate, largest wins: gain (sign bit flipped
+                // for unsigned order), then the lowest position, then its side
+                // (so no thread reads the mover's flags after the max); 0 = none
+                unsigned long long bk = 0;
                 for (int32_t i = threadIdx.x; i < size; i += kBB) {
                     const uint8_t f = sf_[i];
                     const bool left = !(f & 1);
                     if ((f & 2) || (left ? W1 : W0) + sw_[i] > (left ? U1 : U0)) continue;
-                    if (sg_[i] > bg) {
-                        bg = sg_[i];
-                        bi = i;
-                    }
+                    const unsigned long long key =
+                        ((unsigned long long)((uint32_t)sg_[i] ^ 0x80000000u) << 32) |
+                        ((unsigned long long)(0xFFFFu - (uint32_t)i) << 1) | (unsigned long long)(f & 1);
+                    bk = key > bk ? key : bk;
                 }
-                const int64_t gmax = block_max<kBB>(bg, t64);
-                if (gmax == INT64_MIN) break;
-                const int32_t i = block_min<kBB>(bg == gmax ? bi : INT_MAX, t32);
+                bk = block_max<kBB>(bk, tu);
+                if (bk == 0) break;
+                const int64_t gmax = (int32_t)((uint32_t)(bk >> 32) ^ 0x80000000u);
+                const int32_t i = (int32_t)(0xFFFFu - (uint32_t)((bk >> 1) & 0xFFFFu));
                 const int32_t v = slist[i];
-                const uint8_t to = (sf_[i] & 1) ^ 1;
+                const uint8_t to = (uint8_t)((bk & 1) ^ 1);
                 if (to) {
                     W0 -= sw_[i];
                     W1 += sw_[i];
@@ -343,7 +348,6 @@ __global__ __launch_bounds__(kBB) void k_fm(FmArgs a) {
                     W1 -= sw_[i];
                     W0 += sw_[i];
                 }
-                __syncthreads();  // every thread has read v's side
                 if (threadIdx.x == 0) {
                     sf_[i] = to | 2;
                     log[len] = i;
