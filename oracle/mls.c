@@ -170,24 +170,146 @@ static void hash_order(int32_t *list, int32_t len, uint64_t seed, int32_t gi, in
     free(o);
 }
 
-int64_t orc_mls(const orc_graph *g, int32_t k, int64_t lmax, int32_t *part, uint64_t seed, int32_t global_iters,
-                double alpha, int32_t max_idle, orc_mls_stats *st) {
+/* state shared by the searches of one call */
+typedef struct {
+    const orc_graph *g;
+    int32_t k;
+    int64_t lmax;
+    int32_t *part;
+    int64_t *B;
+    int64_t *conn;
+    uint8_t *marked;
+    int32_t *marklist;
+    int32_t nmark;
+    int32_t *logv, *logf;
+    heap_t h;
+    int32_t max_idle;
+} mls_ctx;
+
+/*
+ * One search from seed s on (part, B): queue s and its unmarked neighbours,
+ * move the vertex of largest gain while the stopping rule allows, then
+ * restore the best prefix. Returns its gain; logv/logf[0 .. *nbest) hold the
+ * kept moves (vertex, block it left). Vertices it queued are appended to
+ * marklist.
+ */
+static int64_t mls_search(mls_ctx *c, int32_t s, int32_t *nbest) {
+    const orc_graph *g = c->g;
+    heap_t *h = &c->h;
+    int32_t *part = c->part;
+    int64_t *B = c->B;
+    for (int32_t q = -1; q < g->xadj[s + 1] - g->xadj[s]; q++) {
+        const int32_t u = q < 0 ? s : g->adjncy[g->xadj[s] + q];
+        if (c->marked[u]) continue;
+        c->marked[u] = 1;
+        c->marklist[c->nmark++] = u;
+        int32_t t;
+        int ok;
+        const int64_t gn = gain_of(g, part, B, c->k, c->lmax, u, c->conn, &t, &ok);
+        if (ok) heap_push(h, gn, u);
+    }
+    int32_t nlog = 0, bestlen = 0, idle = 0;
+    int64_t cum = 0, best = 0;
+    while (h->size > 0) {
+        const int32_t w = h->ver[0];
+        const int64_t key = h->key[0];
+        int32_t t;
+        int ok;
+        const int64_t gn = gain_of(g, part, B, c->k, c->lmax, w, c->conn, &t, &ok);
+        if (!ok) {
+            heap_remove(h, w);
+            continue;
+        }
+        if (gn != key) {
+            heap_update(h, w, gn);
+            continue;
+        }
+        heap_remove(h, w);
+        c->logv[nlog] = w;
+        c->logf[nlog] = part[w];
+        nlog++;
+        B[part[w]] -= VW(g, w);
+        B[t] += VW(g, w);
+        part[w] = t;
+        cum += gn;
+        if (cum > best) {
+            best = cum;
+            bestlen = nlog;
+            idle = 0;
+        } else if (++idle >= c->max_idle) {
+            break;
+        }
+        for (int32_t e = g->xadj[w]; e < g->xadj[w + 1]; e++) {
+            const int32_t u = g->adjncy[e];
+            if (h->pos[u] >= 0) {
+                int32_t tu;
+                int oku;
+                const int64_t gu = gain_of(g, part, B, c->k, c->lmax, u, c->conn, &tu, &oku);
+                if (oku) heap_update(h, u, gu);
+                else heap_remove(h, u);
+            } else if (!c->marked[u]) {
+                c->marked[u] = 1;
+                c->marklist[c->nmark++] = u;
+                int32_t tu;
+                int oku;
+                const int64_t gu = gain_of(g, part, B, c->k, c->lmax, u, c->conn, &tu, &oku);
+                if (oku) heap_push(h, gu, u);
+            }
+        }
+    }
+    while (h->size > 0) heap_remove(h, h->ver[0]);
+    for (int32_t i = nlog - 1; i >= bestlen; i--) {
+        const int32_t w = c->logv[i];
+        B[part[w]] -= VW(g, w);
+        B[c->logf[i]] += VW(g, w);
+        part[w] = c->logf[i];
+    }
+    *nbest = bestlen;
+    return best;
+}
+
+/* growable int32 array */
+typedef struct {
+    int32_t *a;
+    int64_t len, cap;
+} vec32;
+static void vpush(vec32 *v, int32_t x) {
+    if (v->len == v->cap) {
+        v->cap = v->cap ? 2 * v->cap : 1024;
+        v->a = (int32_t *)realloc(v->a, sizeof(int32_t) * (size_t)v->cap);
+        if (!v->a) abort();
+    }
+    v->a[v->len++] = x;
+}
+
+int64_t orc_mls_batched(const orc_graph *g, int32_t k, int64_t lmax, int32_t *part, uint64_t seed,
+                        int32_t global_iters, double alpha, int32_t max_idle, int32_t batch, orc_mls_stats *st) {
     const int32_t n = g->n;
-    int64_t *B = (int64_t *)xcalloc((size_t)k, sizeof(int64_t));
-    for (int32_t v = 0; v < n; v++) B[part[v]] += VW(g, v);
-    int64_t *conn = (int64_t *)xcalloc((size_t)k, sizeof(int64_t));
-    uint8_t *marked = (uint8_t *)xcalloc((size_t)n, 1);
-    int32_t *marklist = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
+    mls_ctx c;
+    c.g = g;
+    c.k = k;
+    c.lmax = lmax;
+    c.part = part;
+    c.B = (int64_t *)xcalloc((size_t)k, sizeof(int64_t));
+    for (int32_t v = 0; v < n; v++) c.B[part[v]] += VW(g, v);
+    c.conn = (int64_t *)xcalloc((size_t)k, sizeof(int64_t));
+    c.marked = (uint8_t *)xcalloc((size_t)n, 1);
+    c.marklist = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
+    c.nmark = 0;
+    c.logv = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
+    c.logf = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
+    c.h.key = (int64_t *)xcalloc((size_t)n, sizeof(int64_t));
+    c.h.ver = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
+    c.h.pos = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
+    c.h.size = 0;
+    c.max_idle = max_idle;
+    for (int32_t v = 0; v < n; v++) c.h.pos[v] = -1;
+    int64_t *B = c.B;
     int32_t *todo = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
     int32_t *next = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
-    int32_t *logv = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
-    int32_t *logf = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
-    heap_t h;
-    h.key = (int64_t *)xcalloc((size_t)n, sizeof(int64_t));
-    h.ver = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
-    h.pos = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
-    h.size = 0;
-    for (int32_t v = 0; v < n; v++) h.pos[v] = -1;
+    int32_t *seeds = (int32_t *)xcalloc((size_t)(batch > 0 ? batch : 1), sizeof(int32_t));
+    int64_t *mstart = (int64_t *)xcalloc((size_t)(batch > 0 ? batch : 1) + 1, sizeof(int64_t));
+    vec32 bmarks = {0}, mv_v = {0}, mv_f = {0}, mv_t = {0};
     int64_t total = 0, searches = 0, kept_moves = 0, local_iters = 0;
 
     for (int32_t gi = 0; gi < global_iters; gi++) {
@@ -201,85 +323,101 @@ int64_t orc_mls(const orc_graph *g, int32_t k, int64_t lmax, int32_t *part, uint
         int64_t gtotal = 0;
         for (int32_t li = 0;; li++) {
             local_iters++;
-            int32_t nmark = 0, nnext = 0;
+            int32_t nnext = 0;
             int64_t lgain = 0;
-            for (int32_t ti = 0; ti < ntodo; ti++) {
-                const int32_t s = todo[ti];
-                if (marked[s]) continue;
-                searches++;
-                /* queue v and its unmarked neighbours */
-                for (int32_t q = -1; q < g->xadj[s + 1] - g->xadj[s]; q++) {
-                    const int32_t u = q < 0 ? s : g->adjncy[g->xadj[s] + q];
-                    if (marked[u]) continue;
-                    marked[u] = 1;
-                    marklist[nmark++] = u;
-                    int32_t t;
-                    int ok;
-                    const int64_t gn = gain_of(g, part, B, k, lmax, u, conn, &t, &ok);
-                    if (ok) heap_push(&h, gn, u);
+            c.nmark = 0;
+            if (batch <= 0) {
+                /* sequential: every search sees the moves and marks of the ones before */
+                for (int32_t ti = 0; ti < ntodo; ti++) {
+                    const int32_t s = todo[ti];
+                    if (c.marked[s]) continue;
+                    searches++;
+                    int32_t bl;
+                    const int64_t best = mls_search(&c, s, &bl);
+                    for (int32_t i = 0; i < bl; i++) next[nnext++] = c.logv[i];
+                    lgain += best;
+                    kept_moves += bl;
                 }
-                int32_t nlog = 0, bestlen = 0, idle = 0;
-                int64_t cum = 0, best = 0;
-                while (h.size > 0) {
-                    const int32_t w = h.ver[0];
-                    const int64_t key = h.key[0];
-                    int32_t t;
-                    int ok;
-                    const int64_t gn = gain_of(g, part, B, k, lmax, w, conn, &t, &ok);
-                    if (!ok) {
-                        heap_remove(&h, w);
-                        continue;
+            } else {
+                /* batches of `batch` searches from the same state and marks; their
+                   kept prefixes are then applied in seed order with recomputed gains */
+                int32_t ti = 0;
+                while (ti < ntodo) {
+                    int32_t ns = 0;
+                    while (ti < ntodo && ns < batch) {
+                        const int32_t s = todo[ti++];
+                        if (!c.marked[s]) seeds[ns++] = s;
                     }
-                    if (gn != key) {
-                        heap_update(&h, w, gn);
-                        continue;
+                    if (ns == 0) break;
+                    bmarks.len = mv_v.len = mv_f.len = mv_t.len = 0;
+                    for (int32_t j = 0; j < ns; j++) {
+                        searches++;
+                        const int32_t mark0 = c.nmark;
+                        int32_t bl;
+                        (void)mls_search(&c, seeds[j], &bl);
+                        mstart[j] = mv_v.len;
+                        for (int32_t i = 0; i < bl; i++) {
+                            vpush(&mv_v, c.logv[i]);
+                            vpush(&mv_f, c.logf[i]);
+                            vpush(&mv_t, part[c.logv[i]]);
+                        }
+                        /* back to the batch's state, and its marks kept aside */
+                        for (int32_t i = bl - 1; i >= 0; i--) {
+                            const int32_t w = c.logv[i];
+                            B[part[w]] -= VW(g, w);
+                            B[c.logf[i]] += VW(g, w);
+                            part[w] = c.logf[i];
+                        }
+                        for (int32_t i = mark0; i < c.nmark; i++) {
+                            c.marked[c.marklist[i]] = 0;
+                            vpush(&bmarks, c.marklist[i]);
+                        }
+                        c.nmark = mark0;
                     }
-                    heap_remove(&h, w);
-                    logv[nlog] = w;
-                    logf[nlog] = part[w];
-                    nlog++;
-                    B[part[w]] -= VW(g, w);
-                    B[t] += VW(g, w);
-                    part[w] = t;
-                    cum += gn;
-                    if (cum > best) {
-                        best = cum;
-                        bestlen = nlog;
-                        idle = 0;
-                    } else if (++idle >= max_idle) {
-                        break;
-                    }
-                    for (int32_t e = g->xadj[w]; e < g->xadj[w + 1]; e++) {
-                        const int32_t u = g->adjncy[e];
-                        if (h.pos[u] >= 0) {
-                            int32_t tu;
-                            int oku;
-                            const int64_t gu = gain_of(g, part, B, k, lmax, u, conn, &tu, &oku);
-                            if (oku) heap_update(&h, u, gu);
-                            else heap_remove(&h, u);
-                        } else if (!marked[u]) {
-                            marked[u] = 1;
-                            marklist[nmark++] = u;
-                            int32_t tu;
-                            int oku;
-                            const int64_t gu = gain_of(g, part, B, k, lmax, u, conn, &tu, &oku);
-                            if (oku) heap_push(&h, gu, u);
+                    mstart[ns] = mv_v.len;
+                    for (int64_t i = 0; i < bmarks.len; i++) {
+                        const int32_t u = bmarks.a[i];
+                        if (!c.marked[u]) {
+                            c.marked[u] = 1;
+                            c.marklist[c.nmark++] = u;
                         }
                     }
+                    for (int32_t j = 0; j < ns; j++) {
+                        int64_t cum = 0, best = 0;
+                        int32_t na = 0, bestlen = 0;
+                        for (int64_t m = mstart[j]; m < mstart[j + 1]; m++) {
+                            const int32_t v = mv_v.a[m], f = mv_f.a[m], t = mv_t.a[m];
+                            if (part[v] != f || B[t] + VW(g, v) > lmax) break;
+                            int64_t ct = 0, cf = 0;
+                            for (int32_t e = g->xadj[v]; e < g->xadj[v + 1]; e++) {
+                                const int32_t pu = part[g->adjncy[e]];
+                                if (pu == t) ct += EW(g, e);
+                                else if (pu == f) cf += EW(g, e);
+                            }
+                            B[f] -= VW(g, v);
+                            B[t] += VW(g, v);
+                            part[v] = t;
+                            na++;
+                            cum += ct - cf;
+                            if (cum > best) {
+                                best = cum;
+                                bestlen = na;
+                            }
+                        }
+                        for (int32_t i = na - 1; i >= bestlen; i--) {
+                            const int64_t m = mstart[j] + i;
+                            const int32_t v = mv_v.a[m];
+                            B[part[v]] -= VW(g, v);
+                            B[mv_f.a[m]] += VW(g, v);
+                            part[v] = mv_f.a[m];
+                        }
+                        for (int32_t i = 0; i < bestlen; i++) next[nnext++] = mv_v.a[mstart[j] + i];
+                        lgain += best;
+                        kept_moves += bestlen;
+                    }
                 }
-                while (h.size > 0) heap_remove(&h, h.ver[0]);
-                /* restore the best partition of the search */
-                for (int32_t i = nlog - 1; i >= bestlen; i--) {
-                    const int32_t w = logv[i];
-                    B[part[w]] -= VW(g, w);
-                    B[logf[i]] += VW(g, w);
-                    part[w] = logf[i];
-                }
-                for (int32_t i = 0; i < bestlen; i++) next[nnext++] = logv[i];
-                lgain += best;
-                kept_moves += bestlen;
             }
-            for (int32_t i = 0; i < nmark; i++) marked[marklist[i]] = 0;
+            for (int32_t i = 0; i < c.nmark; i++) c.marked[c.marklist[i]] = 0;
             total += lgain;
             /* another local iteration around the moved vertices while it pays */
             if (lgain > 0 && (double)lgain > alpha * (double)gtotal) {
@@ -299,16 +437,27 @@ int64_t orc_mls(const orc_graph *g, int32_t k, int64_t lmax, int32_t *part, uint
         st->moves = kept_moves;
         st->local_iters = local_iters;
     }
-    free(B);
-    free(conn);
-    free(marked);
-    free(marklist);
+    free(c.B);
+    free(c.conn);
+    free(c.marked);
+    free(c.marklist);
+    free(c.logv);
+    free(c.logf);
+    free(c.h.key);
+    free(c.h.ver);
+    free(c.h.pos);
     free(todo);
     free(next);
-    free(logv);
-    free(logf);
-    free(h.key);
-    free(h.ver);
-    free(h.pos);
+    free(seeds);
+    free(mstart);
+    free(bmarks.a);
+    free(mv_v.a);
+    free(mv_f.a);
+    free(mv_t.a);
     return total;
+}
+
+int64_t orc_mls(const orc_graph *g, int32_t k, int64_t lmax, int32_t *part, uint64_t seed, int32_t global_iters,
+                double alpha, int32_t max_idle, orc_mls_stats *st) {
+    return orc_mls_batched(g, k, lmax, part, seed, global_iters, alpha, max_idle, 0, st);
 }

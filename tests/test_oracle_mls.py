@@ -94,3 +94,36 @@ def test_partition_with_mls_is_balanced_and_better():
         p1, r1 = oracle.partition(g, k, mls=3)
         assert r1["balanced"] == 1 and oracle.cut(g, p1) == r1["cut"]
         assert r1["cut"] < r0["cut"]
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_batched_mls_of_one_is_sequential(seed):
+    # searches in batches of one see every earlier move and mark, and the
+    # recomputed gains of a kept prefix equal the search's own: the result
+    # is the sequential one, statistics included
+    g = graphgen.random_small(300, 0.04, seed, wmax=6, vmax=3)
+    k = 5
+    lm = oracle.lmax(int(g["vwgt"].sum()), k, 0.03)
+    part, _ = oracle.partition(g, k)
+    a, sa = oracle.mls(g, part, k, lm, seed=seed)
+    b, sb = oracle.mls(g, part, k, lm, seed=seed, batch=1)
+    assert np.array_equal(a, b) and sa == sb
+
+
+@pytest.mark.parametrize("batch", [2, 16, 10 ** 6])
+def test_batched_mls_invariants(batch):
+    # searches of a batch start from the same state; their prefixes are
+    # applied in seed order with recomputed gains, so the reported gain is
+    # the exact cut change and no move breaks L_max
+    g = graphgen.rgg2d(3000, 4)
+    k = 8
+    lm = oracle.lmax(3000, k, 0.03)
+    part, _ = oracle.partition(g, k)
+    c0 = oracle.cut(g, part)
+    P, st = oracle.mls(g, part, k, lm, seed=3, batch=batch)
+    assert np.bincount(P, minlength=k).max() <= lm
+    assert st["gain"] >= 0 and oracle.cut(g, P) == c0 - st["gain"]
+    P2, st2 = oracle.mls(g, part, k, lm, seed=3, batch=batch)
+    assert np.array_equal(P, P2) and st == st2
+    p, r = oracle.partition(g, k, mls=3, mls_batch=batch)
+    assert r["balanced"] == 1 and oracle.cut(g, p) == r["cut"]
