@@ -1,7 +1,10 @@
 /*
  * mls.c — multi-try k-way local search (MLS), oracle-only (test
  * infrastructure; see oracle.h). Sequential form of §III-C, used to measure
- * what the GPU path's LP-only refinement leaves on the table.
+ * what the GPU path's LP-only refinement leaves on the table, and a batched
+ * form of §IV-C's parallel MLS (orc_mls_batched): searches of a batch start
+ * from the same partition and marks, then their kept prefixes are replayed in
+ * seed order with recomputed gains; a batch of one is the sequential search.
  *
  * What the paper fixes (§III-C, Algorithm 1 of §IV-C for the iteration
  * control):
