@@ -40,7 +40,7 @@ class _Params(ctypes.Structure):
                 ("init_mode", ctypes.c_int32), ("mpnn_max_n", ctypes.c_int32),
                 ("mpnn_seed", ctypes.c_uint64), ("mpnn_params", ctypes.POINTER(ctypes.c_float)),
                 ("lp_async", ctypes.c_int32), ("active_set", ctypes.c_int32), ("mls", ctypes.c_int32),
-                ("init_fm", ctypes.c_int32), ("mls_batch", ctypes.c_int32)]
+                ("init_fm", ctypes.c_int32), ("mls_batch", ctypes.c_int32), ("mls_queue", ctypes.c_int32)]
 
 
 class _Result(ctypes.Structure):
@@ -186,10 +186,11 @@ class _MLSStats(ctypes.Structure):
                 ("local_iters", ctypes.c_int64)]
 
 
-def mls(g, part, k, lmax_, seed=0, global_iters=3, alpha=0.1, max_idle=50, batch=0):
+def mls(g, part, k, lmax_, seed=0, global_iters=3, alpha=0.1, max_idle=50, batch=0, max_queue=0):
     """§III-C multi-try local search from a partition (oracle-only); returns (part', stats).
     batch > 0: searches in batches that start from the same state, their kept moves
-    applied in seed order with recomputed gains (§IV-C); batch = 1 equals batch = 0."""
+    applied in seed order with recomputed gains (§IV-C); batch = 1 equals batch = 0.
+    max_queue > 0 bounds the vertices one search may queue."""
     G = _G(g)
     P = _i32(part).copy()
     st = _MLSStats()
@@ -197,8 +198,9 @@ def mls(g, part, k, lmax_, seed=0, global_iters=3, alpha=0.1, max_idle=50, batch
     lib.orc_mls_batched.restype = ctypes.c_int64
     lib.orc_mls_batched.argtypes = [ctypes.POINTER(_Graph), ctypes.c_int32, ctypes.c_int64, I32P, ctypes.c_uint64,
                                     ctypes.c_int32, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
-                                    ctypes.POINTER(_MLSStats)]
-    lib.orc_mls_batched(G.ref, k, lmax_, _p32(P), seed, global_iters, alpha, max_idle, batch, ctypes.byref(st))
+                                    ctypes.c_int32, ctypes.POINTER(_MLSStats)]
+    lib.orc_mls_batched(G.ref, k, lmax_, _p32(P), seed, global_iters, alpha, max_idle, batch, max_queue,
+                        ctypes.byref(st))
     return P, {f: getattr(st, f) for f, _ in _MLSStats._fields_}
 
 
@@ -315,7 +317,7 @@ def fill_isolated(g, k, part, B):
 DEFAULT_PARAMS = dict(rounds_coarsen=10, rounds_refine=25, coarsest_per_k=60, attempts=4,
                       stall_num=19, stall_den=20, dir_alternate=1, seed=0, init_mode=0,
                       mpnn_max_n=131072, mpnn_seed=0, mpnn_params=None, lp_async=0, active_set=0, mls=0,
-                      init_fm=0, mls_batch=0)
+                      init_fm=0, mls_batch=0, mls_queue=0)
 
 
 def _params(params):

@@ -187,6 +187,7 @@ typedef struct {
     int32_t *logv, *logf;
     heap_t h;
     int32_t max_idle;
+    int32_t max_queue;  /* 0: unbounded; q > 0: a search queues at most q vertices */
 } mls_ctx;
 
 /*
@@ -201,9 +202,12 @@ static int64_t mls_search(mls_ctx *c, int32_t s, int32_t *nbest) {
     heap_t *h = &c->h;
     int32_t *part = c->part;
     int64_t *B = c->B;
+    int32_t queued = 0;  /* vertices this search marked (a vertex past the bound stays unmarked) */
     for (int32_t q = -1; q < g->xadj[s + 1] - g->xadj[s]; q++) {
         const int32_t u = q < 0 ? s : g->adjncy[g->xadj[s] + q];
         if (c->marked[u]) continue;
+        if (c->max_queue > 0 && queued >= c->max_queue) break;
+        queued++;
         c->marked[u] = 1;
         c->marklist[c->nmark++] = u;
         int32_t t;
@@ -250,7 +254,8 @@ static int64_t mls_search(mls_ctx *c, int32_t s, int32_t *nbest) {
                 const int64_t gu = gain_of(g, part, B, c->k, c->lmax, u, c->conn, &tu, &oku);
                 if (oku) heap_update(h, u, gu);
                 else heap_remove(h, u);
-            } else if (!c->marked[u]) {
+            } else if (!c->marked[u] && (c->max_queue <= 0 || queued < c->max_queue)) {
+                queued++;
                 c->marked[u] = 1;
                 c->marklist[c->nmark++] = u;
                 int32_t tu;
@@ -286,7 +291,8 @@ static void vpush(vec32 *v, int32_t x) {
 }
 
 int64_t orc_mls_batched(const orc_graph *g, int32_t k, int64_t lmax, int32_t *part, uint64_t seed,
-                        int32_t global_iters, double alpha, int32_t max_idle, int32_t batch, orc_mls_stats *st) {
+                        int32_t global_iters, double alpha, int32_t max_idle, int32_t batch, int32_t max_queue,
+                        orc_mls_stats *st) {
     const int32_t n = g->n;
     mls_ctx c;
     c.g = g;
@@ -306,6 +312,7 @@ int64_t orc_mls_batched(const orc_graph *g, int32_t k, int64_t lmax, int32_t *pa
     c.h.pos = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
     c.h.size = 0;
     c.max_idle = max_idle;
+    c.max_queue = max_queue;
     for (int32_t v = 0; v < n; v++) c.h.pos[v] = -1;
     int64_t *B = c.B;
     int32_t *todo = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
@@ -462,5 +469,5 @@ int64_t orc_mls_batched(const orc_graph *g, int32_t k, int64_t lmax, int32_t *pa
 
 int64_t orc_mls(const orc_graph *g, int32_t k, int64_t lmax, int32_t *part, uint64_t seed, int32_t global_iters,
                 double alpha, int32_t max_idle, orc_mls_stats *st) {
-    return orc_mls_batched(g, k, lmax, part, seed, global_iters, alpha, max_idle, 0, st);
+    return orc_mls_batched(g, k, lmax, part, seed, global_iters, alpha, max_idle, 0, 0, st);
 }

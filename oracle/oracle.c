@@ -870,7 +870,8 @@ int orc_partition(const orc_graph *g, int32_t k, double eps, const orc_params *p
         else orc_lp_refine(&lev[l].g, k, lmax, p->rounds_refine,
                            lp_flags(p) | ((p->active_set & 2) ? ORC_LP_ACTIVE_SET : 0), P, &st);
         ev_refine += st.edge_visits;
-        if (p->mls > 0) orc_mls_batched(&lev[l].g, k, lmax, P, p->seed, p->mls, 0.1, 50, p->mls_batch, NULL);
+        if (p->mls > 0) orc_mls_batched(&lev[l].g, k, lmax, P, p->seed, p->mls, 0.1, 50, p->mls_batch,
+                                        p->mls_queue, NULL);
     }
 
     /* back to original ids, then place the isolated vertices */

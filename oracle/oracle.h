@@ -56,6 +56,7 @@ typedef struct {
                                  LP refinement (oracle-only comparison mode) */
     int32_t init_fm;          /* 0; p > 0: at most p 2-way FM passes after every initial bisection */
     int32_t mls_batch;        /* 0: sequential MLS; b > 0: searches in batches of b (orc_mls_batched) */
+    int32_t mls_queue;        /* 0: unbounded; q > 0: an MLS search queues at most q vertices */
 } orc_params;
 
 /* §III-C multi-try k-way local search (sequential, oracle-only; readings in mls.c) */
@@ -71,9 +72,11 @@ int64_t orc_mls(const orc_graph *g, int32_t k, int64_t lmax, int32_t *part, uint
    batch start from the same partition and marks, and their kept prefixes are then
    applied in seed order with recomputed gains, each cut at its first move whose
    vertex has left its block or whose target is full, and kept up to its best
-   recomputed prefix (§IV-C, ApplyMoves). batch = 1 gives the sequential result. */
+   recomputed prefix (§IV-C, ApplyMoves). batch = 1 gives the sequential result.
+   max_queue > 0 bounds the vertices one search may queue (0: unbounded). */
 int64_t orc_mls_batched(const orc_graph *g, int32_t k, int64_t lmax, int32_t *part, uint64_t seed,
-                        int32_t global_iters, double alpha, int32_t max_idle, int32_t batch, orc_mls_stats *st);
+                        int32_t global_iters, double alpha, int32_t max_idle, int32_t batch, int32_t max_queue,
+                        orc_mls_stats *st);
 /* gain of moving v to its best feasible adjacent block (*target, -1 if none) */
 int64_t orc_mls_gain(const orc_graph *g, const int32_t *part, const int64_t *B, int32_t k, int64_t lmax, int32_t v,
                      int32_t *target);

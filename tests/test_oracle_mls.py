@@ -127,3 +127,27 @@ def test_batched_mls_invariants(batch):
     assert np.array_equal(P, P2) and st == st2
     p, r = oracle.partition(g, k, mls=3, mls_batch=batch)
     assert r["balanced"] == 1 and oracle.cut(g, p) == r["cut"]
+
+
+@pytest.mark.parametrize("q", [1, 8, 64])
+def test_mls_queue_bound(q):
+    g = graphgen.rmat(11, 5)
+    n = len(g["xadj"]) - 1
+    k = 8
+    lm = oracle.lmax(n, k, 0.03)
+    part, _ = oracle.partition(g, k)
+    c0 = oracle.cut(g, part)
+    # a bound the searches never reach changes nothing
+    a, sa = oracle.mls(g, part, k, lm, seed=2)
+    b, sb = oracle.mls(g, part, k, lm, seed=2, max_queue=n + 1)
+    assert np.array_equal(a, b) and sa == sb
+    # bounded searches, alone or in batches: exact gains, L_max kept, and a
+    # batch of one is still the sequential search
+    for batch in (0, 1, 32):
+        P, st = oracle.mls(g, part, k, lm, seed=2, batch=batch, max_queue=q)
+        assert np.bincount(P, minlength=k).max() <= lm
+        assert st["gain"] >= 0 and oracle.cut(g, P) == c0 - st["gain"]
+        if batch == 0:
+            seq = (P, st)
+        if batch == 1:
+            assert np.array_equal(P, seq[0]) and st == seq[1]
