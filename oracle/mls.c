@@ -2,9 +2,11 @@
  * mls.c — multi-try k-way local search (MLS), oracle-only (test
  * infrastructure; see oracle.h). Sequential form of §III-C, used to measure
  * what the GPU path's LP-only refinement leaves on the table, and a batched
- * form of §IV-C's parallel MLS (orc_mls_batched): searches of a batch start
- * from the same partition and marks, then their kept prefixes are replayed in
- * seed order with recomputed gains; a batch of one is the sequential search.
+ * form of §IV-C's parallel MLS (orc_mls_batched): a batch takes seeds in
+ * queue order while their closed neighbourhoods are disjoint; its searches
+ * start from the same partition and marks, then their kept prefixes are
+ * replayed in seed order with recomputed gains; a batch of one is the
+ * sequential search.
  *
  * What the paper fixes (§III-C, Algorithm 1 of §IV-C for the iteration
  * control):
@@ -319,7 +321,8 @@ int64_t orc_mls_batched(const orc_graph *g, int32_t k, int64_t lmax, int32_t *pa
     int32_t *next = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
     int32_t *seeds = (int32_t *)xcalloc((size_t)(batch > 0 ? batch : 1), sizeof(int32_t));
     int64_t *mstart = (int64_t *)xcalloc((size_t)(batch > 0 ? batch : 1) + 1, sizeof(int64_t));
-    vec32 bmarks = {0}, mv_v = {0}, mv_f = {0}, mv_t = {0};
+    vec32 bmarks = {0}, mv_v = {0}, mv_f = {0}, mv_t = {0}, claims = {0};
+    uint8_t *claimed = (uint8_t *)xcalloc((size_t)n, 1);
     int64_t total = 0, searches = 0, kept_moves = 0, local_iters = 0;
 
     for (int32_t gi = 0; gi < global_iters; gi++) {
@@ -355,9 +358,29 @@ int64_t orc_mls_batched(const orc_graph *g, int32_t k, int64_t lmax, int32_t *pa
                 while (ti < ntodo) {
                     int32_t ns = 0;
                     while (ti < ntodo && ns < batch) {
-                        const int32_t s = todo[ti++];
-                        if (!c.marked[s]) seeds[ns++] = s;
+                        const int32_t s = todo[ti];
+                        if (c.marked[s]) {
+                            ti++;
+                            continue;
+                        }
+                        /* the batch ends at the first seed whose closed neighbourhood
+                           meets one already taken (it starts the next batch) */
+                        int clash = claimed[s];
+                        for (int32_t e = g->xadj[s]; e < g->xadj[s + 1] && !clash; e++) clash = claimed[g->adjncy[e]];
+                        if (clash && ns > 0) break;
+                        claimed[s] = 1;
+                        vpush(&claims, s);
+                        for (int32_t e = g->xadj[s]; e < g->xadj[s + 1]; e++) {
+                            if (!claimed[g->adjncy[e]]) {
+                                claimed[g->adjncy[e]] = 1;
+                                vpush(&claims, g->adjncy[e]);
+                            }
+                        }
+                        seeds[ns++] = s;
+                        ti++;
                     }
+                    for (int64_t i = 0; i < claims.len; i++) claimed[claims.a[i]] = 0;
+                    claims.len = 0;
                     if (ns == 0) break;
                     bmarks.len = mv_v.len = mv_f.len = mv_t.len = 0;
                     for (int32_t j = 0; j < ns; j++) {
@@ -464,6 +487,8 @@ int64_t orc_mls_batched(const orc_graph *g, int32_t k, int64_t lmax, int32_t *pa
     free(mv_v.a);
     free(mv_f.a);
     free(mv_t.a);
+    free(claims.a);
+    free(claimed);
     return total;
 }
 

@@ -68,7 +68,9 @@ typedef struct {
 } orc_mls_stats;
 int64_t orc_mls(const orc_graph *g, int32_t k, int64_t lmax, int32_t *part, uint64_t seed, int32_t global_iters,
                 double alpha, int32_t max_idle, orc_mls_stats *st);
-/* The same with searches in batches of `batch` (0: sequential): the searches of a
+/* The same with searches in batches of at most `batch` seeds (0: sequential), taken in
+   queue order while the seeds' closed neighbourhoods are disjoint (the first seed
+   whose neighbourhood meets a taken one starts the next batch): the searches of a
    batch start from the same partition and marks, and their kept prefixes are then
    applied in seed order with recomputed gains, each cut at its first move whose
    vertex has left its block or whose target is full, and kept up to its best
