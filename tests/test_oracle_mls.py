@@ -151,3 +151,27 @@ def test_mls_queue_bound(q):
             seq = (P, st)
         if batch == 1:
             assert np.array_equal(P, seq[0]) and st == seq[1]
+
+
+@pytest.mark.parametrize("shape", ["clique", "star"])
+def test_batched_mls_disjoint_neighbourhoods(shape):
+    # every two closed neighbourhoods meet (in a clique directly, in a star
+    # through the hub), so every batch holds a single seed and any batch size
+    # gives the sequential result
+    rng = np.random.default_rng(4)
+    if shape == "clique":
+        n = 24
+        edges = [(a, b) for a in range(n) for b in range(a + 1, n)]
+    else:
+        n = 40
+        edges = [(0, i) for i in range(1, n)]
+    w = rng.integers(1, 6, size=len(edges)).tolist()
+    g = graphgen.from_edges(n, edges, weights=w)
+    k = 4
+    part = (np.arange(n) * 5 % k).astype(np.int32)
+    lm = oracle.lmax(n, k, 0.25)
+    a, sa = oracle.mls(g, part, k, lm, seed=1)
+    for batch in (2, 7, 10 ** 6):
+        b, sb = oracle.mls(g, part, k, lm, seed=1, batch=batch)
+        assert np.array_equal(a, b) and sa == sb, batch
+    assert sa["gain"] > 0
