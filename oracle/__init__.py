@@ -2,11 +2,11 @@
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package. The GPU library never calls it and shares
-no code with it. ``oracle.c`` is the single-threaded plain definition of every
+no code with it. ``oracle.c`` is the plain definition of every
 result of the partitioner's hot path (see its header for the paper sections it
 follows); this module is argument marshalling for it plus the checks the tests
-use to pin it (brute-force optimal cuts and the matrix form of contraction live
-in ``oracle/pins.py``).
+use to pin it (brute-force optimal cuts and the matrix form of contraction are
+written out in the pin tests, ``tests/test_oracle_pins.py``).
 """
 import ctypes
 import os
@@ -58,7 +58,7 @@ def build_lib():
     using it. -ffp-contract=off keeps every binary32 product and sum that mpnn.c does not
     write as fmaf rounded on its own."""
     tmp = _LIB_PATH + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-Wall", "-std=gnu11",
+    subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-Wall", "-std=gnu11", "-fopenmp",
                            "-ffp-contract=off", "-o", tmp, os.path.join(_HERE, "oracle.c"),
                            os.path.join(_HERE, "mpnn.c"), os.path.join(_HERE, "mls.c"), "-lm"])
     os.replace(tmp, _LIB_PATH)
@@ -72,6 +72,7 @@ def _load():
         build_lib()
     lib = ctypes.CDLL(_LIB_PATH)
     G = ctypes.POINTER(_Graph)
+    lib.orc_set_threads.argtypes = [ctypes.c_int32]
     lib.orc_lmax.restype = ctypes.c_int64
     lib.orc_lmax.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_double]
     lib.orc_lp_round.restype = ctypes.c_int64
@@ -137,6 +138,12 @@ class _G:
     @property
     def ref(self):
         return ctypes.byref(self.s)
+
+
+def set_threads(t):
+    """Threads of the proposal loop of full LP rounds (1 = the plain sequential loop).
+    Results do not depend on it."""
+    _load().orc_set_threads(int(t))
 
 
 def lmax(total, k, eps):

@@ -69,47 +69,80 @@ int64_t orc_total_vwgt(const orc_graph *g) {
  * 2 with direction alternation (one per direction, since a round sees only
  * one direction), else 1. All vertices start owing `renew`.
  */
+/* Proposal of vertex v (steps 1-3) from the labels C and weights W of the
+ * round start: the best eligible label, or -1 to stay. conn, seen and touched
+ * are scratch arrays of nlabels entries, all zero on entry and on return. */
+static int32_t propose_vertex(const orc_graph *g, const int32_t *C, const int64_t *W, int64_t U, int32_t r,
+                              int32_t dir_alternate, int32_t v, int64_t *conn, int32_t *seen, int32_t *touched) {
+    int32_t ntouched = 0;
+    for (int32_t e = g->xadj[v]; e < g->xadj[v + 1]; e++) {
+        int32_t L = C[g->adjncy[e]];
+        if (!seen[L]) { seen[L] = 1; touched[ntouched++] = L; }
+        conn[L] += EW(g, e);
+    }
+    int32_t own = C[v];
+    int64_t conn_own = seen[own] ? conn[own] : 0;
+    int32_t best = -1;
+    int64_t best_conn = 0;
+    for (int32_t i = 0; i < ntouched; i++) {
+        int32_t L = touched[i];
+        if (L == own) continue;
+        if (dir_alternate) {
+            if ((r % 2) == 0 && !(L < own)) continue;
+            if ((r % 2) == 1 && !(L > own)) continue;
+        }
+        if (W[L] + VW(g, v) > U) continue;
+        if (best < 0 || conn[L] > best_conn || (conn[L] == best_conn && L < best)) {
+            best = L;
+            best_conn = conn[L];
+        }
+    }
+    for (int32_t i = 0; i < ntouched; i++) { conn[touched[i]] = 0; seen[touched[i]] = 0; }
+    return (best >= 0 && best_conn > conn_own) ? best : -1;
+}
+
+/* Threads of the proposal loop of full rounds (1 unless orc_set_threads says
+ * otherwise). Every proposal reads only the round-start C and W and writes
+ * only its own entry, so the result does not depend on the thread count. */
+static int orc_threads = 1;
+
+void orc_set_threads(int32_t t) { orc_threads = t > 0 ? t : 1; }
+
 static int64_t lp_round_act(const orc_graph *g, int32_t *C, int64_t *W, int32_t nlabels, int64_t U,
                             int32_t r, int32_t dir_alternate, int32_t *prop_out, uint8_t *act, int64_t *visits) {
     int32_t n = g->n;
     int64_t *conn = (int64_t *)xcalloc((size_t)nlabels, sizeof(int64_t));
-    int32_t *seen = (int32_t *)xcalloc((size_t)nlabels, sizeof(int32_t));
-    int32_t *touched = (int32_t *)xcalloc((size_t)nlabels, sizeof(int32_t));
     int32_t *prop = prop_out ? prop_out : (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
     const uint8_t renew = dir_alternate ? 2 : 1;
 
-    for (int32_t v = 0; v < n; v++) {
-        if (act && act[v] == 0) {
-            prop[v] = -1;
-            continue;
-        }
-        if (act) act[v]--;
-        if (visits) *visits += g->xadj[v + 1] - g->xadj[v];
-        int32_t ntouched = 0;
-        for (int32_t e = g->xadj[v]; e < g->xadj[v + 1]; e++) {
-            int32_t L = C[g->adjncy[e]];
-            if (!seen[L]) { seen[L] = 1; touched[ntouched++] = L; }
-            conn[L] += EW(g, e);
-        }
-        int32_t own = C[v];
-        int64_t conn_own = seen[own] ? conn[own] : 0;
-        int32_t best = -1;
-        int64_t best_conn = 0;
-        for (int32_t i = 0; i < ntouched; i++) {
-            int32_t L = touched[i];
-            if (L == own) continue;
-            if (dir_alternate) {
-                if ((r % 2) == 0 && !(L < own)) continue;
-                if ((r % 2) == 1 && !(L > own)) continue;
+    if (act || orc_threads <= 1) {
+        int32_t *seen = (int32_t *)xcalloc((size_t)nlabels, sizeof(int32_t));
+        int32_t *touched = (int32_t *)xcalloc((size_t)nlabels, sizeof(int32_t));
+        for (int32_t v = 0; v < n; v++) {
+            if (act && act[v] == 0) {
+                prop[v] = -1;
+                continue;
             }
-            if (W[L] + VW(g, v) > U) continue;
-            if (best < 0 || conn[L] > best_conn || (conn[L] == best_conn && L < best)) {
-                best = L;
-                best_conn = conn[L];
-            }
+            if (act) act[v]--;
+            if (visits) *visits += g->xadj[v + 1] - g->xadj[v];
+            prop[v] = propose_vertex(g, C, W, U, r, dir_alternate, v, conn, seen, touched);
         }
-        prop[v] = (best >= 0 && best_conn > conn_own) ? best : -1;
-        for (int32_t i = 0; i < ntouched; i++) { conn[touched[i]] = 0; seen[touched[i]] = 0; }
+        free(seen);
+        free(touched);
+    } else {
+        if (visits) *visits += g->xadj[n];
+#pragma omp parallel num_threads(orc_threads)
+        {
+            int64_t *tconn = (int64_t *)xcalloc((size_t)nlabels, sizeof(int64_t));
+            int32_t *tseen = (int32_t *)xcalloc((size_t)nlabels, sizeof(int32_t));
+            int32_t *ttouched = (int32_t *)xcalloc((size_t)nlabels, sizeof(int32_t));
+#pragma omp for schedule(dynamic, 1024)
+            for (int32_t v = 0; v < n; v++)
+                prop[v] = propose_vertex(g, C, W, U, r, dir_alternate, v, tconn, tseen, ttouched);
+            free(tconn);
+            free(tseen);
+            free(ttouched);
+        }
     }
 
     /* admission: running proposal weight per target, vertices in ascending order */
@@ -135,8 +168,6 @@ static int64_t lp_round_act(const orc_graph *g, int32_t *C, int64_t *W, int32_t 
     }
     free(admitted);
     free(conn);
-    free(seen);
-    free(touched);
     if (!prop_out) free(prop);
     return moves;
 }
@@ -301,6 +332,11 @@ int orc_lp_refine_async(const orc_graph *g, int32_t k, int64_t lmax, int32_t rou
     return 0;
 }
 
+static int cmp_i32(const void *a, const void *b) {
+    const int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
 /*
  * §III-A / §IV-A contraction. Coarse ids: prefix sum over "label is used"
  * indicators, so coarse id = rank of the label among the used labels.
@@ -346,12 +382,8 @@ int orc_contract(const orc_graph *g, const int32_t *labels, int32_t *xadj_c, int
                 acc[j] += EW(g, e);
             }
         }
-        /* ascending columns: plain insertion sort */
-        for (int32_t a = 1; a < ncols; a++) {
-            int32_t x = cols[a], b = a - 1;
-            while (b >= 0 && cols[b] > x) { cols[b + 1] = cols[b]; b--; }
-            cols[b + 1] = x;
-        }
+        /* ascending columns */
+        qsort(cols, (size_t)ncols, sizeof(int32_t), cmp_i32);
         for (int32_t a = 0; a < ncols; a++) {
             int32_t j = cols[a];
             adjncy_c[nnz] = j;
@@ -702,7 +734,7 @@ static void coarsen(const orc_graph *g, int32_t k, double eps, const orc_params 
     for (int32_t v = 0; v < n; v++) newid[v] = (g->xadj[v + 1] > g->xadj[v]) ? n0++ : -1;
     int32_t nnz = g->xadj[n];
 
-    int32_t maxlev = 64;
+    int32_t maxlev = 64; /* grows as needed: the number of levels is not bounded */
     level_t *lev = (level_t *)xcalloc((size_t)maxlev, sizeof(level_t));
     lev[0].xadj = (int32_t *)xcalloc((size_t)n0 + 1, sizeof(int32_t));
     lev[0].adjncy = (int32_t *)xcalloc((size_t)nnz, sizeof(int32_t));
@@ -726,7 +758,13 @@ static void coarsen(const orc_graph *g, int32_t k, double eps, const orc_params 
 
     int64_t ev_cluster = 0;
     int32_t L = 0;
-    while (lev[L].g.n > (int64_t)p->coarsest_per_k * k && L + 1 < maxlev) {
+    while (lev[L].g.n > (int64_t)p->coarsest_per_k * k) {
+        if (L + 1 == maxlev) {
+            lev = (level_t *)realloc(lev, sizeof(level_t) * (size_t)maxlev * 2);
+            if (!lev) abort();
+            memset(lev + maxlev, 0, sizeof(level_t) * (size_t)maxlev);
+            maxlev *= 2;
+        }
         level_t *f = &lev[L], *c = &lev[L + 1];
         int32_t fn = f->g.n, fnnz = f->g.xadj[fn];
         int32_t *labels = (int32_t *)xcalloc((size_t)fn, sizeof(int32_t));

@@ -96,6 +96,11 @@ typedef struct {
     int64_t plain_cut_coarsest, learned_cut_coarsest;
 } orc_result;
 
+/* Threads of the proposal loop of full LP rounds (default 1). Proposals are
+ * pure functions of the round-start labels and weights, so every result is
+ * the same for any thread count; only the time changes. */
+void orc_set_threads(int32_t t);
+
 int64_t orc_lmax(int64_t total_vwgt, int32_t k, double eps);
 int64_t orc_total_vwgt(const orc_graph *g);
 
