@@ -6,8 +6,16 @@ isolated-vertex placement, cut and balance) on a graph already in HBM.
 value = LP edge visits of the step (clustering + refinement, summed over
 levels and rounds) / step time; ms_per_step = end-to-end partition time.
 
-Prints one JSON line. Default workload: R-MAT scale 22, edge factor 16
-(a,b,c,d = .57,.19,.19,.05), k = 16, eps = 0.03.
+Prints one JSON line. Default workload: R-MAT scale 24, edge factor 16
+(a,b,c,d = .57,.19,.19,.05, seed 24), k = 64, eps = 0.03.
+
+The timed steps run the production path (LP rounds replayed as HIP graphs).
+Inside them only the eagerly launched first-round launches of the dominant
+proposal kernel are bracketed by HIP events (the roofline sample). Two
+instrumented passes follow the timed region: LP runs per level (production
+path) and every proposal kernel per level (rounds launched one by one).
+The final partition is compared with the oracle's stored result
+(tests/golden/partition_goldens.json) by SHA-256 and by every scalar.
 """
 import argparse
 import json
@@ -45,8 +53,24 @@ def make_graph(w):
     return graphgen.rgg2d(w["n"], w["seed"])
 
 
+def host_cpu():
+    """(nproc, CPU model) of this host."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return os.cpu_count() or 1, model
+
+
 def cpu_baseline(g, w, budget_rounds):
-    """The oracle as it stands, on a bounded sample: LP clustering of level 0."""
+    """The oracle as it stands, on a bounded sample: LP clustering of level 0,
+    once with the proposal loop on the host's cores (OpenMP; bit-identical
+    output) and once on one core."""
     import numpy as np
     import oracle
     n = len(g["xadj"]) - 1
@@ -60,33 +84,104 @@ def cpu_baseline(g, w, budget_rounds):
     newid[keep] = np.arange(len(keep))
     g0 = {"xadj": np.concatenate([[0], np.cumsum(d[keep])]).astype(np.int32),
           "adjncy": newid[g["adjncy"]].astype(np.int32)}
-    t = time.perf_counter()
     # bounded sample: at most `budget_rounds` rounds and about 1.5e9 edge visits (10-30 s on one core)
     rounds = max(1, min(budget_rounds, int(1.5e9 // max(1, len(g0["adjncy"])))))
-    _, st = oracle.lp_cluster(g0, ucl, rounds)
-    dt = time.perf_counter() - t
-    return {"value": st["edge_visits"] / dt, "unit": "edge-visits/s", "cores": 1, "kind": "oracle",
+    nproc, model = host_cpu()
+    threads = int(os.environ.get("OMP_NUM_THREADS") or min(nproc, 16))
+    legs = {}
+    labels = {}
+    for name, th in (("all_cores", threads), ("single_core", 1)):
+        oracle.set_threads(th)
+        t = time.perf_counter()
+        labels[name], st = oracle.lp_cluster(g0, ucl, rounds)
+        dt = time.perf_counter() - t
+        legs[name] = {"value": st["edge_visits"] / dt, "cores": th, "seconds": round(dt, 2),
+                      "edge_visits": st["edge_visits"]}
+        print(f"[bench] cpu baseline {name}: {legs[name]}", file=sys.stderr, flush=True)
+    oracle.set_threads(1)
+    same = bool(np.array_equal(labels["all_cores"], labels["single_core"]))
+    return {"value": legs["all_cores"]["value"], "unit": "edge-visits/s", "cores": legs["all_cores"]["cores"],
+            "kind": "oracle", "nproc": nproc, "cpu_model": model,
+            "single_core": legs["single_core"], "identical_labels": same,
             "sample": f"oracle lp_cluster on level 0 of the same graph (isolated vertices removed), "
-                      f"U={ucl}, up to {rounds} rounds: {st['edge_visits']} edge visits in {dt:.1f} s"}
+                      f"U={ucl}, up to {rounds} rounds ({legs['all_cores']['edge_visits']} edge visits), "
+                      f"proposal loop on {threads} threads; one-core leg beside it"}
 
 
-def roofline(prof, workload):
-    """Dominant instrumented kernel: algorithmic bytes per launch / mean launch time vs HBM peak."""
-    if not prof:
+def roofline(entry, workload):
+    """Dominant proposal kernel: algorithmic bytes per launch / mean launch time
+    (HIP events on the kernel's stream, its eagerly launched first-round
+    launches inside the timed steps) against the HBM peak."""
+    if not entry or not entry["launches"]:
         return None
-    dom = max(prof, key=lambda e: e["ms"])
-    achieved = dom["bytes"] / dom["ms"] / 1e6  # GB/s
+    achieved = entry["bytes"] / entry["ms"] / 1e6  # GB/s
     traffic = None
     tpath = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if os.path.exists(tpath):
         with open(tpath) as f:
             tr = json.load(f)
-        if tr.get("kernel") == dom["name"] and tr.get("source_sha1") == lp_source_sha1():
+        if tr.get("kernel") == entry["name"] and tr.get("source_sha1") == lp_source_sha1():
             traffic = tr["hbm_bytes_per_launch"]
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom["name"],
-            "launches": dom["launches"], "mean_launch_ms": dom["ms"] / dom["launches"],
-            "algorithmic_bytes_per_launch": dom["bytes"] / dom["launches"]}
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": entry["name"],
+            "launches": entry["launches"], "mean_launch_ms": entry["ms"] / entry["launches"],
+            "algorithmic_bytes_per_launch": entry["bytes"] / entry["launches"],
+            "sample": "first-round launches of every LP run in the timed steps (later rounds are graph replays)"}
+
+
+def level_tables(calls, kernels):
+    """Per (phase, level): the LP run's time and algorithmic-bytes fraction of the
+    HBM peak (production path) and its heaviest proposal kernel's (rounds
+    launched one by one); per family: totals over the levels."""
+    def split(name):
+        ctx, _, kern = name.partition("|")
+        phase, _, lev = ctx.partition(" L")
+        return phase, int(lev) if lev.isdigit() else -1, kern
+    rows = {}
+    for e in calls:
+        phase, lev, kern = split(e["name"])
+        if lev < 0:
+            continue
+        rows[(phase, lev)] = {"phase": phase, "level": lev, "lp_ms": round(e["ms"], 3),
+                              "lp_frac": round(e["bytes"] / e["ms"] / 1e6 / HBM_PEAK_GBS, 4)}
+    for e in kernels:
+        phase, lev, kern = split(e["name"])
+        r = rows.get((phase, lev))
+        if r is None or e["ms"] <= r.get("top_kernel_ms", -1):
+            continue
+        r.update({"top_kernel": kern, "top_kernel_ms": round(e["ms"], 3), "top_kernel_launches": e["launches"],
+                  "top_kernel_frac": round(e["bytes"] / e["ms"] / 1e6 / HBM_PEAK_GBS, 4)})
+    fam = {}
+    for e in calls:
+        _, _, kern = split(e["name"])
+        f = fam.setdefault(kern, {"ms": 0.0, "bytes": 0.0})
+        f["ms"] += e["ms"]
+        f["bytes"] += e["bytes"]
+    for k, f in fam.items():
+        f["achieved_gbs"] = round(f["bytes"] / f["ms"] / 1e6, 1)
+        f["frac"] = round(f["achieved_gbs"] / HBM_PEAK_GBS, 4)
+        f["ms"] = round(f["ms"], 3)
+        f["bytes"] = int(f["bytes"])
+    order = {"cluster": 0, "refine": 1}
+    return sorted(rows.values(), key=lambda r: (order.get(r["phase"], 2), r["level"])), fam
+
+
+def golden_parity(workload, part, res):
+    """The partition against the oracle's stored result for this workload."""
+    import hashlib
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", "partition_goldens.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        e = json.load(f).get(workload)
+    if e is None or e["graph"]["kind"] == "batch":
+        return None
+    sha = hashlib.sha256(np.ascontiguousarray(part.cpu().numpy(), dtype="<i4").tobytes()).hexdigest()
+    fields = ("cut", "max_block_w", "lmax", "balanced", "levels", "coarsest_n", "n_isolated",
+              "edge_visits_cluster", "edge_visits_refine")
+    return {"golden": f"tests/golden/partition_goldens.json:{workload}", "sha256_match": sha == e["sha256"],
+            "fields_match": all(int(res[f]) == e[f] for f in fields), "oracle_cut": e["cut"]}
 
 
 def lp_source_sha1():
@@ -238,9 +333,9 @@ def calibrate_copy(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rmat22", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="rmat24", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-rounds", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--attempts", type=int, default=4,
@@ -252,7 +347,7 @@ def main():
     ap.add_argument("--no-tuning", action="store_true",
                     help="ignore paper_1710_08231_amd/tuning/<workload>.json (use the default thresholds)")
     ap.add_argument("--no-profile", action="store_true",
-                    help="time without the per-kernel HIP events (roofline is then null)")
+                    help="no HIP events in the timed steps and no instrumented passes (roofline is then null)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -281,51 +376,67 @@ def main():
     dg = gp.to_device(g)
     torch.cuda.synchronize()
     k = w["k"]
-    # warmup; the last warmup step also times every instrumented kernel once to find the dominant one
+    prm = dict(attempts=args.attempts, active_set=args.active_set, init_fm=args.init_fm)
+    # warmup; the last warmup step also times every proposal kernel (all launches) to find the dominant one
     dominant = None
-    dom_launches = 0
     warm_table = {}
     for i in range(max(1, args.warmup)):
-        last_warm = i == max(1, args.warmup) - 1
+        last_warm = i == max(1, args.warmup) - 1 and not args.no_profile
         if last_warm:
             gp.profile_select(None)
-            gp.profile_enable(True)
-        _, res = gp.partition(dg, k, 0.03, attempts=args.attempts, active_set=args.active_set,
-                              init_fm=args.init_fm)
+            gp.profile_enable(gp.PROFILE_KERNELS)
+        _, res = gp.partition(dg, k, 0.03, **prm)
         if last_warm:
             entries = gp.profile_entries()
-            gp.profile_enable(False)
-            dominant = max(entries, key=lambda e: e["ms"])["name"] if entries else None
-            dom_launches = max(entries, key=lambda e: e["ms"])["launches"] if entries else 0
+            gp.profile_enable(0)
+            if entries:
+                dominant = max(entries, key=lambda e: e["ms"])["name"]
             warm_table = {e["name"]: round(e["ms"], 3) for e in sorted(entries, key=lambda e: -e["ms"])[:10]}
         print(f"[bench] warmup {i} ms={res['ms_total']:.2f}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
+    # timed region: the production path (rounds replayed as HIP graphs); HIP events bracket only
+    # the dominant kernel's eagerly launched first-round launches, on the library's stream, with
+    # events created beforehand
+    if dominant:
+        gp.profile_select(dominant)
+        gp.profile_enable(gp.PROFILE_EAGER)
+        gp.profile_reserve(4096)
     visits = 0
     results = []
-    # timed region: HIP events around the dominant kernel's launches only, on the
-    # library's stream (created beforehand, so none is created while timing)
-    if not args.no_profile:
-        gp.profile_select(dominant)
-        gp.profile_enable(True)
-        gp.profile_reserve(dom_launches * args.steps + 64)
     step_ms = []
+    torch.cuda.synchronize()
     t = time.perf_counter()
     for i in range(args.steps):
         ts = time.perf_counter()
-        part, res = gp.partition(dg, k, 0.03, attempts=args.attempts, active_set=args.active_set,
-                                 init_fm=args.init_fm)
+        part, res = gp.partition(dg, k, 0.03, **prm)
         step_ms.append((time.perf_counter() - ts) * 1000.0)
         visits += res["edge_visits_cluster"] + res["edge_visits_refine"]
         results.append(res)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
-    prof = gp.profile_entries() if not args.no_profile else []
-    gp.profile_enable(False)
+    sample = [e for e in gp.profile_entries() if e["name"] == dominant] if dominant else []
+    gp.profile_enable(0)
     gp.profile_select(None)
     ms = dt * 1000.0 / args.steps
     last = results[-1]
     print(f"[bench] timed {args.steps} steps: {ms:.2f} ms/step (wall per step {[round(x, 1) for x in step_ms]}, "
           f"device {[round(r['ms_total'], 1) for r in results]})", file=sys.stderr, flush=True)
+    parity = golden_parity(args.workload, part, last) if not (args.active_set or args.init_fm or
+                                                               args.attempts != 4) else None
+    print(f"[bench] parity against the oracle's golden: {parity}", file=sys.stderr, flush=True)
+    levels, family = [], {}
+    if not args.no_profile:
+        # instrumented pass 1: every LP run per level, production path
+        gp.profile_enable(gp.PROFILE_CALLS | gp.PROFILE_BY_LEVEL)
+        gp.partition(dg, k, 0.03, **prm)
+        calls = gp.profile_entries()
+        # instrumented pass 2: every proposal kernel per level, rounds launched one by one
+        gp.profile_enable(gp.PROFILE_KERNELS | gp.PROFILE_BY_LEVEL)
+        gp.partition(dg, k, 0.03, **prm)
+        kern = gp.profile_entries()
+        gp.profile_enable(0)
+        levels, family = level_tables(calls, kern)
+        print(f"[bench] LP families: {family}", file=sys.stderr, flush=True)
     out = {
         "metric": "LP edge-visits/sec + end-to-end k-way partition time; cut & balance vs oracle",
         "value": visits / dt,
@@ -345,6 +456,9 @@ def main():
         "partition_ms": ms,
         "cut": last["cut"],
         "balanced": bool(last["balanced"]),
+        "max_block_w": last["max_block_w"],
+        "lmax": last["lmax"],
+        "parity": parity,
         "levels": last["levels"],
         "coarsest_n": last["coarsest_n"],
         "edge_visits_per_step": visits // args.steps,
@@ -352,7 +466,9 @@ def main():
         "step_wall_ms": [round(x, 2) for x in step_ms],
         "step_device_ms": [round(r["ms_total"], 2) for r in results],
     }
-    out["roofline"] = roofline(prof, args.workload)
+    out["roofline"] = roofline(sample[0] if sample else None, args.workload)
+    out["lp_family_roofline"] = family
+    out["lp_levels"] = levels
     out["proposal_kernel_ms_warmup_step"] = warm_table
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)

@@ -30,17 +30,35 @@
  *  - Outputs named *_host are host pointers; every other array is a device
  *    pointer supplied and owned by the caller.
  *  - Work is ordered on `stream`. Calls that return host values synchronise
- *    the stream before returning. The library takes its temporary device
- *    memory from a cache it keeps per (device, stream): blocks allocated
- *    stream-ordered (hipMallocAsync on `stream`) the first time a call needs
- *    them and reused by later calls on that stream; gp_release_cache() frees
- *    them. It never frees caller memory. Concurrent calls on one stream from
- *    several host threads are not supported.
+ *    the stream before returning.
+ *  - Workspace. Every call that needs temporary device memory takes
+ *    `void *ws, size_t ws_bytes` before the stream:
+ *      ws != NULL: the call carves all its temporaries from the caller's
+ *        device buffer [ws, ws + ws_bytes) (aligned up to 256 bytes first) and
+ *        makes no device-memory allocation of its own. A buffer that turns
+ *        out too small ends the call with GP_ERR_WORKSPACE (the outputs are
+ *        then unspecified; gp_last_error() names the size reached). The
+ *        buffer may be reused by the next call on the same stream at once.
+ *        gp_workspace_bytes() gives a size that always suffices for the LP,
+ *        contraction and cut calls; the multilevel calls need an amount that
+ *        depends on the coarse graphs they build, reported afterwards in
+ *        gp_result.workspace_bytes.
+ *      ws == NULL (ws_bytes must be 0): the library takes the temporaries
+ *        from a cache it keeps per (device, stream): blocks allocated
+ *        stream-ordered (hipMallocAsync on `stream`) the first time a call
+ *        needs them and reused by later calls; gp_release_cache() frees them.
+ *    The library never frees caller memory. Concurrent calls on one stream
+ *    from several host threads are not supported.
  *  - Return value: GP_OK (0), GP_WARN_IMBALANCED (1, valid result whose
  *    largest block exceeds L_max), or a negative error code; gp_strerror()
  *    and gp_last_error() describe it. On error the outputs are unspecified.
- *  - Reentrant for distinct output buffers; the only global state is a
- *    thread-local last-error message.
+ *  - Global state: a thread-local last-error message; the process-wide LP
+ *    execution thresholds (gp_set_tuning; they change speed, never results);
+ *    the process-wide instrumentation switches (gp_profile_*); the
+ *    per-(device, stream) scratch cache of ws == NULL calls; and a per-device
+ *    static scratch array used only by gp_lp_refine_static. Calls with
+ *    distinct outputs and distinct workspaces (or distinct streams) are
+ *    independent.
  */
 #ifndef GP_H
 #define GP_H
@@ -57,8 +75,9 @@ extern "C" {
 #define GP_OK 0
 #define GP_WARN_IMBALANCED 1
 #define GP_ERR_ARG (-1)       /* NULL pointer, n < 0, k < 1, eps < 0, rounds < 0, U < 1 */
-#define GP_ERR_GRAPH (-2)     /* bad offsets, neighbour id out of range, label out of range */
-#define GP_ERR_WORKSPACE (-3) /* reserved */
+#define GP_ERR_GRAPH (-2)     /* bad offsets, neighbour id out of range, weight < 1, label out of range; with
+                                 GP_VALIDATE=1 in the environment also a self-loop or an asymmetric graph */
+#define GP_ERR_WORKSPACE (-3) /* the caller's workspace (or the static scratch) is too small */
 #define GP_ERR_OVERFLOW (-4)  /* nnz >= 2^31 or a weight sum that does not fit its type */
 #define GP_ERR_HIP (-5)       /* a HIP runtime call failed */
 
@@ -81,6 +100,7 @@ typedef struct {
     int64_t moves;       /* admitted moves summed over the rounds */
     int64_t edge_visits; /* rounds_run * nnz; with GP_LP_ACTIVE_SET the edges of the vertices evaluated */
     float ms;            /* device time of the call (HIP events on `stream`) */
+    int64_t workspace_bytes; /* scratch the call held at once (see "Workspace" above) */
 } gp_lp_stats;
 
 /* Multilevel parameters; gp_default_params() fills the defaults shown. */
@@ -123,9 +143,29 @@ typedef struct {
     int32_t learned_kept;         /* the proposal replaced the plain initial partition */
     int64_t plain_cut_coarsest;   /* cut of the best plain try on the coarsest graph (-1: not tried) */
     int64_t learned_cut_coarsest; /* cut of the refined proposal (-1: not tried or discarded) */
+    int64_t workspace_bytes;      /* scratch the call held at once: a later call on the same graph with the
+                                     same parameters and tuning succeeds with a workspace of this size
+                                     (gp_partition_batch: the batch's, in every entry) */
 } gp_result;
 
 void gp_default_params(gp_params *p);
+
+/*
+ * Workspace size (bytes) that always suffices for one call of the kind `op`
+ * on a graph of n vertices and nnz entries (k blocks for GP_OP_LP_REFINE; LP
+ * flags as in the call), under the current execution thresholds
+ * (gp_set_tuning). It is an upper bound assembled from the call's own
+ * allocations at their largest sizes, so it is larger than what most graphs
+ * need (gp_lp_stats.workspace_bytes reports what one call held). Returns 0
+ * and sets the last error for invalid arguments or for a multilevel call,
+ * whose need depends on the coarse graphs it builds: gp_partition and the
+ * batched calls report theirs in gp_result.workspace_bytes. Host function.
+ */
+#define GP_OP_LP_CLUSTER 1
+#define GP_OP_LP_REFINE 2
+#define GP_OP_CONTRACT 3
+#define GP_OP_CUT 4
+size_t gp_workspace_bytes(int32_t op, int32_t n, int32_t nnz, int32_t k, int32_t flags);
 
 /* §II-A balance bound: floor((1+eps) * ceil(total_vwgt / k)) in binary64. Pure host function. */
 int64_t gp_lmax(int64_t total_vwgt, int32_t k, double eps);
@@ -152,7 +192,7 @@ int64_t gp_lmax(int64_t total_vwgt, int32_t k, double eps);
  * not compacted). st_host (may be NULL) receives the statistics.
  */
 int gp_lp_cluster(const gp_graph *g, int64_t U, int32_t rounds, int32_t flags,
-                  int32_t *labels_out, gp_lp_stats *st_host, hipStream_t stream);
+                  int32_t *labels_out, gp_lp_stats *st_host, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /*
  * LP refinement (§III-C: LP started from a partition with U = L_max).
@@ -160,7 +200,7 @@ int gp_lp_cluster(const gp_graph *g, int64_t U, int32_t rounds, int32_t flags,
  * refined partition. lmax >= 1 bounds every block.
  */
 int gp_lp_refine(const gp_graph *g, int32_t k, int64_t lmax, int32_t rounds, int32_t flags,
-                 int32_t *part_inout, gp_lp_stats *st_host, hipStream_t stream);
+                 int32_t *part_inout, gp_lp_stats *st_host, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /*
  * Contraction (§III-A; coarse ids by a prefix sum over used labels, §IV-A).
@@ -174,7 +214,7 @@ int gp_lp_refine(const gp_graph *g, int32_t k, int64_t lmax, int32_t rounds, int
  */
 int gp_contract(const gp_graph *g, const int32_t *labels, int32_t *xadj_c, int32_t *adjncy_c,
                 int32_t *adjwgt_c, int32_t *vwgt_c, int32_t *f2c, int32_t *n_c_host,
-                int32_t *nnz_c_host, hipStream_t stream);
+                int32_t *nnz_c_host, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* Projection (§III-C): part_fine[v] = part_coarse[f2c[v]] for v < n (device arrays). */
 int gp_project(int32_t n, const int32_t *f2c, const int32_t *part_coarse, int32_t *part_fine,
@@ -182,7 +222,7 @@ int gp_project(int32_t n, const int32_t *f2c, const int32_t *part_coarse, int32_
 
 /* §II-A cut (each undirected edge once) and block weights B[k] (device int64) of a partition. */
 int gp_cut_and_blocks(const gp_graph *g, int32_t k, const int32_t *part, int64_t *cut_host,
-                      int64_t *block_w_dev, hipStream_t stream);
+                      int64_t *block_w_dev, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /*
  * Multilevel k-way partition (§III scheme): coarsen with gp_lp_cluster /
@@ -207,7 +247,7 @@ int gp_cut_and_blocks(const gp_graph *g, int32_t k, const int32_t *part, int64_t
  * Returns GP_OK, GP_WARN_IMBALANCED, or an error.
  */
 int gp_partition(const gp_graph *g, int32_t k, double eps, const gp_params *p, int32_t *part_out,
-                 gp_result *res_host, hipStream_t stream);
+                 gp_result *res_host, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /*
  * The coarsest graph of gp_partition's hierarchy and its initial partition
@@ -219,7 +259,7 @@ int gp_partition(const gp_graph *g, int32_t k, double eps, const gp_params *p, i
  */
 int gp_coarsest(const gp_graph *g, int32_t k, double eps, const gp_params *p, int32_t *xadj_c, int32_t *adjncy_c,
                 int32_t *adjwgt_c, int32_t *vwgt_c, int32_t *part_c, int32_t *n_c_host, int32_t *nnz_c_host,
-                hipStream_t stream);
+                void *ws, size_t ws_bytes, hipStream_t stream);
 
 /*
  * gp_coarsest for the G graphs of a disjoint-union graph at once (layout as in
@@ -231,7 +271,7 @@ int gp_coarsest(const gp_graph *g, int32_t k, double eps, const gp_params *p, in
  */
 int gp_coarsest_batch(const gp_graph *g, int32_t G, const int32_t *vtx_off_host, const int32_t *k_host, double eps,
                       const gp_params *p, int32_t *xadj_c, int32_t *adjncy_c, int32_t *adjwgt_c, int32_t *vwgt_c,
-                      int32_t *part_c, int32_t *vtx_off_c_host, int32_t *nnz_c_host, hipStream_t stream);
+                      int32_t *part_c, int32_t *vtx_off_c_host, int32_t *nnz_c_host, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /*
  * The learned initial partition's network (a project addition; it fills the
@@ -255,11 +295,11 @@ int gp_coarsest_batch(const gp_graph *g, int32_t G, const int32_t *vtx_off_host,
 int32_t gp_mpnn_param_count(int32_t k);
 
 /* Features X: [n*18] device float (row-major per vertex). */
-int gp_mpnn_features(const gp_graph *g, uint64_t seed, float *X, hipStream_t stream);
+int gp_mpnn_features(const gp_graph *g, uint64_t seed, float *X, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* Logits Z [n*k] and argmax blocks part [n] (device; either may be NULL). */
 int gp_mpnn_forward(const gp_graph *g, int32_t k, const float *params, uint64_t seed, float *Z, int32_t *part,
-                    hipStream_t stream);
+                    void *ws, size_t ws_bytes, hipStream_t stream);
 
 /*
  * Capacity-respecting decoding of finite logits Z [n*k] (device) into blocks
@@ -271,7 +311,7 @@ int gp_mpnn_forward(const gp_graph *g, int32_t k, const float *params, uint64_t 
  * vertices still unplaced after k rounds go, in ascending id, to the block
  * that is lightest at that moment (ties -> lower block). 1 <= k <= 64.
  */
-int gp_mpnn_decode(const gp_graph *g, int32_t k, const float *Z, int64_t lmax, int32_t *part, hipStream_t stream);
+int gp_mpnn_decode(const gp_graph *g, int32_t k, const float *Z, int64_t lmax, int32_t *part, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /*
  * Training loss and gradient (binary32, within tolerance of the exact
@@ -284,7 +324,7 @@ int gp_mpnn_decode(const gp_graph *g, int32_t k, const float *Z, int64_t lmax, i
  * the bfloat16-rounded weights. loss_host (may be NULL): {edge, bal}.
  */
 int gp_mpnn_backward(const gp_graph *g, int32_t k, const float *params, uint64_t seed, const int32_t *target,
-                     float lam, float *grad, double *loss_host, hipStream_t stream);
+                     float lam, float *grad, double *loss_host, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /*
  * Adam on the master weights (device arrays of `count` floats): m = b1 m +
@@ -309,7 +349,7 @@ int gp_mpnn_adam_step(float *params, float *m, float *v, const float *grad, int3
  * Returns GP_OK, GP_WARN_IMBALANCED (some graph imbalanced), or an error.
  */
 int gp_partition_batch(const gp_graph *g, int32_t G, const int32_t *vtx_off_host, const int32_t *k_host, double eps,
-                       const gp_params *p, int32_t *part_out, gp_result *res_host, hipStream_t stream);
+                       const gp_params *p, int32_t *part_out, gp_result *res_host, void *ws, size_t ws_bytes, hipStream_t stream);
 
 const char *gp_strerror(int code);
 const char *gp_last_error(void);
@@ -340,17 +380,34 @@ int gp_set_tuning(const gp_tuning *t);
 int gp_release_cache(void);
 
 /*
- * Instrumentation for measurement (not part of the method). When enabled,
- * the proposal kernels of every LP round are bracketed by HIP events on the
- * caller's stream; per kernel name the library accumulates the number of
- * launches, their summed device time (ms) and their summed algorithmic bytes
- * (CSR, weight and label bytes the kernel must move; see the kernel sources).
- * gp_profile_enable(1) clears the counters and starts recording;
- * gp_profile_enable(0) stops. gp_profile_get copies entry i (0 <=
- * i < gp_profile_count()) into caller memory; name is NUL-terminated and
- * truncated to name_len bytes. Host-only, not thread safe.
+ * Instrumentation for measurement (not part of the method). Per entry name
+ * the library accumulates the number of recorded launches, their summed
+ * device time (ms, HIP events on the caller's stream) and their summed
+ * algorithmic bytes (CSR, weight and label bytes the work must move; see the
+ * kernel sources). gp_profile_enable(mode) clears the counters and starts
+ * recording with the mode bits below; gp_profile_enable(0) stops.
+ *   GP_PROFILE_KERNELS  every launch of an LP proposal kernel is bracketed;
+ *                       rounds are then launched one by one (no replay).
+ *   GP_PROFILE_EAGER    only the proposal launches issued directly (the first
+ *                       round of every LP run); later rounds are replayed as
+ *                       usual, so the timed path is the production one.
+ *   GP_PROFILE_CALLS    every LP run inside gp_partition is bracketed and
+ *                       recorded as "lp_cluster" or "lp_refine", with the
+ *                       run's algorithmic bytes: per edge visit the neighbour
+ *                       id, its weight when present and its label (4 bytes
+ *                       clustering, 1 refining), per vertex and round 12
+ *                       bytes (+4 with vertex weights), per admitted move 16.
+ *   GP_PROFILE_BY_LEVEL names entries "cluster L<l>|<kernel>",
+ *                       "refine L<l>|<kernel>" or "init|<kernel>".
+ * gp_profile_get copies entry i (0 <= i < gp_profile_count()) into caller
+ * memory; name is NUL-terminated and truncated to name_len bytes. Host-only,
+ * not thread safe.
  */
-void gp_profile_enable(int on);
+#define GP_PROFILE_KERNELS 1
+#define GP_PROFILE_BY_LEVEL 2
+#define GP_PROFILE_EAGER 4
+#define GP_PROFILE_CALLS 8
+void gp_profile_enable(int mode);
 /* Restrict recording to launches of kernel `name` (NULL: record all). */
 void gp_profile_select(const char *name);
 /* Create the HIP events for `launches` recorded launches ahead of time, so

@@ -49,7 +49,7 @@ class Graph(ctypes.Structure):
 
 class LPStats(ctypes.Structure):
     _fields_ = [("rounds_run", ctypes.c_int32), ("moves", ctypes.c_int64),
-                ("edge_visits", ctypes.c_int64), ("ms", ctypes.c_float)]
+                ("edge_visits", ctypes.c_int64), ("ms", ctypes.c_float), ("workspace_bytes", ctypes.c_int64)]
 
 
 class Params(ctypes.Structure):
@@ -74,13 +74,15 @@ class Result(ctypes.Structure):
                 ("ms_coarsen", ctypes.c_float), ("ms_init", ctypes.c_float),
                 ("ms_refine", ctypes.c_float), ("ms_total", ctypes.c_float),
                 ("learned_tried", ctypes.c_int32), ("learned_kept", ctypes.c_int32),
-                ("plain_cut_coarsest", ctypes.c_int64), ("learned_cut_coarsest", ctypes.c_int64)]
+                ("plain_cut_coarsest", ctypes.c_int64), ("learned_cut_coarsest", ctypes.c_int64),
+                ("workspace_bytes", ctypes.c_int64)]
 
 
 EXPORTS = ["gp_default_params", "gp_lmax", "gp_lp_cluster", "gp_lp_refine", "gp_contract",
            "gp_project", "gp_cut_and_blocks", "gp_partition", "gp_partition_batch", "gp_strerror", "gp_last_error", "gp_release_cache", "gp_get_tuning", "gp_set_tuning",
            "gp_profile_enable", "gp_profile_select", "gp_profile_reserve", "gp_profile_count", "gp_profile_get", "gp_coarsest", "gp_coarsest_batch",
-           "gp_mpnn_param_count", "gp_mpnn_features", "gp_mpnn_forward", "gp_mpnn_decode", "gp_mpnn_backward", "gp_mpnn_adam_step"]
+           "gp_mpnn_param_count", "gp_mpnn_features", "gp_mpnn_forward", "gp_mpnn_decode", "gp_mpnn_backward", "gp_mpnn_adam_step",
+           "gp_workspace_bytes"]
 
 
 def load():
@@ -94,29 +96,31 @@ def load():
     G = ctypes.POINTER(Graph)
     vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     lib.gp_default_params.argtypes = [ctypes.POINTER(Params)]
+    lib.gp_workspace_bytes.restype = ctypes.c_size_t
+    lib.gp_workspace_bytes.argtypes = [i32, i32, i32, i32, i32]
     lib.gp_lmax.restype = i64
     lib.gp_lmax.argtypes = [i64, i32, ctypes.c_double]
-    lib.gp_lp_cluster.argtypes = [G, i64, i32, i32, vp, ctypes.POINTER(LPStats), vp]
-    lib.gp_lp_refine.argtypes = [G, i32, i64, i32, i32, vp, ctypes.POINTER(LPStats), vp]
-    lib.gp_contract.argtypes = [G, vp, vp, vp, vp, vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i32), vp]
+    lib.gp_lp_cluster.argtypes = [G, i64, i32, i32, vp, ctypes.POINTER(LPStats), vp, ctypes.c_size_t, vp]
+    lib.gp_lp_refine.argtypes = [G, i32, i64, i32, i32, vp, ctypes.POINTER(LPStats), vp, ctypes.c_size_t, vp]
+    lib.gp_contract.argtypes = [G, vp, vp, vp, vp, vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i32), vp, ctypes.c_size_t, vp]
     lib.gp_project.argtypes = [i32, vp, vp, vp, vp]
-    lib.gp_cut_and_blocks.argtypes = [G, i32, vp, ctypes.POINTER(i64), vp, vp]
+    lib.gp_cut_and_blocks.argtypes = [G, i32, vp, ctypes.POINTER(i64), vp, vp, ctypes.c_size_t, vp]
     lib.gp_partition.argtypes = [G, i32, ctypes.c_double, ctypes.POINTER(Params), vp,
-                                 ctypes.POINTER(Result), vp]
+                                 ctypes.POINTER(Result), vp, ctypes.c_size_t, vp]
     lib.gp_partition_batch.argtypes = [G, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.c_double,
-                                       ctypes.POINTER(Params), vp, ctypes.POINTER(Result), vp]
+                                       ctypes.POINTER(Params), vp, ctypes.POINTER(Result), vp, ctypes.c_size_t, vp]
     lib.gp_coarsest.argtypes = [G, i32, ctypes.c_double, ctypes.POINTER(Params), vp, vp, vp, vp, vp,
-                                ctypes.POINTER(i32), ctypes.POINTER(i32), vp]
+                                ctypes.POINTER(i32), ctypes.POINTER(i32), vp, ctypes.c_size_t, vp]
     lib.gp_coarsest_batch.argtypes = [G, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.c_double,
                                       ctypes.POINTER(Params), vp, vp, vp, vp, vp, ctypes.POINTER(i32),
-                                      ctypes.POINTER(i32), vp]
+                                      ctypes.POINTER(i32), vp, ctypes.c_size_t, vp]
     lib.gp_mpnn_param_count.restype = i32
     lib.gp_mpnn_param_count.argtypes = [i32]
-    lib.gp_mpnn_features.argtypes = [G, ctypes.c_uint64, vp, vp]
-    lib.gp_mpnn_forward.argtypes = [G, i32, vp, ctypes.c_uint64, vp, vp, vp]
-    lib.gp_mpnn_decode.argtypes = [G, i32, vp, i64, vp, vp]
+    lib.gp_mpnn_features.argtypes = [G, ctypes.c_uint64, vp, vp, ctypes.c_size_t, vp]
+    lib.gp_mpnn_forward.argtypes = [G, i32, vp, ctypes.c_uint64, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.gp_mpnn_decode.argtypes = [G, i32, vp, i64, vp, vp, ctypes.c_size_t, vp]
     lib.gp_mpnn_backward.argtypes = [G, i32, vp, ctypes.c_uint64, vp, ctypes.c_float, vp,
-                                     ctypes.POINTER(ctypes.c_double), vp]
+                                     ctypes.POINTER(ctypes.c_double), vp, ctypes.c_size_t, vp]
     lib.gp_mpnn_adam_step.argtypes = [vp, vp, vp, vp, i32, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                       ctypes.c_float, vp]
     lib.gp_release_cache.argtypes = []
@@ -154,6 +158,15 @@ def _stream():
     return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
 
 
+def _ws(ws):
+    """(pointer, bytes) of a caller workspace (a contiguous CUDA tensor), or (NULL, 0): the library cache."""
+    if ws is None:
+        return None, 0
+    if not ws.is_cuda or not ws.is_contiguous():
+        raise GPError("ws must be a contiguous CUDA tensor")
+    return ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel() * ws.element_size())
+
+
 def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
@@ -179,6 +192,18 @@ def to_device(g, device="cuda"):
     return out
 
 
+OP_LP_CLUSTER, OP_LP_REFINE, OP_CONTRACT, OP_CUT = 1, 2, 3, 4
+
+
+def workspace_bytes(op, n, nnz, k=1, flags=1):
+    """Workspace size that always suffices for one call of kind `op` (gp_workspace_bytes)."""
+    lib = load()
+    b = int(lib.gp_workspace_bytes(op, n, nnz, k, flags))
+    if b == 0:
+        raise GPError(lib.gp_last_error().decode())
+    return b
+
+
 def lmax(total_vwgt, k, eps):
     return int(load().gp_lmax(total_vwgt, k, eps))
 
@@ -196,27 +221,29 @@ def _lp_flags(dir_alternate, active):
     return (LP_DIR_ALTERNATE if dir_alternate else 0) | (LP_ACTIVE_SET if active else 0)
 
 
-def lp_cluster(g, U, rounds=10, dir_alternate=1, active=False):
+def lp_cluster(g, U, rounds=10, dir_alternate=1, active=False, ws=None):
     torch = _torch()
     gs = _gstruct(g)
     labels = torch.empty(gs.n, dtype=torch.int32, device=g["xadj"].device)
     st = LPStats()
     _check(load().gp_lp_cluster(ctypes.byref(gs), U, rounds, _lp_flags(dir_alternate, active), _ptr(labels),
-                                ctypes.byref(st), _stream()))
-    return labels, {"rounds_run": st.rounds_run, "moves": st.moves, "edge_visits": st.edge_visits, "ms": st.ms}
+                                ctypes.byref(st), *_ws(ws), _stream()))
+    return labels, {"rounds_run": st.rounds_run, "moves": st.moves, "edge_visits": st.edge_visits, "ms": st.ms,
+                    "workspace_bytes": st.workspace_bytes}
 
 
-def lp_refine(g, part, k, lmax_, rounds=25, dir_alternate=1, active=False):
+def lp_refine(g, part, k, lmax_, rounds=25, dir_alternate=1, active=False, ws=None):
     torch = _torch()
     gs = _gstruct(g)
     P = part.to(dtype=torch.int32).clone().contiguous()
     st = LPStats()
     _check(load().gp_lp_refine(ctypes.byref(gs), k, lmax_, rounds, _lp_flags(dir_alternate, active), _ptr(P),
-                               ctypes.byref(st), _stream()))
-    return P, {"rounds_run": st.rounds_run, "moves": st.moves, "edge_visits": st.edge_visits, "ms": st.ms}
+                               ctypes.byref(st), *_ws(ws), _stream()))
+    return P, {"rounds_run": st.rounds_run, "moves": st.moves, "edge_visits": st.edge_visits, "ms": st.ms,
+               "workspace_bytes": st.workspace_bytes}
 
 
-def contract(g, labels):
+def contract(g, labels, ws=None):
     torch = _torch()
     gs = _gstruct(g)
     dev = g["xadj"].device
@@ -228,7 +255,7 @@ def contract(g, labels):
     nc, nnzc = ctypes.c_int32(), ctypes.c_int32()
     lab = labels.to(dtype=torch.int32).contiguous()
     _check(load().gp_contract(ctypes.byref(gs), _ptr(lab), _ptr(xc), _ptr(ac), _ptr(wc), _ptr(vc), _ptr(f2c),
-                              ctypes.byref(nc), ctypes.byref(nnzc), _stream()))
+                              ctypes.byref(nc), ctypes.byref(nnzc), *_ws(ws), _stream()))
     nc, nnzc = nc.value, nnzc.value
     cg = {"xadj": xc[:nc + 1], "adjncy": ac[:nnzc], "adjwgt": wc[:nnzc], "vwgt": vc[:nc]}
     return cg, f2c[:gs.n]
@@ -241,13 +268,13 @@ def project(f2c, part_coarse):
     return out
 
 
-def cut_and_blocks(g, part, k):
+def cut_and_blocks(g, part, k, ws=None):
     torch = _torch()
     gs = _gstruct(g)
     B = torch.empty(k, dtype=torch.int64, device=g["xadj"].device)
     cut = ctypes.c_int64()
     _check(load().gp_cut_and_blocks(ctypes.byref(gs), k, _ptr(part.contiguous()), ctypes.byref(cut), _ptr(B),
-                                    _stream()))
+                                    *_ws(ws), _stream()))
     return cut.value, B
 
 
@@ -264,14 +291,14 @@ def _params(params):
     return p
 
 
-def partition(g, k, eps=0.03, **params):
+def partition(g, k, eps=0.03, ws=None, **params):
     torch = _torch()
     gs = _gstruct(g)
     p = _params(params)
     part = torch.empty(max(gs.n, 1), dtype=torch.int32, device=g["xadj"].device)
     r = Result()
     code = _check(load().gp_partition(ctypes.byref(gs), k, eps, ctypes.byref(p), _ptr(part), ctypes.byref(r),
-                                      _stream()))
+                                      *_ws(ws), _stream()))
     res = {f: getattr(r, f) for f, _ in Result._fields_}
     res["code"] = code
     return part[:gs.n], res
@@ -302,7 +329,7 @@ def union_graph(graphs):
     return u, off
 
 
-def partition_batch(g, vtx_off, ks, eps=0.03, **params):
+def partition_batch(g, vtx_off, ks, eps=0.03, ws=None, **params):
     """Partition the graphs of a disjoint-union graph together (see gp_partition_batch)."""
     torch = _torch()
     gs = _gstruct(g)
@@ -313,7 +340,7 @@ def partition_batch(g, vtx_off, ks, eps=0.03, **params):
     kk = (ctypes.c_int32 * G)(*ks)
     res = (Result * G)()
     code = _check(load().gp_partition_batch(ctypes.byref(gs), G, off, kk, eps, ctypes.byref(p), _ptr(part), res,
-                                            _stream()))
+                                            *_ws(ws), _stream()))
     out = []
     for r in res:
         d = {f: getattr(r, f) for f, _ in Result._fields_}
@@ -321,7 +348,7 @@ def partition_batch(g, vtx_off, ks, eps=0.03, **params):
     return part[:gs.n], out, code
 
 
-def coarsest(g, k, eps=0.03, **params):
+def coarsest(g, k, eps=0.03, ws=None, **params):
     """Coarsest graph of the hierarchy (CSR dict of device tensors) and its initial partition."""
     torch = _torch()
     gs = _gstruct(g)
@@ -334,12 +361,12 @@ def coarsest(g, k, eps=0.03, **params):
     pc = torch.empty(max(gs.n, 1), dtype=torch.int32, device=dev)
     nc, nnzc = ctypes.c_int32(), ctypes.c_int32()
     _check(load().gp_coarsest(ctypes.byref(gs), k, eps, ctypes.byref(p), _ptr(xc), _ptr(ac), _ptr(wc), _ptr(vc),
-                              _ptr(pc), ctypes.byref(nc), ctypes.byref(nnzc), _stream()))
+                              _ptr(pc), ctypes.byref(nc), ctypes.byref(nnzc), *_ws(ws), _stream()))
     nc, nnzc = nc.value, nnzc.value
     return {"xadj": xc[:nc + 1], "adjncy": ac[:nnzc], "adjwgt": wc[:nnzc], "vwgt": vc[:nc]}, pc[:nc]
 
 
-def coarsest_batch(g, vtx_off, ks, eps=0.03, **params):
+def coarsest_batch(g, vtx_off, ks, eps=0.03, ws=None, **params):
     """Coarsest graphs of the graphs of a disjoint-union graph, side by side.
     Returns (CSR dict of device tensors, coarse vertex offsets [G+1], graph-local partition)."""
     torch = _torch()
@@ -357,7 +384,7 @@ def coarsest_batch(g, vtx_off, ks, eps=0.03, **params):
     offc = (ctypes.c_int32 * (G + 1))()
     nnzc = ctypes.c_int32()
     _check(load().gp_coarsest_batch(ctypes.byref(gs), G, off, kk, eps, ctypes.byref(p), _ptr(xc), _ptr(ac), _ptr(wc),
-                                    _ptr(vc), _ptr(pc), offc, ctypes.byref(nnzc), _stream()))
+                                    _ptr(vc), _ptr(pc), offc, ctypes.byref(nnzc), *_ws(ws), _stream()))
     nc, nnzc = offc[G], nnzc.value
     cg = {"xadj": xc[:nc + 1], "adjncy": ac[:nnzc], "adjwgt": wc[:nnzc], "vwgt": vc[:nc]}
     return cg, list(offc), pc[:nc]
@@ -379,26 +406,26 @@ def _fparams(params, k):
     return _ptr(params)
 
 
-def mpnn_features(g, seed=0):
+def mpnn_features(g, seed=0, ws=None):
     torch = _torch()
     gs = _gstruct(g)
     X = torch.empty((max(gs.n, 1), 18), dtype=torch.float32, device=g["xadj"].device)
-    _check(load().gp_mpnn_features(ctypes.byref(gs), seed, _ptr(X), _stream()))
+    _check(load().gp_mpnn_features(ctypes.byref(gs), seed, _ptr(X), *_ws(ws), _stream()))
     return X[:gs.n]
 
 
-def mpnn_forward(g, k, params, seed=0):
+def mpnn_forward(g, k, params, seed=0, ws=None):
     """(logits [n, k], argmax blocks [n]) of the network with bfloat16-rounded weights."""
     torch = _torch()
     gs = _gstruct(g)
     dev = g["xadj"].device
     Z = torch.empty((max(gs.n, 1), k), dtype=torch.float32, device=dev)
     P = torch.empty(max(gs.n, 1), dtype=torch.int32, device=dev)
-    _check(load().gp_mpnn_forward(ctypes.byref(gs), k, _fparams(params, k), seed, _ptr(Z), _ptr(P), _stream()))
+    _check(load().gp_mpnn_forward(ctypes.byref(gs), k, _fparams(params, k), seed, _ptr(Z), _ptr(P), *_ws(ws), _stream()))
     return Z[:gs.n], P[:gs.n]
 
 
-def mpnn_decode(g, k, Z, lmax_):
+def mpnn_decode(g, k, Z, lmax_, ws=None):
     """Blocks [n] from logits Z [n, k] (float32 CUDA) under the block bound lmax_."""
     torch = _torch()
     gs = _gstruct(g)
@@ -406,11 +433,11 @@ def mpnn_decode(g, k, Z, lmax_):
     if z.numel() != gs.n * k:
         raise GPError("Z must hold n * k logits")
     P = torch.empty(max(gs.n, 1), dtype=torch.int32, device=g["xadj"].device)
-    _check(load().gp_mpnn_decode(ctypes.byref(gs), k, _ptr(z), lmax_, _ptr(P), _stream()))
+    _check(load().gp_mpnn_decode(ctypes.byref(gs), k, _ptr(z), lmax_, _ptr(P), *_ws(ws), _stream()))
     return P[:gs.n]
 
 
-def mpnn_backward(g, k, params, target, seed=0, lam=1.0, grad=None):
+def mpnn_backward(g, k, params, target, seed=0, lam=1.0, grad=None, ws=None):
     """(gradient [P] float32, (edge loss, balance loss)) for a target partition."""
     torch = _torch()
     gs = _gstruct(g)
@@ -419,7 +446,7 @@ def mpnn_backward(g, k, params, target, seed=0, lam=1.0, grad=None):
     t = target.to(dtype=torch.int32).contiguous()
     loss = (ctypes.c_double * 2)()
     _check(load().gp_mpnn_backward(ctypes.byref(gs), k, _fparams(params, k), seed, _ptr(t), lam, _ptr(grad), loss,
-                                   _stream()))
+                                   *_ws(ws), _stream()))
     return grad, (loss[0], loss[1])
 
 
@@ -454,9 +481,13 @@ def release_cache():
     _check(load().gp_release_cache())
 
 
-def profile_enable(on=True):
-    """Start (clearing) or stop the library's per-kernel HIP-event timing."""
-    load().gp_profile_enable(1 if on else 0)
+PROFILE_KERNELS, PROFILE_BY_LEVEL, PROFILE_EAGER, PROFILE_CALLS = 1, 2, 4, 8
+
+
+def profile_enable(mode=PROFILE_KERNELS):
+    """Start (clearing) or stop (mode 0 / False) the library's HIP-event timing; mode is a
+    combination of the PROFILE_* bits (True = PROFILE_KERNELS)."""
+    load().gp_profile_enable(int(mode))
 
 
 def profile_select(name=None):

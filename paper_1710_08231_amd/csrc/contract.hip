@@ -651,6 +651,25 @@ int build_rowof(const DevGraph &g, int32_t *rowof, Scratch &sc) {
     return maxscan_inclusive(rowof, nnz, sc);
 }
 
+// Upper bound of the scratch contract() holds at once: the allocations below
+// with every coarse count at n, big-row chunk capacity at 2 nnz (chunks of
+// kRowChunk entries over rows longer than kRowChunk), runs at nnz, each
+// rounded up to 256 bytes; sort and scan temporaries as for the LP (reusable
+// slots grown by 1.25x, at most 6.25 times their final size).
+size_t contract_scratch_bound(int64_t n, int64_t nnz) {
+    auto R = [](double x) { return (double)((((size_t)(x > 1 ? x : 1)) + 255) & ~(size_t)255); };
+    const double N = (double)n, M = (double)nnz, bcap = 2.0 * M + kRowChunk;
+    double b = 2 * R(4 * N) + 2 * R(4) + R(8 * N);                          // used, id, counters, c'
+    b += R(4 * N) + R(4 * N + 4) + R(4 * N) + 3 * R(4 * N + 4) + R(4);      // counts, starts, members
+    b += 2 * R(4 * M) + R(4 * N) + 4 * R(4 * N) + R(12);                     // row buffers, row classes
+    b += 2 * R(4 * N) + 3 * R(4) + R(4 * N + 4);                             // big rows: chunk plan
+    b += 2 * R(8 * bcap) + 2 * R(4 * bcap) + R(4 * (M / kRowChunk + N));     // big rows: triples
+    b += R(8 * M) + R(4 * M) + R(4);                                         // runs
+    const double m = std::max(M, std::max(N, 1.0));
+    const double temps = 6.25 * (m / 4.0) + 6.25 * 2 * 8 * 4 * std::ceil(m / kScanTile) + 128.0 * 1024;
+    return (size_t)(b + temps);
+}
+
 int contract(const DevGraph &g, const int32_t *labels, bool skip_isolated, CoarseOut &out, Scratch &sc) {
     ScratchScope scope(sc);  // the outputs are caller buffers: all scratch below is internal
     hipStream_t s = sc.stream();

@@ -17,6 +17,9 @@ struct CoarseOut {
 // is counted as used.
 int contract(const DevGraph &g, const int32_t *labels, bool skip_isolated, CoarseOut &out, Scratch &sc);
 
+// Upper bound of the scratch bytes contract() holds at once.
+size_t contract_scratch_bound(int64_t n, int64_t nnz);
+
 // part_fine[v] = f2c[v] >= 0 ? part_coarse[f2c[v]] : -1
 int project(int32_t n, const int32_t *f2c, const int32_t *part_coarse, int32_t *part_fine, hipStream_t s);
 

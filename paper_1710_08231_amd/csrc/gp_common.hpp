@@ -73,25 +73,34 @@ struct Arena {
 // The arena of (current device, s), created on first use; null on failure.
 Arena *arena_for(hipStream_t s);
 
-// Scratch memory for one library call, taken from the stream's arena (or,
-// if that arena is already serving another live Scratch, allocated with
-// hipMallocAsync and freed on release). Everything is given back when the
-// object goes out of scope.
+// Scratch memory for one library call. Three sources:
+//  - the stream's arena (or, if that arena is already serving another live
+//    Scratch, hipMallocAsync blocks freed on release);
+//  - caller memory [ws, ws + ws_bytes): carved as a bump allocator, nothing is
+//    ever allocated, and a request that does not fit fails with
+//    GP_ERR_WORKSPACE;
+//  - the same, for a buffer the library owns statically (set_static()): the
+//    call then also creates no HIP events, streams or graphs.
+// Everything is given back when the object goes out of scope.
 class Scratch {
   public:
-    explicit Scratch(hipStream_t s) : s_(s) {
-        keep_pool();
-        a_ = arena_for(s);
-        if (a_ && !a_->busy) {
-            a_->busy = true;
-            a_->cur = 0;
-            a_->off = 0;
-            a_->used = 0;
-            a_->need = 0;
-        } else {
-            a_ = nullptr;
+    explicit Scratch(hipStream_t s) : s_(s) { use_cache(); }
+    Scratch(hipStream_t s, void *ws, size_t ws_bytes) : s_(s) {
+        if (!ws) {
+            use_cache();
+            return;
         }
+        fixed_ = true;
+        const uintptr_t b = ((uintptr_t)ws + 255) & ~(uintptr_t)255;
+        const size_t lost = (size_t)(b - (uintptr_t)ws);
+        own_.blocks.push_back({reinterpret_cast<char *>(b), ws_bytes > lost ? ws_bytes - lost : 0});
+        own_.busy = true;
+        a_ = &own_;
     }
+    // the buffer is the library's own static scratch: no runtime objects either
+    void set_static() { static_ = true; }
+    bool is_static() const { return static_; }
+    bool fixed() const { return fixed_; }
     ~Scratch() { release(); }
     Scratch(const Scratch &) = delete;
     Scratch &operator=(const Scratch &) = delete;
@@ -168,7 +177,8 @@ class Scratch {
         ptrs_.clear();
         tmp_.clear();
         if (a_) {
-            if (a_->grew && a_->blocks.size() > 1) consolidate();
+            if (!fixed_ && a_->grew && a_->blocks.size() > 1) consolidate();
+            if (fixed_) need_fixed_ = a_->need;
             a_->cur = 0;
             a_->off = 0;
             a_->used = 0;
@@ -178,8 +188,8 @@ class Scratch {
             a_ = nullptr;
         }
     }
-    // bytes of the stream's cache this call has held at once so far (0 without a cache)
-    size_t high_water() const { return a_ ? a_->need : 0; }
+    // bytes of scratch this call has held at once so far (0 without a cache)
+    size_t high_water() const { return a_ ? a_->need : (fixed_ ? need_fixed_ : 0); }
     hipStream_t stream() const { return launch_ ? launch_ : s_; }
     // Launch subsequent work on `st` (for recording a launch sequence); while
     // `frozen`, scratch slots may not grow, so nothing is allocated.
@@ -189,6 +199,19 @@ class Scratch {
     }
 
   private:
+    void use_cache() {
+        keep_pool();
+        a_ = arena_for(s_);
+        if (a_ && !a_->busy) {
+            a_->busy = true;
+            a_->cur = 0;
+            a_->off = 0;
+            a_->used = 0;
+            a_->need = 0;
+        } else {
+            a_ = nullptr;
+        }
+    }
     static constexpr size_t kMinBlock = size_t(512) << 20;
     // After a call that had to grow the cache, replace its blocks by one block
     // of the call's high-water mark plus 1/16, so a call with the same needs
@@ -218,8 +241,16 @@ class Scratch {
                 a_->off += bytes;
                 return GP_OK;
             }
+            if (fixed_) break;
             a_->cur++;
             a_->off = 0;
+        }
+        if (fixed_) {
+            set_error((std::string("workspace too small: the call needs more than ") + std::to_string(a_->used) +
+                       " bytes of scratch at once, the workspace holds " + std::to_string(a_->blocks[0].size) +
+                       " (after aligning it to 256 bytes)").c_str());
+            *p = nullptr;
+            return GP_ERR_WORKSPACE;
         }
         void *q = nullptr;
         const size_t size = bytes > kMinBlock ? bytes : kMinBlock;
@@ -256,6 +287,9 @@ class Scratch {
     hipStream_t s_;
     hipStream_t launch_ = nullptr;
     bool frozen_ = false;
+    bool fixed_ = false, static_ = false;
+    size_t need_fixed_ = 0;
+    Arena own_;  // the single block of caller (or static) memory
     Arena *a_ = nullptr;
     std::vector<void *> ptrs_;
     std::vector<std::pair<void *, size_t>> tmp_;
@@ -276,9 +310,17 @@ struct ScratchScope {
 // ---------------------------------------------------------------- instrumentation
 // When enabled (gp_profile_enable), selected kernel launches are bracketed by
 // HIP events on their stream; durations and the algorithmic bytes of each
-// launch accumulate per kernel name until read back (gp_profile_get).
+// launch accumulate per kernel name (optionally prefixed by the phase and
+// level set with prof_context) until read back (gp_profile_get).
 bool prof_on();
 bool prof_wants(const char *name);
+// true when every launch is to be bracketed, so rounds must not be replayed
+bool prof_blocks_replay();
+// LP-call events (whole gp clustering / refinement runs per level)
+bool prof_calls();
+// while a launch sequence is recorded for replay no event is recorded
+void prof_capturing(bool on);
+void prof_context(const char *ctx);
 void prof_record(const char *name, hipEvent_t a, hipEvent_t b, double bytes);
 hipEvent_t prof_event();
 void prof_flush();  // resolves recorded events (the stream must be synchronised)

@@ -1382,6 +1382,58 @@ int set_tuning(const Tuning &t) {
     return GP_OK;
 }
 
+// Upper bound of the scratch one lp_run holds at once (the allocations of
+// lp_run below, each rounded up to 256 bytes, with every per-vertex count
+// taken at n and every per-entry count at nnz), under the current tuning.
+// Scan, compaction and sort temporaries are reusable slots that grow by
+// 1.25x at a time and keep their outgrown buffers until the run ends: at most
+// 1.25 / (1 - 1/1.25) = 6.25 times their final size, i.e. 6.25 * n / 4 bytes
+// of radix histograms, 6.25 * 2 * 8 * ceil(m / 2048) bytes per scan depth,
+// plus 256 bytes of rounding per growth.
+size_t lp_scratch_bound(int64_t n, int64_t nnz, int64_t nlabels, bool active) {
+    auto R = [](double x) { return (double)((((size_t)std::ceil(x > 1 ? x : 1)) + 255) & ~(size_t)255); };
+    const Tuning &tu = tuning();
+    const bool dense = nlabels <= kDenseLabels;
+    double worst = 0;
+    for (int wi = 0; wi < 2; wi++) {
+        const bool wide = wi == 1;
+        double b = 0;
+        b += 4 * R(4.0 * n) + R(40) + R(80) + R(8 * (kTiers + 1));  // tier keys and values, counts, starts
+        if (active) b += R(4.0 * n) + R(n) + R(4) + R(8 * (kTiers + 1));
+        const int32_t b4 = std::min(tu.tier_max[0], tier_cap(4, wide));
+        const int32_t b5 = std::max(std::min(tu.tier_max[1], tier_cap(5, wide)), b4);
+        const int32_t b6 = std::max(std::min(tu.tier_max[2], tier_cap(6, wide)), b5);
+        const int32_t b7 = std::max(std::min(tu.tier_max[2], tier_cap(7, wide)), b6);
+        const int32_t b8 = std::max(std::min(tu.tier_max[3], tier_cap(8, wide)), b7);
+        if (!dense) {
+            const double nh = (double)std::min<int64_t>(n, nnz / ((int64_t)b8 + 1));
+            const double ttot = 4.0 * nnz;
+            if (!wide) {
+                const double nchunks = (double)nnz / kHubChunk + nh, nslices = ttot / kHubSlice + nh,
+                             nbuckets = (double)nnz / kHubPer + nh;
+                b += 8 * R(4 * nh) + 4 * R(8 * nh) + R(12) + R(8);
+                b += R(4 * nchunks) + R(4 * nslices) + 2 * R(4 * nbuckets) + 2 * R(4 * ttot) +
+                     R(8.0 * nbuckets * kBucketCap);
+            } else {
+                b += R(4 * nh) + 2 * R(8 * nh) + R(8) + R(4 * ttot) + R(8 * ttot);
+            }
+        } else {
+            const int32_t split = std::max(b4, tu.dense_split);
+            const double nbig = (double)std::min<int64_t>(n, nnz / ((int64_t)split + 1));
+            const double dchunks = (double)nnz / tu.dense_chunk + nbig;
+            const int KT = nlabels <= 16 ? 16 : (nlabels <= 64 ? 64 : 256);
+            b += 2 * R(4 * nbig) + R(4) + R(8 * nbig) + R(16 * dchunks) + R(nbig * KT * (wide ? 8.0 : 4.0));
+            b += R(n);  // byte labels
+        }
+        b += 6 * R(4.0 * n) + R(4) + R(4.0 * nlabels) + R(8.0 * n) + R(sizeof(LPDev));  // per-round buffers
+        if (active) b += R(n) + R(8.0 * ((double)nnz / kMarkChunk + (double)nnz / kMarkSplit + 1)) + R(4);
+        worst = std::max(worst, b);
+    }
+    const double m = (double)std::max<int64_t>(n, 1);
+    const double temps = 6.25 * (m / 4.0) + 6.25 * 2 * 8 * 4 * std::ceil(m / kScanTile) + 128.0 * 1024;
+    return (size_t)(worst + temps);
+}
+
 int total_edge_weight(const DevGraph &g, int64_t *out, Scratch &sc) {
     if (!g.adjwgt) {
         *out = g.nnz;
@@ -1757,13 +1809,15 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
     GP_TRY(emit_round(s));
     if (rounds > 1) {
         bool replayed = false;
-        if (use_round_graphs() && !prof_on()) {
+        if (use_round_graphs() && !prof_blocks_replay() && !sc.is_static()) {
             hipStream_t cs = capture_stream();
             hipGraph_t graph = nullptr;
             hipGraphExec_t exec = nullptr;
             if (cs && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) {
                 sc.set_stream(cs, true);
+                prof_capturing(true);
                 const int rc = emit_round(cs);
+                prof_capturing(false);
                 sc.set_stream(s, false);
                 const hipError_t ec = hipStreamEndCapture(cs, &graph);
                 if (rc == GP_OK && ec == hipSuccess && graph &&

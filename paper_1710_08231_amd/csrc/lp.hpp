@@ -65,6 +65,10 @@ struct Tuning {
 Tuning &tuning();                  // process-wide, read at the start of every LP call
 int set_tuning(const Tuning &t);   // validates against the table capacities
 
+// Upper bound of the scratch bytes one lp_run over n vertices, nnz entries and
+// nlabels labels holds at once, under the current tuning (either weight width).
+size_t lp_scratch_bound(int64_t n, int64_t nnz, int64_t nlabels, bool active);
+
 // Sum of edge weights (nnz if adjwgt is null); synchronises the stream.
 int total_edge_weight(const DevGraph &g, int64_t *out, Scratch &sc);
 

@@ -54,15 +54,23 @@ struct ProfPending {
     hipEvent_t a, b;
     double bytes;
 };
-bool g_prof = false;
+int g_prof = 0;       // GP_PROFILE_* bits
+bool g_capturing = false;
+std::string g_ctx;   // "cluster L3" etc. (GP_PROFILE_BY_LEVEL)
 std::string g_only;  // when non-empty, only launches of this kernel are recorded
 std::vector<ProfAcc> g_acc;
 std::vector<ProfPending> g_pending;
 std::vector<hipEvent_t> g_events;
 }  // namespace
 
-bool prof_on() { return g_prof; }
-bool prof_wants(const char *name) { return g_prof && (g_only.empty() || g_only == name); }
+bool prof_on() { return g_prof != 0; }
+bool prof_wants(const char *name) {
+    return (g_prof & (GP_PROFILE_KERNELS | GP_PROFILE_EAGER)) && !g_capturing && (g_only.empty() || g_only == name);
+}
+bool prof_blocks_replay() { return (g_prof & GP_PROFILE_KERNELS) != 0; }
+bool prof_calls() { return (g_prof & GP_PROFILE_CALLS) != 0; }
+void prof_capturing(bool on) { g_capturing = on; }
+void prof_context(const char *ctx) { g_ctx = ctx ? ctx : ""; }
 
 hipEvent_t prof_event() {
     if (!g_events.empty()) {
@@ -76,7 +84,8 @@ hipEvent_t prof_event() {
 }
 
 void prof_record(const char *name, hipEvent_t a, hipEvent_t b, double bytes) {
-    g_pending.push_back({name, a, b, bytes});
+    if ((g_prof & GP_PROFILE_BY_LEVEL) && !g_ctx.empty()) g_pending.push_back({g_ctx + "|" + name, a, b, bytes});
+    else g_pending.push_back({name, a, b, bytes});
 }
 
 void prof_flush() {
@@ -147,6 +156,40 @@ __global__ void k_check_adj(const int32_t *adjncy, const int32_t *adjwgt, int32_
     if (lane_id() == 0 && b) atomicMax(bad, b);
 }
 
+// Full graph validation (GP_VALIDATE=1): a self-loop marks the graph bad, and
+// the sums over all entries (v, u, w) of h(v, u, w) and of h(u, v, w) are
+// accumulated (mod 2^64, so the order does not matter). A symmetric graph's
+// entries are the same multiset read either way, so the sums agree; for an
+// asymmetric one they differ unless 64-bit hashes collide. h is the
+// splitmix64 finaliser of (v << 32 | u) combined with the weight.
+__device__ __forceinline__ unsigned long long sym_hash(uint32_t a, uint32_t b, uint32_t w) {
+    unsigned long long z = ((unsigned long long)a << 32 | b) + 0x9E3779B97F4A7C15ull * (1ull + w);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ void k_check_symmetry(const int32_t *xadj, const int32_t *adjncy, const int32_t *adjwgt, int32_t n,
+                                 unsigned long long *acc /* [0] sum h(v,u,w), [1] sum h(u,v,w), [2] self-loop */) {
+    unsigned long long f = 0, r = 0, loop = 0;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        for (int32_t e = xadj[v]; e < xadj[v + 1]; e++) {
+            const uint32_t u = (uint32_t)adjncy[e], w = adjwgt ? (uint32_t)adjwgt[e] : 1u;
+            loop |= u == (uint32_t)v;
+            f += sym_hash((uint32_t)v, u, w);
+            r += sym_hash(u, (uint32_t)v, w);
+        }
+    }
+    f = wave_sum(f);
+    r = wave_sum(r);
+    loop = wave_max(loop);
+    if (lane_id() == 0) {
+        atomicAdd(&acc[0], f);
+        atomicAdd(&acc[1], r);
+        atomicMax(&acc[2], loop);
+    }
+}
+
 __global__ void k_check_labels(const int32_t *lab, int32_t n, int32_t lim, unsigned long long *bad) {
     unsigned long long b = 0;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
@@ -171,6 +214,12 @@ struct GraphInfo {
 
 int partition_batch(const DevGraph &g0, int32_t G, const int32_t *voff_host, const int32_t *k_host, double eps,
                     const gp_params *p, int32_t *part_out, gp_result *res, Scratch &sc, CoarsestOut *cout);
+
+// GP_VALIDATE=1 in the environment adds the symmetry and self-loop pass.
+static bool validating() {
+    const char *e = std::getenv("GP_VALIDATE");
+    return e && *e && *e != '0';
+}
 
 static int graph_info(const DevGraph &g, GraphInfo &gi, Scratch &sc) {
     hipStream_t s = sc.stream();
@@ -201,9 +250,35 @@ static int graph_info(const DevGraph &g, GraphInfo &gi, Scratch &sc) {
         set_error("graph: total vertex weight >= 2^62");
         return GP_ERR_OVERFLOW;
     }
+    if (validating() && g.n > 0) {
+        unsigned long long *sym = nullptr, hs[3];
+        GP_TRY(sc.alloc(&sym, 3));
+        GP_HIP(hipMemsetAsync(sym, 0, sizeof(unsigned long long) * 3, s));
+        hipLaunchKernelGGL(k_check_symmetry, dim3(grid_for(g.n, 256, 4096)), dim3(256), 0, s, g.xadj, g.adjncy,
+                           g.adjwgt, g.n, sym);
+        GP_LAUNCH_CHECK();
+        GP_HIP(hipMemcpyAsync(hs, sym, sizeof(hs), hipMemcpyDeviceToHost, s));
+        GP_HIP(hipStreamSynchronize(s));
+        if (hs[2]) {
+            set_error("graph: self-loop (GP_VALIDATE)");
+            return GP_ERR_GRAPH;
+        }
+        if (hs[0] != hs[1]) {
+            set_error("graph: not symmetric, an entry (v, u, w) has no (u, v, w) (GP_VALIDATE)");
+            return GP_ERR_GRAPH;
+        }
+    }
     gi.W = (int64_t)h[0];
     gi.cmax = (int64_t)h[1];
     gi.niso = (int64_t)h[2];
+    return GP_OK;
+}
+
+static int check_ws(const void *ws, size_t ws_bytes) {
+    if (!ws && ws_bytes) {
+        set_error("workspace: ws is NULL but ws_bytes is not 0");
+        return GP_ERR_ARG;
+    }
     return GP_OK;
 }
 
@@ -294,9 +369,44 @@ static bool tracing() {
     return on;
 }
 
+// Algorithmic bytes of one LP run (GP_PROFILE_CALLS): per edge visit the
+// neighbour id, its weight when present and its label (1 byte in the refining
+// runs, which gather a byte copy of the block ids); per vertex and round the
+// row offsets, own label and proposal (12 bytes, +4 with vertex weights); per
+// admitted move 16 bytes (mover record, label write, two weight updates).
+static double lp_run_bytes(const DevGraph &g, const LPOut &st, bool refine) {
+    const double per_edge = 4.0 + (g.adjwgt ? 4.0 : 0.0) + (refine ? 1.0 : 4.0);
+    const double per_vertex = 12.0 + (g.vwgt ? 4.0 : 0.0);
+    return (double)st.visits * per_edge + (double)st.rounds_run * g.n * per_vertex + (double)st.moves * 16.0;
+}
+
+// Brackets one LP run of the driver with events when GP_PROFILE_CALLS is on.
+struct CallProf {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipStream_t s;
+    CallProf(hipStream_t st, const char *phase, size_t level) : s(st) {
+        char ctx[48];
+        std::snprintf(ctx, sizeof ctx, "%s L%zu", phase, level);
+        prof_context(ctx);
+        if (prof_calls()) {
+            a = prof_event();
+            b = prof_event();
+            (void)hipEventRecord(a, s);
+        }
+    }
+    void done(const char *name, double bytes) {
+        if (a) {
+            (void)hipEventRecord(b, s);
+            prof_record(name, a, b, bytes);
+            a = nullptr;
+        }
+        prof_context(nullptr);
+    }
+};
+
 static int do_partition(const gp_graph *gin, int32_t k, double eps, const gp_params *p, int32_t *part_out,
-                        gp_result *res, hipStream_t s, CoarsestOut *cout = nullptr) {
-    Scratch sc(s);
+                        gp_result *res, void *ws, size_t ws_bytes, hipStream_t s, CoarsestOut *cout = nullptr) {
+    Scratch sc(s, ws, ws_bytes);
     Timer t_total(s);
     const auto host_t0 = std::chrono::steady_clock::now();
     const AllocStats alloc0 = alloc_stats();
@@ -335,8 +445,10 @@ static int do_partition(const gp_graph *gin, int32_t k, double eps, const gp_par
         GP_LAUNCH_CHECK();
         LPOut st;
         Timer t_lp(s);
+        CallProf cp(s, "cluster", L);
         GP_TRY(lp_run(f, labels, W, f.n, ucl, p->rounds_coarsen, p->dir_alternate, wide, &st, sc, nullptr, nullptr,
                       nullptr, 0, (p->active_set & 1) != 0));
+        cp.done("lp_cluster", lp_run_bytes(f, st, false));
         const float ms_lp = t_lp.stop();
         ev_c += st.visits;
         CoarseOut co;
@@ -391,8 +503,10 @@ static int do_partition(const gp_graph *gin, int32_t k, double eps, const gp_par
         else GP_TRY(mpnn_decode(gc, k, Z, lmax, Lc == 0, prop, sc));
     }
     ProposalOut po;
+    prof_context("init");
     GP_TRY(initial_partition(gc, Lc == 0, k, lmax, p->seed, p->attempts, p->rounds_refine, p->dir_alternate,
                              p->init_fm, wide, P, sc, prop, prop ? &po : nullptr));
+    prof_context(nullptr);
     int64_t plain_cut_c = -1, prop_cut_c = -1;
     int32_t kept = 0;
     if (prop) {
@@ -436,8 +550,10 @@ static int do_partition(const gp_graph *gin, int32_t k, double eps, const gp_par
         GP_TRY(label_weights(gl, Pl, B, k, sc));
         LPOut st;
         Timer t_lp(s);
+        CallProf cp(s, "refine", l);
         GP_TRY(lp_run(gl, Pl, B, k, lmax, p->rounds_refine, p->dir_alternate, wide, &st, sc, nullptr, nullptr, nullptr,
                       0, (p->active_set & 2) != 0));
+        cp.done("lp_refine", lp_run_bytes(gl, st, k <= 256));
         if (tracing()) {
             const float ms = t_lp.stop();
             std::fprintf(stderr, "[gp] refine level %zu n=%d nnz=%d %.3f ms (%d rounds, %lld moves, %.1f Gvisits/s)\n",
@@ -490,6 +606,7 @@ static int do_partition(const gp_graph *gin, int32_t k, double eps, const gp_par
         res->learned_kept = kept;
         res->plain_cut_coarsest = plain_cut_c;
         res->learned_cut_coarsest = prop_cut_c;
+        res->workspace_bytes = (int64_t)sc.high_water();
     }
     sc.release();
     GP_HIP(hipStreamSynchronize(s));
@@ -501,6 +618,29 @@ static int do_partition(const gp_graph *gin, int32_t k, double eps, const gp_par
 using namespace gp;
 
 extern "C" {
+
+size_t gp_workspace_bytes(int32_t op, int32_t n, int32_t nnz, int32_t k, int32_t flags) {
+    if (n < 0 || nnz < 0 || (op == GP_OP_LP_REFINE && k < 1) ||
+        (flags & ~(GP_LP_DIR_ALTERNATE | GP_LP_ACTIVE_SET))) {
+        set_error("workspace_bytes: n < 0, nnz < 0, k < 1 or unknown flags");
+        return 0;
+    }
+    auto R = [](double x) { return (size_t)((((size_t)(x > 1 ? x : 1)) + 255) & ~(size_t)255); };
+    const int64_t m = std::max<int64_t>(std::max<int64_t>(n, nnz), 1);
+    // validation counters, the label check, the edge-weight total and its scan temporaries
+    const size_t entry = 4 * R(40) + R(8) + (size_t)(6.25 * 2 * 8 * 4 * std::ceil((double)m / kScanTile)) + 65536;
+    const bool active = (flags & GP_LP_ACTIVE_SET) != 0;
+    switch (op) {
+        case GP_OP_LP_CLUSTER: return entry + R(8.0 * n) + lp_scratch_bound(n, nnz, n, active);
+        case GP_OP_LP_REFINE: return entry + R(8.0 * k) + lp_scratch_bound(n, nnz, k, active);
+        case GP_OP_CONTRACT: return entry + contract_scratch_bound(n, nnz);
+        case GP_OP_CUT:
+            return entry + R(8) + R(4.0 * nnz) + (size_t)(6.25 * 2 * 4 * 2 * std::ceil((double)m / 256)) + 65536;
+        default:
+            set_error("workspace_bytes: unknown op (the multilevel calls report theirs in gp_result.workspace_bytes)");
+            return 0;
+    }
+}
 
 void gp_default_params(gp_params *p) {
     if (!p) return;
@@ -526,13 +666,14 @@ int64_t gp_lmax(int64_t total_vwgt, int32_t k, double eps) {
 }
 
 int gp_lp_cluster(const gp_graph *g, int64_t U, int32_t rounds, int32_t flags, int32_t *labels_out,
-                  gp_lp_stats *st_host, hipStream_t stream) {
+                  gp_lp_stats *st_host, void *ws, size_t ws_bytes, hipStream_t stream) {
+    GP_TRY(check_ws(ws, ws_bytes));
     GP_TRY(check_graph_args(g));
     if (U < 1 || rounds < 0 || !labels_out || (flags & ~(GP_LP_DIR_ALTERNATE | GP_LP_ACTIVE_SET))) {
         set_error("lp_cluster: U < 1, rounds < 0, labels_out is NULL or unknown flags");
         return GP_ERR_ARG;
     }
-    Scratch sc(stream);
+    Scratch sc(stream, ws, ws_bytes);
     Timer t(stream);
     const DevGraph d = dev_graph(g);
     GraphInfo gi;
@@ -555,6 +696,7 @@ int gp_lp_cluster(const gp_graph *g, int64_t U, int32_t rounds, int32_t flags, i
         st_host->moves = o.moves;
         st_host->edge_visits = o.visits;
         st_host->ms = ms;
+        st_host->workspace_bytes = (int64_t)sc.high_water();
     }
     sc.release();
     GP_HIP(hipStreamSynchronize(stream));
@@ -562,13 +704,14 @@ int gp_lp_cluster(const gp_graph *g, int64_t U, int32_t rounds, int32_t flags, i
 }
 
 int gp_lp_refine(const gp_graph *g, int32_t k, int64_t lmax, int32_t rounds, int32_t flags,
-                 int32_t *part_inout, gp_lp_stats *st_host, hipStream_t stream) {
+                 int32_t *part_inout, gp_lp_stats *st_host, void *ws, size_t ws_bytes, hipStream_t stream) {
+    GP_TRY(check_ws(ws, ws_bytes));
     GP_TRY(check_graph_args(g));
     if (k < 1 || lmax < 1 || rounds < 0 || !part_inout || (flags & ~(GP_LP_DIR_ALTERNATE | GP_LP_ACTIVE_SET))) {
         set_error("lp_refine: k < 1, lmax < 1, rounds < 0, part is NULL or unknown flags");
         return GP_ERR_ARG;
     }
-    Scratch sc(stream);
+    Scratch sc(stream, ws, ws_bytes);
     Timer t(stream);
     const DevGraph d = dev_graph(g);
     GraphInfo gi;
@@ -602,6 +745,7 @@ int gp_lp_refine(const gp_graph *g, int32_t k, int64_t lmax, int32_t rounds, int
         st_host->moves = o.moves;
         st_host->edge_visits = o.visits;
         st_host->ms = ms;
+        st_host->workspace_bytes = (int64_t)sc.high_water();
     }
     sc.release();
     GP_HIP(hipStreamSynchronize(stream));
@@ -609,13 +753,14 @@ int gp_lp_refine(const gp_graph *g, int32_t k, int64_t lmax, int32_t rounds, int
 }
 
 int gp_contract(const gp_graph *g, const int32_t *labels, int32_t *xadj_c, int32_t *adjncy_c, int32_t *adjwgt_c,
-                int32_t *vwgt_c, int32_t *f2c, int32_t *n_c_host, int32_t *nnz_c_host, hipStream_t stream) {
+                int32_t *vwgt_c, int32_t *f2c, int32_t *n_c_host, int32_t *nnz_c_host, void *ws, size_t ws_bytes, hipStream_t stream) {
+    GP_TRY(check_ws(ws, ws_bytes));
     GP_TRY(check_graph_args(g));
     if (!labels || !xadj_c || !vwgt_c || !f2c || (g->nnz > 0 && (!adjncy_c || !adjwgt_c))) {
         set_error("contract: an output or the labels array is NULL");
         return GP_ERR_ARG;
     }
-    Scratch sc(stream);
+    Scratch sc(stream, ws, ws_bytes);
     const DevGraph d = dev_graph(g);
     GraphInfo gi;
     GP_TRY(graph_info(d, gi, sc));
@@ -658,13 +803,14 @@ int gp_project(int32_t n, const int32_t *f2c, const int32_t *part_coarse, int32_
 }
 
 int gp_cut_and_blocks(const gp_graph *g, int32_t k, const int32_t *part, int64_t *cut_host, int64_t *block_w_dev,
-                      hipStream_t stream) {
+                      void *ws, size_t ws_bytes, hipStream_t stream) {
+    GP_TRY(check_ws(ws, ws_bytes));
     GP_TRY(check_graph_args(g));
     if (k < 1 || !part) {
         set_error("cut_and_blocks: k < 1 or part is NULL");
         return GP_ERR_ARG;
     }
-    Scratch sc(stream);
+    Scratch sc(stream, ws, ws_bytes);
     const DevGraph d = dev_graph(g);
     int64_t *dcut = nullptr;
     GP_TRY(sc.alloc(&dcut, 1));
@@ -677,7 +823,8 @@ int gp_cut_and_blocks(const gp_graph *g, int32_t k, const int32_t *part, int64_t
 }
 
 int gp_partition(const gp_graph *g, int32_t k, double eps, const gp_params *p, int32_t *part_out,
-                 gp_result *res_host, hipStream_t stream) {
+                 gp_result *res_host, void *ws, size_t ws_bytes, hipStream_t stream) {
+    GP_TRY(check_ws(ws, ws_bytes));
     GP_TRY(check_graph_args(g));
     if (k < 1 || !(eps >= 0.0) || !part_out) {
         set_error("partition: k < 1, eps < 0 or part_out is NULL");
@@ -687,12 +834,13 @@ int gp_partition(const gp_graph *g, int32_t k, double eps, const gp_params *p, i
     gp_default_params(&dp);
     const gp_params *pp = p ? p : &dp;
     GP_TRY(check_params(pp, k, "partition"));
-    return do_partition(g, k, eps, pp, part_out, res_host, stream);
+    return do_partition(g, k, eps, pp, part_out, res_host, ws, ws_bytes, stream);
 }
 
 int gp_coarsest(const gp_graph *g, int32_t k, double eps, const gp_params *p, int32_t *xadj_c, int32_t *adjncy_c,
                 int32_t *adjwgt_c, int32_t *vwgt_c, int32_t *part_c, int32_t *n_c_host, int32_t *nnz_c_host,
-                hipStream_t stream) {
+                void *ws, size_t ws_bytes, hipStream_t stream) {
+    GP_TRY(check_ws(ws, ws_bytes));
     GP_TRY(check_graph_args(g));
     if (k < 1 || !(eps >= 0.0) || !xadj_c || !n_c_host || !nnz_c_host ||
         (g->n > 0 && (!vwgt_c || !part_c)) || (g->nnz > 0 && (!adjncy_c || !adjwgt_c))) {
@@ -704,7 +852,7 @@ int gp_coarsest(const gp_graph *g, int32_t k, double eps, const gp_params *p, in
     const gp_params *pp = p ? p : &dp;
     GP_TRY(check_params(pp, k, "coarsest"));
     CoarsestOut co{xadj_c, adjncy_c, adjwgt_c, vwgt_c, part_c};
-    GP_TRY(do_partition(g, k, eps, pp, nullptr, nullptr, stream, &co));
+    GP_TRY(do_partition(g, k, eps, pp, nullptr, nullptr, ws, ws_bytes, stream, &co));
     *n_c_host = co.voff[1];
     *nnz_c_host = co.nnz;
     return GP_OK;
@@ -712,7 +860,8 @@ int gp_coarsest(const gp_graph *g, int32_t k, double eps, const gp_params *p, in
 
 int gp_coarsest_batch(const gp_graph *g, int32_t G, const int32_t *vtx_off_host, const int32_t *k_host, double eps,
                       const gp_params *p, int32_t *xadj_c, int32_t *adjncy_c, int32_t *adjwgt_c, int32_t *vwgt_c,
-                      int32_t *part_c, int32_t *vtx_off_c_host, int32_t *nnz_c_host, hipStream_t stream) {
+                      int32_t *part_c, int32_t *vtx_off_c_host, int32_t *nnz_c_host, void *ws, size_t ws_bytes, hipStream_t stream) {
+    GP_TRY(check_ws(ws, ws_bytes));
     GP_TRY(check_graph_args(g));
     if (G < 1 || !vtx_off_host || !k_host || !(eps >= 0.0) || !xadj_c || !vtx_off_c_host || !nnz_c_host ||
         (g->n > 0 && (!vwgt_c || !part_c)) || (g->nnz > 0 && (!adjncy_c || !adjwgt_c))) {
@@ -732,7 +881,7 @@ int gp_coarsest_batch(const gp_graph *g, int32_t G, const int32_t *vtx_off_host,
         set_error("coarsest_batch: active-set rounds are available for single graphs only");
         return GP_ERR_ARG;
     }
-    Scratch sc(stream);
+    Scratch sc(stream, ws, ws_bytes);
     const DevGraph d = dev_graph(g);
     GraphInfo gi;
     GP_TRY(graph_info(d, gi, sc));
@@ -747,13 +896,14 @@ int gp_coarsest_batch(const gp_graph *g, int32_t G, const int32_t *vtx_off_host,
 
 int32_t gp_mpnn_param_count(int32_t k) { return k >= 1 && k <= kMpMaxK ? mpnn_param_count(k) : -1; }
 
-int gp_mpnn_features(const gp_graph *g, uint64_t seed, float *X, hipStream_t stream) {
+int gp_mpnn_features(const gp_graph *g, uint64_t seed, float *X, void *ws, size_t ws_bytes, hipStream_t stream) {
+    GP_TRY(check_ws(ws, ws_bytes));
     GP_TRY(check_graph_args(g));
     if (g->n > 0 && !X) {
         set_error("mpnn_features: X is NULL");
         return GP_ERR_ARG;
     }
-    Scratch sc(stream);
+    Scratch sc(stream, ws, ws_bytes);
     const DevGraph d = dev_graph(g);
     GraphInfo gi;
     GP_TRY(graph_info(d, gi, sc));
@@ -764,13 +914,14 @@ int gp_mpnn_features(const gp_graph *g, uint64_t seed, float *X, hipStream_t str
 }
 
 int gp_mpnn_forward(const gp_graph *g, int32_t k, const float *params, uint64_t seed, float *Z, int32_t *part,
-                    hipStream_t stream) {
+                    void *ws, size_t ws_bytes, hipStream_t stream) {
+    GP_TRY(check_ws(ws, ws_bytes));
     GP_TRY(check_graph_args(g));
     if (k < 1 || k > kMpMaxK || !params || (g->n > 0 && !Z && !part)) {
         set_error("mpnn_forward: k outside [1, 64], params NULL, or both outputs NULL");
         return GP_ERR_ARG;
     }
-    Scratch sc(stream);
+    Scratch sc(stream, ws, ws_bytes);
     const DevGraph d = dev_graph(g);
     GraphInfo gi;
     GP_TRY(graph_info(d, gi, sc));
@@ -780,13 +931,14 @@ int gp_mpnn_forward(const gp_graph *g, int32_t k, const float *params, uint64_t 
     return GP_OK;
 }
 
-int gp_mpnn_decode(const gp_graph *g, int32_t k, const float *Z, int64_t lmax, int32_t *part, hipStream_t stream) {
+int gp_mpnn_decode(const gp_graph *g, int32_t k, const float *Z, int64_t lmax, int32_t *part, void *ws, size_t ws_bytes, hipStream_t stream) {
+    GP_TRY(check_ws(ws, ws_bytes));
     GP_TRY(check_graph_args(g));
     if (k < 1 || k > kMpMaxK || lmax < 1 || (g->n > 0 && (!Z || !part))) {
         set_error("mpnn_decode: k outside [1, 64], lmax < 1, or an array is NULL");
         return GP_ERR_ARG;
     }
-    Scratch sc(stream);
+    Scratch sc(stream, ws, ws_bytes);
     const DevGraph d = dev_graph(g);
     GraphInfo gi;
     GP_TRY(graph_info(d, gi, sc));
@@ -797,13 +949,14 @@ int gp_mpnn_decode(const gp_graph *g, int32_t k, const float *Z, int64_t lmax, i
 }
 
 int gp_mpnn_backward(const gp_graph *g, int32_t k, const float *params, uint64_t seed, const int32_t *target,
-                     float lam, float *grad, double *loss_host, hipStream_t stream) {
+                     float lam, float *grad, double *loss_host, void *ws, size_t ws_bytes, hipStream_t stream) {
+    GP_TRY(check_ws(ws, ws_bytes));
     GP_TRY(check_graph_args(g));
     if (k < 1 || k > kMpMaxK || !params || !grad || (g->n > 0 && !target) || !(lam >= 0.0f)) {
         set_error("mpnn_backward: k outside [1, 64], lam < 0 or a required array is NULL");
         return GP_ERR_ARG;
     }
-    Scratch sc(stream);
+    Scratch sc(stream, ws, ws_bytes);
     const DevGraph d = dev_graph(g);
     GraphInfo gi;
     GP_TRY(graph_info(d, gi, sc));
@@ -839,7 +992,8 @@ int gp_mpnn_adam_step(float *params, float *m, float *v, const float *grad, int3
 }
 
 int gp_partition_batch(const gp_graph *g, int32_t G, const int32_t *vtx_off_host, const int32_t *k_host, double eps,
-                       const gp_params *p, int32_t *part_out, gp_result *res_host, hipStream_t stream) {
+                       const gp_params *p, int32_t *part_out, gp_result *res_host, void *ws, size_t ws_bytes, hipStream_t stream) {
+    GP_TRY(check_ws(ws, ws_bytes));
     GP_TRY(check_graph_args(g));
     if (G < 1 || !vtx_off_host || !k_host || !(eps >= 0.0) || (g->n > 0 && !part_out)) {
         set_error("partition_batch: G < 1, eps < 0 or a required array is NULL");
@@ -858,11 +1012,13 @@ int gp_partition_batch(const gp_graph *g, int32_t G, const int32_t *vtx_off_host
         set_error("partition_batch: active-set rounds are available for single graphs only");
         return GP_ERR_ARG;
     }
-    Scratch sc(stream);
+    Scratch sc(stream, ws, ws_bytes);
     const DevGraph d = dev_graph(g);
     GraphInfo gi;
     GP_TRY(graph_info(d, gi, sc));
     const int rc = partition_batch(d, G, vtx_off_host, k_host, eps, pp, part_out, res_host, sc, nullptr);
+    if (rc >= 0 && res_host)
+        for (int32_t q = 0; q < G; q++) res_host[q].workspace_bytes = (int64_t)sc.high_water();
     sc.release();
     GP_HIP(hipStreamSynchronize(stream));
     return rc;
@@ -883,10 +1039,11 @@ const char *gp_strerror(int code) {
 
 const char *gp_last_error(void) { return gp::last_error(); }
 
-void gp_profile_enable(int on) {
+void gp_profile_enable(int mode) {
     gp::prof_flush();
     gp::g_acc.clear();
-    gp::g_prof = on != 0;
+    gp::g_ctx.clear();
+    gp::g_prof = mode & (GP_PROFILE_KERNELS | GP_PROFILE_BY_LEVEL | GP_PROFILE_EAGER | GP_PROFILE_CALLS);
 }
 
 void gp_profile_select(const char *name) { gp::g_only = name ? name : ""; }

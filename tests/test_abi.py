@@ -82,3 +82,30 @@ def test_default_params_host_function(lib):
     assert (p.stall_num, p.stall_den, p.dir_alternate, p.seed) == (19, 20, 1, 0)
     assert (p.init_mode, p.mpnn_max_n, p.mpnn_seed, p.mpnn_params) == (0, 131072, 0, None)
     assert (p.active_set, p.init_fm) == (0, 0)
+
+
+def test_workspace_bytes_host_function(lib):
+    # gp_workspace_bytes is a host function: an upper bound of the scratch of one call
+    lib.gp_workspace_bytes.restype = ctypes.c_size_t
+    lib.gp_workspace_bytes.argtypes = [ctypes.c_int32] * 5
+    cl = [lib.gp_workspace_bytes(gp.OP_LP_CLUSTER, n, 16 * n, 1, 1) for n in (1000, 10_000, 100_000)]
+    assert 0 < cl[0] < cl[1] < cl[2]
+    ref = lib.gp_workspace_bytes(gp.OP_LP_REFINE, 100_000, 1_600_000, 16, 1)
+    assert 0 < ref < cl[2]  # k block weights instead of n label weights and hub tables
+    # the active-set rounds keep more per vertex
+    assert lib.gp_workspace_bytes(gp.OP_LP_REFINE, 100_000, 1_600_000, 16, 3) > ref
+    assert lib.gp_workspace_bytes(gp.OP_CONTRACT, 100_000, 1_600_000, 1, 1) > 44 * 1_600_000
+    assert lib.gp_workspace_bytes(gp.OP_CUT, 100_000, 1_600_000, 1, 1) >= 4 * 1_600_000
+    # invalid arguments and the multilevel calls (their need depends on the hierarchy): 0
+    assert lib.gp_workspace_bytes(99, 10, 10, 1, 1) == 0
+    assert lib.gp_workspace_bytes(gp.OP_LP_REFINE, 10, 10, 0, 1) == 0
+    assert lib.gp_workspace_bytes(gp.OP_LP_CLUSTER, -1, 10, 1, 1) == 0
+
+
+def test_null_workspace_with_bytes_is_rejected_before_device_work(lib):
+    # the argument check comes first, so no GPU is touched
+    g = gp.Graph(0, 0, None, None, None, None)
+    lib.gp_lp_cluster.argtypes = [ctypes.POINTER(gp.Graph), ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                  ctypes.c_void_p]
+    assert lib.gp_lp_cluster(ctypes.byref(g), 1, 1, 1, None, None, None, 64, None) == -1

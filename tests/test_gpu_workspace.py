@@ -1,0 +1,117 @@
+"""Caller-owned workspace and full graph validation, through the C ABI.
+
+With a workspace the library carves every temporary from the caller's buffer
+and allocates nothing; results equal those of the cached mode bit for bit.
+gp_workspace_bytes bounds the LP, contraction and cut calls; a multilevel
+call reports its need in gp_result.workspace_bytes, and a workspace of that
+size suffices for the same graph again. A short workspace is GP_ERR_WORKSPACE.
+GP_VALIDATE=1 adds the check of §II-A's graph: no self-loops, symmetric
+edges and weights (GP_ERR_GRAPH otherwise).
+"""
+import numpy as np
+import pytest
+
+import graphgen
+
+GRAPHS = {
+    "rgg": lambda: graphgen.rgg2d(3000, 5),
+    "rmat_hubs": lambda: graphgen.rmat(14, 9),
+    "grid_w": lambda: graphgen.grid3d(12, 10, 9, seed=4, wmax=10),
+}
+
+
+def _ws(nbytes):
+    import torch
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device="cuda")
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name", sorted(GRAPHS))
+def test_primitives_with_bounded_workspace(name):
+    import paper_1710_08231_amd as gp
+    g = GRAPHS[name]()
+    dg = gp.to_device(g)
+    n, nnz = len(g["xadj"]) - 1, len(g["adjncy"])
+    for active in (False, True):
+        flags = 1 | (2 if active else 0)
+        b = gp.workspace_bytes(gp.OP_LP_CLUSTER, n, nnz, 1, flags)
+        lab0, st0 = gp.lp_cluster(dg, 40, 10, active=active)
+        lab1, st1 = gp.lp_cluster(dg, 40, 10, active=active, ws=_ws(b))
+        assert np.array_equal(lab0.cpu().numpy(), lab1.cpu().numpy())
+        assert st0["moves"] == st1["moves"] and 0 < st1["workspace_bytes"] <= b
+        part = (lab0 % 8).to(dtype=lab0.dtype)
+        lm = gp.lmax(int(g["vwgt"].sum()) if g.get("vwgt") is not None else n, 8, 0.03)
+        b = gp.workspace_bytes(gp.OP_LP_REFINE, n, nnz, 8, flags)
+        p0, s0 = gp.lp_refine(dg, part, 8, lm * 2, 25, active=active)
+        p1, s1 = gp.lp_refine(dg, part, 8, lm * 2, 25, active=active, ws=_ws(b))
+        assert np.array_equal(p0.cpu().numpy(), p1.cpu().numpy()) and 0 < s1["workspace_bytes"] <= b
+    b = gp.workspace_bytes(gp.OP_CONTRACT, n, nnz)
+    c0, f0 = gp.contract(dg, lab0)
+    c1, f1 = gp.contract(dg, lab0, ws=_ws(b))
+    assert np.array_equal(f0.cpu().numpy(), f1.cpu().numpy())
+    for key in ("xadj", "adjncy", "adjwgt", "vwgt"):
+        assert np.array_equal(c0[key].cpu().numpy(), c1[key].cpu().numpy()), key
+    b = gp.workspace_bytes(gp.OP_CUT, n, nnz)
+    assert gp.cut_and_blocks(dg, part, 8, ws=_ws(b))[0] == gp.cut_and_blocks(dg, part, 8)[0]
+
+
+@pytest.mark.gpu
+def test_partition_workspace_reported_and_sufficient():
+    import paper_1710_08231_amd as gp
+    g = graphgen.rmat(15, 3)
+    dg = gp.to_device(g)
+    p0, r0 = gp.partition(dg, 16, 0.03)
+    need = r0["workspace_bytes"]
+    assert need > 0
+    p1, r1 = gp.partition(dg, 16, 0.03, ws=_ws(need))
+    assert np.array_equal(p0.cpu().numpy(), p1.cpu().numpy()) and r1["cut"] == r0["cut"]
+    assert r1["workspace_bytes"] == need
+    with pytest.raises(gp.GPError, match="workspace"):
+        gp.partition(dg, 16, 0.03, ws=_ws(need - 4096))
+
+
+@pytest.mark.gpu
+def test_batch_workspace_reported_and_sufficient():
+    import paper_1710_08231_amd as gp
+    graphs = [graphgen.rgg2d(2000 + 300 * i, 40 + i) for i in range(4)] + [graphgen.rmat(11, 50)]
+    ks = [2, 8, 3, 16, 4]
+    u, off = gp.union_graph(graphs)
+    du = gp.to_device(u)
+    p0, r0, _ = gp.partition_batch(du, off, ks)
+    need = r0[0]["workspace_bytes"]
+    p1, r1, _ = gp.partition_batch(du, off, ks, ws=_ws(need))
+    assert np.array_equal(p0.cpu().numpy(), p1.cpu().numpy())
+    with pytest.raises(gp.GPError, match="workspace"):
+        gp.partition_batch(du, off, ks, ws=_ws(need // 2))
+
+
+def _csr(n, rows, weights=None):
+    xadj = np.zeros(n + 1, np.int32)
+    adj, w = [], []
+    for v in range(n):
+        adj += rows[v]
+        if weights is not None:
+            w += weights[v]
+        xadj[v + 1] = len(adj)
+    g = {"xadj": xadj, "adjncy": np.asarray(adj, np.int32)}
+    if weights is not None:
+        g["adjwgt"] = np.asarray(w, np.int32)
+    return g
+
+
+@pytest.mark.gpu
+def test_validate_self_loops_and_asymmetry(monkeypatch):
+    import paper_1710_08231_amd as gp
+    good = _csr(4, [[1], [0, 2], [1, 3], [2]], [[2], [2, 5], [5, 1], [1]])
+    loop = _csr(4, [[1], [0, 1], [3], [2]])
+    one_way = _csr(4, [[1, 2], [0], [], []])          # 0 -> 2 without 2 -> 0 (offsets still valid)
+    bad_w = _csr(4, [[1], [0, 2], [1, 3], [2]], [[2], [2, 5], [4, 1], [1]])  # w(1,2) = 5, w(2,1) = 4
+    monkeypatch.setenv("GP_VALIDATE", "1")
+    gp.partition(gp.to_device(good), 2, 0.03)
+    for g, what in ((loop, "self-loop"), (one_way, "symmetric"), (bad_w, "symmetric")):
+        with pytest.raises(gp.GPError, match=what):
+            gp.partition(gp.to_device(g), 2, 0.03)
+        with pytest.raises(gp.GPError, match=what):
+            gp.lp_cluster(gp.to_device(g), 2, 3)
+    monkeypatch.setenv("GP_VALIDATE", "0")
+    gp.lp_cluster(gp.to_device(one_way), 2, 3)  # without the pass the graph is taken as given
