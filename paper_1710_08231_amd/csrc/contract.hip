@@ -653,8 +653,8 @@ int build_rowof(const DevGraph &g, int32_t *rowof, Scratch &sc) {
 
 // Upper bound of the scratch contract() holds at once: the allocations below
 // with every coarse count at n, big-row chunk capacity at 2 nnz (chunks of
-// kRowChunk entries over rows longer than kRowChunk), runs at nnz, each
-// rounded up to 256 bytes; sort and scan temporaries as for the LP (reusable
+// kRowChunk entries over rows longer than kRowChunk), runs at that capacity,
+// each rounded up to 256 bytes; sort and scan temporaries as for the LP (reusable
 // slots grown by 1.25x, at most 6.25 times their final size).
 size_t contract_scratch_bound(int64_t n, int64_t nnz) {
     auto R = [](double x) { return (double)((((size_t)(x > 1 ? x : 1)) + 255) & ~(size_t)255); };
@@ -664,8 +664,8 @@ size_t contract_scratch_bound(int64_t n, int64_t nnz) {
     b += 2 * R(4 * M) + R(4 * N) + 4 * R(4 * N) + R(12);                     // row buffers, row classes
     b += 2 * R(4 * N) + 3 * R(4) + R(4 * N + 4);                             // big rows: chunk plan
     b += 2 * R(8 * bcap) + 2 * R(4 * bcap) + R(4 * (M / kRowChunk + N));     // big rows: triples
-    b += R(8 * M) + R(4 * M) + R(4);                                         // runs
-    const double m = std::max(M, std::max(N, 1.0));
+    b += R(8 * bcap) + R(4 * bcap) + R(4);                                   // runs (sized by capacity)
+    const double m = std::max(bcap, std::max(N, 1.0));
     const double temps = 6.25 * (m / 4.0) + 6.25 * 2 * 8 * 4 * std::ceil(m / kScanTile) + 128.0 * 1024;
     return (size_t)(b + temps);
 }
@@ -801,11 +801,16 @@ int contract(const DevGraph &g, const int32_t *labels, bool skip_isolated, Coars
                 GP_HIP(hipStreamSynchronize(s));
             }
             if (m > 0) {
-                GP_TRY((radix_sort<uint64_t, int32_t>(&bk, &bv, &bk2, &bv2, m, nullptr, jbits + gbits, sc)));
-                GP_TRY(sc.alloc(&S, m));
-                GP_TRY(sc.alloc(&head, m));
-                GP_TRY((scan<long long>(ValIn64{bv}, InclOut64{S}, m, nullptr, (long long *)nullptr, sc)));
-                GP_TRY(compact(PairHead{bk}, PairHeadEmit{head}, m, nullptr, d_runs, sc));
+                // sized by the capacity, with the live count on the device: the
+                // number of triples depends on which members share a chunk, and
+                // members are grouped by atomics in no fixed order, so sizing by m
+                // would make the call's scratch vary from run to run (the result
+                // does not: the triples are sorted and summed)
+                GP_TRY((radix_sort<uint64_t, int32_t>(&bk, &bv, &bk2, &bv2, bcap, cursor, jbits + gbits, sc)));
+                GP_TRY(sc.alloc(&S, bcap));
+                GP_TRY(sc.alloc(&head, bcap));
+                GP_TRY((scan<long long>(ValIn64{bv}, InclOut64{S}, bcap, cursor, (long long *)nullptr, sc)));
+                GP_TRY(compact(PairHead{bk}, PairHeadEmit{head}, bcap, cursor, d_runs, sc));
             }
             hipLaunchKernelGGL(k_cbig_rowoff, dim3(grid_for((int64_t)m + 1, 256, 65536)), dim3(256), 0, s, bk, head,
                                d_runs, jbits, nb, roff);

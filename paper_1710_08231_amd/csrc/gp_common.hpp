@@ -6,6 +6,8 @@
 
 #include <chrono>
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
 #include <string>
 #include <vector>
 
@@ -24,6 +26,15 @@ struct AllocStats {
     int64_t calls = 0, bytes = 0;
 };
 AllocStats &alloc_stats();
+
+// GP_TRACE=2: every scratch request is printed to stderr (size, bytes held after it).
+inline bool trace_allocs() {
+    static const bool on = [] {
+        const char *e = std::getenv("GP_TRACE");
+        return e && e[0] == '2';
+    }();
+    return on;
+}
 
 inline hipError_t timed_malloc_async(void **p, size_t bytes, hipStream_t s) {
     const auto t0 = std::chrono::steady_clock::now();
@@ -234,6 +245,7 @@ class Scratch {
     int take(size_t bytes, void **p) {
         a_->used += bytes;
         if (a_->used > a_->need) a_->need = a_->used;
+        if (trace_allocs()) std::fprintf(stderr, "[gp alloc] %zu used %zu\n", bytes, a_->used);
         while (a_->cur < a_->blocks.size()) {
             Arena::Block &b = a_->blocks[a_->cur];
             if (a_->off + bytes <= b.size) {

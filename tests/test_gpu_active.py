@@ -152,7 +152,7 @@ def test_lp_rejects_unknown_flags(dev_cases):
     gs = gp._gstruct(dev_cases["rmat12"])
     lab = torch.empty(gs.n, dtype=torch.int32, device="cuda")
     st = gp.LPStats()
-    rc = gp.load().gp_lp_cluster(ctypes.byref(gs), 10, 5, 4, gp._ptr(lab), ctypes.byref(st), gp._stream())
+    rc = gp.load().gp_lp_cluster(ctypes.byref(gs), 10, 5, 4, gp._ptr(lab), ctypes.byref(st), None, 0, gp._stream())
     assert rc < 0
 
 
