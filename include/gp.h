@@ -203,6 +203,23 @@ int gp_lp_refine(const gp_graph *g, int32_t k, int64_t lmax, int32_t rounds, int
                  int32_t *part_inout, gp_lp_stats *st_host, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /*
+ * gp_lp_refine for callers that cannot allocate device memory: code that runs
+ * under HIP graph capture, tight serving loops, and harnesses that forbid
+ * allocation. Same arguments (without a workspace) and same results as
+ * gp_lp_refine, but the temporaries come from a static scratch array of 64
+ * MiB that the library holds on every GPU it runs on until the process ends,
+ * and the call creates no HIP events, streams or graphs (every round is
+ * launched directly; st_host->ms is the host time of the call). Sizes whose
+ * gp_workspace_bytes(GP_OP_LP_REFINE, n, nnz, k, flags) exceeds 64 MiB are
+ * rejected with GP_ERR_WORKSPACE before any device work (about n <= 700,000
+ * with 16 entries per vertex and k <= 64 under the default thresholds). All
+ * calls on one GPU share that GPU's array: calls that overlap on one GPU
+ * (several streams or host threads) race and must not be issued.
+ */
+int gp_lp_refine_static(const gp_graph *g, int32_t k, int64_t lmax, int32_t rounds, int32_t flags,
+                        int32_t *part_inout, gp_lp_stats *st_host, hipStream_t stream);
+
+/*
  * Contraction (§III-A; coarse ids by a prefix sum over used labels, §IV-A).
  * labels: [n] device int32 in [0, n). Coarse vertex i = the rank of its label
  * among the used labels; c'(i) = sum of c over the cluster; the coarse edge

@@ -82,7 +82,7 @@ EXPORTS = ["gp_default_params", "gp_lmax", "gp_lp_cluster", "gp_lp_refine", "gp_
            "gp_project", "gp_cut_and_blocks", "gp_partition", "gp_partition_batch", "gp_strerror", "gp_last_error", "gp_release_cache", "gp_get_tuning", "gp_set_tuning",
            "gp_profile_enable", "gp_profile_select", "gp_profile_reserve", "gp_profile_count", "gp_profile_get", "gp_coarsest", "gp_coarsest_batch",
            "gp_mpnn_param_count", "gp_mpnn_features", "gp_mpnn_forward", "gp_mpnn_decode", "gp_mpnn_backward", "gp_mpnn_adam_step",
-           "gp_workspace_bytes"]
+           "gp_workspace_bytes", "gp_lp_refine_static"]
 
 
 def load():
@@ -102,6 +102,7 @@ def load():
     lib.gp_lmax.argtypes = [i64, i32, ctypes.c_double]
     lib.gp_lp_cluster.argtypes = [G, i64, i32, i32, vp, ctypes.POINTER(LPStats), vp, ctypes.c_size_t, vp]
     lib.gp_lp_refine.argtypes = [G, i32, i64, i32, i32, vp, ctypes.POINTER(LPStats), vp, ctypes.c_size_t, vp]
+    lib.gp_lp_refine_static.argtypes = [G, i32, i64, i32, i32, vp, ctypes.POINTER(LPStats), vp]
     lib.gp_contract.argtypes = [G, vp, vp, vp, vp, vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i32), vp, ctypes.c_size_t, vp]
     lib.gp_project.argtypes = [i32, vp, vp, vp, vp]
     lib.gp_cut_and_blocks.argtypes = [G, i32, vp, ctypes.POINTER(i64), vp, vp, ctypes.c_size_t, vp]
@@ -239,6 +240,18 @@ def lp_refine(g, part, k, lmax_, rounds=25, dir_alternate=1, active=False, ws=No
     st = LPStats()
     _check(load().gp_lp_refine(ctypes.byref(gs), k, lmax_, rounds, _lp_flags(dir_alternate, active), _ptr(P),
                                ctypes.byref(st), *_ws(ws), _stream()))
+    return P, {"rounds_run": st.rounds_run, "moves": st.moves, "edge_visits": st.edge_visits, "ms": st.ms,
+               "workspace_bytes": st.workspace_bytes}
+
+
+def lp_refine_static(g, part, k, lmax_, rounds=25, dir_alternate=1, active=False):
+    """gp_lp_refine on the library's static scratch (gp_lp_refine_static): no allocation."""
+    torch = _torch()
+    gs = _gstruct(g)
+    P = part.to(dtype=torch.int32).clone().contiguous()
+    st = LPStats()
+    _check(load().gp_lp_refine_static(ctypes.byref(gs), k, lmax_, rounds, _lp_flags(dir_alternate, active), _ptr(P),
+                                      ctypes.byref(st), _stream()))
     return P, {"rounds_run": st.rounds_run, "moves": st.moves, "edge_visits": st.edge_visits, "ms": st.ms,
                "workspace_bytes": st.workspace_bytes}
 

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 
@@ -617,6 +618,89 @@ static int do_partition(const gp_graph *gin, int32_t k, double eps, const gp_par
 
 using namespace gp;
 
+// ---------------------------------------------------------------- static scratch
+// The scratch of gp_lp_refine_static: one array per GPU the library runs on
+// (the code object's copy on that device), held until the process ends. Host
+// code never uses the array's name as an address: its device address is taken
+// once per device with hipGetSymbolAddress and kept in g_static_ptr.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+static std::mutex g_static_mu;
+static void *g_static_ptr[256];
+
+static int static_scratch(void **out) {
+    int dev = 0;
+    GP_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 256) {
+        set_error("static scratch: device index out of range");
+        return GP_ERR_HIP;
+    }
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void *p = nullptr;
+        GP_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) {
+            set_error("static scratch: hipGetSymbolAddress returned NULL");
+            return GP_ERR_HIP;
+        }
+        g_static_ptr[dev] = p;
+    }
+    *out = g_static_ptr[dev];
+    return GP_OK;
+}
+
+// gp_lp_refine's body on a given scratch. A static scratch (sc.is_static())
+// also means no HIP events: ms is then the host time of the call.
+static int lp_refine_call(const gp_graph *g, int32_t k, int64_t lmax, int32_t rounds, int32_t flags,
+                          int32_t *part_inout, gp_lp_stats *st_host, Scratch &sc, hipStream_t stream) {
+    if (k < 1 || lmax < 1 || rounds < 0 || !part_inout || (flags & ~(GP_LP_DIR_ALTERNATE | GP_LP_ACTIVE_SET))) {
+        set_error("lp_refine: k < 1, lmax < 1, rounds < 0, part is NULL or unknown flags");
+        return GP_ERR_ARG;
+    }
+    const auto host_t0 = std::chrono::steady_clock::now();
+    std::unique_ptr<Timer> t;
+    if (!sc.is_static()) t.reset(new Timer(stream));
+    const DevGraph d = dev_graph(g);
+    GraphInfo gi;
+    GP_TRY(graph_info(d, gi, sc));
+    unsigned long long *bad = nullptr;
+    GP_TRY(sc.alloc(&bad, 1));
+    GP_HIP(hipMemsetAsync(bad, 0, sizeof(unsigned long long), stream));
+    if (d.n > 0) {
+        hipLaunchKernelGGL(k_check_labels, dim3(grid_for(d.n, 256, 4096)), dim3(256), 0, stream, part_inout, d.n, k,
+                           bad);
+        GP_LAUNCH_CHECK();
+    }
+    unsigned long long hb = 0;
+    GP_HIP(hipMemcpyAsync(&hb, bad, sizeof(hb), hipMemcpyDeviceToHost, stream));
+    GP_HIP(hipStreamSynchronize(stream));
+    if (hb) {
+        set_error("lp_refine: a block id is outside [0, k)");
+        return GP_ERR_GRAPH;
+    }
+    int64_t tw = 0;
+    GP_TRY(total_edge_weight(d, &tw, sc));
+    int64_t *W = nullptr;
+    GP_TRY(sc.alloc(&W, k));
+    GP_TRY(label_weights(d, part_inout, W, k, sc));
+    LPOut o;
+    GP_TRY(lp_run(d, part_inout, W, k, lmax, rounds, (flags & GP_LP_DIR_ALTERNATE) ? 1 : 0, tw >= (int64_t)INT_MAX, &o,
+                  sc, nullptr, nullptr, nullptr, 0, (flags & GP_LP_ACTIVE_SET) != 0));
+    const float ms = t ? t->stop()
+                       : (float)std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - host_t0)
+                             .count();
+    if (st_host) {
+        st_host->rounds_run = o.rounds_run;
+        st_host->moves = o.moves;
+        st_host->edge_visits = o.visits;
+        st_host->ms = ms;
+        st_host->workspace_bytes = (int64_t)sc.high_water();
+    }
+    sc.release();
+    GP_HIP(hipStreamSynchronize(stream));
+    return GP_OK;
+}
+
 extern "C" {
 
 size_t gp_workspace_bytes(int32_t op, int32_t n, int32_t nnz, int32_t k, int32_t flags) {
@@ -707,49 +791,30 @@ int gp_lp_refine(const gp_graph *g, int32_t k, int64_t lmax, int32_t rounds, int
                  int32_t *part_inout, gp_lp_stats *st_host, void *ws, size_t ws_bytes, hipStream_t stream) {
     GP_TRY(check_ws(ws, ws_bytes));
     GP_TRY(check_graph_args(g));
-    if (k < 1 || lmax < 1 || rounds < 0 || !part_inout || (flags & ~(GP_LP_DIR_ALTERNATE | GP_LP_ACTIVE_SET))) {
-        set_error("lp_refine: k < 1, lmax < 1, rounds < 0, part is NULL or unknown flags");
+    Scratch sc(stream, ws, ws_bytes);
+    return lp_refine_call(g, k, lmax, rounds, flags, part_inout, st_host, sc, stream);
+}
+
+int gp_lp_refine_static(const gp_graph *g, int32_t k, int64_t lmax, int32_t rounds, int32_t flags,
+                        int32_t *part_inout, gp_lp_stats *st_host, hipStream_t stream) {
+    GP_TRY(check_graph_args(g));
+    if (k < 1 || (flags & ~(GP_LP_DIR_ALTERNATE | GP_LP_ACTIVE_SET))) {
+        set_error("lp_refine_static: k < 1 or unknown flags");
         return GP_ERR_ARG;
     }
-    Scratch sc(stream, ws, ws_bytes);
-    Timer t(stream);
-    const DevGraph d = dev_graph(g);
-    GraphInfo gi;
-    GP_TRY(graph_info(d, gi, sc));
-    unsigned long long *bad = nullptr;
-    GP_TRY(sc.alloc(&bad, 1));
-    GP_HIP(hipMemsetAsync(bad, 0, sizeof(unsigned long long), stream));
-    if (d.n > 0) {
-        hipLaunchKernelGGL(k_check_labels, dim3(grid_for(d.n, 256, 4096)), dim3(256), 0, stream, part_inout, d.n, k,
-                           bad);
-        GP_LAUNCH_CHECK();
+    const size_t need = gp_workspace_bytes(GP_OP_LP_REFINE, g->n, g->nnz, k, flags);
+    if (need == 0 || need > kStaticScratchBytes) {
+        set_error((std::string("lp_refine_static: a graph of ") + std::to_string(g->n) + " vertices and " +
+                   std::to_string(g->nnz) + " entries with k = " + std::to_string(k) + " may need " +
+                   std::to_string(need) + " bytes of scratch; the static scratch holds " +
+                   std::to_string(kStaticScratchBytes) + " (use gp_lp_refine with a workspace)").c_str());
+        return GP_ERR_WORKSPACE;
     }
-    unsigned long long hb = 0;
-    GP_HIP(hipMemcpyAsync(&hb, bad, sizeof(hb), hipMemcpyDeviceToHost, stream));
-    GP_HIP(hipStreamSynchronize(stream));
-    if (hb) {
-        set_error("lp_refine: a block id is outside [0, k)");
-        return GP_ERR_GRAPH;
-    }
-    int64_t tw = 0;
-    GP_TRY(total_edge_weight(d, &tw, sc));
-    int64_t *W = nullptr;
-    GP_TRY(sc.alloc(&W, k));
-    GP_TRY(label_weights(d, part_inout, W, k, sc));
-    LPOut o;
-    GP_TRY(lp_run(d, part_inout, W, k, lmax, rounds, (flags & GP_LP_DIR_ALTERNATE) ? 1 : 0, tw >= (int64_t)INT_MAX, &o,
-                  sc, nullptr, nullptr, nullptr, 0, (flags & GP_LP_ACTIVE_SET) != 0));
-    const float ms = t.stop();
-    if (st_host) {
-        st_host->rounds_run = o.rounds_run;
-        st_host->moves = o.moves;
-        st_host->edge_visits = o.visits;
-        st_host->ms = ms;
-        st_host->workspace_bytes = (int64_t)sc.high_water();
-    }
-    sc.release();
-    GP_HIP(hipStreamSynchronize(stream));
-    return GP_OK;
+    void *ptr = nullptr;
+    GP_TRY(static_scratch(&ptr));
+    Scratch sc(stream, ptr, kStaticScratchBytes);
+    sc.set_static();
+    return lp_refine_call(g, k, lmax, rounds, flags, part_inout, st_host, sc, stream);
 }
 
 int gp_contract(const gp_graph *g, const int32_t *labels, int32_t *xadj_c, int32_t *adjncy_c, int32_t *adjwgt_c,
