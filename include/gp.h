@@ -125,6 +125,11 @@ typedef struct {
                                weigh at most j * L_max; each pass keeps its shortest best prefix of moves
                                and stops after 50 moves without a new best; passes end early once one
                                gains nothing. Single graphs and batches. */
+    int32_t mls;            /* 0; g > 0: after every level's LP refinement, multi-try k-way local search
+                               (§III-C; gp_mls_refine) with g global iterations. Single graphs, k <= 256 */
+    int32_t mls_batch;      /* 0: searches in batches of 1 (the sequential search); b > 0: batches of at most
+                               b searches from one shared state (gp_mls_refine) */
+    int32_t mls_queue;      /* 64: vertices one search may queue (1..64) */
 } gp_params;
 
 typedef struct {
@@ -143,6 +148,7 @@ typedef struct {
     int32_t learned_kept;         /* the proposal replaced the plain initial partition */
     int64_t plain_cut_coarsest;   /* cut of the best plain try on the coarsest graph (-1: not tried) */
     int64_t learned_cut_coarsest; /* cut of the refined proposal (-1: not tried or discarded) */
+    int64_t mls_gain;             /* cut reduction of the multi-try local search, summed over levels */
     int64_t workspace_bytes;      /* scratch the call held at once: a later call on the same graph with the
                                      same parameters and tuning succeeds with a workspace of this size
                                      (gp_partition_batch: the batch's, in every entry) */
@@ -218,6 +224,45 @@ int gp_lp_refine(const gp_graph *g, int32_t k, int64_t lmax, int32_t rounds, int
  */
 int gp_lp_refine_static(const gp_graph *g, int32_t k, int64_t lmax, int32_t rounds, int32_t flags,
                         int32_t *part_inout, gp_lp_stats *st_host, hipStream_t stream);
+
+/*
+ * Multi-try k-way local search (§III-C) on a k-way partition, in the batched
+ * form of §IV-C's parallel search (PerformMoves on every PE, then ApplyMoves):
+ *  - a global iteration visits the boundary vertices in a seeded hash order
+ *    (key splitmix64(h ^ v), h chained from seed, global and local iteration);
+ *  - a local iteration takes them in batches: the next at most `batch` seeds
+ *    not marked at the batch's start, ending before the first one whose
+ *    closed neighbourhood meets an earlier seed's;
+ *  - every seed of a batch starts one search from the batch's partition and
+ *    marks (one wavefront each, none sees the others' moves): it queues the
+ *    seed and its unmarked neighbours, at most `queue` vertices in all;
+ *    repeatedly takes the queued vertex of largest gain (ties: lower id),
+ *    re-queues it if its gain changed, else moves it to its best block (the
+ *    largest connection to an adjacent other block with room under lmax,
+ *    ties: lowest block; gain = that connection minus the one to its own
+ *    block); re-evaluates queued neighbours and queues unmarked ones; stops on
+ *    an empty queue or after 50 moves without a new best; keeps its shortest
+ *    prefix of largest positive cumulative gain;
+ *  - the kept prefixes are applied in seed order with gains recomputed on the
+ *    current partition (ApplyMoves), each cut at a vertex that already left
+ *    its block or a target without room and kept up to its best recomputed
+ *    gain, so lmax is never broken; the searches' queued vertices stay marked
+ *    for the rest of the local iteration;
+ *  - the vertices moved in a local iteration are the next one's todo list
+ *    while its gain exceeds 10% of the global iteration's gain so far.
+ * part_inout: [n] device int32 in [0, k) (vertices without neighbours may hold
+ * -1), overwritten. 1 <= k <= 256, 1 <= queue <= 64, 1 <= batch <= 65536.
+ * st_host (may be NULL): gain (cut reduction), searches, kept moves, local
+ * iterations. Results are deterministic.
+ */
+typedef struct {
+    int64_t gain, searches, moves, local_iters;
+    float ms;
+    int64_t workspace_bytes;
+} gp_mls_stats;
+int gp_mls_refine(const gp_graph *g, int32_t k, int64_t lmax, int32_t *part_inout, uint64_t seed,
+                  int32_t global_iters, int32_t batch, int32_t queue, gp_mls_stats *st_host, void *ws,
+                  size_t ws_bytes, hipStream_t stream);
 
 /*
  * Contraction (§III-A; coarse ids by a prefix sum over used labels, §IV-A).

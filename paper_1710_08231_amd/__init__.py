@@ -20,7 +20,7 @@ import subprocess
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _ROOT = os.path.dirname(_HERE)
 LIB_PATH = os.path.join(_HERE, "libgp.so")
-SOURCES = ["lp.hip", "contract.hip", "initpart.hip", "partition.hip", "batch.hip", "mpnn.hip"]
+SOURCES = ["lp.hip", "contract.hip", "initpart.hip", "partition.hip", "batch.hip", "mpnn.hip", "mls.hip"]
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
@@ -59,7 +59,13 @@ class Params(ctypes.Structure):
                 ("dir_alternate", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("init_mode", ctypes.c_int32), ("mpnn_max_n", ctypes.c_int32),
                 ("mpnn_seed", ctypes.c_uint64), ("mpnn_params", ctypes.c_void_p), ("active_set", ctypes.c_int32),
-                ("init_fm", ctypes.c_int32)]
+                ("init_fm", ctypes.c_int32), ("mls", ctypes.c_int32), ("mls_batch", ctypes.c_int32),
+                ("mls_queue", ctypes.c_int32)]
+
+
+class MLSStats(ctypes.Structure):
+    _fields_ = [("gain", ctypes.c_int64), ("searches", ctypes.c_int64), ("moves", ctypes.c_int64),
+                ("local_iters", ctypes.c_int64), ("ms", ctypes.c_float), ("workspace_bytes", ctypes.c_int64)]
 
 
 class Tuning(ctypes.Structure):
@@ -75,14 +81,14 @@ class Result(ctypes.Structure):
                 ("ms_refine", ctypes.c_float), ("ms_total", ctypes.c_float),
                 ("learned_tried", ctypes.c_int32), ("learned_kept", ctypes.c_int32),
                 ("plain_cut_coarsest", ctypes.c_int64), ("learned_cut_coarsest", ctypes.c_int64),
-                ("workspace_bytes", ctypes.c_int64)]
+                ("mls_gain", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64)]
 
 
 EXPORTS = ["gp_default_params", "gp_lmax", "gp_lp_cluster", "gp_lp_refine", "gp_contract",
            "gp_project", "gp_cut_and_blocks", "gp_partition", "gp_partition_batch", "gp_strerror", "gp_last_error", "gp_release_cache", "gp_get_tuning", "gp_set_tuning",
            "gp_profile_enable", "gp_profile_select", "gp_profile_reserve", "gp_profile_count", "gp_profile_get", "gp_coarsest", "gp_coarsest_batch",
            "gp_mpnn_param_count", "gp_mpnn_features", "gp_mpnn_forward", "gp_mpnn_decode", "gp_mpnn_backward", "gp_mpnn_adam_step",
-           "gp_workspace_bytes", "gp_lp_refine_static"]
+           "gp_workspace_bytes", "gp_lp_refine_static", "gp_mls_refine"]
 
 
 def load():
@@ -103,6 +109,8 @@ def load():
     lib.gp_lp_cluster.argtypes = [G, i64, i32, i32, vp, ctypes.POINTER(LPStats), vp, ctypes.c_size_t, vp]
     lib.gp_lp_refine.argtypes = [G, i32, i64, i32, i32, vp, ctypes.POINTER(LPStats), vp, ctypes.c_size_t, vp]
     lib.gp_lp_refine_static.argtypes = [G, i32, i64, i32, i32, vp, ctypes.POINTER(LPStats), vp]
+    lib.gp_mls_refine.argtypes = [G, i32, i64, vp, ctypes.c_uint64, i32, i32, i32, ctypes.POINTER(MLSStats), vp,
+                                  ctypes.c_size_t, vp]
     lib.gp_contract.argtypes = [G, vp, vp, vp, vp, vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i32), vp, ctypes.c_size_t, vp]
     lib.gp_project.argtypes = [i32, vp, vp, vp, vp]
     lib.gp_cut_and_blocks.argtypes = [G, i32, vp, ctypes.POINTER(i64), vp, vp, ctypes.c_size_t, vp]
@@ -254,6 +262,17 @@ def lp_refine_static(g, part, k, lmax_, rounds=25, dir_alternate=1, active=False
                                       ctypes.byref(st), _stream()))
     return P, {"rounds_run": st.rounds_run, "moves": st.moves, "edge_visits": st.edge_visits, "ms": st.ms,
                "workspace_bytes": st.workspace_bytes}
+
+
+def mls_refine(g, part, k, lmax_, seed=0, global_iters=3, batch=1, queue=64, ws=None):
+    """Multi-try k-way local search from a partition (gp_mls_refine); returns (part', stats)."""
+    torch = _torch()
+    gs = _gstruct(g)
+    P = part.to(dtype=torch.int32).clone().contiguous()
+    st = MLSStats()
+    _check(load().gp_mls_refine(ctypes.byref(gs), k, lmax_, _ptr(P), seed, global_iters, batch, queue,
+                                ctypes.byref(st), *_ws(ws), _stream()))
+    return P, {f: getattr(st, f) for f, _ in MLSStats._fields_}
 
 
 def contract(g, labels, ws=None):

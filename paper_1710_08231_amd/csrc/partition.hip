@@ -17,6 +17,7 @@
 
 #include "contract.hpp"
 #include "initpart.hpp"
+#include "mls.hpp"
 #include "mpnn.hpp"
 #include "prims.hpp"
 
@@ -112,6 +113,11 @@ void prof_flush() {
 
 namespace {
 
+struct HasEdges {
+    const int32_t *xadj;
+    __device__ int32_t operator()(int64_t v) const { return xadj[v + 1] > xadj[v] ? 1 : 0; }
+};
+
 __global__ void k_identity_labels(const int32_t *xadj, int32_t n, bool skip_isolated, const int32_t *vwgt,
                                   int32_t *labels, int64_t *W) {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
@@ -189,6 +195,18 @@ __global__ void k_check_symmetry(const int32_t *xadj, const int32_t *adjncy, con
         atomicAdd(&acc[1], r);
         atomicMax(&acc[2], loop);
     }
+}
+
+// block ids of the vertices with neighbours must lie in [0, lim); the others may hold -1
+__global__ void k_check_blocks(const int32_t *xadj, const int32_t *lab, int32_t n, int32_t lim,
+                               unsigned long long *bad) {
+    unsigned long long b = 0;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const bool has = xadj[v + 1] > xadj[v];
+        if (lab[v] >= lim || lab[v] < (has ? 0 : -1)) b = 1;
+    }
+    b = wave_max(b);
+    if (lane_id() == 0 && b) atomicMax(bad, b);
 }
 
 __global__ void k_check_labels(const int32_t *lab, int32_t n, int32_t lim, unsigned long long *bad) {
@@ -311,6 +329,12 @@ static int check_params(const gp_params *pp, int32_t k, const char *who) {
         pp->stall_den < 1 || pp->stall_num < 0 || (pp->init_mode != GP_INIT_PLAIN && pp->init_mode != GP_INIT_LEARNED) ||
         pp->active_set < 0 || pp->active_set > 3 || pp->init_fm < 0) {
         set_error((std::string(who) + ": invalid parameters").c_str());
+        return GP_ERR_ARG;
+    }
+    if (pp->mls < 0 || (pp->mls > 0 && (k > kMlsMaxK || pp->mls_queue < 1 || pp->mls_queue > kMlsMaxQueue ||
+                                        pp->mls_batch < 0 || pp->mls_batch > kMlsMaxBatch))) {
+        set_error((std::string(who) + ": multi-try local search needs mls >= 0, k <= 256, 1 <= mls_queue <= 64 and "
+                                      "0 <= mls_batch <= 65536").c_str());
         return GP_ERR_ARG;
     }
     if (pp->init_mode == GP_INIT_LEARNED && (!pp->mpnn_params || k > kMpMaxK || pp->mpnn_max_n < 0)) {
@@ -537,6 +561,14 @@ static int do_partition(const gp_graph *gin, int32_t k, double eps, const gp_par
     Timer t_ref(s);
     int64_t *B = nullptr;
     GP_TRY(sc.alloc(&B, k));
+    // level 0 keeps the vertices without neighbours: the search's hash order
+    // takes each vertex's rank among the others (its id on the graph without them)
+    int32_t *rank0 = nullptr;
+    int64_t mls_gain = 0;
+    if (p->mls > 0 && gi.niso > 0) {
+        GP_TRY(sc.alloc(&rank0, g0.n));
+        GP_TRY((scan<int32_t>(HasEdges{g0.xadj}, StoreExcl<int32_t>{rank0}, g0.n, nullptr, (int32_t *)nullptr, sc)));
+    }
     for (size_t l = Lc + 1; l-- > 0;) {
         const DevGraph &gl = lev[l].g;
         int32_t *Pl = P;
@@ -555,6 +587,12 @@ static int do_partition(const gp_graph *gin, int32_t k, double eps, const gp_par
         GP_TRY(lp_run(gl, Pl, B, k, lmax, p->rounds_refine, p->dir_alternate, wide, &st, sc, nullptr, nullptr, nullptr,
                       0, (p->active_set & 2) != 0));
         cp.done("lp_refine", lp_run_bytes(gl, st, k <= 256));
+        if (p->mls > 0) {
+            MlsOut mo;
+            GP_TRY(mls_refine(gl, k, lmax, Pl, B, l == 0 ? rank0 : nullptr, p->seed, p->mls,
+                              p->mls_batch > 0 ? p->mls_batch : 1, p->mls_queue, 50, 0.1, &mo, sc));
+            mls_gain += mo.gain;
+        }
         if (tracing()) {
             const float ms = t_lp.stop();
             std::fprintf(stderr, "[gp] refine level %zu n=%d nnz=%d %.3f ms (%d rounds, %lld moves, %.1f Gvisits/s)\n",
@@ -607,6 +645,7 @@ static int do_partition(const gp_graph *gin, int32_t k, double eps, const gp_par
         res->learned_kept = kept;
         res->plain_cut_coarsest = plain_cut_c;
         res->learned_cut_coarsest = prop_cut_c;
+        res->mls_gain = mls_gain;
         res->workspace_bytes = (int64_t)sc.high_water();
     }
     sc.release();
@@ -742,6 +781,9 @@ void gp_default_params(gp_params *p) {
     p->mpnn_params = nullptr;
     p->active_set = 0;
     p->init_fm = 0;
+    p->mls = 0;
+    p->mls_batch = 0;
+    p->mls_queue = kMlsMaxQueue;
 }
 
 int64_t gp_lmax(int64_t total_vwgt, int32_t k, double eps) {
@@ -815,6 +857,56 @@ int gp_lp_refine_static(const gp_graph *g, int32_t k, int64_t lmax, int32_t roun
     Scratch sc(stream, ptr, kStaticScratchBytes);
     sc.set_static();
     return lp_refine_call(g, k, lmax, rounds, flags, part_inout, st_host, sc, stream);
+}
+
+int gp_mls_refine(const gp_graph *g, int32_t k, int64_t lmax, int32_t *part_inout, uint64_t seed,
+                  int32_t global_iters, int32_t batch, int32_t queue, gp_mls_stats *st_host, void *ws,
+                  size_t ws_bytes, hipStream_t stream) {
+    GP_TRY(check_ws(ws, ws_bytes));
+    GP_TRY(check_graph_args(g));
+    if (k < 1 || k > kMlsMaxK || lmax < 1 || global_iters < 0 || batch < 1 || batch > kMlsMaxBatch || queue < 1 ||
+        queue > kMlsMaxQueue || !part_inout) {
+        set_error("mls_refine: needs 1 <= k <= 256, lmax >= 1, global_iters >= 0, 1 <= batch <= 65536, "
+                  "1 <= queue <= 64 and part");
+        return GP_ERR_ARG;
+    }
+    Scratch sc(stream, ws, ws_bytes);
+    Timer t(stream);
+    const DevGraph d = dev_graph(g);
+    GraphInfo gi;
+    GP_TRY(graph_info(d, gi, sc));
+    unsigned long long *bad = nullptr;
+    GP_TRY(sc.alloc(&bad, 1));
+    GP_HIP(hipMemsetAsync(bad, 0, sizeof(unsigned long long), stream));
+    if (d.n > 0) {
+        hipLaunchKernelGGL(k_check_blocks, dim3(grid_for(d.n, 256, 4096)), dim3(256), 0, stream, d.xadj, part_inout,
+                           d.n, k, bad);
+        GP_LAUNCH_CHECK();
+    }
+    unsigned long long hb = 0;
+    GP_HIP(hipMemcpyAsync(&hb, bad, sizeof(hb), hipMemcpyDeviceToHost, stream));
+    GP_HIP(hipStreamSynchronize(stream));
+    if (hb) {
+        set_error("mls_refine: a vertex with neighbours has a block id outside [0, k)");
+        return GP_ERR_GRAPH;
+    }
+    int64_t *B = nullptr;
+    GP_TRY(sc.alloc(&B, k));
+    GP_TRY(label_weights(d, part_inout, B, k, sc));
+    MlsOut mo;
+    GP_TRY(mls_refine(d, k, lmax, part_inout, B, nullptr, seed, global_iters, batch, queue, 50, 0.1, &mo, sc));
+    const float ms = t.stop();
+    if (st_host) {
+        st_host->gain = mo.gain;
+        st_host->searches = mo.searches;
+        st_host->moves = mo.moves;
+        st_host->local_iters = mo.local_iters;
+        st_host->ms = ms;
+        st_host->workspace_bytes = (int64_t)sc.high_water();
+    }
+    sc.release();
+    GP_HIP(hipStreamSynchronize(stream));
+    return GP_OK;
 }
 
 int gp_contract(const gp_graph *g, const int32_t *labels, int32_t *xadj_c, int32_t *adjncy_c, int32_t *adjwgt_c,
@@ -1073,8 +1165,9 @@ int gp_partition_batch(const gp_graph *g, int32_t G, const int32_t *vtx_off_host
         set_error("partition_batch: the learned initial partition is available for single graphs only");
         return GP_ERR_ARG;
     }
-    if (pp->active_set) {
-        set_error("partition_batch: active-set rounds are available for single graphs only");
+    if (pp->active_set || pp->mls) {
+        set_error("partition_batch: active-set rounds and the multi-try local search are available for single "
+                  "graphs only");
         return GP_ERR_ARG;
     }
     Scratch sc(stream, ws, ws_bytes);

@@ -68,7 +68,7 @@ def _header_struct_fields(name):
 
 @pytest.mark.parametrize("cls,name", [(gp.Graph, "gp_graph"), (gp.LPStats, "gp_lp_stats"),
                                       (gp.Params, "gp_params"), (gp.Result, "gp_result"),
-                                      (gp.Tuning, "gp_tuning")])
+                                      (gp.Tuning, "gp_tuning"), (gp.MLSStats, "gp_mls_stats")])
 def test_binding_structs_match_header(cls, name):
     # the ctypes mirrors list the header's fields in the header's order
     assert [f for f, _ in cls._fields_] == _header_struct_fields(name)
@@ -82,6 +82,7 @@ def test_default_params_host_function(lib):
     assert (p.stall_num, p.stall_den, p.dir_alternate, p.seed) == (19, 20, 1, 0)
     assert (p.init_mode, p.mpnn_max_n, p.mpnn_seed, p.mpnn_params) == (0, 131072, 0, None)
     assert (p.active_set, p.init_fm) == (0, 0)
+    assert (p.mls, p.mls_batch, p.mls_queue) == (0, 0, 64)
 
 
 def test_workspace_bytes_host_function(lib):
