@@ -259,6 +259,255 @@ __global__ __launch_bounds__(kPropBlock) void k_propose_group(LPArgs a, TierList
     }
 }
 
+// ---------------------------------------------------------------- packed tables (32-bit sums)
+//
+// With 32-bit connection sums a table slot is one 64-bit LDS word, label in
+// the high half and connection in the low half (an empty slot holds label
+// 0xFFFFFFFF), so an insert is one CAS (new label) or one 64-bit add (known
+// label) that returns the label's running sum. The largest connection (ties:
+// smallest label) is then known without scanning the table: every lane keeps
+// the maximum of the sums its own adds returned, packed as (sum << 32 | ~label);
+// the last add to a label returns its final sum, so the maximum over the lanes
+// is the maximum over the labels. Each lane remembers the slots it touched and
+// clears them afterwards. The table is scanned only when the best label has no
+// room under its bound (then for the best label with room), exactly as before.
+constexpr unsigned long long kSlotEmpty = 0xFFFFFFFF00000000ull;
+
+__device__ __forceinline__ unsigned long long pack_best(uint32_t c, int32_t L) {
+    return ((unsigned long long)c << 32) | (uint32_t)(~(uint32_t)L);
+}
+
+// Adds w to label L's slot (inserting it); returns the slot, *sum the label's sum after the add.
+__device__ __forceinline__ uint32_t slot_add(unsigned long long *tbl, uint32_t mask, int lg, int32_t L, uint32_t w,
+                                             uint32_t *sum) {
+    uint32_t h = hash_label(L) >> (32 - lg);
+    for (;;) {
+        unsigned long long cur = tbl[h];
+        if (cur == kSlotEmpty) {
+            cur = atomicCAS(&tbl[h], kSlotEmpty, ((unsigned long long)(uint32_t)L << 32) | w);
+            if (cur == kSlotEmpty) {
+                *sum = w;
+                return h;
+            }
+        }
+        if ((uint32_t)(cur >> 32) == (uint32_t)L) {
+            *sum = (uint32_t)atomicAdd(&tbl[h], (unsigned long long)w) + w;
+            return h;
+        }
+        h = (h + 1) & mask;
+    }
+}
+
+template <int GL>
+__device__ __forceinline__ unsigned long long group_max_u64(unsigned long long x) {
+#pragma unroll
+    for (int d = GL / 2; d > 0; d >>= 1) {
+        const unsigned long long y = __shfl_xor(x, d, GL);
+        x = y > x ? y : x;
+    }
+    return x;
+}
+
+// GL lanes per vertex, TBL packed slots per vertex (degrees up to TBL / 2).
+template <int GL, int TBL>
+__global__ __launch_bounds__(kPropBlock) void k_pgroup(LPArgs a, TierList lists, int tier) {
+    if (*a.done) return;
+    const int64_t t0 = lists.ts[tier];
+    const int32_t count = (int32_t)(lists.ts[tier + 1] - t0);
+    const int32_t *__restrict__ verts = lists.verts + t0;
+    const int32_t dmode = cur_dirmode(a);
+    constexpr int GPW = kWave / GL;
+    constexpr int NW = kPropBlock / kWave;
+    constexpr int LOG2 = __builtin_ctz(TBL);
+    constexpr int MAXE = 2 * ((TBL / 2 + 2 * GL - 1) / (2 * GL));  // entries per lane and vertex
+    __shared__ unsigned long long stbl[NW * GPW * TBL];
+    const int lane = lane_id(), w = threadIdx.x / kWave;
+    const int gl = lane % GL, grp = lane / GL;
+    unsigned long long *tbl = stbl + (w * GPW + grp) * TBL;
+    for (int i = gl; i < TBL; i += GL) tbl[i] = kSlotEmpty;
+    wave_sync();
+    const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t stride = (int64_t)gridDim.x * NW * GPW;
+    for (int64_t wb = ((int64_t)b * NW + w) * GPW; wb < count; wb += stride) {
+        const int64_t idx = wb + grp;
+        const bool valid = idx < count;
+        const int32_t v = valid ? verts[idx] : 0;
+        const int32_t beg = valid ? a.xadj[v] : 0;
+        const int32_t end = (valid && !inactive(a, v)) ? a.xadj[v + 1] : beg;
+        const int32_t own = valid ? a.labels[v] : -1;
+        int32_t oc = 0;
+        unsigned long long mybest = 0;
+        uint32_t touched[MAXE];  // fixed positions (registers): entry it*2 + j, ~0u when none
+        const int nch = (end - beg + GL - 1) / GL;
+        const int maxch = wave_max(nch);
+#pragma unroll
+        for (int it = 0; it < MAXE / 2; it++) {
+            touched[2 * it] = ~0u;
+            touched[2 * it + 1] = ~0u;
+            if (2 * it >= maxch) continue;
+            const int32_t e0 = beg + 2 * it * GL + gl, e1 = e0 + GL;
+            const int32_t u0 = e0 < end ? a.adjncy[e0] : -1, u1 = e1 < end ? a.adjncy[e1] : -1;
+            const int32_t w0 = (e0 < end && a.adjwgt) ? a.adjwgt[e0] : 1;
+            const int32_t w1 = (e1 < end && a.adjwgt) ? a.adjwgt[e1] : 1;
+            const int32_t L0 = u0 >= 0 ? a.labels[u0] : -1, L1 = u1 >= 0 ? a.labels[u1] : -1;
+            uint32_t sum;
+            if (u0 >= 0) {
+                if (L0 == own) oc += w0;
+                else if (dir_ok(L0, own, dmode)) {
+                    touched[2 * it] = slot_add(tbl, TBL - 1, LOG2, L0, (uint32_t)w0, &sum);
+                    const unsigned long long pb = pack_best(sum, L0);
+                    mybest = pb > mybest ? pb : mybest;
+                }
+            }
+            if (u1 >= 0) {
+                if (L1 == own) oc += w1;
+                else if (dir_ok(L1, own, dmode)) {
+                    touched[2 * it + 1] = slot_add(tbl, TBL - 1, LOG2, L1, (uint32_t)w1, &sum);
+                    const unsigned long long pb = pack_best(sum, L1);
+                    mybest = pb > mybest ? pb : mybest;
+                }
+            }
+        }
+        wave_sync();
+        oc = group_sum<GL>(oc);
+        mybest = group_max_u64<GL>(mybest);
+        const int32_t bc = (int32_t)(mybest >> 32);
+        const int32_t bl = mybest ? (int32_t)~(uint32_t)mybest : INT_MAX;
+        const int64_t cv = valid ? vweight(a.vwgt, v) : 0;
+        int32_t target = -1;
+        bool need2 = false;
+        if (valid && bl != INT_MAX && bc > oc) {
+            if (a.W[bl] + cv <= capof(a, bl)) target = bl;
+            else need2 = true;
+        }
+        if (__ballot(need2)) {
+            int32_t bc2 = 0, bl2 = INT_MAX;
+            if (need2) {
+                for (int i = gl; i < TBL; i += GL) {
+                    const unsigned long long sl = tbl[i];
+                    if (sl == kSlotEmpty) continue;
+                    const int32_t L = (int32_t)(sl >> 32), c = (int32_t)(uint32_t)sl;
+                    if (better(c, L, bc2, bl2) && a.W[L] + cv <= capof(a, L)) {
+                        bc2 = c;
+                        bl2 = L;
+                    }
+                }
+            }
+            group_best<GL, int32_t>(bc2, bl2);
+            if (need2 && bl2 != INT_MAX && bc2 > oc) target = bl2;
+        }
+        if (valid && gl == 0) a.prop[v] = target;
+        wave_sync();
+#pragma unroll
+        for (int i = 0; i < MAXE; i++)
+            if (touched[i] != ~0u) tbl[touched[i]] = kSlotEmpty;
+        wave_sync();
+    }
+}
+
+// One workgroup per vertex, BLOCK threads, packed table of the next power of
+// two >= 2*deg slots (at most TBL).
+template <int BLOCK, int TBL>
+__global__ __launch_bounds__(BLOCK) void k_pblock(LPArgs a, TierList lists, int tier) {
+    if (*a.done) return;
+    const int64_t t0 = lists.ts[tier];
+    const int32_t count = (int32_t)(lists.ts[tier + 1] - t0);
+    const int32_t *__restrict__ verts = lists.verts + t0;
+    const int32_t dmode = cur_dirmode(a);
+    constexpr int NW = BLOCK / kWave;
+    constexpr int U4 = 4;
+    constexpr int MAXE = U4 * ((TBL / 2 + U4 * BLOCK - 1) / (U4 * BLOCK));
+    __shared__ unsigned long long tbl[TBL];
+    __shared__ unsigned long long wbest[NW];
+    __shared__ int32_t tc[NW + 1];
+    __shared__ int32_t tl[NW + 1];
+    for (int i = threadIdx.x; i < TBL; i += BLOCK) tbl[i] = kSlotEmpty;
+    __syncthreads();
+    const int lane = lane_id(), w = threadIdx.x / kWave;
+    // the next vertex's id is loaded with the current vertex's edges, and its
+    // row range and label during the current selection, so each vertex
+    // starts with its edge loads
+    int64_t idx = xcd_block(blockIdx.x, gridDim.x);
+    int32_t v = idx < count ? verts[idx] : 0;
+    int32_t beg = idx < count ? a.xadj[v] : 0, end = idx < count ? a.xadj[v + 1] : 0;
+    int32_t own = idx < count ? a.labels[v] : -1;
+    for (; idx < count; idx += gridDim.x) {
+        const int64_t nidx = idx + gridDim.x;
+        const int32_t nv = nidx < count ? verts[nidx] : 0;
+        if (inactive(a, v)) end = beg;
+        int lg = 6;
+        while ((1 << lg) < 2 * (end - beg) && (1 << lg) < TBL) lg++;
+        const uint32_t cap = 1u << lg;
+        int32_t oc = 0;
+        unsigned long long mybest = 0;
+        uint32_t touched[MAXE];  // fixed positions (registers): entry it*U4 + j, ~0u when none
+#pragma unroll
+        for (int it = 0; it < MAXE / U4; it++) {
+            const int32_t e0 = beg + (int32_t)threadIdx.x + it * U4 * BLOCK;
+            int32_t u[U4], L[U4], wv[U4];
+#pragma unroll
+            for (int j = 0; j < U4; j++) {
+                const int32_t e = e0 + j * BLOCK;
+                u[j] = e < end ? a.adjncy[e] : -1;
+                wv[j] = (e < end && a.adjwgt) ? a.adjwgt[e] : 1;
+            }
+#pragma unroll
+            for (int j = 0; j < U4; j++) L[j] = u[j] >= 0 ? a.labels[u[j]] : -1;
+#pragma unroll
+            for (int j = 0; j < U4; j++) {
+                touched[it * U4 + j] = ~0u;
+                if (u[j] < 0) continue;
+                if (L[j] == own) oc += wv[j];
+                else if (dir_ok(L[j], own, dmode)) {
+                    uint32_t sum;
+                    touched[it * U4 + j] = slot_add(tbl, cap - 1, lg, L[j], (uint32_t)wv[j], &sum);
+                    const unsigned long long pb = pack_best(sum, L[j]);
+                    mybest = pb > mybest ? pb : mybest;
+                }
+            }
+        }
+        mybest = group_max_u64<kWave>(mybest);
+        if (lane == 0) wbest[w] = mybest;
+        const int32_t nbeg = nidx < count ? a.xadj[nv] : 0, nend = nidx < count ? a.xadj[nv + 1] : 0;
+        const int32_t nown = nidx < count ? a.labels[nv] : -1;
+        oc = block_sum<BLOCK>(oc, tc);  // its barriers also publish wbest and the table
+        unsigned long long best = wbest[0];
+        for (int i = 1; i < NW; i++) best = wbest[i] > best ? wbest[i] : best;
+        const int32_t bc = (int32_t)(best >> 32);
+        const int32_t bl = best ? (int32_t)~(uint32_t)best : INT_MAX;
+        const int64_t cv = vweight(a.vwgt, v);
+        int32_t target = -1;
+        if (bl != INT_MAX && bc > oc) {
+            if (a.W[bl] + cv <= capof(a, bl)) {
+                target = bl;
+            } else {
+                int32_t bc2 = 0, bl2 = INT_MAX;
+                for (uint32_t i = threadIdx.x; i < cap; i += BLOCK) {
+                    const unsigned long long sl = tbl[i];
+                    if (sl == kSlotEmpty) continue;
+                    const int32_t Li = (int32_t)(sl >> 32), c = (int32_t)(uint32_t)sl;
+                    if (better(c, Li, bc2, bl2) && a.W[Li] + cv <= capof(a, Li)) {
+                        bc2 = c;
+                        bl2 = Li;
+                    }
+                }
+                block_best<BLOCK, int32_t>(bc2, bl2, tc, tl);
+                if (bl2 != INT_MAX && bc2 > oc) target = bl2;
+            }
+        }
+        if (threadIdx.x == 0) a.prop[v] = target;
+        __syncthreads();  // every lane has read the table and wbest
+#pragma unroll
+        for (int i = 0; i < MAXE; i++)
+            if (touched[i] != ~0u) tbl[touched[i]] = kSlotEmpty;
+        __syncthreads();
+        v = nv;
+        beg = nbeg;
+        end = nend;
+        own = nown;
+    }
+}
+
 // One workgroup per vertex, table in LDS sized to the vertex: next power of
 // two >= 2*deg (at most TBL), so scanning and clearing cost O(deg).
 template <int BLOCK, int TBL, typename AccT>
@@ -1303,36 +1552,44 @@ int launch_proposals(const LPArgs &a, const int32_t *verts, const int64_t *tstar
     auto blocks_for = [&](int32_t c, int per_block) { return grid_for(c, per_block, 16384); };
     int32_t c;
     if ((c = cnt(1)) > 0) {
-        GP_PROF_LAUNCH((std::string("k_propose_group<4, 8, ") + acc + ">").c_str(), tb[1], s, hipLaunchKernelGGL((k_propose_group<4, 8, AccT>), dim3(blocks_for(c, NW * 16)), dim3(kPropBlock), 0, s,
+        if constexpr (sizeof(AccT) == 4) GP_PROF_LAUNCH((std::string("k_pgroup<4, 8, ") + acc + ">").c_str(), tb[1], s, hipLaunchKernelGGL((k_pgroup<4, 8>), dim3(blocks_for(c, NW * 16)), dim3(kPropBlock), 0, s,
+                           a, tl, 1)); else GP_PROF_LAUNCH((std::string("k_propose_group<4, 8, ") + acc + ">").c_str(), tb[1], s, hipLaunchKernelGGL((k_propose_group<4, 8, AccT>), dim3(blocks_for(c, NW * 16)), dim3(kPropBlock), 0, s,
                            a, tl, 1));
     }
     if ((c = cnt(2)) > 0) {
-        GP_PROF_LAUNCH((std::string("k_propose_group<8, 16, ") + acc + ">").c_str(), tb[2], s, hipLaunchKernelGGL((k_propose_group<8, 16, AccT>), dim3(blocks_for(c, NW * 8)), dim3(kPropBlock), 0, s,
+        if constexpr (sizeof(AccT) == 4) GP_PROF_LAUNCH((std::string("k_pgroup<8, 16, ") + acc + ">").c_str(), tb[2], s, hipLaunchKernelGGL((k_pgroup<8, 16>), dim3(blocks_for(c, NW * 8)), dim3(kPropBlock), 0, s,
+                           a, tl, 2)); else GP_PROF_LAUNCH((std::string("k_propose_group<8, 16, ") + acc + ">").c_str(), tb[2], s, hipLaunchKernelGGL((k_propose_group<8, 16, AccT>), dim3(blocks_for(c, NW * 8)), dim3(kPropBlock), 0, s,
                            a, tl, 2));
     }
     if ((c = cnt(3)) > 0) {
-        GP_PROF_LAUNCH((std::string("k_propose_group<16, 32, ") + acc + ">").c_str(), tb[3], s, hipLaunchKernelGGL((k_propose_group<16, 32, AccT>), dim3(blocks_for(c, NW * 4)), dim3(kPropBlock), 0,
+        if constexpr (sizeof(AccT) == 4) GP_PROF_LAUNCH((std::string("k_pgroup<16, 32, ") + acc + ">").c_str(), tb[3], s, hipLaunchKernelGGL((k_pgroup<16, 32>), dim3(blocks_for(c, NW * 4)), dim3(kPropBlock), 0,
+                           s, a, tl, 3)); else GP_PROF_LAUNCH((std::string("k_propose_group<16, 32, ") + acc + ">").c_str(), tb[3], s, hipLaunchKernelGGL((k_propose_group<16, 32, AccT>), dim3(blocks_for(c, NW * 4)), dim3(kPropBlock), 0,
                            s, a, tl, 3));
     }
     if ((c = cnt(4)) > 0) {
-        GP_PROF_LAUNCH((std::string("k_propose_group<32, 128, ") + acc + ">").c_str(), tb[4], s, hipLaunchKernelGGL((k_propose_group<32, 128, AccT>), dim3(blocks_for(c, NW * 2)), dim3(kPropBlock), 0,
+        if constexpr (sizeof(AccT) == 4) GP_PROF_LAUNCH((std::string("k_pgroup<32, 128, ") + acc + ">").c_str(), tb[4], s, hipLaunchKernelGGL((k_pgroup<32, 128>), dim3(blocks_for(c, NW * 2)), dim3(kPropBlock), 0,
+                           s, a, tl, 4)); else GP_PROF_LAUNCH((std::string("k_propose_group<32, 128, ") + acc + ">").c_str(), tb[4], s, hipLaunchKernelGGL((k_propose_group<32, 128, AccT>), dim3(blocks_for(c, NW * 2)), dim3(kPropBlock), 0,
                            s, a, tl, 4));
     }
     if ((c = cnt(5)) > 0) {
-        GP_PROF_LAUNCH((std::string("k_propose_group<64, 512, ") + acc + ">").c_str(), tb[5], s, hipLaunchKernelGGL((k_propose_group<64, 512, AccT>), dim3(blocks_for(c, NW)), dim3(kPropBlock), 0, s,
+        if constexpr (sizeof(AccT) == 4) GP_PROF_LAUNCH((std::string("k_pgroup<64, 512, ") + acc + ">").c_str(), tb[5], s, hipLaunchKernelGGL((k_pgroup<64, 512>), dim3(blocks_for(c, NW)), dim3(kPropBlock), 0, s,
+                           a, tl, 5)); else GP_PROF_LAUNCH((std::string("k_propose_group<64, 512, ") + acc + ">").c_str(), tb[5], s, hipLaunchKernelGGL((k_propose_group<64, 512, AccT>), dim3(blocks_for(c, NW)), dim3(kPropBlock), 0, s,
                            a, tl, 5));
     }
     if ((c = cnt(6)) > 0) {
-        GP_PROF_LAUNCH((std::string("k_propose_block<128, 2048, ") + acc + ">").c_str(), tb[6], s, hipLaunchKernelGGL((k_propose_block<128, 2048, AccT>), dim3(grid_for(c, 1, 16384)), dim3(128), 0, s, a,
+        if constexpr (sizeof(AccT) == 4) GP_PROF_LAUNCH((std::string("k_pblock<128, 2048, ") + acc + ">").c_str(), tb[6], s, hipLaunchKernelGGL((k_pblock<128, 2048>), dim3(grid_for(c, 1, 16384)), dim3(128), 0, s, a,
+                           tl, 6)); else GP_PROF_LAUNCH((std::string("k_propose_block<128, 2048, ") + acc + ">").c_str(), tb[6], s, hipLaunchKernelGGL((k_propose_block<128, 2048, AccT>), dim3(grid_for(c, 1, 16384)), dim3(128), 0, s, a,
                            tl, 6));
     }
     if ((c = cnt(7)) > 0) {
-        GP_PROF_LAUNCH((std::string("k_propose_block<256, 4096, ") + acc + ">").c_str(), tb[7], s, hipLaunchKernelGGL((k_propose_block<256, 4096, AccT>), dim3(grid_for(c, 1, 8192)), dim3(256), 0, s, a,
+        if constexpr (sizeof(AccT) == 4) GP_PROF_LAUNCH((std::string("k_pblock<256, 4096, ") + acc + ">").c_str(), tb[7], s, hipLaunchKernelGGL((k_pblock<256, 4096>), dim3(grid_for(c, 1, 8192)), dim3(256), 0, s, a,
+                           tl, 7)); else GP_PROF_LAUNCH((std::string("k_propose_block<256, 4096, ") + acc + ">").c_str(), tb[7], s, hipLaunchKernelGGL((k_propose_block<256, 4096, AccT>), dim3(grid_for(c, 1, 8192)), dim3(256), 0, s, a,
                            tl, 7));
     }
     if ((c = cnt(8)) > 0) {
         constexpr int T8 = sizeof(AccT) == 4 ? 16384 : 8192;
-        GP_PROF_LAUNCH((std::string("k_propose_block<1024, ") + std::to_string(T8) + ", " + acc + ">").c_str(), tb[8], s, hipLaunchKernelGGL((k_propose_block<1024, T8, AccT>), dim3(grid_for(c, 1, 2048)), dim3(1024), 0, s, a,
+        if constexpr (sizeof(AccT) == 4) GP_PROF_LAUNCH((std::string("k_pblock<1024, ") + std::to_string(T8) + ", " + acc + ">").c_str(), tb[8], s, hipLaunchKernelGGL((k_pblock<1024, T8>), dim3(grid_for(c, 1, 2048)), dim3(1024), 0, s, a,
+                           tl, 8)); else GP_PROF_LAUNCH((std::string("k_propose_block<1024, ") + std::to_string(T8) + ", " + acc + ">").c_str(), tb[8], s, hipLaunchKernelGGL((k_propose_block<1024, T8, AccT>), dim3(grid_for(c, 1, 2048)), dim3(1024), 0, s, a,
                            tl, 8));
     }
     if (!skip_hubs && (c = cnt(9)) > 0) {
