@@ -197,7 +197,7 @@ def apply_tuning(args):
     """Apply the autotuned LP thresholds of this workload, when present (they
     change speed only, never a result)."""
     import paper_1710_08231_amd as gp
-    path = os.path.join(ROOT, "paper_1710_08231_amd", "tuning", f"{args.workload}.json")
+    path = args.tuning or os.path.join(ROOT, "paper_1710_08231_amd", "tuning", f"{args.workload}.json")
     if args.no_tuning or not os.path.exists(path):
         return
     with open(path) as f:
@@ -344,6 +344,11 @@ def main():
                     help="active-set LP rounds: 1 coarsening, 2 refinement, 3 both (results differ from full rounds)")
     ap.add_argument("--init-fm", type=int, default=0,
                     help="2-way FM passes after every initial bisection (0: none; results differ)")
+    ap.add_argument("--mls", type=int, default=0,
+                    help="multi-try local search after every level's LP refinement: global iterations (0: off)")
+    ap.add_argument("--mls-batch", type=int, default=1024, help="searches per batch of the local search")
+    ap.add_argument("--mls-queue", type=int, default=64, help="vertices one search may queue (1..64)")
+    ap.add_argument("--tuning", default=None, help="a tuning file to apply instead of the workload's own")
     ap.add_argument("--no-tuning", action="store_true",
                     help="ignore paper_1710_08231_amd/tuning/<workload>.json (use the default thresholds)")
     ap.add_argument("--no-profile", action="store_true",
@@ -376,7 +381,8 @@ def main():
     dg = gp.to_device(g)
     torch.cuda.synchronize()
     k = w["k"]
-    prm = dict(attempts=args.attempts, active_set=args.active_set, init_fm=args.init_fm)
+    prm = dict(attempts=args.attempts, active_set=args.active_set, init_fm=args.init_fm, mls=args.mls,
+               mls_batch=args.mls_batch, mls_queue=args.mls_queue)
     # warmup; the last warmup step also times every proposal kernel (all launches) to find the dominant one
     dominant = None
     warm_table = {}
@@ -421,7 +427,7 @@ def main():
     last = results[-1]
     print(f"[bench] timed {args.steps} steps: {ms:.2f} ms/step (wall per step {[round(x, 1) for x in step_ms]}, "
           f"device {[round(r['ms_total'], 1) for r in results]})", file=sys.stderr, flush=True)
-    parity = golden_parity(args.workload, part, last) if not (args.active_set or args.init_fm or
+    parity = golden_parity(args.workload, part, last) if not (args.active_set or args.init_fm or args.mls or
                                                                args.attempts != 4) else None
     print(f"[bench] parity against the oracle's golden: {parity}", file=sys.stderr, flush=True)
     levels, family = [], {}
@@ -451,7 +457,8 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "nnz": nnz, "k": k, "eps": 0.03, "attempts": args.attempts,
-                   "active_set": args.active_set, "init_fm": args.init_fm,
+                   "active_set": args.active_set, "init_fm": args.init_fm, "mls": args.mls,
+                   "mls_batch": args.mls_batch if args.mls else None, "mls_queue": args.mls_queue if args.mls else None,
                    "tuning": TUNING},
         "partition_ms": ms,
         "cut": last["cut"],
@@ -461,6 +468,7 @@ def main():
         "parity": parity,
         "levels": last["levels"],
         "coarsest_n": last["coarsest_n"],
+        "mls_gain": last["mls_gain"],
         "edge_visits_per_step": visits // args.steps,
         "phase_ms": {"coarsen": last["ms_coarsen"], "init": last["ms_init"], "refine": last["ms_refine"]},
         "step_wall_ms": [round(x, 2) for x in step_ms],

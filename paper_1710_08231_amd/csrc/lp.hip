@@ -954,11 +954,13 @@ __global__ __launch_bounds__(kPropBlock) void k_dense_group(LPArgs a, int32_t nl
     const int32_t dmode = cur_dirmode(a);
     constexpr int GPW = kWave / GL;
     constexpr int NW = kPropBlock / kWave;
-    __shared__ AccT sval[NW * GPW * KT];
+    // one table per lane group, KT + 1 apart so that the same block id of two
+    // groups falls in different LDS banks
+    __shared__ AccT sval[NW * GPW * (KT + 1)];
     __shared__ int64_t sW[KT];
     const int lane = lane_id(), w = threadIdx.x / kWave;
     const int gl = lane % GL, grp = lane / GL;
-    AccT *val = sval + (w * GPW + grp) * KT;
+    AccT *val = sval + (w * GPW + grp) * (KT + 1);
     // slack of each label at the round start: W - capacity (> 0 never eligible)
     for (int i = threadIdx.x; i < KT; i += kPropBlock) sW[i] = i < nlabels ? a.W[i] - capof(a, i) : (int64_t(1) << 62);
     for (int i = gl; i < KT; i += GL) val[i] = 0;
@@ -1041,11 +1043,12 @@ __global__ __launch_bounds__(256) void k_dense_chunk(LPArgs a, DenseBig db) {
     constexpr int NW = 256 / kWave;
     // SUB tables per wave (lanes split evenly) spread the LDS atomics of a
     // wave over SUB x KT addresses when k is small
-    constexpr int SUB = KT <= 16 ? 8 : (KT <= 64 ? 4 : 1);
-    __shared__ AccT val[NW * SUB][KT];
+    constexpr int SUB = KT <= 64 ? 8 : 2;
+    // rows KT + 1 apart: the same block id of two tables falls in different LDS banks
+    __shared__ AccT val[NW * SUB][KT + 1];
     __shared__ AccT tmp[NW + 1];
     const int w = (threadIdx.x / kWave) * SUB + lane_id() / (kWave / SUB);
-    for (int i = threadIdx.x; i < NW * SUB * KT; i += 256) (&val[0][0])[i] = 0;
+    for (int i = threadIdx.x; i < NW * SUB * (KT + 1); i += 256) (&val[0][0])[i] = 0;
     __syncthreads();
     // the chunk's vertex and entry range come in one load (planned once per
     // call), so the edge loads wait on one load, not on three dependent ones
@@ -1076,11 +1079,13 @@ __global__ __launch_bounds__(256) void k_dense_chunk(LPArgs a, DenseBig db) {
     }
     __syncthreads();
     AccT *row = (AccT *)db.gconn + (int64_t)b * KT;
-    for (int i = threadIdx.x; i < KT; i += 256) {
-        AccT c = 0;
-        for (int q = 0; q < NW * SUB; q++) c += val[q][i];
-        if (c) gadd<AccT>(&row[i], c);
-    }
+    // all threads reduce the tables: P consecutive lanes per block id
+    constexpr int P = 256 / KT, NT = NW * SUB;
+    const int lab = threadIdx.x / P, part = threadIdx.x % P;
+    AccT c = 0;
+    for (int q = part; q < NT; q += P) c += val[q][lab];
+    c = group_sum<P>(c);
+    if (part == 0 && c) gadd<AccT>(&row[lab], c);
     oc = block_sum<256>(oc, tmp);
     if (threadIdx.x == 0 && oc) atomicAdd(&db.own[b], (unsigned long long)oc);
 }
@@ -1344,6 +1349,123 @@ __global__ void k_apply_w(const uint32_t *mk, const int32_t *mv, const int32_t *
     }
 }
 
+// Admission, weight update and round bookkeeping of one round in a single
+// workgroup, for at most kFuseMax movers (single graphs without active sets):
+// the work of k_heads, the prefix scan, k_admit, k_apply_w and k_round_end
+// in one launch. Movers arrive sorted by target (stable, so ascending vertex
+// inside a target); each thread owns kFuseItems consecutive movers. The
+// prefix of a mover is the inclusive sum of c over its target's segment up to
+// it: a segmented scan (a segment starts where the target changes).
+constexpr int kFuseBlock = 1024;
+constexpr int kFuseItems = 16;
+constexpr int kFuseMax = kFuseBlock * kFuseItems;
+
+__global__ __launch_bounds__(kFuseBlock) void k_admit_fused(const uint32_t *mk, const int32_t *mv,
+                                                            const int32_t *nmov, const int32_t *vwgt, int64_t *W,
+                                                            int64_t U, const int64_t *capv, int32_t *labels,
+                                                            uint8_t *lab8, LPDev *dev) {
+    constexpr int NW = kFuseBlock / kWave;
+    __shared__ uint8_t adm[kFuseMax + 1];
+    __shared__ int32_t wf[NW], pf[NW];
+    __shared__ long long wv[NW], pv[NW];
+    __shared__ int32_t cnt_s[NW + 1];
+    const int32_t n = min(*nmov, kFuseMax);
+    const int lane = lane_id(), w = threadIdx.x / kWave;
+    const int32_t base = threadIdx.x * kFuseItems;
+    uint32_t t[kFuseItems];
+    long long c[kFuseItems];
+    bool hd[kFuseItems];
+    // the thread's aggregate: (has a segment head, sum after its last head)
+    bool tf = false;
+    long long tv = 0;
+#pragma unroll
+    for (int j = 0; j < kFuseItems; j++) {
+        const int32_t p = base + j;
+        const bool valid = p < n;
+        t[j] = valid ? mk[p] : 0u;
+        c[j] = valid ? vweight(vwgt, mv[p]) : 0;
+        hd[j] = valid && (p == 0 || mk[p - 1] != t[j]);
+        if (hd[j]) {
+            tf = true;
+            tv = c[j];
+        } else {
+            tv += c[j];
+        }
+    }
+    // block exclusive scan of the aggregates: (f1, v1) then (f2, v2) = (f1 | f2, f2 ? v2 : v1 + v2)
+    bool f = tf;
+    long long v = tv;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int fo = __shfl_up((int)f, d, kWave);
+        const long long vo = __shfl_up(v, d, kWave);
+        if (lane >= d) {
+            v = f ? v : vo + v;
+            f = f || fo;
+        }
+    }
+    int fe = __shfl_up((int)f, 1, kWave);
+    long long ve = __shfl_up(v, 1, kWave);
+    if (lane == 0) {
+        fe = 0;
+        ve = 0;
+    }
+    if (lane == kWave - 1) {
+        wf[w] = f;
+        wv[w] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t af = 0;
+        long long av = 0;
+        for (int i = 0; i < NW; i++) {
+            pf[i] = af;
+            pv[i] = av;
+            av = wf[i] ? wv[i] : av + wv[i];
+            af = af || wf[i];
+        }
+    }
+    __syncthreads();
+    long long run = fe ? ve : pv[w] + ve;  // sum of the open segment before this thread's first mover
+    long long pre[kFuseItems];
+#pragma unroll
+    for (int j = 0; j < kFuseItems; j++) {
+        run = hd[j] ? c[j] : run + c[j];
+        pre[j] = run;
+        const int32_t p = base + j;
+        if (p < n) adm[p] = (W[t[j]] + pre[j] <= (capv ? capv[t[j]] : U)) ? 1 : 0;
+    }
+    if (threadIdx.x == 0) adm[n] = 0;
+    __syncthreads();  // every admission read the weights of the round start
+    int32_t cnt = 0;
+#pragma unroll
+    for (int j = 0; j < kFuseItems; j++) {
+        const int32_t p = base + j;
+        if (p >= n || !adm[p]) continue;
+        const int32_t vx = mv[p];
+        const int32_t old = labels[vx];
+        labels[vx] = (int32_t)t[j];
+        if (lab8) lab8[vx] = (uint8_t)t[j];
+        atomicAdd((unsigned long long *)&W[old], (unsigned long long)(-c[j]));
+        // admitted movers form a prefix of their segment: its last one adds the segment's weight
+        const bool tail = p + 1 == n || !adm[p + 1] || mk[p + 1] != t[j];
+        if (tail) atomicAdd((unsigned long long *)&W[t[j]], (unsigned long long)pre[j]);
+        cnt++;
+    }
+    cnt = block_sum<kFuseBlock>(cnt, cnt_s);
+    if (threadIdx.x == 0) {  // k_round_end with this round's moves
+        const int32_t r = dev->round;
+        dev->round = r + 1;
+        if (!dev->done) {
+            dev->rounds_run = r + 1;
+            dev->total_moves += cnt;
+            if (r >= 1 && cnt == 0 && dev->prev_moves == 0) dev->done = 1;
+            dev->prev_moves = cnt;
+            dev->round_moves = 0;
+        }
+    }
+}
+
 // Few labels: net weight change per label aggregated in LDS first.
 __global__ __launch_bounds__(256) void k_apply_w_small(const uint32_t *mk, const int32_t *mv, const int32_t *nmov,
                                                        const int32_t *oldlab, const int32_t *vwgt, int32_t nl,
@@ -1543,7 +1665,7 @@ struct NoOut64 {
 template <typename AccT>
 int launch_proposals(const LPArgs &a, const int32_t *verts, const int64_t *tstart, TierList tl,
                      const int32_t *hub_log, const int64_t *hub_off, int32_t *gkey, AccT *gval, hipStream_t s,
-                     const double *tb, bool skip_hubs = false) {
+                     const double *tb, bool skip_hubs, int32_t t8max) {
     const char *acc = sizeof(AccT) == 4 ? "int" : "long";
     auto cnt = [&](int t) { return (int32_t)(tstart[t + 1] - tstart[t]); };
     auto lst = [&](int t) { return verts + tstart[t]; };
@@ -1588,8 +1710,14 @@ int launch_proposals(const LPArgs &a, const int32_t *verts, const int64_t *tstar
     }
     if ((c = cnt(8)) > 0) {
         constexpr int T8 = sizeof(AccT) == 4 ? 16384 : 8192;
-        if constexpr (sizeof(AccT) == 4) GP_PROF_LAUNCH((std::string("k_pblock<1024, ") + std::to_string(T8) + ", " + acc + ">").c_str(), tb[8], s, hipLaunchKernelGGL((k_pblock<1024, T8>), dim3(grid_for(c, 1, 2048)), dim3(1024), 0, s, a,
-                           tl, 8)); else GP_PROF_LAUNCH((std::string("k_propose_block<1024, ") + std::to_string(T8) + ", " + acc + ">").c_str(), tb[8], s, hipLaunchKernelGGL((k_propose_block<1024, T8, AccT>), dim3(grid_for(c, 1, 2048)), dim3(1024), 0, s, a,
+        // degrees up to 4096 fit a 64 KB packed table: two workgroups per CU
+        if constexpr (sizeof(AccT) == 4) {
+            if (t8max <= 4096)
+                GP_PROF_LAUNCH("k_pblock<1024, 8192, int>", tb[8], s, hipLaunchKernelGGL((k_pblock<1024, 8192>), dim3(grid_for(c, 1, 4096)), dim3(1024), 0, s, a, tl, 8));
+            else
+                GP_PROF_LAUNCH((std::string("k_pblock<1024, ") + std::to_string(T8) + ", " + acc + ">").c_str(), tb[8], s, hipLaunchKernelGGL((k_pblock<1024, T8>), dim3(grid_for(c, 1, 2048)), dim3(1024), 0, s, a,
+                           tl, 8));
+        } else GP_PROF_LAUNCH((std::string("k_propose_block<1024, ") + std::to_string(T8) + ", " + acc + ">").c_str(), tb[8], s, hipLaunchKernelGGL((k_propose_block<1024, T8, AccT>), dim3(grid_for(c, 1, 2048)), dim3(1024), 0, s, a,
                            tl, 8));
     }
     if (!skip_hubs && (c = cnt(9)) > 0) {
@@ -2016,10 +2144,10 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
             RT_TRY(launch_dense_any<int32_t>(a, nlabels, tstart, tl, &db, dchunks, s, tbytes));
         else if (wide)
             RT_TRY(launch_proposals<int64_t>(a, verts, tstart, tl, hub_log, hub_off, gkey, (int64_t *)gval, s,
-                                             tbytes, false));
+                                             tbytes, false, tk.bound[8]));
         else
             RT_TRY(launch_proposals<int32_t>(a, verts, tstart, tl, hub_log, hub_off, gkey, (int32_t *)gval, s,
-                                             tbytes, split_hubs));
+                                             tbytes, split_hubs, tk.bound[8]));
         if (split_hubs) {
             GP_PROF_LAUNCH("k_hub_insert", tbytes[kTiers - 1], s, hipLaunchKernelGGL(k_hub_insert, dim3(nchunks), dim3(kHubBlock), 0, s, a, hp));
             hipLaunchKernelGGL(k_hub_reduce, dim3(nbuckets), dim3(kRedBlock), 0, s, a, hp);
@@ -2037,6 +2165,12 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
         uint32_t *k1 = mk, *k2 = mk2;
         int32_t *v1 = mv, *v2 = mv2;
         RT_TRY((radix_sort<uint32_t, int32_t>(&k1, &v1, &k2, &v2, n, nmov, key_bits, sc)));
+        if (!group && !act && n <= kFuseMax) {  // small level: the rest of the round in one launch
+            hipLaunchKernelGGL(k_admit_fused, dim3(1), dim3(kFuseBlock), 0, s, k1, v1, nmov, g.vwgt, W, U, capv,
+                               labels, lab8, dev);
+            GP_LAUNCH_CHECK();
+            return GP_OK;
+        }
         const unsigned gb = grid_for(n, 256, 8192);
         hipLaunchKernelGGL(k_heads, dim3(gb), dim3(256), 0, s, k1, nmov, headpos);
         GP_LAUNCH_CHECK();

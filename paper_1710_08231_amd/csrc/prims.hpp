@@ -215,7 +215,7 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K *kin, cons
     const int lane = lane_id(), w = threadIdx.x / kWave;
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (kWave - lane));
     for (int d = threadIdx.x; d < NW * 256; d += kSortBlock) (&wc[0][0])[d] = 0;
-    goff[threadIdx.x] = offs[(int64_t)threadIdx.x * ntiles + blockIdx.x];
+    if (offs) goff[threadIdx.x] = offs[(int64_t)threadIdx.x * ntiles + blockIdx.x];
     __syncthreads();
     const int64_t wbase = base + (int64_t)w * PER_W;
     K key[R];
@@ -252,6 +252,8 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K *kin, cons
         acc += t;
     }
     dstart[threadIdx.x] = block_excl_scan<kSortBlock>(acc, tmp, (uint32_t *)nullptr);
+    // one tile alone (offs == null): its own digit starts are the global ones
+    if (!offs) goff[threadIdx.x] = dstart[threadIdx.x];
     __syncthreads();
     // local position of each item; its digit is kept for the value pass
 #pragma unroll
@@ -294,6 +296,21 @@ int radix_sort(K **keys, V **vals, K **ktmp, V **vtmp, int64_t nmax, const int32
     hipStream_t s = sc.stream();
     if (nmax <= 0 || bits <= 0) return GP_OK;
     const int ntiles = (int)((nmax + kSortTile - 1) / kSortTile);
+    if (ntiles == 1) {  // one tile: one launch per pass ranks, places and writes it
+        for (int shift = 0; shift < bits; shift += 8) {
+            const int nb = (bits - shift) < 8 ? (bits - shift) : 8;
+            hipLaunchKernelGGL((k_radix_scatter<K, V>), dim3(1), dim3(kSortBlock), 0, s, *keys, *vals, *ktmp, *vtmp,
+                               nmax, n_dev, shift, nb, (const uint32_t *)nullptr, 1);
+            GP_LAUNCH_CHECK();
+            K *tk = *keys;
+            *keys = *ktmp;
+            *ktmp = tk;
+            V *tv = *vals;
+            *vals = *vtmp;
+            *vtmp = tv;
+        }
+        return GP_OK;
+    }
     uint32_t *hist = nullptr;
     GP_TRY(sc.temp(&hist, (size_t)256 * ntiles, kSortHistSlot));
     for (int shift = 0; shift < bits; shift += 8) {

@@ -402,3 +402,23 @@ def test_hub_bucket_overflow(dirs):
     p, st = gp.lp_refine(dg, torch.from_numpy(part).cuda(), 300, lm, 6, dirs)
     op, ost = oracle.lp_refine(g, part, 300, lm, 6, dirs)
     assert np.array_equal(_np(p), op) and {k: st[k] for k in ost} == ost
+
+
+def test_packed_tables_at_every_block_tier_size():
+    # tier bounds of 4096 and 8192 select the 1024-thread workgroups with 8192-
+    # and 16384-slot packed tables; R-MAT-17 has vertices in both degree ranges
+    g = graphgen.rmat(17, 11)
+    deg = np.diff(g["xadj"])
+    assert np.count_nonzero((deg > 2048) & (deg <= 4096)) > 5 and np.count_nonzero((deg > 4096) & (deg <= 8192)) > 0
+    dg = gp.to_device(g)
+    olab, ost = oracle.lp_cluster(g, 300, 10)
+    opart, ores = oracle.partition(g, 16)
+    try:
+        for t3 in (4096, 8192):
+            gp.set_tuning({"tier_max": [64, 256, 2048, t3], "dense_split": 256, "dense_chunk": 2048})
+            lab, st = gp.lp_cluster(dg, 300, 10)
+            assert np.array_equal(_np(lab), olab) and st["moves"] == ost["moves"], t3
+            p, r = gp.partition(dg, 16)
+            assert np.array_equal(_np(p), opart) and r["cut"] == ores["cut"], t3
+    finally:
+        gp.set_tuning(None)
