@@ -1349,118 +1349,210 @@ __global__ void k_apply_w(const uint32_t *mk, const int32_t *mv, const int32_t *
     }
 }
 
-// Admission, weight update and round bookkeeping of one round in a single
-// workgroup, for at most kFuseMax movers (single graphs without active sets):
-// the work of k_heads, the prefix scan, k_admit, k_apply_w and k_round_end
-// in one launch. Movers arrive sorted by target (stable, so ascending vertex
-// inside a target); each thread owns kFuseItems consecutive movers. The
-// prefix of a mover is the inclusive sum of c over its target's segment up to
-// it: a segmented scan (a segment starts where the target changes).
+// Everything of a round after the proposals, in one workgroup, for graphs of
+// at most kFuseMax vertices (single graphs without active sets): compaction
+// of the movers in ascending vertex order, the stable sort by target, the
+// segmented prefix of mover weights per target, admission against the
+// weights of the round start, the label and weight updates and the round
+// bookkeeping — the work of compact, radix_sort, k_heads, the prefix scan,
+// k_admit, k_apply_w and k_round_end. A mover is packed as
+// (target << vbits) | vertex in LDS. Position p of a sequence belongs to wave
+// p / kFuseWaveSpan, row (p % kFuseWaveSpan) / kWave, lane p % kWave, so the
+// (wave, row, lane) order is the position order.
 constexpr int kFuseBlock = 1024;
-constexpr int kFuseItems = 16;
-constexpr int kFuseMax = kFuseBlock * kFuseItems;
+constexpr int kFuseRows = 16;
+constexpr int kFuseWaveSpan = kFuseRows * kWave;
+constexpr int kFuseMax = kFuseBlock * kFuseRows;
+constexpr int kFuseAggLabels = 2048;  // labels whose weight changes are summed in LDS first
 
-__global__ __launch_bounds__(kFuseBlock) void k_admit_fused(const uint32_t *mk, const int32_t *mv,
-                                                            const int32_t *nmov, const int32_t *vwgt, int64_t *W,
-                                                            int64_t U, const int64_t *capv, int32_t *labels,
-                                                            uint8_t *lab8, LPDev *dev) {
+__global__ __launch_bounds__(kFuseBlock) void k_round_small(const int32_t *prop, int32_t n, int vbits,
+                                                            int key_bits, const int32_t *vwgt, int64_t *W,
+                                                            int64_t U, const int64_t *capv, int32_t nlabels,
+                                                            int32_t *labels, uint8_t *lab8, LPDev *dev) {
     constexpr int NW = kFuseBlock / kWave;
-    __shared__ uint8_t adm[kFuseMax + 1];
-    __shared__ int32_t wf[NW], pf[NW];
-    __shared__ long long wv[NW], pv[NW];
-    __shared__ int32_t cnt_s[NW + 1];
-    const int32_t n = min(*nmov, kFuseMax);
+    __shared__ uint32_t bufA[kFuseMax], bufB[kFuseMax];
+    __shared__ __align__(8) uint32_t wc[NW * 256];  // digit counters; later the per-label weight deltas
+    __shared__ uint32_t dstart[256];
+    __shared__ int32_t wcount[NW + 1];
+    __shared__ int32_t wf[NW];
+    __shared__ long long wv[NW];
     const int lane = lane_id(), w = threadIdx.x / kWave;
-    const int32_t base = threadIdx.x * kFuseItems;
-    uint32_t t[kFuseItems];
-    long long c[kFuseItems];
-    bool hd[kFuseItems];
-    // the thread's aggregate: (has a segment head, sum after its last head)
-    bool tf = false;
-    long long tv = 0;
-#pragma unroll
-    for (int j = 0; j < kFuseItems; j++) {
-        const int32_t p = base + j;
-        const bool valid = p < n;
-        t[j] = valid ? mk[p] : 0u;
-        c[j] = valid ? vweight(vwgt, mv[p]) : 0;
-        hd[j] = valid && (p == 0 || mk[p - 1] != t[j]);
-        if (hd[j]) {
-            tf = true;
-            tv = c[j];
-        } else {
-            tv += c[j];
-        }
-    }
-    // block exclusive scan of the aggregates: (f1, v1) then (f2, v2) = (f1 | f2, f2 ? v2 : v1 + v2)
-    bool f = tf;
-    long long v = tv;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const int fo = __shfl_up((int)f, d, kWave);
-        const long long vo = __shfl_up(v, d, kWave);
-        if (lane >= d) {
-            v = f ? v : vo + v;
-            f = f || fo;
-        }
-    }
-    int fe = __shfl_up((int)f, 1, kWave);
-    long long ve = __shfl_up(v, 1, kWave);
-    if (lane == 0) {
-        fe = 0;
-        ve = 0;
-    }
-    if (lane == kWave - 1) {
-        wf[w] = f;
-        wv[w] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int32_t af = 0;
-        long long av = 0;
-        for (int i = 0; i < NW; i++) {
-            pf[i] = af;
-            pv[i] = av;
-            av = wf[i] ? wv[i] : av + wv[i];
-            af = af || wf[i];
-        }
-    }
-    __syncthreads();
-    long long run = fe ? ve : pv[w] + ve;  // sum of the open segment before this thread's first mover
-    long long pre[kFuseItems];
-#pragma unroll
-    for (int j = 0; j < kFuseItems; j++) {
-        run = hd[j] ? c[j] : run + c[j];
-        pre[j] = run;
-        const int32_t p = base + j;
-        if (p < n) adm[p] = (W[t[j]] + pre[j] <= (capv ? capv[t[j]] : U)) ? 1 : 0;
-    }
-    if (threadIdx.x == 0) adm[n] = 0;
-    __syncthreads();  // every admission read the weights of the round start
+    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (kWave - lane));
+    const int32_t wbase = w * kFuseWaveSpan;
+    const int32_t done = dev->done;
+    // ---- compaction: movers in ascending vertex order
+    uint32_t item[kFuseRows];
+    int32_t rank[kFuseRows];
     int32_t cnt = 0;
 #pragma unroll
-    for (int j = 0; j < kFuseItems; j++) {
-        const int32_t p = base + j;
-        if (p >= n || !adm[p]) continue;
-        const int32_t vx = mv[p];
-        const int32_t old = labels[vx];
-        labels[vx] = (int32_t)t[j];
-        if (lab8) lab8[vx] = (uint8_t)t[j];
-        atomicAdd((unsigned long long *)&W[old], (unsigned long long)(-c[j]));
-        // admitted movers form a prefix of their segment: its last one adds the segment's weight
-        const bool tail = p + 1 == n || !adm[p + 1] || mk[p + 1] != t[j];
-        if (tail) atomicAdd((unsigned long long *)&W[t[j]], (unsigned long long)pre[j]);
-        cnt++;
+    for (int r = 0; r < kFuseRows; r++) {
+        const int32_t v = wbase + r * kWave + lane;
+        int32_t t = -1;
+        if (!done && v < n) t = prop[v];
+        const uint64_t m = __ballot(t >= 0);
+        item[r] = ((uint32_t)t << vbits) | (uint32_t)v;
+        rank[r] = (t >= 0) ? cnt + (int32_t)__popcll(m & lt) : -1;
+        cnt += (int32_t)__popcll(m);
     }
-    cnt = block_sum<kFuseBlock>(cnt, cnt_s);
-    if (threadIdx.x == 0) {  // k_round_end with this round's moves
+    if (lane == 0) wcount[w] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t acc = 0;
+        for (int i = 0; i < NW; i++) {
+            const int32_t c = wcount[i];
+            wcount[i] = acc;
+            acc += c;
+        }
+        wcount[NW] = acc;
+    }
+    __syncthreads();
+    const int32_t m = wcount[NW];
+#pragma unroll
+    for (int r = 0; r < kFuseRows; r++)
+        if (rank[r] >= 0) bufA[wcount[w] + rank[r]] = item[r];
+    __syncthreads();
+    // ---- stable LSD sort by target, 8 bits a pass
+    uint32_t *cur = bufA, *oth = bufB;
+    for (int shift = 0; shift < key_bits; shift += 8) {
+        const int nb = (key_bits - shift) < 8 ? (key_bits - shift) : 8;
+        const uint32_t mask = (1u << nb) - 1u;
+        for (int d = threadIdx.x; d < NW * 256; d += kFuseBlock) wc[d] = 0;
+        __syncthreads();
+        uint32_t dg[kFuseRows];
+#pragma unroll
+        for (int r = 0; r < kFuseRows; r++) {
+            const int32_t p = wbase + r * kWave + lane;
+            rank[r] = -1;
+            if (wbase + r * kWave >= m) continue;  // wave-uniform
+            const bool valid = p < m;
+            item[r] = valid ? cur[p] : 0u;
+            const uint32_t dig = (item[r] >> (vbits + shift)) & mask;
+            dg[r] = dig;
+            uint64_t peers = __ballot(valid);
+            for (int bt = 0; bt < nb; bt++) {
+                const bool bit = (dig >> bt) & 1u;
+                const uint64_t bm = __ballot(bit);
+                peers &= bit ? bm : ~bm;
+            }
+            const uint32_t before = valid ? wc[w * 256 + dig] : 0u;
+            const uint32_t pr = (uint32_t)__popcll(peers & lt);
+            if (valid) rank[r] = (int32_t)(before + pr);
+            // every lane read the counter before the group's first lane advances it
+            if (valid && pr == 0) wc[w * 256 + dig] = before + (uint32_t)__popcll(peers);
+        }
+        __syncthreads();
+        uint32_t acc = 0;
+        if (threadIdx.x < 256)
+            for (int q = 0; q < NW; q++) {
+                const uint32_t c = wc[q * 256 + threadIdx.x];
+                wc[q * 256 + threadIdx.x] = acc;
+                acc += c;
+            }
+        const uint32_t ds = block_excl_scan<kFuseBlock>(acc, (uint32_t *)wcount, (uint32_t *)nullptr);
+        if (threadIdx.x < 256) dstart[threadIdx.x] = ds;
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kFuseRows; r++)
+            if (rank[r] >= 0) oth[dstart[dg[r]] + wc[w * 256 + dg[r]] + (uint32_t)rank[r]] = item[r];
+        __syncthreads();
+        uint32_t *tq = cur;
+        cur = oth;
+        oth = tq;
+    }
+    // ---- segmented prefix of mover weights per target, in position order
+    const uint32_t vmask = (vbits >= 32) ? ~0u : ((1u << vbits) - 1u);
+    long long pre[kFuseRows];
+    bool seen[kFuseRows];
+    bool cf = false;  // a segment head at or before the row's end within this wave
+    long long cv = 0;
+#pragma unroll
+    for (int r = 0; r < kFuseRows; r++) {
+        const int32_t p = wbase + r * kWave + lane;
+        pre[r] = 0;
+        seen[r] = false;
+        if (wbase + r * kWave >= m) continue;  // wave-uniform
+        const bool valid = p < m;
+        const uint32_t it = valid ? cur[p] : 0u;
+        item[r] = it;
+        const long long c = valid ? (long long)vweight(vwgt, (int32_t)(it & vmask)) : 0;
+        const bool hd = valid && (p == 0 || (cur[p - 1] >> vbits) != (it >> vbits));
+        bool f = hd;
+        long long v = c;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const int fo = __shfl_up((int)f, d, kWave);
+            const long long vo = __shfl_up(v, d, kWave);
+            if (lane >= d) {
+                v = f ? v : vo + v;
+                f = f || fo;
+            }
+        }
+        if (!f) v += cv;
+        f = f || cf;
+        pre[r] = v;
+        seen[r] = f;
+        cf = __shfl(f, kWave - 1, kWave);
+        cv = __shfl(v, kWave - 1, kWave);
+    }
+    if (lane == 0) {
+        wf[w] = cf;
+        wv[w] = cv;
+    }
+    __syncthreads();
+    long long carry = 0;  // the open segment's sum before this wave
+    for (int i = 0; i < w; i++) carry = wf[i] ? wv[i] : carry + wv[i];
+    // ---- admission against the weights of the round start
+    uint8_t *adm = reinterpret_cast<uint8_t *>(oth);
+#pragma unroll
+    for (int r = 0; r < kFuseRows; r++) {
+        const int32_t p = wbase + r * kWave + lane;
+        if (p >= m) continue;
+        if (!seen[r]) pre[r] += carry;
+        const uint32_t t = item[r] >> vbits;
+        adm[p] = (W[t] + pre[r] <= (capv ? capv[t] : U)) ? 1 : 0;
+    }
+    const bool agg = nlabels <= kFuseAggLabels;
+    unsigned long long *dw = reinterpret_cast<unsigned long long *>(wc);
+    if (agg)
+        for (int i = threadIdx.x; i < nlabels; i += kFuseBlock) dw[i] = 0;
+    __syncthreads();
+    // ---- labels and weights
+    int32_t moves = 0;
+#pragma unroll
+    for (int r = 0; r < kFuseRows; r++) {
+        const int32_t p = wbase + r * kWave + lane;
+        if (p >= m || !adm[p]) continue;
+        const uint32_t t = item[r] >> vbits;
+        const int32_t vx = (int32_t)(item[r] & vmask);
+        const int32_t old = labels[vx];
+        const long long c = (long long)vweight(vwgt, vx);
+        labels[vx] = (int32_t)t;
+        if (lab8) lab8[vx] = (uint8_t)t;
+        // admitted movers form a prefix of their target's segment: its last one adds the segment's weight
+        const bool tail = p + 1 == m || !adm[p + 1] || (cur[p + 1] >> vbits) != t;
+        if (agg) {
+            atomicAdd(&dw[old], (unsigned long long)(-c));
+            if (tail) atomicAdd(&dw[t], (unsigned long long)pre[r]);
+        } else {
+            atomicAdd((unsigned long long *)&W[old], (unsigned long long)(-c));
+            if (tail) atomicAdd((unsigned long long *)&W[t], (unsigned long long)pre[r]);
+        }
+        moves++;
+    }
+    moves = block_sum<kFuseBlock>(moves, wcount);
+    if (agg) {  // this workgroup is the only writer of W in this launch
+        __syncthreads();
+        for (int i = threadIdx.x; i < nlabels; i += kFuseBlock)
+            if (dw[i]) W[i] += (int64_t)dw[i];
+    }
+    if (threadIdx.x == 0) {  // round bookkeeping (k_round_end with this round's moves)
         const int32_t r = dev->round;
         dev->round = r + 1;
-        if (!dev->done) {
+        if (!done) {
             dev->rounds_run = r + 1;
-            dev->total_moves += cnt;
-            if (r >= 1 && cnt == 0 && dev->prev_moves == 0) dev->done = 1;
-            dev->prev_moves = cnt;
+            dev->total_moves += moves;
+            if (r >= 1 && moves == 0 && dev->prev_moves == 0) dev->done = 1;
+            dev->prev_moves = moves;
             dev->round_moves = 0;
         }
     }
@@ -2091,6 +2183,8 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
         group = nullptr;
     }
     const int key_bits = bits_for(nlabels > 0 ? nlabels - 1 : 0);
+    const int vbits = bits_for(n > 0 ? n - 1 : 0);
+    const bool fuse_rest = !group && !active && n <= kFuseMax && vbits + key_bits <= 32;
     // active-set rounds: every vertex starts owing one evaluation per direction
     const uint8_t renew = dir_alternate ? 2 : 1;
     uint8_t *act = nullptr;
@@ -2160,17 +2254,17 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
                                nmbig);
             GP_LAUNCH_CHECK();
         }
+        if (fuse_rest) {  // small level: the rest of the round in one launch
+            hipLaunchKernelGGL(k_round_small, dim3(1), dim3(kFuseBlock), 0, s, prop, (int32_t)n, vbits, key_bits,
+                               g.vwgt, W, U, capv, (int32_t)nlabels, labels, lab8, dev);
+            GP_LAUNCH_CHECK();
+            return GP_OK;
+        }
         // compaction of movers (ascending vertex id)
         RT_TRY(compact(MoverFlag{prop, &dev->done}, MoverEmit{prop, mk, mv}, n, nullptr, nmov, sc));
         uint32_t *k1 = mk, *k2 = mk2;
         int32_t *v1 = mv, *v2 = mv2;
         RT_TRY((radix_sort<uint32_t, int32_t>(&k1, &v1, &k2, &v2, n, nmov, key_bits, sc)));
-        if (!group && !act && n <= kFuseMax) {  // small level: the rest of the round in one launch
-            hipLaunchKernelGGL(k_admit_fused, dim3(1), dim3(kFuseBlock), 0, s, k1, v1, nmov, g.vwgt, W, U, capv,
-                               labels, lab8, dev);
-            GP_LAUNCH_CHECK();
-            return GP_OK;
-        }
         const unsigned gb = grid_for(n, 256, 8192);
         hipLaunchKernelGGL(k_heads, dim3(gb), dim3(256), 0, s, k1, nmov, headpos);
         GP_LAUNCH_CHECK();
