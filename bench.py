@@ -9,9 +9,9 @@ levels and rounds) / step time; ms_per_step = end-to-end partition time.
 Prints one JSON line. Default workload: R-MAT scale 24, edge factor 16
 (a,b,c,d = .57,.19,.19,.05, seed 24), k = 64, eps = 0.03.
 
-The timed steps run the production path (LP rounds replayed as HIP graphs).
-Inside them only the eagerly launched first-round launches of the dominant
-proposal kernel are bracketed by HIP events (the roofline sample). Two
+The timed steps run the production path (every LP round launched directly).
+Inside them only the first-round launches of the dominant proposal kernel in
+every LP run are bracketed by HIP events (the roofline sample). Two
 instrumented passes follow the timed region: LP runs per level (production
 path) and every proposal kernel per level (rounds launched one by one).
 The final partition is compared with the oracle's stored result
@@ -110,8 +110,8 @@ def cpu_baseline(g, w, budget_rounds):
 
 def roofline(entry, workload):
     """Dominant proposal kernel: algorithmic bytes per launch / mean launch time
-    (HIP events on the kernel's stream, its eagerly launched first-round
-    launches inside the timed steps) against the HBM peak."""
+    (HIP events on the kernel's stream around its first-round launches of
+    every LP run inside the timed steps) against the HBM peak."""
     if not entry or not entry["launches"]:
         return None
     achieved = entry["bytes"] / entry["ms"] / 1e6  # GB/s
@@ -126,7 +126,7 @@ def roofline(entry, workload):
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": entry["name"],
             "launches": entry["launches"], "mean_launch_ms": entry["ms"] / entry["launches"],
             "algorithmic_bytes_per_launch": entry["bytes"] / entry["launches"],
-            "sample": "first-round launches of every LP run in the timed steps (later rounds are graph replays)"}
+            "sample": "first-round launches of every LP run in the timed steps (a first round does a full round's work)"}
 
 
 def level_tables(calls, kernels):
@@ -384,7 +384,7 @@ def main():
     prm = dict(attempts=args.attempts, active_set=args.active_set, init_fm=args.init_fm, mls=args.mls,
                mls_batch=args.mls_batch, mls_queue=args.mls_queue)
     # warmup; the last warmup step also times every proposal kernel (all launches) to find the dominant one
-    dominant = None
+    dominant, dom_launches = None, 0
     warm_table = {}
     for i in range(max(1, args.warmup)):
         last_warm = i == max(1, args.warmup) - 1 and not args.no_profile
@@ -396,17 +396,17 @@ def main():
             entries = gp.profile_entries()
             gp.profile_enable(0)
             if entries:
-                dominant = max(entries, key=lambda e: e["ms"])["name"]
+                top = max(entries, key=lambda e: e["ms"])
+                dominant, dom_launches = top["name"], top["launches"]
             warm_table = {e["name"]: round(e["ms"], 3) for e in sorted(entries, key=lambda e: -e["ms"])[:10]}
         print(f"[bench] warmup {i} ms={res['ms_total']:.2f}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    # timed region: the production path (rounds replayed as HIP graphs); HIP events bracket only
-    # the dominant kernel's eagerly launched first-round launches, on the library's stream, with
-    # events created beforehand
+    # timed region: the production path; HIP events bracket only the dominant kernel's first-round
+    # launches of every LP run, on the library's stream, with events created beforehand
     if dominant:
         gp.profile_select(dominant)
         gp.profile_enable(gp.PROFILE_EAGER)
-        gp.profile_reserve(4096)
+        gp.profile_reserve(dom_launches * args.steps + 64)
     visits = 0
     results = []
     step_ms = []

@@ -450,9 +450,9 @@ int gp_release_cache(void);
  * recording with the mode bits below; gp_profile_enable(0) stops.
  *   GP_PROFILE_KERNELS  every launch of an LP proposal kernel is bracketed;
  *                       rounds are then launched one by one (no replay).
- *   GP_PROFILE_EAGER    only the proposal launches issued directly (the first
- *                       round of every LP run); later rounds are replayed as
- *                       usual, so the timed path is the production one.
+ *   GP_PROFILE_EAGER    only the proposal launches of the first round of
+ *                       every LP run; the later rounds run without events, so
+ *                       the timed path stays the production one.
  *   GP_PROFILE_CALLS    every LP run inside gp_partition is bracketed and
  *                       recorded as "lp_cluster" or "lp_refine", with the
  *                       run's algorithmic bytes: per edge visit the neighbour

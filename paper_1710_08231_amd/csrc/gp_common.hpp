@@ -330,8 +330,21 @@ bool prof_wants(const char *name);
 bool prof_blocks_replay();
 // LP-call events (whole gp clustering / refinement runs per level)
 bool prof_calls();
-// while a launch sequence is recorded for replay no event is recorded
-void prof_capturing(bool on);
+// while suspended no event is recorded (a launch sequence recorded for
+// replay; the rounds after the first under GP_PROFILE_EAGER)
+void prof_suspend(bool on);
+// GP_PROFILE_EAGER without GP_PROFILE_KERNELS: only the first round of every
+// LP run is sampled, so the rounds that follow run without events
+bool prof_first_round_only();
+struct ProfSuspend {
+    bool on;
+    explicit ProfSuspend(bool b) : on(b) {
+        if (on) prof_suspend(true);
+    }
+    ~ProfSuspend() {
+        if (on) prof_suspend(false);
+    }
+};
 void prof_context(const char *ctx);
 void prof_record(const char *name, hipEvent_t a, hipEvent_t b, double bytes);
 hipEvent_t prof_event();

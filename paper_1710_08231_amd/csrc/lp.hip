@@ -1360,26 +1360,63 @@ __global__ void k_apply_w(const uint32_t *mk, const int32_t *mv, const int32_t *
 // p / kFuseWaveSpan, row (p % kFuseWaveSpan) / kWave, lane p % kWave, so the
 // (wave, row, lane) order is the position order.
 constexpr int kFuseBlock = 1024;
+constexpr int kFuseWaves = kFuseBlock / kWave;
 constexpr int kFuseRows = 16;
 constexpr int kFuseWaveSpan = kFuseRows * kWave;
 constexpr int kFuseMax = kFuseBlock * kFuseRows;
-constexpr int kFuseAggLabels = 2048;  // labels whose weight changes are summed in LDS first
+constexpr int kFuseLdsLabels = 1024;  // label weights held in LDS for the whole round
+
+// Exclusive prefix of x over the workgroup in thread order; *total gets the
+// sum. Every thread adds up the wave totals before its own wave.
+template <typename T>
+__device__ __forceinline__ T fuse_excl_scan(T x, T *tmp, T *total) {
+    const int lane = lane_id(), w = threadIdx.x / kWave;
+    const T inc = wave_incl_scan(x);
+    if (lane == kWave - 1) tmp[w] = inc;
+    __syncthreads();
+    T before = 0, all = 0;
+#pragma unroll
+    for (int i = 0; i < kFuseWaves; i++) {
+        const T t = tmp[i];
+        before += i < w ? t : T(0);
+        all += t;
+    }
+    *total = all;
+    __syncthreads();
+    return before + inc - x;
+}
 
 __global__ __launch_bounds__(kFuseBlock) void k_round_small(const int32_t *prop, int32_t n, int vbits,
                                                             int key_bits, const int32_t *vwgt, int64_t *W,
                                                             int64_t U, const int64_t *capv, int32_t nlabels,
                                                             int32_t *labels, uint8_t *lab8, LPDev *dev) {
-    constexpr int NW = kFuseBlock / kWave;
+    constexpr int NW = kFuseWaves;
     __shared__ uint32_t bufA[kFuseMax], bufB[kFuseMax];
-    __shared__ __align__(8) uint32_t wc[NW * 256];  // digit counters; later the per-label weight deltas
-    __shared__ uint32_t dstart[256];
-    __shared__ int32_t wcount[NW + 1];
+    __shared__ uint32_t wc[NW * 256];  // per (wave, digit) counters, then placement offsets
+    __shared__ long long Wl[kFuseLdsLabels];
+    __shared__ int32_t tmpi[NW];
+    __shared__ uint32_t tmpu[NW];
     __shared__ int32_t wf[NW];
     __shared__ long long wv[NW];
     const int lane = lane_id(), w = threadIdx.x / kWave;
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (kWave - lane));
     const int32_t wbase = w * kFuseWaveSpan;
+    const bool wlds = nlabels <= kFuseLdsLabels;
+    // everything the round reads from its start state is requested at once
     const int32_t done = dev->done;
+    int32_t round = 0, prev_moves = 0;
+    if (threadIdx.x == 0) {
+        round = dev->round;
+        prev_moves = dev->prev_moves;
+    }
+    int32_t t_of[kFuseRows];
+#pragma unroll
+    for (int r = 0; r < kFuseRows; r++) {
+        const int32_t v = wbase + r * kWave + lane;
+        t_of[r] = v < n ? prop[v] : -1;
+    }
+    if (wlds)
+        for (int i = threadIdx.x; i < nlabels; i += kFuseBlock) Wl[i] = W[i];
     // ---- compaction: movers in ascending vertex order
     uint32_t item[kFuseRows];
     int32_t rank[kFuseRows];
@@ -1387,33 +1424,22 @@ __global__ __launch_bounds__(kFuseBlock) void k_round_small(const int32_t *prop,
 #pragma unroll
     for (int r = 0; r < kFuseRows; r++) {
         const int32_t v = wbase + r * kWave + lane;
-        int32_t t = -1;
-        if (!done && v < n) t = prop[v];
-        const uint64_t m = __ballot(t >= 0);
+        const int32_t t = done ? -1 : t_of[r];
+        const uint64_t mb = __ballot(t >= 0);
         item[r] = ((uint32_t)t << vbits) | (uint32_t)v;
-        rank[r] = (t >= 0) ? cnt + (int32_t)__popcll(m & lt) : -1;
-        cnt += (int32_t)__popcll(m);
+        rank[r] = (t >= 0) ? cnt + (int32_t)__popcll(mb & lt) : -1;
+        cnt += (int32_t)__popcll(mb);
     }
-    if (lane == 0) wcount[w] = cnt;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int32_t acc = 0;
-        for (int i = 0; i < NW; i++) {
-            const int32_t c = wcount[i];
-            wcount[i] = acc;
-            acc += c;
-        }
-        wcount[NW] = acc;
-    }
-    __syncthreads();
-    const int32_t m = wcount[NW];
+    int32_t m = 0;
+    const int32_t woff = fuse_excl_scan<int32_t>(lane == 0 ? cnt : 0, tmpi, &m);
+    const int32_t wstart = __shfl(woff, 0, kWave);
 #pragma unroll
     for (int r = 0; r < kFuseRows; r++)
-        if (rank[r] >= 0) bufA[wcount[w] + rank[r]] = item[r];
+        if (rank[r] >= 0) bufA[wstart + rank[r]] = item[r];
     __syncthreads();
     // ---- stable LSD sort by target, 8 bits a pass
     uint32_t *cur = bufA, *oth = bufB;
-    for (int shift = 0; shift < key_bits; shift += 8) {
+    for (int shift = 0; m > 0 && shift < key_bits; shift += 8) {
         const int nb = (key_bits - shift) < 8 ? (key_bits - shift) : 8;
         const uint32_t mask = (1u << nb) - 1u;
         for (int d = threadIdx.x; d < NW * 256; d += kFuseBlock) wc[d] = 0;
@@ -1423,6 +1449,7 @@ __global__ __launch_bounds__(kFuseBlock) void k_round_small(const int32_t *prop,
         for (int r = 0; r < kFuseRows; r++) {
             const int32_t p = wbase + r * kWave + lane;
             rank[r] = -1;
+            dg[r] = 0;
             if (wbase + r * kWave >= m) continue;  // wave-uniform
             const bool valid = p < m;
             item[r] = valid ? cur[p] : 0u;
@@ -1441,26 +1468,34 @@ __global__ __launch_bounds__(kFuseBlock) void k_round_small(const int32_t *prop,
             if (valid && pr == 0) wc[w * 256 + dig] = before + (uint32_t)__popcll(peers);
         }
         __syncthreads();
-        uint32_t acc = 0;
-        if (threadIdx.x < 256)
-            for (int q = 0; q < NW; q++) {
-                const uint32_t c = wc[q * 256 + threadIdx.x];
-                wc[q * 256 + threadIdx.x] = acc;
-                acc += c;
+        // placement offsets in (digit, wave) order: thread i owns digit i / 4, waves 4 (i % 4) .. + 3
+        {
+            const int d = threadIdx.x >> 2, q0 = (threadIdx.x & 3) * 4;
+            uint32_t c[4], sum = 0;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                c[j] = wc[(q0 + j) * 256 + d];
+                sum += c[j];
             }
-        const uint32_t ds = block_excl_scan<kFuseBlock>(acc, (uint32_t *)wcount, (uint32_t *)nullptr);
-        if (threadIdx.x < 256) dstart[threadIdx.x] = ds;
+            uint32_t tot = 0;
+            uint32_t off = fuse_excl_scan<uint32_t>(sum, tmpu, &tot);
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                wc[(q0 + j) * 256 + d] = off;
+                off += c[j];
+            }
+        }
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < kFuseRows; r++)
-            if (rank[r] >= 0) oth[dstart[dg[r]] + wc[w * 256 + dg[r]] + (uint32_t)rank[r]] = item[r];
+            if (rank[r] >= 0) oth[wc[w * 256 + dg[r]] + (uint32_t)rank[r]] = item[r];
         __syncthreads();
         uint32_t *tq = cur;
         cur = oth;
         oth = tq;
     }
     // ---- segmented prefix of mover weights per target, in position order
-    const uint32_t vmask = (vbits >= 32) ? ~0u : ((1u << vbits) - 1u);
+    const uint32_t vmask = (1u << vbits) - 1u;
     long long pre[kFuseRows];
     bool seen[kFuseRows];
     bool cf = false;  // a segment head at or before the row's end within this wave
@@ -1509,12 +1544,9 @@ __global__ __launch_bounds__(kFuseBlock) void k_round_small(const int32_t *prop,
         if (p >= m) continue;
         if (!seen[r]) pre[r] += carry;
         const uint32_t t = item[r] >> vbits;
-        adm[p] = (W[t] + pre[r] <= (capv ? capv[t] : U)) ? 1 : 0;
+        const long long wt = wlds ? Wl[t] : W[t];
+        adm[p] = (wt + pre[r] <= (capv ? capv[t] : U)) ? 1 : 0;
     }
-    const bool agg = nlabels <= kFuseAggLabels;
-    unsigned long long *dw = reinterpret_cast<unsigned long long *>(wc);
-    if (agg)
-        for (int i = threadIdx.x; i < nlabels; i += kFuseBlock) dw[i] = 0;
     __syncthreads();
     // ---- labels and weights
     int32_t moves = 0;
@@ -1530,29 +1562,25 @@ __global__ __launch_bounds__(kFuseBlock) void k_round_small(const int32_t *prop,
         if (lab8) lab8[vx] = (uint8_t)t;
         // admitted movers form a prefix of their target's segment: its last one adds the segment's weight
         const bool tail = p + 1 == m || !adm[p + 1] || (cur[p + 1] >> vbits) != t;
-        if (agg) {
-            atomicAdd(&dw[old], (unsigned long long)(-c));
-            if (tail) atomicAdd(&dw[t], (unsigned long long)pre[r]);
-        } else {
-            atomicAdd((unsigned long long *)&W[old], (unsigned long long)(-c));
-            if (tail) atomicAdd((unsigned long long *)&W[t], (unsigned long long)pre[r]);
+        unsigned long long *wo = wlds ? (unsigned long long *)&Wl[old] : (unsigned long long *)&W[old];
+        atomicAdd(wo, (unsigned long long)(-c));
+        if (tail) {
+            unsigned long long *wt = wlds ? (unsigned long long *)&Wl[t] : (unsigned long long *)&W[t];
+            atomicAdd(wt, (unsigned long long)pre[r]);
         }
         moves++;
     }
-    moves = block_sum<kFuseBlock>(moves, wcount);
-    if (agg) {  // this workgroup is the only writer of W in this launch
-        __syncthreads();
-        for (int i = threadIdx.x; i < nlabels; i += kFuseBlock)
-            if (dw[i]) W[i] += (int64_t)dw[i];
-    }
+    int32_t total = 0;
+    (void)fuse_excl_scan<int32_t>(moves, tmpi, &total);  // ends with a barrier
+    if (wlds)  // this workgroup is the only writer of W in this launch
+        for (int i = threadIdx.x; i < nlabels; i += kFuseBlock) W[i] = Wl[i];
     if (threadIdx.x == 0) {  // round bookkeeping (k_round_end with this round's moves)
-        const int32_t r = dev->round;
-        dev->round = r + 1;
+        dev->round = round + 1;
         if (!done) {
-            dev->rounds_run = r + 1;
-            dev->total_moves += moves;
-            if (r >= 1 && moves == 0 && dev->prev_moves == 0) dev->done = 1;
-            dev->prev_moves = moves;
+            dev->rounds_run = round + 1;
+            dev->total_moves += total;
+            if (round >= 1 && total == 0 && prev_moves == 0) dev->done = 1;
+            dev->prev_moves = total;
             dev->round_moves = 0;
         }
     }
@@ -1820,13 +1848,13 @@ int launch_proposals(const LPArgs &a, const int32_t *verts, const int64_t *tstar
     return GP_OK;
 }
 
-// GP_ROUND_GRAPHS=0 disables graph replay of rounds (eager launches every round).
+// GP_ROUND_GRAPHS=1 records one round's launch sequence once per LP run and
+// replays it as a HIP graph for the later rounds; unset or 0, every round is
+// launched directly (faster on this stack: a graph launch costs the host more
+// than the few launches of a round it replaces). Read at every LP run.
 bool use_round_graphs() {
-    static const bool on = [] {
-        const char *e = std::getenv("GP_ROUND_GRAPHS");
-        return !(e && e[0] == '0');
-    }();
-    return on;
+    const char *e = std::getenv("GP_ROUND_GRAPHS");
+    return e && e[0] == '1';
 }
 
 // A library-owned stream (default priority) used only to record launch
@@ -2300,9 +2328,9 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
             hipGraphExec_t exec = nullptr;
             if (cs && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) {
                 sc.set_stream(cs, true);
-                prof_capturing(true);
+                prof_suspend(true);
                 const int rc = emit_round(cs);
-                prof_capturing(false);
+                prof_suspend(false);
                 sc.set_stream(s, false);
                 const hipError_t ec = hipStreamEndCapture(cs, &graph);
                 if (rc == GP_OK && ec == hipSuccess && graph &&
@@ -2316,8 +2344,10 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
             if (exec) (void)hipGraphExecDestroy(exec);
             if (graph) (void)hipGraphDestroy(graph);
         }
-        if (!replayed)
+        if (!replayed) {
+            const ProfSuspend quiet(prof_first_round_only());
             for (int32_t r = 1; r < rounds; r++) GP_TRY(emit_round(s));
+        }
     }
     if (out || prof_on()) {
         LPDev h;

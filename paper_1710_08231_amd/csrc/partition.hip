@@ -71,7 +71,8 @@ bool prof_wants(const char *name) {
 }
 bool prof_blocks_replay() { return (g_prof & GP_PROFILE_KERNELS) != 0; }
 bool prof_calls() { return (g_prof & GP_PROFILE_CALLS) != 0; }
-void prof_capturing(bool on) { g_capturing = on; }
+void prof_suspend(bool on) { g_capturing = on; }
+bool prof_first_round_only() { return (g_prof & GP_PROFILE_EAGER) && !(g_prof & GP_PROFILE_KERNELS); }
 void prof_context(const char *ctx) { g_ctx = ctx ? ctx : ""; }
 
 hipEvent_t prof_event() {
