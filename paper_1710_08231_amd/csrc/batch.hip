@@ -26,14 +26,26 @@ namespace gp {
 
 namespace {
 
+// Per graph: total vertex weight, largest vertex weight, vertices without
+// neighbours. The vertices of one graph are contiguous, so a wave mostly
+// lies in one graph and adds its sums with one atomic each.
 __global__ void k_graph_sums(const int32_t *xadj, const int32_t *vwgt, const int32_t *gid, int32_t n,
                              unsigned long long *W, unsigned long long *cmax, int32_t *niso) {
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t q = gid[v];
-        const unsigned long long c = vwgt ? (unsigned long long)vwgt[v] : 1ull;
-        atomicAdd(&W[q], c);
-        atomicMax(&cmax[q], c);
-        if (xadj[v + 1] == xadj[v]) atomicAdd(&niso[q], 1);
+    const int lane = lane_id();
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v - lane < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const bool valid = v < n;
+        const int32_t q = valid ? gid[v] : 0;
+        const unsigned long long c = valid ? (vwgt ? (unsigned long long)vwgt[v] : 1ull) : 0ull;
+        wave_add_keyed(W, q, c, valid);
+        wave_add_keyed(niso, q, 1, valid && xadj[v + 1] == xadj[v]);
+        const uint64_t vm = __ballot(valid);
+        const int32_t q0 = __shfl(q, __ffsll((unsigned long long)vm) - 1, kWave);
+        if (__ballot(valid && q != q0) == 0) {
+            const unsigned long long mx = wave_max(c);
+            if (lane == 0) atomicMax(&cmax[q0], mx);
+        } else if (valid) {
+            atomicMax(&cmax[q], c);
+        }
     }
 }
 
@@ -68,8 +80,9 @@ __global__ void k_coarse_gid(const int32_t *f2c, const int32_t *gid, int32_t n, 
 }
 
 __global__ void k_count_gid(const int32_t *gid, int32_t n, int32_t *cnt) {
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-        atomicAdd(&cnt[gid[v]], 1);
+    const int lane = lane_id();
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v - lane < n; v += (int64_t)gridDim.x * blockDim.x)
+        wave_add_keyed(cnt, v < n ? gid[v] : 0, 1, v < n);
 }
 
 __global__ void k_frozen_of(const int32_t *gid, int32_t n, const uint8_t *active, uint8_t *frozen) {
@@ -92,11 +105,44 @@ __global__ void k_local_parts(const int32_t *gid, const int32_t *kbase, int32_t 
         part[v] -= kbase[gid[v]];
 }
 
-__global__ void k_graph_cuts(const int32_t *rowof, const int32_t *adjncy, const int32_t *adjwgt, const int32_t *part,
-                             const int32_t *gid, int32_t nnz, unsigned long long *cut) {
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t v = rowof[e], u = adjncy[e];
-        if (part[v] != part[u]) atomicAdd(&cut[gid[v]], (unsigned long long)(adjwgt ? adjwgt[e] : 1));
+// Cut weight per graph. The entries of one graph are contiguous, so a wave
+// takes kCutRows x 64 consecutive entries, each lane sums its cut entries of
+// one graph at a time, and the wave adds its sum with one atomic when all of
+// its lanes ended in the same graph (a few hundred counters would otherwise
+// take one atomic per cut entry).
+constexpr int kCutRows = 32;
+__global__ __launch_bounds__(256) void k_graph_cuts(const int32_t *rowof, const int32_t *adjncy, const int32_t *adjwgt,
+                                                    const int32_t *part, const int32_t *gid, int32_t nnz,
+                                                    unsigned long long *cut) {
+    constexpr int64_t kSpan = (int64_t)kCutRows * kWave;
+    const int lane = lane_id();
+    const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
+    for (int64_t base = wid * kSpan; base < nnz; base += nw * kSpan) {
+        int32_t g = -1;
+        unsigned long long acc = 0;
+        for (int r = 0; r < kCutRows; r++) {
+            const int64_t e = base + (int64_t)r * kWave + lane;
+            if (e >= nnz) break;
+            const int32_t v = rowof[e];
+            if (part[v] == part[adjncy[e]]) continue;
+            const int32_t gv = gid[v];
+            if (gv != g) {
+                if (acc) atomicAdd(&cut[g], acc);
+                g = gv;
+                acc = 0;
+            }
+            acc += (unsigned long long)(adjwgt ? adjwgt[e] : 1);
+        }
+        const uint64_t has = __ballot(acc != 0);
+        if (!has) continue;
+        const int32_t g0 = __shfl(g, __ffsll((unsigned long long)has) - 1, kWave);
+        if (__ballot(acc != 0 && g != g0) == 0) {
+            const unsigned long long sum = wave_sum(acc);
+            if (lane == 0) atomicAdd(&cut[g0], sum);
+        } else if (acc) {
+            atomicAdd(&cut[g], acc);
+        }
     }
 }
 
@@ -458,7 +504,7 @@ int partition_batch(const DevGraph &g0, int32_t G, const int32_t *voff_host, con
     GP_TRY(sc.alloc(&dcut, G));
     GP_HIP(hipMemsetAsync(dcut, 0, sizeof(unsigned long long) * G, s));
     if (g0.nnz > 0) {
-        hipLaunchKernelGGL(k_graph_cuts, dim3(grid_for(g0.nnz, 256, 65536)), dim3(256), 0, s, rowof0, g0.adjncy,
+        hipLaunchKernelGGL(k_graph_cuts, dim3(grid_for(g0.nnz, 256 * kCutRows, 8192)), dim3(256), 0, s, rowof0, g0.adjncy,
                            g0.adjwgt, part_out, L0.gid, g0.nnz, dcut);
         GP_LAUNCH_CHECK();
     }

@@ -404,6 +404,24 @@ __device__ __forceinline__ T wave_sum(T x) {
     return x;
 }
 
+// a[key] += x over the lanes with `valid`: one atomic for the wave when all of
+// them share one key (entries grouped by graph or label), else one per lane.
+// Every lane of the wave calls it.
+template <typename T>
+__device__ __forceinline__ void wave_add_keyed(T *a, int32_t key, T x, bool valid) {
+    const uint64_t vm = __ballot(valid);
+    if (!vm) return;
+    const int32_t k0 = __shfl(key, __ffsll((unsigned long long)vm) - 1, kWave);
+    if (__ballot(valid && key != k0) == 0) {
+        T v = valid ? x : T(0);
+#pragma unroll
+        for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+        if (lane_id() == 0) atomicAdd(&a[k0], v);
+    } else if (valid) {
+        atomicAdd(&a[key], x);
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_max(T x) {
 #pragma unroll

@@ -1305,31 +1305,43 @@ __global__ void k_admit(const uint32_t *mk, const int32_t *mv, const int32_t *nm
                         uint8_t *lab8, int32_t *oldlab, LPDev *dev, const int32_t *group, GroupState *gs,
                         uint8_t *act) {
     const int32_t n = *nmov;
+    const int lane = lane_id();
     int32_t cnt = 0;
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p - lane < n;
          p += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t t = (int32_t)mk[p];
-        const int32_t h = headpos[t];
-        const int64_t pre = S[p] - (h > 0 ? S[h - 1] : 0);
-        if (W[t] + pre <= (capv ? capv[t] : U)) {
-            const int32_t v = mv[p];
-            oldlab[p] = labels[v];
-            labels[v] = t;
-            if (lab8) lab8[v] = (uint8_t)t;
-            cnt++;
-            if (group) atomicAdd(&gs[group[v]].moves, 1);
-        } else {
-            oldlab[p] = -1;
-            if (act && act[mv[p]] == 0) act[mv[p]] = 1;  // refused by capacity: evaluated again
+        bool moved = false;
+        int32_t gq = 0;
+        if (p < n) {
+            const int32_t t = (int32_t)mk[p];
+            const int32_t h = headpos[t];
+            const int64_t pre = S[p] - (h > 0 ? S[h - 1] : 0);
+            if (W[t] + pre <= (capv ? capv[t] : U)) {
+                const int32_t v = mv[p];
+                oldlab[p] = labels[v];
+                labels[v] = t;
+                if (lab8) lab8[v] = (uint8_t)t;
+                cnt++;
+                moved = true;
+                if (group) gq = group[v];
+            } else {
+                oldlab[p] = -1;
+                if (act && act[mv[p]] == 0) act[mv[p]] = 1;  // refused by capacity: evaluated again
+            }
+        }
+        // movers sorted by target lie mostly in one graph: one count per wave
+        const uint64_t mm = group ? __ballot(moved) : 0ull;
+        if (mm) {
+            const int32_t g0 = __shfl(gq, __ffsll((unsigned long long)mm) - 1, kWave);
+            if (__ballot(moved && gq != g0) == 0) {
+                if (lane == 0) atomicAdd(&gs[g0].moves, (int32_t)__popcll(mm));
+            } else if (moved) {
+                atomicAdd(&gs[gq].moves, 1);
+            }
         }
     }
     cnt = wave_sum(cnt);
     if (lane_id() == 0 && cnt) atomicAdd(&dev->round_moves, cnt);
 }
-
-// Departures one atomic per mover (distinct labels in general); arrivals one
-// atomic per target: the last admitted mover of a target's segment adds the
-// segment's admitted weight (admitted movers form a prefix of the segment).
 __global__ void k_apply_w(const uint32_t *mk, const int32_t *mv, const int32_t *nmov, const int32_t *oldlab,
                           const int32_t *vwgt, const int32_t *headpos, const int64_t *S, int64_t *W) {
     const int32_t n = *nmov;
@@ -1758,6 +1770,61 @@ __global__ void k_label_weights(const int32_t *labels, const int32_t *vwgt, int3
     }
 }
 
+// Many vertices per label but too many labels for one LDS array (the blocks of
+// a batch of graphs): a workgroup sums a span of consecutive vertices in an
+// LDS hash keyed by label, a wave on one label inserting once, and adds each
+// slot to W at the end; a label that finds no slot in 8 probes goes to W
+// directly.
+constexpr int kLwLog = 11;
+constexpr int kLwSlots = 1 << kLwLog;
+constexpr int kLwSpan = 16384;
+__global__ __launch_bounds__(256) void k_label_weights_hash(const int32_t *labels, const int32_t *vwgt, int32_t n,
+                                                            int64_t *W) {
+    __shared__ int32_t key[kLwSlots];
+    __shared__ unsigned long long val[kLwSlots];
+    const int lane = lane_id();
+    for (int64_t base = (int64_t)blockIdx.x * kLwSpan; base < n; base += (int64_t)gridDim.x * kLwSpan) {
+        for (int i = threadIdx.x; i < kLwSlots; i += blockDim.x) {
+            key[i] = -1;
+            val[i] = 0;
+        }
+        __syncthreads();
+        const int64_t end = min(base + kLwSpan, (int64_t)n);
+        for (int64_t v = base + threadIdx.x; v - lane < end; v += blockDim.x) {
+            const bool valid = v < end;
+            const int32_t L = valid ? labels[v] : -1;
+            bool todo = L >= 0;
+            const uint64_t vm = __ballot(todo);
+            if (!vm) continue;
+            unsigned long long x = todo ? (unsigned long long)vweight(vwgt, (int32_t)v) : 0ull;
+            int32_t Lx = L;
+            const int32_t L0 = __shfl(L, __ffsll((unsigned long long)vm) - 1, kWave);
+            if (__ballot(todo && L != L0) == 0) {
+                x = wave_sum(x);
+                todo = lane == 0;
+                Lx = L0;
+            }
+            if (!todo) continue;
+            uint32_t h = ((uint32_t)Lx * 2654435761u) >> (32 - kLwLog);
+            bool placed = false;
+            for (int probe = 0; probe < 8 && !placed; probe++) {
+                const int32_t k = atomicCAS(&key[h], -1, Lx);
+                if (k == -1 || k == Lx) {
+                    atomicAdd(&val[h], x);
+                    placed = true;
+                } else {
+                    h = (h + 1) & (kLwSlots - 1);
+                }
+            }
+            if (!placed) atomicAdd((unsigned long long *)&W[Lx], x);
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < kLwSlots; i += blockDim.x)
+            if (key[i] >= 0 && val[i]) atomicAdd((unsigned long long *)&W[key[i]], val[i]);
+        __syncthreads();
+    }
+}
+
 // Few labels (k-way partitions): per-block LDS totals, then one global atomic per label and block.
 __global__ __launch_bounds__(256) void k_label_weights_small(const int32_t *labels, const int32_t *vwgt, int32_t n,
                                                              int32_t nl, int64_t *W) {
@@ -1958,6 +2025,9 @@ int label_weights(const DevGraph &g, const int32_t *labels, int64_t *W, int32_t 
         if (nlabels <= kSmallLabels)
             hipLaunchKernelGGL(k_label_weights_small, dim3(grid_for(g.n, 256, 1024)), dim3(256), 0, sc.stream(),
                                labels, g.vwgt, g.n, nlabels, W);
+        else if ((int64_t)nlabels * 4 <= g.n)
+            hipLaunchKernelGGL(k_label_weights_hash, dim3(grid_for(g.n, kLwSpan, 4096)), dim3(256), 0, sc.stream(),
+                               labels, g.vwgt, g.n, W);
         else
             hipLaunchKernelGGL(k_label_weights, dim3(grid_for(g.n, 256, 65536)), dim3(256), 0, sc.stream(), labels,
                                g.vwgt, g.n, W);
