@@ -29,6 +29,12 @@ namespace gp {
 
 namespace {
 
+// per-group round bookkeeping: gs[q] = {moves this round, previous moves, done, rounds_run, rounds seen}
+struct GroupState {
+    int32_t moves, prev, done, rounds_run, seen;
+    int64_t total;
+};
+
 struct LPArgs {
     const int32_t *xadj, *adjncy, *adjwgt, *vwgt;
     const int32_t *labels;
@@ -41,10 +47,17 @@ struct LPArgs {
     const int64_t *capv;   // optional per-label capacity (batched graphs); null: every label has U
     const uint8_t *lab8;   // dense mode (<= 256 labels): byte copy of labels for the neighbour gathers
     const uint8_t *act;    // active-set rounds: evaluations each vertex still owes (0: no proposal); null: all
+    const int32_t *group;  // batched graphs: group of each vertex; null: one graph
+    const GroupState *gs;  // batched graphs: per-group state
 };
 
-// an inactive vertex makes no proposal: its edge range is taken as empty
-__device__ __forceinline__ bool inactive(const LPArgs &a, int32_t v) { return a.act && a.act[v] == 0; }
+// An inactive vertex makes no proposal: its edge range is taken as empty.
+// A group that stopped (two idle rounds) stays idle: its state is a fixed
+// point of the rounds, and its labels and weights are its own, so evaluating
+// its vertices again could only yield proposals refused as before.
+__device__ __forceinline__ bool inactive(const LPArgs &a, int32_t v) {
+    return (a.act && a.act[v] == 0) || (a.group && a.gs[a.group[v]].done);
+}
 
 // Vertices of the degree tiers: tier t is verts[ts[t] .. ts[t+1]), both on the
 // device, so a recorded round can read lists rebuilt every round (active-set
@@ -1287,11 +1300,6 @@ struct StoreIncl {
     __device__ void operator()(int64_t p, int64_t ex, int64_t v) const { S[p] = ex + v; }
 };
 
-// per-group round bookkeeping: gs[q] = {moves this round, previous moves, done, rounds_run, rounds seen}
-struct GroupState {
-    int32_t moves, prev, done, rounds_run, seen;
-    int64_t total;
-};
 
 __global__ void k_heads(const uint32_t *mk, const int32_t *nmov, int32_t *headpos) {
     const int32_t n = *nmov;
@@ -2324,6 +2332,8 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
         a.capv = capv;
         a.lab8 = lab8;
         a.act = act;
+        a.group = group;
+        a.gs = gstate;
         if (act && afirst < n) {
             RT_TRY(compact(ActFlag{verts + afirst, act, &dev->done}, ActEmit{verts, averts, atier, tsh, afirst},
                            n - afirst, nullptr, acount, sc));
