@@ -419,7 +419,11 @@ __global__ __launch_bounds__(kPropBlock) void k_pgroup(LPArgs a, TierList lists,
 }
 
 // One workgroup per vertex, BLOCK threads, packed table of the next power of
-// two >= 2*deg slots (at most TBL).
+// two >= 2*deg slots (at most TBL). The loads are pipelined over the
+// workgroup's vertices: the next vertex's neighbour ids and weights are
+// requested before the current vertex's selection, its neighbour labels
+// during it, so a vertex's memory latency overlaps the previous vertex's
+// reductions and barriers.
 template <int BLOCK, int TBL>
 __global__ __launch_bounds__(BLOCK) void k_pblock(LPArgs a, TierList lists, int tier) {
     if (*a.done) return;
@@ -428,8 +432,7 @@ __global__ __launch_bounds__(BLOCK) void k_pblock(LPArgs a, TierList lists, int 
     const int32_t *__restrict__ verts = lists.verts + t0;
     const int32_t dmode = cur_dirmode(a);
     constexpr int NW = BLOCK / kWave;
-    constexpr int U4 = 4;
-    constexpr int MAXE = U4 * ((TBL / 2 + U4 * BLOCK - 1) / (U4 * BLOCK));
+    constexpr int MAXE = 4 * ((TBL / 2 + 4 * BLOCK - 1) / (4 * BLOCK));  // entries per thread
     __shared__ unsigned long long tbl[TBL];
     __shared__ unsigned long long wbest[NW];
     __shared__ int32_t tc[NW + 1];
@@ -437,53 +440,63 @@ __global__ __launch_bounds__(BLOCK) void k_pblock(LPArgs a, TierList lists, int 
     for (int i = threadIdx.x; i < TBL; i += BLOCK) tbl[i] = kSlotEmpty;
     __syncthreads();
     const int lane = lane_id(), w = threadIdx.x / kWave;
-    // the next vertex's id is loaded with the current vertex's edges, and its
-    // row range and label during the current selection, so each vertex
-    // starts with its edge loads
     int64_t idx = xcd_block(blockIdx.x, gridDim.x);
     int32_t v = idx < count ? verts[idx] : 0;
     int32_t beg = idx < count ? a.xadj[v] : 0, end = idx < count ? a.xadj[v + 1] : 0;
     int32_t own = idx < count ? a.labels[v] : -1;
+    if (idx < count && inactive(a, v)) end = beg;
+    // entry it of this thread is beg + threadIdx.x + it * BLOCK
+    int32_t L[MAXE], wv[MAXE];
+    {
+        int32_t u[MAXE];
+#pragma unroll
+        for (int it = 0; it < MAXE; it++) {
+            const int32_t e = beg + (int32_t)threadIdx.x + it * BLOCK;
+            u[it] = e < end ? a.adjncy[e] : -1;
+            wv[it] = (e < end && a.adjwgt) ? a.adjwgt[e] : 1;
+        }
+#pragma unroll
+        for (int it = 0; it < MAXE; it++) L[it] = u[it] >= 0 ? a.labels[u[it]] : -2;
+    }
     for (; idx < count; idx += gridDim.x) {
         const int64_t nidx = idx + gridDim.x;
         const int32_t nv = nidx < count ? verts[nidx] : 0;
-        if (inactive(a, v)) end = beg;
         int lg = 6;
         while ((1 << lg) < 2 * (end - beg) && (1 << lg) < TBL) lg++;
         const uint32_t cap = 1u << lg;
         int32_t oc = 0;
         unsigned long long mybest = 0;
-        uint32_t touched[MAXE];  // fixed positions (registers): entry it*U4 + j, ~0u when none
+        uint32_t touched[MAXE];  // fixed positions (registers), ~0u when none
 #pragma unroll
-        for (int it = 0; it < MAXE / U4; it++) {
-            const int32_t e0 = beg + (int32_t)threadIdx.x + it * U4 * BLOCK;
-            int32_t u[U4], L[U4], wv[U4];
-#pragma unroll
-            for (int j = 0; j < U4; j++) {
-                const int32_t e = e0 + j * BLOCK;
-                u[j] = e < end ? a.adjncy[e] : -1;
-                wv[j] = (e < end && a.adjwgt) ? a.adjwgt[e] : 1;
+        for (int it = 0; it < MAXE; it++) {
+            touched[it] = ~0u;
+            if (L[it] == -2) continue;  // no entry
+            if (L[it] == own) oc += wv[it];
+            else if (dir_ok(L[it], own, dmode)) {
+                uint32_t sum;
+                touched[it] = slot_add(tbl, cap - 1, lg, L[it], (uint32_t)wv[it], &sum);
+                const unsigned long long pb = pack_best(sum, L[it]);
+                mybest = pb > mybest ? pb : mybest;
             }
+        }
+        // the next vertex: row, label, then its neighbour ids and weights
+        const int32_t nbeg = nidx < count ? a.xadj[nv] : 0;
+        int32_t nend = nidx < count ? a.xadj[nv + 1] : 0;
+        const int32_t nown = nidx < count ? a.labels[nv] : -1;
+        if (nidx < count && inactive(a, nv)) nend = nbeg;
+        int32_t nu[MAXE];
 #pragma unroll
-            for (int j = 0; j < U4; j++) L[j] = u[j] >= 0 ? a.labels[u[j]] : -1;
-#pragma unroll
-            for (int j = 0; j < U4; j++) {
-                touched[it * U4 + j] = ~0u;
-                if (u[j] < 0) continue;
-                if (L[j] == own) oc += wv[j];
-                else if (dir_ok(L[j], own, dmode)) {
-                    uint32_t sum;
-                    touched[it * U4 + j] = slot_add(tbl, cap - 1, lg, L[j], (uint32_t)wv[j], &sum);
-                    const unsigned long long pb = pack_best(sum, L[j]);
-                    mybest = pb > mybest ? pb : mybest;
-                }
-            }
+        for (int it = 0; it < MAXE; it++) {
+            const int32_t e = nbeg + (int32_t)threadIdx.x + it * BLOCK;
+            nu[it] = e < nend ? a.adjncy[e] : -1;
+            wv[it] = (e < nend && a.adjwgt) ? a.adjwgt[e] : 1;  // this vertex's weights are no longer needed
         }
         mybest = group_max_u64<kWave>(mybest);
         if (lane == 0) wbest[w] = mybest;
-        const int32_t nbeg = nidx < count ? a.xadj[nv] : 0, nend = nidx < count ? a.xadj[nv + 1] : 0;
-        const int32_t nown = nidx < count ? a.labels[nv] : -1;
         oc = block_sum<BLOCK>(oc, tc);  // its barriers also publish wbest and the table
+        // the next vertex's neighbour labels are in flight during the selection
+#pragma unroll
+        for (int it = 0; it < MAXE; it++) L[it] = nu[it] >= 0 ? a.labels[nu[it]] : -2;
         unsigned long long best = wbest[0];
         for (int i = 1; i < NW; i++) best = wbest[i] > best ? wbest[i] : best;
         const int32_t bc = (int32_t)(best >> 32);
