@@ -232,15 +232,17 @@ def bench_batch(args, w):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
     # the plain GPU form beside it: one gp_partition per graph, graphs already resident
-    dgs = [gp.to_device(g) for g in b["graphs"]]
-    torch.cuda.synchronize()
-    tp = time.perf_counter()
-    plain_cut = 0
-    for dg, k in zip(dgs, ks):
-        _, r = gp.partition(dg, k, 0.03)
-        plain_cut += r["cut"]
-    torch.cuda.synchronize()
-    plain_ms = (time.perf_counter() - tp) * 1000.0
+    plain_ms, plain_cut = None, None
+    if not args.no_plain_form:
+        dgs = [gp.to_device(g) for g in b["graphs"]]
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        plain_cut = 0
+        for dg, k in zip(dgs, ks):
+            _, r = gp.partition(dg, k, 0.03)
+            plain_cut += r["cut"]
+        torch.cuda.synchronize()
+        plain_ms = (time.perf_counter() - tp) * 1000.0
     ms = dt * 1000.0 / args.steps
     out = {
         "metric": "LP edge-visits/sec + end-to-end k-way partition time; cut & balance vs oracle",
@@ -254,9 +256,14 @@ def bench_batch(args, w):
         "balanced_graphs": sum(r["balanced"] for r in res),
         "plain_form_ms": plain_ms,
         "plain_form_cut_total": plain_cut,
-        "speedup_vs_plain_form": plain_ms / ms,
+        "speedup_vs_plain_form": plain_ms / ms if plain_ms else None,
     }
     print(json.dumps(out), flush=True)
+
+
+# Coarsest-graph sizes of the pairs the committed k = 16 weights were trained on (train_mpnn's default
+# recipe: 20,000 source graphs of master seed 17).
+LEARNED_TRAINING = {"pairs": 20000, "coarsest_n_median": 835, "coarsest_n_max": 3252}
 
 
 def bench_learned(args, w):
@@ -311,6 +318,8 @@ def bench_learned(args, w):
         "cut_geomean_learned_over_plain": geo,
         "proposals_tried": sum(r["tried"] for r in rows),
         "proposals_kept": sum(r["kept"] for r in rows),
+        "envelope": dict(LEARNED_TRAINING, evaluation_coarsest_n=rows[0]["coarsest_n"],
+                         inside_training_sizes=rows[0]["coarsest_n"] <= LEARNED_TRAINING["coarsest_n_max"]),
         "per_seed": rows,
     }
     print(json.dumps(out), flush=True)
@@ -353,6 +362,8 @@ def main():
                     help="ignore paper_1710_08231_amd/tuning/<workload>.json (use the default thresholds)")
     ap.add_argument("--no-profile", action="store_true",
                     help="no HIP events in the timed steps and no instrumented passes (roofline is then null)")
+    ap.add_argument("--no-plain-form", action="store_true",
+                    help="batch512: time the batched call only, not the 512 single calls beside it")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
