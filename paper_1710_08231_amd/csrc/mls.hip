@@ -36,6 +36,7 @@ namespace {
 constexpr int kHT = 128;      // per-search hash of queued vertices (slots; at most 64 keys)
 constexpr int kSW = 4;        // searches (wavefronts) per workgroup
 constexpr int kAB = 1024;     // threads of the single-workgroup kernels
+constexpr int kGG = 8;        // flagged queue entries whose gains one edge pass evaluates together
 
 struct Ctl {
     int32_t ti, ntodo, nsel, tiw;  // todo cursor, todo length, window seeds, todo index after the window
@@ -184,7 +185,8 @@ struct SearchArgs {
 };
 
 struct WaveLds {
-    long long conn[kMlsMaxK];  // connection sums of the vertex being evaluated
+    long long conn[kGG][kMlsMaxK];  // connection sums of the vertices being evaluated
+    int32_t gpre[kGG + 1], gbase[kGG], gslot[kGG];  // a group of evaluations: edge prefix, row start, slot
     long long Bp[kMlsMaxK];    // the search's block weights
     long long key[kMlsMaxQueue];
     int32_t hk[kHT], hs[kHT];  // queued vertex -> slot
@@ -236,6 +238,30 @@ __device__ __forceinline__ void best_pair(long long &bc, int32_t &bl) {
     }
 }
 
+// From a vertex's connection sums: the best adjacent other block with room
+// for it under L_max (ties: lowest block) and the gain of moving there;
+// target -1 when there is none. Clears the sums (wave-uniform call).
+__device__ void select_gain(const SearchArgs &a, long long *conn, const long long *Bp, int32_t own, long long cu,
+                            long long &gain, int32_t &target) {
+    const int lane = lane_id();
+    long long bc = 0;
+    int32_t bl = INT_MAX;
+    for (int32_t b = lane; b < a.k; b += kWave) {
+        const long long cb = conn[b];
+        if (b != own && cb > 0 && Bp[b] + cu <= a.lmax && (cb > bc || (cb == bc && b < bl))) {
+            bc = cb;
+            bl = b;
+        }
+    }
+    best_pair(bc, bl);
+    const long long oc = conn[own];
+    wave_sync();
+    for (int32_t b = lane; b < a.k; b += kWave) conn[b] = 0;
+    wave_sync();
+    target = bl == INT_MAX ? -1 : bl;
+    gain = bc - oc;
+}
+
 // gain and target of the queued vertex in slot su, in the search's view;
 // target -1 when no adjacent other block has room (wave-uniform call)
 __device__ void wave_gain(const SearchArgs &a, WaveLds &L, int32_t su, long long &gain, int32_t &target) {
@@ -245,24 +271,9 @@ __device__ void wave_gain(const SearchArgs &a, WaveLds &L, int32_t su, long long
     const long long cu = vw(a.g, u);
     const int32_t b0 = a.g.xadj[u], b1 = a.g.xadj[u + 1];
     for (int32_t e = b0 + lane; e < b1; e += kWave)
-        atomicAdd((unsigned long long *)&L.conn[label_in(a, L, a.g.adjncy[e])], (unsigned long long)ew(a.g, e));
+        atomicAdd((unsigned long long *)&L.conn[0][label_in(a, L, a.g.adjncy[e])], (unsigned long long)ew(a.g, e));
     wave_sync();
-    long long bc = 0;
-    int32_t bl = INT_MAX;
-    for (int32_t b = lane; b < a.k; b += kWave) {
-        const long long cb = L.conn[b];
-        if (b != own && cb > 0 && L.Bp[b] + cu <= a.lmax && (cb > bc || (cb == bc && b < bl))) {
-            bc = cb;
-            bl = b;
-        }
-    }
-    best_pair(bc, bl);
-    const long long oc = L.conn[own];
-    wave_sync();
-    for (int32_t b = lane; b < a.k; b += kWave) L.conn[b] = 0;
-    wave_sync();
-    target = bl == INT_MAX ? -1 : bl;
-    gain = bc - oc;
+    select_gain(a, L.conn[0], L.Bp, own, cu, gain, target);
 }
 
 // Queues, in list order, the unmarked vertices of list[0, len) (list == null:
@@ -298,24 +309,63 @@ __device__ int32_t scan_list(const SearchArgs &a, WaveLds &L, const int32_t *lis
 
 // Evaluates the flagged slots: re-evaluated queue entries take their new gain
 // (or leave the queue), newly queued vertices enter it if they have a move.
+// Every gain is taken on the same state, so up to kGG of them share one pass
+// over their concatenated edge lists (slot s sits on lane s).
 __device__ void eval_flags(const SearchArgs &a, WaveLds &L, int32_t queued) {
     const int lane = lane_id();
-    for (int32_t s = 0; s < queued; s++) {
-        const int32_t f = L.flag[s];
-        if (!f) continue;
-        long long gn;
-        int32_t t;
-        wave_gain(a, L, s, gn, t);
-        if (lane == 0) {
-            if (t >= 0) {
-                L.key[s] = gn;
-                L.inh[s] = 1;
-            } else if (f == 1) {
-                L.inh[s] = 0;
-            }
-            L.flag[s] = 0;
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
+    uint64_t rem = __ballot(lane < queued && L.flag[lane] != 0);
+    while (rem) {
+        // the next kGG flagged slots, in slot order
+        uint64_t grp = rem;
+        for (int i = 0, c = (int)__popcll(rem); i < c - kGG; i++) grp &= ~(1ull << (63 - __clzll(grp)));
+        rem &= ~grp;
+        const int ng = (int)__popcll(grp);
+        const bool member = (grp >> lane) & 1ull;
+        const int r = (int)__popcll(grp & lt);
+        int32_t d = 0, b0 = 0;
+        if (member) {
+            const int32_t u = L.qv[lane];
+            b0 = a.g.xadj[u];
+            d = a.g.xadj[u + 1] - b0;
+        }
+        int32_t inc = d;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int32_t y = __shfl_up(inc, o, kWave);
+            if (lane >= o) inc += y;
+        }
+        if (member) {
+            L.gpre[r] = inc - d;
+            L.gbase[r] = b0;
+            L.gslot[r] = lane;
+        }
+        const int32_t total = __shfl(inc, kWave - 1, kWave);
+        if (lane == 0) L.gpre[ng] = total;
+        wave_sync();
+        for (int32_t f = lane; f < total; f += kWave) {
+            int q = 0;
+            while (f >= L.gpre[q + 1]) q++;
+            const int32_t e = L.gbase[q] + (f - L.gpre[q]);
+            atomicAdd((unsigned long long *)&L.conn[q][label_in(a, L, a.g.adjncy[e])], (unsigned long long)ew(a.g, e));
         }
         wave_sync();
+        for (int q = 0; q < ng; q++) {
+            const int32_t sl = L.gslot[q];
+            long long gn;
+            int32_t t;
+            select_gain(a, L.conn[q], L.Bp, L.plab[sl], vw(a.g, L.qv[sl]), gn, t);
+            if (lane == 0) {
+                if (t >= 0) {
+                    L.key[sl] = gn;
+                    L.inh[sl] = 1;
+                } else if (L.flag[sl] == 1) {
+                    L.inh[sl] = 0;
+                }
+                L.flag[sl] = 0;
+            }
+            wave_sync();
+        }
     }
 }
 
@@ -328,7 +378,7 @@ __global__ __launch_bounds__(kWave * kSW) void k_search(SearchArgs a) {
     WaveLds &L = lds[w];
     for (int i = lane; i < kHT; i += kWave) L.hk[i] = -1;
     for (int b = lane; b < a.k; b += kWave) {
-        L.conn[b] = 0;
+        for (int q = 0; q < kGG; q++) L.conn[q][b] = 0;
         L.Bp[b] = a.B[b];
     }
     L.inh[lane] = 0;
