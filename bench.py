@@ -162,7 +162,7 @@ def level_tables(calls, kernels):
         f["frac"] = round(f["achieved_gbs"] / HBM_PEAK_GBS, 4)
         f["ms"] = round(f["ms"], 3)
         f["bytes"] = int(f["bytes"])
-    order = {"cluster": 0, "refine": 1}
+    order = {"cluster": 0, "contract": 1, "refine": 2}
     return sorted(rows.values(), key=lambda r: (order.get(r["phase"], 2), r["level"])), fam
 
 

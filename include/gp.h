@@ -458,9 +458,15 @@ int gp_release_cache(void);
  *                       run's algorithmic bytes: per edge visit the neighbour
  *                       id, its weight when present and its label (4 bytes
  *                       clustering, 1 refining), per vertex and round 12
- *                       bytes (+4 with vertex weights), per admitted move 16.
+ *                       bytes (+4 with vertex weights), per admitted move 16;
+ *                       and every contraction, as "contract", with its
+ *                       algorithmic bytes: the fine graph read once (row
+ *                       offsets, labels, neighbour ids, weights), one coarse
+ *                       id gathered per entry, f2c and the coarse graph
+ *                       written.
  *   GP_PROFILE_BY_LEVEL names entries "cluster L<l>|<kernel>",
- *                       "refine L<l>|<kernel>" or "init|<kernel>".
+ *                       "refine L<l>|<kernel>", "contract L<l>|contract" or
+ *                       "init|<kernel>".
  * gp_profile_get copies entry i (0 <= i < gp_profile_count()) into caller
  * memory; name is NUL-terminated and truncated to name_len bytes. Host-only,
  * not thread safe.

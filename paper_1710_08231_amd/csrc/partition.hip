@@ -406,7 +406,18 @@ static double lp_run_bytes(const DevGraph &g, const LPOut &st, bool refine) {
     return (double)st.visits * per_edge + (double)st.rounds_run * g.n * per_vertex + (double)st.moves * 16.0;
 }
 
-// Brackets one LP run of the driver with events when GP_PROFILE_CALLS is on.
+// Algorithmic bytes of one contraction: the fine graph read once (row
+// offsets, labels, neighbour ids, edge and vertex weights when present), the
+// coarse id of every entry's neighbour gathered, f2c written, and the coarse
+// graph written (row offsets, vertex weights, columns and weights).
+static double contract_bytes(const DevGraph &g, const CoarseOut &co) {
+    const double fine = 4.0 * (double)g.n * (3.0 + (g.vwgt ? 1.0 : 0.0)) +
+                        (double)g.nnz * (8.0 + (g.adjwgt ? 4.0 : 0.0));
+    const double coarse = 8.0 * (double)co.n + 8.0 * (double)co.nnz;
+    return fine + coarse;
+}
+
+// Brackets one LP run (or contraction) of the driver with events when GP_PROFILE_CALLS is on.
 struct CallProf {
     hipEvent_t a = nullptr, b = nullptr;
     hipStream_t s;
@@ -484,7 +495,9 @@ static int do_partition(const gp_graph *gin, int32_t k, double eps, const gp_par
         GP_TRY(sc.alloc(&co.vwgt, f.n));
         GP_TRY(sc.alloc(&co.f2c, f.n));
         Timer t_ct(s);
+        CallProf cpc(s, "contract", L);
         GP_TRY(contract(f, labels, skip, co, sc));
+        cpc.done("contract", contract_bytes(f, co));
         if (tracing())
             std::fprintf(stderr, "[gp] level %zu n=%d nnz=%d cluster %.3f ms (%d rounds, %.1f Gvisits/s) "
                                  "contract %.3f ms -> n=%d nnz=%d\n",

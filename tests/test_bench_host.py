@@ -49,18 +49,20 @@ def test_workload_table():
 def test_level_tables_group_by_phase_and_level():
     calls = [{"name": "cluster L0|lp_cluster", "launches": 1, "ms": 2.0, "bytes": 8e9},
              {"name": "cluster L1|lp_cluster", "launches": 1, "ms": 1.0, "bytes": 1e9},
-             {"name": "refine L0|lp_refine", "launches": 1, "ms": 4.0, "bytes": 16e9}]
+             {"name": "refine L0|lp_refine", "launches": 1, "ms": 4.0, "bytes": 16e9},
+             {"name": "contract L0|contract", "launches": 1, "ms": 1.0, "bytes": 2e9}]
     kern = [{"name": "cluster L0|k_a", "launches": 10, "ms": 1.5, "bytes": 6e9},
             {"name": "cluster L0|k_b", "launches": 10, "ms": 0.2, "bytes": 1e9},
             {"name": "refine L0|k_c", "launches": 25, "ms": 3.0, "bytes": 12e9},
             {"name": "init|k_d", "launches": 3, "ms": 0.1, "bytes": 1e6}]
     rows, fam = bench.level_tables(calls, kern)
-    assert [(r["phase"], r["level"]) for r in rows] == [("cluster", 0), ("cluster", 1), ("refine", 0)]
+    assert [(r["phase"], r["level"]) for r in rows] == [("cluster", 0), ("cluster", 1), ("contract", 0),
+                                                        ("refine", 0)]
     # 8 GB in 2 ms = 4000 GB/s = half of the 8 TB/s peak
     assert rows[0]["lp_frac"] == 0.5 and rows[0]["top_kernel"] == "k_a"
     assert rows[0]["top_kernel_frac"] == 0.5 and "top_kernel" not in rows[1]
     assert fam["lp_cluster"]["ms"] == 3.0 and fam["lp_cluster"]["frac"] == round(9e9 / 3e-3 / 1e9 / 8000, 4)
-    assert fam["lp_refine"]["frac"] == 0.5
+    assert fam["lp_refine"]["frac"] == 0.5 and fam["contract"]["frac"] == 0.25
 
 
 def test_default_workload_is_rmat24():

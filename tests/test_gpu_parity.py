@@ -177,6 +177,41 @@ def test_contract_large_rows():
         assert np.array_equal(_np(cg[key]), ocg[key]), key
 
 
+def test_contract_rows_above_2048_entries_weighted():
+    # many coarse rows of 2,049..8,192 entries and above (chunked, pair-sorted class)
+    # beside rows of every other class; then the weighted coarse graph once more
+    g = graphgen.rmat(15, 7)
+    n = len(g["xadj"]) - 1
+    lab = np.array([(v // 256) * 256 if v < 16384 else v for v in range(n)], np.int32)
+    D = np.bincount(lab, weights=np.diff(g["xadj"]), minlength=n)
+    assert ((D > 2048) & (D <= 8192)).sum() >= 10 and (D > 8192).sum() >= 10
+    ocg, of2c = oracle.contract(g, lab)
+    cg, f2c = gp.contract(gp.to_device(g), torch.from_numpy(lab).cuda())
+    assert np.array_equal(_np(f2c), of2c)
+    for key in ("xadj", "adjncy", "adjwgt", "vwgt"):
+        assert np.array_equal(_np(cg[key]), ocg[key]), key
+    nc = len(ocg["xadj"]) - 1
+    lab2 = np.array([(v // 32) * 32 for v in range(nc)], np.int32)
+    D2 = np.bincount(lab2, weights=np.diff(ocg["xadj"]), minlength=nc)
+    assert ((D2 > 2048) & (D2 <= 8192)).sum() >= 5
+    ocg2, of2c2 = oracle.contract(ocg, lab2)
+    cg2, f2c2 = gp.contract(gp.to_device(ocg), torch.from_numpy(lab2).cuda())
+    assert np.array_equal(_np(f2c2), of2c2)
+    for key in ("xadj", "adjncy", "adjwgt", "vwgt"):
+        assert np.array_equal(_np(cg2[key]), ocg2[key]), key
+
+
+def test_contract_weight_overflow_in_large_rows():
+    # coarse rows of 3,000 entries to one column of weight 2^30 each: the sum does not
+    # fit the int32 coarse weight, so the call fails with GP_ERR_OVERFLOW
+    n = 3001
+    g = graphgen.from_edges(n, [(v, 3000) for v in range(3000)], weights=[1 << 30] * 3000)
+    lab = np.arange(n, dtype=np.int32)
+    lab[:3000] = 0
+    with pytest.raises(gp.GPError, match="overflow"):
+        gp.contract(gp.to_device(g), torch.from_numpy(lab).cuda())
+
+
 def test_project_and_cut():
     g = graphgen.rmat(12, 5)
     dg = gp.to_device(g)
