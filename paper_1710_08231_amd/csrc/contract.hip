@@ -14,7 +14,9 @@
 //   tables and only their distinct (row, column) pairs are radix sorted;
 //   a scan of the per-row column counts gives the coarse row offsets and a
 //   copy compacts the rows.
+#include <algorithm>
 #include <climits>
+#include <vector>
 
 #include "contract.hpp"
 #include "prims.hpp"
@@ -400,17 +402,21 @@ __global__ __launch_bounds__(kCB) void k_crow_block(RowCtx c, const int32_t *row
 
 // Rows above the LDS classes: chunks of kRowChunk flattened entries, one
 // workgroup each, sum their entries per column in an LDS hash and append the
-// distinct (row rank, column) pairs through one reservation per chunk; a
-// radix sort then brings equal pairs together and a run reduction merges the
-// chunks of a row.
+// distinct (row, column) pairs through one reservation per chunk; a radix
+// sort then brings equal pairs together and a run reduction merges the chunks
+// of a row. The rows are taken in batches of 2^rbits by rank, rbits + jbits
+// <= 32, so that a pair's key (rank within the batch << jbits | column) fits
+// 32 bits; each batch owns the region of the triple buffers that its chunks'
+// capacity spans, and is sorted and reduced on its own.
 struct BigRows {
     const int32_t *rows;         // [nb] coarse row ids
     const int32_t *chunk_owner;  // [nchunks] row rank of each chunk
     const int32_t *chunk_first;  // [nb] first chunk of each row
-    uint64_t *key;               // [cap] (row rank << jbits) | column
+    uint32_t *key;               // [cap] (row rank within its batch << jbits) | column
     int32_t *val;                // [cap] a chunk's partial sum (a coarse weight must fit int32 anyway)
-    int32_t *cursor;             // [1] append position
-    int jbits;
+    int32_t *cursor;             // [nbatch] append position within each batch's region
+    const int64_t *boff;         // [nbatch] first slot of each batch's region
+    int jbits, rbits;
     int32_t *ovf;                // set when a partial sum exceeds int32
 };
 
@@ -459,8 +465,9 @@ __global__ __launch_bounds__(kCB) void k_cbig_chunk(RowCtx c, BigRows b) {
     int32_t cnt = 0;
     for (int q = threadIdx.x; q < CAP; q += kCB) cnt += skey[q] >= 0;
     cnt = block_sum<kCB>(cnt, t32);
+    const int32_t bt = g >> b.rbits;
     if (threadIdx.x == 0) {
-        resv = cnt ? atomicAdd(b.cursor, cnt) : 0;
+        resv = cnt ? atomicAdd(&b.cursor[bt], cnt) : 0;
         spos = 0;
     }
     __syncthreads();
@@ -476,8 +483,8 @@ __global__ __launch_bounds__(kCB) void k_cbig_chunk(RowCtx c, BigRows b) {
         if (lane == 0 && m) wb = atomicAdd(&spos, (int32_t)__popcll(m));
         wb = __shfl(wb, 0);
         if (occ) {
-            const int32_t pos = resv + wb + (int32_t)__popcll(m & lt);
-            b.key[pos] = ((uint64_t)(uint32_t)g << b.jbits) | (uint64_t)(uint32_t)skey[q];
+            const int64_t pos = b.boff[bt] + resv + wb + (int32_t)__popcll(m & lt);
+            b.key[pos] = ((uint32_t)(g & ((1 << b.rbits) - 1)) << b.jbits) | (uint32_t)skey[q];
             const long long w = sval[q];
             if (w > INT_MAX) atomicOr(b.ovf, 1);  // the row's total would overflow too
             b.val[pos] = (int32_t)(w > INT_MAX ? INT_MAX : w);
@@ -486,7 +493,7 @@ __global__ __launch_bounds__(kCB) void k_cbig_chunk(RowCtx c, BigRows b) {
 }
 
 struct PairHead {
-    const uint64_t *key;
+    const uint32_t *key;
     __device__ bool operator()(int64_t p) const { return p == 0 || key[p] != key[p - 1]; }
 };
 struct PairHeadEmit {
@@ -502,33 +509,36 @@ struct InclOut64 {
     __device__ void operator()(int64_t p, long long ex, long long v) const { S[p] = ex + v; }
 };
 
-// runs are sorted by row rank: roff[g] = first run of rank >= g, for g in [0, nb]
-__global__ void k_cbig_rowoff(const uint64_t *key, const int32_t *head, const int32_t *nruns, int jbits, int32_t nb,
-                              int32_t *roff) {
+// One batch of big rows, its sorted pairs (key, S: inclusive weight prefix)
+// and run heads (positions within the batch's region). Runs are sorted by
+// row rank: roff[g] = first run of the batch's rank >= g, for g in [0, nrows].
+__global__ void k_cbig_rowoff(const uint32_t *key, const int32_t *head, const int32_t *nruns, int jbits,
+                              int32_t nrows, int32_t *roff) {
     const int32_t R = *nruns;
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r <= R; r += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t cur = r < R ? (int64_t)(key[head[r]] >> jbits) : (int64_t)nb;
+        const int64_t cur = r < R ? (int64_t)(key[head[r]] >> jbits) : (int64_t)nrows;
         const int64_t prev = r > 0 ? (int64_t)(key[head[r - 1]] >> jbits) : -1;
         for (int64_t g = prev + 1; g <= cur; g++) roff[g] = (int32_t)r;
     }
 }
 
-__global__ void k_cbig_place(RowCtx c, BigRows b, const int32_t *head, const int32_t *nruns, int32_t m,
-                             const long long *S, const int32_t *roff, int32_t nb) {
-    const int32_t R = *nruns;
-    const uint64_t jm = (uint64_t(1) << b.jbits) - 1;
+__global__ void k_cbig_place(RowCtx c, const int32_t *rows, const uint32_t *key, int jbits, const int32_t *head,
+                             const int32_t *nruns, const int32_t *m_dev, const long long *S, const int32_t *roff,
+                             int32_t nrows) {
+    const int32_t R = *nruns, m = *m_dev;
+    const uint32_t jm = jbits >= 32 ? ~0u : ((1u << jbits) - 1u);
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R; r += (int64_t)gridDim.x * blockDim.x) {
         const int32_t p0 = head[r], p1 = (r + 1 < R) ? head[r + 1] - 1 : m - 1;
-        const uint64_t k = b.key[p0];
-        const int32_t g = (int32_t)(k >> b.jbits);
-        const int32_t i = b.rows[g];
+        const uint32_t k = key[p0];
+        const int32_t g = (int32_t)(k >> jbits);
+        const int32_t i = rows[g];
         const int32_t base = c.flat[c.mstart[i]];
         const int64_t pos = r - roff[g];
         c.tj[base + pos] = (int32_t)(k & jm);
         c.tw[base + pos] = S[p1] - (p0 > 0 ? S[p0 - 1] : 0);
     }
-    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < nb; g += (int64_t)gridDim.x * blockDim.x)
-        c.rcnt[b.rows[g]] = roff[g + 1] - roff[g];
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < nrows; g += (int64_t)gridDim.x * blockDim.x)
+        c.rcnt[rows[g]] = roff[g + 1] - roff[g];
 }
 
 __global__ void k_big_nchunk(RowCtx c, const int32_t *rows, int32_t nb, int32_t *nch) {
@@ -662,7 +672,7 @@ size_t contract_scratch_bound(int64_t n, int64_t nnz) {
     double b = 2 * R(4 * N) + 2 * R(4) + R(8 * N);                          // used, id, counters, c'
     b += R(4 * N) + R(4 * N + 4) + R(4 * N) + 3 * R(4 * N + 4) + R(4);      // counts, starts, members
     b += 2 * R(4 * M) + R(4 * N) + 4 * R(4 * N) + R(12);                     // row buffers, row classes
-    b += 2 * R(4 * N) + 3 * R(4) + R(4 * N + 4);                             // big rows: chunk plan
+    b += 2 * R(4 * N) + R(4) + 3 * R(4 * N) + R(4 * N + 4) + R(8 * N);      // big rows: chunk plan, batches
     b += 2 * R(8 * bcap) + 2 * R(4 * bcap) + R(4 * (M / kRowChunk + N));     // big rows: triples
     b += R(8 * bcap) + R(4 * bcap) + R(4);                                   // runs (sized by capacity)
     const double m = std::max(bcap, std::max(N, 1.0));
@@ -767,58 +777,78 @@ int contract(const DevGraph &g, const int32_t *labels, bool skip_isolated, Coars
             GP_TRY(sc.alloc(&nch, nb));
             GP_TRY(sc.alloc(&cfirst, nb));
             GP_TRY(sc.alloc(&d_tot, 1));
-            GP_TRY(sc.alloc(&cursor, 1));
-            GP_TRY(sc.alloc(&d_runs, 1));
-            GP_TRY(sc.alloc(&roff, (size_t)nb + 1));
             hipLaunchKernelGGL(k_big_nchunk, dim3(grid_for(nb, 256, 1024)), dim3(256), 0, s, c, rows_g, nb, nch);
             GP_LAUNCH_CHECK();
             GP_TRY((scan<int32_t>(LoadIn<int32_t>{nch}, StoreExcl<int32_t>{cfirst}, nb, nullptr, d_tot, sc)));
             int32_t nchunks = 0;
             GP_HIP(hipMemcpyAsync(&nchunks, d_tot, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            std::vector<int32_t> hfirst(nb);
+            GP_HIP(hipMemcpyAsync(hfirst.data(), cfirst, sizeof(int32_t) * (size_t)nb, hipMemcpyDeviceToHost, s));
             GP_HIP(hipStreamSynchronize(s));
             const int64_t bcap = (int64_t)nchunks * kRowChunk;
-            uint64_t *bk = nullptr, *bk2 = nullptr;
+            const int jbits = bits_for(nc - 1) > 0 ? bits_for(nc - 1) : 1;
+            const int gbits = bits_for(nb - 1) > 0 ? bits_for(nb - 1) : 1;
+            const int rbits = std::max(1, std::min(gbits, 32 - jbits));
+            const int32_t rows_per = (int32_t)1 << rbits;
+            const int32_t nbatch = (nb + rows_per - 1) / rows_per;
+            // batch t: ranks [t * rows_per, +rows_per), slots [boff[t], boff[t + 1])
+            std::vector<int64_t> hoff(nbatch + 1);
+            for (int32_t t = 0; t < nbatch; t++) hoff[t] = (int64_t)hfirst[(size_t)t * rows_per] * kRowChunk;
+            hoff[nbatch] = bcap;
+            uint32_t *bk = nullptr, *bk2 = nullptr;
             int32_t *bv = nullptr, *bv2 = nullptr;
             long long *S = nullptr;
+            int64_t *boff = nullptr;
             GP_TRY(sc.alloc(&bk, bcap));
             GP_TRY(sc.alloc(&bk2, bcap));
             GP_TRY(sc.alloc(&bv, bcap));
             GP_TRY(sc.alloc(&bv2, bcap));
-            GP_HIP(hipMemsetAsync(cursor, 0, sizeof(int32_t), s));
-            GP_HIP(hipMemsetAsync(d_runs, 0, sizeof(int32_t), s));
-            const int jbits = bits_for(nc - 1) > 0 ? bits_for(nc - 1) : 1;
-            const int gbits = bits_for(nb - 1) > 0 ? bits_for(nb - 1) : 1;
-            int32_t m = 0;
+            GP_TRY(sc.alloc(&S, bcap));
+            GP_TRY(sc.alloc(&head, bcap));
+            GP_TRY(sc.alloc(&cursor, nbatch));
+            GP_TRY(sc.alloc(&d_runs, nbatch));
+            GP_TRY(sc.alloc(&roff, (size_t)nb + nbatch));
+            GP_TRY(sc.alloc(&boff, nbatch));
+            GP_HIP(hipMemcpyAsync(boff, hoff.data(), sizeof(int64_t) * (size_t)nbatch, hipMemcpyHostToDevice, s));
+            GP_HIP(hipMemsetAsync(cursor, 0, sizeof(int32_t) * (size_t)nbatch, s));
+            GP_HIP(hipMemsetAsync(d_runs, 0, sizeof(int32_t) * (size_t)nbatch, s));
+            std::vector<int32_t> hm(nbatch, 0);
             if (nchunks > 0) {  // rows whose members have no neighbours have no chunks
                 GP_TRY(sc.alloc(&cown, nchunks));
                 hipLaunchKernelGGL(k_expand_owner, dim3(grid_for(nb, 4, 4096)), dim3(256), 0, s, cfirst, nch, nb,
                                    cown);
                 GP_LAUNCH_CHECK();
-                BigRows br{rows_g, cown, cfirst, bk, bv, cursor, jbits, flags};
+                BigRows br{rows_g, cown, cfirst, bk, bv, cursor, boff, jbits, rbits, flags};
                 hipLaunchKernelGGL(k_cbig_chunk, dim3(nchunks), dim3(kCB), 0, s, c, br);
                 GP_LAUNCH_CHECK();
-                GP_HIP(hipMemcpyAsync(&m, cursor, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-                GP_HIP(hipStreamSynchronize(s));
+                GP_HIP(hipMemcpyAsync(hm.data(), cursor, sizeof(int32_t) * (size_t)nbatch, hipMemcpyDeviceToHost, s));
+                GP_HIP(hipStreamSynchronize(s));  // the host vectors outlive every copy queued above
             }
-            if (m > 0) {
-                // sized by the capacity, with the live count on the device: the
-                // number of triples depends on which members share a chunk, and
-                // members are grouped by atomics in no fixed order, so sizing by m
-                // would make the call's scratch vary from run to run (the result
-                // does not: the triples are sorted and summed)
-                GP_TRY((radix_sort<uint64_t, int32_t>(&bk, &bv, &bk2, &bv2, bcap, cursor, jbits + gbits, sc)));
-                GP_TRY(sc.alloc(&S, bcap));
-                GP_TRY(sc.alloc(&head, bcap));
-                GP_TRY((scan<long long>(ValIn64{bv}, InclOut64{S}, bcap, cursor, (long long *)nullptr, sc)));
-                GP_TRY(compact(PairHead{bk}, PairHeadEmit{head}, bcap, cursor, d_runs, sc));
+            for (int32_t t = 0; t < nbatch; t++) {
+                const int64_t o = hoff[t], cap = hoff[t + 1] - o;
+                const int32_t nrows = std::min(rows_per, nb - t * rows_per);
+                const int kbits = jbits + (bits_for(nrows - 1) > 0 ? bits_for(nrows - 1) : 1);
+                uint32_t *k1 = bk + o, *k2 = bk2 + o;
+                int32_t *v1 = bv + o, *v2 = bv2 + o;
+                if (hm[t] > 0) {
+                    // sized by the capacity, with the live count on the device: the
+                    // number of triples depends on which members share a chunk, and
+                    // members are grouped by atomics in no fixed order, so sizing by
+                    // the count would make the call's scratch vary from run to run
+                    // (the result does not: the triples are sorted and summed)
+                    GP_TRY((radix_sort<uint32_t, int32_t>(&k1, &v1, &k2, &v2, cap, cursor + t, kbits, sc)));
+                    GP_TRY((scan<long long>(ValIn64{v1}, InclOut64{S + o}, cap, cursor + t, (long long *)nullptr, sc)));
+                    GP_TRY(compact(PairHead{k1}, PairHeadEmit{head + o}, cap, cursor + t, d_runs + t, sc));
+                }
+                int32_t *ro = roff + (int64_t)t * (rows_per + 1);
+                hipLaunchKernelGGL(k_cbig_rowoff, dim3(grid_for((int64_t)hm[t] + 1, 256, 65536)), dim3(256), 0, s,
+                                   k1, head + o, d_runs + t, jbits, nrows, ro);
+                GP_LAUNCH_CHECK();
+                hipLaunchKernelGGL(k_cbig_place, dim3(grid_for((int64_t)hm[t] + nrows, 256, 65536)), dim3(256), 0, s, c,
+                                   rows_g + (int64_t)t * rows_per, k1, jbits, head + o, d_runs + t, cursor + t, S + o,
+                                   ro, nrows);
+                GP_LAUNCH_CHECK();
             }
-            hipLaunchKernelGGL(k_cbig_rowoff, dim3(grid_for((int64_t)m + 1, 256, 65536)), dim3(256), 0, s, bk, head,
-                               d_runs, jbits, nb, roff);
-            GP_LAUNCH_CHECK();
-            BigRows br{rows_g, cown, cfirst, bk, bv, cursor, jbits, flags};
-            hipLaunchKernelGGL(k_cbig_place, dim3(grid_for((int64_t)m + nb, 256, 65536)), dim3(256), 0, s, c, br,
-                               head, d_runs, m, S, roff, nb);
-            GP_LAUNCH_CHECK();
         }
         // ---- coarse row offsets and the compacted rows
         int32_t *d_nnzc = nullptr;
