@@ -762,6 +762,8 @@ __global__ void k_iso_plan(const int64_t *B, int32_t k, int64_t c, int64_t *MT, 
     }
 }
 
+// UNIT: every isolated vertex weighs 1 (c == 1), so the divisions by c drop out
+template <bool UNIT>
 __global__ void k_iso_uniform(const int32_t *iso, const int32_t *niso, const int64_t *B, int32_t k, int64_t c,
                               const int64_t *MT, const int32_t *perm, int32_t *part) {
     const int32_t m = *niso;
@@ -779,18 +781,18 @@ __global__ void k_iso_uniform(const int32_t *iso, const int32_t *niso, const int
             const int64_t mid = lo + (hi - lo) / 2;
             int64_t f = 0;
             for (int b = 0; b < k; b++)
-                if (B[b] <= mid) f += (mid - B[b]) / c + 1;
+                if (B[b] <= mid) f += (UNIT ? (mid - B[b]) : (mid - B[b]) / c) + 1;
             if (f >= i + 1) hi = mid;
             else lo = mid + 1;
         }
         const int64_t x = lo;
         int64_t below = 0;  // elements < x
         for (int b = 0; b < k; b++)
-            if (B[b] <= x - 1) below += (x - 1 - B[b]) / c + 1;
+            if (B[b] <= x - 1) below += (UNIT ? (x - 1 - B[b]) : (x - 1 - B[b]) / c) + 1;
         int64_t rank = i - below;
         int32_t pick = -1;
         for (int b = 0; b < k; b++) {
-            if (B[b] <= x && (x - B[b]) % c == 0) {
+            if (B[b] <= x && (UNIT || (x - B[b]) % c == 0)) {
                 if (rank == 0) {
                     pick = b;
                     break;
@@ -848,6 +850,7 @@ __global__ void k_iso_serial(const int32_t *iso, const int32_t *niso, const int6
 // Batched placement of vertices without neighbours. The list iso[] is in
 // ascending id, hence grouped by graph; vertex iso[i] belongs to graph
 // q = gid[iso[i]] and is the (i - iso_first[q])-th of its graph.
+template <bool UNIT>
 __global__ void k_iso_uniform_batch(const int32_t *iso, const int32_t *niso, const int32_t *gid,
                                     const int32_t *iso_first, const int32_t *kbase, const int64_t *Ball, int64_t c,
                                     int32_t *part) {
@@ -864,18 +867,18 @@ __global__ void k_iso_uniform_batch(const int32_t *iso, const int32_t *niso, con
             const int64_t mid = lo + (hi - lo) / 2;
             int64_t f = 0;
             for (int b = 0; b < k; b++)
-                if (B[b] <= mid) f += (mid - B[b]) / c + 1;
+                if (B[b] <= mid) f += (UNIT ? (mid - B[b]) : (mid - B[b]) / c) + 1;
             if (f >= r + 1) hi = mid;
             else lo = mid + 1;
         }
         const int64_t x = lo;
         int64_t below = 0;
         for (int b = 0; b < k; b++)
-            if (B[b] <= x - 1) below += (x - 1 - B[b]) / c + 1;
+            if (B[b] <= x - 1) below += (UNIT ? (x - 1 - B[b]) : (x - 1 - B[b]) / c) + 1;
         int64_t rank = r - below;
         int32_t pick = -1;
         for (int b = 0; b < k; b++) {
-            if (B[b] <= x && (x - B[b]) % c == 0) {
+            if (B[b] <= x && (UNIT || (x - B[b]) % c == 0)) {
                 if (rank == 0) {
                     pick = b;
                     break;
@@ -1172,8 +1175,12 @@ int fill_isolated(const DevGraph &g, int32_t k, int32_t *part, const int64_t *B,
         GP_TRY(sc.alloc(&MT, 2));
         GP_TRY(sc.alloc(&perm, k));
         hipLaunchKernelGGL(k_iso_plan, dim3(1), dim3(256), 0, s, B, k, (int64_t)h[0], MT, perm);
-        hipLaunchKernelGGL(k_iso_uniform, dim3(grid_for(niso, 256, 8192)), dim3(256), 0, s, iso, d_niso, B, k,
-                           (int64_t)h[0], MT, perm, part);
+        if (h[0] == 1)
+            hipLaunchKernelGGL(k_iso_uniform<true>, dim3(grid_for(niso, 256, 8192)), dim3(256), 0, s, iso, d_niso, B,
+                               k, (int64_t)1, MT, perm, part);
+        else
+            hipLaunchKernelGGL(k_iso_uniform<false>, dim3(grid_for(niso, 256, 8192)), dim3(256), 0, s, iso, d_niso, B,
+                               k, (int64_t)h[0], MT, perm, part);
         GP_LAUNCH_CHECK();
     } else {
         int64_t *hv = nullptr;
@@ -1212,8 +1219,12 @@ int fill_isolated_batch(const DevGraph &g, const BatchInfo &bi, const int32_t *d
     GP_HIP(hipStreamSynchronize(s));
     if (niso == 0) return GP_OK;
     if (h[0] == h[1]) {
-        hipLaunchKernelGGL(k_iso_uniform_batch, dim3(grid_for(niso, 256, 8192)), dim3(256), 0, s, iso, d_niso,
-                           bi.d_gid, d_iso_first, bi.d_kbase, B, (int64_t)h[0], part);
+        if (h[0] == 1)
+            hipLaunchKernelGGL(k_iso_uniform_batch<true>, dim3(grid_for(niso, 256, 8192)), dim3(256), 0, s, iso,
+                               d_niso, bi.d_gid, d_iso_first, bi.d_kbase, B, (int64_t)1, part);
+        else
+            hipLaunchKernelGGL(k_iso_uniform_batch<false>, dim3(grid_for(niso, 256, 8192)), dim3(256), 0, s, iso,
+                               d_niso, bi.d_gid, d_iso_first, bi.d_kbase, B, (int64_t)h[0], part);
         GP_LAUNCH_CHECK();
     } else {
         int64_t *hv = nullptr;
