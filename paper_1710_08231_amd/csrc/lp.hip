@@ -970,7 +970,10 @@ __global__ void k_hub_expand(const int32_t *first, const int32_t *num, int32_t n
 // Refinement of a k-way partition: labels are block ids < nlabels <= KT, so
 // the per-vertex table is a dense array of KT connection sums (no hashing)
 // and the k label weights of the round start sit in LDS, which lets the
-// capacity test run inside the single selection pass.
+// capacity test run inside the single selection pass. The first two GL-entry
+// chunks of a group's next vertex (ids, weights, then labels) are loaded
+// while the current vertex is selected, so each vertex's chain of dependent
+// loads overlaps the previous vertex's reductions.
 template <int GL, int KT, typename AccT>
 __global__ __launch_bounds__(kPropBlock) void k_dense_group(LPArgs a, int32_t nlabels, TierList lists, int tier) {
     if (*a.done) return;
@@ -993,33 +996,60 @@ __global__ __launch_bounds__(kPropBlock) void k_dense_group(LPArgs a, int32_t nl
     __syncthreads();
     const unsigned b = xcd_block(blockIdx.x, gridDim.x);
     const int64_t stride = (int64_t)gridDim.x * NW * GPW;
-    for (int64_t wb = ((int64_t)b * NW + w) * GPW; wb < count; wb += stride) {
-        const int64_t idx = wb + grp;
-        const bool valid = idx < count;
-        const int32_t v = valid ? verts[idx] : 0;
-        const int32_t beg = valid ? a.xadj[v] : 0;
-        const int32_t end = (valid && !inactive(a, v)) ? a.xadj[v + 1] : beg;
-        const int32_t own = valid ? a.labels[v] : -1;
+    int64_t wb = ((int64_t)b * NW + w) * GPW;
+    // the group's vertex and its first two chunks, loaded one iteration ahead
+    bool valid = wb + grp < count;
+    int32_t v = valid ? verts[wb + grp] : 0;
+    int32_t beg = valid ? a.xadj[v] : 0;
+    int32_t end = (valid && !inactive(a, v)) ? a.xadj[v + 1] : beg;
+    int32_t own = valid ? a.labels[v] : -1;
+    int32_t u0 = beg + gl < end ? a.adjncy[beg + gl] : -1, u1 = beg + gl + GL < end ? a.adjncy[beg + gl + GL] : -1;
+    AccT w0 = (u0 >= 0 && a.adjwgt) ? (AccT)a.adjwgt[beg + gl] : (AccT)1;
+    AccT w1 = (u1 >= 0 && a.adjwgt) ? (AccT)a.adjwgt[beg + gl + GL] : (AccT)1;
+    int32_t L0 = u0 >= 0 ? (int32_t)a.lab8[u0] : -1, L1 = u1 >= 0 ? (int32_t)a.lab8[u1] : -1;
+    for (; wb < count; wb += stride) {
+        const int64_t nwb = wb + stride;
+        const bool nvalid = nwb + grp < count;
+        const int32_t nv = nvalid ? verts[nwb + grp] : 0;
         AccT oc = 0;
         const int nch = (end - beg + GL - 1) / GL;
         const int maxch = wave_max(nch);
-        for (int ch = 0; ch < maxch; ch += 2) {
+        // chunks 0 and 1 from the registers, the rest as they come
+        if (u0 >= 0) {
+            if (L0 == own) oc += w0;
+            else if (dir_ok(L0, own, dmode)) lds_add<AccT>(&val[L0], w0);
+        }
+        if (u1 >= 0) {
+            if (L1 == own) oc += w1;
+            else if (dir_ok(L1, own, dmode)) lds_add<AccT>(&val[L1], w1);
+        }
+        for (int ch = 2; ch < maxch; ch += 2) {
             const int32_t e0 = beg + ch * GL + gl, e1 = e0 + GL;
-            const int32_t u0 = e0 < end ? a.adjncy[e0] : -1, u1 = e1 < end ? a.adjncy[e1] : -1;
-            const AccT w0 = (e0 < end && a.adjwgt) ? (AccT)a.adjwgt[e0] : (AccT)1;
-            const AccT w1 = (e1 < end && a.adjwgt) ? (AccT)a.adjwgt[e1] : (AccT)1;
-            const int32_t L0 = u0 >= 0 ? (int32_t)a.lab8[u0] : -1, L1 = u1 >= 0 ? (int32_t)a.lab8[u1] : -1;
-            if (u0 >= 0) {
-                if (L0 == own) oc += w0;
-                else if (dir_ok(L0, own, dmode)) lds_add<AccT>(&val[L0], w0);
+            const int32_t x0 = e0 < end ? a.adjncy[e0] : -1, x1 = e1 < end ? a.adjncy[e1] : -1;
+            const AccT y0 = (e0 < end && a.adjwgt) ? (AccT)a.adjwgt[e0] : (AccT)1;
+            const AccT y1 = (e1 < end && a.adjwgt) ? (AccT)a.adjwgt[e1] : (AccT)1;
+            const int32_t M0 = x0 >= 0 ? (int32_t)a.lab8[x0] : -1, M1 = x1 >= 0 ? (int32_t)a.lab8[x1] : -1;
+            if (x0 >= 0) {
+                if (M0 == own) oc += y0;
+                else if (dir_ok(M0, own, dmode)) lds_add<AccT>(&val[M0], y0);
             }
-            if (u1 >= 0) {
-                if (L1 == own) oc += w1;
-                else if (dir_ok(L1, own, dmode)) lds_add<AccT>(&val[L1], w1);
+            if (x1 >= 0) {
+                if (M1 == own) oc += y1;
+                else if (dir_ok(M1, own, dmode)) lds_add<AccT>(&val[M1], y1);
             }
         }
+        // the next vertex's row, label and first two chunks
+        const int32_t nbeg = nvalid ? a.xadj[nv] : 0;
+        const int32_t nend = (nvalid && !inactive(a, nv)) ? a.xadj[nv + 1] : nbeg;
+        const int32_t nown = nvalid ? a.labels[nv] : -1;
+        u0 = nbeg + gl < nend ? a.adjncy[nbeg + gl] : -1;
+        u1 = nbeg + gl + GL < nend ? a.adjncy[nbeg + gl + GL] : -1;
+        w0 = (u0 >= 0 && a.adjwgt) ? (AccT)a.adjwgt[nbeg + gl] : (AccT)1;
+        w1 = (u1 >= 0 && a.adjwgt) ? (AccT)a.adjwgt[nbeg + gl + GL] : (AccT)1;
         wave_sync();
         oc = group_sum<GL>(oc);
+        L0 = u0 >= 0 ? (int32_t)a.lab8[u0] : -1;
+        L1 = u1 >= 0 ? (int32_t)a.lab8[u1] : -1;
         const int64_t cv = valid ? vweight(a.vwgt, v) : 0;
         AccT bc = 0;
         int32_t bl = INT_MAX;
@@ -1035,6 +1065,11 @@ __global__ __launch_bounds__(kPropBlock) void k_dense_group(LPArgs a, int32_t nl
         wave_sync();
         for (int i = gl; i < KT; i += GL) val[i] = 0;
         wave_sync();
+        valid = nvalid;
+        v = nv;
+        beg = nbeg;
+        end = nend;
+        own = nown;
     }
 }
 
