@@ -8,6 +8,8 @@
 * The batched form at 512 graphs equals one single-graph call per graph.
 * The network's inference on the R-MAT-24 coarsest graph (k = 16) equals the
   oracle's bit for bit.
+* A contraction whose big rows need more than one batch of 32-bit pair keys
+  equals the oracle's.
 """
 import json
 import os
@@ -142,3 +144,22 @@ def test_rmat24_coarsest_network_inference_full():
     assert np.array_equal(P.cpu().numpy(), Po)
     # the coarsest graph conserves the weight of the vertices with neighbours
     assert int(hg["vwgt"].sum()) == int(np.count_nonzero(np.diff(g["xadj"])))
+
+
+def test_contract_big_rows_in_two_batches():
+    # R-MAT scale 21 with 4,608 groups of 128 vertices and every other vertex alone:
+    # 1,511,936 coarse vertices (21 column bits) and 2,232 rows above 2048 entries
+    # (12 rank bits), so the big rows' pair keys need two 32-bit batches
+    g = graphgen.rmat(21, 21)
+    n = len(g["xadj"]) - 1
+    lab = np.arange(n, dtype=np.int32)
+    grouped = 4608 * 128
+    lab[:grouped] = (np.arange(grouped) // 128) * 128
+    D = np.bincount(lab, weights=np.diff(g["xadj"]), minlength=n)
+    nc, nb = len(np.unique(lab)), int((D > 2048).sum())
+    assert (nc - 1).bit_length() + (nb - 1).bit_length() > 32
+    ocg, of2c = oracle.contract(g, lab)
+    cg, f2c = gp.contract(gp.to_device(g), torch.from_numpy(lab).cuda())
+    assert np.array_equal(f2c.cpu().numpy(), of2c)
+    for key in ("xadj", "adjncy", "adjwgt", "vwgt"):
+        assert np.array_equal(cg[key].cpu().numpy(), ocg[key]), key
