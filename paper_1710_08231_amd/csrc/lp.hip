@@ -311,6 +311,46 @@ __device__ __forceinline__ uint32_t slot_add(unsigned long long *tbl, uint32_t m
     }
 }
 
+// The best label with room for a vertex of weight cv among the table slots
+// first, first + step, ... below cap (ties: lower label). A slot is a
+// candidate when it beats the best found so far; the weights of up to four
+// candidates are requested together, so a lane waits on memory once per four
+// slots, not once per candidate. The result is the maximum over the eligible
+// labels and does not depend on the order of the slots.
+__device__ __forceinline__ void best_with_room(const LPArgs &a, const unsigned long long *tbl, uint32_t first,
+                                               uint32_t step, uint32_t cap, int64_t cv, int32_t &bc2,
+                                               int32_t &bl2) {
+    for (uint32_t i0 = first; i0 < cap; i0 += 4 * step) {
+        int32_t L[4], c[4];
+        int64_t wl[4], cl[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const uint32_t i = i0 + q * step;
+            L[q] = -1;
+            c[q] = 0;
+            if (i < cap) {
+                const unsigned long long sl = tbl[i];
+                if (sl != kSlotEmpty) {
+                    L[q] = (int32_t)(sl >> 32);
+                    c[q] = (int32_t)(uint32_t)sl;
+                    if (!better(c[q], L[q], bc2, bl2)) L[q] = -1;
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            wl[q] = L[q] >= 0 ? a.W[L[q]] : 0;
+            cl[q] = L[q] >= 0 ? capof(a, L[q]) : 0;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+            if (L[q] >= 0 && wl[q] + cv <= cl[q] && better(c[q], L[q], bc2, bl2)) {
+                bc2 = c[q];
+                bl2 = L[q];
+            }
+    }
+}
+
 template <int GL>
 __device__ __forceinline__ unsigned long long group_max_u64(unsigned long long x) {
 #pragma unroll
@@ -508,15 +548,7 @@ __global__ __launch_bounds__(BLOCK) void k_pblock(LPArgs a, TierList lists, int 
                 target = bl;
             } else {
                 int32_t bc2 = 0, bl2 = INT_MAX;
-                for (uint32_t i = threadIdx.x; i < cap; i += BLOCK) {
-                    const unsigned long long sl = tbl[i];
-                    if (sl == kSlotEmpty) continue;
-                    const int32_t Li = (int32_t)(sl >> 32), c = (int32_t)(uint32_t)sl;
-                    if (better(c, Li, bc2, bl2) && a.W[Li] + cv <= capof(a, Li)) {
-                        bc2 = c;
-                        bl2 = Li;
-                    }
-                }
+                best_with_room(a, tbl, threadIdx.x, BLOCK, cap, cv, bc2, bl2);
                 block_best<BLOCK, int32_t>(bc2, bl2, tc, tl);
                 if (bl2 != INT_MAX && bc2 > oc) target = bl2;
             }
@@ -2355,10 +2387,11 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
         GP_LAUNCH_CHECK();
     }
 
-    // One round = one fixed launch sequence; the round index lives on the
-    // device. Round 0 runs eagerly (it also sizes every scratch slot), then
-    // the sequence is captured once as a HIP graph and replayed, which removes
-    // the per-kernel host launch cost from every later round.
+    // One round = one fixed launch sequence; the round index and the stop flag
+    // live on the device, so the host issues every round without reading
+    // anything back. Round 0 also sizes every scratch slot; with
+    // GP_ROUND_GRAPHS=1 the sequence is then captured once as a HIP graph and
+    // replayed for the later rounds.
     auto emit_round = [&](hipStream_t s) -> int {
 #define RT_TRY(expr)             \
     do {                         \
