@@ -159,7 +159,13 @@ def test_contract_big_rows_in_two_batches():
     nc, nb = len(np.unique(lab)), int((D > 2048).sum())
     assert (nc - 1).bit_length() + (nb - 1).bit_length() > 32
     ocg, of2c = oracle.contract(g, lab)
-    cg, f2c = gp.contract(gp.to_device(g), torch.from_numpy(lab).cuda())
+    dg = gp.to_device(g)
+    cg, f2c = gp.contract(dg, torch.from_numpy(lab).cuda())
     assert np.array_equal(f2c.cpu().numpy(), of2c)
     for key in ("xadj", "adjncy", "adjwgt", "vwgt"):
         assert np.array_equal(cg[key].cpu().numpy(), ocg[key]), key
+    # the reported workspace bound covers the batched big-row path
+    b = gp.workspace_bytes(gp.OP_CONTRACT, n, len(g["adjncy"]))
+    ws = torch.empty(b, dtype=torch.uint8, device="cuda")
+    cg2, _ = gp.contract(dg, torch.from_numpy(lab).cuda(), ws=ws)
+    assert np.array_equal(cg2["adjncy"].cpu().numpy(), ocg["adjncy"])

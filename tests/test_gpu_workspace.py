@@ -56,6 +56,24 @@ def test_primitives_with_bounded_workspace(name):
 
 
 @pytest.mark.gpu
+def test_contract_workspace_with_rows_above_2048_entries():
+    import torch
+    import paper_1710_08231_amd as gp
+    g = graphgen.rmat(14, 3)
+    n, nnz = len(g["xadj"]) - 1, len(g["adjncy"])
+    lab = np.array([(v // 64) * 64 if v < 4096 else v for v in range(n)], np.int32)
+    D = np.bincount(lab, weights=np.diff(g["xadj"]), minlength=n)
+    assert (D > 2048).sum() > 0
+    dg = gp.to_device(g)
+    lt = torch.from_numpy(lab).cuda()
+    c0, f0 = gp.contract(dg, lt)
+    c1, f1 = gp.contract(dg, lt, ws=_ws(gp.workspace_bytes(gp.OP_CONTRACT, n, nnz)))
+    assert np.array_equal(f0.cpu().numpy(), f1.cpu().numpy())
+    for key in ("xadj", "adjncy", "adjwgt", "vwgt"):
+        assert np.array_equal(c0[key].cpu().numpy(), c1[key].cpu().numpy()), key
+
+
+@pytest.mark.gpu
 def test_partition_workspace_reported_and_sufficient():
     import paper_1710_08231_amd as gp
     g = graphgen.rmat(15, 3)
