@@ -420,7 +420,8 @@ const char *gp_last_error(void);
  * Execution thresholds of the LP kernels (process-wide; results never depend
  * on them, only speed). tier_max: upper degree bounds of the hashed-table
  * tiers served by 32 lanes, 64 lanes, one workgroup (128 threads up to
- * degree 1024, 256 threads above) and a 1024-thread workgroup (defaults 64,
+ * degree 1024, 256 threads above) and a larger workgroup (512 threads up to
+ * degree 4096, 1024 threads above) (defaults 64,
  * 256, 2048, 8192 — also the largest allowed, as each tier's table holds
  * twice its bound; non-decreasing, tier_max[0] >= 16);
  * vertices above the last bound take the multi-workgroup path. dense_split:

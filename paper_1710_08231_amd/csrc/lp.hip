@@ -1238,7 +1238,7 @@ int launch_dense(const LPArgs &a, int32_t nlabels, const int64_t *tstart, TierLi
         GP_PROF_LAUNCH((std::string("k_dense_group<64") + sfx).c_str(), tb[5], s, hipLaunchKernelGGL((k_dense_group<64, KT, AccT>), dim3(blocks_for(c, NW)), dim3(kPropBlock), 0, s, a, nlabels,
                            tl, 5));
     if (db && db->nbig > 0) {
-        GP_PROF_LAUNCH((std::string("k_dense_chunk<") + std::to_string(KT) + sfx.substr(std::to_string(KT).size() + 2)).c_str(), tb[6] + tb[7] + tb[8] + tb[9], s, hipLaunchKernelGGL((k_dense_chunk<KT, AccT>), dim3(nchunks), dim3(256), 0, s, a, *db));
+        GP_PROF_LAUNCH((std::string("k_dense_chunk<") + std::to_string(KT) + sfx.substr(std::to_string(KT).size() + 2)).c_str(), tb[6] + tb[7] + tb[8] + tb[9] + tb[10], s, hipLaunchKernelGGL((k_dense_chunk<KT, AccT>), dim3(nchunks), dim3(256), 0, s, a, *db));
         hipLaunchKernelGGL((k_dense_finish<KT, AccT>), dim3((db->nbig + 3) / 4), dim3(256), 0, s, a, *db, nlabels);
     }
     GP_LAUNCH_CHECK();
@@ -1281,10 +1281,12 @@ __global__ void k_chunk_desc(const int32_t *xadj, const int32_t *verts, const in
 // ---------------------------------------------------------------- tiers
 
 // Degree tiers. Tier 0: no neighbours (never proposes). Tiers 1..5: GL lanes
-// per vertex. Tiers 6, 7, 8: one workgroup per vertex (128, 256 and 1024
-// threads; the smaller ones fit more workgroups per CU). Tier 9: hub
+// per vertex. Tiers 6..9: one workgroup per vertex (128, 256, 512 and 1024
+// threads; the smaller ones fit more workgroups per CU). Tier 8's 64 KB packed
+// table lets two of its workgroups share a CU, so one waits at a barrier while
+// the other works; tier 9's 128 KB table takes a CU whole. Tier 10: hub
 // (global table).
-constexpr int kTiers = 10;
+constexpr int kTiers = 11;
 
 // Largest degree each hashed-table tier can hold (its table has 2x slots);
 // the tuned bounds may only be lower.
@@ -1298,7 +1300,8 @@ __host__ __device__ inline int32_t tier_cap(int t, bool wide) {
         case 5: return 256;
         case 6: return 1024;
         case 7: return 2048;
-        case 8: return wide ? 4096 : 8192;
+        case 8: return 4096;
+        case 9: return wide ? 4096 : 8192;
         default: return INT_MAX;
     }
 }
@@ -1940,7 +1943,7 @@ struct NoOut64 {
 template <typename AccT>
 int launch_proposals(const LPArgs &a, const int32_t *verts, const int64_t *tstart, TierList tl,
                      const int32_t *hub_log, const int64_t *hub_off, int32_t *gkey, AccT *gval, hipStream_t s,
-                     const double *tb, bool skip_hubs, int32_t t8max) {
+                     const double *tb, bool skip_hubs) {
     const char *acc = sizeof(AccT) == 4 ? "int" : "long";
     auto cnt = [&](int t) { return (int32_t)(tstart[t + 1] - tstart[t]); };
     auto lst = [&](int t) { return verts + tstart[t]; };
@@ -1984,19 +1987,18 @@ int launch_proposals(const LPArgs &a, const int32_t *verts, const int64_t *tstar
                            tl, 7));
     }
     if ((c = cnt(8)) > 0) {
-        constexpr int T8 = sizeof(AccT) == 4 ? 16384 : 8192;
-        // degrees up to 4096 fit a 64 KB packed table: two workgroups per CU
-        if constexpr (sizeof(AccT) == 4) {
-            if (t8max <= 4096)
-                GP_PROF_LAUNCH("k_pblock<1024, 8192, int>", tb[8], s, hipLaunchKernelGGL((k_pblock<1024, 8192>), dim3(grid_for(c, 1, 4096)), dim3(1024), 0, s, a, tl, 8));
-            else
-                GP_PROF_LAUNCH((std::string("k_pblock<1024, ") + std::to_string(T8) + ", " + acc + ">").c_str(), tb[8], s, hipLaunchKernelGGL((k_pblock<1024, T8>), dim3(grid_for(c, 1, 2048)), dim3(1024), 0, s, a,
-                           tl, 8));
-        } else GP_PROF_LAUNCH((std::string("k_propose_block<1024, ") + std::to_string(T8) + ", " + acc + ">").c_str(), tb[8], s, hipLaunchKernelGGL((k_propose_block<1024, T8, AccT>), dim3(grid_for(c, 1, 2048)), dim3(1024), 0, s, a,
+        if constexpr (sizeof(AccT) == 4) GP_PROF_LAUNCH("k_pblock<512, 8192, int>", tb[8], s, hipLaunchKernelGGL((k_pblock<512, 8192>), dim3(grid_for(c, 1, 4096)), dim3(512), 0, s, a, tl, 8));
+        else GP_PROF_LAUNCH((std::string("k_propose_block<1024, 8192, ") + acc + ">").c_str(), tb[8], s, hipLaunchKernelGGL((k_propose_block<1024, 8192, AccT>), dim3(grid_for(c, 1, 2048)), dim3(1024), 0, s, a,
                            tl, 8));
     }
-    if (!skip_hubs && (c = cnt(9)) > 0) {
-        GP_PROF_LAUNCH((std::string("k_propose_hub<1024, ") + acc + ">").c_str(), tb[9], s, hipLaunchKernelGGL((k_propose_hub<1024, AccT>), dim3(c), dim3(1024), 0, s, a, lst(9), c, hub_off,
+    if ((c = cnt(9)) > 0) {  // 64-bit sums: the tier is empty (its cap is tier 8's)
+        if constexpr (sizeof(AccT) == 4) GP_PROF_LAUNCH("k_pblock<1024, 16384, int>", tb[9], s, hipLaunchKernelGGL((k_pblock<1024, 16384>), dim3(grid_for(c, 1, 2048)), dim3(1024), 0, s, a, tl, 9));
+        else GP_PROF_LAUNCH((std::string("k_propose_block<1024, 8192, ") + acc + ">").c_str(), tb[9], s, hipLaunchKernelGGL((k_propose_block<1024, 8192, AccT>), dim3(grid_for(c, 1, 2048)), dim3(1024), 0, s, a,
+                           tl, 9));
+    }
+    constexpr int H = kTiers - 1;
+    if (!skip_hubs && (c = cnt(H)) > 0) {
+        GP_PROF_LAUNCH((std::string("k_propose_hub<1024, ") + acc + ">").c_str(), tb[H], s, hipLaunchKernelGGL((k_propose_hub<1024, AccT>), dim3(c), dim3(1024), 0, s, a, lst(H), c, hub_off,
                            hub_log, gkey, gval));
     }
     GP_LAUNCH_CHECK();
@@ -2031,7 +2033,7 @@ int set_tuning(const Tuning &t) {
     const int32_t *b = t.tier_max;
     const bool ok = b[0] >= tier_cap(3, false) && b[0] <= tier_cap(4, false) && b[1] >= b[0] &&
                     b[1] <= tier_cap(5, false) && b[2] >= b[1] && b[2] <= tier_cap(7, false) && b[3] >= b[2] &&
-                    b[3] <= tier_cap(8, false) && t.dense_split >= 16 && t.dense_split <= (1 << 30) &&
+                    b[3] <= tier_cap(9, false) && t.dense_split >= 16 && t.dense_split <= (1 << 30) &&
                     t.dense_chunk >= 256 && t.dense_chunk <= 65536 && t.dense_chunk % 256 == 0;
     if (!ok) {
         set_error("tuning: tier bounds must be non-decreasing within 16..64, ..256, ..2048, ..8192; dense_split in "
@@ -2064,9 +2066,9 @@ size_t lp_scratch_bound(int64_t n, int64_t nnz, int64_t nlabels, bool active) {
         const int32_t b5 = std::max(std::min(tu.tier_max[1], tier_cap(5, wide)), b4);
         const int32_t b6 = std::max(std::min(tu.tier_max[2], tier_cap(6, wide)), b5);
         const int32_t b7 = std::max(std::min(tu.tier_max[2], tier_cap(7, wide)), b6);
-        const int32_t b8 = std::max(std::min(tu.tier_max[3], tier_cap(8, wide)), b7);
+        const int32_t bh = std::max(std::min(tu.tier_max[3], tier_cap(9, wide)), b7);
         if (!dense) {
-            const double nh = (double)std::min<int64_t>(n, nnz / ((int64_t)b8 + 1));
+            const double nh = (double)std::min<int64_t>(n, nnz / ((int64_t)bh + 1));
             const double ttot = 4.0 * nnz;
             if (!wide) {
                 const double nchunks = (double)nnz / kHubChunk + nh, nslices = ttot / kHubSlice + nh,
@@ -2160,9 +2162,10 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
         tk.bound[6] = std::min(tu.tier_max[2], tier_cap(6, wide));
         tk.bound[7] = std::min(tu.tier_max[2], tier_cap(7, wide));
         tk.bound[8] = std::min(tu.tier_max[3], tier_cap(8, wide));
+        tk.bound[9] = std::min(tu.tier_max[3], tier_cap(9, wide));
         if (dense_tiers) {  // dense tables have no degree limit: rows above the split are chunked
             tk.bound[5] = std::max(tk.bound[4], tu.dense_split);
-            tk.bound[6] = tk.bound[7] = tk.bound[8] = tk.bound[5];
+            tk.bound[6] = tk.bound[7] = tk.bound[8] = tk.bound[9] = tk.bound[5];
         }
         for (int t = 1; t < kTiers - 1; t++) tk.bound[t] = std::max(tk.bound[t], tk.bound[t - 1]);
     }
@@ -2427,10 +2430,10 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
             RT_TRY(launch_dense_any<int32_t>(a, nlabels, tstart, tl, &db, dchunks, s, tbytes));
         else if (wide)
             RT_TRY(launch_proposals<int64_t>(a, verts, tstart, tl, hub_log, hub_off, gkey, (int64_t *)gval, s,
-                                             tbytes, false, tk.bound[8]));
+                                             tbytes, false));
         else
             RT_TRY(launch_proposals<int32_t>(a, verts, tstart, tl, hub_log, hub_off, gkey, (int32_t *)gval, s,
-                                             tbytes, split_hubs, tk.bound[8]));
+                                             tbytes, split_hubs));
         if (split_hubs) {
             GP_PROF_LAUNCH("k_hub_insert", tbytes[kTiers - 1], s, hipLaunchKernelGGL(k_hub_insert, dim3(nchunks), dim3(kHubBlock), 0, s, a, hp));
             hipLaunchKernelGGL(k_hub_reduce, dim3(nbuckets), dim3(kRedBlock), 0, s, a, hp);

@@ -58,7 +58,7 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
 // vertex and how big vertices are split; results never depend on them.
 struct Tuning {
     int32_t tier_max[4] = {64, 256, 2048, 8192};  // hashed tables: degree bounds of the 32-lane,
-                                                  // 64-lane, 256-thread and 1024-thread tiers
+                                                  // 64-lane, 256-thread and 512/1024-thread tiers
     int32_t dense_split = 256;                    // dense tables (k <= 256): rows above are chunked
     int32_t dense_chunk = 2048;                   // entries per chunk workgroup
 };

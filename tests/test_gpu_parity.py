@@ -440,8 +440,9 @@ def test_hub_bucket_overflow(dirs):
 
 
 def test_packed_tables_at_every_block_tier_size():
-    # tier bounds of 4096 and 8192 select the 1024-thread workgroups with 8192-
-    # and 16384-slot packed tables; R-MAT-17 has vertices in both degree ranges
+    # degrees 2049-4096 take 512-thread workgroups with 8192-slot packed tables,
+    # 4097-8192 1024-thread ones with 16384 slots (bound 8192) or the hub path
+    # (bound 4096); R-MAT-17 has vertices in both degree ranges
     g = graphgen.rmat(17, 11)
     deg = np.diff(g["xadj"])
     assert np.count_nonzero((deg > 2048) & (deg <= 4096)) > 5 and np.count_nonzero((deg > 4096) & (deg <= 8192)) > 0
