@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <climits>
 #include <cstdlib>
+#include <cstring>
 #include <string>
 
 #include "lp.hpp"
@@ -1213,10 +1214,11 @@ __global__ __launch_bounds__(256) void k_dense_finish(LPArgs a, DenseBig db, int
 
 template <int KT, typename AccT>
 int launch_dense(const LPArgs &a, int32_t nlabels, const int64_t *tstart, TierList tl, const DenseBig *db,
-                 int32_t nchunks, hipStream_t s, const double *tb) {
+                 int32_t nchunks, hipStream_t s, const double *tb, int tg_end) {
     const std::string sfx = std::string(", ") + std::to_string(KT) + ", " + (sizeof(AccT) == 4 ? "int" : "long") + ">";
     // grids are sized by the full tier (an upper bound of the list the kernel reads)
-    auto cnt = [&](int t) { return (int32_t)(tstart[t + 1] - tstart[t]); };
+    // tiers from tg_end on read connection rows instead
+    auto cnt = [&](int t) { return t < tg_end ? (int32_t)(tstart[t + 1] - tstart[t]) : 0; };
     constexpr int NW = kPropBlock / kWave;
     constexpr int G1 = KT >= 256 ? 16 : 4;
     constexpr int G2 = KT >= 256 ? 16 : 8;
@@ -1247,11 +1249,269 @@ int launch_dense(const LPArgs &a, int32_t nlabels, const int64_t *tstart, TierLi
 
 template <typename AccT>
 int launch_dense_any(const LPArgs &a, int32_t nlabels, const int64_t *tstart, TierList tl, const DenseBig *db,
-                     int32_t nchunks, hipStream_t s, const double *tb) {
-    if (nlabels <= 16) return launch_dense<16, AccT>(a, nlabels, tstart, tl, db, nchunks, s, tb);
-    if (nlabels <= 64) return launch_dense<64, AccT>(a, nlabels, tstart, tl, db, nchunks, s, tb);
-    return launch_dense<256, AccT>(a, nlabels, tstart, tl, db, nchunks, s, tb);
+                     int32_t nchunks, hipStream_t s, const double *tb, int tg_end) {
+    if (nlabels <= 16) return launch_dense<16, AccT>(a, nlabels, tstart, tl, db, nchunks, s, tb, tg_end);
+    if (nlabels <= 64) return launch_dense<64, AccT>(a, nlabels, tstart, tl, db, nchunks, s, tb, tg_end);
+    return launch_dense<256, AccT>(a, nlabels, tstart, tl, db, nchunks, s, tb, tg_end);
 }
+
+// ---------------------------------------------------------------- connection rows (refinement)
+//
+// Refinement rounds move few vertices (well under one percent of them per
+// round on large graphs), yet a plain round gathers the neighbour labels of
+// every vertex again. For the vertices above KT/4 neighbours the sums are
+// therefore kept from round to round: row r holds the KT connection sums of
+// table vertex r (own block included, no direction filter), filled once from
+// the labels of the first round's start and afterwards changed only by the
+// admitted moves. A vertex u moved from block a to block b takes the weight of
+// each edge (u, v) off row(v)[a] and adds it to row(v)[b]; the edge lists are
+// symmetric (§II-A), so the weight is found in u's own list. A round's
+// proposal for a table vertex then reads KT sums instead of deg label gathers.
+// The sums are integers: after every round the rows equal a recomputation
+// from the labels, so the proposals are those of the plain rounds.
+
+// Rows of table vertices 0 .. count-1 (tverts) from the labels: one wave per
+// vertex, a KT-sum LDS table per wave, written out whole.
+template <int KT, typename AccT>
+__global__ __launch_bounds__(256) void k_rows_fill(const int32_t *__restrict__ xadj, const int32_t *__restrict__ adjncy,
+                                                   const int32_t *__restrict__ adjwgt, const uint8_t *__restrict__ lab8,
+                                                   const int32_t *__restrict__ tverts, int32_t count, AccT *rows) {
+    constexpr int NW = 256 / kWave;
+    __shared__ AccT sval[NW][KT + 1];
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    AccT *val = sval[w];
+    for (int i = lane; i < KT; i += kWave) val[i] = 0;
+    wave_sync();
+    for (int64_t j = (int64_t)blockIdx.x * NW + w; j < count; j += (int64_t)gridDim.x * NW) {
+        const int32_t v = tverts[j];
+        const int32_t beg = xadj[v], end = xadj[v + 1];
+        for (int32_t e = beg + lane; e < end; e += kWave)
+            lds_add<AccT>(&val[lab8[adjncy[e]]], adjwgt ? (AccT)adjwgt[e] : (AccT)1);
+        wave_sync();
+        AccT *row = rows + j * KT;
+        for (int i = lane; i < KT; i += kWave) {
+            row[i] = val[i];
+            val[i] = 0;
+        }
+        wave_sync();
+    }
+}
+
+// Rows of the chunked big vertices: chunk (vertex, first entry, end entry, b)
+// adds its sums into row rowbase + b, which starts at zero.
+template <int KT, typename AccT>
+__global__ __launch_bounds__(256) void k_rows_fill_chunk(const int32_t *__restrict__ adjncy,
+                                                         const int32_t *__restrict__ adjwgt,
+                                                         const uint8_t *__restrict__ lab8, const int4 *desc,
+                                                         int32_t rowbase, AccT *rows) {
+    constexpr int NW = 256 / kWave;
+    constexpr int SUB = KT <= 64 ? 8 : 2;
+    __shared__ AccT val[NW * SUB][KT + 1];
+    const int w = (threadIdx.x / kWave) * SUB + lane_id() / (kWave / SUB);
+    for (int i = threadIdx.x; i < NW * SUB * (KT + 1); i += 256) (&val[0][0])[i] = 0;
+    __syncthreads();
+    const int4 d = desc[blockIdx.x];
+    constexpr int UC = 4;
+    for (int32_t e0 = d.y + threadIdx.x; e0 < d.z; e0 += UC * 256) {
+        int32_t u[UC];
+        AccT wv[UC];
+#pragma unroll
+        for (int q = 0; q < UC; q++) {
+            const int32_t e = e0 + q * 256;
+            u[q] = e < d.z ? adjncy[e] : -1;
+            wv[q] = (e < d.z && adjwgt) ? (AccT)adjwgt[e] : (AccT)1;
+        }
+#pragma unroll
+        for (int q = 0; q < UC; q++)
+            if (u[q] >= 0) lds_add<AccT>(&val[w][lab8[u[q]]], wv[q]);
+    }
+    __syncthreads();
+    AccT *row = rows + (int64_t)(rowbase + d.w) * KT;
+    constexpr int P = 256 / KT, NT = NW * SUB;
+    const int lab = threadIdx.x / P, part = threadIdx.x % P;
+    AccT c = 0;
+    for (int q = part; q < NT; q += P) c += val[q][lab];
+    c = group_sum<P>(c);
+    if (part == 0 && c) gadd<AccT>(&row[lab], c);
+}
+
+// A round's proposals of the table vertices (list entries ts[tfirst] ..
+// ts[tend]): min(KT, 64) lanes per vertex read its row, the rule of the other
+// kernels applied to the sums (strongest eligible block other than its own,
+// ties to the smaller id, taken if it beats the own block's sum). Entry j of
+// the full list is row j; the per-round lists of active-set rounds look the
+// row up in rowidx. Also empties the round's queue of big movers.
+template <int KT, typename AccT>
+__global__ __launch_bounds__(kPropBlock) void k_dense_rows(LPArgs a, int32_t nlabels, TierList lists, int tfirst,
+                                                           int tend, const AccT *__restrict__ rows,
+                                                           const int32_t *__restrict__ rowidx, int32_t *nbig) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *nbig = 0;
+    if (*a.done) return;
+    constexpr int GL = KT < kWave ? KT : kWave;
+    constexpr int PER = KT / GL;
+    constexpr int GPW = kWave / GL;
+    constexpr int NW = kPropBlock / kWave;
+    __shared__ int64_t sW[KT];
+    for (int i = threadIdx.x; i < KT; i += kPropBlock) sW[i] = i < nlabels ? a.W[i] - capof(a, i) : (int64_t(1) << 62);
+    __syncthreads();
+    const int64_t t0 = lists.ts[tfirst];
+    const int64_t count = lists.ts[tend] - t0;
+    const int32_t dmode = cur_dirmode(a);
+    const int lane = lane_id(), gl = lane % GL, grp = lane / GL, w = threadIdx.x / kWave;
+    const int64_t stride = (int64_t)gridDim.x * NW * GPW;
+    for (int64_t base = ((int64_t)xcd_block(blockIdx.x, gridDim.x) * NW + w) * GPW; base < count; base += stride) {
+        const int64_t j = base + grp;
+        const bool valid = j < count;
+        const int32_t v = valid ? lists.verts[t0 + j] : 0;
+        const bool live = valid && !inactive(a, v);
+        const int32_t own = live ? a.labels[v] : -1;
+        const int64_t r = live ? (rowidx ? (int64_t)rowidx[v] : j) : 0;
+        AccT c[PER];
+#pragma unroll
+        for (int q = 0; q < PER; q++) c[q] = live ? rows[r * KT + gl + q * GL] : (AccT)0;
+        const int64_t cv = live ? vweight(a.vwgt, v) : 0;
+        AccT oc = 0, bc = 0;
+        int32_t bl = INT_MAX;
+#pragma unroll
+        for (int q = 0; q < PER; q++) {
+            const int32_t i = gl + q * GL;
+            if (i == own) oc = c[q];
+            else if (c[q] > 0 && dir_ok(i, own, dmode) && sW[i] + cv <= 0 && better(c[q], i, bc, bl)) {
+                bc = c[q];
+                bl = i;
+            }
+        }
+        oc = group_sum<GL>(oc);
+        group_best<GL, AccT>(bc, bl);
+        if (valid && gl == 0) a.prop[v] = (live && bl != INT_MAX && bc > oc) ? bl : -1;
+    }
+}
+
+// After the admission: the admitted movers' edges change the rows of their
+// table neighbours. 16 lanes per mover; a mover above kRowSplit neighbours is
+// queued instead as chunks of kRowChunk entries (vertex, first entry, old
+// block, new block), which k_rows_update_big spreads over whole workgroups.
+constexpr int kRowSplit = 256;
+constexpr int kRowChunk = 4096;
+template <typename AccT>
+__device__ __forceinline__ void row_move(AccT *rows, int KT, int32_t r, int32_t from, int32_t to, AccT w) {
+    AccT *row = rows + (int64_t)r * KT;
+    gadd<AccT>(&row[from], (AccT)-w);
+    gadd<AccT>(&row[to], w);
+}
+
+template <int KT, typename AccT>
+__global__ __launch_bounds__(256) void k_rows_update(const uint32_t *mk, const int32_t *mv, const int32_t *oldlab,
+                                                     const int32_t *nmov, const int32_t *__restrict__ xadj,
+                                                     const int32_t *__restrict__ adjncy,
+                                                     const int32_t *__restrict__ adjwgt,
+                                                     const int32_t *__restrict__ rowidx, AccT *rows, int4 *big,
+                                                     int32_t *nbig) {
+    constexpr int GL = 16;
+    const int32_t n = *nmov;
+    const int gl = threadIdx.x % GL;
+    const int64_t step = (int64_t)gridDim.x * blockDim.x / GL;
+    for (int64_t p = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GL; p < n; p += step) {
+        const int32_t from = oldlab[p];
+        if (from < 0) continue;  // refused by the admission
+        const int32_t u = mv[p], to = (int32_t)mk[p];
+        const int32_t e0 = xadj[u], e1 = xadj[u + 1];
+        if (e1 - e0 > kRowSplit) {
+            if (gl == 0) {
+                const int32_t nc = (e1 - e0 + kRowChunk - 1) / kRowChunk;
+                const int32_t at = atomicAdd(nbig, nc);
+                for (int32_t q = 0; q < nc; q++) big[at + q] = make_int4(u, e0 + q * kRowChunk, from, to);
+            }
+            continue;
+        }
+        for (int32_t e = e0 + gl; e < e1; e += GL) {
+            const int32_t r = rowidx[adjncy[e]];
+            if (r >= 0) row_move<AccT>(rows, KT, r, from, to, adjwgt ? (AccT)adjwgt[e] : (AccT)1);
+        }
+    }
+}
+
+template <int KT, typename AccT>
+__global__ __launch_bounds__(256) void k_rows_update_big(const int4 *big, const int32_t *nbig,
+                                                         const int32_t *__restrict__ xadj,
+                                                         const int32_t *__restrict__ adjncy,
+                                                         const int32_t *__restrict__ adjwgt,
+                                                         const int32_t *__restrict__ rowidx, AccT *rows) {
+    const int32_t nb = *nbig;
+    for (int64_t i = blockIdx.x; i < nb; i += gridDim.x) {
+        const int4 c = big[i];
+        const int32_t e1 = min(xadj[c.x + 1], c.y + kRowChunk);
+        for (int32_t e = c.y + threadIdx.x; e < e1; e += 256) {
+            const int32_t r = rowidx[adjncy[e]];
+            if (r >= 0) row_move<AccT>(rows, KT, r, c.z, c.w, adjwgt ? (AccT)adjwgt[e] : (AccT)1);
+        }
+    }
+}
+
+// rowidx[v] = row of table vertex v (list entry first + j holds row j)
+__global__ void k_rows_index(const int32_t *verts, int64_t first, int32_t nt, int32_t *rowidx) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nt; j += (int64_t)gridDim.x * blockDim.x)
+        rowidx[verts[first + j]] = (int32_t)j;
+}
+
+// Connection rows of one LP run (rows == nullptr: plain rounds). Table
+// vertices are the tier-list entries from tier tfirst on; row j belongs to
+// entry tstart[tfirst] + j.
+struct RowTables {
+    void *rows = nullptr;     // [nt * KT] AccT
+    int32_t *rowidx = nullptr;  // [n] row of each vertex, -1 outside the table
+    int4 *big = nullptr;      // the round's chunks of movers above kRowSplit neighbours
+    int32_t *nbig = nullptr;
+    int tfirst = 0;
+    int32_t nt = 0;
+    int32_t nsmall = 0;  // rows filled per vertex; the rest (chunked big vertices) by chunks
+    double sel_bytes = 0;
+};
+
+template <int KT, typename AccT>
+int rows_fill(const RowTables &rt, const int32_t *xadj, const int32_t *adjncy, const int32_t *adjwgt,
+              const uint8_t *lab8, const int32_t *tverts, const DenseBig *db, int32_t nchunks, hipStream_t s) {
+    if (rt.nsmall > 0)
+        hipLaunchKernelGGL((k_rows_fill<KT, AccT>), dim3(grid_for(rt.nsmall, 256 / kWave, 16384)), dim3(256), 0, s,
+                           xadj, adjncy, adjwgt, lab8, tverts, rt.nsmall, (AccT *)rt.rows);
+    if (db && db->nbig > 0 && nchunks > 0)
+        hipLaunchKernelGGL((k_rows_fill_chunk<KT, AccT>), dim3(nchunks), dim3(256), 0, s, adjncy, adjwgt, lab8,
+                           db->desc, rt.nsmall, (AccT *)rt.rows);
+    GP_LAUNCH_CHECK();
+    return GP_OK;
+}
+
+template <int KT, typename AccT>
+int rows_select(const LPArgs &a, int32_t nlabels, TierList tl, const RowTables &rt, int tend, bool active,
+                hipStream_t s) {
+    constexpr int GL = KT < kWave ? KT : kWave;
+    constexpr int per_block = (kPropBlock / kWave) * (kWave / GL);
+    const std::string name = std::string("k_dense_rows<") + std::to_string(KT) + (sizeof(AccT) == 4 ? ", int>" : ", long>");
+    GP_PROF_LAUNCH(name.c_str(), rt.sel_bytes, s, hipLaunchKernelGGL((k_dense_rows<KT, AccT>), dim3(grid_for(rt.nt, per_block, 16384)), dim3(kPropBlock), 0, s, a, nlabels, tl, rt.tfirst, tend, (const AccT *)rt.rows, active ? rt.rowidx : nullptr, rt.nbig));
+    GP_LAUNCH_CHECK();
+    return GP_OK;
+}
+
+template <int KT, typename AccT>
+int rows_update(const RowTables &rt, const uint32_t *mk, const int32_t *mv, const int32_t *oldlab,
+                const int32_t *nmov, const int32_t *xadj, const int32_t *adjncy, const int32_t *adjwgt, int64_t n,
+                int64_t nnz, hipStream_t s) {
+    hipLaunchKernelGGL((k_rows_update<KT, AccT>), dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, mk, mv, oldlab, nmov,
+                       xadj, adjncy, adjwgt, rt.rowidx, (AccT *)rt.rows, rt.big, rt.nbig);
+    hipLaunchKernelGGL((k_rows_update_big<KT, AccT>), dim3(grid_for(nnz / kRowChunk + 1, 1, 4096)), dim3(256), 0, s,
+                       rt.big, rt.nbig, xadj, adjncy, adjwgt, rt.rowidx, (AccT *)rt.rows);
+    GP_LAUNCH_CHECK();
+    return GP_OK;
+}
+
+// GP_REFINE_ROWS=0 runs every refinement round on label gathers; unset or any
+// other value keeps connection rows where they are allowed. Read at every LP run.
+bool use_refine_rows() {
+    const char *e = std::getenv("GP_REFINE_ROWS");
+    return !(e && std::strcmp(e, "0") == 0);
+}
+// largest row storage of one LP run
+constexpr double kRowsMaxBytes = 32.0 * (1 << 30);
 
 __global__ void k_labels_u8(const int32_t *labels, int32_t n, uint8_t *lab8) {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
@@ -2390,6 +2650,52 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
         GP_LAUNCH_CHECK();
     }
 
+    // ---- dense mode: connection rows of the vertices above KT/4 neighbours
+    // (the plain rounds keep gathering for the others). Not for the levels
+    // whose round tail runs in one workgroup, nor in a caller's workspace or
+    // the static scratch, whose bounds are those of the plain rounds.
+    RowTables rt;
+    const int KTd = nlabels <= 16 ? 16 : (nlabels <= 64 ? 64 : 256);
+    if (dense && !fuse_rest && !sc.fixed() && !sc.is_static() && use_refine_rows()) {
+        int tT = 6;
+        for (int t = 1; t < 6; t++)
+            if (tk.bound[t - 1] >= KTd / 4) {
+                tT = t;
+                break;
+            }
+        const int64_t nt = tstart[kTiers] - tstart[tT];
+        const double rb = (double)nt * KTd * (wide ? 8.0 : 4.0);
+        if (nt > 0 && rb <= kRowsMaxBytes) {
+            rt.tfirst = tT;
+            rt.nt = (int32_t)nt;
+            rt.nsmall = (int32_t)(tstart[6] - tstart[tT]);
+            GP_TRY(sc.alloc((char **)&rt.rows, (size_t)rb));
+            GP_TRY(sc.alloc(&rt.rowidx, n));
+            GP_TRY(sc.alloc(&rt.big, (size_t)g.nnz / kRowChunk + (size_t)g.nnz / kRowSplit + 1));
+            GP_TRY(sc.alloc(&rt.nbig, 1));
+            GP_HIP(hipMemsetAsync(rt.rows, 0, (size_t)rb, s));
+            GP_HIP(hipMemsetAsync(rt.rowidx, 0xFF, sizeof(int32_t) * (size_t)n, s));
+            GP_HIP(hipMemsetAsync(rt.nbig, 0, sizeof(int32_t), s));
+            hipLaunchKernelGGL(k_rows_index, dim3(grid_for(nt, 256, 8192)), dim3(256), 0, s, verts, tstart[tT], rt.nt,
+                               rt.rowidx);
+            GP_LAUNCH_CHECK();
+            const int32_t *tv = verts + tstart[tT];
+            const DenseBig *dbp = nbig > 0 ? &db : nullptr;
+            int rc;
+            if (wide)
+                rc = KTd == 16 ? rows_fill<16, int64_t>(rt, g.xadj, g.adjncy, g.adjwgt, lab8, tv, dbp, dchunks, s)
+                   : KTd == 64 ? rows_fill<64, int64_t>(rt, g.xadj, g.adjncy, g.adjwgt, lab8, tv, dbp, dchunks, s)
+                               : rows_fill<256, int64_t>(rt, g.xadj, g.adjncy, g.adjwgt, lab8, tv, dbp, dchunks, s);
+            else
+                rc = KTd == 16 ? rows_fill<16, int32_t>(rt, g.xadj, g.adjncy, g.adjwgt, lab8, tv, dbp, dchunks, s)
+                   : KTd == 64 ? rows_fill<64, int32_t>(rt, g.xadj, g.adjncy, g.adjwgt, lab8, tv, dbp, dchunks, s)
+                               : rows_fill<256, int32_t>(rt, g.xadj, g.adjncy, g.adjwgt, lab8, tv, dbp, dchunks, s);
+            GP_TRY(rc);
+            // per table vertex: its row, list entry, label, proposal and weight
+            rt.sel_bytes = (double)nt * (KTd * (wide ? 8.0 : 4.0) + 12.0 + (g.vwgt ? 4.0 : 0.0));
+        }
+    }
+
     // One round = one fixed launch sequence; the round index and the stop flag
     // live on the device, so the host issues every round without reading
     // anything back. Round 0 also sizes every scratch slot; with
@@ -2424,16 +2730,29 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
             hipLaunchKernelGGL(k_act_bounds, dim3(1), dim3(64), 0, s, atier, acount, ats);
             GP_LAUNCH_CHECK();
         }
+        const int tg_end = rt.rows ? rt.tfirst : kTiers;
+        const DenseBig *dbr = rt.rows ? nullptr : &db;
         if (dense && wide)
-            RT_TRY(launch_dense_any<int64_t>(a, nlabels, tstart, tl, &db, dchunks, s, tbytes));
+            RT_TRY(launch_dense_any<int64_t>(a, nlabels, tstart, tl, dbr, dchunks, s, tbytes, tg_end));
         else if (dense)
-            RT_TRY(launch_dense_any<int32_t>(a, nlabels, tstart, tl, &db, dchunks, s, tbytes));
+            RT_TRY(launch_dense_any<int32_t>(a, nlabels, tstart, tl, dbr, dchunks, s, tbytes, tg_end));
         else if (wide)
             RT_TRY(launch_proposals<int64_t>(a, verts, tstart, tl, hub_log, hub_off, gkey, (int64_t *)gval, s,
                                              tbytes, false));
         else
             RT_TRY(launch_proposals<int32_t>(a, verts, tstart, tl, hub_log, hub_off, gkey, (int32_t *)gval, s,
                                              tbytes, split_hubs));
+        if (rt.rows) {
+            const bool av = act != nullptr;
+            if (wide)
+                RT_TRY((KTd == 16 ? rows_select<16, int64_t>(a, nlabels, tl, rt, kTiers, av, s)
+                       : KTd == 64 ? rows_select<64, int64_t>(a, nlabels, tl, rt, kTiers, av, s)
+                                   : rows_select<256, int64_t>(a, nlabels, tl, rt, kTiers, av, s)));
+            else
+                RT_TRY((KTd == 16 ? rows_select<16, int32_t>(a, nlabels, tl, rt, kTiers, av, s)
+                       : KTd == 64 ? rows_select<64, int32_t>(a, nlabels, tl, rt, kTiers, av, s)
+                                   : rows_select<256, int32_t>(a, nlabels, tl, rt, kTiers, av, s)));
+        }
         if (split_hubs) {
             GP_PROF_LAUNCH("k_hub_insert", tbytes[kTiers - 1], s, hipLaunchKernelGGL(k_hub_insert, dim3(nchunks), dim3(kHubBlock), 0, s, a, hp));
             hipLaunchKernelGGL(k_hub_reduce, dim3(nbuckets), dim3(kRedBlock), 0, s, a, hp);
@@ -2477,6 +2796,16 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
         else
             hipLaunchKernelGGL(k_apply_w, dim3(gb), dim3(256), 0, s, k1, v1, nmov, oldlab, g.vwgt, headpos, S, W);
         GP_LAUNCH_CHECK();
+        if (rt.rows) {
+            if (wide)
+                RT_TRY((KTd == 16 ? rows_update<16, int64_t>(rt, k1, v1, oldlab, nmov, g.xadj, g.adjncy, g.adjwgt, n, g.nnz, s)
+                       : KTd == 64 ? rows_update<64, int64_t>(rt, k1, v1, oldlab, nmov, g.xadj, g.adjncy, g.adjwgt, n, g.nnz, s)
+                                   : rows_update<256, int64_t>(rt, k1, v1, oldlab, nmov, g.xadj, g.adjncy, g.adjwgt, n, g.nnz, s)));
+            else
+                RT_TRY((KTd == 16 ? rows_update<16, int32_t>(rt, k1, v1, oldlab, nmov, g.xadj, g.adjncy, g.adjwgt, n, g.nnz, s)
+                       : KTd == 64 ? rows_update<64, int32_t>(rt, k1, v1, oldlab, nmov, g.xadj, g.adjncy, g.adjwgt, n, g.nnz, s)
+                                   : rows_update<256, int32_t>(rt, k1, v1, oldlab, nmov, g.xadj, g.adjncy, g.adjwgt, n, g.nnz, s)));
+        }
         if (group) hipLaunchKernelGGL(k_round_end_groups, dim3(grid_for(ngroups, 256, 1024)), dim3(256), 0, s, gstate, ngroups);
         hipLaunchKernelGGL(k_round_end, dim3(1), dim3(1), 0, s, dev);
         GP_LAUNCH_CHECK();
