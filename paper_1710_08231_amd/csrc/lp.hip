@@ -1335,22 +1335,43 @@ __global__ __launch_bounds__(256) void k_rows_fill_chunk(const int32_t *__restri
     if (part == 0 && c) gadd<AccT>(&row[lab], c);
 }
 
+// Four consecutive sums of a row in 16-byte loads.
+template <typename AccT>
+__device__ __forceinline__ void load4(const AccT *p, AccT (&c)[4]);
+template <>
+__device__ __forceinline__ void load4<int32_t>(const int32_t *p, int32_t (&c)[4]) {
+    const int4 x = *reinterpret_cast<const int4 *>(p);
+    c[0] = x.x;
+    c[1] = x.y;
+    c[2] = x.z;
+    c[3] = x.w;
+}
+template <>
+__device__ __forceinline__ void load4<int64_t>(const int64_t *p, int64_t (&c)[4]) {
+    const longlong2 x = reinterpret_cast<const longlong2 *>(p)[0], y = reinterpret_cast<const longlong2 *>(p)[1];
+    c[0] = x.x;
+    c[1] = x.y;
+    c[2] = y.x;
+    c[3] = y.y;
+}
+
 // A round's proposals of the table vertices (list entries ts[tfirst] ..
-// ts[tend]): min(KT, 64) lanes per vertex read its row, the rule of the other
-// kernels applied to the sums (strongest eligible block other than its own,
-// ties to the smaller id, taken if it beats the own block's sum). Entry j of
-// the full list is row j; the per-round lists of active-set rounds look the
-// row up in rowidx. Also empties the round's queue of big movers.
+// ts[tend]): KT/4 lanes per vertex read its row, four sums per lane, and the
+// rule of the other kernels is applied to the sums (strongest eligible block
+// other than its own, ties to the smaller id, taken if it beats the own
+// block's sum). Each lane group has UV vertices in flight. Entry j of the full
+// list is row j; the per-round lists of active-set rounds look the row up in
+// rowidx. Also empties the round's queue of big movers.
 template <int KT, typename AccT>
 __global__ __launch_bounds__(kPropBlock) void k_dense_rows(LPArgs a, int32_t nlabels, TierList lists, int tfirst,
                                                            int tend, const AccT *__restrict__ rows,
                                                            const int32_t *__restrict__ rowidx, int32_t *nbig) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *nbig = 0;
     if (*a.done) return;
-    constexpr int GL = KT < kWave ? KT : kWave;
-    constexpr int PER = KT / GL;
+    constexpr int GL = KT / 4;
     constexpr int GPW = kWave / GL;
     constexpr int NW = kPropBlock / kWave;
+    constexpr int UV = 4;
     __shared__ int64_t sW[KT];
     for (int i = threadIdx.x; i < KT; i += kPropBlock) sW[i] = i < nlabels ? a.W[i] - capof(a, i) : (int64_t(1) << 62);
     __syncthreads();
@@ -1359,31 +1380,45 @@ __global__ __launch_bounds__(kPropBlock) void k_dense_rows(LPArgs a, int32_t nla
     const int32_t dmode = cur_dirmode(a);
     const int lane = lane_id(), gl = lane % GL, grp = lane / GL, w = threadIdx.x / kWave;
     const int64_t stride = (int64_t)gridDim.x * NW * GPW;
-    for (int64_t base = ((int64_t)xcd_block(blockIdx.x, gridDim.x) * NW + w) * GPW; base < count; base += stride) {
-        const int64_t j = base + grp;
-        const bool valid = j < count;
-        const int32_t v = valid ? lists.verts[t0 + j] : 0;
-        const bool live = valid && !inactive(a, v);
-        const int32_t own = live ? a.labels[v] : -1;
-        const int64_t r = live ? (rowidx ? (int64_t)rowidx[v] : j) : 0;
-        AccT c[PER];
+    for (int64_t base = ((int64_t)xcd_block(blockIdx.x, gridDim.x) * NW + w) * GPW + grp; base - grp < count;
+         base += UV * stride) {
+        int32_t v[UV], own[UV];
+        bool valid[UV], live[UV];
+        AccT c[UV][4];
 #pragma unroll
-        for (int q = 0; q < PER; q++) c[q] = live ? rows[r * KT + gl + q * GL] : (AccT)0;
-        const int64_t cv = live ? vweight(a.vwgt, v) : 0;
-        AccT oc = 0, bc = 0;
-        int32_t bl = INT_MAX;
-#pragma unroll
-        for (int q = 0; q < PER; q++) {
-            const int32_t i = gl + q * GL;
-            if (i == own) oc = c[q];
-            else if (c[q] > 0 && dir_ok(i, own, dmode) && sW[i] + cv <= 0 && better(c[q], i, bc, bl)) {
-                bc = c[q];
-                bl = i;
-            }
+        for (int u = 0; u < UV; u++) {
+            const int64_t j = base + u * stride;
+            valid[u] = j < count;
+            v[u] = valid[u] ? lists.verts[t0 + j] : 0;
+            if (!rowidx && valid[u]) load4<AccT>(rows + j * KT + 4 * gl, c[u]);
         }
-        oc = group_sum<GL>(oc);
-        group_best<GL, AccT>(bc, bl);
-        if (valid && gl == 0) a.prop[v] = (live && bl != INT_MAX && bc > oc) ? bl : -1;
+#pragma unroll
+        for (int u = 0; u < UV; u++) {
+            live[u] = valid[u] && !inactive(a, v[u]);
+            own[u] = live[u] ? a.labels[v[u]] : -1;
+            if (rowidx && valid[u]) load4<AccT>(rows + (int64_t)rowidx[v[u]] * KT + 4 * gl, c[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < UV; u++) {
+            const int64_t cv = live[u] ? vweight(a.vwgt, v[u]) : 0;
+            AccT oc = 0, bc = 0;
+            int32_t bl = INT_MAX;
+            if (live[u]) {
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    const int32_t i = 4 * gl + q;
+                    const AccT x = c[u][q];
+                    if (i == own[u]) oc = x;
+                    else if (x > 0 && dir_ok(i, own[u], dmode) && sW[i] + cv <= 0 && better(x, i, bc, bl)) {
+                        bc = x;
+                        bl = i;
+                    }
+                }
+            }
+            oc = group_sum<GL>(oc);
+            group_best<GL, AccT>(bc, bl);
+            if (valid[u] && gl == 0) a.prop[v[u]] = (bl != INT_MAX && bc > oc) ? bl : -1;
+        }
     }
 }
 
@@ -1484,8 +1519,7 @@ int rows_fill(const RowTables &rt, const int32_t *xadj, const int32_t *adjncy, c
 template <int KT, typename AccT>
 int rows_select(const LPArgs &a, int32_t nlabels, TierList tl, const RowTables &rt, int tend, bool active,
                 hipStream_t s) {
-    constexpr int GL = KT < kWave ? KT : kWave;
-    constexpr int per_block = (kPropBlock / kWave) * (kWave / GL);
+    constexpr int per_block = (kPropBlock / kWave) * (kWave / (KT / 4)) * 4;
     const std::string name = std::string("k_dense_rows<") + std::to_string(KT) + (sizeof(AccT) == 4 ? ", int>" : ", long>");
     GP_PROF_LAUNCH(name.c_str(), rt.sel_bytes, s, hipLaunchKernelGGL((k_dense_rows<KT, AccT>), dim3(grid_for(rt.nt, per_block, 16384)), dim3(kPropBlock), 0, s, a, nlabels, tl, rt.tfirst, tend, (const AccT *)rt.rows, active ? rt.rowidx : nullptr, rt.nbig));
     GP_LAUNCH_CHECK();
