@@ -150,7 +150,7 @@ static_assert(kRowWaveMax % kWave == 0, "wave rows: whole entries per lane");
 struct RowCtx {
     const int32_t *xadj, *adjncy, *adjwgt, *f2c;
     const int32_t *mstart;   // [nc+1]
-    const int32_t *members;  // [n_incl]
+    const int32_t *mrow;     // [n_incl] first entry (xadj) of each member, grouped by coarse vertex
     const int32_t *flat;     // [n_incl+1] exclusive prefix of member degrees
     int32_t *tj;             // [nnz] sorted columns of row i at flat[mstart[i]]
     long long *tw;           // [nnz] their weights
@@ -182,11 +182,11 @@ __device__ __forceinline__ int32_t upper_pos(const int32_t *F, int32_t lo, int32
 
 // Entries t = first, first + STRIDE, ... (< tend, at most UB of them) of a
 // row. F is the member degree prefix in LDS, relative to the row's first
-// entry, for the members members[mbase + p], p in [0, pmax]. Each entry's
-// chain of dependent loads (member, its row start, neighbour, neighbour's
-// coarse id) is issued as one batch over the UB entries, so a thread waits on
-// memory four times, not four times per entry; the columns other than the
-// row itself then go into the row's LDS hash table.
+// entry, for the members whose rows start at mrow[mbase + p], p in [0, pmax].
+// Each entry's chain of dependent loads (its member's row start, neighbour,
+// neighbour's coarse id) is issued as one batch over the UB entries, so a
+// thread waits on memory three times, not three times per entry; the columns
+// other than the row itself then go into the row's LDS hash table.
 template <int UB, int STRIDE>
 __device__ __forceinline__ void gather_insert(const RowCtx &c, const int32_t *F, int32_t mbase, int32_t pmax,
                                               int32_t first, int32_t tend, int32_t i, int32_t *skey,
@@ -198,13 +198,13 @@ __device__ __forceinline__ void gather_insert(const RowCtx &c, const int32_t *F,
         const int32_t t = first + q * STRIDE;
         if (t < tend) {
             p = upper_pos(F, p, pmax, t);  // t grows: search from the last member
-            x[q] = c.members[mbase + p];
+            x[q] = c.mrow[mbase + p];
             off[q] = t - F[p];
         }
     }
 #pragma unroll
     for (int q = 0; q < UB; q++)
-        if (first + q * STRIDE < tend) x[q] = c.xadj[x[q]] + off[q];  // entry index
+        if (first + q * STRIDE < tend) x[q] += off[q];  // entry index
 #pragma unroll
     for (int q = 0; q < UB; q++)
         if (first + q * STRIDE < tend) {
@@ -455,8 +455,7 @@ __global__ __launch_bounds__(kCB) void k_cbig_chunk(RowCtx c, BigRows b) {
         int32_t p = plo;
         for (int32_t t = t0 + threadIdx.x; t < t1; t += kCB) {
             p = upper_pos(c.flat, p, phi, base + t);  // t grows per thread: search from the last member
-            const int32_t v = c.members[p];
-            const int32_t e = c.xadj[v] + (base + t - c.flat[p]);
+            const int32_t e = c.mrow[p] + (base + t - c.flat[p]);
             const int32_t j = c.f2c[c.adjncy[e]];
             if (j != i) col_insert(skey, sval, CAP - 1, __builtin_ctz(CAP), j, c.adjwgt ? c.adjwgt[e] : 1);
         }
@@ -557,12 +556,12 @@ __global__ void k_row_counts(const int32_t *f2c, const int32_t *xadj, int32_t n,
 }
 
 __global__ void k_members(const int32_t *f2c, const int32_t *xadj, int32_t n, const int32_t *mstart, int32_t *fill,
-                          int32_t *members, int32_t *mdeg) {
+                          int32_t *mrow, int32_t *mdeg) {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         const int32_t i = f2c[v];
         if (i < 0) continue;
         const int32_t p = mstart[i] + atomicAdd(&fill[i], 1);
-        members[p] = (int32_t)v;
+        mrow[p] = xadj[v];
         mdeg[p] = xadj[v + 1] - xadj[v];
     }
 }
@@ -717,12 +716,12 @@ int contract(const DevGraph &g, const int32_t *labels, bool skip_isolated, Coars
     int32_t nnz_c = 0;
     if (nnz > 0 && nc > 0) {
         // ---- members of each coarse vertex and the prefix of their degrees
-        int32_t *cnt = nullptr, *mstart = nullptr, *fill = nullptr, *members = nullptr, *mdeg = nullptr,
+        int32_t *cnt = nullptr, *mstart = nullptr, *fill = nullptr, *mrow = nullptr, *mdeg = nullptr,
                 *flat = nullptr, *d_ni = nullptr;
         GP_TRY(sc.alloc(&cnt, nc));
         GP_TRY(sc.alloc(&mstart, (size_t)nc + 1));
         GP_TRY(sc.alloc(&fill, nc));
-        GP_TRY(sc.alloc(&members, n));
+        GP_TRY(sc.alloc(&mrow, n));
         GP_TRY(sc.alloc(&mdeg, n));
         GP_TRY(sc.alloc(&flat, (size_t)n + 1));
         GP_TRY(sc.alloc(&d_ni, 1));
@@ -731,7 +730,7 @@ int contract(const DevGraph &g, const int32_t *labels, bool skip_isolated, Coars
         hipLaunchKernelGGL(k_row_counts, dim3(gv), dim3(256), 0, s, out.f2c, g.xadj, n, cnt);
         GP_LAUNCH_CHECK();
         GP_TRY((scan<int32_t>(LoadIn<int32_t>{cnt}, StoreExcl<int32_t>{mstart}, nc, nullptr, mstart + nc, sc)));
-        hipLaunchKernelGGL(k_members, dim3(gv), dim3(256), 0, s, out.f2c, g.xadj, n, mstart, fill, members, mdeg);
+        hipLaunchKernelGGL(k_members, dim3(gv), dim3(256), 0, s, out.f2c, g.xadj, n, mstart, fill, mrow, mdeg);
         GP_LAUNCH_CHECK();
         int32_t ni = 0;
         GP_HIP(hipMemcpyAsync(&ni, mstart + nc, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -743,7 +742,7 @@ int contract(const DevGraph &g, const int32_t *labels, bool skip_isolated, Coars
         GP_TRY(sc.alloc(&tj, nnz));
         GP_TRY(sc.alloc(&tw, nnz));
         GP_TRY(sc.alloc(&rcnt, nc));
-        RowCtx c{g.xadj, g.adjncy, g.adjwgt, out.f2c, mstart, members, flat, tj, tw, rcnt};
+        RowCtx c{g.xadj, g.adjncy, g.adjwgt, out.f2c, mstart, mrow, flat, tj, tw, rcnt};
 
         // ---- rows by size class (stable, ascending ids inside a class)
         uint32_t *ck = nullptr, *ck2 = nullptr;
