@@ -1441,16 +1441,18 @@ __global__ __launch_bounds__(256) void k_rows_update(const uint32_t *mk, const i
                                                      const int32_t *__restrict__ adjncy,
                                                      const int32_t *__restrict__ adjwgt,
                                                      const int32_t *__restrict__ rowidx, AccT *rows, int4 *big,
-                                                     int32_t *nbig) {
+                                                     int32_t *nbig, unsigned long long *pushed_total) {
     constexpr int GL = 16;
     const int32_t n = *nmov;
     const int gl = threadIdx.x % GL;
     const int64_t step = (int64_t)gridDim.x * blockDim.x / GL;
+    long long pushed = 0;  // the movers' edges, counted once per mover
     for (int64_t p = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GL; p < n; p += step) {
         const int32_t from = oldlab[p];
         if (from < 0) continue;  // refused by the admission
         const int32_t u = mv[p], to = (int32_t)mk[p];
         const int32_t e0 = xadj[u], e1 = xadj[u + 1];
+        if (gl == 0) pushed += e1 - e0;
         if (e1 - e0 > kRowSplit) {
             if (gl == 0) {
                 const int32_t nc = (e1 - e0 + kRowChunk - 1) / kRowChunk;
@@ -1464,6 +1466,8 @@ __global__ __launch_bounds__(256) void k_rows_update(const uint32_t *mk, const i
             if (r >= 0) row_move<AccT>(rows, KT, r, from, to, adjwgt ? (AccT)adjwgt[e] : (AccT)1);
         }
     }
+    pushed = wave_sum(pushed);
+    if (lane_id() == 0 && pushed) atomicAdd(pushed_total, (unsigned long long)pushed);
 }
 
 template <int KT, typename AccT>
@@ -1500,6 +1504,8 @@ struct RowTables {
     int tfirst = 0;
     int32_t nt = 0;
     int32_t nsmall = 0;  // rows filled per vertex; the rest (chunked big vertices) by chunks
+    int64_t entries = 0;  // edges of the table vertices
+    unsigned long long *pushed = nullptr;  // edges of the admitted movers pushed into rows
     double sel_bytes = 0;
 };
 
@@ -1531,7 +1537,7 @@ int rows_update(const RowTables &rt, const uint32_t *mk, const int32_t *mv, cons
                 const int32_t *nmov, const int32_t *xadj, const int32_t *adjncy, const int32_t *adjwgt, int64_t n,
                 int64_t nnz, hipStream_t s) {
     hipLaunchKernelGGL((k_rows_update<KT, AccT>), dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, mk, mv, oldlab, nmov,
-                       xadj, adjncy, adjwgt, rt.rowidx, (AccT *)rt.rows, rt.big, rt.nbig);
+                       xadj, adjncy, adjwgt, rt.rowidx, (AccT *)rt.rows, rt.big, rt.nbig, rt.pushed);
     hipLaunchKernelGGL((k_rows_update_big<KT, AccT>), dim3(grid_for(nnz / kRowChunk + 1, 1, 4096)), dim3(256), 0, s,
                        rt.big, rt.nbig, xadj, adjncy, adjwgt, rt.rowidx, (AccT *)rt.rows);
     GP_LAUNCH_CHECK();
@@ -2703,10 +2709,13 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
             rt.tfirst = tT;
             rt.nt = (int32_t)nt;
             rt.nsmall = (int32_t)(tstart[6] - tstart[tT]);
+            for (int t = tT; t < kTiers; t++) rt.entries += (int64_t)hedge[t];
             GP_TRY(sc.alloc((char **)&rt.rows, (size_t)rb));
             GP_TRY(sc.alloc(&rt.rowidx, n));
             GP_TRY(sc.alloc(&rt.big, (size_t)g.nnz / kRowChunk + (size_t)g.nnz / kRowSplit + 1));
             GP_TRY(sc.alloc(&rt.nbig, 1));
+            GP_TRY(sc.alloc(&rt.pushed, 1));
+            GP_HIP(hipMemsetAsync(rt.pushed, 0, sizeof(unsigned long long), s));
             GP_HIP(hipMemsetAsync(rt.rows, 0, (size_t)rb, s));
             GP_HIP(hipMemsetAsync(rt.rowidx, 0xFF, sizeof(int32_t) * (size_t)n, s));
             GP_HIP(hipMemsetAsync(rt.nbig, 0, sizeof(int32_t), s));
@@ -2878,13 +2887,20 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
     }
     if (out || prof_on()) {
         LPDev h;
+        unsigned long long pushed = 0;
         GP_HIP(hipMemcpyAsync(&h, dev, sizeof(LPDev), hipMemcpyDeviceToHost, s));
+        if (rt.rows) GP_HIP(hipMemcpyAsync(&pushed, rt.pushed, sizeof(pushed), hipMemcpyDeviceToHost, s));
         GP_HIP(hipStreamSynchronize(s));
         prof_flush();
         if (!out) return GP_OK;
         out->rounds_run = h.rounds_run;
         out->moves = h.total_moves;
         out->visits = act ? h.visits : (int64_t)h.rounds_run * g.nnz;
+        out->row_vertices = rt.rows ? rt.nt : 0;
+        out->row_entries = rt.rows ? rt.entries : 0;
+        out->row_width = rt.rows ? KTd : 0;
+        out->row_sum_bytes = rt.rows ? (wide ? 8 : 4) : 0;
+        out->row_updates = rt.rows ? (int64_t)pushed : 0;
         out->group_rounds.clear();
         out->group_moves.clear();
         if (group) {

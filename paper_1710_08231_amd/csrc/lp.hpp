@@ -29,6 +29,12 @@ struct LPOut {
     int64_t visits = 0;  // edge visits: rounds_run * nnz, or the active vertices' edges
     std::vector<int32_t> group_rounds;  // per group (when groups are given): its own rounds_run
     std::vector<int64_t> group_moves;
+    // connection rows of a refinement run (all zero when every round gathered the labels)
+    int64_t row_vertices = 0;  // vertices with a row
+    int64_t row_entries = 0;   // their edges, gathered once to fill the rows
+    int32_t row_width = 0;     // sums per row
+    int32_t row_sum_bytes = 0;
+    int64_t row_updates = 0;  // edges of the admitted movers pushed into rows
 };
 
 // Runs up to `rounds` synchronous LP rounds on (labels, W) in place.

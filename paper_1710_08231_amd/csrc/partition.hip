@@ -5,6 +5,7 @@
 // of lp.hip, contract.hip and initpart.hip. The host reads back two integers
 // per level (coarse n and nnz) and small tier counts; rounds of LP never
 // synchronise with the host.
+#include <algorithm>
 #include <chrono>
 #include <climits>
 #include <cmath>
@@ -400,10 +401,21 @@ static bool tracing() {
 // runs, which gather a byte copy of the block ids); per vertex and round the
 // row offsets, own label and proposal (12 bytes, +4 with vertex weights); per
 // admitted move 16 bytes (mover record, label write, two weight updates).
+// With connection rows (refinement) a table vertex's edges are gathered once,
+// to fill its row; every round then reads its row (row_width sums), and each
+// admitted mover's edge is pushed into the rows: neighbour id, weight, the
+// neighbour's row index, and the two sums it changes.
 static double lp_run_bytes(const DevGraph &g, const LPOut &st, bool refine) {
     const double per_edge = 4.0 + (g.adjwgt ? 4.0 : 0.0) + (refine ? 1.0 : 4.0);
     const double per_vertex = 12.0 + (g.vwgt ? 4.0 : 0.0);
-    return (double)st.visits * per_edge + (double)st.rounds_run * g.n * per_vertex + (double)st.moves * 16.0;
+    double b = (double)st.rounds_run * g.n * per_vertex + (double)st.moves * 16.0;
+    if (st.row_vertices == 0) return b + (double)st.visits * per_edge;
+    // (active-set rounds count only the evaluated vertices' edges: then a bound)
+    const double gathered = std::max(0.0, (double)st.visits - (double)st.rounds_run * (double)st.row_entries);
+    b += (gathered + (double)st.row_entries) * per_edge;
+    b += (double)st.rounds_run * (double)st.row_vertices * st.row_width * st.row_sum_bytes;
+    b += (double)st.row_updates * (4.0 + (g.adjwgt ? 4.0 : 0.0) + 4.0 + 2.0 * st.row_sum_bytes);
+    return b;
 }
 
 // Algorithmic bytes of one contraction: the fine graph read once (row
