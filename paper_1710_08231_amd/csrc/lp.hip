@@ -1259,7 +1259,7 @@ int launch_dense_any(const LPArgs &a, int32_t nlabels, const int64_t *tstart, Ti
 //
 // Refinement rounds move few vertices (well under one percent of them per
 // round on large graphs), yet a plain round gathers the neighbour labels of
-// every vertex again. For the vertices above KT/4 neighbours the sums are
+// every vertex again. For the vertices above KT/8 neighbours the sums are
 // therefore kept from round to round: row r holds the KT connection sums of
 // table vertex r (own block included, no direction filter), filled once from
 // the labels of the first round's start and afterwards changed only by the
@@ -2690,7 +2690,7 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
         GP_LAUNCH_CHECK();
     }
 
-    // ---- dense mode: connection rows of the vertices above KT/4 neighbours
+    // ---- dense mode: connection rows of the vertices above KT/8 neighbours
     // (the plain rounds keep gathering for the others). Not for the levels
     // whose round tail runs in one workgroup, nor in a caller's workspace or
     // the static scratch, whose bounds are those of the plain rounds.
@@ -2699,7 +2699,7 @@ int lp_run(const DevGraph &g, int32_t *labels, int64_t *W, int32_t nlabels, int6
     if (dense && !fuse_rest && !sc.fixed() && !sc.is_static() && use_refine_rows()) {
         int tT = 6;
         for (int t = 1; t < 6; t++)
-            if (tk.bound[t - 1] >= KTd / 4) {
+            if (tk.bound[t - 1] >= KTd / 8) {
                 tT = t;
                 break;
             }

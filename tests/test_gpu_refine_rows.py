@@ -1,7 +1,7 @@
 """GPU parity of refinement with connection rows.
 
 On levels above 16,384 vertices the refinement keeps, for every vertex above
-KT/4 neighbours (KT = 16, 64 or 256 from k), its k connection sums from round
+KT/8 neighbours (KT = 16, 64 or 256 from k), its k connection sums from round
 to round and changes them only by the admitted moves. The labels, rounds and
 moves must be the oracle's bit for bit, as with the plain rounds
 (GP_REFINE_ROWS=0): every row width, unit and weighted edges, vertex weights,
