@@ -459,6 +459,86 @@ __global__ __launch_bounds__(kPropBlock) void k_pgroup(LPArgs a, TierList lists,
     }
 }
 
+// Tiers of at most E neighbours (4 or 8, E <= GL), 32-bit sums: one entry per
+// lane, so a label's connection is summed over the group's first E lanes by
+// shuffles and no table is written, read or cleared. Each lane offers its own
+// label (lanes of one label offer the same sum), and the rule is that of
+// k_pgroup: the strongest label other than its own, if it beats the own
+// label's sum and has room, else the strongest with room. The next vertex's
+// row and entry are loaded while the current one is selected. (With 16 lanes
+// the shuffles cost more than the table: the tier of up to 16 neighbours keeps
+// k_pgroup.)
+template <int GL, int E>
+__global__ __launch_bounds__(kPropBlock) void k_plane(LPArgs a, TierList lists, int tier) {
+    static_assert(E <= GL, "one entry per lane");
+    if (*a.done) return;
+    const int64_t t0 = lists.ts[tier];
+    const int32_t count = (int32_t)(lists.ts[tier + 1] - t0);
+    const int32_t *__restrict__ verts = lists.verts + t0;
+    const int32_t dmode = cur_dirmode(a);
+    constexpr int GPW = kWave / GL;
+    constexpr int NW = kPropBlock / kWave;
+    const int lane = lane_id(), w = threadIdx.x / kWave;
+    const int gl = lane % GL, grp = lane / GL;
+    const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t stride = (int64_t)gridDim.x * NW * GPW;
+    int64_t wb = ((int64_t)b * NW + w) * GPW;
+    bool valid = wb + grp < count;
+    int32_t v = valid ? verts[wb + grp] : 0;
+    int32_t beg = valid ? a.xadj[v] : 0;
+    int32_t end = (valid && !inactive(a, v)) ? a.xadj[v + 1] : beg;
+    int32_t own = valid ? a.labels[v] : -1;
+    int32_t u = beg + gl < end ? a.adjncy[beg + gl] : -1;
+    int32_t wt = (u >= 0 && a.adjwgt) ? a.adjwgt[beg + gl] : 1;
+    int32_t L = u >= 0 ? a.labels[u] : -1;
+    for (; wb < count; wb += stride) {
+        // the next vertex's row, label and entry
+        const int64_t nwb = wb + stride;
+        const bool nvalid = nwb + grp < count;
+        const int32_t nv = nvalid ? verts[nwb + grp] : 0;
+        const int32_t nbeg = nvalid ? a.xadj[nv] : 0;
+        const int32_t nend = (nvalid && !inactive(a, nv)) ? a.xadj[nv + 1] : nbeg;
+        const int32_t nown = nvalid ? a.labels[nv] : -1;
+        const int32_t nu = nbeg + gl < nend ? a.adjncy[nbeg + gl] : -1;
+        const int32_t nwt = (nu >= 0 && a.adjwgt) ? a.adjwgt[nbeg + gl] : 1;
+        int32_t c = 0;
+#pragma unroll
+        for (int d = 0; d < E; d++) {
+            const int32_t Ld = __shfl(L, d, GL);
+            const int32_t wd = __shfl(wt, d, GL);
+            if (Ld == L) c += wd;
+        }
+        const int32_t oc = group_sum<GL>((L >= 0 && L == own) ? wt : 0);
+        const bool cand = L >= 0 && L != own && dir_ok(L, own, dmode);
+        const unsigned long long best = group_max_u64<GL>(cand ? pack_best((uint32_t)c, L) : 0ull);
+        const int32_t bc = (int32_t)(best >> 32);
+        const int32_t bl = best ? (int32_t)~(uint32_t)best : INT_MAX;
+        const int64_t cv = valid ? vweight(a.vwgt, v) : 0;
+        int32_t target = -1;
+        bool need2 = false;
+        if (valid && bl != INT_MAX && bc > oc) {
+            if (a.W[bl] + cv <= capof(a, bl)) target = bl;
+            else need2 = true;
+        }
+        if (__ballot(need2)) {
+            int32_t bc2 = 0, bl2 = INT_MAX;
+            if (need2 && cand && a.W[L] + cv <= capof(a, L)) {
+                bc2 = c;
+                bl2 = L;
+            }
+            group_best<GL, int32_t>(bc2, bl2);
+            if (need2 && bl2 != INT_MAX && bc2 > oc) target = bl2;
+        }
+        if (valid && gl == 0) a.prop[v] = target;
+        valid = nvalid;
+        v = nv;
+        own = nown;
+        u = nu;
+        wt = nwt;
+        L = nu >= 0 ? a.labels[nu] : -1;
+    }
+}
+
 // One workgroup per vertex, BLOCK threads, packed table of the next power of
 // two >= 2*deg slots (at most TBL). The loads are pipelined over the
 // workgroup's vertices: the next vertex's neighbour ids and weights are
@@ -1106,6 +1186,71 @@ __global__ __launch_bounds__(kPropBlock) void k_dense_group(LPArgs a, int32_t nl
     }
 }
 
+// Dense-table counterpart of k_plane for the tiers of at most E neighbours
+// (4 or 8, E <= GL): one entry per lane, each label's connection summed over
+// the group's first E lanes by shuffles, the k label weights of the round
+// start in LDS, the rule of k_dense_group.
+template <int GL, int E, int KT, typename AccT>
+__global__ __launch_bounds__(kPropBlock) void k_dense_lanes(LPArgs a, int32_t nlabels, TierList lists, int tier) {
+    static_assert(E <= GL, "one entry per lane");
+    if (*a.done) return;
+    const int64_t t0 = lists.ts[tier];
+    const int32_t count = (int32_t)(lists.ts[tier + 1] - t0);
+    const int32_t *__restrict__ verts = lists.verts + t0;
+    const int32_t dmode = cur_dirmode(a);
+    constexpr int GPW = kWave / GL;
+    constexpr int NW = kPropBlock / kWave;
+    __shared__ int64_t sW[KT];
+    for (int i = threadIdx.x; i < KT; i += kPropBlock) sW[i] = i < nlabels ? a.W[i] - capof(a, i) : (int64_t(1) << 62);
+    __syncthreads();
+    const int lane = lane_id(), w = threadIdx.x / kWave;
+    const int gl = lane % GL, grp = lane / GL;
+    const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t stride = (int64_t)gridDim.x * NW * GPW;
+    int64_t wb = ((int64_t)b * NW + w) * GPW;
+    bool valid = wb + grp < count;
+    int32_t v = valid ? verts[wb + grp] : 0;
+    int32_t beg = valid ? a.xadj[v] : 0;
+    int32_t end = (valid && !inactive(a, v)) ? a.xadj[v + 1] : beg;
+    int32_t own = valid ? a.labels[v] : -1;
+    int32_t u = beg + gl < end ? a.adjncy[beg + gl] : -1;
+    AccT wt = (u >= 0 && a.adjwgt) ? (AccT)a.adjwgt[beg + gl] : (AccT)1;
+    int32_t L = u >= 0 ? (int32_t)a.lab8[u] : -1;
+    for (; wb < count; wb += stride) {
+        const int64_t nwb = wb + stride;
+        const bool nvalid = nwb + grp < count;
+        const int32_t nv = nvalid ? verts[nwb + grp] : 0;
+        const int32_t nbeg = nvalid ? a.xadj[nv] : 0;
+        const int32_t nend = (nvalid && !inactive(a, nv)) ? a.xadj[nv + 1] : nbeg;
+        const int32_t nown = nvalid ? a.labels[nv] : -1;
+        const int32_t nu = nbeg + gl < nend ? a.adjncy[nbeg + gl] : -1;
+        const AccT nwt = (nu >= 0 && a.adjwgt) ? (AccT)a.adjwgt[nbeg + gl] : (AccT)1;
+        AccT c = 0;
+#pragma unroll
+        for (int d = 0; d < E; d++) {
+            const int32_t Ld = __shfl(L, d, GL);
+            const AccT wd = __shfl(wt, d, GL);
+            if (Ld == L) c += wd;
+        }
+        const AccT oc = group_sum<GL>((L >= 0 && L == own) ? wt : (AccT)0);
+        const int64_t cv = valid ? vweight(a.vwgt, v) : 0;
+        AccT bc = 0;
+        int32_t bl = INT_MAX;
+        if (L >= 0 && L != own && c > 0 && dir_ok(L, own, dmode) && sW[L] + cv <= 0) {
+            bc = c;
+            bl = L;
+        }
+        group_best<GL, AccT>(bc, bl);
+        if (valid && gl == 0) a.prop[v] = (bl != INT_MAX && bc > oc) ? bl : -1;
+        valid = nvalid;
+        v = nv;
+        own = nown;
+        u = nu;
+        wt = nwt;
+        L = nu >= 0 ? (int32_t)a.lab8[nu] : -1;
+    }
+}
+
 // Vertices above the group tiers in dense mode: edges cut into chunks of
 // kDenseChunk entries, one workgroup per chunk; each chunk adds its k
 // connection sums into the vertex's row of a global [nbig x KT] array, then
@@ -1225,10 +1370,10 @@ int launch_dense(const LPArgs &a, int32_t nlabels, const int64_t *tstart, TierLi
     auto blocks_for = [&](int32_t c, int per_block) { return grid_for(c, per_block, 16384); };
     int32_t c;
     if ((c = cnt(1)) > 0)
-        GP_PROF_LAUNCH((std::string("k_dense_group<") + std::to_string(G1) + sfx).c_str(), tb[1], s, hipLaunchKernelGGL((k_dense_group<G1, KT, AccT>), dim3(blocks_for(c, NW * (kWave / G1))), dim3(kPropBlock), 0,
+        GP_PROF_LAUNCH((std::string("k_dense_lanes<") + std::to_string(G1) + sfx).c_str(), tb[1], s, hipLaunchKernelGGL((k_dense_lanes<G1, 4, KT, AccT>), dim3(blocks_for(c, NW * (kWave / G1))), dim3(kPropBlock), 0,
                            s, a, nlabels, tl, 1));
     if ((c = cnt(2)) > 0)
-        GP_PROF_LAUNCH((std::string("k_dense_group<") + std::to_string(G2) + sfx).c_str(), tb[2], s, hipLaunchKernelGGL((k_dense_group<G2, KT, AccT>), dim3(blocks_for(c, NW * (kWave / G2))), dim3(kPropBlock), 0,
+        GP_PROF_LAUNCH((std::string("k_dense_lanes<") + std::to_string(G2) + sfx).c_str(), tb[2], s, hipLaunchKernelGGL((k_dense_lanes<G2, 8, KT, AccT>), dim3(blocks_for(c, NW * (kWave / G2))), dim3(kPropBlock), 0,
                            s, a, nlabels, tl, 2));
     if ((c = cnt(3)) > 0)
         GP_PROF_LAUNCH((std::string("k_dense_group<16") + sfx).c_str(), tb[3], s, hipLaunchKernelGGL((k_dense_group<16, KT, AccT>), dim3(blocks_for(c, NW * 4)), dim3(kPropBlock), 0, s, a,
@@ -2252,12 +2397,12 @@ int launch_proposals(const LPArgs &a, const int32_t *verts, const int64_t *tstar
     auto blocks_for = [&](int32_t c, int per_block) { return grid_for(c, per_block, 16384); };
     int32_t c;
     if ((c = cnt(1)) > 0) {
-        if constexpr (sizeof(AccT) == 4) GP_PROF_LAUNCH((std::string("k_pgroup<4, 8, ") + acc + ">").c_str(), tb[1], s, hipLaunchKernelGGL((k_pgroup<4, 8>), dim3(blocks_for(c, NW * 16)), dim3(kPropBlock), 0, s,
+        if constexpr (sizeof(AccT) == 4) GP_PROF_LAUNCH("k_plane<4, int>", tb[1], s, hipLaunchKernelGGL((k_plane<4, 4>), dim3(blocks_for(c, NW * 16)), dim3(kPropBlock), 0, s,
                            a, tl, 1)); else GP_PROF_LAUNCH((std::string("k_propose_group<4, 8, ") + acc + ">").c_str(), tb[1], s, hipLaunchKernelGGL((k_propose_group<4, 8, AccT>), dim3(blocks_for(c, NW * 16)), dim3(kPropBlock), 0, s,
                            a, tl, 1));
     }
     if ((c = cnt(2)) > 0) {
-        if constexpr (sizeof(AccT) == 4) GP_PROF_LAUNCH((std::string("k_pgroup<8, 16, ") + acc + ">").c_str(), tb[2], s, hipLaunchKernelGGL((k_pgroup<8, 16>), dim3(blocks_for(c, NW * 8)), dim3(kPropBlock), 0, s,
+        if constexpr (sizeof(AccT) == 4) GP_PROF_LAUNCH("k_plane<8, int>", tb[2], s, hipLaunchKernelGGL((k_plane<8, 8>), dim3(blocks_for(c, NW * 8)), dim3(kPropBlock), 0, s,
                            a, tl, 2)); else GP_PROF_LAUNCH((std::string("k_propose_group<8, 16, ") + acc + ">").c_str(), tb[2], s, hipLaunchKernelGGL((k_propose_group<8, 16, AccT>), dim3(blocks_for(c, NW * 8)), dim3(kPropBlock), 0, s,
                            a, tl, 2));
     }
