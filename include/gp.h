@@ -204,6 +204,12 @@ int gp_lp_cluster(const gp_graph *g, int64_t U, int32_t rounds, int32_t flags,
  * LP refinement (§III-C: LP started from a partition with U = L_max).
  * part_inout: [n] device int32 with 0 <= part[v] < k; overwritten with the
  * refined partition. lmax >= 1 bounds every block.
+ * With ws == NULL on graphs above 16,384 vertices, the block connections of
+ * every vertex above KT/8 neighbours (KT = k rounded up to 16, 64 or 256)
+ * are kept from round to round in the cache (KT sums per such vertex) and
+ * changed only by the admitted moves; this takes the edge weights of u's list
+ * for both (u, v) and (v, u), as in any graph of §II-A. The result equals the
+ * plain rounds', which a caller workspace and GP_REFINE_ROWS=0 select.
  */
 int gp_lp_refine(const gp_graph *g, int32_t k, int64_t lmax, int32_t rounds, int32_t flags,
                  int32_t *part_inout, gp_lp_stats *st_host, void *ws, size_t ws_bytes, hipStream_t stream);
