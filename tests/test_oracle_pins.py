@@ -268,6 +268,36 @@ def test_rebalance_worked_example():
     assert P.tolist() == [0, 0, 1, 1] and bal
 
 
+def test_rebalance_ties_and_recomputed_gains():
+    # edges 0-1, 2-3 inside block 0; P = [0,0,0,0,1,2], k = 3, L_max = 2 (B = [4,1,1]).
+    # step 1: every vertex of block 0 has gain -1 to blocks 1 and 2 -> lowest vertex,
+    #         lowest block: v0 -> 1 (B = [3,2,1]).
+    # step 2: v1 now has gain 0 to block 2 (its neighbour left block 0; block 1 is full),
+    #         v2, v3 have -1 -> v1 -> 2 (B = [2,2,2]).
+    g = graphgen.from_edges(6, [(0, 1), (2, 3)])
+    P, bal = oracle.rebalance(g, 3, 2, [0, 0, 0, 0, 1, 2])
+    assert P.tolist() == [1, 2, 0, 0, 1, 2] and bal
+
+
+def test_rebalance_room_is_at_most_lmax():
+    # vwgt [2,1,1,1], edges 0-3 (w 1) and 1-2 (w 5), P = [0,0,0,1], L_max = 3 (B = [4,1]):
+    # v0 -> 1 has gain 1 and fills block 1 exactly (1 + 2 = 3 <= 3); v1, v2 would lose 5
+    g = graphgen.from_edges(4, [(0, 3), (1, 2)], weights=[1, 5], vwgt=[2, 1, 1, 1])
+    P, bal = oracle.rebalance(g, 2, 3, [0, 0, 0, 1])
+    assert P.tolist() == [1, 0, 0, 1] and bal
+
+
+def test_fill_isolated_worked_example():
+    # 0-1-2 placed (B = [2,1,0]); isolated 3 (weight 2), 4, 5 in ascending order into the
+    # lightest block, ties to the lowest: 3 -> 2 (B = [2,1,2]), 4 -> 1 (B = [2,2,2]),
+    # 5 -> 0 (B = [3,2,2]). Descending order or ties to the highest block differ.
+    g = graphgen.from_edges(6, [(0, 1), (1, 2)], vwgt=[1, 1, 1, 2, 1, 1])
+    part = np.array([0, 0, 1, -1, -1, -1], np.int32)
+    P, B = oracle.fill_isolated(g, 3, part, np.array([2, 1, 0], np.int64))
+    assert P.tolist() == [0, 0, 1, 2, 1, 0]
+    assert B.tolist() == [3, 2, 2]
+
+
 def test_rebalance_flags_infeasible():
     g = graphgen.from_edges(3, [(0, 1), (1, 2)], vwgt=[5, 1, 1])
     P, bal = oracle.rebalance(g, 2, 4, [0, 1, 1])
