@@ -18,3 +18,23 @@ def two_cliques(size):
     edges = [(i, j) for i in range(size) for j in range(i + 1, size)]
     edges += [(i + size, j + size) for i, j in edges]
     return graphgen.from_edges(2 * size, edges)
+
+
+def star(leaves=7):
+    """Centre 0 joined to leaves 1..leaves."""
+    return graphgen.from_edges(leaves + 1, [(0, i) for i in range(1, leaves + 1)])
+
+
+def spider():
+    """Centre 0 with three legs 0-1-2-3, 0-4-5-6, 0-7-8-9."""
+    return graphgen.from_edges(10, [(0, 1), (1, 2), (2, 3), (0, 4), (4, 5), (5, 6), (0, 7), (7, 8), (8, 9)])
+
+
+def three_parts():
+    """Three components: path 0-1-2-3-4, triangle 5-6-7, edge 8-9."""
+    return graphgen.from_edges(10, [(0, 1), (1, 2), (2, 3), (3, 4), (5, 6), (6, 7), (5, 7), (8, 9)])
+
+
+def path(n, vwgt=None):
+    """Path 0-1-...-(n-1)."""
+    return graphgen.from_edges(n, [(i, i + 1) for i in range(n - 1)], vwgt=vwgt)

@@ -19,8 +19,8 @@ unmarked one, or a '>' stop rule gives another side in at least one case.
 import numpy as np
 import pytest
 
-import graphgen
 import oracle
+from hand_graphs import path, spider, star, three_parts
 
 
 def _seed_for(start_index, size, ks, base=0, attempt=0):
@@ -36,7 +36,7 @@ def _side0(g, seed, k=2, attempt=0):
 
 
 # star: centre 0, leaves 1..7 (unit weights, k = 2: the grown side weighs 4)
-STAR = graphgen.from_edges(8, [(0, i) for i in range(1, 8)])
+STAR = star(7)
 # traced: from the centre the leaves are enqueued 1, 2, ..., 7 and 1, 2, 3 follow it;
 # from a leaf s the centre comes second, then the smallest leaves other than s
 STAR_SIDES = {
@@ -54,7 +54,7 @@ def test_star_neighbours_in_ascending_order(start):
 
 
 # spider: centre 0 with legs 0-1-2-3, 0-4-5-6, 0-7-8-9 (n = 10, the grown side weighs 5)
-SPIDER = graphgen.from_edges(10, [(0, 1), (1, 2), (2, 3), (0, 4), (4, 5), (5, 6), (0, 7), (7, 8), (8, 9)])
+SPIDER = spider()
 # traced (dequeue order):
 #   from 0: 0 | 1 4 7 | 2            -> a queue reaches all three legs before going deeper
 #   from 3: 3 2 1 0 | 4              -> the first leg, then the lowest next leg
@@ -74,7 +74,7 @@ def test_spider_is_grown_breadth_first(start):
 
 
 # three components: path 0-1-2-3-4, triangle 5-6-7, edge 8-9 (the grown side weighs 5)
-PARTS = graphgen.from_edges(10, [(0, 1), (1, 2), (2, 3), (3, 4), (5, 6), (6, 7), (5, 7), (8, 9)])
+PARTS = three_parts()
 # traced: a component smaller than the target runs dry and the search restarts at the
 # smallest unmarked vertex
 PARTS_SIDES = {
@@ -93,7 +93,7 @@ def test_search_restarts_at_smallest_unmarked_vertex(start):
 def test_weighted_stop_is_at_least_target():
     # path 0-1-2-3 with vertex weights 3, 1, 1, 3 (c(S) = 8, target 4), started at 1:
     # 1 (weight 1), then 0 (total 4 >= 4): stop. A '>' rule would take 2 as well.
-    g = graphgen.from_edges(4, [(0, 1), (1, 2), (2, 3)], vwgt=[3, 1, 1, 3])
+    g = path(4, vwgt=[3, 1, 1, 3])
     assert _side0(g, _seed_for(1, 4, 2)) == {0, 1}
     # started at 2: 2, then 1 (total 2), then 3 (total 5): the lower neighbour 1 is
     # dequeued before 3, so 0 stays out
@@ -105,7 +105,7 @@ def test_four_blocks_on_a_path_traced():
     # and takes blocks 0, 1; the rest takes blocks 2, 3. Each side is then bisected with
     # k_S = 2 (first block 0 and 2): its grown side weighs 2.
     n = 8
-    g = graphgen.from_edges(n, [(i, i + 1) for i in range(n - 1)])
+    g = path(n)
     # find a seed whose first start is vertex 5: 5 | 4 6 | 3 -> side {3, 4, 5, 6}
     found = 0
     for seed in range(20000):
