@@ -61,3 +61,17 @@ def test_batch_rejects_cross_edges():
     bad = graphgen.from_edges(6, [(0, 1), (3, 5), (2, 3)])
     with pytest.raises(gp.GPError):
         gp.partition_batch(gp.to_device(bad), off, [2, 2])
+
+
+def test_batch_mixed_block_counts_and_hubs():
+    # block counts on both sides of the refinement's table switches (64, 256, 300) in one
+    # batch, with hubs of 2,049 to 9,000 neighbours and graphs just past 1,024 and 16,384 vertices
+    rng = np.random.default_rng(3)
+    n = 20000
+    edges = [(int(u), int(v)) for u, v in rng.integers(0, n - 3, size=(3 * n, 2)) if u != v]
+    for h, d in ((n - 3, 2049), (n - 2, 4097), (n - 1, 9000)):
+        edges += [(h, int(u)) for u in rng.choice(n - 3, d, replace=False)]
+    hubs = graphgen.from_edges(n, edges)
+    graphs = [hubs, graphgen.rgg2d(16385, 12), graphgen.rmat(12, 5), graphgen.grid3d(5, 5, 41, seed=4, wmax=9),
+              graphgen.from_edges(4, [(0, 1), (1, 2), (2, 3)]), graphgen.rgg2d(1025, 2)]
+    _check_batch(graphs, [16, 300, 64, 256, 4, 65])
