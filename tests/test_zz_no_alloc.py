@@ -54,3 +54,44 @@ def test_static_refine_rejects_sizes_beyond_the_array():
     st = gp.LPStats()
     rc = lib.gp_lp_refine_static(ctypes.byref(g), 16, 10, 25, 1, fake, ctypes.byref(st), None)
     assert rc == -3 and b"static scratch" in lib.gp_last_error()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("flags", [1, 3])
+def test_static_refine_just_below_the_array_limit(flags):
+    # the largest geometric graph (in steps of 5,000 vertices) whose workspace bound fits
+    # the 64 MiB array: the bound must suffice there too, and the result equal gp_lp_refine's
+    # and the oracle's
+    import torch
+    import paper_1710_08231_amd as gp
+    limit, k = 64 << 20, 64
+
+    def bound(n):
+        g = graphgen.rgg2d(n, 31)
+        return g, gp.workspace_bytes(2, n, len(g["adjncy"]), k, flags)
+
+    # the bound grows about linearly with the size: start near the limit
+    n = int(700000 * limit / bound(700000)[1]) // 5000 * 5000
+    g, b = bound(n)
+    while b > limit:
+        n -= 5000
+        g, b = bound(n)
+    best = (g, b)
+    while True:
+        n += 5000
+        g, b = bound(n)
+        if b > limit:
+            break
+        best = (g, b)
+    g, b = best
+    assert b > 0.97 * limit
+    dg = gp.to_device(g)
+    part, lm = _case(g, k, 5)
+    P = torch.from_numpy(part).cuda()
+    got, st_g = gp.lp_refine_static(dg, P, k, lm, 25, active=bool(flags & 2))
+    assert 0 < st_g["workspace_bytes"] <= b
+    want, st_w = gp.lp_refine(dg, P, k, lm, 25, active=bool(flags & 2))
+    assert np.array_equal(want.cpu().numpy(), got.cpu().numpy())
+    assert (st_g["rounds_run"], st_g["moves"]) == (st_w["rounds_run"], st_w["moves"])
+    opart, ost = oracle.lp_refine(g, part, k, lm, 25, active=bool(flags & 2))
+    assert np.array_equal(got.cpu().numpy(), opart)
