@@ -2,10 +2,15 @@
 
 Without a GPU the program is only compiled against include/gp.h with a C
 compiler and linked against libgp.so, which checks that the header is plain C
-and self-contained. On a GPU it runs as a child process: it partitions graphs
-written by the seeded generators, once on the library's scratch and once on a
-caller workspace of the reported size, and its partition must equal the
-oracle's (the multilevel scheme of §III)."""
+and self-contained. On a GPU it runs as a child process on graphs written by
+the seeded generators:
+  * partition mode: the whole multilevel scheme (§III), once on the library's
+    scratch and once on a caller workspace of the reported size, must equal the
+    oracle's partition;
+  * steps mode: one level by hand on one caller workspace sized by
+    gp_workspace_bytes (clustering §III-A, contraction, coarse refinement
+    §III-C, projection, fine refinement, cut and block weights §II-A), each
+    result equal to the oracle's step on the same input."""
 import os
 import subprocess
 
@@ -61,7 +66,7 @@ def test_c_caller_partition_equals_oracle(tmp_path, name, make, k):
     g = make()
     gfile, pfile = os.path.join(str(tmp_path), "g.bin"), os.path.join(str(tmp_path), "p.bin")
     _write_graph(gfile, g)
-    run = subprocess.run([exe, gfile, str(k), pfile], capture_output=True, text=True, timeout=120)
+    run = subprocess.run([exe, "partition", gfile, str(k), pfile], capture_output=True, text=True, timeout=120)
     assert run.returncode == 0, run.stderr
     part = np.fromfile(pfile, dtype=np.int32)
     opart, ores = oracle.partition(g, k, 0.03)
@@ -69,3 +74,48 @@ def test_c_caller_partition_equals_oracle(tmp_path, name, make, k):
     fields = dict(kv.split("=") for kv in run.stdout.split()[1:])
     assert int(fields["cut"]) == ores["cut"] and int(fields["max_block_w"]) == ores["max_block_w"]
     assert int(fields["levels"]) == ores["levels"]
+
+
+def _ints(path):
+    return np.fromfile(path, dtype=np.int32)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name,make,k,U", [
+    ("rgg30k", lambda: graphgen.rgg2d(30000, 4), 8, 40),
+    ("rmat15", lambda: graphgen.rmat(15, 3), 16, 300),
+    ("rmat14_k300", lambda: graphgen.rmat(14, 9), 300, 20),
+])
+def test_c_caller_steps_equal_oracle(tmp_path, name, make, k, U):
+    exe = _compile(tmp_path)
+    g = make()
+    n = len(g["xadj"]) - 1
+    gfile = os.path.join(str(tmp_path), "g.bin")
+    _write_graph(gfile, g)
+    run = subprocess.run([exe, "steps", gfile, str(k), str(U), str(tmp_path)], capture_output=True, text=True,
+                         timeout=120)
+    assert run.returncode == 0, run.stderr
+    fields = dict(kv.split("=") for kv in run.stdout.split()[1:])
+
+    labels = _ints(os.path.join(str(tmp_path), "labels.bin"))
+    olab, ost = oracle.lp_cluster(g, U, 10, 1)
+    assert np.array_equal(labels, olab) and int(fields["moves_c"]) == ost["moves"]
+
+    coarse = _ints(os.path.join(str(tmp_path), "coarse.bin"))
+    n_c, nnz_c = int(coarse[0]), int(coarse[1])
+    parts = np.split(coarse[2:], np.cumsum([n_c + 1, nnz_c, nnz_c]))
+    ocg, of2c = oracle.contract(g, olab)
+    for got, key in zip(parts, ("xadj", "adjncy", "adjwgt", "vwgt")):
+        assert np.array_equal(got, ocg[key]), key
+    assert np.array_equal(_ints(os.path.join(str(tmp_path), "f2c.bin")), of2c)
+
+    lm = oracle.lmax(n, k, 0.03)
+    opc, osc = oracle.lp_refine(ocg, np.arange(n_c, dtype=np.int32) % k, k, lm, 25, 1)
+    assert np.array_equal(_ints(os.path.join(str(tmp_path), "partc.bin")), opc)
+    assert int(fields["moves_rc"]) == osc["moves"]
+
+    opf, osf = oracle.lp_refine(g, oracle.project(of2c, opc), k, lm, 25, 1)
+    assert np.array_equal(_ints(os.path.join(str(tmp_path), "partf.bin")), opf)
+    assert int(fields["moves_rf"]) == osf["moves"]
+    assert int(fields["cut"]) == oracle.cut(g, opf)
+    assert [int(b) for b in fields["B"].split(",")] == oracle.block_weights(g, opf, k).tolist()
