@@ -82,3 +82,27 @@ def test_cluster_refine_partition_at_exact_degree_bounds(dg, tuned):
     opart, ores = oracle.partition(G, 16, 0.03)
     assert np.array_equal(part.cpu().numpy(), opart)
     assert res["cut"] == ores["cut"] and res["levels"] == ores["levels"]
+
+
+@pytest.mark.gpu
+def test_opt_in_modes_at_exact_degree_bounds(dg):
+    # active-set rounds renew the neighbours of movers above 256 neighbours in chunks of 4,096
+    # entries (hubs of 255-257, 4,095-4,097, 8,191-8,193 and 16,383-16,385 neighbours straddle
+    # both), FM after the bisections and the batched multi-try local search see the same hubs
+    n = len(G["xadj"]) - 1
+    for U in (3, 60):
+        lab, st = gp.lp_cluster(dg, U, 6, 1, active=True)
+        olab, ost = oracle.lp_cluster(G, U, 6, 1, active=True)
+        assert np.array_equal(lab.cpu().numpy(), olab), U
+        assert {k: st[k] for k in ost} == ost, U
+    part = np.array([graphgen.rand_u64(16, i) % 16 for i in range(n)], np.int32)
+    lm = oracle.lmax(n, 16, 0.03)
+    p, st = gp.lp_refine(dg, torch.from_numpy(part).cuda(), 16, lm, 12, 1, active=True)
+    op, ost = oracle.lp_refine(G, part, 16, lm, 12, 1, active=True)
+    assert np.array_equal(p.cpu().numpy(), op)
+    assert {k: st[k] for k in ost} == ost
+    for params in (dict(active_set=3), dict(init_fm=2), dict(mls=2, mls_batch=64, mls_queue=64)):
+        part, res = gp.partition(dg, 16, 0.03, **params)
+        opart, ores = oracle.partition(G, 16, 0.03, **params)
+        assert np.array_equal(part.cpu().numpy(), opart), params
+        assert res["cut"] == ores["cut"] and res["levels"] == ores["levels"], params
