@@ -311,6 +311,8 @@ int gp_cut_and_blocks(const gp_graph *g, int32_t k, const int32_t *part, int64_t
  * either the plain try is not or it cuts no more edge weight (ties keep the
  * proposal). A proposal with a NaN or infinite logit is discarded. Requires
  * k <= 64 and mpnn_params.
+ * 1 <= k <= 2048: the initial partitioner's rebalance keeps per-block state
+ * in LDS; a larger k returns GP_ERR_ARG once the coarsest graph is reached.
  * part_out: [n] device int32 in [0, k). res_host may be NULL.
  * Returns GP_OK, GP_WARN_IMBALANCED, or an error.
  */
@@ -412,7 +414,8 @@ int gp_mpnn_adam_step(float *params, float *m, float *v, const float *grad, int3
  * graphs that stopped coarsening are carried along unchanged), and one
  * batched initial partitioning runs on the coarsest level. The result for
  * every graph equals gp_partition on that graph alone (same parameters).
- * part_out: [n] device int32, block ids local to each graph (0 <= b < k[q]).
+ * part_out: [n] device int32, block ids local to each graph (0 <= b < k[q]),
+ * 1 <= k[q] <= 2048 as in gp_partition.
  * res_host: [G] host results (may be NULL); the ms_* fields are batch totals.
  * Returns GP_OK, GP_WARN_IMBALANCED (some graph imbalanced), or an error.
  */

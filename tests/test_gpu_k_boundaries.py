@@ -66,3 +66,17 @@ def test_partition_with_coarsening_at_the_byte_label_bound(k):
     assert np.array_equal(part.cpu().numpy(), opart)
     for key in ("cut", "max_block_w", "balanced", "levels", "coarsest_n", "edge_visits_refine"):
         assert res[key] == ores[key], key
+
+
+@pytest.mark.gpu
+def test_partition_at_the_largest_block_count():
+    # the initial partitioner supports up to 2,048 blocks: 2,048 equals the oracle (one level and,
+    # on the larger graph, two), 2,049 is an argument error
+    for n in (40000, 300000):
+        g = graphgen.rgg2d(n, 8)
+        part, res = gp.partition(gp.to_device(g), 2048, 0.03)
+        opart, ores = oracle.partition(g, 2048, 0.03)
+        assert np.array_equal(part.cpu().numpy(), opart), n
+        assert (res["cut"], res["max_block_w"], res["levels"]) == (ores["cut"], ores["max_block_w"], ores["levels"])
+    with pytest.raises(gp.GPError, match="2048"):
+        gp.partition(gp.to_device(graphgen.rgg2d(40000, 8)), 2049, 0.03)
