@@ -99,6 +99,11 @@ def _load():
     lib.orc_partition.argtypes = [G, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(_Params),
                                   I32P, ctypes.POINTER(_Result)]
     lib.orc_lp_cluster_async.argtypes = [G, ctypes.c_int64, ctypes.c_int32, I32P, ctypes.POINTER(_LPStats)]
+    lib.orc_colour_classes.restype = ctypes.c_int32
+    lib.orc_colour_classes.argtypes = [G, I32P]
+    lib.orc_lp_cluster_colour.argtypes = [G, ctypes.c_int64, ctypes.c_int32, I32P, ctypes.POINTER(_LPStats)]
+    lib.orc_lp_refine_colour.argtypes = [G, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, I32P,
+                                         ctypes.POINTER(_LPStats)]
     lib.orc_lp_refine_async.argtypes = [G, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, I32P,
                                         ctypes.POINTER(_LPStats)]
     lib.orc_coarsest.argtypes = [G, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(_Params),
@@ -242,6 +247,31 @@ def lp_refine_async(g, part, k, lmax_, rounds=25):
     P = _i32(part).copy()
     st = _LPStats()
     _load().orc_lp_refine_async(G.ref, k, lmax_, rounds, _p32(P), ctypes.byref(st))
+    return P, {"rounds_run": st.rounds_run, "moves": st.moves, "edge_visits": st.edge_visits}
+
+
+def colour_classes(g):
+    """(number of colours, colour[n]) of the colour-class LP's first-fit colouring."""
+    G = _G(g)
+    col = np.zeros(max(G.n, 1), np.int32)
+    ncol = int(_load().orc_colour_classes(G.ref, _p32(col)))
+    return ncol, col[:G.n].copy()
+
+
+def lp_cluster_colour(g, U, rounds=10):
+    """Colour-class LP clustering (oracle-only comparison mode)."""
+    G = _G(g)
+    out = np.zeros(max(G.n, 1), dtype=np.int32)
+    st = _LPStats()
+    _load().orc_lp_cluster_colour(G.ref, U, rounds, _p32(out), ctypes.byref(st))
+    return out[:G.n].copy(), {"rounds_run": st.rounds_run, "moves": st.moves, "edge_visits": st.edge_visits}
+
+
+def lp_refine_colour(g, part, k, lmax_, rounds=25):
+    G = _G(g)
+    P = _i32(part).copy()
+    st = _LPStats()
+    _load().orc_lp_refine_colour(G.ref, k, lmax_, rounds, _p32(P), ctypes.byref(st))
     return P, {"rounds_run": st.rounds_run, "moves": st.moves, "edge_visits": st.edge_visits}
 
 

@@ -204,6 +204,152 @@ static void lp_rounds(const orc_graph *g, int32_t *C, int64_t *W, int32_t nlabel
     }
 }
 
+/*
+ * Colour-class LP (oracle-only comparison mode; lp_async = 2 in orc_params).
+ * A schedule between the synchronous rounds and the paper's sequential queue
+ * (§III-A) that keeps the parallelism a GPU needs: vertices are split into
+ * classes of pairwise non-adjacent vertices, and a round visits the classes
+ * one after the other.
+ *  - Colouring: in decreasing order of the priority sm64(v) (ties: larger id
+ *    first), each vertex takes the smallest colour that no already coloured
+ *    neighbour holds (first fit). The same colouring comes out of the
+ *    parallel rule "colour v once all neighbours of higher priority are
+ *    coloured" (Jones and Plassmann 1993).
+ *  - Round: for each colour in increasing order, every vertex of the class
+ *    proposes from the current labels and weights (steps 1-3; no direction
+ *    rule, since no two proposers of a class are adjacent), the proposals are
+ *    admitted per target in ascending id (step 4), and applied (step 5)
+ *    before the next class proposes. Stop after two idle rounds in a row.
+ */
+typedef struct {
+    uint64_t p;
+    int32_t v;
+} prio_t;
+
+static int cmp_prio_desc(const void *a, const void *b) {
+    const prio_t *x = (const prio_t *)a, *y = (const prio_t *)b;
+    if (x->p != y->p) return x->p < y->p ? 1 : -1;
+    return (x->v < y->v) - (x->v > y->v);
+}
+
+static uint64_t sm64(uint64_t x);
+
+int32_t orc_colour_classes(const orc_graph *g, int32_t *colour) {
+    const int32_t n = g->n;
+    if (n == 0) return 0;
+    prio_t *order = (prio_t *)xcalloc((size_t)n, sizeof(prio_t));
+    int32_t dmax = 0;
+    for (int32_t v = 0; v < n; v++) {
+        order[v].p = sm64((uint64_t)v);
+        order[v].v = v;
+        colour[v] = -1;
+        if (g->xadj[v + 1] - g->xadj[v] > dmax) dmax = g->xadj[v + 1] - g->xadj[v];
+    }
+    qsort(order, (size_t)n, sizeof(prio_t), cmp_prio_desc);
+    int32_t *stamp = (int32_t *)xcalloc((size_t)dmax + 2, sizeof(int32_t));
+    int32_t ncol = 0;
+    for (int32_t i = 0; i < n; i++) {
+        const int32_t v = order[i].v;
+        for (int32_t e = g->xadj[v]; e < g->xadj[v + 1]; e++) {
+            const int32_t c = colour[g->adjncy[e]];
+            if (c >= 0 && c <= dmax) stamp[c] = i + 1;
+        }
+        int32_t c = 0;
+        while (stamp[c] == i + 1) c++;
+        colour[v] = c;
+        if (c + 1 > ncol) ncol = c + 1;
+    }
+    free(stamp);
+    free(order);
+    return ncol;
+}
+
+static void lp_colour(const orc_graph *g, int32_t *C, int64_t *W, int32_t nlabels, int64_t U, int32_t rounds,
+                      orc_lp_stats *st) {
+    const int32_t n = g->n;
+    int32_t *colour = (int32_t *)xcalloc((size_t)(n > 0 ? n : 1), sizeof(int32_t));
+    const int32_t ncol = orc_colour_classes(g, colour);
+    /* classes in ascending id: counting sort by colour */
+    int32_t *start = (int32_t *)xcalloc((size_t)ncol + 2, sizeof(int32_t));
+    int32_t *cls = (int32_t *)xcalloc((size_t)(n > 0 ? n : 1), sizeof(int32_t));
+    for (int32_t v = 0; v < n; v++) start[colour[v] + 1]++;
+    for (int32_t c = 0; c < ncol; c++) start[c + 1] += start[c];
+    for (int32_t v = 0; v < n; v++) cls[start[colour[v]]++] = v;
+    for (int32_t c = ncol; c > 0; c--) start[c] = start[c - 1];
+    start[0] = 0;
+    int64_t *conn = (int64_t *)xcalloc((size_t)nlabels, sizeof(int64_t));
+    int32_t *seen = (int32_t *)xcalloc((size_t)nlabels, sizeof(int32_t));
+    int32_t *touched = (int32_t *)xcalloc((size_t)nlabels, sizeof(int32_t));
+    int64_t *acc = (int64_t *)xcalloc((size_t)nlabels, sizeof(int64_t));
+    int32_t *prop = (int32_t *)xcalloc((size_t)(n > 0 ? n : 1), sizeof(int32_t));
+    uint8_t *admitted = (uint8_t *)xcalloc((size_t)(n > 0 ? n : 1), 1);
+    int64_t prev = -1, total = 0, visits = 0;
+    int32_t run = 0;
+    for (int32_t r = 0; r < rounds; r++) {
+        int64_t m = 0;
+        for (int32_t c = 0; c < ncol; c++) {
+            const int32_t b = start[c], e = start[c + 1];
+            for (int32_t j = b; j < e; j++) {
+                const int32_t v = cls[j];
+                visits += g->xadj[v + 1] - g->xadj[v];
+                prop[j] = propose_vertex(g, C, W, U, r, 0, v, conn, seen, touched);
+            }
+            for (int32_t j = b; j < e; j++) {
+                if (prop[j] < 0) continue;
+                acc[prop[j]] += VW(g, cls[j]);
+                admitted[j] = (W[prop[j]] + acc[prop[j]] <= U);
+            }
+            for (int32_t j = b; j < e; j++) {
+                if (prop[j] < 0) continue;
+                acc[prop[j]] = 0;
+                if (!admitted[j]) continue;
+                const int32_t v = cls[j], t = prop[j];
+                W[t] += VW(g, v);
+                W[C[v]] -= VW(g, v);
+                C[v] = t;
+                admitted[j] = 0;
+                m++;
+            }
+        }
+        total += m;
+        run = r + 1;
+        if (r >= 1 && m == 0 && prev == 0) break;
+        prev = m;
+    }
+    if (st) {
+        st->rounds_run = run;
+        st->moves = total;
+        st->edge_visits = visits;
+    }
+    free(colour);
+    free(start);
+    free(cls);
+    free(conn);
+    free(seen);
+    free(touched);
+    free(acc);
+    free(prop);
+    free(admitted);
+}
+
+int orc_lp_cluster_colour(const orc_graph *g, int64_t U, int32_t rounds, int32_t *labels_out, orc_lp_stats *st) {
+    int32_t n = g->n;
+    int64_t *W = (int64_t *)xcalloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+    for (int32_t v = 0; v < n; v++) { labels_out[v] = v; W[v] = VW(g, v); }
+    lp_colour(g, labels_out, W, n > 0 ? n : 1, U, rounds, st);
+    free(W);
+    return 0;
+}
+
+int orc_lp_refine_colour(const orc_graph *g, int32_t k, int64_t lmax, int32_t rounds, int32_t *part,
+                         orc_lp_stats *st) {
+    int64_t *W = (int64_t *)xcalloc((size_t)k, sizeof(int64_t));
+    for (int32_t v = 0; v < g->n; v++) W[part[v]] += VW(g, v);
+    lp_colour(g, part, W, k, lmax, rounds, st);
+    free(W);
+    return 0;
+}
+
 /* §III-A: size-constrained LP clustering from singletons, C[v] = v, bound U. */
 int orc_lp_cluster(const orc_graph *g, int64_t U, int32_t rounds, int32_t flags,
                    int32_t *labels_out, orc_lp_stats *st) {
@@ -769,7 +915,8 @@ static void coarsen(const orc_graph *g, int32_t k, double eps, const orc_params 
         int32_t fn = f->g.n, fnnz = f->g.xadj[fn];
         int32_t *labels = (int32_t *)xcalloc((size_t)fn, sizeof(int32_t));
         orc_lp_stats st;
-        if (p->lp_async) orc_lp_cluster_async(&f->g, ucl, p->rounds_coarsen, labels, &st);
+        if (p->lp_async == 2) orc_lp_cluster_colour(&f->g, ucl, p->rounds_coarsen, labels, &st);
+        else if (p->lp_async) orc_lp_cluster_async(&f->g, ucl, p->rounds_coarsen, labels, &st);
         else orc_lp_cluster(&f->g, ucl, p->rounds_coarsen,
                             lp_flags(p) | ((p->active_set & 1) ? ORC_LP_ACTIVE_SET : 0), labels, &st);
         ev_cluster += st.edge_visits;
@@ -904,7 +1051,8 @@ int orc_partition(const orc_graph *g, int32_t k, double eps, const orc_params *p
             P = Pf;
         }
         orc_lp_stats st;
-        if (p->lp_async) orc_lp_refine_async(&lev[l].g, k, lmax, p->rounds_refine, P, &st);
+        if (p->lp_async == 2) orc_lp_refine_colour(&lev[l].g, k, lmax, p->rounds_refine, P, &st);
+        else if (p->lp_async) orc_lp_refine_async(&lev[l].g, k, lmax, p->rounds_refine, P, &st);
         else orc_lp_refine(&lev[l].g, k, lmax, p->rounds_refine,
                            lp_flags(p) | ((p->active_set & 2) ? ORC_LP_ACTIVE_SET : 0), P, &st);
         ev_refine += st.edge_visits;

@@ -50,7 +50,8 @@ typedef struct {
     int32_t mpnn_max_n;       /* learned proposal only when the coarsest graph has <= this many vertices */
     uint64_t mpnn_seed;       /* probe features */
     const float *mpnn_params; /* fp32 master weights (see orc_mpnn_param_count) */
-    int32_t lp_async;         /* 0; 1: the paper's sequential LP (oracle-only comparison mode) */
+    int32_t lp_async;         /* 0; 1: the paper's sequential LP, 2: colour-class LP (oracle-only
+                                 comparison modes) */
     int32_t active_set;       /* 0; bit 0: coarsening LP in active-set rounds, bit 1: uncoarsening LP */
     int32_t mls;              /* 0; g > 0: multi-try local search (g global iterations) after each level's
                                  LP refinement (oracle-only comparison mode) */
@@ -118,6 +119,10 @@ int orc_lp_refine(const orc_graph *g, int32_t k, int64_t lmax, int32_t rounds,
 /* §III-A sequential LP as the paper states it (queue by increasing degree,
  * in-place moves, neighbours of movers re-queued); an oracle-only mode. */
 int orc_lp_cluster_async(const orc_graph *g, int64_t U, int32_t rounds, int32_t *labels_out, orc_lp_stats *st);
+int32_t orc_colour_classes(const orc_graph *g, int32_t *colour);
+int orc_lp_cluster_colour(const orc_graph *g, int64_t U, int32_t rounds, int32_t *labels_out, orc_lp_stats *st);
+int orc_lp_refine_colour(const orc_graph *g, int32_t k, int64_t lmax, int32_t rounds, int32_t *part,
+                         orc_lp_stats *st);
 int orc_lp_refine_async(const orc_graph *g, int32_t k, int64_t lmax, int32_t rounds, int32_t *part,
                         orc_lp_stats *st);
 
