@@ -205,7 +205,8 @@ static void lp_rounds(const orc_graph *g, int32_t *C, int64_t *W, int32_t nlabel
 }
 
 /*
- * Colour-class LP (oracle-only comparison mode; lp_async = 2 in orc_params).
+ * Colour-class LP (oracle-only comparison mode; lp_async = 2 in orc_params for
+ * clustering and refinement, 3 for clustering only).
  * A schedule between the synchronous rounds and the paper's sequential queue
  * (§III-A) that keeps the parallelism a GPU needs: vertices are split into
  * classes of pairwise non-adjacent vertices, and a round visits the classes
@@ -915,8 +916,8 @@ static void coarsen(const orc_graph *g, int32_t k, double eps, const orc_params 
         int32_t fn = f->g.n, fnnz = f->g.xadj[fn];
         int32_t *labels = (int32_t *)xcalloc((size_t)fn, sizeof(int32_t));
         orc_lp_stats st;
-        if (p->lp_async == 2) orc_lp_cluster_colour(&f->g, ucl, p->rounds_coarsen, labels, &st);
-        else if (p->lp_async) orc_lp_cluster_async(&f->g, ucl, p->rounds_coarsen, labels, &st);
+        if (p->lp_async == 2 || p->lp_async == 3) orc_lp_cluster_colour(&f->g, ucl, p->rounds_coarsen, labels, &st);
+        else if (p->lp_async == 1) orc_lp_cluster_async(&f->g, ucl, p->rounds_coarsen, labels, &st);
         else orc_lp_cluster(&f->g, ucl, p->rounds_coarsen,
                             lp_flags(p) | ((p->active_set & 1) ? ORC_LP_ACTIVE_SET : 0), labels, &st);
         ev_cluster += st.edge_visits;
@@ -1052,7 +1053,7 @@ int orc_partition(const orc_graph *g, int32_t k, double eps, const orc_params *p
         }
         orc_lp_stats st;
         if (p->lp_async == 2) orc_lp_refine_colour(&lev[l].g, k, lmax, p->rounds_refine, P, &st);
-        else if (p->lp_async) orc_lp_refine_async(&lev[l].g, k, lmax, p->rounds_refine, P, &st);
+        else if (p->lp_async == 1) orc_lp_refine_async(&lev[l].g, k, lmax, p->rounds_refine, P, &st);
         else orc_lp_refine(&lev[l].g, k, lmax, p->rounds_refine,
                            lp_flags(p) | ((p->active_set & 2) ? ORC_LP_ACTIVE_SET : 0), P, &st);
         ev_refine += st.edge_visits;

@@ -50,8 +50,8 @@ typedef struct {
     int32_t mpnn_max_n;       /* learned proposal only when the coarsest graph has <= this many vertices */
     uint64_t mpnn_seed;       /* probe features */
     const float *mpnn_params; /* fp32 master weights (see orc_mpnn_param_count) */
-    int32_t lp_async;         /* 0; 1: the paper's sequential LP, 2: colour-class LP (oracle-only
-                                 comparison modes) */
+    int32_t lp_async;         /* 0; 1: the paper's sequential LP, 2: colour-class LP, 3: colour-class
+                                 LP in clustering only (oracle-only comparison modes) */
     int32_t active_set;       /* 0; bit 0: coarsening LP in active-set rounds, bit 1: uncoarsening LP */
     int32_t mls;              /* 0; g > 0: multi-try local search (g global iterations) after each level's
                                  LP refinement (oracle-only comparison mode) */

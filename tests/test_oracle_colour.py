@@ -106,3 +106,27 @@ def test_multilevel_scheme_in_colour_mode(g, k):
     assert np.array_equal(p1, p2) and r1["balanced"]
     assert r1["cut"] == oracle.cut(g, p1)
     assert r1["levels"] >= 1 and r1["edge_visits_cluster"] > 0
+
+
+@pytest.mark.parametrize("g,k", [(graphgen.grid3d(24, 24, 24, seed=3, wmax=10), 16), (graphgen.rmat(13, 6), 8)])
+def test_clustering_only_mode_composes_the_other_two(g, k):
+    # lp_async = 3: colour classes in clustering, synchronous rounds in refinement. Its
+    # hierarchy is that of lp_async = 2 (same clustering), its refinement that of lp_async = 0
+    p2, r2 = oracle.partition(g, k, 0.03, lp_async=2)
+    p3, r3 = oracle.partition(g, k, 0.03, lp_async=3)
+    for key in ("levels", "coarsest_n", "edge_visits_cluster"):
+        assert r3[key] == r2[key], key
+    c2, i2 = oracle.coarsest(g, k, 0.03, lp_async=2)
+    c3, i3 = oracle.coarsest(g, k, 0.03, lp_async=3)
+    assert all(np.array_equal(c2[f], c3[f]) for f in c2) and np.array_equal(i2, i3)
+    assert r3["balanced"] and r3["cut"] == oracle.cut(g, p3)
+
+
+def test_clustering_only_mode_without_coarsening_is_the_synchronous_scheme():
+    # 2,000 vertices <= 60 k for k = 64: no clustering runs, so lp_async = 3 is lp_async = 0
+    # exactly (the refinement rounds are the synchronous ones in both)
+    g = graphgen.rgg2d(2000, 5)
+    p0, r0 = oracle.partition(g, 64, 0.03)
+    p3, r3 = oracle.partition(g, 64, 0.03, lp_async=3)
+    assert r0["levels"] == 1 and np.array_equal(p0, p3)
+    assert (r0["cut"], r0["edge_visits_refine"]) == (r3["cut"], r3["edge_visits_refine"])
