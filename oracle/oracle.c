@@ -26,6 +26,7 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#include <omp.h>
 
 #define VW(g, v) ((g)->vwgt ? (int64_t)(g)->vwgt[v] : (int64_t)1)
 #define EW(g, e) ((g)->adjwgt ? (int64_t)(g)->adjwgt[e] : (int64_t)1)
@@ -101,9 +102,10 @@ static int32_t propose_vertex(const orc_graph *g, const int32_t *C, const int64_
     return (best >= 0 && best_conn > conn_own) ? best : -1;
 }
 
-/* Threads of the proposal loop of full rounds (1 unless orc_set_threads says
- * otherwise). Every proposal reads only the round-start C and W and writes
- * only its own entry, so the result does not depend on the thread count. */
+/* Threads of the proposal loop of full rounds and of a colour class (1 unless
+ * orc_set_threads says otherwise). Every proposal reads only the labels and
+ * weights as they stand before the loop and writes only its own entry, so the
+ * result does not depend on the thread count. */
 static int orc_threads = 1;
 
 void orc_set_threads(int32_t t) { orc_threads = t > 0 ? t : 1; }
@@ -284,16 +286,38 @@ static void lp_colour(const orc_graph *g, int32_t *C, int64_t *W, int32_t nlabel
     int64_t *acc = (int64_t *)xcalloc((size_t)nlabels, sizeof(int64_t));
     int32_t *prop = (int32_t *)xcalloc((size_t)(n > 0 ? n : 1), sizeof(int32_t));
     uint8_t *admitted = (uint8_t *)xcalloc((size_t)(n > 0 ? n : 1), 1);
+    /* per-thread proposal scratch (all zero between proposals), allocated once */
+    const int nthr = orc_threads;
+    int64_t **tconn = NULL;
+    int32_t **tseen = NULL, **ttouched = NULL;
+    if (nthr > 1) {
+        tconn = (int64_t **)xcalloc((size_t)nthr, sizeof(int64_t *));
+        tseen = (int32_t **)xcalloc((size_t)nthr, sizeof(int32_t *));
+        ttouched = (int32_t **)xcalloc((size_t)nthr, sizeof(int32_t *));
+        for (int t = 0; t < nthr; t++) {
+            tconn[t] = (int64_t *)xcalloc((size_t)nlabels, sizeof(int64_t));
+            tseen[t] = (int32_t *)xcalloc((size_t)nlabels, sizeof(int32_t));
+            ttouched[t] = (int32_t *)xcalloc((size_t)nlabels, sizeof(int32_t));
+        }
+    }
     int64_t prev = -1, total = 0, visits = 0;
     int32_t run = 0;
     for (int32_t r = 0; r < rounds; r++) {
         int64_t m = 0;
         for (int32_t c = 0; c < ncol; c++) {
             const int32_t b = start[c], e = start[c + 1];
-            for (int32_t j = b; j < e; j++) {
-                const int32_t v = cls[j];
-                visits += g->xadj[v + 1] - g->xadj[v];
-                prop[j] = propose_vertex(g, C, W, U, r, 0, v, conn, seen, touched);
+            for (int32_t j = b; j < e; j++) visits += g->xadj[cls[j] + 1] - g->xadj[cls[j]];
+            if (nthr > 1 && e - b >= 4096) {
+                /* proposals of one class read C and W and write only their own entry */
+#pragma omp parallel num_threads(nthr)
+                {
+                    const int t = omp_get_thread_num();
+#pragma omp for schedule(dynamic, 1024)
+                    for (int32_t j = b; j < e; j++)
+                        prop[j] = propose_vertex(g, C, W, U, r, 0, cls[j], tconn[t], tseen[t], ttouched[t]);
+                }
+            } else {
+                for (int32_t j = b; j < e; j++) prop[j] = propose_vertex(g, C, W, U, r, 0, cls[j], conn, seen, touched);
             }
             for (int32_t j = b; j < e; j++) {
                 if (prop[j] < 0) continue;
@@ -322,6 +346,14 @@ static void lp_colour(const orc_graph *g, int32_t *C, int64_t *W, int32_t nlabel
         st->moves = total;
         st->edge_visits = visits;
     }
+    for (int t = 0; t < nthr && tconn; t++) {
+        free(tconn[t]);
+        free(tseen[t]);
+        free(ttouched[t]);
+    }
+    free(tconn);
+    free(tseen);
+    free(ttouched);
     free(colour);
     free(start);
     free(cls);

@@ -130,3 +130,15 @@ def test_clustering_only_mode_without_coarsening_is_the_synchronous_scheme():
     p3, r3 = oracle.partition(g, 64, 0.03, lp_async=3)
     assert r0["levels"] == 1 and np.array_equal(p0, p3)
     assert (r0["cut"], r0["edge_visits_refine"]) == (r3["cut"], r3["edge_visits_refine"])
+
+
+def test_thread_count_changes_nothing():
+    g = graphgen.grid3d(40, 40, 30, seed=3, wmax=10)
+    try:
+        oracle.set_threads(1)
+        p1, r1 = oracle.partition(g, 16, 0.03, lp_async=2)
+        oracle.set_threads(4)
+        p4, r4 = oracle.partition(g, 16, 0.03, lp_async=2)
+    finally:
+        oracle.set_threads(1)
+    assert np.array_equal(p1, p4) and r1 == r4
