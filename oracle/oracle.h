@@ -119,12 +119,17 @@ int orc_lp_refine(const orc_graph *g, int32_t k, int64_t lmax, int32_t rounds,
 /* §III-A sequential LP as the paper states it (queue by increasing degree,
  * in-place moves, neighbours of movers re-queued); an oracle-only mode. */
 int orc_lp_cluster_async(const orc_graph *g, int64_t U, int32_t rounds, int32_t *labels_out, orc_lp_stats *st);
+int orc_lp_refine_async(const orc_graph *g, int32_t k, int64_t lmax, int32_t rounds, int32_t *part,
+                        orc_lp_stats *st);
+
+/* Colour-class LP, an oracle-only mode between the two above: the classes of a
+ * first-fit colouring (decreasing splitmix64 priority) are visited one after
+ * the other, each proposing from the current labels and admitting per target
+ * in ascending id. orc_colour_classes writes colour[n] and returns the count. */
 int32_t orc_colour_classes(const orc_graph *g, int32_t *colour);
 int orc_lp_cluster_colour(const orc_graph *g, int64_t U, int32_t rounds, int32_t *labels_out, orc_lp_stats *st);
 int orc_lp_refine_colour(const orc_graph *g, int32_t k, int64_t lmax, int32_t rounds, int32_t *part,
                          orc_lp_stats *st);
-int orc_lp_refine_async(const orc_graph *g, int32_t k, int64_t lmax, int32_t rounds, int32_t *part,
-                        orc_lp_stats *st);
 
 /* Coarse graph into caller buffers sized for the fine graph (n+1, nnz, nnz, n, n). */
 int orc_contract(const orc_graph *g, const int32_t *labels, int32_t *xadj_c, int32_t *adjncy_c,
