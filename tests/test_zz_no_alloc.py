@@ -75,10 +75,12 @@ def test_static_refine_just_below_the_array_limit(flags):
     g, b = bound(n)
     while b > limit:
         n -= 5000
+        assert n > 5000, "the workspace bound does not shrink with the graph"
         g, b = bound(n)
     best = (g, b)
     while True:
         n += 5000
+        assert n < 4_000_000, "the workspace bound does not grow with the graph"
         g, b = bound(n)
         if b > limit:
             break
