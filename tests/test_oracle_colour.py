@@ -5,7 +5,9 @@ each vertex, §IV-A's ascending-id admission per target), with the classes of a
 first-fit colouring in decreasing hash priority. Pinned here:
   * the colouring: proper (no edge inside a class) and first fit (a vertex of
     colour c has neighbours of every colour below c); K_m takes m colours, a
-    star two;
+    star two; and it equals the colouring of the parallel rule (Jones and
+    Plassmann) run step by step with splitmix64 priorities written from the
+    published definition, which is what a GPU colouring would compute;
   * the sweep, traced by hand on paths whose colouring the oracle reports:
     a class proposes from the labels its earlier classes left, so a label
     travels two hops in one round, and the admission inside a class refuses
@@ -142,3 +144,43 @@ def test_thread_count_changes_nothing():
     finally:
         oracle.set_threads(1)
     assert np.array_equal(p1, p4) and r1 == r4
+
+
+def _splitmix64(x):
+    # the finaliser of state x + gamma (Steele, Lea & Flood 2014), on uint64 arrays
+    m = np.uint64(0xFFFFFFFFFFFFFFFF)
+    with np.errstate(over="ignore"):
+        z = (x + np.uint64(0x9E3779B97F4A7C15)) & m
+        z = ((z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)) & m
+        z = ((z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)) & m
+        return z ^ (z >> np.uint64(31))
+
+
+def _parallel_rule_colouring(g):
+    # steps of the parallel rule: a vertex whose neighbours of higher priority are all
+    # coloured takes the smallest colour absent among them; all such vertices at once
+    n = len(g["xadj"]) - 1
+    p = _splitmix64(np.arange(n, dtype=np.uint64))
+    col = np.full(n, -1)
+    while (col < 0).any():
+        ready = []
+        for v in np.flatnonzero(col < 0):
+            nb = g["adjncy"][g["xadj"][v]:g["xadj"][v + 1]]
+            hi = nb[(p[nb] > p[v]) | ((p[nb] == p[v]) & (nb > v))]
+            if (col[hi] >= 0).all():
+                ready.append((v, set(col[hi].tolist())))
+        assert ready
+        for v, used in ready:
+            c = 0
+            while c in used:
+                c += 1
+            col[v] = c
+    return col
+
+
+def test_colouring_is_that_of_the_parallel_rule():
+    # the published first output of splitmix64 from state 0 guards the numpy finaliser
+    assert int(_splitmix64(np.array([0], np.uint64))[0]) == 0xE220A8397B1DCDAF
+    for g in (graphgen.rgg2d(1500, 7), graphgen.rmat(9, 3), graphgen.grid3d(7, 6, 5, wmax=0), path(12),
+              graphgen.random_small(120, 0.08, 5)):
+        assert np.array_equal(oracle.colour_classes(g)[1], _parallel_rule_colouring(g))
