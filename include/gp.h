@@ -114,7 +114,8 @@ typedef struct {
     int32_t dir_alternate;  /* 1: direction alternation of synchronous rounds */
     uint64_t seed;          /* start-vertex hash of the initial bisections */
     int32_t init_mode;      /* GP_INIT_PLAIN; GP_INIT_LEARNED adds the network's proposal */
-    int32_t mpnn_max_n;     /* 131072: the proposal is tried only on coarsest graphs this small */
+    int32_t mpnn_max_n;     /* 131072: the proposal is tried only on coarsest graphs this small (the
+                               shipped k = 16 weights were trained on graphs of at most 3,252) */
     uint64_t mpnn_seed;     /* 0: seed of the network's probe features */
     const float *mpnn_params; /* NULL: device fp32 master weights, gp_mpnn_param_count(k) of them */
     int32_t active_set;     /* 0; bit 0: coarsening LP in active-set rounds (GP_LP_ACTIVE_SET), bit 1:
